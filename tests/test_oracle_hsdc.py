@@ -1,0 +1,289 @@
+"""Pins of the oracle's HSDC sweep and PFASST (Algorithm 1) against closed
+forms, stability statements of the paper, convergence orders and an independent
+stiff ODE integrator (no GPU)."""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import ttp06
+from oracle.coeffs import exp_colloc_matrix
+from oracle.hsdc import Level, collocation_solve, run_serial, serial_step
+from oracle.pfasst import Hierarchy, pfasst_block, run_pfasst
+from oracle.problems import Monodomain, ScalarTest
+from oracle.tissue import coarse_dims, prolong_space, restrict_space
+
+
+def stability(lI, lE, le, Ms, P, K, exponential=True):
+    """R_P(lam_I, lam_E, lam_e) of Sec. 4.1: y_P after P steps of dt = 1 from y = 1."""
+    p = ScalarTest(lI, lE, le)
+    h = Hierarchy([Level(p, M, 1.0, exponential=exponential) for M in Ms])
+    z, _, _ = pfasst_block(h, np.ones((1, p.N)), P, K, tol=0.0)
+    return z[-1][-1][0]
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 6])
+def test_sweeps_reach_collocation_closed_form(M):
+    """K -> inf solves (I - dt(lam_I+lam_E) A(dt lam_e)) y = (1 + dt lam_e A 1) y_n."""
+    lI = np.array([-1.0, -5.0, -0.1, -20.0])
+    lE = np.array([-0.5, -1.0, 0.0, -2.0])
+    le = np.array([-2.0, -30.0, -0.3, -400.0])
+    dt = 0.1
+    lev = Level(ScalarTest(lI, lE, le), M, dt)
+    Y = serial_step(lev, 0, np.ones((1, 4)), 150)
+    for q in range(4):
+        A = exp_colloc_matrix(np.array(dt * le[q]), lev.c)
+        yc = np.linalg.solve(np.eye(M) - dt * (lI[q] + lE[q]) * A, 1.0 + dt * le[q] * A.sum(axis=1))
+        assert np.max(np.abs(Y[1:, 0, q] - yc)) < 1e-12
+
+
+@pytest.mark.parametrize("M,num,den", [
+    (1, [1.0], [1.0, -1.0]),
+    (2, [1.0, 1.0 / 3.0], [1.0, -2.0 / 3.0, 1.0 / 6.0]),
+    (3, [1.0, 2.0 / 5.0, 1.0 / 20.0], [1.0, -3.0 / 5.0, 3.0 / 20.0, -1.0 / 60.0]),
+])
+def test_radau_stability_function(M, num, den):
+    """lam_e = lam_E = 0: converged HSDC is Radau IIA, R(z) = Pade (M-1, M)."""
+    z = np.array([-0.1, -1.0, -7.0, -60.0])
+    r = stability(z, 0.0, 0.0, [M], 1, 200)
+    ref = np.polyval(num[::-1], z) / np.polyval(den[::-1], z)
+    assert np.max(np.abs(r - ref)) < 1e-12
+
+
+class _GatesOnly:
+    """y' = Lam (y - y_inf) with constant diagonal Lam and y_inf (frozen V)."""
+
+    def __init__(self, lam, yinf):
+        self.L = np.asarray(lam, float)[None]
+        self.yi = np.asarray(yinf, float)[None]
+        self.nf, self.N = 1, self.L.shape[1]
+
+    def f_I(self, t, y):
+        return np.zeros_like(y)
+
+    def solve_I(self, t, b, a):
+        return b.copy()
+
+    def f_E(self, t, y):
+        return np.zeros_like(y)
+
+    def lam(self, y):
+        return self.L.copy()
+
+    def y_inf(self, y):
+        return self.yi.copy()
+
+
+@pytest.mark.parametrize("M", [2, 4, 6])
+def test_one_sweep_exact_for_exponential_part(M):
+    """With f_I = f_E = 0 and frozen Lambda, y_inf, one sweep from the spread
+    initial guess gives y_i = y_inf + exp(c_i dt Lambda)(y_n - y_inf) exactly."""
+    lam = np.array([-1e-3, -0.7, -35.0, -900.0, -2.0e4])
+    yinf = np.array([0.3, 0.9, 0.05, 1.0, 0.5])
+    yn = np.array([[0.1, 0.2, 0.9, 0.0, 0.7]])
+    lev = Level(_GatesOnly(lam, yinf), M, 0.05)
+    Y = serial_step(lev, 0, yn, 1)
+    exact = yinf + np.exp(lev.c[:, None] * 0.05 * lam) * (yn - yinf)
+    assert np.max(np.abs(Y[1:, 0, :] - exact)) < 2e-13  # rounding of eq. def_aij_computable
+
+
+def test_naive_sdc_unstable_below_diagonal():
+    """Sec. 4.2: naive SDC (Lambda_n = 0), K = 1, lam_E = -2, M = 6: unstable for
+    lam_e < lam_I; HSDC with the same preconditioner stays stable."""
+    g = np.linspace(-1000.0, 0.0, 61)
+    LI, LE = np.meshgrid(g, g, indexing="ij")
+    lI, le = LI.ravel(), LE.ravel()
+    r = stability(lI, -2.0, le, [6], 1, 1, exponential=False)
+    below, above = le < lI, le > lI
+    assert np.mean(np.abs(r[below]) > 1.0) > 0.99
+    assert np.all(np.abs(r[above]) <= 1.0)
+    r_h = stability(lI, -2.0, le, [6], 1, 1)
+    assert np.max(np.abs(r_h)) <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("Ms,P", [([6], 1), ([6, 3], 1), ([6, 3], 4)])
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_nonstiff_stability(Ms, P, K):
+    """Sec. 4.1, first experiment: lam_E = 0, (lam_I, lam_e) in [-2, 0]^2: |R_P| <= 1."""
+    g = np.linspace(-2.0, 0.0, 21)
+    A, B = np.meshgrid(g, g, indexing="ij")
+    r = stability(A.ravel(), 0.0, B.ravel(), Ms, P, K)
+    assert np.max(np.abs(r)) <= 1.0 + 1e-12
+
+
+def test_stiff_stability_single_level():
+    """Sec. 4.1, stiff regime, L = 1, P = 1: |R| <= 1 after K = 1 and K = 100."""
+    g = np.linspace(-1000.0, 0.0, 31)
+    A, B = np.meshgrid(g, g, indexing="ij")
+    for K in (1, 100):
+        r = stability(A.ravel(), -2.0, B.ravel(), [6], 1, K)
+        assert np.max(np.abs(r)) <= 1.0 + 1e-9
+
+
+class _TwoVar:
+    """Small stiff nonlinear forced problem: v has an implicit linear part and an
+    explicit nonlinear forced part, w is a gate with V-dependent rate."""
+    nf, N = 2, 1
+
+    def f_I(self, t, y):
+        o = np.zeros_like(y)
+        o[0] = -10.0 * y[0]
+        return o
+
+    def solve_I(self, t, b, a):
+        x = b.copy()
+        x[0] = b[0] / (1.0 + 10.0 * a)
+        return x
+
+    def f_E(self, t, y):
+        o = np.zeros_like(y)
+        o[0] = y[0] - y[0] ** 3 / 3.0 - y[1] + np.sin(5.0 * t)
+        return o
+
+    def lam(self, y):
+        o = np.zeros_like(y)
+        o[1] = -(5.0 + 200.0 / (1.0 + np.exp(-4.0 * y[0])))
+        return o
+
+    def y_inf(self, y):
+        o = np.zeros_like(y)
+        o[1] = 1.0 / (1.0 + np.exp(-2.0 * y[0]))
+        return o
+
+
+def _two_var_ref():
+    p = _TwoVar()
+
+    def rhs(t, y):
+        y = y.reshape(2, 1)
+        return (p.f_I(t, y) + p.f_E(t, y) + p.lam(y) * (y - p.y_inf(y))).ravel()
+
+    return p, solve_ivp(rhs, (0.0, 1.0), [1.0, 0.2], method="Radau", rtol=1e-13, atol=1e-15).y[:, -1]
+
+
+def test_order_grows_with_sweeps():
+    """Sec. 5.1: order min(K, M+1) per sweep count; converged M = 4 reaches >= M+1."""
+    p, ref = _two_var_ref()
+    y0 = np.array([[1.0], [0.2]])
+
+    def slope(M, K):
+        e = []
+        for n in (16, 32, 64):
+            y = run_serial(Level(p, M, 1.0 / n), y0, n, K)
+            e.append(np.max(np.abs(y.ravel() - ref)))
+        return np.log2(e[1] / e[2])
+
+    for K in (1, 2, 3, 4):
+        s = slope(4, K)
+        assert K - 0.3 < s < K + 0.6, (K, s)
+    assert slope(4, 40) > 5.0 - 0.2
+
+
+def _ttp_cell():
+    return Monodomain((1,), 0.01, stim_w=np.ones(1), stim_amp=50.0, stim_t0=0.0, stim_dur=1.0)
+
+
+def test_single_cell_trace_against_stiff_integrator():
+    """TTP06 single cell (sigma = 0): converged HSDC vs scipy Radau on a smooth
+    segment of the action potential (2 ms -> 4 ms, V > -40 mV throughout, so no
+    branch point of the h, j rates is crossed)."""
+    p = _ttp_cell()
+
+    def rhs(t, y):
+        y = y.reshape(19, 1)
+        return (p.f_E(t, y) + p.lam(y) * (y - p.y_inf(y))).ravel()
+
+    y0 = ttp06.rest_state()
+    s1 = solve_ivp(lambda t, y: rhs(min(t, 1.0 - 1e-12), y), (0.0, 1.0), y0, method="Radau",
+                   rtol=1e-12, atol=1e-14)
+    ya = solve_ivp(rhs, (1.0, 2.0), s1.y[:, -1], method="Radau", rtol=1e-12, atol=1e-14).y[:, -1]
+    assert ya[0] > 0.0  # an action potential was triggered
+    ref = solve_ivp(rhs, (2.0, 4.0), ya, method="Radau", rtol=1e-13, atol=1e-16).y[:, -1]
+    errs = []
+    for dt in (0.1, 0.05):
+        lev = Level(p, 4, dt)
+        n0 = int(round(2.0 / dt))
+        y = run_serial(lev, ya[:, None], n0, 20, step0=n0).ravel()
+        errs.append(np.max(np.abs(y - ref) / np.abs(ref)))
+    assert errs[1] < 2e-10
+    assert np.log2(errs[0] / errs[1]) > 4.5
+
+
+def test_single_cell_action_potential_shape():
+    """Sanity of the TTP06 restatement (parity unpinned vs the model publication):
+    rest near -85 mV, overshoot above 0 mV, repolarisation within 250-350 ms."""
+    p = _ttp_cell()
+    lev = Level(p, 3, 0.2)
+    Vs = []
+    run_serial(lev, ttp06.rest_state()[:, None], 2000, 2, callback=lambda n, Y: Vs.append(Y[-1, 0, 0]))
+    Vs = np.array(Vs)
+    t = 0.2 * (np.arange(len(Vs)) + 1)
+    assert Vs.max() > 20.0
+    rep = t[(t > 50.0) & (Vs < -75.0)][0]
+    assert 250.0 < rep < 350.0
+    assert abs(Vs[-1] + 85.2) < 1.0
+
+
+def _tiny_tissue(dims, dx=0.025, sigma=(1.0, 1.0, 1.0)):
+    w = np.zeros(int(np.prod(dims)))
+    w[:2] = 1.0
+    return Monodomain(dims, dx, sigma, stim_w=w, stim_amp=50.0, stim_t0=0.0, stim_dur=1.0)
+
+
+def test_pfasst_single_slice_single_level_is_serial_sdc():
+    p = _tiny_tissue((12,))
+    y0 = np.repeat(ttp06.rest_state()[:, None], p.N, 1)
+    lev = Level(p, 3, 0.05)
+    h = Hierarchy([lev])
+    z, _, k = pfasst_block(h, y0, 1, 4, tol=0.0)
+    Y = serial_step(lev, 0, y0, 4)
+    assert k == 4
+    assert np.array_equal(z[0], Y)
+
+
+def test_pfasst_converges_to_serial_collocation():
+    """Converged PFASST (P = 4, L = 2, M = 6,3) equals the serial collocation
+    solution (Sec. 5.1.2: accuracy independent of P once converged)."""
+    p = _tiny_tissue((8,))
+    y0 = np.repeat(ttp06.rest_state()[:, None], p.N, 1)
+    fine, coarse = Level(p, 6, 0.05), Level(p, 3, 0.05)
+    h = Hierarchy([fine, coarse])
+    z, hist, k = pfasst_block(h, y0, 4, 60, tol=1e-13)
+    assert max(hist[-1]) < 1e-13 and k < 60
+    y = y0
+    for n in range(4):
+        Y, _ = collocation_solve(fine, n, y, tol=1e-14)
+        y = Y[-1]
+    assert np.max(np.abs(z[-1][-1] - y)) < 1e-12 * np.max(np.abs(y))
+
+
+def test_pfasst_space_coarsened_converges_to_serial():
+    """Two levels with the coarse level also coarsened 2x in space: the FAS
+    correction keeps the fine collocation solution as the fixed point."""
+    dims = (8, 4)
+    p = _tiny_tissue(dims, sigma=(3.0, 1.0, 1.0))
+    pc = Monodomain(coarse_dims(dims), 0.05, (3.0, 1.0, 1.0), stim_w=restrict_space(p.stim_w, dims),
+                    stim_amp=50.0, stim_t0=0.0, stim_dur=1.0)
+    y0 = np.repeat(ttp06.rest_state()[:, None], p.N, 1)
+    h = Hierarchy([Level(p, 6, 0.1), Level(pc, 3, 0.1)],
+                  space_restrict=[lambda u: restrict_space(u, dims)],
+                  space_prolong=[lambda u: prolong_space(u, dims)])
+    z, hist, k = pfasst_block(h, y0, 4, 80, tol=1e-13)
+    assert max(hist[-1]) < 1e-13
+    y = y0
+    fine = h.levels[0]
+    for n in range(4):
+        Y, _ = collocation_solve(fine, n, y, tol=1e-14)
+        y = Y[-1]
+    assert np.max(np.abs(z[-1][-1] - y)) < 1e-12 * np.max(np.abs(y))
+
+
+def test_run_pfasst_blocks_chain():
+    p = _tiny_tissue((8,))
+    y0 = np.repeat(ttp06.rest_state()[:, None], p.N, 1)
+    h = Hierarchy([Level(p, 4, 0.05), Level(p, 2, 0.05)])
+    y2, iters = run_pfasst(h, y0, 2, 2, 50, 1e-12)
+    y = y0
+    for n in range(4):
+        Y, _ = collocation_solve(h.levels[0], n, y, tol=1e-14)
+        y = Y[-1]
+    assert np.max(np.abs(y2 - y)) < 1e-11 * np.max(np.abs(y))
