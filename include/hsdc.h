@@ -1,0 +1,188 @@
+/*
+ * hsdc.h -- C ABI of the MI355X (gfx950) hybrid spectral deferred correction
+ * library for the monodomain equation.
+ *
+ * Method: de Souza, Pezzuto, Krause, "High-order parallel-in-time method for
+ * the monodomain equation in cardiac electrophysiology" (arXiv 2405.19994).
+ * The semi-discrete problem is y' = f_I + f_E + f_e with y = (V_m, w_a, w_g)
+ * (Sec. 2.2, eqs. sd_sys, def_f_IE, def_Lambda); one HSDC step solves the
+ * exponential collocation system C(y_n) = 1 (x) y_n (Sec. 3.1.2, eq. def_C) by
+ * the preconditioned Picard iteration of eq. prec_picard with the IMEX /
+ * exponential-Euler preconditioner of eq. def_P; PFASST couples P steps
+ * (Sec. 3.2, eqs. erk_sys, def_D, def_Q, Algorithm 1).
+ *
+ * Cell model: ten Tusscher-Panfilov 2006 epicardial cell, 19 states per node:
+ *   0 V;  1 Ca_i 2 Ca_SR 3 Ca_ss 4 Na_i 5 K_i 6 Rbar (w_a, explicit);
+ *   7 m 8 h 9 j 10 xr1 11 xr2 12 xs 13 r 14 s 15 d 16 f 17 f2 18 fCass
+ *   (w_g, exponential).
+ * Units: ms, mV, cm, mS/cm, uF/cm^2, uA/cm^2, mM.
+ *
+ * Layout: a state is field-major (structure of arrays): field f of node p at
+ * y[f * N + p], nodes numbered x fastest, p = ix + nx (iy + ny iz).  All
+ * device arrays passed in are FP64, contiguous, and owned by the caller; the
+ * library copies what it keeps.  All device work is enqueued on the caller's
+ * HIP stream (hipStream_t passed as void *); calls that return host values
+ * synchronise that stream.
+ *
+ * Errors: every call returns an hsdc_status; nothing throws across the ABI.
+ * Argument checks fail with HSDC_EINVAL before any device work;
+ * hsdc_last_error() gives a message.  A context is used by one host thread at
+ * a time.
+ */
+#ifndef HSDC_H
+#define HSDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSDC_NFIELDS 19
+#define HSDC_NAUX 6
+#define HSDC_NGATES 12
+#define HSDC_MAX_M 8
+
+typedef struct hsdc_ctx hsdc_ctx;
+
+typedef enum {
+  HSDC_OK = 0,
+  HSDC_EINVAL = -1,     /* malformed argument; nothing was enqueued            */
+  HSDC_ENOMEM = -2,     /* device allocation failed                            */
+  HSDC_EDEVICE = -3,    /* a HIP runtime call failed                           */
+  HSDC_ENOCONV = -4,    /* a diffusion solve missed cg_rtol within cg_maxit;   */
+                        /* the state was still advanced                        */
+  HSDC_ENONFINITE = -5, /* a residual or state norm is NaN or Inf              */
+  HSDC_ESTATE = -6      /* call not valid in the context's mode                */
+} hsdc_status;
+
+/* Semi-discrete monodomain problem (Sec. 2.1-2.2).  Cell-centred uniform mesh,
+ * node p at ((ix + 1/2) dx, ...), no-flux walls (mirror ghost).  The diffusion
+ * operator is (A V)_p = sum over faces (p,q) of k_pq (V_q - V_p), with
+ * k_pq = sigma_axis / dx^2, or the harmonic mean of sigma_node over the face
+ * divided by dx^2 when sigma_node is given; f_I = (chi Cm)^-1 A V. */
+typedef struct {
+  int32_t dim;               /* 1, 2 or 3                                         */
+  int32_t nx, ny, nz;        /* nodes per axis; unused axes must be 1             */
+  double dx;                 /* cm                                                */
+  double sigma[3];           /* mS/cm, diagonal conductivity tensor (x, y, z)     */
+  const double *sigma_node;  /* device [N] per-node sigma (mS/cm) or NULL         */
+  double chi;                /* surface-to-volume ratio, 1/cm                     */
+  double Cm;                 /* membrane capacitance, uF/cm^2                     */
+  double g_scale[3];         /* multipliers of G_Na, G_CaL, G_Kr (1 = published)  */
+  const double *stim_w;      /* device [N] stimulus weight per node, or NULL      */
+  double stim_amp;           /* uA/cm^2; I_stim = stim_amp * stim_w(x) while      */
+  double stim_t0;            /*   stim_t0 < t <= stim_t0 + stim_dur (window open  */
+  double stim_dur;           /*   on the left, closed on the right)               */
+} hsdc_problem;
+
+/* Method (Sec. 3, Algorithm 1). */
+typedef struct {
+  int32_t levels;            /* 1 (serial HSDC) or 2 (two-level PFASST)           */
+  int32_t M[2];              /* Radau IIA nodes per level, M[0] fine, 1..8        */
+  int32_t space_coarsen;     /* 1, or 2: coarse level on the mesh coarsened 2x    */
+  int32_t P;                 /* time slices per block (1 for serial HSDC)         */
+  double dt;                 /* step size per slice, ms                           */
+  int32_t max_iter;          /* sweeps per step (levels = 1, P = 1) or maximum    */
+                             /* PFASST iterations per block                       */
+  double tol;                /* PFASST stop: all ||r_n||_inf < tol ||y_n||_inf;   */
+                             /* tol <= 0 runs exactly max_iter iterations         */
+  int32_t burn_in;           /* 1: staggered coarse burn-in before a block, P > 1 */
+  double cg_rtol;            /* diffusion solve: ||b - A x||_2 <= cg_rtol ||b||_2 */
+  int32_t cg_maxit;          /* iteration cap per diffusion solve                 */
+} hsdc_method;
+
+/* Counters since init (host copy). */
+typedef struct {
+  int64_t steps;             /* time steps completed (blocks x P for PFASST)      */
+  int64_t sweeps;            /* sweeps on the fine level                          */
+  int64_t coarse_sweeps;     /* sweeps on the coarse level (incl. burn-in)        */
+  int64_t cg_solves;         /* diffusion solves                                  */
+  int64_t cg_iters;          /* CG iterations over all solves                     */
+  int64_t cg_unconverged;    /* solves that hit cg_maxit                          */
+  int64_t pfasst_iters;      /* PFASST iterations                                 */
+  int64_t ionic_evals;       /* node-wise cell-model evaluations (x mesh nodes)   */
+} hsdc_stats;
+
+/* Create a context and its initial state (Sec. 3.1: y(0) = y_0).
+ * y0: device [19][N] initial state, or NULL for the TTP06 epicardial rest state
+ * on every node.  The first step (serial) or block (PFASST: spread of y0 on every
+ * slice, then the burn-in when enabled and P > 1) is prepared, so sweeps and
+ * iterations can be applied at once.  *out receives the context; on failure
+ * *out is NULL.  hip_stream may be NULL (the null stream). */
+hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth,
+                            const double *y0, void *hip_stream, hsdc_ctx **out);
+
+/* Apply nsweeps preconditioned Picard iterations (eq. prec_picard, one forward
+ * substitution with P^-1 of eq. def_P each) to the stage vector of one slice of
+ * the fine level, keeping its start value y_{n,0}.  level must be 0. */
+hsdc_status hsdc_sdc_sweep(hsdc_ctx *ctx, int32_t level, int32_t slice, int32_t nsweeps);
+
+/* Serial mode: nsteps times {max_iter sweeps; y_{n+1} = y_{n,M}; spread y_{n+1}}
+ * (the step applies the sweeps the current step has not had yet).
+ * PFASST mode: nsteps blocks, each iterated until converged or max_iter
+ * (Algorithm 1), then the next block starts from y_{P-1,M}. */
+hsdc_status hsdc_advance(hsdc_ctx *ctx, int32_t nsteps);
+
+/* One iteration of Algorithm 1 on the current block: FAS correction tau,
+ * coarse Q^seq sweep, coarse-grid correction, fine Q^par sweep, residual.
+ * res_host (host [P], may be NULL) receives ||r_n||_inf / ||y_n||_inf;
+ * *all_converged (may be NULL) is 1 when every slice is below tol. */
+hsdc_status hsdc_pfasst_iter(hsdc_ctx *ctx, double *res_host, int32_t *all_converged);
+
+/* Relative residual ||r_n||_inf / ||y_n||_inf of every slice of the fine level,
+ * r_n = C(y_n) - 1 (x) y_{n-1,M} (rows of D(z) - b in Algorithm 1; y_{-1,M} is
+ * the block start value).  level must be 0.  res_host: host [P]. */
+hsdc_status hsdc_residual(hsdc_ctx *ctx, int32_t level, double *res_host);
+
+/* Copy stage `node` (0..M) of `slice` of `level` to / from device [19][N_level]. */
+hsdc_status hsdc_get_state(const hsdc_ctx *ctx, int32_t level, int32_t slice, int32_t node,
+                           double *dst);
+hsdc_status hsdc_set_state(hsdc_ctx *ctx, int32_t level, int32_t slice, int32_t node,
+                           const double *src);
+
+/* Current global step index n of the first slice (time t_n = n dt). */
+int64_t hsdc_current_step(const hsdc_ctx *ctx);
+hsdc_status hsdc_get_stats(const hsdc_ctx *ctx, hsdc_stats *out);
+
+void hsdc_destroy(hsdc_ctx *ctx);
+/* Message of the last failed call on ctx (or of the last failed context-free
+ * call when ctx is NULL).  Never NULL. */
+const char *hsdc_last_error(const hsdc_ctx *ctx);
+
+/* ---- exported building blocks (used by the parity tests) ---------------- */
+
+/* Node-wise TTP06 evaluation at n states y (device [19][n]): I_ion (pA/pF,
+ * device [n]), h_a (device [6][n]), Lambda_g = -1/tau (device [12][n]) and
+ * w_g,inf (device [12][n]) (eqs. monodomain_g_lambda, def_Lambda). */
+hsdc_status hsdc_ionic_eval(int64_t n, const double *y, const double *g_scale_host3,
+                            double *I_ion, double *h_a, double *lam, double *w_inf,
+                            void *hip_stream);
+
+/* phi_k(x) for k = 1..kmax (Appendix A, eq. def_phik): out device [kmax][n]. */
+hsdc_status hsdc_phi(int64_t n, const double *x, int32_t kmax, double *out, void *hip_stream);
+
+/* out = (chi Cm)^-1 A v for the operator of *prob (device [N] each). */
+hsdc_status hsdc_apply_diffusion(const hsdc_problem *prob, const double *v, double *out,
+                                 void *hip_stream);
+
+/* Solve (I - a (chi Cm)^-1 A) x = b by CG to ||b - A x||_2 <= rtol ||b||_2;
+ * x (device [N]) holds the initial guess on entry.  *iters_host receives the
+ * iteration count.  Returns HSDC_ENOCONV when maxit is reached. */
+hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const double *b, double *x,
+                                 double rtol, int32_t maxit, int32_t *iters_host,
+                                 void *hip_stream);
+
+/* Exponential collocation coefficients a_ij(z) (eq. def_aij), computed on the
+ * device as sum_k c_i^k w_j^{k-1} phi_k(c_i z) (eq. def_aij_computable) with
+ * the Radau IIA nodes and Fornberg weights of the library: z device [n],
+ * out device [n][M][M] (row i, column j); c_host (host [M], may be NULL)
+ * receives the nodes c_1..c_M. */
+hsdc_status hsdc_colloc_coefficients(int32_t M, int64_t n, const double *z, double *out,
+                                     double *c_host, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSDC_H */

@@ -1,0 +1,128 @@
+// hsdc_internal.h -- declarations shared by the host runtime and the HIP
+// kernels of libhsdc (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hsdc.h"
+
+namespace hsdc {
+
+constexpr int NF = HSDC_NFIELDS;
+constexpr int NG = HSDC_NGATES;
+constexpr int GATE0 = 7;  // first gate field
+constexpr int MAXM = HSDC_MAX_M;
+constexpr int BLOCK = 256;
+
+// Mesh and diffusion operator K = (chi Cm)^-1 A (cell-centred, no-flux).
+struct Grid {
+  int dim, nx, ny, nz;
+  int64_t N;    // nodes
+  int64_t Np;   // padded row length (multiple of 64 doubles)
+  double cx, cy, cz;           // sigma_axis / (dx^2 chi Cm) for uniform sigma
+  const double *kx, *ky, *kz;  // per-node face coefficients (face p -> p+e_axis), or null
+};
+
+// Collocation data of one level (host-computed in FP64, passed by value).
+struct Colloc {
+  int M;
+  double dt;
+  double c[MAXM];           // c_1..c_M
+  double d[MAXM];           // d_1..d_M
+  double W[MAXM][MAXM];     // W[k][j] = l_j^{(k)}(0)
+  double Q[MAXM][MAXM];     // a_ij(0)
+  double cpow[MAXM][MAXM + 1];  // c_i^k
+  double invfact[MAXM + 2];     // 1/k!
+};
+
+// Strided view of a set of stage vectors on one level.
+struct Stages {
+  double *Y;    // [P][M+1][NF][Np]
+  double *G;    // [P][M+1][NF][Np]  reaction part of g at each stage
+  double *FV;   // [P][M+1][Np]      K V at each stage
+  double *RH;   // [P][M][NF][Np]    assembled right-hand-side differences
+  double *L0;   // [P][NG][Np]       Lambda of the anchor of the current iterate
+  double *Lu;   // [P][NG][Np]       Lambda of the new anchor u
+  double *B;    // [P][Np]           diffusion right-hand side
+  int64_t Np;
+  int M;
+  __host__ __device__ int64_t sY() const { return (int64_t)(M + 1) * NF * Np; }
+  __host__ __device__ int64_t sS() const { return (int64_t)NF * Np; }
+  __host__ __device__ int64_t sFV() const { return (int64_t)(M + 1) * Np; }
+  __host__ __device__ int64_t sRH() const { return (int64_t)M * NF * Np; }
+  __host__ __device__ int64_t sL() const { return (int64_t)NG * Np; }
+};
+
+struct Stim {
+  const double *w;  // [Np] or null
+  double amp, t0, dur, eps;
+  double Cm;
+};
+
+struct CgScalars {
+  double rr, bb, pq, alpha, beta;
+  int32_t it, done, pad0, pad1;
+};
+
+// ---- kernel launch wrappers (defined in hsdc_kernels.hip) -------------------
+hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                              const Stim &stim, double gs0, double gs1, double gs2, int slice0,
+                              int nslices, int stage0, int nstages, int64_t step0,
+                              double *L_anchor_out, const double *L_anchor_in);
+hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
+                              int nslices, int stage0, int nstages);
+hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                         const Stim &stim, int slice0, int nslices, int64_t step0,
+                         bool copy_Y_from_stage0);
+hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                           int slice0, int nslices, const double *RI, int64_t sRI);
+hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                              const Stim &stim, double gs0, double gs1, double gs2, int slice0,
+                              int nslices, int i, int64_t step0);
+hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                           int slice0, int nslices, const double *y_block0, double *part,
+                           int nblk, double *out2, const double *Rt, int Mc, double *RI,
+                           int64_t sRI);
+int residual_blocks(const Grid &g);
+hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sdst,
+                              const double *src, int64_t ssrc, int nf, int nslices);
+
+// CG on (I - a K) x = b, batched over slices with strided vectors.
+struct CgBatch {
+  double *x; int64_t sx;    // solution (in place), slice stride
+  const double *b; int64_t sb;
+  double *r, *p0, *p1, *q;  // [nslices][Np]
+  double *part;             // [nslices][2][nblk]
+  unsigned *cnt;            // [nslices]
+  CgScalars *sc;            // [nslices]
+  int nslices, nblk;
+  double a, tol2;
+  int maxit;
+};
+int cg_blocks(const Grid &g);
+hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb);
+hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int parity);
+hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out);
+
+// transfers (space coarsening 2x or identity) between a fine and a coarse level
+hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
+                                  const double *Yf, int64_t sYf, int Mf, const double *Rt,
+                                  int Mc, double *Yc, int64_t sYc, double *Yc_copy, int nslices);
+hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
+                                  const double *src, int64_t ssrc, double *dst, int64_t sdst,
+                                  int nrows, int nslices);
+hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
+                                  const double *Yc, const double *Sz, int64_t sYc, int Mc,
+                                  const double *Tt, int Mf, double *Yf, int64_t sYf,
+                                  int nslices, double *scratch);
+
+// building blocks exported for tests
+hipError_t launch_ionic_test(hipStream_t s, int64_t n, const double *y, double gs0, double gs1,
+                             double gs2, double *I_ion, double *ha, double *lam, double *winf);
+hipError_t launch_phi_test(hipStream_t s, int64_t n, const double *x, int kmax, double *out);
+hipError_t launch_aij_test(hipStream_t s, int64_t n, const double *z, const Colloc &co,
+                           double *out);
+hipError_t launch_fill_rest(hipStream_t s, int64_t N, int64_t Np, double *y);
+
+}  // namespace hsdc

@@ -1,0 +1,969 @@
+// hsdc_kernels.hip -- gfx950 kernels of the hybrid SDC / PFASST hot path.
+//
+// One lane per mesh node, states field-major (SoA) so every field load is a
+// coalesced 64-lane FP64 row.  Nothing here is a dense contraction, so no MFMA:
+// the cell model is bound by FP64 VALU work (exp/log/div sequences), the
+// stencil, CG vector updates, assembly, residual and transfers by HBM bytes.
+#include <hip/hip_runtime.h>
+
+#include "hsdc_internal.h"
+#include "ttp06_device.h"
+
+namespace hsdc {
+
+// ---------------------------------------------------------------------------
+// phi functions (Appendix A, eq. def_phik)
+// ---------------------------------------------------------------------------
+
+// phi_1(x) = (e^x - 1)/x, phi_1(0) = 1.
+__device__ __forceinline__ double phi1(double x) { return x == 0.0 ? 1.0 : expm1(x) / x; }
+
+// phi_1(x) .. phi_M(x) into out[0..M-1].  For |x| >= M the forward recurrence
+// phi_{k+1} = (phi_k - 1/k!)/x from phi_1 = expm1(x)/x is stable (errors shrink by
+// k/|x| per step); for |x| < M the Taylor series sum_m x^m/(m+M)! of phi_M and the
+// backward recurrence phi_k = 1/k! + x phi_{k+1} are.
+template <int M>
+__device__ __forceinline__ void phis(double x, const double *invfact, double *out) {
+  if (fabs(x) >= (double)M) {
+    double p = expm1(x) / x;
+    out[0] = p;
+#pragma unroll
+    for (int k = 1; k < M; ++k) {
+      p = (p - invfact[k]) / x;
+      out[k] = p;
+    }
+  } else {
+    double term = invfact[M], acc = term;
+    for (int m = 1; m < 48; ++m) {
+      term *= x / (double)(m + M);
+      acc += term;
+      if (fabs(term) <= 1e-17 * fabs(acc)) break;
+    }
+    out[M - 1] = acc;
+#pragma unroll
+    for (int k = M - 1; k >= 1; --k) {
+      acc = invfact[k] + x * acc;
+      out[k - 1] = acc;
+    }
+  }
+}
+
+// I_i = sum_j a_ij(z) g_j, i, j = 1..M, with a_ij(z) = sum_k c_i^k w_j^{k-1} phi_k(c_i z)
+// (eq. def_aij_computable) evaluated through the moments m_k = sum_j w_j^{k-1} g_j;
+// z = 0 uses the collocation weights a(0) = Q.
+template <int M>
+__device__ __forceinline__ void colloc_integrals(const Colloc &co, double z, const double *g,
+                                                 double *I) {
+  if (z == 0.0) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) s += co.Q[i][j] * g[j];
+      I[i] = s;
+    }
+    return;
+  }
+  double mom[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) s += co.W[k][j] * g[j];
+    mom[k] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    double ph[M];
+    phis<M>(co.c[i] * z, co.invfact, ph);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) s += co.cpow[i][k + 1] * ph[k] * mom[k];
+    I[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// NaN-propagating maximum
+__device__ __forceinline__ double nmax(double a, double b) { return (b != b || b > a) ? b : a; }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = nmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+// Sum over the block (BLOCK threads); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < BLOCK / 64; ++k) t += lds[k];
+  }
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ double block_max(double v, double *lds) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    t = lds[0];
+#pragma unroll
+    for (int k = 1; k < BLOCK / 64; ++k) t = nmax(t, lds[k]);
+  }
+  __syncthreads();
+  return t;
+}
+
+// Deterministic grid reduction: every block writes its partial sums; the last
+// block to finish (device-scope counter) adds the partials in a fixed order.
+// Returns true in the last block, with tot[0..NS-1] valid in thread 0.
+template <int NS>
+__device__ __forceinline__ bool grid_sums(const double (&v)[NS], double *part, int nblk,
+                                          unsigned *cnt, double (&tot)[NS]) {
+  __shared__ double lds[BLOCK / 64];
+  __shared__ bool last;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double b = block_sum(v[s], lds);
+    if (threadIdx.x == 0) part[s * nblk + blockIdx.x] = b;
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(cnt, 1u);
+    last = (prev == (unsigned)(nblk - 1));
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += BLOCK) acc += part[s * nblk + k];
+    tot[s] = block_sum(acc, lds);
+  }
+  if (threadIdx.x == 0) *cnt = 0u;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// diffusion operator K = (chi Cm)^-1 A, cell-centred, no-flux
+// ---------------------------------------------------------------------------
+
+struct Ijk {
+  int ix, iy, iz;
+};
+__device__ __forceinline__ Ijk ijk(const Grid &g, int64_t p) {
+  Ijk r;
+  r.ix = (int)(p % g.nx);
+  const int64_t q = p / g.nx;
+  r.iy = (int)(q % g.ny);
+  r.iz = (int)(q / g.ny);
+  return r;
+}
+
+// (K v)_p with v given through val(k) (so callers can form v on the fly).
+template <int DIM, bool PN, class Val>
+__device__ __forceinline__ double applyK(const Grid &g, int64_t p, const Ijk &c, double vc,
+                                         Val &&val) {
+  if (PN) {
+    double acc = 0.0;
+    if (c.ix > 0) acc += g.kx[p - 1] * (val(p - 1) - vc);
+    if (c.ix < g.nx - 1) acc += g.kx[p] * (val(p + 1) - vc);
+    if (DIM >= 2) {
+      if (c.iy > 0) acc += g.ky[p - g.nx] * (val(p - g.nx) - vc);
+      if (c.iy < g.ny - 1) acc += g.ky[p] * (val(p + g.nx) - vc);
+    }
+    if (DIM >= 3) {
+      const int64_t pl = (int64_t)g.nx * g.ny;
+      if (c.iz > 0) acc += g.kz[p - pl] * (val(p - pl) - vc);
+      if (c.iz < g.nz - 1) acc += g.kz[p] * (val(p + pl) - vc);
+    }
+    return acc;
+  }
+  double ax = 0.0;
+  if (c.ix > 0) ax += val(p - 1) - vc;
+  if (c.ix < g.nx - 1) ax += val(p + 1) - vc;
+  double acc = g.cx * ax;
+  if (DIM >= 2) {
+    double ay = 0.0;
+    if (c.iy > 0) ay += val(p - g.nx) - vc;
+    if (c.iy < g.ny - 1) ay += val(p + g.nx) - vc;
+    acc += g.cy * ay;
+  }
+  if (DIM >= 3) {
+    const int64_t pl = (int64_t)g.nx * g.ny;
+    double az = 0.0;
+    if (c.iz > 0) az += val(p - pl) - vc;
+    if (c.iz < g.nz - 1) az += val(p + pl) - vc;
+    acc += g.cz * az;
+  }
+  return acc;
+}
+
+#define HSDC_DISPATCH_OP(g, ...)                                    \
+  do {                                                              \
+    const bool pn_ = (g).kx != nullptr;                             \
+    if ((g).dim == 1) {                                             \
+      if (pn_) { constexpr int DIM = 1; constexpr bool PN = true; __VA_ARGS__; }  \
+      else { constexpr int DIM = 1; constexpr bool PN = false; __VA_ARGS__; }     \
+    } else if ((g).dim == 2) {                                      \
+      if (pn_) { constexpr int DIM = 2; constexpr bool PN = true; __VA_ARGS__; }  \
+      else { constexpr int DIM = 2; constexpr bool PN = false; __VA_ARGS__; }     \
+    } else {                                                        \
+      if (pn_) { constexpr int DIM = 3; constexpr bool PN = true; __VA_ARGS__; }  \
+      else { constexpr int DIM = 3; constexpr bool PN = false; __VA_ARGS__; }     \
+    }                                                               \
+  } while (0)
+
+#define HSDC_DISPATCH_M(M_, ...)                               \
+  do {                                                         \
+    switch (M_) {                                              \
+      case 1: { constexpr int M = 1; __VA_ARGS__; } break;     \
+      case 2: { constexpr int M = 2; __VA_ARGS__; } break;     \
+      case 3: { constexpr int M = 3; __VA_ARGS__; } break;     \
+      case 4: { constexpr int M = 4; __VA_ARGS__; } break;     \
+      case 5: { constexpr int M = 5; __VA_ARGS__; } break;     \
+      case 6: { constexpr int M = 6; __VA_ARGS__; } break;     \
+      case 7: { constexpr int M = 7; __VA_ARGS__; } break;     \
+      case 8: { constexpr int M = 8; __VA_ARGS__; } break;     \
+      default: return hipErrorInvalidValue;                    \
+    }                                                          \
+  } while (0)
+
+static inline unsigned nblocks(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+// ---------------------------------------------------------------------------
+// cell model at stages: G_j = f_E + f_e + Lambda(u)(u - y_j) (reaction part of g)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double stim_value(const Stim &st, double t, int64_t p) {
+  if (st.w == nullptr) return 0.0;
+  const bool on = (t > st.t0 + st.eps) && (t <= st.t0 + st.dur + st.eps);
+  return on ? st.amp * st.w[p] : 0.0;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_eval_stages(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
+              int slice0, int stage0, int64_t step0, double *Lout, const double *Lin) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int n = slice0 + blockIdx.z;
+  const int j = stage0 + blockIdx.y;
+  const int64_t Np = st.Np;
+  const double *y = st.Y + n * st.sY() + j * st.sS();
+  const double *u = st.Y + n * st.sY();
+  double *G = st.G + n * st.sY() + j * st.sS();
+  double yv[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) yv[f] = y[f * Np + p];
+  const double cj = (j == 0) ? 0.0 : co.c[j - 1];
+  const double t = ((double)(step0 + n) + cj) * co.dt;
+  const double *La = (j == 0) ? nullptr : Lin + n * st.sL();
+  double *Lo = (j == 0 && Lout) ? Lout + n * st.sL() : nullptr;
+  ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
+    const double lam = -1.0 / tau;
+    const double w = yv[GATE0 + k];
+    double gv = lam * (w - inf);
+    if (La) gv += La[k * Np + p] * (u[(GATE0 + k) * Np + p] - w);
+    G[(GATE0 + k) * Np + p] = gv;
+    if (Lo) Lo[k * Np + p] = lam;
+  });
+  double I_ion, ha[6];
+  ttp06::currents(yv, gs0, gs1, gs2, I_ion, ha);
+  G[p] = (stim_value(stim, t, p) - stim.Cm * I_ion) / stim.Cm;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) G[(1 + k) * Np + p] = ha[k];
+}
+
+hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                              const Stim &stim, double gs0, double gs1, double gs2, int slice0,
+                              int nslices, int stage0, int nstages, int64_t step0,
+                              double *L_anchor_out, const double *L_anchor_in) {
+  if (nslices <= 0 || nstages <= 0) return hipSuccess;
+  dim3 grid(nblocks(g.N), nstages, nslices);
+  hipLaunchKernelGGL(k_eval_stages, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
+                     slice0, stage0, step0, L_anchor_out, L_anchor_in);
+  return hipGetLastError();
+}
+
+// FV_j = K V_j at stages.
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(BLOCK) k_spmv_stages(Grid g, Stages st, int slice0, int stage0) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int n = slice0 + blockIdx.z;
+  const int j = stage0 + blockIdx.y;
+  const double *v = st.Y + n * st.sY() + j * st.sS();
+  const Ijk c = ijk(g, p);
+  const double vc = v[p];
+  st.FV[n * st.sFV() + j * st.Np + p] = applyK<DIM, PN>(g, p, c, vc, [&](int64_t k) { return v[k]; });
+}
+
+hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
+                              int nslices, int stage0, int nstages) {
+  if (nslices <= 0 || nstages <= 0) return hipSuccess;
+  dim3 grid(nblocks(g.N), nstages, nslices);
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_spmv_stages<DIM, PN>), grid, dim3(BLOCK), 0, s, g, st,
+                                         slice0, stage0));
+  return hipGetLastError();
+}
+
+// Spread stage 0 (Y optionally, G, FV) to stages 1..M; the stimulus part of the
+// V entry of G follows the stage time.
+__global__ void __launch_bounds__(BLOCK)
+k_spread(Grid g, Stages st, Colloc co, Stim stim, int slice0, int64_t step0, int copyY) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int n = slice0 + blockIdx.z;
+  const int64_t Np = st.Np;
+  double *Y = st.Y + n * st.sY();
+  double *G = st.G + n * st.sY();
+  double *FV = st.FV + n * st.sFV();
+  const double t0 = ((double)(step0 + n)) * co.dt;
+  const double s0 = stim_value(stim, t0, p);
+  const double fv = FV[p];
+  for (int j = 1; j <= st.M; ++j) {
+    const double tj = ((double)(step0 + n) + co.c[j - 1]) * co.dt;
+    const double sj = stim_value(stim, tj, p);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      double gv = G[f * Np + p];
+      if (f == 0 && sj != s0) gv += (sj - s0) / stim.Cm;
+      G[j * st.sS() + f * Np + p] = gv;
+      if (copyY) Y[j * st.sS() + f * Np + p] = Y[f * Np + p];
+    }
+    FV[j * Np + p] = fv;
+  }
+}
+
+hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                         const Stim &stim, int slice0, int nslices, int64_t step0,
+                         bool copy_Y_from_stage0) {
+  dim3 grid(nblocks(g.N), 1, nslices);
+  hipLaunchKernelGGL(k_spread, grid, dim3(BLOCK), 0, s, g, st, co, stim, slice0, step0,
+                     copy_Y_from_stage0 ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sweep right-hand side: RH_i = R_i - R_{i-1} of eq. prec_picard in node-to-node
+// form,  dt (I_i - I_{i-1}) - dt d_i Phi_i(y^k) (+ FAS: I replaced by the
+// restricted fine integrals RI).
+// ---------------------------------------------------------------------------
+
+template <int M>
+__global__ void __launch_bounds__(BLOCK)
+k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t sRI) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int n = slice0 + blockIdx.z;
+  const int64_t Np = st.Np;
+  const double *G = st.G + n * st.sY();
+  const double *FV = st.FV + n * st.sFV();
+  const double *L0 = st.L0 + n * st.sL();
+  double *RH = st.RH + n * st.sRH();
+  const double dt = co.dt;
+  double fv[M + 1];
+#pragma unroll
+  for (int j = 1; j <= M; ++j) fv[j] = FV[j * Np + p];
+  for (int f = 0; f < NF; ++f) {
+    double Gv[M + 1], gfull[M], I[M];
+#pragma unroll
+    for (int j = 0; j <= M; ++j) Gv[j] = G[j * st.sS() + f * Np + p];
+#pragma unroll
+    for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + (f == 0 ? fv[j + 1] : 0.0);
+    const double z = (f >= GATE0) ? dt * L0[(f - GATE0) * Np + p] : 0.0;
+    if (RI) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) I[i] = RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
+    } else {
+      colloc_integrals<M>(co, z, gfull, I);
+    }
+    double prevI = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      const double ph = (f >= GATE0) ? phi1(co.d[i] * z) : 1.0;
+      const double Phi = (f == 0 ? fv[i + 1] : 0.0) + ph * Gv[i];
+      RH[(int64_t)i * st.sS() + f * Np + p] = dt * (I[i] - prevI) - dt * co.d[i] * Phi;
+      prevI = I[i];
+    }
+  }
+}
+
+hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                           int slice0, int nslices, const double *RI, int64_t sRI) {
+  dim3 grid(nblocks(g.N), 1, nslices);
+  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_assemble<M>), grid, dim3(BLOCK), 0, s, g, st, co,
+                                           slice0, RI, sRI));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// node i of the forward substitution with P (eq. def_P): explicit f_E,
+// exponential Euler on the gates (phi_1(d_i dt Lambda(u))), and the right-hand
+// side of the implicit diffusion solve for V.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(BLOCK)
+k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
+              int slice0, int i, int64_t step0) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int n = slice0 + blockIdx.z;
+  const int64_t Np = st.Np;
+  const double *Yp = st.Y + n * st.sY() + (int64_t)(i - 1) * st.sS();
+  double *Yi = st.Y + n * st.sY() + (int64_t)i * st.sS();
+  const double *u = st.Y + n * st.sY();
+  const double *RH = st.RH + n * st.sRH() + (int64_t)(i - 1) * st.sS();
+  const double *Lu = st.Lu + n * st.sL();
+  double *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
+  const double ddt = co.dt * co.d[i - 1];
+  double yv[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) yv[f] = Yp[f * Np + p];
+  if (i == 1) {
+    // y_{n,0} = u: its reaction term was evaluated with the anchor
+#pragma unroll
+    for (int f = 1; f < NF; ++f) {
+      const double gv = Gp[f * Np + p];
+      const double ph = (f >= GATE0) ? phi1(ddt * Lu[(f - GATE0) * Np + p]) : 1.0;
+      Yi[f * Np + p] = yv[f] + RH[f * Np + p] + ddt * ph * gv;
+    }
+    st.B[n * Np + p] = yv[0] + RH[p] + ddt * Gp[p];
+    return;
+  }
+  const double t = ((double)(step0 + n) + co.c[i - 2]) * co.dt;
+  ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
+    const int f = GATE0 + k;
+    const double lu = Lu[k * Np + p];
+    const double w = yv[f];
+    const double gv = (-1.0 / tau) * (w - inf) + lu * (u[f * Np + p] - w);
+    Gp[f * Np + p] = gv;
+    Yi[f * Np + p] = w + RH[f * Np + p] + ddt * phi1(ddt * lu) * gv;
+  });
+  double I_ion, ha[6];
+  ttp06::currents(yv, gs0, gs1, gs2, I_ion, ha);
+  const double gV = (stim_value(stim, t, p) - stim.Cm * I_ion) / stim.Cm;
+  Gp[p] = gV;
+  st.B[n * Np + p] = yv[0] + RH[p] + ddt * gV;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    Gp[(1 + k) * Np + p] = ha[k];
+    Yi[(1 + k) * Np + p] = yv[1 + k] + RH[(1 + k) * Np + p] + ddt * ha[k];
+  }
+}
+
+hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                              const Stim &stim, double gs0, double gs1, double gs2, int slice0,
+                              int nslices, int i, int64_t step0) {
+  dim3 grid(nblocks(g.N), 1, nslices);
+  hipLaunchKernelGGL(k_node_update, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
+                     slice0, i, step0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// residual r_n = C(y_n) - 1 (x) u_prev (Algorithm 1), per-slice inf norms of r
+// and y; optionally the time-restricted integrals RI_i = sum_l R_il I_l.
+// ---------------------------------------------------------------------------
+
+template <int M>
+__global__ void __launch_bounds__(BLOCK)
+k_residual(Grid g, Stages st, Colloc co, int slice0, const double *yblk0, double *part, int nblk,
+           const double *Rt, int Mc, double *RI, int64_t sRI) {
+  __shared__ double lds[BLOCK / 64];
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int n = slice0 + blockIdx.z;
+  const int64_t Np = st.Np;
+  double rmax = 0.0, ymax = 0.0;
+  if (p < g.N) {
+    const double *Y = st.Y + n * st.sY();
+    const double *G = st.G + n * st.sY();
+    const double *FV = st.FV + n * st.sFV();
+    const double *L0 = st.L0 + n * st.sL();
+    const double *up = (n == 0) ? yblk0 : st.Y + (n - 1) * st.sY() + (int64_t)M * st.sS();
+    double fv[M + 1];
+#pragma unroll
+    for (int j = 1; j <= M; ++j) fv[j] = FV[j * Np + p];
+    for (int f = 0; f < NF; ++f) {
+      double gfull[M], I[M];
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        gfull[j] = G[(j + 1) * st.sS() + f * Np + p] + (f == 0 ? fv[j + 1] : 0.0);
+      const double z = (f >= GATE0) ? co.dt * L0[(f - GATE0) * Np + p] : 0.0;
+      colloc_integrals<M>(co, z, gfull, I);
+      const double u = up[f * Np + p];
+      const double y0 = Y[f * Np + p];
+      rmax = nmax(rmax, fabs(y0 - u));
+      ymax = nmax(ymax, fabs(y0));
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        const double yi = Y[(i + 1) * st.sS() + f * Np + p];
+        rmax = nmax(rmax, fabs(yi - co.dt * I[i] - u));
+        ymax = nmax(ymax, fabs(yi));
+      }
+      if (RI) {
+        for (int ic = 0; ic < Mc; ++ic) {
+          double s = 0.0;
+#pragma unroll
+          for (int l = 0; l < M; ++l) s += Rt[(ic + 1) * (M + 1) + (l + 1)] * I[l];
+          RI[n * sRI + ((int64_t)ic * NF + f) * Np + p] = s;
+        }
+      }
+    }
+  }
+  const double br = block_max(rmax, lds);
+  const double by = block_max(ymax, lds);
+  if (threadIdx.x == 0) {
+    part[((int64_t)blockIdx.z * nblk + blockIdx.x) * 2 + 0] = br;
+    part[((int64_t)blockIdx.z * nblk + blockIdx.x) * 2 + 1] = by;
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_reduce_max2(const double *part, int nblk, double *out) {
+  __shared__ double lds[BLOCK / 64];
+  const int n = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += BLOCK) {
+    a = nmax(a, part[((int64_t)n * nblk + k) * 2 + 0]);
+    b = nmax(b, part[((int64_t)n * nblk + k) * 2 + 1]);
+  }
+  a = block_max(a, lds);
+  b = block_max(b, lds);
+  if (threadIdx.x == 0) {
+    out[2 * n] = a;
+    out[2 * n + 1] = b;
+  }
+}
+
+int residual_blocks(const Grid &g) { return (int)nblocks(g.N); }
+
+hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                           int slice0, int nslices, const double *y_block0, double *part,
+                           int nblk, double *out2, const double *Rt, int Mc, double *RI,
+                           int64_t sRI) {
+  dim3 grid(nblocks(g.N), 1, nslices);
+  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_residual<M>), grid, dim3(BLOCK), 0, s, g, st, co,
+                                           slice0, y_block0, part, nblk, Rt, Mc, RI, sRI));
+  hipLaunchKernelGGL(k_reduce_max2, dim3(nslices), dim3(BLOCK), 0, s, part, nblk, out2);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_copy_fields(int64_t Np, double *dst, int64_t sdst, const double *src, int64_t ssrc, int nf) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= Np) return;
+  const int n = blockIdx.z;
+  for (int f = 0; f < nf; ++f) dst[n * sdst + f * Np + p] = src[n * ssrc + f * Np + p];
+}
+
+hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sdst,
+                              const double *src, int64_t ssrc, int nf, int nslices) {
+  if (nslices <= 0) return hipSuccess;
+  dim3 grid(nblocks(Np), 1, nslices);
+  hipLaunchKernelGGL(k_copy_fields, grid, dim3(BLOCK), 0, s, Np, dst, sdst, src, ssrc, nf);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// CG on (I - a K) x = b, batched over slices; two kernels per iteration:
+//   k_cg_pq: p = r + beta p_old (formed on the fly at the stencil points),
+//            q = (I - a K) p, partial p.q  -> alpha = rr / pq
+//   k_cg_xr: x += alpha p, r -= alpha q, partial r.r -> beta, convergence
+// Scalars stay on the device; finished slices return at once.
+// ---------------------------------------------------------------------------
+
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatch cb) {
+  const int n = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const double *x = cb.x + n * cb.sx;
+  const double *b = cb.b + n * cb.sb;
+  double *r = cb.r + n * g.Np;
+  double v[2] = {0.0, 0.0};
+  if (p < g.N) {
+    const Ijk c = ijk(g, p);
+    const double xc = x[p];
+    const double Ax = xc - cb.a * applyK<DIM, PN>(g, p, c, xc, [&](int64_t k) { return x[k]; });
+    const double rv = b[p] - Ax;
+    r[p] = rv;
+    v[0] = rv * rv;
+    v[1] = b[p] * b[p];
+  }
+  double tot[2];
+  if (grid_sums<2>(v, cb.part + (int64_t)n * 2 * cb.nblk, cb.nblk, cb.cnt + n, tot) &&
+      threadIdx.x == 0) {
+    CgScalars &sc = cb.sc[n];
+    sc.rr = tot[0];
+    sc.bb = tot[1];
+    sc.beta = 0.0;
+    sc.alpha = 0.0;
+    sc.pq = 0.0;
+    sc.it = 0;
+    sc.done = (tot[0] <= cb.tol2 * tot[1] || tot[0] == 0.0) ? 1 : 0;
+  }
+}
+
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(BLOCK) k_cg_pq(Grid g, CgBatch cb, int parity) {
+  const int n = blockIdx.y;
+  if (cb.sc[n].done) return;
+  const double beta = cb.sc[n].beta;
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const double *r = cb.r + n * g.Np;
+  const double *pold = (parity ? cb.p1 : cb.p0) + n * g.Np;
+  double *pnew = (parity ? cb.p0 : cb.p1) + n * g.Np;
+  double *q = cb.q + n * g.Np;
+  double v[1] = {0.0};
+  if (p < g.N) {
+    const Ijk c = ijk(g, p);
+    auto val = [&](int64_t k) { return beta == 0.0 ? r[k] : r[k] + beta * pold[k]; };
+    const double pc = val(p);
+    const double qv = pc - cb.a * applyK<DIM, PN>(g, p, c, pc, val);
+    pnew[p] = pc;
+    q[p] = qv;
+    v[0] = pc * qv;
+  }
+  double tot[1];
+  if (grid_sums<1>(v, cb.part + (int64_t)n * 2 * cb.nblk, cb.nblk, cb.cnt + n, tot) &&
+      threadIdx.x == 0) {
+    CgScalars &sc = cb.sc[n];
+    sc.pq = tot[0];
+    sc.alpha = sc.rr / tot[0];
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_cg_xr(Grid g, CgBatch cb, int parity) {
+  const int n = blockIdx.y;
+  if (cb.sc[n].done) return;
+  const double alpha = cb.sc[n].alpha;
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  double *x = cb.x + n * cb.sx;
+  const double *pnew = (parity ? cb.p0 : cb.p1) + n * g.Np;
+  double *r = cb.r + n * g.Np;
+  const double *q = cb.q + n * g.Np;
+  double v[1] = {0.0};
+  if (p < g.N) {
+    x[p] += alpha * pnew[p];
+    const double rv = r[p] - alpha * q[p];
+    r[p] = rv;
+    v[0] = rv * rv;
+  }
+  double tot[1];
+  if (grid_sums<1>(v, cb.part + (int64_t)n * 2 * cb.nblk, cb.nblk, cb.cnt + n, tot) &&
+      threadIdx.x == 0) {
+    CgScalars &sc = cb.sc[n];
+    sc.beta = tot[0] / sc.rr;
+    sc.rr = tot[0];
+    sc.it += 1;
+    sc.done = (tot[0] <= cb.tol2 * sc.bb || sc.it >= cb.maxit || tot[0] == 0.0) ? 1 : 0;
+  }
+}
+
+int cg_blocks(const Grid &g) { return (int)nblocks(g.N); }
+
+hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb) {
+  dim3 grid(cb.nblk, cb.nslices);
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_init<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int parity) {
+  dim3 grid(cb.nblk, cb.nslices);
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_pq<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb,
+                                         parity));
+  hipLaunchKernelGGL(k_cg_xr, grid, dim3(BLOCK), 0, s, g, cb, parity);
+  return hipGetLastError();
+}
+
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(BLOCK) k_apply_K(Grid g, const double *v, double *out) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const Ijk c = ijk(g, p);
+  out[p] = applyK<DIM, PN>(g, p, c, v[p], [&](int64_t k) { return v[k]; });
+}
+
+hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out) {
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_apply_K<DIM, PN>), dim3(nblocks(g.N)), dim3(BLOCK), 0,
+                                         s, g, v, out));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// transfers between levels: time (R, T) composed with space (average of the
+// 2^d children / cell-centred multilinear interpolation), or time only.
+// ---------------------------------------------------------------------------
+
+struct Children {
+  int64_t idx[8];
+  int n;
+};
+__device__ __forceinline__ Children children(const Grid &gf, const Grid &gc, int64_t pc, int f) {
+  Children ch;
+  if (f == 1) {
+    ch.idx[0] = pc;
+    ch.n = 1;
+    return ch;
+  }
+  const Ijk c = ijk(gc, pc);
+  const int ax = gf.nx > 1 ? 2 : 1, ay = gf.ny > 1 ? 2 : 1, az = gf.nz > 1 ? 2 : 1;
+  ch.n = 0;
+  for (int c2 = 0; c2 < az; ++c2)
+    for (int b = 0; b < ay; ++b)
+      for (int a = 0; a < ax; ++a) {
+        const int64_t ix = (int64_t)c.ix * ax + a, iy = (int64_t)c.iy * ay + b,
+                      iz = (int64_t)c.iz * az + c2;
+        ch.idx[ch.n++] = ix + gf.nx * (iy + gf.ny * iz);
+      }
+  return ch;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_restrict_stages(Grid gf, Grid gc, int scf, const double *Yf, int64_t sYf, int Mf,
+                  const double *Rt, int Mc, double *Yc, int64_t sYc, double *Yc2) {
+  const int64_t pc = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (pc >= gc.N) return;
+  const int n = blockIdx.z;
+  const Children ch = children(gf, gc, pc, scf);
+  const double inv = 1.0 / ch.n;
+  for (int f = 0; f < NF; ++f) {
+    double av[MAXM + 1];
+    for (int l = 0; l <= Mf; ++l) {
+      double s = 0.0;
+      for (int k = 0; k < ch.n; ++k) s += Yf[n * sYf + ((int64_t)l * NF + f) * gf.Np + ch.idx[k]];
+      av[l] = s * inv;
+    }
+    for (int i = 0; i <= Mc; ++i) {
+      double s = 0.0;
+      for (int l = 0; l <= Mf; ++l) s += Rt[i * (Mf + 1) + l] * av[l];
+      const int64_t o = n * sYc + ((int64_t)i * NF + f) * gc.Np + pc;
+      Yc[o] = s;
+      if (Yc2) Yc2[o] = s;
+    }
+  }
+}
+
+hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
+                                  const double *Yf, int64_t sYf, int Mf, const double *Rt,
+                                  int Mc, double *Yc, int64_t sYc, double *Yc_copy, int nslices) {
+  dim3 grid(nblocks(gc.N), 1, nslices);
+  hipLaunchKernelGGL(k_restrict_stages, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, Yf, sYf, Mf,
+                     Rt, Mc, Yc, sYc, Yc_copy);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(BLOCK)
+k_restrict_fields(Grid gf, Grid gc, int scf, const double *src, int64_t ssrc, double *dst,
+                  int64_t sdst, int nrows) {
+  const int64_t pc = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (pc >= gc.N) return;
+  const int n = blockIdx.z;
+  const Children ch = children(gf, gc, pc, scf);
+  const double inv = 1.0 / ch.n;
+  for (int r = 0; r < nrows; ++r) {
+    double s = 0.0;
+    for (int k = 0; k < ch.n; ++k) s += src[n * ssrc + (int64_t)r * gf.Np + ch.idx[k]];
+    dst[n * sdst + (int64_t)r * gc.Np + pc] = s * inv;
+  }
+}
+
+hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
+                                  const double *src, int64_t ssrc, double *dst, int64_t sdst,
+                                  int nrows, int nslices) {
+  dim3 grid(nblocks(gc.N), 1, nslices);
+  hipLaunchKernelGGL(k_restrict_fields, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, src, ssrc,
+                     dst, sdst, nrows);
+  return hipGetLastError();
+}
+
+// D = Yc - Sz on the coarse level (in the scratch buffer).
+__global__ void __launch_bounds__(BLOCK)
+k_coarse_diff(int64_t Ncp, const double *Yc, const double *Sz, double *D, int64_t sYc, int rows) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= Ncp) return;
+  const int n = blockIdx.z;
+  for (int r = 0; r < rows; ++r) {
+    const int64_t o = n * sYc + (int64_t)r * Ncp + p;
+    D[o] = Yc[o] - Sz[o];
+  }
+}
+
+// Yf_i += sum_j T_ij Ps(D_j) with Ps the cell-centred multilinear interpolation
+// (weights 3/4 and 1/4 per coarsened axis, mirror at the walls).
+__global__ void __launch_bounds__(BLOCK)
+k_prolong_correct(Grid gf, Grid gc, int scf, const double *D, int64_t sYc, int Mc,
+                  const double *Tt, int Mf, double *Yf, int64_t sYf) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= gf.N) return;
+  const int n = blockIdx.z;
+  int64_t idx[8];
+  double wt[8];
+  int nn = 0;
+  if (scf == 1) {
+    idx[0] = p;
+    wt[0] = 1.0;
+    nn = 1;
+  } else {
+    const Ijk c = ijk(gf, p);
+    int I0[3], I1[3];
+    double w0[3], w1[3];
+    const int fi[3] = {c.ix, c.iy, c.iz};
+    const int nf_[3] = {gf.nx, gf.ny, gf.nz};
+    const int nc_[3] = {gc.nx, gc.ny, gc.nz};
+    for (int a = 0; a < 3; ++a) {
+      if (nf_[a] > 1) {
+        const int I = fi[a] >> 1;
+        const int side = fi[a] & 1;
+        int J = side ? I + 1 : I - 1;
+        J = J < 0 ? 0 : (J > nc_[a] - 1 ? nc_[a] - 1 : J);
+        I0[a] = I;
+        I1[a] = J;
+        w0[a] = 0.75;
+        w1[a] = 0.25;
+      } else {
+        I0[a] = I1[a] = 0;
+        w0[a] = 1.0;
+        w1[a] = 0.0;
+      }
+    }
+    for (int cz = 0; cz < 2; ++cz)
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          const double w = (cx ? w1[0] : w0[0]) * (cy ? w1[1] : w0[1]) * (cz ? w1[2] : w0[2]);
+          if (w == 0.0) continue;
+          const int ix = cx ? I1[0] : I0[0], iy = cy ? I1[1] : I0[1], iz = cz ? I1[2] : I0[2];
+          idx[nn] = ix + (int64_t)gc.nx * (iy + (int64_t)gc.ny * iz);
+          wt[nn] = w;
+          ++nn;
+        }
+  }
+  for (int f = 0; f < NF; ++f) {
+    double dc[MAXM + 1];
+    for (int j = 0; j <= Mc; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < nn; ++k) s += wt[k] * D[n * sYc + ((int64_t)j * NF + f) * gc.Np + idx[k]];
+      dc[j] = s;
+    }
+    for (int i = 0; i <= Mf; ++i) {
+      double s = 0.0;
+      for (int j = 0; j <= Mc; ++j) s += Tt[i * (Mc + 1) + j] * dc[j];
+      Yf[n * sYf + ((int64_t)i * NF + f) * gf.Np + p] += s;
+    }
+  }
+}
+
+hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
+                                  const double *Yc, const double *Sz, int64_t sYc, int Mc,
+                                  const double *Tt, int Mf, double *Yf, int64_t sYf,
+                                  int nslices, double *scratch) {
+  const int rows = (Mc + 1) * NF;
+  hipLaunchKernelGGL(k_coarse_diff, dim3(nblocks(gc.Np), 1, nslices), dim3(BLOCK), 0, s, gc.Np,
+                     Yc, Sz, scratch, sYc, rows);
+  hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks(gf.N), 1, nslices), dim3(BLOCK), 0, s, gf,
+                     gc, sc_factor, scratch, sYc, Mc, Tt, Mf, Yf, sYf);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exported building blocks
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(BLOCK)
+k_ionic_test(int64_t n, const double *y, double gs0, double gs1, double gs2, double *I_ion,
+             double *ha, double *lam, double *winf) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= n) return;
+  double yv[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) yv[f] = y[f * n + p];
+  ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
+    lam[k * n + p] = -1.0 / tau;
+    winf[k * n + p] = inf;
+  });
+  double I, h[6];
+  ttp06::currents(yv, gs0, gs1, gs2, I, h);
+  I_ion[p] = I;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ha[k * n + p] = h[k];
+}
+
+hipError_t launch_ionic_test(hipStream_t s, int64_t n, const double *y, double gs0, double gs1,
+                             double gs2, double *I_ion, double *ha, double *lam, double *winf) {
+  hipLaunchKernelGGL(k_ionic_test, dim3(nblocks(n)), dim3(BLOCK), 0, s, n, y, gs0, gs1, gs2, I_ion,
+                     ha, lam, winf);
+  return hipGetLastError();
+}
+
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_phi_test(int64_t n, const double *x, double *out) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= n) return;
+  double invf[MAXM + 2];
+  invf[0] = 1.0;
+  for (int k = 1; k < MAXM + 2; ++k) invf[k] = invf[k - 1] / (double)k;
+  double ph[K];
+  phis<K>(x[p], invf, ph);
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k * n + p] = ph[k];
+}
+
+hipError_t launch_phi_test(hipStream_t s, int64_t n, const double *x, int kmax, double *out) {
+  HSDC_DISPATCH_M(kmax, hipLaunchKernelGGL((k_phi_test<M>), dim3(nblocks(n)), dim3(BLOCK), 0, s, n,
+                                           x, out));
+  return hipGetLastError();
+}
+
+// a_ij(z) through colloc_integrals applied to the unit vectors e_j.
+template <int M>
+__global__ void __launch_bounds__(BLOCK)
+k_aij_test(int64_t n, const double *z, Colloc co, double *out) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= n) return;
+  for (int j = 0; j < M; ++j) {
+    double e[M], I[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) e[k] = (k == j) ? 1.0 : 0.0;
+    colloc_integrals<M>(co, z[p], e, I);
+    for (int i = 0; i < M; ++i) out[(p * M + i) * M + j] = I[i];
+  }
+}
+
+hipError_t launch_aij_test(hipStream_t s, int64_t n, const double *z, const Colloc &co,
+                           double *out) {
+  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_aij_test<M>), dim3(nblocks(n)), dim3(BLOCK), 0, s, n,
+                                           z, co, out));
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(BLOCK) k_fill_rest(int64_t N, int64_t Np, double *y) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= N) return;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) y[f * Np + p] = ttp06::kRest[f];
+}
+
+hipError_t launch_fill_rest(hipStream_t s, int64_t N, int64_t Np, double *y) {
+  hipLaunchKernelGGL(k_fill_rest, dim3(nblocks(N)), dim3(BLOCK), 0, s, N, Np, y);
+  return hipGetLastError();
+}
+
+}  // namespace hsdc

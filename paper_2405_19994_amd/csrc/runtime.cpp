@@ -1,0 +1,862 @@
+// runtime.cpp -- host runtime of libhsdc: context, workspace, the HSDC sweep
+// driver (Sec. 3.1.3), serial stepping, two-level PFASST (Sec. 3.2,
+// Algorithm 1) and the C ABI of include/hsdc.h.
+//
+// Sweep in node-to-node form.  With R_i = (P_i - C_i)(y^k) + u + tau_i the
+// right-hand side of eq. prec_picard, the forward substitution with P of
+// eq. def_P reads, node by node,
+//     (I - dt d_i f_I) y^{k+1}_i = y^{k+1}_{i-1} + (R_i - R_{i-1})
+//         + dt d_i [ f_E(y^{k+1}_{i-1}) + phi_1(d_i dt Lambda(u)) (f_e(y^{k+1}_{i-1})
+//                    + Lambda(u)(u - y^{k+1}_{i-1})) ]
+// where R_i - R_{i-1} = dt sum_j (a_ij - a_{i-1,j}) g_j(y^k) - dt d_i Phi_i(y^k)
+// + tau_i - tau_{i-1} uses only the previous iterate (kernel k_assemble) and
+// the implicit part acts on V only (a CG solve).  (P - C)(y^k) is evaluated with
+// the anchor y^k_{n,0} and Lambda(y^k_{n,0}); P^-1 with the new start value u.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hsdc_internal.h"
+
+namespace hsdc {
+bool make_colloc(int M, double dt, Colloc &co);
+void transfer_matrix(int Mfrom, const double *c_from, int Mto, const double *c_to, double *out);
+}  // namespace hsdc
+
+using namespace hsdc;
+
+namespace {
+
+thread_local std::string g_free_error;
+
+struct HipFail {
+  hipError_t e;
+  const char *what;
+};
+
+#define HIPC(call)                                  \
+  do {                                              \
+    hipError_t e_ = (call);                         \
+    if (e_ != hipSuccess) throw HipFail{e_, #call}; \
+  } while (0)
+
+struct Level {
+  Grid g{};
+  Colloc co{};
+  Stages st{};
+  int P = 0;
+  double *stim_w = nullptr;
+  double *kface[3] = {nullptr, nullptr, nullptr};
+  // CG workspace
+  double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_q = nullptr;
+  double *cg_part = nullptr;
+  unsigned *cg_cnt = nullptr;
+  CgScalars *cg_sc = nullptr;
+  CgScalars *cg_sc_host = nullptr;
+  int cg_nblk = 0;
+  // residual
+  double *res_part = nullptr, *res_out = nullptr, *res_out_host = nullptr;
+  int res_nblk = 0;
+  // PFASST
+  double *U = nullptr;    // [P][NF][Np] start values of a Q sweep
+  double *Sz = nullptr;   // coarse: copy of the restricted fine iterate
+  double *RI = nullptr;   // fine: time-restricted integrals [P][Mc][NF][Np]; coarse: restricted
+  double *D = nullptr;    // coarse scratch
+  double *y0c = nullptr;  // coarse: restricted block start value [NF][Np]
+  int cg_pred[16][MAXM];
+};
+
+}  // namespace
+
+struct hsdc_ctx {
+  hipStream_t s = nullptr;
+  hsdc_problem prob{};
+  hsdc_method meth{};
+  Level L[2];
+  int nlev = 1;
+  double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
+  double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices
+  int64_t step = 0;
+  int sweeps_done = 0;  // serial: sweeps applied to the current step
+  int sweep_index = 0;
+  bool pfasst = false;
+  bool block_ready = false;
+  bool ri_fresh = false;  // fine RI holds the restricted integrals of the current iterate
+  hsdc_stats stats{};
+  std::string err;
+  std::vector<void *> allocs;
+  std::vector<void *> host_allocs;
+  Stim stim[2]{};
+};
+
+namespace {
+
+hsdc_status fail(hsdc_ctx *c, hsdc_status st, const std::string &msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_free_error = msg;
+  return st;
+}
+
+template <class T>
+T *dalloc(hsdc_ctx *c, size_t n) {
+  void *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+  c->allocs.push_back(p);
+  HIPC(hipMemsetAsync(p, 0, n * sizeof(T), c->s));
+  return (T *)p;
+}
+
+template <class T>
+T *halloc(hsdc_ctx *c, size_t n) {
+  void *p = nullptr;
+  hipError_t e = hipHostMalloc(&p, n * sizeof(T), hipHostMallocDefault);
+  if (e != hipSuccess) throw HipFail{e, "hipHostMalloc"};
+  c->host_allocs.push_back(p);
+  return (T *)p;
+}
+
+int64_t pad64(int64_t n) { return (n + 63) / 64 * 64; }
+
+bool check_problem(const hsdc_problem *p, std::string &why) {
+  if (!p) return why = "problem is NULL", false;
+  if (p->dim < 1 || p->dim > 3) return why = "dim must be 1, 2 or 3", false;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return why = "nx, ny, nz must be >= 1", false;
+  if (p->dim < 2 && p->ny != 1) return why = "ny must be 1 for dim < 2", false;
+  if (p->dim < 3 && p->nz != 1) return why = "nz must be 1 for dim < 3", false;
+  if (!(p->dx > 0) || !std::isfinite(p->dx)) return why = "dx must be > 0", false;
+  if (!(p->chi > 0) || !(p->Cm > 0)) return why = "chi and Cm must be > 0", false;
+  for (int a = 0; a < 3; ++a)
+    if (!(p->sigma[a] >= 0) || !std::isfinite(p->sigma[a])) return why = "sigma must be >= 0", false;
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->g_scale[a])) return why = "g_scale must be finite", false;
+  if (!std::isfinite(p->stim_amp) || !std::isfinite(p->stim_t0) || !(p->stim_dur >= 0))
+    return why = "stimulus parameters must be finite, stim_dur >= 0", false;
+  const double N = (double)p->nx * p->ny * p->nz;
+  if (N > 2.0e9) return why = "mesh too large", false;
+  return true;
+}
+
+bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why) {
+  if (!m) return why = "method is NULL", false;
+  if (m->levels < 1 || m->levels > 2) return why = "levels must be 1 or 2", false;
+  for (int l = 0; l < m->levels; ++l)
+    if (m->M[l] < 1 || m->M[l] > HSDC_MAX_M) return why = "M must be in 1..8", false;
+  if (m->levels == 2 && m->space_coarsen != 1 && m->space_coarsen != 2)
+    return why = "space_coarsen must be 1 or 2", false;
+  if (m->levels == 2 && m->space_coarsen == 2) {
+    if ((p->nx > 1 && p->nx % 2) || (p->ny > 1 && p->ny % 2) || (p->nz > 1 && p->nz % 2))
+      return why = "space_coarsen 2 needs even mesh sizes", false;
+    if (p->sigma_node) return why = "space_coarsen 2 needs a uniform sigma", false;
+  }
+  if (m->P < 1 || m->P > 4096) return why = "P must be in 1..4096", false;
+  if (!(m->dt > 0) || !std::isfinite(m->dt)) return why = "dt must be > 0", false;
+  if (m->max_iter < 1) return why = "max_iter must be >= 1", false;
+  if (!std::isfinite(m->tol)) return why = "tol must be finite", false;
+  if (!(m->cg_rtol > 0) || !(m->cg_rtol < 1)) return why = "cg_rtol must be in (0, 1)", false;
+  if (m->cg_maxit < 1) return why = "cg_maxit must be >= 1", false;
+  return true;
+}
+
+Grid make_grid(const hsdc_problem &p, int nx, int ny, int nz, double dx) {
+  Grid g{};
+  g.dim = p.dim;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.N = (int64_t)nx * ny * nz;
+  g.Np = pad64(g.N);
+  const double s = 1.0 / (dx * dx * p.chi * p.Cm);
+  g.cx = p.sigma[0] * s;
+  g.cy = p.sigma[1] * s;
+  g.cz = p.sigma[2] * s;
+  return g;
+}
+
+// Per-node conductivity: face coefficient between p and p + e_axis is the
+// harmonic mean of the two node values over dx^2 chi Cm (0 on the last layer).
+void build_faces(hsdc_ctx *c, Level &L, const double *sigma_node_dev) {
+  const Grid &g = L.g;
+  std::vector<double> s(g.N);
+  HIPC(hipMemcpyAsync(s.data(), sigma_node_dev, g.N * sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPC(hipStreamSynchronize(c->s));
+  const double sc = 1.0 / (c->prob.dx * c->prob.dx * c->prob.chi * c->prob.Cm);
+  const int64_t strides[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+  const int sizes[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < g.dim; ++a) {
+    std::vector<double> k(g.N, 0.0);
+    for (int64_t p = 0; p < g.N; ++p) {
+      const int64_t q = p + strides[a];
+      const int coord = (int)((p / strides[a]) % sizes[a]);
+      if (coord < sizes[a] - 1) {
+        const double sp = s[p], sq = s[q];
+        k[p] = (sp + sq > 0) ? 2.0 * sp * sq / (sp + sq) * sc : 0.0;
+      }
+    }
+    L.kface[a] = dalloc<double>(c, g.N);
+    HIPC(hipMemcpyAsync(L.kface[a], k.data(), g.N * sizeof(double), hipMemcpyHostToDevice, c->s));
+  }
+  HIPC(hipStreamSynchronize(c->s));
+  L.g.kx = L.kface[0];
+  L.g.ky = g.dim >= 2 ? L.kface[1] : nullptr;
+  L.g.kz = g.dim >= 3 ? L.kface[2] : nullptr;
+}
+
+void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc_for_RI) {
+  const int64_t Np = L.g.Np;
+  L.P = P;
+  L.st.Np = Np;
+  L.st.M = M;
+  L.st.Y = dalloc<double>(c, (size_t)P * L.st.sY());
+  L.st.G = dalloc<double>(c, (size_t)P * L.st.sY());
+  L.st.FV = dalloc<double>(c, (size_t)P * L.st.sFV());
+  L.st.RH = dalloc<double>(c, (size_t)P * L.st.sRH());
+  L.st.L0 = dalloc<double>(c, (size_t)P * L.st.sL());
+  L.st.Lu = dalloc<double>(c, (size_t)P * L.st.sL());
+  L.st.B = dalloc<double>(c, (size_t)P * Np);
+  L.cg_nblk = cg_blocks(L.g);
+  L.cg_r = dalloc<double>(c, (size_t)P * Np);
+  L.cg_p0 = dalloc<double>(c, (size_t)P * Np);
+  L.cg_p1 = dalloc<double>(c, (size_t)P * Np);
+  L.cg_q = dalloc<double>(c, (size_t)P * Np);
+  L.cg_part = dalloc<double>(c, (size_t)P * 2 * L.cg_nblk);
+  L.cg_cnt = dalloc<unsigned>(c, P);
+  L.cg_sc = dalloc<CgScalars>(c, P);
+  L.cg_sc_host = halloc<CgScalars>(c, P);
+  L.res_nblk = residual_blocks(L.g);
+  L.res_part = dalloc<double>(c, (size_t)P * 2 * L.res_nblk);
+  L.res_out = dalloc<double>(c, (size_t)2 * P);
+  L.res_out_host = halloc<double>(c, 2 * P);
+  L.U = dalloc<double>(c, (size_t)P * NF * Np);
+  if (Mc_for_RI > 0) L.RI = dalloc<double>(c, (size_t)P * Mc_for_RI * NF * Np);
+  if (coarse_extras) {
+    L.Sz = dalloc<double>(c, (size_t)P * L.st.sY());
+    L.D = dalloc<double>(c, (size_t)P * L.st.sY());
+    L.y0c = dalloc<double>(c, (size_t)NF * Np);
+  }
+  for (auto &row : L.cg_pred)
+    for (int &v : row) v = 6;
+}
+
+// ---------------------------------------------------------------------------
+// diffusion solve for node i of a sweep, slices [s0, s0+ns)
+// ---------------------------------------------------------------------------
+void cg_solve(hsdc_ctx *c, Level &L, int s0, int ns, int i, int pred_row) {
+  CgBatch cb{};
+  const int64_t Np = L.g.Np;
+  cb.x = L.st.Y + s0 * L.st.sY() + (int64_t)i * L.st.sS();
+  cb.sx = L.st.sY();
+  cb.b = L.st.B + s0 * Np;
+  cb.sb = Np;
+  cb.r = L.cg_r + s0 * Np;
+  cb.p0 = L.cg_p0 + s0 * Np;
+  cb.p1 = L.cg_p1 + s0 * Np;
+  cb.q = L.cg_q + s0 * Np;
+  cb.part = L.cg_part + (int64_t)s0 * 2 * L.cg_nblk;
+  cb.cnt = L.cg_cnt + s0;
+  cb.sc = L.cg_sc + s0;
+  cb.nslices = ns;
+  cb.nblk = L.cg_nblk;
+  cb.a = L.co.dt * L.co.d[i - 1];
+  cb.tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
+  cb.maxit = c->meth.cg_maxit;
+  HIPC(launch_cg_init(c->s, L.g, cb));
+  int &pred = L.cg_pred[pred_row & 15][i - 1];
+  int it = 0, parity = 0;
+  int batch = std::max(1, std::min(pred, cb.maxit));
+  for (;;) {
+    for (int k = 0; k < batch && it < cb.maxit; ++k, ++it) {
+      HIPC(launch_cg_iter(c->s, L.g, cb, parity));
+      parity ^= 1;
+    }
+    HIPC(hipMemcpyAsync(L.cg_sc_host + s0, L.cg_sc + s0, ns * sizeof(CgScalars),
+                        hipMemcpyDeviceToHost, c->s));
+    HIPC(hipStreamSynchronize(c->s));
+    bool all = true;
+    for (int n = 0; n < ns; ++n) all = all && L.cg_sc_host[s0 + n].done;
+    if (all || it >= cb.maxit) break;
+    batch = 1;
+  }
+  int maxused = 0;
+  for (int n = 0; n < ns; ++n) {
+    const CgScalars &sc = L.cg_sc_host[s0 + n];
+    maxused = std::max(maxused, sc.it);
+    c->stats.cg_iters += sc.it;
+    c->stats.cg_solves += 1;
+    if (!(sc.rr <= cb.tol2 * sc.bb || sc.rr == 0.0)) c->stats.cg_unconverged += 1;
+  }
+  pred = std::max(1, maxused);
+}
+
+// ---------------------------------------------------------------------------
+// one sweep on slices [s0, s0+ns) of level L.
+//   Precondition: G, FV and L0 hold the reaction terms, K V and Lambda(anchor)
+//   of the current iterate.  u_src: new start values [ns][NF][Np] (NULL keeps
+//   y_{n,0}); RI: FAS integrals (coarse level of PFASST) or NULL.
+//   Postcondition: same invariant for the new iterate.
+// ---------------------------------------------------------------------------
+void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const double *RI,
+           int pred_row) {
+  Level &L = c->L[lev];
+  const Colloc &co = L.co;
+  const hsdc_problem &p = c->prob;
+  const int M = co.M;
+  const int64_t N = L.g.N;
+  const int64_t step0 = c->step;
+  const int64_t sRI = (int64_t)M * NF * L.g.Np;
+  HIPC(launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI));
+  Stages st = L.st;
+  if (u_src) {
+    HIPC(launch_copy_fields(c->s, L.g.Np, L.st.Y + s0 * L.st.sY(), L.st.sY(), u_src,
+                            (int64_t)NF * L.g.Np, NF, ns));
+    HIPC(launch_eval_stages(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                            p.g_scale[2], s0, ns, 0, 1, step0, L.st.Lu, nullptr));
+    c->stats.ionic_evals += N * ns;
+  } else {
+    st.Lu = L.st.L0;  // the anchor is unchanged
+  }
+  for (int i = 1; i <= M; ++i) {
+    HIPC(launch_node_update(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                            p.g_scale[2], s0, ns, i, step0));
+    if (i > 1) c->stats.ionic_evals += N * ns;
+    cg_solve(c, L, s0, ns, i, pred_row);
+  }
+  HIPC(launch_eval_stages(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                          p.g_scale[2], s0, ns, M, 1, step0, nullptr, st.Lu));
+  c->stats.ionic_evals += N * ns;
+  HIPC(launch_spmv_stages(c->s, L.g, L.st, s0, ns, 1, M));
+  if (u_src)
+    HIPC(launch_copy_fields(c->s, L.g.Np, L.st.L0 + s0 * L.st.sL(), L.st.sL(),
+                            L.st.Lu + s0 * L.st.sL(), L.st.sL(), NG, ns));
+  if (lev == 0)
+    c->stats.sweeps += ns;
+  else
+    c->stats.coarse_sweeps += ns;
+}
+
+// Reaction terms, K V and Lambda(anchor) of every stage of slices [s0, s0+ns).
+void evaluate_all(hsdc_ctx *c, int lev, int s0, int ns) {
+  Level &L = c->L[lev];
+  const hsdc_problem &p = c->prob;
+  HIPC(launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                          p.g_scale[2], s0, ns, 0, 1, c->step, L.st.L0, nullptr));
+  HIPC(launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                          p.g_scale[2], s0, ns, 1, L.co.M, c->step, nullptr, L.st.L0));
+  HIPC(launch_spmv_stages(c->s, L.g, L.st, s0, ns, 0, L.co.M + 1));
+  c->stats.ionic_evals += L.g.N * ns * (L.co.M + 1);
+}
+
+// Serial step start: y^0 = 1 (x) y_n from Y[0][0].
+void begin_serial_step(hsdc_ctx *c) {
+  Level &L = c->L[0];
+  const hsdc_problem &p = c->prob;
+  HIPC(launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0], p.g_scale[1],
+                          p.g_scale[2], 0, 1, 0, 1, c->step, L.st.L0, nullptr));
+  HIPC(launch_spmv_stages(c->s, L.g, L.st, 0, 1, 0, 1));
+  HIPC(launch_spread(c->s, L.g, L.st, L.co, c->stim[0], 0, 1, c->step, true));
+  c->stats.ionic_evals += L.g.N;
+  c->sweeps_done = 0;
+  c->sweep_index = 0;
+}
+
+hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
+  Level &L = c->L[0];
+  const double *yb = c->pfasst ? c->y0blk : L.st.Y;  // serial: u = y_{n,0}
+  const int Mc = c->nlev == 2 ? c->L[1].co.M : 0;
+  double *RI = (want_RI && c->nlev == 2) ? L.RI : nullptr;
+  HIPC(launch_residual(c->s, L.g, L.st, L.co, 0, L.P, yb, L.res_part, L.res_nblk, L.res_out,
+                       c->Rt, Mc, RI, (int64_t)Mc * NF * L.g.Np));
+  HIPC(hipMemcpyAsync(L.res_out_host, L.res_out, 2 * L.P * sizeof(double), hipMemcpyDeviceToHost,
+                      c->s));
+  HIPC(hipStreamSynchronize(c->s));
+  bool finite = true;
+  for (int n = 0; n < L.P; ++n) {
+    const double r = L.res_out_host[2 * n], y = L.res_out_host[2 * n + 1];
+    const double rel = y > 0 ? r / y : r;
+    if (!std::isfinite(rel) || !std::isfinite(y)) finite = false;
+    if (res_host) res_host[n] = rel;
+  }
+  if (!finite) return fail(c, HSDC_ENONFINITE, "non-finite residual or state");
+  return HSDC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PFASST (two levels)
+// ---------------------------------------------------------------------------
+void restrict_fine_to_coarse(hsdc_ctx *c) {
+  Level &F = c->L[0], &Cc = c->L[1];
+  HIPC(launch_restrict_stages(c->s, F.g, Cc.g, c->meth.space_coarsen, F.st.Y, F.st.sY(), F.co.M,
+                              c->Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
+}
+
+void coarse_correct_fine(hsdc_ctx *c) {
+  Level &F = c->L[0], &Cc = c->L[1];
+  HIPC(launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz, Cc.st.sY(),
+                              Cc.co.M, c->Tt, F.co.M, F.st.Y, F.st.sY(), F.P, Cc.D));
+}
+
+// start values u_n of a sweep over slices [s0, s0+ns) from the stage-M values
+// of slices n-1 (ends) and the level's block start value for n = 0
+void gather_starts(hsdc_ctx *c, int lev, int s0, int ns) {
+  Level &L = c->L[lev];
+  const int64_t sS = L.st.sS();
+  const double *blk0 = (lev == 0) ? c->y0blk : L.y0c;
+  int n = s0;
+  if (n == 0) {
+    HIPC(launch_copy_fields(c->s, L.g.Np, L.U, sS, blk0, sS, NF, 1));
+    ++n;
+  }
+  if (n < s0 + ns)
+    HIPC(launch_copy_fields(c->s, L.g.Np, L.U + n * sS, sS,
+                            L.st.Y + (n - 1) * L.st.sY() + (int64_t)L.co.M * sS, L.st.sY(), NF,
+                            s0 + ns - n));
+}
+
+void burn_in(hsdc_ctx *c) {
+  Level &Cc = c->L[1];
+  const int P = Cc.P;
+  restrict_fine_to_coarse(c);
+  evaluate_all(c, 1, 0, P);
+  for (int s = 0; s < P; ++s) {
+    gather_starts(c, 1, s, P - s);
+    sweep(c, 1, s, P - s, Cc.U + s * Cc.st.sS(), nullptr, 15);
+  }
+  coarse_correct_fine(c);
+}
+
+void begin_block(hsdc_ctx *c) {
+  Level &F = c->L[0];
+  const int P = F.P;
+  // spread y0 over every stage of every slice
+  for (int j = 0; j <= F.co.M; ++j)
+    HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y + (int64_t)j * F.st.sS(), F.st.sY(), c->y0blk, 0,
+                            NF, P));
+  if (c->nlev == 2) {
+    Level &Cc = c->L[1];
+    HIPC(launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, c->y0blk, 0, Cc.y0c, 0, NF,
+                                1));
+    if (P > 1 && c->meth.burn_in) burn_in(c);
+  }
+  evaluate_all(c, 0, 0, P);
+  c->block_ready = true;
+  c->ri_fresh = false;
+}
+
+hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
+  Level &F = c->L[0];
+  const int P = F.P;
+  if (c->nlev == 2) {
+    Level &Cc = c->L[1];
+    const int Mc = Cc.co.M;
+    // tau: the coarse sweep uses the restricted fine integrals S (A G)(z) in place
+    // of its own collocation integrals (eq. def_D and the tau of Algorithm 1)
+    if (!c->ri_fresh) {
+      hsdc_status st = residual_pass(c, nullptr, true);
+      if (st != HSDC_OK) return st;
+    }
+    HIPC(launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
+                                (int64_t)Mc * NF * F.g.Np, Cc.RI, (int64_t)Mc * NF * Cc.g.Np,
+                                Mc * NF, P));
+    restrict_fine_to_coarse(c);
+    evaluate_all(c, 1, 0, P);
+    for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
+      gather_starts(c, 1, n, 1);
+      sweep(c, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14);
+    }
+    coarse_correct_fine(c);
+    evaluate_all(c, 0, 0, P);
+  }
+  // Q^par on the fine level: start values from the (corrected) iterate
+  gather_starts(c, 0, 0, P);
+  sweep(c, 0, 0, P, F.U, nullptr, c->sweep_index++);
+  c->stats.pfasst_iters += 1;
+  std::vector<double> rel(P);
+  hsdc_status st = residual_pass(c, rel.data(), c->nlev == 2);
+  c->ri_fresh = (st == HSDC_OK && c->nlev == 2);
+  if (res_host)
+    for (int n = 0; n < P; ++n) res_host[n] = rel[n];
+  bool all = c->meth.tol > 0;
+  for (int n = 0; n < P; ++n) all = all && rel[n] < c->meth.tol;
+  if (conv) *conv = all ? 1 : 0;
+  return st;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+namespace {
+template <class Fn>
+hsdc_status run_guarded(hsdc_ctx *c, Fn &&fn) {
+  try {
+    return fn();
+  } catch (const HipFail &h) {
+    std::string m = std::string("HIP error in ") + h.what + ": " + hipGetErrorString(h.e);
+    if (h.e == hipErrorOutOfMemory || h.e == hipErrorMemoryAllocation) return fail(c, HSDC_ENOMEM, m);
+    return fail(c, HSDC_EDEVICE, m);
+  } catch (const std::exception &e) {
+    return fail(c, HSDC_EDEVICE, e.what());
+  }
+}
+}  // namespace
+
+extern "C" {
+
+hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, const double *y0,
+                            void *hip_stream, hsdc_ctx **out) {
+  if (!out) return fail(nullptr, HSDC_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!check_problem(prob, why)) return fail(nullptr, HSDC_EINVAL, why);
+  if (!check_method(meth, prob, why)) return fail(nullptr, HSDC_EINVAL, why);
+  if (meth->levels == 1 && meth->P > 1)
+    return fail(nullptr, HSDC_EINVAL, "P > 1 needs levels = 2");
+  hsdc_ctx *c = new hsdc_ctx();
+  c->s = (hipStream_t)hip_stream;
+  c->prob = *prob;
+  c->meth = *meth;
+  c->nlev = meth->levels;
+  c->pfasst = !(meth->levels == 1 && meth->P == 1);
+  hsdc_status st = run_guarded(c, [&]() -> hsdc_status {
+    const int P = meth->P;
+    Level &F = c->L[0];
+    F.g = make_grid(*prob, prob->nx, prob->ny, prob->nz, prob->dx);
+    if (!make_colloc(meth->M[0], meth->dt, F.co))
+      return fail(c, HSDC_EINVAL, "Radau node computation failed");
+    const int Mc = c->nlev == 2 ? meth->M[1] : 0;
+    alloc_level(c, F, meth->M[0], P, false, Mc);
+    if (prob->sigma_node) build_faces(c, F, prob->sigma_node);
+    c->y0blk = dalloc<double>(c, (size_t)NF * F.g.Np);
+    if (prob->stim_w) {
+      F.stim_w = dalloc<double>(c, F.g.Np);
+      HIPC(hipMemcpyAsync(F.stim_w, prob->stim_w, F.g.N * sizeof(double),
+                          hipMemcpyDeviceToDevice, c->s));
+    }
+    for (int l = 0; l < 2; ++l) {
+      c->stim[l].amp = prob->stim_amp;
+      c->stim[l].t0 = prob->stim_t0;
+      c->stim[l].dur = prob->stim_dur;
+      c->stim[l].eps = 1e-9 * meth->dt;
+      c->stim[l].Cm = prob->Cm;
+    }
+    c->stim[0].w = F.stim_w;
+    if (c->nlev == 2) {
+      Level &Cc = c->L[1];
+      const int f = meth->space_coarsen;
+      const int cnx = prob->nx > 1 ? prob->nx / f : 1;
+      const int cny = prob->ny > 1 ? prob->ny / f : 1;
+      const int cnz = prob->nz > 1 ? prob->nz / f : 1;
+      Cc.g = make_grid(*prob, cnx, cny, cnz, prob->dx * f);
+      if (!make_colloc(meth->M[1], meth->dt, Cc.co))
+        return fail(c, HSDC_EINVAL, "Radau node computation failed");
+      alloc_level(c, Cc, meth->M[1], P, true, Mc);
+      if (prob->sigma_node) build_faces(c, Cc, prob->sigma_node);  // f == 1 only
+      if (F.stim_w) {
+        Cc.stim_w = dalloc<double>(c, Cc.g.Np);
+        HIPC(launch_restrict_fields(c->s, F.g, Cc.g, f, F.stim_w, 0, Cc.stim_w, 0, 1, 1));
+      }
+      c->stim[1].w = Cc.stim_w;
+      std::vector<double> R((Mc + 1) * (meth->M[0] + 1)), T((meth->M[0] + 1) * (Mc + 1));
+      transfer_matrix(meth->M[0], F.co.c, Mc, Cc.co.c, R.data());
+      transfer_matrix(Mc, Cc.co.c, meth->M[0], F.co.c, T.data());
+      c->Rt = dalloc<double>(c, R.size());
+      c->Tt = dalloc<double>(c, T.size());
+      HIPC(hipMemcpyAsync(c->Rt, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+      HIPC(hipMemcpyAsync(c->Tt, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+    }
+    // initial state
+    if (y0) {
+      for (int f = 0; f < NF; ++f)
+        HIPC(hipMemcpyAsync(c->y0blk + f * F.g.Np, y0 + f * F.g.N, F.g.N * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->s));
+    } else {
+      HIPC(launch_fill_rest(c->s, F.g.N, F.g.Np, c->y0blk));
+    }
+    if (c->pfasst) {
+      begin_block(c);
+    } else {
+      HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0, c->y0blk, 0, NF, 1));
+      begin_serial_step(c);
+    }
+    HIPC(hipStreamSynchronize(c->s));
+    return HSDC_OK;
+  });
+  if (st != HSDC_OK) {
+    g_free_error = c->err;
+    hsdc_destroy(c);
+    return st;
+  }
+  *out = c;
+  return HSDC_OK;
+}
+
+hsdc_status hsdc_sdc_sweep(hsdc_ctx *c, int32_t level, int32_t slice, int32_t nsweeps) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (level != 0) return fail(c, HSDC_EINVAL, "level must be 0");
+  if (slice < 0 || slice >= c->L[0].P) return fail(c, HSDC_EINVAL, "slice out of range");
+  if (nsweeps < 0) return fail(c, HSDC_EINVAL, "nsweeps must be >= 0");
+  return run_guarded(c, [&]() -> hsdc_status {
+    for (int k = 0; k < nsweeps; ++k) {
+      sweep(c, 0, slice, 1, nullptr, nullptr, c->pfasst ? 13 : c->sweep_index++);
+      if (!c->pfasst) c->sweeps_done += 1;
+    }
+    if (nsweeps > 0) c->ri_fresh = false;
+    HIPC(hipGetLastError());
+    return HSDC_OK;
+  });
+}
+
+hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(c, HSDC_EINVAL, "nsteps must be >= 0");
+  return run_guarded(c, [&]() -> hsdc_status {
+    Level &F = c->L[0];
+    for (int s = 0; s < nsteps; ++s) {
+      if (!c->pfasst) {
+        while (c->sweeps_done < c->meth.max_iter) {
+          sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++);
+          c->sweeps_done += 1;
+        }
+        // y_{n+1} = y_{n,M}
+        HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0, F.st.Y + (int64_t)F.co.M * F.st.sS(), 0,
+                                NF, 1));
+        c->step += 1;
+        c->stats.steps += 1;
+        begin_serial_step(c);
+      } else {
+        int32_t conv = 0;
+        c->sweep_index = 0;
+        for (int k = 0; k < c->meth.max_iter && !conv; ++k) {
+          hsdc_status st = pfasst_iteration(c, nullptr, &conv);
+          if (st != HSDC_OK) return st;
+        }
+        HIPC(launch_copy_fields(c->s, F.g.Np, c->y0blk, 0,
+                                F.st.Y + (int64_t)(F.P - 1) * F.st.sY() +
+                                    (int64_t)F.co.M * F.st.sS(),
+                                0, NF, 1));
+        c->step += F.P;
+        c->stats.steps += F.P;
+        begin_block(c);
+      }
+    }
+    if (c->stats.cg_unconverged > 0)
+      return fail(c, HSDC_ENOCONV, "a diffusion solve reached cg_maxit");
+    return HSDC_OK;
+  });
+}
+
+hsdc_status hsdc_pfasst_iter(hsdc_ctx *c, double *res_host, int32_t *all_converged) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (!c->pfasst) return fail(c, HSDC_ESTATE, "context is in serial mode (levels = 1, P = 1)");
+  return run_guarded(c, [&]() -> hsdc_status { return pfasst_iteration(c, res_host, all_converged); });
+}
+
+hsdc_status hsdc_residual(hsdc_ctx *c, int32_t level, double *res_host) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (level != 0) return fail(c, HSDC_EINVAL, "level must be 0");
+  if (!res_host) return fail(c, HSDC_EINVAL, "res_host is NULL");
+  return run_guarded(c, [&]() -> hsdc_status { return residual_pass(c, res_host, false); });
+}
+
+static hsdc_status state_copy(hsdc_ctx *c, int32_t level, int32_t slice, int32_t node, double *dev,
+                              bool get) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (level < 0 || level >= c->nlev) return fail(c, HSDC_EINVAL, "level out of range");
+  Level &L = c->L[level];
+  if (slice < 0 || slice >= L.P) return fail(c, HSDC_EINVAL, "slice out of range");
+  if (node < 0 || node > L.co.M) return fail(c, HSDC_EINVAL, "node out of range");
+  if (!dev) return fail(c, HSDC_EINVAL, "buffer is NULL");
+  return run_guarded(c, [&]() -> hsdc_status {
+    double *base = L.st.Y + slice * L.st.sY() + (int64_t)node * L.st.sS();
+    for (int f = 0; f < NF; ++f) {
+      if (get)
+        HIPC(hipMemcpyAsync(dev + f * L.g.N, base + f * L.g.Np, L.g.N * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->s));
+      else
+        HIPC(hipMemcpyAsync(base + f * L.g.Np, dev + f * L.g.N, L.g.N * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->s));
+    }
+    if (!get) {
+      c->ri_fresh = false;
+      // keep the cached stage terms consistent with the new state
+      if (c->pfasst) {
+        if (level == 0 && node == 0 && slice == 0) {
+          for (int f = 0; f < NF; ++f)
+            HIPC(hipMemcpyAsync(c->y0blk + f * L.g.Np, dev + f * L.g.N, L.g.N * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->s));
+        }
+        evaluate_all(c, level, slice, 1);
+      } else if (node == 0) {
+        begin_serial_step(c);
+      } else {
+        evaluate_all(c, 0, 0, 1);
+      }
+    }
+    HIPC(hipStreamSynchronize(c->s));
+    return HSDC_OK;
+  });
+}
+
+hsdc_status hsdc_get_state(const hsdc_ctx *c, int32_t level, int32_t slice, int32_t node,
+                           double *dst) {
+  return state_copy(const_cast<hsdc_ctx *>(c), level, slice, node, dst, true);
+}
+
+hsdc_status hsdc_set_state(hsdc_ctx *c, int32_t level, int32_t slice, int32_t node,
+                           const double *src) {
+  return state_copy(c, level, slice, node, const_cast<double *>(src), false);
+}
+
+int64_t hsdc_current_step(const hsdc_ctx *c) { return c ? c->step : -1; }
+
+hsdc_status hsdc_get_stats(const hsdc_ctx *c, hsdc_stats *out) {
+  if (!c || !out) return fail(const_cast<hsdc_ctx *>(c), HSDC_EINVAL, "NULL argument");
+  *out = c->stats;
+  return HSDC_OK;
+}
+
+void hsdc_destroy(hsdc_ctx *c) {
+  if (!c) return;
+  if (c->s) hipStreamSynchronize(c->s);
+  else hipDeviceSynchronize();
+  for (void *p : c->allocs) hipFree(p);
+  for (void *p : c->host_allocs) hipHostFree(p);
+  delete c;
+}
+
+const char *hsdc_last_error(const hsdc_ctx *c) {
+  if (c) return c->err.c_str();
+  return g_free_error.c_str();
+}
+
+// ---- exported building blocks ---------------------------------------------
+
+hsdc_status hsdc_ionic_eval(int64_t n, const double *y, const double *g_scale_host3, double *I_ion,
+                            double *h_a, double *lam, double *w_inf, void *hip_stream) {
+  if (n < 0 || (n > 0 && (!y || !I_ion || !h_a || !lam || !w_inf)))
+    return fail(nullptr, HSDC_EINVAL, "bad arguments");
+  if (n == 0) return HSDC_OK;
+  const double gs0 = g_scale_host3 ? g_scale_host3[0] : 1.0;
+  const double gs1 = g_scale_host3 ? g_scale_host3[1] : 1.0;
+  const double gs2 = g_scale_host3 ? g_scale_host3[2] : 1.0;
+  hipError_t e = launch_ionic_test((hipStream_t)hip_stream, n, y, gs0, gs1, gs2, I_ion, h_a, lam, w_inf);
+  if (e != hipSuccess) return fail(nullptr, HSDC_EDEVICE, hipGetErrorString(e));
+  return HSDC_OK;
+}
+
+hsdc_status hsdc_phi(int64_t n, const double *x, int32_t kmax, double *out, void *hip_stream) {
+  if (n < 0 || kmax < 1 || kmax > HSDC_MAX_M || (n > 0 && (!x || !out)))
+    return fail(nullptr, HSDC_EINVAL, "bad arguments");
+  if (n == 0) return HSDC_OK;
+  hipError_t e = launch_phi_test((hipStream_t)hip_stream, n, x, kmax, out);
+  if (e != hipSuccess) return fail(nullptr, HSDC_EDEVICE, hipGetErrorString(e));
+  return HSDC_OK;
+}
+
+hsdc_status hsdc_apply_diffusion(const hsdc_problem *prob, const double *v, double *out,
+                                 void *hip_stream) {
+  std::string why;
+  if (!check_problem(prob, why)) return fail(nullptr, HSDC_EINVAL, why);
+  if (!v || !out) return fail(nullptr, HSDC_EINVAL, "NULL vector");
+  hsdc_ctx tmp;
+  tmp.s = (hipStream_t)hip_stream;
+  tmp.prob = *prob;
+  hsdc_status st = run_guarded(&tmp, [&]() -> hsdc_status {
+    Level L;
+    L.g = make_grid(*prob, prob->nx, prob->ny, prob->nz, prob->dx);
+    if (prob->sigma_node) build_faces(&tmp, L, prob->sigma_node);
+    HIPC(launch_apply_K(tmp.s, L.g, v, out));
+    HIPC(hipStreamSynchronize(tmp.s));
+    return HSDC_OK;
+  });
+  for (void *p : tmp.allocs) hipFree(p);
+  tmp.allocs.clear();
+  if (st != HSDC_OK) g_free_error = tmp.err;
+  return st;
+}
+
+hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const double *b, double *x,
+                                 double rtol, int32_t maxit, int32_t *iters_host,
+                                 void *hip_stream) {
+  std::string why;
+  if (!check_problem(prob, why)) return fail(nullptr, HSDC_EINVAL, why);
+  if (!b || !x || !(rtol > 0) || maxit < 1 || !(a >= 0))
+    return fail(nullptr, HSDC_EINVAL, "bad arguments");
+  hsdc_ctx tmp;
+  tmp.s = (hipStream_t)hip_stream;
+  tmp.prob = *prob;
+  tmp.meth.cg_rtol = rtol;
+  tmp.meth.cg_maxit = maxit;
+  int used = 0;
+  bool conv = false;
+  hsdc_status st = run_guarded(&tmp, [&]() -> hsdc_status {
+    Level L;
+    L.g = make_grid(*prob, prob->nx, prob->ny, prob->nz, prob->dx);
+    if (prob->sigma_node) build_faces(&tmp, L, prob->sigma_node);
+    const int64_t Np = L.g.Np;
+    L.cg_nblk = cg_blocks(L.g);
+    CgBatch cb{};
+    cb.x = x;
+    cb.sx = 0;
+    cb.b = b;
+    cb.sb = 0;
+    cb.r = dalloc<double>(&tmp, Np);
+    cb.p0 = dalloc<double>(&tmp, Np);
+    cb.p1 = dalloc<double>(&tmp, Np);
+    cb.q = dalloc<double>(&tmp, Np);
+    cb.part = dalloc<double>(&tmp, 2 * L.cg_nblk);
+    cb.cnt = dalloc<unsigned>(&tmp, 1);
+    cb.sc = dalloc<CgScalars>(&tmp, 1);
+    cb.nslices = 1;
+    cb.nblk = L.cg_nblk;
+    cb.a = a;
+    cb.tol2 = rtol * rtol;
+    cb.maxit = maxit;
+    HIPC(launch_cg_init(tmp.s, L.g, cb));
+    int parity = 0;
+    CgScalars sc{};
+    for (int it = 0; it < maxit; ++it) {
+      HIPC(launch_cg_iter(tmp.s, L.g, cb, parity));
+      parity ^= 1;
+    }
+    HIPC(hipMemcpyAsync(&sc, cb.sc, sizeof(sc), hipMemcpyDeviceToHost, tmp.s));
+    HIPC(hipStreamSynchronize(tmp.s));
+    used = sc.it;
+    conv = sc.rr <= cb.tol2 * sc.bb || sc.rr == 0.0;
+    return HSDC_OK;
+  });
+  for (void *p : tmp.allocs) hipFree(p);
+  tmp.allocs.clear();
+  if (iters_host) *iters_host = used;
+  if (st != HSDC_OK) {
+    g_free_error = tmp.err;
+    return st;
+  }
+  if (!conv) return fail(nullptr, HSDC_ENOCONV, "CG reached maxit");
+  return HSDC_OK;
+}
+
+hsdc_status hsdc_colloc_coefficients(int32_t M, int64_t n, const double *z, double *out,
+                                     double *c_host, void *hip_stream) {
+  if (M < 1 || M > HSDC_MAX_M || n < 0 || (n > 0 && (!z || !out)))
+    return fail(nullptr, HSDC_EINVAL, "bad arguments");
+  Colloc co;
+  if (!make_colloc(M, 1.0, co)) return fail(nullptr, HSDC_EINVAL, "Radau node computation failed");
+  if (c_host)
+    for (int i = 0; i < M; ++i) c_host[i] = co.c[i];
+  if (n == 0) return HSDC_OK;
+  hipError_t e = launch_aij_test((hipStream_t)hip_stream, n, z, co, out);
+  if (e != hipSuccess) return fail(nullptr, HSDC_EDEVICE, hipGetErrorString(e));
+  return HSDC_OK;
+}
+
+}  // extern "C"

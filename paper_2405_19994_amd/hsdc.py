@@ -1,0 +1,285 @@
+"""Thin Python binding of libhsdc (include/hsdc.h): argument marshalling only.
+
+Device arrays are torch tensors (float64, contiguous, on a ROCm device); the
+HIP stream is torch's current stream unless one is given.  Every step of the
+method runs in the library's HIP kernels; this module never computes any of
+it and fails loudly when the library is missing.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsdc.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hsdc.h")
+
+NF, NAUX, NGATES, MAX_M = 19, 6, 12, 8
+
+STATUS = {0: "HSDC_OK", -1: "HSDC_EINVAL", -2: "HSDC_ENOMEM", -3: "HSDC_EDEVICE",
+          -4: "HSDC_ENOCONV", -5: "HSDC_ENONFINITE", -6: "HSDC_ESTATE"}
+
+
+class HsdcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("dx", ctypes.c_double), ("sigma", ctypes.c_double * 3),
+                ("sigma_node", ctypes.c_void_p), ("chi", ctypes.c_double), ("Cm", ctypes.c_double),
+                ("g_scale", ctypes.c_double * 3), ("stim_w", ctypes.c_void_p),
+                ("stim_amp", ctypes.c_double), ("stim_t0", ctypes.c_double),
+                ("stim_dur", ctypes.c_double)]
+
+
+class Method(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("M", ctypes.c_int32 * 2),
+                ("space_coarsen", ctypes.c_int32), ("P", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("burn_in", ctypes.c_int32),
+                ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("steps", "sweeps", "coarse_sweeps", "cg_solves",
+                                              "cg_iters", "cg_unconverged", "pfasst_iters",
+                                              "ionic_evals")]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhsdc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2405_19994_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "hsdc_init_state": [ctypes.POINTER(Problem), ctypes.POINTER(Method), vp, vp,
+                                ctypes.POINTER(vp)],
+            "hsdc_sdc_sweep": [vp, i32, i32, i32],
+            "hsdc_advance": [vp, i32],
+            "hsdc_pfasst_iter": [vp, vp, vp],
+            "hsdc_residual": [vp, i32, vp],
+            "hsdc_get_state": [vp, i32, i32, i32, vp],
+            "hsdc_set_state": [vp, i32, i32, i32, vp],
+            "hsdc_get_stats": [vp, ctypes.POINTER(Stats)],
+            "hsdc_ionic_eval": [i64, vp, vp, vp, vp, vp, vp, vp],
+            "hsdc_phi": [i64, vp, i32, vp, vp],
+            "hsdc_apply_diffusion": [ctypes.POINTER(Problem), vp, vp, vp],
+            "hsdc_diffusion_solve": [ctypes.POINTER(Problem), dbl, vp, vp, dbl, i32, vp, vp],
+            "hsdc_colloc_coefficients": [i32, i64, vp, vp, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.hsdc_current_step.argtypes = [vp]
+        L.hsdc_current_step.restype = ctypes.c_int64
+        L.hsdc_destroy.argtypes = [vp]
+        L.hsdc_destroy.restype = None
+        L.hsdc_last_error.argtypes = [vp]
+        L.hsdc_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/hsdc.h."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsdc_[a-z_]+)\s*\(", text)))
+
+
+def _check(code, ctx=None):
+    if code != 0:
+        msg = lib().hsdc_last_error(ctx).decode()
+        raise HsdcError(code, msg)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, name, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_problem(dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None, chi=1400.0, Cm=1.0,
+                 g_scale=(1.0, 1.0, 1.0), stim_w=None, stim_amp=0.0, stim_t0=0.0, stim_dur=0.0):
+    """hsdc_problem for a cell-centred mesh of `dims` nodes (x fastest)."""
+    dims = tuple(int(n) for n in dims)
+    p = Problem()
+    p.dim = len(dims)
+    p.nx, p.ny, p.nz = (dims + (1, 1))[:3]
+    p.dx = float(dx)
+    p.sigma[:] = [float(s) for s in (tuple(sigma) + (1.0, 1.0, 1.0))[:3]]
+    p.chi, p.Cm = float(chi), float(Cm)
+    p.g_scale[:] = [float(g) for g in g_scale]
+    N = int(np.prod(dims))
+    p._keep = []
+    if sigma_node is not None:
+        p.sigma_node = _dev(sigma_node, "sigma_node", (N,))
+        p._keep.append(sigma_node)
+    if stim_w is not None:
+        p.stim_w = _dev(stim_w, "stim_w", (N,))
+        p._keep.append(stim_w)
+    p.stim_amp, p.stim_t0, p.stim_dur = float(stim_amp), float(stim_t0), float(stim_dur)
+    p.N = N
+    return p
+
+
+def make_method(M=(4, 2), levels=1, space_coarsen=1, P=1, dt=0.05, max_iter=4, tol=0.0,
+                burn_in=1, cg_rtol=1e-12, cg_maxit=200):
+    m = Method()
+    m.levels = int(levels)
+    Ms = (tuple(M) + (1, 1))[:2] if not isinstance(M, int) else (M, 1)
+    m.M[:] = [int(Ms[0]), int(Ms[1])]
+    m.space_coarsen, m.P, m.dt = int(space_coarsen), int(P), float(dt)
+    m.max_iter, m.tol, m.burn_in = int(max_iter), float(tol), int(burn_in)
+    m.cg_rtol, m.cg_maxit = float(cg_rtol), int(cg_maxit)
+    return m
+
+
+class Context:
+    """An hsdc_ctx: the state of a serial HSDC run or of a PFASST block."""
+
+    def __init__(self, problem, method, y0=None, stream=None):
+        self.problem, self.method = problem, method
+        self.N = problem.N
+        self.P = method.P
+        self._stream_obj = stream
+        ptr = ctypes.c_void_p()
+        y0p = None if y0 is None else _dev(y0, "y0", (NF, self.N))
+        _check(lib().hsdc_init_state(ctypes.byref(problem), ctypes.byref(method), y0p,
+                                     _stream(stream), ctypes.byref(ptr)))
+        self._ctx = ptr
+
+    @property
+    def handle(self):
+        if self._ctx is None:
+            raise HsdcError(-6, "context destroyed")
+        return self._ctx
+
+    def sdc_sweep(self, nsweeps=1, level=0, slice=0):
+        _check(lib().hsdc_sdc_sweep(self.handle, level, slice, nsweeps), self.handle)
+
+    def advance(self, nsteps=1):
+        _check(lib().hsdc_advance(self.handle, nsteps), self.handle)
+
+    def pfasst_iter(self):
+        res = np.zeros(self.P)
+        conv = ctypes.c_int32(0)
+        _check(lib().hsdc_pfasst_iter(self.handle, res.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(conv)), self.handle)
+        return res, bool(conv.value)
+
+    def residual(self, level=0):
+        res = np.zeros(self.P)
+        _check(lib().hsdc_residual(self.handle, level, res.ctypes.data_as(ctypes.c_void_p)),
+               self.handle)
+        return res
+
+    def _level_n(self, level):
+        if level == 0 or self.method.space_coarsen == 1:
+            return self.N
+        p = self.problem
+        dims = [n // 2 if n > 1 else 1 for n in (p.nx, p.ny, p.nz)]
+        return int(np.prod(dims))
+
+    def get_state(self, level=0, slice=0, node=0, out=None):
+        n = self._level_n(level)
+        if out is None:
+            out = torch.empty((NF, n), dtype=torch.float64, device="cuda")
+        _check(lib().hsdc_get_state(self.handle, level, slice, node, _dev(out, "out", (NF, n))),
+               self.handle)
+        return out
+
+    def set_state(self, src, level=0, slice=0, node=0):
+        n = self._level_n(level)
+        _check(lib().hsdc_set_state(self.handle, level, slice, node, _dev(src, "src", (NF, n))),
+               self.handle)
+
+    def stats(self):
+        s = Stats()
+        _check(lib().hsdc_get_stats(self.handle, ctypes.byref(s)), self.handle)
+        return {n: getattr(s, n) for n, _ in Stats._fields_}
+
+    @property
+    def step(self):
+        return int(lib().hsdc_current_step(self.handle))
+
+    def destroy(self):
+        if self._ctx is not None:
+            lib().hsdc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def ionic_eval(y, g_scale=(1.0, 1.0, 1.0), stream=None):
+    """(I_ion, h_a, Lambda_g, w_inf) of the TTP06 model at states y (19, n)."""
+    n = y.shape[1]
+    yp = _dev(y, "y", (NF, n))
+    I = torch.empty(n, dtype=torch.float64, device=y.device)
+    ha = torch.empty((NAUX, n), dtype=torch.float64, device=y.device)
+    lam = torch.empty((NGATES, n), dtype=torch.float64, device=y.device)
+    winf = torch.empty((NGATES, n), dtype=torch.float64, device=y.device)
+    gs = (ctypes.c_double * 3)(*g_scale)
+    _check(lib().hsdc_ionic_eval(n, yp, ctypes.cast(gs, ctypes.c_void_p), _dev(I, "I"),
+                                 _dev(ha, "ha"), _dev(lam, "lam"), _dev(winf, "winf"),
+                                 _stream(stream)))
+    return I, ha, lam, winf
+
+
+def phi(x, kmax, stream=None):
+    """phi_1..phi_kmax at x (n,) -> (kmax, n)."""
+    out = torch.empty((kmax, x.shape[0]), dtype=torch.float64, device=x.device)
+    _check(lib().hsdc_phi(x.shape[0], _dev(x, "x"), kmax, _dev(out, "out"), _stream(stream)))
+    return out
+
+
+def apply_diffusion(problem, v, stream=None):
+    out = torch.empty_like(v)
+    _check(lib().hsdc_apply_diffusion(ctypes.byref(problem), _dev(v, "v", (problem.N,)),
+                                      _dev(out, "out"), _stream(stream)))
+    return out
+
+
+def diffusion_solve(problem, a, b, x0=None, rtol=1e-12, maxit=500, stream=None):
+    x = b.clone() if x0 is None else x0.clone()
+    it = ctypes.c_int32(0)
+    code = lib().hsdc_diffusion_solve(ctypes.byref(problem), float(a), _dev(b, "b", (problem.N,)),
+                                      _dev(x, "x"), float(rtol), int(maxit), ctypes.byref(it),
+                                      _stream(stream))
+    _check(code)
+    return x, it.value
+
+
+def colloc_coefficients(M, z, stream=None):
+    """a_ij(z) computed on the device: (n, M, M), and the nodes c (numpy)."""
+    out = torch.empty((z.shape[0], M, M), dtype=torch.float64, device=z.device)
+    c = np.zeros(M)
+    _check(lib().hsdc_colloc_coefficients(M, z.shape[0], _dev(z, "z"), _dev(out, "out"),
+                                          c.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+    return out, c

@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every function include/hsdc.h declares;
+argument checks fail with HSDC_EINVAL before any device work (no GPU needed)."""
+import ctypes
+
+import pytest
+
+from paper_2405_19994_amd import hsdc as H
+
+
+def test_header_symbols_exported():
+    names = H.header_functions()
+    assert "hsdc_init_state" in names and "hsdc_pfasst_iter" in names
+    lib = H.lib()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_header():
+    # field order and C types of the two public structs
+    assert ctypes.sizeof(H.Problem) == 4 * 4 + 8 + 24 + 8 + 8 + 8 + 24 + 8 + 24
+    assert [f for f, _ in H.Problem._fields_][:5] == ["dim", "nx", "ny", "nz", "dx"]
+    assert ctypes.sizeof(H.Stats) == 8 * 8
+
+
+def _init(p, m):
+    ptr = ctypes.c_void_p()
+    code = H.lib().hsdc_init_state(ctypes.byref(p), ctypes.byref(m), None, None, ctypes.byref(ptr))
+    return code, ptr
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=(0,)), dict(dx=-1.0), dict(chi=0.0), dict(sigma=(-1.0, 1, 1)),
+])
+def test_bad_problem_is_einval(bad):
+    kw = dict(dims=(16,), dx=0.01)
+    kw.update(bad)
+    p = H.make_problem(**kw)
+    if "dims" in bad:
+        p.nx = 0
+    code, ptr = _init(p, H.make_method())
+    assert code == -1 and not ptr.value
+    assert H.lib().hsdc_last_error(None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(M=(0, 1)), dict(M=(9, 1)), dict(dt=0.0), dict(max_iter=0), dict(cg_rtol=0.0),
+    dict(levels=3), dict(levels=1, P=4), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
+])
+def test_bad_method_is_einval(bad):
+    p = H.make_problem((15,), 0.01)
+    code, ptr = _init(p, H.make_method(**bad))
+    assert code == -1 and not ptr.value
+
+
+def test_null_context_calls_are_einval():
+    L = H.lib()
+    assert L.hsdc_advance(None, 1) == -1
+    assert L.hsdc_sdc_sweep(None, 0, 0, 1) == -1
+    assert L.hsdc_pfasst_iter(None, None, None) == -1
+    assert L.hsdc_residual(None, 0, None) == -1
+    assert L.hsdc_current_step(None) == -1
+    L.hsdc_destroy(None)
+    assert L.hsdc_phi(10, None, 0, None, None) == -1
+    assert L.hsdc_colloc_coefficients(0, 1, None, None, None, None) == -1

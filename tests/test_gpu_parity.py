@@ -1,0 +1,248 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Tolerances: building blocks 1e-13 relative (rounding order only); runs of the
+method 1e-10 relative per field (max |gpu - oracle| / max |oracle|), the FP64
+bar of the hot path, with CG solves at 1e-14 relative residual."""
+import numpy as np
+import pytest
+import torch
+
+import synthetic_inputs as si
+from oracle import coeffs, ttp06
+from oracle.hsdc import Level, collocation_solve, run_serial, serial_step
+from oracle.pfasst import pfasst_block
+from oracle.tissue import ImplicitSolver, laplacian
+from tests._parity import field_errors, oracle_hierarchy, oracle_problem, rest
+
+pytestmark = pytest.mark.gpu
+
+H = pytest.importorskip("paper_2405_19994_amd.hsdc")
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def lib_problem(w, dims=None):
+    dims = tuple(dims or w["dims"])
+    sn = None if w.get("sigma_node") is None else dev(w["sigma_node"])
+    return H.make_problem(dims, w["dx"], w["sigma"], sn, w["chi"], w["Cm"], w.get("g_scale", (1, 1, 1)),
+                          dev(w["stim_w"]), w["stim_amp"], w["stim_t0"], w["stim_dur"])
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("gs", [(1.0, 1.0, 1.0), (1.1, 0.9, 1.2)])
+def test_ionic_eval_parity(gs):
+    y = si.random_states(100_003, seed=11)
+    I, ha, lam, winf = (host(t) for t in H.ionic_eval(dev(y), gs))
+    I_o, ha_o, lam_o, winf_o = ttp06.evaluate(y, gs)
+    assert np.max(field_errors(I[None], I_o[None])) < 1e-13
+    assert np.max(field_errors(ha, ha_o)) < 1e-13
+    assert np.max(np.abs(lam - lam_o) / np.abs(lam_o)) < 1e-13
+    assert np.max(field_errors(winf, winf_o)) < 1e-13
+
+
+def test_ionic_eval_full_slab_size():
+    """One cell-model evaluation per node of the 512 x 512 slab, every node compared."""
+    y = si.random_states(512 * 512, seed=12)
+    I, ha, lam, winf = (host(t) for t in H.ionic_eval(dev(y)))
+    I_o, ha_o, lam_o, winf_o = ttp06.evaluate(y)
+    assert np.max(field_errors(I[None], I_o[None])) < 1e-13
+    assert np.max(field_errors(ha, ha_o)) < 1e-13
+    assert np.max(np.abs(lam - lam_o) / np.abs(lam_o)) < 1e-13
+
+
+@pytest.mark.parametrize("kmax", [1, 3, 4, 6, 8])
+def test_phi_parity(kmax):
+    x = np.concatenate([-np.logspace(-12, 3.6, 3001), np.linspace(-12.0, 12.0, 1201), [0.0]])
+    got = host(H.phi(dev(x), kmax))
+    for k in range(1, kmax + 1):
+        ref = coeffs.phi(k, x)
+        err = np.abs(got[k - 1] - ref) / np.abs(ref)
+        assert np.max(err) < 5e-14, (k, x[np.argmax(err)], np.max(err))
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 6, 8])
+def test_colloc_coefficients_parity(M):
+    z = np.concatenate([[0.0], -np.logspace(-9, 3.3, 400)])
+    a, c = H.colloc_coefficients(M, dev(z))
+    a = host(a)
+    assert np.max(np.abs(c - coeffs.radau_iia_nodes(M))) < 1e-15
+    ref = coeffs.exp_colloc_matrix(z, coeffs.radau_iia_nodes(M))
+    tol = 2e-13 if M <= 6 else 2e-12
+    assert np.max(np.abs(a - ref)) < tol
+
+
+@pytest.mark.parametrize("case", ["1d", "2d", "3d_aniso", "2d_pernode"])
+def test_apply_diffusion_parity(case):
+    rng = np.random.default_rng(3)
+    dims, sigma, sn = {"1d": ((37,), (1.0, 1, 1), None), "2d": ((13, 11), (1.0, 1, 1), None),
+                       "3d_aniso": ((9, 7, 5), (3.0, 1.0, 0.5), None),
+                       "2d_pernode": ((13, 11), (1.0, 1, 1), np.exp(0.3 * rng.standard_normal(143)))}[case]
+    N = int(np.prod(dims))
+    v = rng.standard_normal(N)
+    K = laplacian(dims, 0.025, sigma, sn) / (1400.0 * 1.0)
+    p = H.make_problem(dims, 0.025, sigma, None if sn is None else dev(sn))
+    got = host(H.apply_diffusion(p, dev(v)))
+    ref = K @ v
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("case", ["2d", "3d_aniso", "2d_pernode"])
+def test_diffusion_solve_parity(case):
+    rng = np.random.default_rng(4)
+    dims, sigma, sn = {"2d": ((33, 21), (1.0, 1, 1), None),
+                       "3d_aniso": ((12, 10, 6), (3.0, 1.0, 1.0), None),
+                       "2d_pernode": ((33, 21), (1.0, 1, 1), np.exp(0.3 * rng.standard_normal(693)))}[case]
+    N = int(np.prod(dims))
+    b = -85.0 + rng.standard_normal(N)
+    a = 0.05 * 0.26
+    K = laplacian(dims, 0.025, sigma, sn) / 1400.0
+    ref = ImplicitSolver(K).solve(b, a)
+    p = H.make_problem(dims, 0.025, sigma, None if sn is None else dev(sn))
+    x, it = H.diffusion_solve(p, a, dev(b), rtol=1e-14, maxit=200)
+    assert 1 <= it < 200
+    assert np.max(np.abs(host(x) - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# serial HSDC runs
+# ---------------------------------------------------------------------------
+
+def _serial_parity(w, nsteps, every, M, K, y0=None, tol=1e-10):
+    po = oracle_problem(w)
+    lev = Level(po, M, w["dt"])
+    N = po.N
+    y0 = rest(N) if y0 is None else y0
+    ctx = H.Context(lib_problem(w), H.make_method(M=(M, 1), dt=w["dt"], max_iter=K, cg_rtol=1e-14,
+                                                  cg_maxit=300), dev(y0))
+    y = y0.copy()
+    worst = 0.0
+    for n0 in range(0, nsteps, every):
+        y = run_serial(lev, y, every, K, step0=n0)
+        ctx.advance(every)
+        g = host(ctx.get_state(0, 0, 0))
+        e = field_errors(g, y)
+        worst = max(worst, float(np.max(e)))
+        assert np.max(e) < tol, (n0 + every, ttp06.FIELD_NAMES[int(np.argmax(e))], np.max(e))
+    st = ctx.stats()
+    assert st["steps"] == nsteps and st["cg_unconverged"] == 0
+    ctx.destroy()
+    return y, worst
+
+
+def test_cable1d_full_run_parity():
+    """The 1D cable workload in full: 128 nodes, M 4, K 4, dt 0.05, T 10 ms."""
+    w = si.workload("cable1d")
+    y, _ = _serial_parity(w, 200, 20, 4, 4)
+    assert y[0].max() > 0.0  # the stimulus launched a propagating action potential
+
+
+def test_slab2d_reduced_parity():
+    """The 2D slab workload at a reduced, ragged mesh (31 x 23), M 6, K 6."""
+    w = si.workload("slab2d", dims=(31, 23))
+    _serial_parity(w, 30, 10, 6, 6)
+
+
+def test_pernode_sigma_parity():
+    """Per-node lognormal conductivity (the batched-tissue workload's field)."""
+    t = si.batch2d_tissues(1, seed=3, lo=20, hi=40)[0]
+    _serial_parity(t, 24, 8, 4, 4)
+
+
+def test_slab3d_serial_parity():
+    w = si.workload("slab3d", dims=(10, 8, 6))
+    _serial_parity(w, 12, 4, 3, 3)
+
+
+def test_sweep_and_residual_parity():
+    """hsdc_sdc_sweep applies eq. prec_picard sweeps to the current step;
+    hsdc_residual returns ||C(y_n) - 1 (x) y_n||_inf / ||y_n||_inf."""
+    w = si.workload("slab2d", dims=(17, 13))
+    po = oracle_problem(w)
+    lev = Level(po, 6, w["dt"])
+    y0 = rest(po.N)
+    ctx = H.Context(lib_problem(w), H.make_method(M=(6, 1), dt=w["dt"], max_iter=6, cg_rtol=1e-14),
+                    dev(y0))
+    for K in (1, 2, 3):
+        ctx.sdc_sweep(1)
+        Y = serial_step(lev, 0, y0, K)
+        for j in range(7):
+            assert np.max(field_errors(host(ctx.get_state(0, 0, j)), Y[j])) < 1e-12
+        _, rel = lev.residual(0, Y, y0)
+        assert abs(ctx.residual()[0] - rel) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# PFASST
+# ---------------------------------------------------------------------------
+
+def _pfasst_case(dims, Mf, Mc, coarsen, P, dt, seed_state=False):
+    w = dict(si.workload("slab3d" if len(dims) == 3 else "cable1d", dims=dims))
+    w["dt"] = dt
+    if len(dims) == 1:
+        w["stim_w"] = si.corner_weights(dims, (2,))
+    h = oracle_hierarchy(w, Mf, Mc, coarsen)
+    y0 = rest(h.levels[0].prob.N)
+    m = H.make_method(M=(Mf, Mc), levels=2, space_coarsen=coarsen, P=P, dt=dt, max_iter=50,
+                      tol=0.0, burn_in=1, cg_rtol=1e-14, cg_maxit=300)
+    return w, h, y0, m
+
+
+@pytest.mark.parametrize("dims,coarsen", [((8, 6, 4), 2), ((16,), 1)])
+def test_pfasst_iterates_parity(dims, coarsen):
+    """Every iterate of Algorithm 1 (burn-in, tau, Q^seq coarse sweep, coarse
+    grid correction, Q^par fine sweep) matches the oracle, slice by slice."""
+    P = 4
+    w, h, y0, m = _pfasst_case(dims, 6 if coarsen == 2 else 4, 3 if coarsen == 2 else 2,
+                                coarsen, P, 0.1)
+    ctx = H.Context(lib_problem(w), m, dev(y0))
+    for k in (1, 2, 3):
+        res, _ = ctx.pfasst_iter()
+        z, hist, _ = pfasst_block(h, y0, P, k, tol=0.0)
+        for n in range(P):
+            for j in (0, h.levels[0].M):
+                e = field_errors(host(ctx.get_state(0, n, j)), z[n][j])
+                assert np.max(e) < 1e-10, (k, n, j, np.max(e))
+        assert np.max(np.abs(np.array(hist[-1]) - res)) < 1e-9 * max(1.0, np.max(hist[-1]))
+
+
+def test_pfasst_converges_to_serial_collocation():
+    P = 4
+    w, h, y0, m = _pfasst_case((8, 6, 4), 6, 3, 2, P, 0.1)
+    m.tol, m.max_iter = 1e-13, 60
+    ctx = H.Context(lib_problem(w), m, dev(y0))
+    conv = False
+    for _ in range(60):
+        res, conv = ctx.pfasst_iter()
+        if conv:
+            break
+    assert conv
+    y = y0
+    for n in range(P):
+        Y, _ = collocation_solve(h.levels[0], n, y, tol=1e-14)
+        y = Y[-1]
+    g = host(ctx.get_state(0, P - 1, h.levels[0].M))
+    assert np.max(np.abs(g - y)) < 1e-11 * np.max(np.abs(y))
+
+
+def test_pfasst_advance_blocks():
+    """hsdc_advance in PFASST mode: two blocks iterated to tol, chained."""
+    from oracle.pfasst import run_pfasst
+    P = 2
+    w, h, y0, m = _pfasst_case((16,), 4, 2, 1, P, 0.1)
+    m.tol, m.max_iter = 1e-12, 40
+    ctx = H.Context(lib_problem(w), m, dev(y0))
+    ctx.advance(2)
+    y_ref, _ = run_pfasst(h, y0, 2, P, 40, 1e-12)
+    g = host(ctx.get_state(0, 0, 0))
+    assert ctx.step == 2 * P
+    assert np.max(field_errors(g, y_ref)) < 1e-10
