@@ -18,23 +18,29 @@ namespace hsdc {
 // phi_1(x) = (e^x - 1)/x, phi_1(0) = 1.
 __device__ __forceinline__ double phi1(double x) { return x == 0.0 ? 1.0 : expm1(x) / x; }
 
-// phi_1(x) .. phi_M(x) into out[0..M-1].  For |x| >= M the forward recurrence
-// phi_{k+1} = (phi_k - 1/k!)/x from phi_1 = expm1(x)/x is stable (errors shrink by
-// k/|x| per step); for |x| < M the Taylor series sum_m x^m/(m+M)! of phi_M and the
-// backward recurrence phi_k = 1/k! + x phi_{k+1} are.
+// phi_1(x) .. phi_M(x) into out[0..M-1].  The forward recurrence
+// phi_{k+1} = (phi_k - 1/k!)/x from phi_1 = expm1(x)/x damps errors while k <= |x|
+// (factor about k/|x| per step); the backward recurrence phi_k = 1/k! + x phi_{k+1}
+// from the Taylor series sum_m x^m/(m+M)! of phi_M damps them while k + 1 > |x|.
+// Each k is taken from the direction that is stable for it.
 template <int M>
 __device__ __forceinline__ void phis(double x, const double *invfact, double *out) {
-  if (fabs(x) >= (double)M) {
+  const double ax = fabs(x);
+  const int kf = ax >= (double)M ? M : (int)ax;  // phi_1..phi_kf forward
+  if (kf >= 1) {
     double p = expm1(x) / x;
     out[0] = p;
 #pragma unroll
     for (int k = 1; k < M; ++k) {
-      p = (p - invfact[k]) / x;
-      out[k] = p;
+      if (k < kf) {
+        p = (p - invfact[k]) / x;
+        out[k] = p;
+      }
     }
-  } else {
+  }
+  if (kf < M) {
     double term = invfact[M], acc = term;
-    for (int m = 1; m < 48; ++m) {
+    for (int m = 1; m < 64; ++m) {
       term *= x / (double)(m + M);
       acc += term;
       if (fabs(term) <= 1e-17 * fabs(acc)) break;
@@ -42,8 +48,10 @@ __device__ __forceinline__ void phis(double x, const double *invfact, double *ou
     out[M - 1] = acc;
 #pragma unroll
     for (int k = M - 1; k >= 1; --k) {
-      acc = invfact[k] + x * acc;
-      out[k - 1] = acc;
+      if (k > kf) {
+        acc = invfact[k] + x * acc;
+        out[k - 1] = acc;
+      }
     }
   }
 }
