@@ -102,6 +102,8 @@ typedef struct {
   int64_t cg_unconverged;    /* solves that hit cg_maxit                          */
   int64_t pfasst_iters;      /* PFASST iterations                                 */
   int64_t ionic_evals;       /* node-wise cell-model evaluations (x mesh nodes)   */
+  int64_t cg_redo_steps;     /* serial steps recomputed because a solve run with  */
+                             /* a predicted iteration budget missed cg_rtol       */
 } hsdc_stats;
 
 /* Create a context and its initial state (Sec. 3.1: y(0) = y_0).

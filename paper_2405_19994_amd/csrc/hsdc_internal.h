@@ -60,9 +60,14 @@ struct Stim {
   double Cm;
 };
 
+// Per-slice CG scalars, double-buffered by iteration parity; written only by
+// block 0 of the kernel that computes them and read by the next kernel.
 struct CgScalars {
-  double rr, bb, pq, alpha, beta;
-  int32_t it, done, pad0, pad1;
+  double bb;      // ||b||^2
+  double gamma;   // (r_k, r_k) of the last iteration started
+  double alpha;   // alpha of that iteration
+  int32_t it;     // iterations completed
+  int32_t done;   // 1: converged (or maxit reached) -- x is final
 };
 
 // ---- kernel launch wrappers (defined in hsdc_kernels.hip) -------------------
@@ -88,21 +93,24 @@ int residual_blocks(const Grid &g);
 hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sdst,
                               const double *src, int64_t ssrc, int nf, int nslices);
 
-// CG on (I - a K) x = b, batched over slices with strided vectors.
+// CG on (I - a K) x = b, batched over slices with strided vectors
+// (Chronopoulos-Gear single-reduction form: one stencil kernel per iteration).
 struct CgBatch {
-  double *x; int64_t sx;    // solution (in place), slice stride
+  double *x; int64_t sx;        // solution (in place), slice stride
   const double *b; int64_t sb;
-  double *r, *p0, *p1, *q;  // [nslices][Np]
-  double *part;             // [nslices][2][nblk]
-  unsigned *cnt;            // [nslices]
-  CgScalars *sc;            // [nslices]
+  double *r[2], *w[2], *s[2];   // ping-pong [nslices][Np]
+  double *p;                    // [nslices][Np]
+  double *part;                 // [nslices][3][2][nblk] partial sums (gamma, delta by parity; bb)
+  CgScalars *sc;                // [nslices][2] by parity
+  CgScalars *log;               // [nslices] final scalars (written by the kernel k == last_k) or null
+  int last_k;
   int nslices, nblk;
   double a, tol2;
   int maxit;
 };
 int cg_blocks(const Grid &g);
 hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb);
-hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int parity);
+hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k);
 hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out);
 
 // transfers (space coarsening 2x or identity) between a fine and a coarse level

@@ -15,6 +15,18 @@ namespace hsdc {
 // phi functions (Appendix A, eq. def_phik)
 // ---------------------------------------------------------------------------
 
+// 1/n for n = 0..79 (kRecip[0] unused)
+__constant__ double kRecip[80] = {
+    0.0, 1.0 / 1, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9,
+    1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18,
+    1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
+    1.0 / 28, 1.0 / 29, 1.0 / 30, 1.0 / 31, 1.0 / 32, 1.0 / 33, 1.0 / 34, 1.0 / 35, 1.0 / 36,
+    1.0 / 37, 1.0 / 38, 1.0 / 39, 1.0 / 40, 1.0 / 41, 1.0 / 42, 1.0 / 43, 1.0 / 44, 1.0 / 45,
+    1.0 / 46, 1.0 / 47, 1.0 / 48, 1.0 / 49, 1.0 / 50, 1.0 / 51, 1.0 / 52, 1.0 / 53, 1.0 / 54,
+    1.0 / 55, 1.0 / 56, 1.0 / 57, 1.0 / 58, 1.0 / 59, 1.0 / 60, 1.0 / 61, 1.0 / 62, 1.0 / 63,
+    1.0 / 64, 1.0 / 65, 1.0 / 66, 1.0 / 67, 1.0 / 68, 1.0 / 69, 1.0 / 70, 1.0 / 71, 1.0 / 72,
+    1.0 / 73, 1.0 / 74, 1.0 / 75, 1.0 / 76, 1.0 / 77, 1.0 / 78, 1.0 / 79};
+
 // phi_1(x) = (e^x - 1)/x, phi_1(0) = 1.
 __device__ __forceinline__ double phi1(double x) { return x == 0.0 ? 1.0 : expm1(x) / x; }
 
@@ -28,12 +40,13 @@ __device__ __forceinline__ void phis(double x, const double *invfact, double *ou
   const double ax = fabs(x);
   const int kf = ax >= (double)M ? M : (int)ax;  // phi_1..phi_kf forward
   if (kf >= 1) {
-    double p = expm1(x) / x;
+    const double xi = 1.0 / x;
+    double p = expm1(x) * xi;
     out[0] = p;
 #pragma unroll
     for (int k = 1; k < M; ++k) {
       if (k < kf) {
-        p = (p - invfact[k]) / x;
+        p = (p - invfact[k]) * xi;
         out[k] = p;
       }
     }
@@ -41,7 +54,7 @@ __device__ __forceinline__ void phis(double x, const double *invfact, double *ou
   if (kf < M) {
     double term = invfact[M], acc = term;
     for (int m = 1; m < 64; ++m) {
-      term *= x / (double)(m + M);
+      term *= x * kRecip[m + M];
       acc += term;
       if (fabs(term) <= 1e-17 * fabs(acc)) break;
     }
@@ -140,35 +153,22 @@ __device__ __forceinline__ double block_max(double v, double *lds) {
   return t;
 }
 
-// Deterministic grid reduction: every block writes its partial sums; the last
-// block to finish (device-scope counter) adds the partials in a fixed order.
-// Returns true in the last block, with tot[0..NS-1] valid in thread 0.
-template <int NS>
-__device__ __forceinline__ bool grid_sums(const double (&v)[NS], double *part, int nblk,
-                                          unsigned *cnt, double (&tot)[NS]) {
-  __shared__ double lds[BLOCK / 64];
-  __shared__ bool last;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const double b = block_sum(v[s], lds);
-    if (threadIdx.x == 0) part[s * nblk + blockIdx.x] = b;
-  }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(cnt, 1u);
-    last = (prev == (unsigned)(nblk - 1));
-  }
+// Block-wide sum broadcast to every thread of the block.
+__device__ __forceinline__ double block_sum_all(double v, double *lds) {
+  __shared__ double out;
+  const double t = block_sum(v, lds);
+  if (threadIdx.x == 0) out = t;
   __syncthreads();
-  if (!last) return false;
-  __threadfence();
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += BLOCK) acc += part[s * nblk + k];
-    tot[s] = block_sum(acc, lds);
-  }
-  if (threadIdx.x == 0) *cnt = 0u;
-  return true;
+  return out;
+}
+
+// Sum of n partials in a fixed order; every block of a kernel obtains the same
+// value, so reductions need no atomics and no cross-block fences: partials are
+// written by one kernel and combined by each block of the next one.
+__device__ __forceinline__ double reduce_partials(const double *part, int n, double *lds) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += BLOCK) acc += part[k];
+  return block_sum_all(acc, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,101 +592,145 @@ hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sd
 }
 
 // ---------------------------------------------------------------------------
-// CG on (I - a K) x = b, batched over slices; two kernels per iteration:
-//   k_cg_pq: p = r + beta p_old (formed on the fly at the stencil points),
-//            q = (I - a K) p, partial p.q  -> alpha = rr / pq
-//   k_cg_xr: x += alpha p, r -= alpha q, partial r.r -> beta, convergence
-// Scalars stay on the device; finished slices return at once.
+// CG on A x = b, A = I - a K, batched over slices, in the single-reduction
+// (Chronopoulos-Gear) form:
+//   gamma = (r, r), delta = (A r, r), beta = gamma / gamma_prev,
+//   alpha = gamma / (delta - beta gamma / alpha_prev),
+//   p = r + beta p, s = A r + beta s, x += alpha p, r -= alpha s, w = A r.
+// One stencil kernel per iteration: the new r at the stencil neighbours is
+// formed on the fly from the previous r, w, s (ping-pong buffers), so one grid
+// synchronisation (the kernel boundary) and one reduction suffice.  Converged
+// slices return at once; the iteration budget is set by the host.
+// Partials per slice: [gamma par0 | delta par0 | gamma par1 | delta par1 | bb].
 // ---------------------------------------------------------------------------
 
+int cg_blocks(const Grid &g) {
+  const int64_t nb = ((int64_t)g.N + BLOCK - 1) / BLOCK;
+  return (int)(nb < 512 ? nb : 512);
+}
+
+// r_0 = b - A x_0 and w_0 = A r_0 in one pass: r_0 at the stencil neighbours is
+// formed from x_0 and b on the fly.  p_0 = s_0 = 0; partials gamma_0, delta_0, bb.
 template <int DIM, bool PN>
 __global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatch cb) {
+  __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const double *x = cb.x + n * cb.sx;
   const double *b = cb.b + n * cb.sb;
-  double *r = cb.r + n * g.Np;
-  double v[2] = {0.0, 0.0};
-  if (p < g.N) {
+  double *r = cb.r[0] + n * g.Np;
+  double *w = cb.w[0] + n * g.Np;
+  double *s = cb.s[0] + n * g.Np;
+  double *pp = cb.p + n * g.Np;
+  auto xv = [&](int64_t k) { return x[k]; };
+  auto r0 = [&](int64_t q) {
+    const Ijk cq = ijk(g, q);
+    const double xq = x[q];
+    return b[q] - (xq - cb.a * applyK<DIM, PN>(g, q, cq, xq, xv));
+  };
+  double gam = 0.0, del = 0.0, bb = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
-    const double xc = x[p];
-    const double Ax = xc - cb.a * applyK<DIM, PN>(g, p, c, xc, [&](int64_t k) { return x[k]; });
-    const double rv = b[p] - Ax;
-    r[p] = rv;
-    v[0] = rv * rv;
-    v[1] = b[p] * b[p];
+    const double rc = r0(p);
+    const double wv = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, r0);
+    r[p] = rc;
+    w[p] = wv;
+    s[p] = 0.0;
+    pp[p] = 0.0;
+    const double bv = b[p];
+    gam += rc * rc;
+    del += wv * rc;
+    bb += bv * bv;
   }
-  double tot[2];
-  if (grid_sums<2>(v, cb.part + (int64_t)n * 2 * cb.nblk, cb.nblk, cb.cnt + n, tot) &&
-      threadIdx.x == 0) {
-    CgScalars &sc = cb.sc[n];
-    sc.rr = tot[0];
-    sc.bb = tot[1];
-    sc.beta = 0.0;
-    sc.alpha = 0.0;
-    sc.pq = 0.0;
-    sc.it = 0;
-    sc.done = (tot[0] <= cb.tol2 * tot[1] || tot[0] == 0.0) ? 1 : 0;
+  double *part = cb.part + (int64_t)n * 5 * cb.nblk;
+  const double tg = block_sum(gam, lds);
+  const double td = block_sum(del, lds);
+  const double tb = block_sum(bb, lds);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = tg;
+    part[cb.nblk + blockIdx.x] = td;
+    part[4 * cb.nblk + blockIdx.x] = tb;
+    if (blockIdx.x == 0) {
+      CgScalars o;
+      o.bb = -1.0;  // reduced by the first iteration kernel
+      o.gamma = 1.0;
+      o.alpha = 1.0;
+      o.it = 0;
+      o.done = 0;
+      cb.sc[2 * n] = o;
+    }
   }
 }
 
 template <int DIM, bool PN>
-__global__ void __launch_bounds__(BLOCK) k_cg_pq(Grid g, CgBatch cb, int parity) {
+__global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
+  __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
-  if (cb.sc[n].done) return;
-  const double beta = cb.sc[n].beta;
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  const double *r = cb.r + n * g.Np;
-  const double *pold = (parity ? cb.p1 : cb.p0) + n * g.Np;
-  double *pnew = (parity ? cb.p0 : cb.p1) + n * g.Np;
-  double *q = cb.q + n * g.Np;
-  double v[1] = {0.0};
-  if (p < g.N) {
-    const Ijk c = ijk(g, p);
-    auto val = [&](int64_t k) { return beta == 0.0 ? r[k] : r[k] + beta * pold[k]; };
-    const double pc = val(p);
-    const double qv = pc - cb.a * applyK<DIM, PN>(g, p, c, pc, val);
-    pnew[p] = pc;
-    q[p] = qv;
-    v[0] = pc * qv;
+  const int in = k & 1, out = in ^ 1;
+  CgScalars si = cb.sc[2 * n + in];
+  CgScalars *so = cb.sc + 2 * n + out;
+  const bool publish = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool logit = publish && cb.log && k == cb.last_k;
+  if (si.done) {
+    if (publish) *so = si;
+    if (logit) cb.log[n] = si;
+    return;
   }
-  double tot[1];
-  if (grid_sums<1>(v, cb.part + (int64_t)n * 2 * cb.nblk, cb.nblk, cb.cnt + n, tot) &&
-      threadIdx.x == 0) {
-    CgScalars &sc = cb.sc[n];
-    sc.pq = tot[0];
-    sc.alpha = sc.rr / tot[0];
+  double *part = cb.part + (int64_t)n * 5 * cb.nblk;
+  if (si.it == 0) si.bb = reduce_partials(part + 4 * cb.nblk, cb.nblk, lds);
+  const double gamma = reduce_partials(part + (2 * in) * cb.nblk, cb.nblk, lds);
+  const double delta = reduce_partials(part + (2 * in + 1) * cb.nblk, cb.nblk, lds);
+  if (gamma <= cb.tol2 * si.bb || gamma == 0.0 || si.it >= cb.maxit) {
+    if (publish) {
+      CgScalars o = si;
+      o.gamma = gamma;
+      o.done = 1;
+      *so = o;
+      if (logit) cb.log[n] = o;
+    }
+    return;
   }
-}
-
-__global__ void __launch_bounds__(BLOCK) k_cg_xr(Grid g, CgBatch cb, int parity) {
-  const int n = blockIdx.y;
-  if (cb.sc[n].done) return;
-  const double alpha = cb.sc[n].alpha;
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const double beta = si.it == 0 ? 0.0 : gamma / si.gamma;
+  const double alpha = si.it == 0 ? gamma / delta : gamma / (delta - beta * gamma / si.alpha);
+  const double *r = cb.r[in] + n * g.Np;
+  const double *w = cb.w[in] + n * g.Np;
+  const double *s = cb.s[in] + n * g.Np;
+  double *ro = cb.r[out] + n * g.Np;
+  double *wo = cb.w[out] + n * g.Np;
+  double *sout = cb.s[out] + n * g.Np;
+  double *pp = cb.p + n * g.Np;
   double *x = cb.x + n * cb.sx;
-  const double *pnew = (parity ? cb.p0 : cb.p1) + n * g.Np;
-  double *r = cb.r + n * g.Np;
-  const double *q = cb.q + n * g.Np;
-  double v[1] = {0.0};
-  if (p < g.N) {
-    x[p] += alpha * pnew[p];
-    const double rv = r[p] - alpha * q[p];
-    r[p] = rv;
-    v[0] = rv * rv;
+  double gam = 0.0, del = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
+    const Ijk c = ijk(g, p);
+    auto rn = [&](int64_t q) { return r[q] - alpha * (w[q] + beta * s[q]); };
+    const double pn = r[p] + beta * pp[p];
+    const double sn = w[p] + beta * s[p];
+    const double rc = r[p] - alpha * sn;
+    x[p] += alpha * pn;
+    const double wn = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, rn);
+    pp[p] = pn;
+    sout[p] = sn;
+    ro[p] = rc;
+    wo[p] = wn;
+    gam += rc * rc;
+    del += wn * rc;
   }
-  double tot[1];
-  if (grid_sums<1>(v, cb.part + (int64_t)n * 2 * cb.nblk, cb.nblk, cb.cnt + n, tot) &&
-      threadIdx.x == 0) {
-    CgScalars &sc = cb.sc[n];
-    sc.beta = tot[0] / sc.rr;
-    sc.rr = tot[0];
-    sc.it += 1;
-    sc.done = (tot[0] <= cb.tol2 * sc.bb || sc.it >= cb.maxit || tot[0] == 0.0) ? 1 : 0;
+  const double tg = block_sum(gam, lds);
+  const double td = block_sum(del, lds);
+  if (threadIdx.x == 0) {
+    part[(2 * out) * cb.nblk + blockIdx.x] = tg;
+    part[(2 * out + 1) * cb.nblk + blockIdx.x] = td;
+  }
+  if (publish) {
+    CgScalars o = si;
+    o.gamma = gamma;
+    o.alpha = alpha;
+    o.it = si.it + 1;
+    o.done = 0;
+    *so = o;
+    if (logit) cb.log[n] = o;
   }
 }
-
-int cg_blocks(const Grid &g) { return (int)nblocks(g.N); }
 
 hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb) {
   dim3 grid(cb.nblk, cb.nslices);
@@ -694,11 +738,9 @@ hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb) {
   return hipGetLastError();
 }
 
-hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int parity) {
+hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k) {
   dim3 grid(cb.nblk, cb.nslices);
-  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_pq<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb,
-                                         parity));
-  hipLaunchKernelGGL(k_cg_xr, grid, dim3(BLOCK), 0, s, g, cb, parity);
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_iter<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb, k));
   return hipGetLastError();
 }
 

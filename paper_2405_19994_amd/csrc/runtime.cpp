@@ -53,11 +53,11 @@ struct Level {
   double *stim_w = nullptr;
   double *kface[3] = {nullptr, nullptr, nullptr};
   // CG workspace
-  double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_q = nullptr;
+  double *cg_r[2] = {nullptr, nullptr}, *cg_w[2] = {nullptr, nullptr};
+  double *cg_s[2] = {nullptr, nullptr}, *cg_p = nullptr;
   double *cg_part = nullptr;
-  unsigned *cg_cnt = nullptr;
-  CgScalars *cg_sc = nullptr;
-  CgScalars *cg_sc_host = nullptr;
+  CgScalars *cg_sc = nullptr;       // [P][2]
+  CgScalars *cg_sc_host = nullptr;  // [P][2]
   int cg_nblk = 0;
   // residual
   double *res_part = nullptr, *res_out = nullptr, *res_out_host = nullptr;
@@ -68,7 +68,12 @@ struct Level {
   double *RI = nullptr;   // fine: time-restricted integrals [P][Mc][NF][Np]; coarse: restricted
   double *D = nullptr;    // coarse scratch
   double *y0c = nullptr;  // coarse: restricted block start value [NF][Np]
-  int cg_pred[16][MAXM];
+  int cg_pred[16][MAXM];  // iteration budget per (sweep index, node)
+};
+
+// A diffusion solve whose outcome is checked later (budgeted mode).
+struct CgLogEntry {
+  int lev, s0, ns, i, row, parity, off, budget;
 };
 
 }  // namespace
@@ -92,6 +97,14 @@ struct hsdc_ctx {
   std::vector<void *> allocs;
   std::vector<void *> host_allocs;
   Stim stim[2]{};
+  // budgeted CG: solves enqueued without a host synchronisation, verified in
+  // bulk at the end of a step; a step with an unconverged solve is recomputed
+  bool safe_cg = true;
+  CgScalars *cg_log = nullptr;   // pinned host copy of cg_dlog
+  CgScalars *cg_dlog = nullptr;  // device: final scalars of every budgeted solve
+  int cg_log_cap = 0, cg_log_used = 0;
+  int cg_fails = 0;  // unconverged budgeted solves found by flush_cg_log
+  std::vector<CgLogEntry> cg_pending;
 };
 
 namespace {
@@ -223,14 +236,15 @@ void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc
   L.st.Lu = dalloc<double>(c, (size_t)P * L.st.sL());
   L.st.B = dalloc<double>(c, (size_t)P * Np);
   L.cg_nblk = cg_blocks(L.g);
-  L.cg_r = dalloc<double>(c, (size_t)P * Np);
-  L.cg_p0 = dalloc<double>(c, (size_t)P * Np);
-  L.cg_p1 = dalloc<double>(c, (size_t)P * Np);
-  L.cg_q = dalloc<double>(c, (size_t)P * Np);
-  L.cg_part = dalloc<double>(c, (size_t)P * 2 * L.cg_nblk);
-  L.cg_cnt = dalloc<unsigned>(c, P);
-  L.cg_sc = dalloc<CgScalars>(c, P);
-  L.cg_sc_host = halloc<CgScalars>(c, P);
+  for (int k = 0; k < 2; ++k) {
+    L.cg_r[k] = dalloc<double>(c, (size_t)P * Np);
+    L.cg_w[k] = dalloc<double>(c, (size_t)P * Np);
+    L.cg_s[k] = dalloc<double>(c, (size_t)P * Np);
+  }
+  L.cg_p = dalloc<double>(c, (size_t)P * Np);
+  L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_nblk);
+  L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
+  L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
   L.res_nblk = residual_blocks(L.g);
   L.res_part = dalloc<double>(c, (size_t)P * 2 * L.res_nblk);
   L.res_out = dalloc<double>(c, (size_t)2 * P);
@@ -243,57 +257,114 @@ void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc
     L.y0c = dalloc<double>(c, (size_t)NF * Np);
   }
   for (auto &row : L.cg_pred)
-    for (int &v : row) v = 6;
+    for (int &v : row) v = 8;
 }
 
 // ---------------------------------------------------------------------------
 // diffusion solve for node i of a sweep, slices [s0, s0+ns)
 // ---------------------------------------------------------------------------
-void cg_solve(hsdc_ctx *c, Level &L, int s0, int ns, int i, int pred_row) {
+CgBatch make_batch(hsdc_ctx *c, Level &L, int s0, int ns, int i) {
   CgBatch cb{};
   const int64_t Np = L.g.Np;
   cb.x = L.st.Y + s0 * L.st.sY() + (int64_t)i * L.st.sS();
   cb.sx = L.st.sY();
   cb.b = L.st.B + s0 * Np;
   cb.sb = Np;
-  cb.r = L.cg_r + s0 * Np;
-  cb.p0 = L.cg_p0 + s0 * Np;
-  cb.p1 = L.cg_p1 + s0 * Np;
-  cb.q = L.cg_q + s0 * Np;
-  cb.part = L.cg_part + (int64_t)s0 * 2 * L.cg_nblk;
-  cb.cnt = L.cg_cnt + s0;
-  cb.sc = L.cg_sc + s0;
+  for (int k = 0; k < 2; ++k) {
+    cb.r[k] = L.cg_r[k] + s0 * Np;
+    cb.w[k] = L.cg_w[k] + s0 * Np;
+    cb.s[k] = L.cg_s[k] + s0 * Np;
+  }
+  cb.p = L.cg_p + s0 * Np;
+  cb.part = L.cg_part + (int64_t)s0 * 5 * L.cg_nblk;
+  cb.sc = L.cg_sc + 2 * s0;
+  cb.log = nullptr;
+  cb.last_k = -1;
   cb.nslices = ns;
   cb.nblk = L.cg_nblk;
   cb.a = L.co.dt * L.co.d[i - 1];
   cb.tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
   cb.maxit = c->meth.cg_maxit;
+  return cb;
+}
+
+bool cg_ok(const CgScalars &sc, double tol2) {
+  return sc.done && (sc.gamma <= tol2 * sc.bb || sc.gamma == 0.0);
+}
+
+// Check every budgeted solve enqueued since the last check (one host
+// synchronisation); slices whose solve missed cg_rtol are added to cg_fails.
+void flush_cg_log(hsdc_ctx *c) {
+  if (c->cg_pending.empty()) return;
+  HIPC(hipMemcpyAsync(c->cg_log, c->cg_dlog, c->cg_log_used * sizeof(CgScalars),
+                      hipMemcpyDeviceToHost, c->s));
+  HIPC(hipStreamSynchronize(c->s));
+  const double tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
+  int fails = 0;
+  for (const CgLogEntry &e : c->cg_pending) {
+    Level &L = c->L[e.lev];
+    int used = 0;
+    bool ok_all = true;
+    for (int n = 0; n < e.ns; ++n) {
+      const CgScalars &sc = c->cg_log[e.off + n];
+      const bool ok = cg_ok(sc, tol2);
+      ok_all = ok_all && ok;
+      used = std::max(used, sc.it);
+      c->stats.cg_iters += sc.it;
+      c->stats.cg_solves += 1;
+      if (!ok) ++fails;
+    }
+    // budget = iterations needed + 2, lowered by at most one per check; doubled
+    // after a miss (a spare no-op iteration costs far less than a recomputed step)
+    int &pred = L.cg_pred[e.row & 15][e.i - 1];
+    if (ok_all)
+      pred = std::max(used + 2, pred - 1);
+    else
+      pred = std::min(c->meth.cg_maxit + 1, std::max(2 * e.budget, used + 4));
+  }
+  c->cg_pending.clear();
+  c->cg_log_used = 0;
+  c->cg_fails += fails;
+}
+
+void cg_solve(hsdc_ctx *c, int lev, int s0, int ns, int i, int pred_row) {
+  Level &L = c->L[lev];
+  CgBatch cb = make_batch(c, L, s0, ns, i);
   HIPC(launch_cg_init(c->s, L.g, cb));
   int &pred = L.cg_pred[pred_row & 15][i - 1];
-  int it = 0, parity = 0;
-  int batch = std::max(1, std::min(pred, cb.maxit));
+  if (!c->safe_cg) {
+    if (c->cg_log_used + ns > c->cg_log_cap) flush_cg_log(c);  // log full: verify now
+    const int budget = std::max(1, std::min(pred, cb.maxit + 1));
+    cb.log = c->cg_dlog + c->cg_log_used;
+    cb.last_k = budget - 1;
+    for (int k = 0; k < budget; ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+    c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget});
+    c->cg_log_used += ns;
+    return;
+  }
+  // safe mode: iterate until every slice has converged, checking on the host
+  const double tol2 = cb.tol2;
+  int k = 0;
+  int batch = std::max(1, std::min(pred, cb.maxit + 1));
   for (;;) {
-    for (int k = 0; k < batch && it < cb.maxit; ++k, ++it) {
-      HIPC(launch_cg_iter(c->s, L.g, cb, parity));
-      parity ^= 1;
-    }
-    HIPC(hipMemcpyAsync(L.cg_sc_host + s0, L.cg_sc + s0, ns * sizeof(CgScalars),
+    for (int q = 0; q < batch && k <= cb.maxit; ++q, ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+    HIPC(hipMemcpyAsync(L.cg_sc_host + 2 * s0, L.cg_sc + 2 * s0, 2 * ns * sizeof(CgScalars),
                         hipMemcpyDeviceToHost, c->s));
     HIPC(hipStreamSynchronize(c->s));
     bool all = true;
-    for (int n = 0; n < ns; ++n) all = all && L.cg_sc_host[s0 + n].done;
-    if (all || it >= cb.maxit) break;
-    batch = 1;
+    for (int n = 0; n < ns; ++n) all = all && L.cg_sc_host[2 * (s0 + n) + (k & 1)].done;
+    if (all || k > cb.maxit) break;
+    batch = 2;
   }
-  int maxused = 0;
+  int used = 0;
   for (int n = 0; n < ns; ++n) {
-    const CgScalars &sc = L.cg_sc_host[s0 + n];
-    maxused = std::max(maxused, sc.it);
+    const CgScalars &sc = L.cg_sc_host[2 * (s0 + n) + (k & 1)];
+    used = std::max(used, sc.it);
     c->stats.cg_iters += sc.it;
     c->stats.cg_solves += 1;
-    if (!(sc.rr <= cb.tol2 * sc.bb || sc.rr == 0.0)) c->stats.cg_unconverged += 1;
+    if (!cg_ok(sc, tol2)) c->stats.cg_unconverged += 1;
   }
-  pred = std::max(1, maxused);
+  pred = std::max(used + 2, pred - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,7 +398,7 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
     HIPC(launch_node_update(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                             p.g_scale[2], s0, ns, i, step0));
     if (i > 1) c->stats.ionic_evals += N * ns;
-    cg_solve(c, L, s0, ns, i, pred_row);
+    cg_solve(c, lev, s0, ns, i, pred_row);
   }
   HIPC(launch_eval_stages(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                           p.g_scale[2], s0, ns, M, 1, step0, nullptr, st.Lu));
@@ -536,6 +607,9 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
     alloc_level(c, F, meth->M[0], P, false, Mc);
     if (prob->sigma_node) build_faces(c, F, prob->sigma_node);
     c->y0blk = dalloc<double>(c, (size_t)NF * F.g.Np);
+    c->cg_log_cap = 8192;
+    c->cg_log = halloc<CgScalars>(c, c->cg_log_cap);
+    c->cg_dlog = dalloc<CgScalars>(c, c->cg_log_cap);
     if (prob->stim_w) {
       F.stim_w = dalloc<double>(c, F.g.Np);
       HIPC(hipMemcpyAsync(F.stim_w, prob->stim_w, F.g.N * sizeof(double),
@@ -622,9 +696,24 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
     Level &F = c->L[0];
     for (int s = 0; s < nsteps; ++s) {
       if (!c->pfasst) {
+        // budgeted solves, verified once per step; a step with a solve that
+        // missed cg_rtol is recomputed from y_n with every solve checked
+        c->safe_cg = false;
+        c->cg_fails = 0;
         while (c->sweeps_done < c->meth.max_iter) {
           sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++);
           c->sweeps_done += 1;
+        }
+        flush_cg_log(c);
+        c->safe_cg = true;
+        if (c->cg_fails > 0) {
+          c->stats.cg_redo_steps += 1;
+          c->cg_fails = 0;
+          begin_serial_step(c);
+          while (c->sweeps_done < c->meth.max_iter) {
+            sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++);
+            c->sweeps_done += 1;
+          }
         }
         // y_{n+1} = y_{n,M}
         HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0, F.st.Y + (int64_t)F.co.M * F.st.sS(), 0,
@@ -809,29 +898,33 @@ hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const doubl
     cb.sx = 0;
     cb.b = b;
     cb.sb = 0;
-    cb.r = dalloc<double>(&tmp, Np);
-    cb.p0 = dalloc<double>(&tmp, Np);
-    cb.p1 = dalloc<double>(&tmp, Np);
-    cb.q = dalloc<double>(&tmp, Np);
-    cb.part = dalloc<double>(&tmp, 2 * L.cg_nblk);
-    cb.cnt = dalloc<unsigned>(&tmp, 1);
-    cb.sc = dalloc<CgScalars>(&tmp, 1);
+    for (int k = 0; k < 2; ++k) {
+      cb.r[k] = dalloc<double>(&tmp, Np);
+      cb.w[k] = dalloc<double>(&tmp, Np);
+      cb.s[k] = dalloc<double>(&tmp, Np);
+    }
+    cb.p = dalloc<double>(&tmp, Np);
+    cb.part = dalloc<double>(&tmp, 5 * L.cg_nblk);
+    cb.sc = dalloc<CgScalars>(&tmp, 2);
+    cb.log = nullptr;
+    cb.last_k = -1;
     cb.nslices = 1;
     cb.nblk = L.cg_nblk;
     cb.a = a;
     cb.tol2 = rtol * rtol;
     cb.maxit = maxit;
     HIPC(launch_cg_init(tmp.s, L.g, cb));
-    int parity = 0;
-    CgScalars sc{};
-    for (int it = 0; it < maxit; ++it) {
-      HIPC(launch_cg_iter(tmp.s, L.g, cb, parity));
-      parity ^= 1;
+    CgScalars sc2[2];
+    int k = 0;
+    for (;;) {
+      for (int q = 0; q < 4 && k <= maxit; ++q, ++k) HIPC(launch_cg_iter(tmp.s, L.g, cb, k));
+      HIPC(hipMemcpyAsync(sc2, cb.sc, sizeof(sc2), hipMemcpyDeviceToHost, tmp.s));
+      HIPC(hipStreamSynchronize(tmp.s));
+      if (sc2[k & 1].done || k > maxit) break;
     }
-    HIPC(hipMemcpyAsync(&sc, cb.sc, sizeof(sc), hipMemcpyDeviceToHost, tmp.s));
-    HIPC(hipStreamSynchronize(tmp.s));
+    const CgScalars &sc = sc2[k & 1];
     used = sc.it;
-    conv = sc.rr <= cb.tol2 * sc.bb || sc.rr == 0.0;
+    conv = cg_ok(sc, cb.tol2);
     return HSDC_OK;
   });
   for (void *p : tmp.allocs) hipFree(p);

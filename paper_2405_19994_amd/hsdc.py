@@ -47,7 +47,7 @@ class Method(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("steps", "sweeps", "coarse_sweeps", "cg_solves",
                                               "cg_iters", "cg_unconverged", "pfasst_iters",
-                                              "ionic_evals")]
+                                              "ionic_evals", "cg_redo_steps")]
 
 
 _lib = None

@@ -19,7 +19,7 @@ def test_struct_layout_matches_header():
     # field order and C types of the two public structs
     assert ctypes.sizeof(H.Problem) == 4 * 4 + 8 + 24 + 8 + 8 + 8 + 24 + 8 + 24
     assert [f for f, _ in H.Problem._fields_][:5] == ["dim", "nx", "ny", "nz", "dx"]
-    assert ctypes.sizeof(H.Stats) == 8 * 8
+    assert ctypes.sizeof(H.Stats) == 9 * 8
 
 
 def _init(p, m):
