@@ -82,9 +82,13 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
                          bool copy_Y_from_stage0);
 hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *RI, int64_t sRI);
+// The node update also forms the CG start residual r_0 = b - x_0 + a K x_0 from
+// the cached K x_0 (x_0 = V^k_i) and writes the partials of ||b||^2, ||r_0||^2.
+struct CgBatch;
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int i, int64_t step0);
+                              int nslices, int i, int64_t step0, const CgBatch &cb);
+int node_blocks(const Grid &g);
 hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *y_block0, double *part,
                            int nblk, double *out2, const double *Rt, int Mc, double *RI,
@@ -100,16 +104,20 @@ struct CgBatch {
   const double *b; int64_t sb;
   double *r[2], *w[2], *s[2];   // ping-pong [nslices][Np]
   double *p;                    // [nslices][Np]
-  double *part;                 // [nslices][3][2][nblk] partial sums (gamma, delta by parity; bb)
+  double *part;                 // [nslices][5][pstride] partial sums:
+                                //   gamma par0 | delta par0 | gamma par1 | delta par1 | bb
+  int64_t pstride;
   CgScalars *sc;                // [nslices][2] by parity
   CgScalars *log;               // [nslices] final scalars (written by the kernel k == last_k) or null
   int last_k;
-  int nslices, nblk;
+  int nslices, nblk;            // blocks of the CG kernels (<= 512)
+  int nblk0;                    // partials of gamma_0 and bb (written by the producer of r_0)
   double a, tol2;
   int maxit;
 };
 int cg_blocks(const Grid &g);
 hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb);
+hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatch &cb);
 hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k);
 hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out);
 

@@ -382,43 +382,39 @@ __global__ void __launch_bounds__(BLOCK)
 k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t sRI) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= g.N) return;
+  const int f = blockIdx.y;  // one field per block row: no divergence between field kinds
   const int n = slice0 + blockIdx.z;
   const int64_t Np = st.Np;
-  const double *G = st.G + n * st.sY();
-  const double *FV = st.FV + n * st.sFV();
-  const double *L0 = st.L0 + n * st.sL();
-  double *RH = st.RH + n * st.sRH();
+  const double *G = st.G + n * st.sY() + f * Np + p;
+  const double *FV = st.FV + n * st.sFV() + p;
+  double *RH = st.RH + n * st.sRH() + f * Np + p;
   const double dt = co.dt;
-  double fv[M + 1];
+  double Gv[M + 1], fv[M + 1], gfull[M], I[M];
 #pragma unroll
-  for (int j = 1; j <= M; ++j) fv[j] = FV[j * Np + p];
-  for (int f = 0; f < NF; ++f) {
-    double Gv[M + 1], gfull[M], I[M];
+  for (int j = 0; j <= M; ++j) Gv[j] = G[j * st.sS()];
 #pragma unroll
-    for (int j = 0; j <= M; ++j) Gv[j] = G[j * st.sS() + f * Np + p];
+  for (int j = 0; j <= M; ++j) fv[j] = (f == 0 && j > 0) ? FV[j * Np] : 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + (f == 0 ? fv[j + 1] : 0.0);
-    const double z = (f >= GATE0) ? dt * L0[(f - GATE0) * Np + p] : 0.0;
-    if (RI) {
+  for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + fv[j + 1];
+  const double z = (f >= GATE0) ? dt * st.L0[n * st.sL() + (f - GATE0) * Np + p] : 0.0;
+  if (RI) {
 #pragma unroll
-      for (int i = 0; i < M; ++i) I[i] = RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
-    } else {
-      colloc_integrals<M>(co, z, gfull, I);
-    }
-    double prevI = 0.0;
+    for (int i = 0; i < M; ++i) I[i] = RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
+  } else {
+    colloc_integrals<M>(co, z, gfull, I);
+  }
+  double prevI = 0.0;
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      const double ph = (f >= GATE0) ? phi1(co.d[i] * z) : 1.0;
-      const double Phi = (f == 0 ? fv[i + 1] : 0.0) + ph * Gv[i];
-      RH[(int64_t)i * st.sS() + f * Np + p] = dt * (I[i] - prevI) - dt * co.d[i] * Phi;
-      prevI = I[i];
-    }
+  for (int i = 0; i < M; ++i) {
+    const double ph = (f >= GATE0) ? phi1(co.d[i] * z) : 1.0;
+    RH[(int64_t)i * st.sS()] = dt * (I[i] - prevI) - dt * co.d[i] * (fv[i + 1] + ph * Gv[i]);
+    prevI = I[i];
   }
 }
 
 hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *RI, int64_t sRI) {
-  dim3 grid(nblocks(g.N), 1, nslices);
+  dim3 grid(nblocks(g.N), NF, nslices);
   HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_assemble<M>), grid, dim3(BLOCK), 0, s, g, st, co,
                                            slice0, RI, sRI));
   return hipGetLastError();
@@ -432,59 +428,79 @@ hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const
 
 __global__ void __launch_bounds__(BLOCK)
 k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int i, int64_t step0) {
+              int slice0, int i, int64_t step0, CgBatch cb) {
+  __shared__ double lds[BLOCK / 64];
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= g.N) return;
   const int n = slice0 + blockIdx.z;
   const int64_t Np = st.Np;
-  const double *Yp = st.Y + n * st.sY() + (int64_t)(i - 1) * st.sS();
-  double *Yi = st.Y + n * st.sY() + (int64_t)i * st.sS();
-  const double *u = st.Y + n * st.sY();
-  const double *RH = st.RH + n * st.sRH() + (int64_t)(i - 1) * st.sS();
-  const double *Lu = st.Lu + n * st.sL();
-  double *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
   const double ddt = co.dt * co.d[i - 1];
-  double yv[NF];
+  double bb = 0.0, rr = 0.0;
+  if (p < g.N) {
+    const double *Yp = st.Y + n * st.sY() + (int64_t)(i - 1) * st.sS();
+    double *Yi = st.Y + n * st.sY() + (int64_t)i * st.sS();
+    const double *u = st.Y + n * st.sY();
+    const double *RH = st.RH + n * st.sRH() + (int64_t)(i - 1) * st.sS();
+    const double *Lu = st.Lu + n * st.sL();
+    double *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
+    double yv[NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) yv[f] = Yp[f * Np + p];
-  if (i == 1) {
-    // y_{n,0} = u: its reaction term was evaluated with the anchor
+    for (int f = 0; f < NF; ++f) yv[f] = Yp[f * Np + p];
+    double gV;
+    if (i == 1) {
+      // y_{n,0} = u: its reaction term was evaluated with the anchor
 #pragma unroll
-    for (int f = 1; f < NF; ++f) {
-      const double gv = Gp[f * Np + p];
-      const double ph = (f >= GATE0) ? phi1(ddt * Lu[(f - GATE0) * Np + p]) : 1.0;
-      Yi[f * Np + p] = yv[f] + RH[f * Np + p] + ddt * ph * gv;
+      for (int f = 1; f < NF; ++f) {
+        const double gv = Gp[f * Np + p];
+        const double ph = (f >= GATE0) ? phi1(ddt * Lu[(f - GATE0) * Np + p]) : 1.0;
+        Yi[f * Np + p] = yv[f] + RH[f * Np + p] + ddt * ph * gv;
+      }
+      gV = Gp[p];
+    } else {
+      const double t = ((double)(step0 + n) + co.c[i - 2]) * co.dt;
+      ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
+        const int f = GATE0 + k;
+        const double lu = Lu[k * Np + p];
+        const double w = yv[f];
+        const double gv = (-1.0 / tau) * (w - inf) + lu * (u[f * Np + p] - w);
+        Gp[f * Np + p] = gv;
+        Yi[f * Np + p] = w + RH[f * Np + p] + ddt * phi1(ddt * lu) * gv;
+      });
+      double I_ion, ha[6];
+      ttp06::currents(yv, gs0, gs1, gs2, I_ion, ha);
+      gV = (stim_value(stim, t, p) - stim.Cm * I_ion) / stim.Cm;
+      Gp[p] = gV;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        Gp[(1 + k) * Np + p] = ha[k];
+        Yi[(1 + k) * Np + p] = yv[1 + k] + RH[(1 + k) * Np + p] + ddt * ha[k];
+      }
     }
-    st.B[n * Np + p] = yv[0] + RH[p] + ddt * Gp[p];
-    return;
+    // right-hand side of (I - dt d_i K) V_i = b and the CG start residual for
+    // the warm start x_0 = V^k_i, whose K x_0 is cached from the previous sweep
+    const double bv = yv[0] + RH[p] + ddt * gV;
+    const double x0 = Yi[p];
+    const double r0 = bv - x0 + cb.a * st.FV[n * st.sFV() + (int64_t)i * Np + p];
+    cb.r[0][(int64_t)(n - slice0) * Np + p] = r0;
+    bb = bv * bv;
+    rr = r0 * r0;
   }
-  const double t = ((double)(step0 + n) + co.c[i - 2]) * co.dt;
-  ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
-    const int f = GATE0 + k;
-    const double lu = Lu[k * Np + p];
-    const double w = yv[f];
-    const double gv = (-1.0 / tau) * (w - inf) + lu * (u[f * Np + p] - w);
-    Gp[f * Np + p] = gv;
-    Yi[f * Np + p] = w + RH[f * Np + p] + ddt * phi1(ddt * lu) * gv;
-  });
-  double I_ion, ha[6];
-  ttp06::currents(yv, gs0, gs1, gs2, I_ion, ha);
-  const double gV = (stim_value(stim, t, p) - stim.Cm * I_ion) / stim.Cm;
-  Gp[p] = gV;
-  st.B[n * Np + p] = yv[0] + RH[p] + ddt * gV;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    Gp[(1 + k) * Np + p] = ha[k];
-    Yi[(1 + k) * Np + p] = yv[1 + k] + RH[(1 + k) * Np + p] + ddt * ha[k];
+  const double tb = block_sum(bb, lds);
+  const double tr = block_sum(rr, lds);
+  if (threadIdx.x == 0) {
+    double *part = cb.part + (int64_t)(n - slice0) * 5 * cb.pstride;
+    part[4 * cb.pstride + blockIdx.x] = tb;
+    part[blockIdx.x] = tr;
   }
 }
 
+int node_blocks(const Grid &g) { return (int)nblocks(g.N); }
+
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int i, int64_t step0) {
+                              int nslices, int i, int64_t step0, const CgBatch &cb) {
   dim3 grid(nblocks(g.N), 1, nslices);
   hipLaunchKernelGGL(k_node_update, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
-                     slice0, i, step0);
+                     slice0, i, step0, cb);
   return hipGetLastError();
 }
 
@@ -609,46 +625,53 @@ int cg_blocks(const Grid &g) {
   return (int)(nb < 512 ? nb : 512);
 }
 
-// r_0 = b - A x_0 and w_0 = A r_0 in one pass: r_0 at the stencil neighbours is
-// formed from x_0 and b on the fly.  p_0 = s_0 = 0; partials gamma_0, delta_0, bb.
+// Start residual r_0 = b - A x_0 with the partials of ||r_0||^2 and ||b||^2
+// (used when r_0 is not produced by the node update).
 template <int DIM, bool PN>
-__global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatch cb) {
+__global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g, CgBatch cb) {
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
   const double *x = cb.x + n * cb.sx;
   const double *b = cb.b + n * cb.sb;
   double *r = cb.r[0] + n * g.Np;
-  double *w = cb.w[0] + n * g.Np;
-  double *s = cb.s[0] + n * g.Np;
-  double *pp = cb.p + n * g.Np;
-  auto xv = [&](int64_t k) { return x[k]; };
-  auto r0 = [&](int64_t q) {
-    const Ijk cq = ijk(g, q);
-    const double xq = x[q];
-    return b[q] - (xq - cb.a * applyK<DIM, PN>(g, q, cq, xq, xv));
-  };
-  double gam = 0.0, del = 0.0, bb = 0.0;
+  double rr = 0.0, bb = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
-    const double rc = r0(p);
-    const double wv = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, r0);
-    r[p] = rc;
-    w[p] = wv;
-    s[p] = 0.0;
-    pp[p] = 0.0;
+    const double xc = x[p];
     const double bv = b[p];
-    gam += rc * rc;
-    del += wv * rc;
+    const double rc = bv - (xc - cb.a * applyK<DIM, PN>(g, p, c, xc, [&](int64_t k) { return x[k]; }));
+    r[p] = rc;
+    rr += rc * rc;
     bb += bv * bv;
   }
-  double *part = cb.part + (int64_t)n * 5 * cb.nblk;
-  const double tg = block_sum(gam, lds);
-  const double td = block_sum(del, lds);
+  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+  const double tr = block_sum(rr, lds);
   const double tb = block_sum(bb, lds);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = tg;
-    part[cb.nblk + blockIdx.x] = td;
-    part[4 * cb.nblk + blockIdx.x] = tb;
+    part[blockIdx.x] = tr;
+    part[4 * cb.pstride + blockIdx.x] = tb;
+  }
+}
+
+// w_0 = A r_0 and the partials of delta_0 = (w_0, r_0); resets the scalars.
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatch cb) {
+  __shared__ double lds[BLOCK / 64];
+  const int n = blockIdx.y;
+  const double *r = cb.r[0] + n * g.Np;
+  double *w = cb.w[0] + n * g.Np;
+  double del = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
+    const Ijk c = ijk(g, p);
+    const double rc = r[p];
+    const double wv = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, [&](int64_t k) { return r[k]; });
+    w[p] = wv;
+    del += wv * rc;
+  }
+  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+  const double td = block_sum(del, lds);
+  if (threadIdx.x == 0) {
+    part[cb.pstride + blockIdx.x] = td;
     if (blockIdx.x == 0) {
       CgScalars o;
       o.bb = -1.0;  // reduced by the first iteration kernel
@@ -675,10 +698,45 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
     if (logit) cb.log[n] = si;
     return;
   }
-  double *part = cb.part + (int64_t)n * 5 * cb.nblk;
-  if (si.it == 0) si.bb = reduce_partials(part + 4 * cb.nblk, cb.nblk, lds);
-  const double gamma = reduce_partials(part + (2 * in) * cb.nblk, cb.nblk, lds);
-  const double delta = reduce_partials(part + (2 * in + 1) * cb.nblk, cb.nblk, lds);
+  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+  const double *r = cb.r[in] + n * g.Np;
+  const double *w = cb.w[in] + n * g.Np;
+  const double *s = cb.s[in] + n * g.Np;
+  double gamma, delta;
+  // first owned node: its stencil loads are issued before the partial sums
+  // are combined, so the reduction latency overlaps the memory traffic
+  const int64_t p0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  double r_c = 0.0, w_c = 0.0, s_c = 0.0, rn_[2 * DIM], wn_[2 * DIM], sn_[2 * DIM];
+  Ijk c0{0, 0, 0};
+  if (si.it == 0) {
+    si.bb = reduce_partials(part + 4 * cb.pstride, cb.nblk0, lds);
+    gamma = reduce_partials(part, cb.nblk0, lds);
+    delta = reduce_partials(part + cb.pstride, cb.nblk, lds);
+  } else {
+    const double *pg = part + (2 * in) * cb.pstride, *pd = part + (2 * in + 1) * cb.pstride;
+    const int t = threadIdx.x;
+    const double g0 = t < cb.nblk ? pg[t] : 0.0, g1 = t + BLOCK < cb.nblk ? pg[t + BLOCK] : 0.0;
+    const double d0 = t < cb.nblk ? pd[t] : 0.0, d1 = t + BLOCK < cb.nblk ? pd[t + BLOCK] : 0.0;
+    if (!PN && p0 < g.N) {
+      c0 = ijk(g, p0);
+      r_c = r[p0];
+      w_c = w[p0];
+      s_c = s[p0];
+      const int64_t off[6] = {-1, 1, -(int64_t)g.nx, (int64_t)g.nx, -(int64_t)g.nx * g.ny,
+                              (int64_t)g.nx * g.ny};
+      const bool ok[6] = {c0.ix > 0, c0.ix < g.nx - 1, c0.iy > 0, c0.iy < g.ny - 1, c0.iz > 0,
+                          c0.iz < g.nz - 1};
+#pragma unroll
+      for (int q = 0; q < 2 * DIM; ++q) {
+        const int64_t idx = ok[q] ? p0 + off[q] : p0;
+        rn_[q] = r[idx];
+        wn_[q] = w[idx];
+        sn_[q] = s[idx];
+      }
+    }
+    gamma = block_sum_all(g0 + g1, lds);
+    delta = block_sum_all(d0 + d1, lds);
+  }
   if (gamma <= cb.tol2 * si.bb || gamma == 0.0 || si.it >= cb.maxit) {
     if (publish) {
       CgScalars o = si;
@@ -689,23 +747,20 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
     }
     return;
   }
-  const double beta = si.it == 0 ? 0.0 : gamma / si.gamma;
-  const double alpha = si.it == 0 ? gamma / delta : gamma / (delta - beta * gamma / si.alpha);
-  const double *r = cb.r[in] + n * g.Np;
-  const double *w = cb.w[in] + n * g.Np;
-  const double *s = cb.s[in] + n * g.Np;
+  const bool first = si.it == 0;
+  const double beta = first ? 0.0 : gamma / si.gamma;
+  const double alpha = first ? gamma / delta : gamma / (delta - beta * gamma / si.alpha);
   double *ro = cb.r[out] + n * g.Np;
   double *wo = cb.w[out] + n * g.Np;
   double *sout = cb.s[out] + n * g.Np;
   double *pp = cb.p + n * g.Np;
   double *x = cb.x + n * cb.sx;
   double gam = 0.0, del = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
-    const Ijk c = ijk(g, p);
-    auto rn = [&](int64_t q) { return r[q] - alpha * (w[q] + beta * s[q]); };
-    const double pn = r[p] + beta * pp[p];
-    const double sn = w[p] + beta * s[p];
-    const double rc = r[p] - alpha * sn;
+  // iteration 0 takes p = r, s = w (p and s hold nothing yet)
+  auto update = [&](int64_t p, const Ijk &c, double rc0, double wc0, double sc0, auto &&rn) {
+    const double pn = first ? rc0 : rc0 + beta * pp[p];
+    const double sn = first ? wc0 : wc0 + beta * sc0;
+    const double rc = rc0 - alpha * sn;
     x[p] += alpha * pn;
     const double wn = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, rn);
     pp[p] = pn;
@@ -714,12 +769,46 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
     wo[p] = wn;
     gam += rc * rc;
     del += wn * rc;
+  };
+  // r of this iteration at a stencil neighbour, formed from the previous r, w, s
+  auto rfull = [&](int64_t qq) {
+    return first ? r[qq] - alpha * w[qq] : r[qq] - alpha * (w[qq] + beta * s[qq]);
+  };
+  int64_t p = p0;
+  if (!PN && !first && p0 < g.N) {
+    // first owned node from the prefetched registers; the neighbour order
+    // -x, +x, -y, +y, -z, +z and the per-axis grouping follow applyK
+    const bool ok[6] = {c0.ix > 0, c0.ix < g.nx - 1, c0.iy > 0, c0.iy < g.ny - 1, c0.iz > 0,
+                        c0.iz < g.nz - 1};
+    const double pn = r_c + beta * pp[p0];
+    const double sn = w_c + beta * s_c;
+    const double rc = r_c - alpha * sn;
+    x[p0] += alpha * pn;
+    double ax[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int qq = 0; qq < 2 * DIM; ++qq)
+      if (ok[qq]) ax[qq >> 1] += (rn_[qq] - alpha * (wn_[qq] + beta * sn_[qq])) - rc;
+    double acc = g.cx * ax[0];
+    if (DIM >= 2) acc += g.cy * ax[1];
+    if (DIM >= 3) acc += g.cz * ax[2];
+    const double wn = rc - cb.a * acc;
+    pp[p0] = pn;
+    sout[p0] = sn;
+    ro[p0] = rc;
+    wo[p0] = wn;
+    gam += rc * rc;
+    del += wn * rc;
+    p += (int64_t)cb.nblk * BLOCK;
+  }
+  for (; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
+    const Ijk c = ijk(g, p);
+    update(p, c, r[p], w[p], s[p], rfull);
   }
   const double tg = block_sum(gam, lds);
   const double td = block_sum(del, lds);
   if (threadIdx.x == 0) {
-    part[(2 * out) * cb.nblk + blockIdx.x] = tg;
-    part[(2 * out + 1) * cb.nblk + blockIdx.x] = td;
+    part[(2 * out) * cb.pstride + blockIdx.x] = tg;
+    part[(2 * out + 1) * cb.pstride + blockIdx.x] = td;
   }
   if (publish) {
     CgScalars o = si;
@@ -735,6 +824,12 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
 hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb) {
   dim3 grid(cb.nblk, cb.nslices);
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_init<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatch &cb) {
+  dim3 grid(cb.nblk, cb.nslices);
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_resid0<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb));
   return hipGetLastError();
 }
 

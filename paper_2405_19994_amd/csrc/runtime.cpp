@@ -59,6 +59,7 @@ struct Level {
   CgScalars *cg_sc = nullptr;       // [P][2]
   CgScalars *cg_sc_host = nullptr;  // [P][2]
   int cg_nblk = 0;
+  int64_t cg_pstride = 0;
   // residual
   double *res_part = nullptr, *res_out = nullptr, *res_out_host = nullptr;
   int res_nblk = 0;
@@ -242,7 +243,8 @@ void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc
     L.cg_s[k] = dalloc<double>(c, (size_t)P * Np);
   }
   L.cg_p = dalloc<double>(c, (size_t)P * Np);
-  L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_nblk);
+  L.cg_pstride = std::max(L.cg_nblk, node_blocks(L.g));
+  L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
   L.res_nblk = residual_blocks(L.g);
@@ -276,12 +278,14 @@ CgBatch make_batch(hsdc_ctx *c, Level &L, int s0, int ns, int i) {
     cb.s[k] = L.cg_s[k] + s0 * Np;
   }
   cb.p = L.cg_p + s0 * Np;
-  cb.part = L.cg_part + (int64_t)s0 * 5 * L.cg_nblk;
+  cb.pstride = L.cg_pstride;
+  cb.part = L.cg_part + (int64_t)s0 * 5 * L.cg_pstride;
   cb.sc = L.cg_sc + 2 * s0;
   cb.log = nullptr;
   cb.last_k = -1;
   cb.nslices = ns;
   cb.nblk = L.cg_nblk;
+  cb.nblk0 = node_blocks(L.g);  // r_0 and its partials come from the node update
   cb.a = L.co.dt * L.co.d[i - 1];
   cb.tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
   cb.maxit = c->meth.cg_maxit;
@@ -395,8 +399,9 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
     st.Lu = L.st.L0;  // the anchor is unchanged
   }
   for (int i = 1; i <= M; ++i) {
+    const CgBatch cb = make_batch(c, L, s0, ns, i);
     HIPC(launch_node_update(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                            p.g_scale[2], s0, ns, i, step0));
+                            p.g_scale[2], s0, ns, i, step0, cb));
     if (i > 1) c->stats.ionic_evals += N * ns;
     cg_solve(c, lev, s0, ns, i, pred_row);
   }
@@ -910,9 +915,12 @@ hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const doubl
     cb.last_k = -1;
     cb.nslices = 1;
     cb.nblk = L.cg_nblk;
+    cb.nblk0 = L.cg_nblk;
+    cb.pstride = L.cg_nblk;
     cb.a = a;
     cb.tol2 = rtol * rtol;
     cb.maxit = maxit;
+    HIPC(launch_cg_resid0(tmp.s, L.g, cb));
     HIPC(launch_cg_init(tmp.s, L.g, cb));
     CgScalars sc2[2];
     int k = 0;
