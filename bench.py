@@ -29,7 +29,8 @@ def _args():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-kernels", action="store_true", default=True)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -54,6 +55,31 @@ def cpu_baseline(w, nsteps=2, side=128):
     return {"value": updates / dt, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{side}x{side} corner sub-slab of the 512x512 slab, first {nsteps} steps "
                       f"(M {ws['M']}, K {ws['K']}, dt {ws['dt']} ms), {dt:.1f} s wall"}
+
+
+def _kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hsdc_kernels.hip", "ttp06_device.h", "hsdc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2405_19994_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 counters
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the ratio the same counter gives
+    for a plain copy of known size), from profiles/hbm_traffic_slab2d.json; None
+    when absent or taken on kernel sources other than the current ones."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_slab2d.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_digest") != _kernel_sources_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def main():
@@ -97,6 +123,34 @@ def main():
     Vmax = float(ctx.get_state(0, 0, 0)[0].max())
     ctx.destroy()
 
+    # second pass, same workload and launch configuration, with every kernel
+    # bracketed by HIP events on the library's stream: per-class durations
+    prof_steps = min(a.steps, 100)
+    ctx = H.Context(prob, meth, None, stream)
+    ctx.profile(True)
+    ctx.advance(prof_steps)
+    torch.cuda.synchronize()
+    kp = ctx.profile_read()
+    pst = ctx.stats()
+    ctx.destroy()
+    kernels = {}
+    for k, v in kp.items():
+        b = v["bytes"]
+        if k == "cg_iter":
+            # iterations that did work: 80 B/node (r, w, s, p, x read and written);
+            # the first of a solve reads neither s nor p (64 B); early-exit launches move nothing
+            b = (pst["cg_iters"] - pst["cg_solves"]) * 80.0 * N + pst["cg_solves"] * 64.0 * N
+        kernels[k] = {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / v["launches"],
+                      "time_share": 0.0, "GBps": b / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else 0.0,
+                      "bytes_per_launch": b / v["launches"]}
+    tot_ms = sum(v["ms"] for v in kp.values())
+    for k, v in kp.items():
+        kernels[k]["time_share"] = v["ms"] / tot_ms
+    dom = max(kernels, key=lambda k: kernels[k]["time_share"])
+    traffic = _traffic(dom)
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["GBps"], "peak": 8000.0,
+                "unit": "GB/s", "frac": kernels[dom]["GBps"] / 8000.0, "traffic": traffic}
+
     updates = N * w["M"] * w["K"] * a.steps
     value = updates / wall
     out = {
@@ -120,7 +174,21 @@ def main():
         "cg_iters_per_solve": st["cg_iters"] / max(1, st["cg_solves"]),
         "cg_unconverged": st["cg_unconverged"],
         "V_max_end_mV": Vmax,
+        "roofline": roofline,
+        "kernels": kernels,
     }
+    if a.calibrate_copy:
+        # a plain copy of known size whose source is not cache resident: the
+        # 2 GiB written in between exceeds the 256 MB last-level cache
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        evict = torch.empty(4 * 64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        evict.fill_(2.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 8
+        del evict
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

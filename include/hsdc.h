@@ -147,6 +147,25 @@ hsdc_status hsdc_set_state(hsdc_ctx *ctx, int32_t level, int32_t slice, int32_t 
 int64_t hsdc_current_step(const hsdc_ctx *ctx);
 hsdc_status hsdc_get_stats(const hsdc_ctx *ctx, hsdc_stats *out);
 
+/* Kernel timing (diagnostics).  While enabled, every kernel the context
+ * launches is bracketed by HIP events on the context's stream; per kernel
+ * class the launch count, the summed event time and the algorithmic HBM bytes
+ * (the distinct bytes the launch must read and write, counted from the sizes)
+ * are accumulated.  Enabling adds a small per-launch overhead.  Classes:
+ * "node_update", "assemble", "cg_init", "cg_iter", "eval_stages", "spmv",
+ * "residual", "transfer", "copy". */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} hsdc_kernel_profile;
+hsdc_status hsdc_profile_enable(hsdc_ctx *ctx, int32_t on);
+/* Copies up to max class records to out (host), *count receives the number
+ * of classes with at least one launch; resets the accumulators. */
+hsdc_status hsdc_profile_read(hsdc_ctx *ctx, hsdc_kernel_profile *out, int32_t max,
+                              int32_t *count);
+
 void hsdc_destroy(hsdc_ctx *ctx);
 /* Message of the last failed call on ctx (or of the last failed context-free
  * call when ctx is NULL).  Never NULL. */

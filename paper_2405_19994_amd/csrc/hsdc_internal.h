@@ -13,7 +13,7 @@ constexpr int NF = HSDC_NFIELDS;
 constexpr int NG = HSDC_NGATES;
 constexpr int GATE0 = 7;  // first gate field
 constexpr int MAXM = HSDC_MAX_M;
-constexpr int BLOCK = 256;
+constexpr int BLOCK = 512;
 
 // Mesh and diffusion operator K = (chi Cm)^-1 A (cell-centred, no-flux).
 struct Grid {
@@ -80,14 +80,22 @@ hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const Stages &st, in
 hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                          const Stim &stim, int slice0, int nslices, int64_t step0,
                          bool copy_Y_from_stage0);
+// spread != 0: stages 1..M are the spread of stage 0 (y^0 = 1 (x) y_n) and are
+// read from stage 0 (the stimulus part of the V reaction term follows t_{n,j}).
 hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                           int slice0, int nslices, const double *RI, int64_t sRI);
+                           int slice0, int nslices, const double *RI, int64_t sRI, int spread,
+                           const Stim &stim, int64_t step0);
 // The node update also forms the CG start residual r_0 = b - x_0 + a K x_0 from
 // the cached K x_0 (x_0 = V^k_i) and writes the partials of ||b||^2, ||r_0||^2.
 struct CgBatch;
+// store_g = 0 skips storing the reaction term (last sweep of a step);
+// spread != 0 takes K x_0 from stage 0 (first sweep after a spread).
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int i, int64_t step0, const CgBatch &cb);
+                              int nslices, int i, int64_t step0, const CgBatch &cb, int store_g,
+                              int spread);
+hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
+                                   int nslices);
 int node_blocks(const Grid &g);
 hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *y_block0, double *part,

@@ -379,7 +379,8 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
 
 template <int M>
 __global__ void __launch_bounds__(BLOCK)
-k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t sRI) {
+k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t sRI, int spread,
+           Stim stim, int64_t step0) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= g.N) return;
   const int f = blockIdx.y;  // one field per block row: no divergence between field kinds
@@ -390,10 +391,28 @@ k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t s
   double *RH = st.RH + n * st.sRH() + f * Np + p;
   const double dt = co.dt;
   double Gv[M + 1], fv[M + 1], gfull[M], I[M];
+  if (spread) {
+    const double g0 = G[0];
+    const double f0 = (f == 0) ? FV[0] : 0.0;
+    const double s0 = (f == 0) ? stim_value(stim, ((double)(step0 + n)) * co.dt, p) : 0.0;
+    Gv[0] = g0;
+    fv[0] = 0.0;
 #pragma unroll
-  for (int j = 0; j <= M; ++j) Gv[j] = G[j * st.sS()];
+    for (int j = 1; j <= M; ++j) {
+      double gv = g0;
+      if (f == 0) {
+        const double sj = stim_value(stim, ((double)(step0 + n) + co.c[j - 1]) * co.dt, p);
+        if (sj != s0) gv += (sj - s0) / stim.Cm;
+      }
+      Gv[j] = gv;
+      fv[j] = f0;
+    }
+  } else {
 #pragma unroll
-  for (int j = 0; j <= M; ++j) fv[j] = (f == 0 && j > 0) ? FV[j * Np] : 0.0;
+    for (int j = 0; j <= M; ++j) Gv[j] = G[j * st.sS()];
+#pragma unroll
+    for (int j = 0; j <= M; ++j) fv[j] = (f == 0 && j > 0) ? FV[j * Np] : 0.0;
+  }
 #pragma unroll
   for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + fv[j + 1];
   const double z = (f >= GATE0) ? dt * st.L0[n * st.sL() + (f - GATE0) * Np + p] : 0.0;
@@ -413,10 +432,11 @@ k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t s
 }
 
 hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                           int slice0, int nslices, const double *RI, int64_t sRI) {
+                           int slice0, int nslices, const double *RI, int64_t sRI, int spread,
+                           const Stim &stim, int64_t step0) {
   dim3 grid(nblocks(g.N), NF, nslices);
   HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_assemble<M>), grid, dim3(BLOCK), 0, s, g, st, co,
-                                           slice0, RI, sRI));
+                                           slice0, RI, sRI, spread, stim, step0));
   return hipGetLastError();
 }
 
@@ -428,7 +448,7 @@ hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const
 
 __global__ void __launch_bounds__(BLOCK)
 k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int i, int64_t step0, CgBatch cb) {
+              int slice0, int i, int64_t step0, CgBatch cb, int store_g, int spread) {
   __shared__ double lds[BLOCK / 64];
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
@@ -462,16 +482,16 @@ k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, d
         const double lu = Lu[k * Np + p];
         const double w = yv[f];
         const double gv = (-1.0 / tau) * (w - inf) + lu * (u[f * Np + p] - w);
-        Gp[f * Np + p] = gv;
+        if (store_g) Gp[f * Np + p] = gv;
         Yi[f * Np + p] = w + RH[f * Np + p] + ddt * phi1(ddt * lu) * gv;
       });
       double I_ion, ha[6];
       ttp06::currents(yv, gs0, gs1, gs2, I_ion, ha);
       gV = (stim_value(stim, t, p) - stim.Cm * I_ion) / stim.Cm;
-      Gp[p] = gV;
+      if (store_g) Gp[p] = gV;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        Gp[(1 + k) * Np + p] = ha[k];
+        if (store_g) Gp[(1 + k) * Np + p] = ha[k];
         Yi[(1 + k) * Np + p] = yv[1 + k] + RH[(1 + k) * Np + p] + ddt * ha[k];
       }
     }
@@ -479,7 +499,7 @@ k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, d
     // the warm start x_0 = V^k_i, whose K x_0 is cached from the previous sweep
     const double bv = yv[0] + RH[p] + ddt * gV;
     const double x0 = Yi[p];
-    const double r0 = bv - x0 + cb.a * st.FV[n * st.sFV() + (int64_t)i * Np + p];
+    const double r0 = bv - x0 + cb.a * st.FV[n * st.sFV() + (int64_t)(spread ? 0 : i) * Np + p];
     cb.r[0][(int64_t)(n - slice0) * Np + p] = r0;
     bb = bv * bv;
     rr = r0 * r0;
@@ -497,10 +517,27 @@ int node_blocks(const Grid &g) { return (int)nblocks(g.N); }
 
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int i, int64_t step0, const CgBatch &cb) {
+                              int nslices, int i, int64_t step0, const CgBatch &cb, int store_g,
+                              int spread) {
   dim3 grid(nblocks(g.N), 1, nslices);
   hipLaunchKernelGGL(k_node_update, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
-                     slice0, i, step0, cb);
+                     slice0, i, step0, cb, store_g, spread);
+  return hipGetLastError();
+}
+
+// V of stage 0 to stages 1..M (the CG warm starts of the first sweep of a step).
+__global__ void __launch_bounds__(BLOCK) k_copy_V_to_stages(Grid g, Stages st, int slice0) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  double *Y = st.Y + (slice0 + blockIdx.z) * st.sY();
+  const double v = Y[p];
+  for (int j = 1; j <= st.M; ++j) Y[(int64_t)j * st.sS() + p] = v;
+}
+
+hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
+                                   int nslices) {
+  hipLaunchKernelGGL(k_copy_V_to_stages, dim3(nblocks(g.N), 1, nslices), dim3(BLOCK), 0, s, g, st,
+                     slice0);
   return hipGetLastError();
 }
 

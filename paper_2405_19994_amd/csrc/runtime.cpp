@@ -79,6 +79,27 @@ struct CgLogEntry {
 
 }  // namespace
 
+namespace {
+enum ProfClass { PC_NODE, PC_ASSEMBLE, PC_CGINIT, PC_CGITER, PC_EVAL, PC_SPMV, PC_RESIDUAL,
+                 PC_TRANSFER, PC_COPY, PC_COUNT };
+const char *kProfNames[PC_COUNT] = {"node_update", "assemble", "cg_init", "cg_iter", "eval_stages",
+                                    "spmv", "residual", "transfer", "copy"};
+struct ProfPending {
+  int cls;
+  int launches;
+  double bytes;
+  hipEvent_t e0, e1;
+};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<ProfPending> pending;
+  int64_t launches[PC_COUNT] = {};
+  double ms[PC_COUNT] = {};
+  double bytes[PC_COUNT] = {};
+};
+}  // namespace
+
 struct hsdc_ctx {
   hipStream_t s = nullptr;
   hsdc_problem prob{};
@@ -93,6 +114,9 @@ struct hsdc_ctx {
   bool pfasst = false;
   bool block_ready = false;
   bool ri_fresh = false;  // fine RI holds the restricted integrals of the current iterate
+  // serial mode: stages 1..M of the current step are the spread of stage 0 and
+  // only their V (the CG warm starts) is stored; the first sweep reads stage 0
+  bool spread_pending = false;
   hsdc_stats stats{};
   std::string err;
   std::vector<void *> allocs;
@@ -106,6 +130,7 @@ struct hsdc_ctx {
   int cg_log_cap = 0, cg_log_used = 0;
   int cg_fails = 0;  // unconverged budgeted solves found by flush_cg_log
   std::vector<CgLogEntry> cg_pending;
+  Profiler prof;
 };
 
 namespace {
@@ -117,6 +142,65 @@ hsdc_status fail(hsdc_ctx *c, hsdc_status st, const std::string &msg) {
     g_free_error = msg;
   return st;
 }
+
+// ---- kernel timing -----------------------------------------------------------
+void prof_harvest(hsdc_ctx *c) {
+  Profiler &P = c->prof;
+  if (P.pending.empty()) return;
+  HIPC(hipStreamSynchronize(c->s));
+  for (ProfPending &q : P.pending) {
+    float ms = 0.0f;
+    HIPC(hipEventElapsedTime(&ms, q.e0, q.e1));
+    P.launches[q.cls] += q.launches;
+    P.ms[q.cls] += ms;
+    P.bytes[q.cls] += q.bytes;
+    P.pool.push_back(q.e0);
+    P.pool.push_back(q.e1);
+  }
+  P.pending.clear();
+}
+
+hipEvent_t prof_event(hsdc_ctx *c) {
+  Profiler &P = c->prof;
+  if (P.pool.empty()) {
+    hipEvent_t e;
+    HIPC(hipEventCreate(&e));
+    return e;
+  }
+  hipEvent_t e = P.pool.back();
+  P.pool.pop_back();
+  return e;
+}
+
+// Brackets one launch with events when timing is enabled.
+struct ProfScope {
+  hsdc_ctx *c;
+  int cls;
+  double bytes;
+  hipEvent_t e0 = nullptr;
+  ProfScope(hsdc_ctx *c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
+    if (c->prof.on) {
+      if (c->prof.pending.size() >= 4096) prof_harvest(c);
+      e0 = prof_event(c);
+      HIPC(hipEventRecord(e0, c->s));
+    }
+  }
+  // nlaunch > 1: the bracket holds a run of back-to-back launches of one class
+  void end(int nlaunch = 1) {
+    if (!e0) return;
+    hipEvent_t e1 = prof_event(c);
+    HIPC(hipEventRecord(e1, c->s));
+    c->prof.pending.push_back(ProfPending{cls, nlaunch, bytes, e0, e1});
+    e0 = nullptr;
+  }
+};
+
+#define PLAUNCH(ctx, cls, bytes, call) \
+  do {                                 \
+    ProfScope ps_((ctx), (cls), (bytes)); \
+    HIPC(call);                        \
+    ps_.end();                         \
+  } while (0)
 
 template <class T>
 T *dalloc(hsdc_ctx *c, size_t n) {
@@ -334,14 +418,17 @@ void flush_cg_log(hsdc_ctx *c) {
 void cg_solve(hsdc_ctx *c, int lev, int s0, int ns, int i, int pred_row) {
   Level &L = c->L[lev];
   CgBatch cb = make_batch(c, L, s0, ns, i);
-  HIPC(launch_cg_init(c->s, L.g, cb));
+  const double nodes = (double)L.g.N * ns;
+  PLAUNCH(c, PC_CGINIT, 16.0 * nodes, launch_cg_init(c->s, L.g, cb));
   int &pred = L.cg_pred[pred_row & 15][i - 1];
   if (!c->safe_cg) {
     if (c->cg_log_used + ns > c->cg_log_cap) flush_cg_log(c);  // log full: verify now
     const int budget = std::max(1, std::min(pred, cb.maxit + 1));
     cb.log = c->cg_dlog + c->cg_log_used;
     cb.last_k = budget - 1;
+    ProfScope ps(c, PC_CGITER, 0.0);
     for (int k = 0; k < budget; ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+    ps.end(budget);
     c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget});
     c->cg_log_used += ns;
     return;
@@ -351,7 +438,10 @@ void cg_solve(hsdc_ctx *c, int lev, int s0, int ns, int i, int pred_row) {
   int k = 0;
   int batch = std::max(1, std::min(pred, cb.maxit + 1));
   for (;;) {
-    for (int q = 0; q < batch && k <= cb.maxit; ++q, ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+    ProfScope ps(c, PC_CGITER, 0.0);
+    int nl = 0;
+    for (int q = 0; q < batch && k <= cb.maxit; ++q, ++k, ++nl) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+    ps.end(nl);
     HIPC(hipMemcpyAsync(L.cg_sc_host + 2 * s0, L.cg_sc + 2 * s0, 2 * ns * sizeof(CgScalars),
                         hipMemcpyDeviceToHost, c->s));
     HIPC(hipStreamSynchronize(c->s));
@@ -379,7 +469,7 @@ void cg_solve(hsdc_ctx *c, int lev, int s0, int ns, int i, int pred_row) {
 //   Postcondition: same invariant for the new iterate.
 // ---------------------------------------------------------------------------
 void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const double *RI,
-           int pred_row) {
+           int pred_row, bool last_of_step = false) {
   Level &L = c->L[lev];
   const Colloc &co = L.co;
   const hsdc_problem &p = c->prob;
@@ -387,7 +477,13 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
   const int64_t N = L.g.N;
   const int64_t step0 = c->step;
   const int64_t sRI = (int64_t)M * NF * L.g.Np;
-  HIPC(launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI));
+  const int spread = (lev == 0 && c->spread_pending) ? 1 : 0;
+  {
+    const double per = spread ? (NF + 1 + NG + M * NF)
+                              : ((M + 1) * NF + M + NG + M * NF + (RI ? M * NF : 0));
+    PLAUNCH(c, PC_ASSEMBLE, 8.0 * per * N * ns,
+            launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI, spread, c->stim[lev], step0));
+  }
   Stages st = L.st;
   if (u_src) {
     HIPC(launch_copy_fields(c->s, L.g.Np, L.st.Y + s0 * L.st.sY(), L.st.sY(), u_src,
@@ -400,15 +496,23 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
   }
   for (int i = 1; i <= M; ++i) {
     const CgBatch cb = make_batch(c, L, s0, ns, i);
-    HIPC(launch_node_update(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                            p.g_scale[2], s0, ns, i, step0, cb));
+    const double per = (i == 1) ? 90.0 : (last_of_step ? 83.0 : 102.0);
+    PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
+            launch_node_update(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                               p.g_scale[2], s0, ns, i, step0, cb, last_of_step ? 0 : 1, spread));
     if (i > 1) c->stats.ionic_evals += N * ns;
     cg_solve(c, lev, s0, ns, i, pred_row);
   }
-  HIPC(launch_eval_stages(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                          p.g_scale[2], s0, ns, M, 1, step0, nullptr, st.Lu));
-  c->stats.ionic_evals += N * ns;
-  HIPC(launch_spmv_stages(c->s, L.g, L.st, s0, ns, 1, M));
+  if (lev == 0) c->spread_pending = false;
+  if (!last_of_step) {
+    // reaction terms and K V of the new iterate, for the next sweep or residual;
+    // the last sweep of a serial step skips them (the next step starts afresh)
+    PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns,
+            launch_eval_stages(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                               p.g_scale[2], s0, ns, M, 1, step0, nullptr, st.Lu));
+    c->stats.ionic_evals += N * ns;
+    PLAUNCH(c, PC_SPMV, 16.0 * M * N * ns, launch_spmv_stages(c->s, L.g, L.st, s0, ns, 1, M));
+  }
   if (u_src)
     HIPC(launch_copy_fields(c->s, L.g.Np, L.st.L0 + s0 * L.st.sL(), L.st.sL(),
                             L.st.Lu + s0 * L.st.sL(), L.st.sL(), NG, ns));
@@ -434,16 +538,29 @@ void evaluate_all(hsdc_ctx *c, int lev, int s0, int ns) {
 void begin_serial_step(hsdc_ctx *c) {
   Level &L = c->L[0];
   const hsdc_problem &p = c->prob;
-  HIPC(launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0], p.g_scale[1],
-                          p.g_scale[2], 0, 1, 0, 1, c->step, L.st.L0, nullptr));
-  HIPC(launch_spmv_stages(c->s, L.g, L.st, 0, 1, 0, 1));
-  HIPC(launch_spread(c->s, L.g, L.st, L.co, c->stim[0], 0, 1, c->step, true));
+  const double N = (double)L.g.N;
+  PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N,
+          launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0], p.g_scale[1],
+                             p.g_scale[2], 0, 1, 0, 1, c->step, L.st.L0, nullptr));
+  PLAUNCH(c, PC_SPMV, 16.0 * N, launch_spmv_stages(c->s, L.g, L.st, 0, 1, 0, 1));
+  PLAUNCH(c, PC_COPY, 8.0 * (1 + L.co.M) * N, launch_copy_V_to_stages(c->s, L.g, L.st, 0, 1));
+  c->spread_pending = true;
   c->stats.ionic_evals += L.g.N;
   c->sweeps_done = 0;
   c->sweep_index = 0;
 }
 
+// Store the spread of stage 0 in full (states, reaction terms, K V) when a
+// caller needs the stage vector itself before the first sweep of a step.
+void materialize(hsdc_ctx *c) {
+  if (!c->spread_pending) return;
+  Level &L = c->L[0];
+  HIPC(launch_spread(c->s, L.g, L.st, L.co, c->stim[0], 0, 1, c->step, true));
+  c->spread_pending = false;
+}
+
 hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
+  materialize(c);
   Level &L = c->L[0];
   const double *yb = c->pfasst ? c->y0blk : L.st.Y;  // serial: u = y_{n,0}
   const int Mc = c->nlev == 2 ? c->L[1].co.M : 0;
@@ -706,7 +823,8 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
         c->safe_cg = false;
         c->cg_fails = 0;
         while (c->sweeps_done < c->meth.max_iter) {
-          sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++);
+          const bool last = c->sweeps_done == c->meth.max_iter - 1;
+          sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
           c->sweeps_done += 1;
         }
         flush_cg_log(c);
@@ -716,7 +834,8 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
           c->cg_fails = 0;
           begin_serial_step(c);
           while (c->sweeps_done < c->meth.max_iter) {
-            sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++);
+            const bool last = c->sweeps_done == c->meth.max_iter - 1;
+            sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
             c->sweeps_done += 1;
           }
         }
@@ -770,6 +889,7 @@ static hsdc_status state_copy(hsdc_ctx *c, int32_t level, int32_t slice, int32_t
   if (node < 0 || node > L.co.M) return fail(c, HSDC_EINVAL, "node out of range");
   if (!dev) return fail(c, HSDC_EINVAL, "buffer is NULL");
   return run_guarded(c, [&]() -> hsdc_status {
+    if (node != 0 || !get) materialize(c);
     double *base = L.st.Y + slice * L.st.sY() + (int64_t)node * L.st.sS();
     for (int f = 0; f < NF; ++f) {
       if (get)
@@ -818,8 +938,48 @@ hsdc_status hsdc_get_stats(const hsdc_ctx *c, hsdc_stats *out) {
   return HSDC_OK;
 }
 
+hsdc_status hsdc_profile_enable(hsdc_ctx *c, int32_t on) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  return run_guarded(c, [&]() -> hsdc_status {
+    if (!on) prof_harvest(c);
+    c->prof.on = on != 0;
+    return HSDC_OK;
+  });
+}
+
+hsdc_status hsdc_profile_read(hsdc_ctx *c, hsdc_kernel_profile *out, int32_t max, int32_t *count) {
+  if (!c || (max > 0 && !out)) return fail(c, HSDC_EINVAL, "NULL argument");
+  return run_guarded(c, [&]() -> hsdc_status {
+    prof_harvest(c);
+    Profiler &P = c->prof;
+    int k = 0;
+    for (int q = 0; q < PC_COUNT; ++q) {
+      if (P.launches[q] == 0) continue;
+      if (k < max) {
+        hsdc_kernel_profile &o = out[k];
+        std::memset(&o, 0, sizeof(o));
+        std::strncpy(o.name, kProfNames[q], sizeof(o.name) - 1);
+        o.launches = P.launches[q];
+        o.total_ms = P.ms[q];
+        o.bytes = P.bytes[q];
+      }
+      ++k;
+      P.launches[q] = 0;
+      P.ms[q] = 0.0;
+      P.bytes[q] = 0.0;
+    }
+    if (count) *count = k;
+    return HSDC_OK;
+  });
+}
+
 void hsdc_destroy(hsdc_ctx *c) {
   if (!c) return;
+  try {
+    prof_harvest(c);
+  } catch (...) {
+  }
+  for (hipEvent_t e : c->prof.pool) hipEventDestroy(e);
   if (c->s) hipStreamSynchronize(c->s);
   else hipDeviceSynchronize();
   for (void *p : c->allocs) hipFree(p);

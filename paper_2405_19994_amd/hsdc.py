@@ -44,6 +44,11 @@ class Method(ctypes.Structure):
                 ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32)]
 
 
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("steps", "sweeps", "coarse_sweeps", "cg_solves",
                                               "cg_iters", "cg_unconverged", "pfasst_iters",
@@ -76,6 +81,8 @@ def lib():
             "hsdc_apply_diffusion": [ctypes.POINTER(Problem), vp, vp, vp],
             "hsdc_diffusion_solve": [ctypes.POINTER(Problem), dbl, vp, vp, dbl, i32, vp, vp],
             "hsdc_colloc_coefficients": [i32, i64, vp, vp, vp, vp],
+            "hsdc_profile_enable": [vp, i32],
+            "hsdc_profile_read": [vp, vp, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -220,6 +227,19 @@ class Context:
         s = Stats()
         _check(lib().hsdc_get_stats(self.handle, ctypes.byref(s)), self.handle)
         return {n: getattr(s, n) for n, _ in Stats._fields_}
+
+    def profile(self, on=True):
+        """Enable or disable per-kernel-class event timing."""
+        _check(lib().hsdc_profile_enable(self.handle, 1 if on else 0), self.handle)
+
+    def profile_read(self):
+        """{class: {"launches", "ms", "bytes"}} accumulated since the last read."""
+        arr = (KernelProfile * 16)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().hsdc_profile_read(self.handle, ctypes.cast(arr, ctypes.c_void_p), 16,
+                                       ctypes.byref(cnt)), self.handle)
+        return {arr[k].name.decode(): {"launches": arr[k].launches, "ms": arr[k].total_ms,
+                                       "bytes": arr[k].bytes} for k in range(min(cnt.value, 16))}
 
     @property
     def step(self):

@@ -172,6 +172,9 @@ def test_sweep_and_residual_parity():
     y0 = rest(po.N)
     ctx = H.Context(lib_problem(w), H.make_method(M=(6, 1), dt=w["dt"], max_iter=6, cg_rtol=1e-14),
                     dev(y0))
+    # the initial guess is the spread 1 (x) y_n (eq. prec_picard)
+    for j in range(7):
+        assert np.array_equal(host(ctx.get_state(0, 0, j)), y0)
     for K in (1, 2, 3):
         ctx.sdc_sweep(1)
         Y = serial_step(lev, 0, y0, K)
