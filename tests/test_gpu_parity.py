@@ -249,3 +249,59 @@ def test_pfasst_advance_blocks():
     g = host(ctx.get_state(0, 0, 0))
     assert ctx.step == 2 * P
     assert np.max(field_errors(g, y_ref)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# full size: the 512 x 512 slab in the benchmark's launch configuration
+# ---------------------------------------------------------------------------
+
+def test_slab2d_full_size_sweep_equation_at_sampled_nodes():
+    """At full size, after 30 steps (through the stimulus), two more sweeps of
+    the 31st step; the oracle evaluates eq. prec_picard at 3000 sampled nodes
+    (plus corners and stimulus edges) from the library's whole stage vectors.
+    Bound on V: the node-to-node form accumulates the CG residuals of nodes
+    1..i, so |defect_i| <= i * cg_rtol * max ||b||_2; other fields: rounding."""
+    from oracle.sampled import sweep_defect
+    w = si.workload("slab2d")
+    po = oracle_problem(w)
+    N = po.N
+    ctx = H.Context(lib_problem(w), H.make_method(M=(6, 1), dt=w["dt"], max_iter=6,
+                                                  cg_rtol=w["cg_rtol"], cg_maxit=500))
+    ctx.advance(30)
+    ctx.sdc_sweep(1)
+    Yk = np.stack([host(ctx.get_state(0, 0, j)) for j in range(7)])
+    ctx.sdc_sweep(1)
+    Yn = np.stack([host(ctx.get_state(0, 0, j)) for j in range(7)])
+    assert ctx.stats()["cg_unconverged"] == 0
+    ctx.destroy()
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([rng.choice(N, 3000, replace=False),
+                                     [0, 511, N - 512, N - 1, 15, 16, 15 * 512, 16 * 512 + 16]]))
+    D = sweep_defect(po, 6, w["dt"], 30, Yk, Yn, Yk[0], rows)
+    bnorm = np.sqrt(np.sum(Yn[:, 0] ** 2, axis=1)).max()
+    for i in range(7):
+        assert np.max(np.abs(D[i, 0])) <= 2 * max(i, 1) * w["cg_rtol"] * bnorm, (i, np.max(np.abs(D[i, 0])))
+    scale = np.max(np.abs(Yn[:, 1:, rows]), axis=(0, 2))
+    assert np.max(np.max(np.abs(D[:, 1:]), axis=(0, 2)) / scale) < 1e-12
+    # the stimulated corner has fired and the wave is moving through the slab
+    assert Yn[-1, 0].max() > 0.0 and Yn[-1, 0].min() < -80.0
+
+
+def test_slab2d_full_size_uniform_state_is_a_single_cell():
+    """Property at any size: without stimulus a uniform state stays uniform (the
+    no-flux Laplacian of a constant is exactly 0) and equals the single-cell run."""
+    w = dict(si.workload("slab2d"))
+    w["stim_amp"] = 0.0
+    N = 512 * 512
+    y1 = ttp06.rest_state()
+    y1[0] = -55.0  # above threshold: an action potential starts everywhere
+    ctx = H.Context(lib_problem(w), H.make_method(M=(6, 1), dt=w["dt"], max_iter=6,
+                                                  cg_rtol=w["cg_rtol"], cg_maxit=500),
+                    dev(np.repeat(y1[:, None], N, axis=1)))
+    ctx.advance(20)
+    g = host(ctx.get_state(0, 0, 0))
+    ctx.destroy()
+    assert np.all(g == g[:, :1])
+    cell = oracle_problem(dict(w, dims=(1,), stim_w=np.zeros(1)))
+    ref = run_serial(Level(cell, 6, w["dt"]), y1[:, None], 20, 6)
+    assert np.max(field_errors(g[:, :1], ref)) < 1e-10

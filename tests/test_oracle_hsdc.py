@@ -287,3 +287,24 @@ def test_run_pfasst_blocks_chain():
         Y, _ = collocation_solve(h.levels[0], n, y, tol=1e-14)
         y = Y[-1]
     assert np.max(np.abs(y2 - y)) < 1e-11 * np.max(np.abs(y))
+
+
+def test_sampled_sweep_defect_vanishes_on_oracle_sweeps():
+    """oracle.sampled evaluates eq. prec_picard at chosen nodes: zero (to
+    rounding) on the oracle's own sweeps, and it sees a planted error."""
+    import synthetic_inputs as si
+    from oracle.sampled import sweep_defect
+    w = si.workload("slab2d", dims=(20, 16))
+    po = Monodomain(w["dims"], w["dx"], w["sigma"], None, w["chi"], w["Cm"], w["stim_w"],
+                    w["stim_amp"], w["stim_t0"], w["stim_dur"], dt_ref=w["dt"])
+    lev = Level(po, 6, w["dt"])
+    y0 = np.repeat(ttp06.rest_state()[:, None], po.N, axis=1)
+    Y1 = lev.sweep(0, lev.spread(y0), lev.spread(y0))
+    Y2 = lev.sweep(0, Y1, lev.spread(y0))
+    rows = np.array([0, 5, 17, 100, 319])
+    D = sweep_defect(po, 6, w["dt"], 0, Y1, Y2, y0, rows)
+    scale = np.max(np.abs(Y2[:, :, rows]), axis=(0, 2))
+    assert np.max(np.max(np.abs(D), axis=(0, 2)) / scale) < 1e-13
+    Y2[3, 9, 17] += 1e-6
+    D = sweep_defect(po, 6, w["dt"], 0, Y1, Y2, y0, rows)
+    assert np.abs(D[3, 9, 2]) > 5e-7
