@@ -107,7 +107,7 @@ bool make_colloc(int M, double dt, Colloc &co) {
   for (int k = 0; k < M; ++k)
     for (int j = 0; j < M; ++j) co.W[k][j] = (double)delta[k][j];
   co.invfact[0] = 1.0;
-  for (int k = 1; k < MAXM + 2; ++k) co.invfact[k] = co.invfact[k - 1] / (double)k;
+  for (int k = 1; k < MAXM + 10; ++k) co.invfact[k] = co.invfact[k - 1] / (double)k;
   for (int i = 0; i < M; ++i) {
     co.cpow[i][0] = 1.0;
     for (int k = 1; k <= M; ++k) co.cpow[i][k] = co.cpow[i][k - 1] * co.c[i];

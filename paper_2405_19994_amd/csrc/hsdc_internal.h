@@ -33,7 +33,7 @@ struct Colloc {
   double W[MAXM][MAXM];     // W[k][j] = l_j^{(k)}(0)
   double Q[MAXM][MAXM];     // a_ij(0)
   double cpow[MAXM][MAXM + 1];  // c_i^k
-  double invfact[MAXM + 2];     // 1/k!
+  double invfact[MAXM + 10];    // 1/k!, k = 0..MAXM+9
 };
 
 // Strided view of a set of stage vectors on one level.
@@ -123,7 +123,7 @@ struct CgBatch {
   double a, tol2;
   int maxit;
 };
-int cg_blocks(const Grid &g);
+int cg_blocks(const Grid &g, int cap = 512);
 hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb);
 hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatch &cb);
 hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k);

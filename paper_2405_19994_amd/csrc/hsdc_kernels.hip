@@ -27,8 +27,23 @@ __constant__ double kRecip[80] = {
     1.0 / 64, 1.0 / 65, 1.0 / 66, 1.0 / 67, 1.0 / 68, 1.0 / 69, 1.0 / 70, 1.0 / 71, 1.0 / 72,
     1.0 / 73, 1.0 / 74, 1.0 / 75, 1.0 / 76, 1.0 / 77, 1.0 / 78, 1.0 / 79};
 
-// phi_1(x) = (e^x - 1)/x, phi_1(0) = 1.
-__device__ __forceinline__ double phi1(double x) { return x == 0.0 ? 1.0 : expm1(x) / x; }
+// phi_1(x) = (e^x - 1)/x.  For |x| < 1/8 the Taylor series sum_{m<=9} x^m/(m+1)!
+// (truncation below 2e-17 relative) replaces expm1 and the division.
+__device__ __forceinline__ double phi1(double x) {
+  if (fabs(x) < 0.125) {
+    double t = 1.0 / 3628800.0;  // 1/10!
+    t = fma(t, x, 1.0 / 362880.0);
+    t = fma(t, x, 1.0 / 40320.0);
+    t = fma(t, x, 1.0 / 5040.0);
+    t = fma(t, x, 1.0 / 720.0);
+    t = fma(t, x, 1.0 / 120.0);
+    t = fma(t, x, 1.0 / 24.0);
+    t = fma(t, x, 1.0 / 6.0);
+    t = fma(t, x, 0.5);
+    return fma(t, x, 1.0);
+  }
+  return expm1(x) / x;
+}
 
 // phi_1(x) .. phi_M(x) into out[0..M-1].  The forward recurrence
 // phi_{k+1} = (phi_k - 1/k!)/x from phi_1 = expm1(x)/x damps errors while k <= |x|
@@ -52,11 +67,20 @@ __device__ __forceinline__ void phis(double x, const double *invfact, double *ou
     }
   }
   if (kf < M) {
-    double term = invfact[M], acc = term;
-    for (int m = 1; m < 64; ++m) {
-      term *= x * kRecip[m + M];
-      acc += term;
-      if (fabs(term) <= 1e-17 * fabs(acc)) break;
+    double acc;
+    if (ax < 0.125) {
+      // phi_M(x) = sum_m x^m/(m+M)!, m <= 9 (truncation below 2e-17 relative)
+      acc = invfact[M + 9];
+#pragma unroll
+      for (int m = 8; m >= 0; --m) acc = fma(acc, x, invfact[M + m]);
+    } else {
+      double term = invfact[M];
+      acc = term;
+      for (int m = 1; m < 64; ++m) {
+        term *= x * kRecip[m + M];
+        acc += term;
+        if (fabs(term) <= 1e-17 * fabs(acc)) break;
+      }
     }
     out[M - 1] = acc;
 #pragma unroll
@@ -657,9 +681,12 @@ hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sd
 // Partials per slice: [gamma par0 | delta par0 | gamma par1 | delta par1 | bb].
 // ---------------------------------------------------------------------------
 
-int cg_blocks(const Grid &g) {
+// Blocks of the CG kernels: at most cap (<= 2 BLOCK partials per reduction);
+// nodes beyond cap * BLOCK are handled by a grid-stride loop.
+int cg_blocks(const Grid &g, int cap) {
   const int64_t nb = ((int64_t)g.N + BLOCK - 1) / BLOCK;
-  return (int)(nb < 512 ? nb : 512);
+  cap = cap < 1 ? 1 : (cap > 2 * BLOCK ? 2 * BLOCK : cap);
+  return (int)(nb < cap ? nb : cap);
 }
 
 // Start residual r_0 = b - A x_0 with the partials of ||r_0||^2 and ||b||^2
@@ -1099,9 +1126,9 @@ template <int K>
 __global__ void __launch_bounds__(BLOCK) k_phi_test(int64_t n, const double *x, double *out) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= n) return;
-  double invf[MAXM + 2];
+  double invf[MAXM + 10];
   invf[0] = 1.0;
-  for (int k = 1; k < MAXM + 2; ++k) invf[k] = invf[k - 1] / (double)k;
+  for (int k = 1; k < MAXM + 10; ++k) invf[k] = invf[k - 1] / (double)k;
   double ph[K];
   phis<K>(x[p], invf, ph);
 #pragma unroll

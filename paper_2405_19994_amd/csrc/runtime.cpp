@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -131,6 +132,9 @@ struct hsdc_ctx {
   int cg_fails = 0;  // unconverged budgeted solves found by flush_cg_log
   std::vector<CgLogEntry> cg_pending;
   Profiler prof;
+  // launch tuning (environment: HSDC_CG_BLOCKS, HSDC_CG_MARGIN)
+  int tune_cg_blocks = 512;
+  int tune_cg_margin = 2;
 };
 
 namespace {
@@ -320,7 +324,7 @@ void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc
   L.st.L0 = dalloc<double>(c, (size_t)P * L.st.sL());
   L.st.Lu = dalloc<double>(c, (size_t)P * L.st.sL());
   L.st.B = dalloc<double>(c, (size_t)P * Np);
-  L.cg_nblk = cg_blocks(L.g);
+  L.cg_nblk = cg_blocks(L.g, c->tune_cg_blocks);
   for (int k = 0; k < 2; ++k) {
     L.cg_r[k] = dalloc<double>(c, (size_t)P * Np);
     L.cg_w[k] = dalloc<double>(c, (size_t)P * Np);
@@ -406,7 +410,7 @@ void flush_cg_log(hsdc_ctx *c) {
     // after a miss (a spare no-op iteration costs far less than a recomputed step)
     int &pred = L.cg_pred[e.row & 15][e.i - 1];
     if (ok_all)
-      pred = std::max(used + 2, pred - 1);
+      pred = std::max(used + c->tune_cg_margin, pred - 1);
     else
       pred = std::min(c->meth.cg_maxit + 1, std::max(2 * e.budget, used + 4));
   }
@@ -714,6 +718,8 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
   if (meth->levels == 1 && meth->P > 1)
     return fail(nullptr, HSDC_EINVAL, "P > 1 needs levels = 2");
   hsdc_ctx *c = new hsdc_ctx();
+  if (const char *e = std::getenv("HSDC_CG_BLOCKS")) c->tune_cg_blocks = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("HSDC_CG_MARGIN")) c->tune_cg_margin = std::max(1, std::atoi(e));
   c->s = (hipStream_t)hip_stream;
   c->prob = *prob;
   c->meth = *meth;
