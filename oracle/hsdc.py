@@ -6,10 +6,14 @@ Y[0] = y_{n,0}, ..., Y[M] = y_{n,M}, at times t_{n,j} = (n + c_j) dt.
 Readings of the paper used here (the full list is in the design notes):
 * Lambda_n = Lambda(y_{n,0}) (text after eq. def_A_matrix: y_n is replaced by
   y_{n,0} in g and in A(dt Lambda)).
-* In the preconditioned Picard iteration (eq. prec_picard) both P and C on the
-  right-hand side are evaluated wholly at y^k, including y^k_{n,0} and
-  Lambda(y^k_{n,0}); P on the left uses the new y^{k+1}_{n,0}.  For a single
-  step y_{n,0} never changes and the two coincide.
+* In the preconditioned Picard iteration (eq. prec_picard) the right-hand side
+  (P - C)(y^k) is evaluated at y^k with its start value replaced by the start
+  value u of the new iterate (row 0 of the sweep gives y^{k+1}_{n,0} = u), so
+  that P, C, Lambda_n and g_n of both sides belong to the same step, as in
+  Sec. 3.1.3 where y^k_{n,0} = y_n for every k.  For a single step nothing is
+  replaced; in PFASST the start values move between iterations, and evaluating
+  the right-hand side at the old start value makes the two-level iteration
+  unstable in the stiff regime that Sec. 4.1 reports stable (L = 2, P = 4, K = 2).
 * f_E(y_{n,j-1}) in P is taken at time t_{n,j-1}; g(y_{n,j}) at t_{n,j}.
 * f_I(y_{n,j}) inside P is evaluated by applying the operator to the stage
   (never recovered from the implicit solve's right-hand side).
@@ -127,9 +131,13 @@ class Level:
     def sweep(self, step, Yk, shift):
         """One preconditioned Picard iteration (eq. prec_picard):
         P(Y^{k+1}) = (P - C)(Y^k) + shift, where shift is 1 (x) y_n for a single
-        step, or the block right-hand side b_n + tau_n + H y_{n-1} of PFASST."""
-        coef = self.coefficients(Yk[0])
-        rhs = self.P(step, Yk, coef) - self.C(step, Yk, coef) + shift
+        step, or the block right-hand side b_n + tau_n + H y_{n-1} of PFASST.
+        Row 0 of shift is the start value u of the new iterate; Y^k enters with
+        its start value replaced by u (reading in the module doc)."""
+        Y = np.array(Yk, float, copy=True)
+        Y[0] = shift[0]
+        coef = self.coefficients(Y[0])
+        rhs = self.P(step, Y, coef) - self.C(step, Y, coef) + shift
         return self.solve_P(step, rhs)
 
     def residual(self, step, Y, u):

@@ -46,14 +46,17 @@ class FrozenDiffusion:
 
 
 def sweep_defect(full, M, dt, step, Yk, Ynew, yn, rows):
-    """P(Y^{k+1}) - [(P - C)(Y^k) + 1 (x) y_n] at the nodes `rows` (eq. prec_picard),
-    for whole stage vectors Yk, Ynew of shape (M+1, nf, N).  Returns (M+1, nf, len(rows))."""
+    """P(Y^{k+1}) - [(P - C)(Y^k) + 1 (x) y_n] at the nodes `rows` (eq. prec_picard,
+    Y^k with its start value replaced by y_n as in Level.sweep), for whole stage
+    vectors Yk, Ynew of shape (M+1, nf, N).  Returns (M+1, nf, len(rows))."""
     times = [(step + c) * dt for c in np.concatenate([[0.0], Level(full, M, dt).c])]
 
     def level_for(Y):
         kv = [full.K[rows] @ Y[j, 0] for j in range(M + 1)]
         return Level(FrozenDiffusion(full, rows, kv, times), M, dt)
 
+    Yk = np.array(Yk, float, copy=True)
+    Yk[0] = yn                      # the right-hand side takes the new start value
     lev_new, lev_old = level_for(Ynew), level_for(Yk)
     Yn = Ynew[:, :, rows]
     Yo = Yk[:, :, rows]
