@@ -42,8 +42,7 @@ struct Stages {
   double *G;    // [P][M+1][NF][Np]  reaction part of g at each stage
   double *FV;   // [P][M+1][Np]      K V at each stage
   double *RH;   // [P][M][NF][Np]    assembled right-hand-side differences
-  double *L0;   // [P][NG][Np]       Lambda of the anchor of the current iterate
-  double *Lu;   // [P][NG][Np]       Lambda of the new anchor u
+  double *L0;   // [P][NG][Np]       Lambda(y_{n,0}) of the current iterate
   double *B;    // [P][Np]           diffusion right-hand side
   int64_t Np;
   int M;
@@ -85,10 +84,13 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
 hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *RI, int64_t sRI, int spread,
                            const Stim &stim, int64_t step0);
+// RI[n][i][f] -= (A G)_i of the stage vector held by st (coarse FAS term of tau).
+hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                                int slice0, int nslices, double *RI, int64_t sRI);
 // The node update also forms the CG start residual r_0 = b - x_0 + a K x_0 from
 // the cached K x_0 (x_0 = V^k_i) and writes the partials of ||b||^2, ||r_0||^2.
 struct CgBatch;
-// store_g = 0 skips storing the reaction term (last sweep of a step);
+// store_g = 0 skips storing the reaction term (its caller discards it);
 // spread != 0 takes K x_0 from stage 0 (first sweep after a spread).
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,

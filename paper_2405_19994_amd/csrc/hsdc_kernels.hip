@@ -397,8 +397,9 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
 
 // ---------------------------------------------------------------------------
 // sweep right-hand side: RH_i = R_i - R_{i-1} of eq. prec_picard in node-to-node
-// form,  dt (I_i - I_{i-1}) - dt d_i Phi_i(y^k) (+ FAS: I replaced by the
-// restricted fine integrals RI).
+// form,  dt (I_i - I_{i-1}) - dt d_i Phi_i(y^k), where I are the collocation
+// integrals of the iterate; on the coarse level of PFASST the FAS term of tau
+// (per unit dt, from k_fas_integrals) is added to them.
 // ---------------------------------------------------------------------------
 
 template <int M>
@@ -440,11 +441,10 @@ k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t s
 #pragma unroll
   for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + fv[j + 1];
   const double z = (f >= GATE0) ? dt * st.L0[n * st.sL() + (f - GATE0) * Np + p] : 0.0;
+  colloc_integrals<M>(co, z, gfull, I);
   if (RI) {
 #pragma unroll
-    for (int i = 0; i < M; ++i) I[i] = RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
-  } else {
-    colloc_integrals<M>(co, z, gfull, I);
+    for (int i = 0; i < M; ++i) I[i] += RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
   }
   double prevI = 0.0;
 #pragma unroll
@@ -461,6 +461,40 @@ hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const
   dim3 grid(nblocks(g.N), NF, nslices);
   HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_assemble<M>), grid, dim3(BLOCK), 0, s, g, st, co,
                                            slice0, RI, sRI, spread, stim, step0));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FAS term of tau (Algorithm 1) on the coarse level, per unit dt: rows i >= 1 of
+// tau = D_c(S z) - S D_f(z) are dt (S (A G)_f(z) - (A G)_c(S z))_i; the first
+// part arrives in RI (fine integrals restricted in time and space), the second
+// is computed here from the reaction terms, K V and Lambda of S z.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(BLOCK)
+k_fas_integrals(Grid g, Stages st, Colloc co, int slice0, double *RI, int64_t sRI) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int f = blockIdx.y;
+  const int n = slice0 + blockIdx.z;
+  const int64_t Np = st.Np;
+  const double *G = st.G + n * st.sY() + f * Np + p;
+  const double *FV = st.FV + n * st.sFV() + p;
+  double gfull[M], I[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) gfull[j] = G[(j + 1) * st.sS()] + (f == 0 ? FV[(j + 1) * Np] : 0.0);
+  const double z = (f >= GATE0) ? co.dt * st.L0[n * st.sL() + (f - GATE0) * Np + p] : 0.0;
+  colloc_integrals<M>(co, z, gfull, I);
+  double *R = RI + n * sRI + (int64_t)f * Np + p;
+#pragma unroll
+  for (int i = 0; i < M; ++i) R[(int64_t)i * NF * Np] -= I[i];
+}
+
+hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                                int slice0, int nslices, double *RI, int64_t sRI) {
+  dim3 grid(nblocks(g.N), NF, nslices);
+  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_fas_integrals<M>), grid, dim3(BLOCK), 0, s, g, st,
+                                           co, slice0, RI, sRI));
   return hipGetLastError();
 }
 
@@ -484,7 +518,7 @@ k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, d
     double *Yi = st.Y + n * st.sY() + (int64_t)i * st.sS();
     const double *u = st.Y + n * st.sY();
     const double *RH = st.RH + n * st.sRH() + (int64_t)(i - 1) * st.sS();
-    const double *Lu = st.Lu + n * st.sL();
+    const double *Lu = st.L0 + n * st.sL();  // Lambda of the anchor u
     double *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
     double yv[NF];
 #pragma unroll

@@ -322,7 +322,6 @@ void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc
   L.st.FV = dalloc<double>(c, (size_t)P * L.st.sFV());
   L.st.RH = dalloc<double>(c, (size_t)P * L.st.sRH());
   L.st.L0 = dalloc<double>(c, (size_t)P * L.st.sL());
-  L.st.Lu = dalloc<double>(c, (size_t)P * L.st.sL());
   L.st.B = dalloc<double>(c, (size_t)P * Np);
   L.cg_nblk = cg_blocks(L.g, c->tune_cg_blocks);
   for (int k = 0; k < 2; ++k) {
@@ -465,15 +464,37 @@ void cg_solve(hsdc_ctx *c, int lev, int s0, int ns, int i, int pred_row) {
   pred = std::max(used + 2, pred - 1);
 }
 
+// Reaction terms, Lambda(y_{n,0}) and K V of every stage of slices [s0, s0+ns).
+void evaluate_all(hsdc_ctx *c, int lev, int s0, int ns) {
+  Level &L = c->L[lev];
+  const hsdc_problem &p = c->prob;
+  const int M = L.co.M;
+  const double N = (double)L.g.N;
+  PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N * ns,
+          launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                             p.g_scale[2], s0, ns, 0, 1, c->step, L.st.L0, nullptr));
+  PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns * M,
+          launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                             p.g_scale[2], s0, ns, 1, M, c->step, nullptr, L.st.L0));
+  PLAUNCH(c, PC_SPMV, 16.0 * (M + 1) * N * ns,
+          launch_spmv_stages(c->s, L.g, L.st, s0, ns, 0, M + 1));
+  c->stats.ionic_evals += L.g.N * ns * (M + 1);
+}
+
 // ---------------------------------------------------------------------------
 // one sweep on slices [s0, s0+ns) of level L.
-//   Precondition: G, FV and L0 hold the reaction terms, K V and Lambda(anchor)
-//   of the current iterate.  u_src: new start values [ns][NF][Np] (NULL keeps
-//   y_{n,0}); RI: FAS integrals (coarse level of PFASST) or NULL.
-//   Postcondition: same invariant for the new iterate.
+//   u_src: new start values [ns][NF][Np], or NULL to keep y_{n,0}.  With
+//   u_src the start values are stored into stage 0 first and the reaction
+//   terms, Lambda(y_{n,0}) and K V of every stage are evaluated afresh, so the
+//   right-hand side (P - C)(y^k) is taken at the new start value.  Without it:
+//   precondition G, FV and L0 hold those terms of the current iterate.
+//   RI: FAS term of tau per unit dt (coarse level of PFASST), or NULL.
+//   drop_terms: the caller discards the new iterate's reaction terms and K V
+//   (last sweep of a serial step, every coarse and burn-in sweep); otherwise
+//   the postcondition is the precondition for the new iterate.
 // ---------------------------------------------------------------------------
 void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const double *RI,
-           int pred_row, bool last_of_step = false) {
+           int pred_row, bool drop_terms = false) {
   Level &L = c->L[lev];
   const Colloc &co = L.co;
   const hsdc_problem &p = c->prob;
@@ -482,60 +503,40 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
   const int64_t step0 = c->step;
   const int64_t sRI = (int64_t)M * NF * L.g.Np;
   const int spread = (lev == 0 && c->spread_pending) ? 1 : 0;
+  if (u_src) {
+    HIPC(launch_copy_fields(c->s, L.g.Np, L.st.Y + s0 * L.st.sY(), L.st.sY(), u_src,
+                            (int64_t)NF * L.g.Np, NF, ns));
+    evaluate_all(c, lev, s0, ns);
+  }
   {
     const double per = spread ? (NF + 1 + NG + M * NF)
                               : ((M + 1) * NF + M + NG + M * NF + (RI ? M * NF : 0));
     PLAUNCH(c, PC_ASSEMBLE, 8.0 * per * N * ns,
             launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI, spread, c->stim[lev], step0));
   }
-  Stages st = L.st;
-  if (u_src) {
-    HIPC(launch_copy_fields(c->s, L.g.Np, L.st.Y + s0 * L.st.sY(), L.st.sY(), u_src,
-                            (int64_t)NF * L.g.Np, NF, ns));
-    HIPC(launch_eval_stages(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                            p.g_scale[2], s0, ns, 0, 1, step0, L.st.Lu, nullptr));
-    c->stats.ionic_evals += N * ns;
-  } else {
-    st.Lu = L.st.L0;  // the anchor is unchanged
-  }
   for (int i = 1; i <= M; ++i) {
     const CgBatch cb = make_batch(c, L, s0, ns, i);
-    const double per = (i == 1) ? 90.0 : (last_of_step ? 83.0 : 102.0);
+    const double per = (i == 1) ? 90.0 : (drop_terms ? 83.0 : 102.0);
     PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
-            launch_node_update(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                               p.g_scale[2], s0, ns, i, step0, cb, last_of_step ? 0 : 1, spread));
+            launch_node_update(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                               p.g_scale[2], s0, ns, i, step0, cb, drop_terms ? 0 : 1, spread));
     if (i > 1) c->stats.ionic_evals += N * ns;
     cg_solve(c, lev, s0, ns, i, pred_row);
   }
   if (lev == 0) c->spread_pending = false;
-  if (!last_of_step) {
-    // reaction terms and K V of the new iterate, for the next sweep or residual;
-    // the last sweep of a serial step skips them (the next step starts afresh)
+  if (!drop_terms) {
+    // reaction terms and K V of the new iterate's last stage, for the next
+    // sweep or the residual (stages 1..M-1 were stored by the node updates)
     PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns,
-            launch_eval_stages(c->s, L.g, st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                               p.g_scale[2], s0, ns, M, 1, step0, nullptr, st.Lu));
+            launch_eval_stages(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+                               p.g_scale[2], s0, ns, M, 1, step0, nullptr, L.st.L0));
     c->stats.ionic_evals += N * ns;
     PLAUNCH(c, PC_SPMV, 16.0 * M * N * ns, launch_spmv_stages(c->s, L.g, L.st, s0, ns, 1, M));
   }
-  if (u_src)
-    HIPC(launch_copy_fields(c->s, L.g.Np, L.st.L0 + s0 * L.st.sL(), L.st.sL(),
-                            L.st.Lu + s0 * L.st.sL(), L.st.sL(), NG, ns));
   if (lev == 0)
     c->stats.sweeps += ns;
   else
     c->stats.coarse_sweeps += ns;
-}
-
-// Reaction terms, K V and Lambda(anchor) of every stage of slices [s0, s0+ns).
-void evaluate_all(hsdc_ctx *c, int lev, int s0, int ns) {
-  Level &L = c->L[lev];
-  const hsdc_problem &p = c->prob;
-  HIPC(launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                          p.g_scale[2], s0, ns, 0, 1, c->step, L.st.L0, nullptr));
-  HIPC(launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                          p.g_scale[2], s0, ns, 1, L.co.M, c->step, nullptr, L.st.L0));
-  HIPC(launch_spmv_stages(c->s, L.g, L.st, s0, ns, 0, L.co.M + 1));
-  c->stats.ionic_evals += L.g.N * ns * (L.co.M + 1);
 }
 
 // Serial step start: y^0 = 1 (x) y_n from Y[0][0].
@@ -617,14 +618,15 @@ void gather_starts(hsdc_ctx *c, int lev, int s0, int ns) {
                             s0 + ns - n));
 }
 
+// Staggered coarse predictor: at stage s every slice n >= s takes one coarse
+// sweep (tau = 0) from the end value slice n-1 held after stage s-1.
 void burn_in(hsdc_ctx *c) {
   Level &Cc = c->L[1];
   const int P = Cc.P;
   restrict_fine_to_coarse(c);
-  evaluate_all(c, 1, 0, P);
   for (int s = 0; s < P; ++s) {
     gather_starts(c, 1, s, P - s);
-    sweep(c, 1, s, P - s, Cc.U + s * Cc.st.sS(), nullptr, 15);
+    sweep(c, 1, s, P - s, Cc.U + s * Cc.st.sS(), nullptr, 15, true);
   }
   coarse_correct_fine(c);
 }
@@ -653,23 +655,24 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
   if (c->nlev == 2) {
     Level &Cc = c->L[1];
     const int Mc = Cc.co.M;
-    // tau: the coarse sweep uses the restricted fine integrals S (A G)(z) in place
-    // of its own collocation integrals (eq. def_D and the tau of Algorithm 1)
+    // tau (Algorithm 1): its rows i >= 1 are dt (S (A G)_f(z) - (A G)_c(S z))_i,
+    // the row-0 and H parts cancel; the fine integrals come with the residual
     if (!c->ri_fresh) {
       hsdc_status st = residual_pass(c, nullptr, true);
       if (st != HSDC_OK) return st;
     }
+    const int64_t sRIc = (int64_t)Mc * NF * Cc.g.Np;
     HIPC(launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
-                                (int64_t)Mc * NF * F.g.Np, Cc.RI, (int64_t)Mc * NF * Cc.g.Np,
-                                Mc * NF, P));
+                                (int64_t)Mc * NF * F.g.Np, Cc.RI, sRIc, Mc * NF, P));
     restrict_fine_to_coarse(c);
     evaluate_all(c, 1, 0, P);
+    PLAUNCH(c, PC_ASSEMBLE, 8.0 * ((Mc + 1) * NF + NG + 2 * Mc * NF) * Cc.g.N * P,
+            launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, 0, P, Cc.RI, sRIc));
     for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
       gather_starts(c, 1, n, 1);
-      sweep(c, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14);
+      sweep(c, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14, true);
     }
     coarse_correct_fine(c);
-    evaluate_all(c, 0, 0, P);
   }
   // Q^par on the fine level: start values from the (corrected) iterate
   gather_starts(c, 0, 0, P);
