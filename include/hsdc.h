@@ -153,7 +153,7 @@ hsdc_status hsdc_get_stats(const hsdc_ctx *ctx, hsdc_stats *out);
  * (the distinct bytes the launch must read and write, counted from the sizes)
  * are accumulated.  Enabling adds a small per-launch overhead.  Classes:
  * "node_update", "assemble", "cg_init", "cg_iter", "eval_stages", "spmv",
- * "residual", "transfer", "copy". */
+ * "residual", "transfer", "copy", "fas_integrals" (at most 16). */
 typedef struct {
   char name[32];
   int64_t launches;

@@ -82,9 +82,9 @@ struct CgLogEntry {
 
 namespace {
 enum ProfClass { PC_NODE, PC_ASSEMBLE, PC_CGINIT, PC_CGITER, PC_EVAL, PC_SPMV, PC_RESIDUAL,
-                 PC_TRANSFER, PC_COPY, PC_COUNT };
+                 PC_TRANSFER, PC_COPY, PC_FAS, PC_COUNT };
 const char *kProfNames[PC_COUNT] = {"node_update", "assemble", "cg_init", "cg_iter", "eval_stages",
-                                    "spmv", "residual", "transfer", "copy"};
+                                    "spmv", "residual", "transfer", "copy", "fas_integrals"};
 struct ProfPending {
   int cls;
   int launches;
@@ -504,8 +504,9 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
   const int64_t sRI = (int64_t)M * NF * L.g.Np;
   const int spread = (lev == 0 && c->spread_pending) ? 1 : 0;
   if (u_src) {
-    HIPC(launch_copy_fields(c->s, L.g.Np, L.st.Y + s0 * L.st.sY(), L.st.sY(), u_src,
-                            (int64_t)NF * L.g.Np, NF, ns));
+    PLAUNCH(c, PC_COPY, 16.0 * NF * N * ns,
+            launch_copy_fields(c->s, L.g.Np, L.st.Y + s0 * L.st.sY(), L.st.sY(), u_src,
+                               (int64_t)NF * L.g.Np, NF, ns));
     evaluate_all(c, lev, s0, ns);
   }
   {
@@ -570,8 +571,13 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
   const double *yb = c->pfasst ? c->y0blk : L.st.Y;  // serial: u = y_{n,0}
   const int Mc = c->nlev == 2 ? c->L[1].co.M : 0;
   double *RI = (want_RI && c->nlev == 2) ? L.RI : nullptr;
-  HIPC(launch_residual(c->s, L.g, L.st, L.co, 0, L.P, yb, L.res_part, L.res_nblk, L.res_out,
-                       c->Rt, Mc, RI, (int64_t)Mc * NF * L.g.Np));
+  {
+    const double M = L.co.M;
+    const double per = (M + 1) * NF + M * NF + M + NG + NF + (RI ? Mc * NF : 0);
+    PLAUNCH(c, PC_RESIDUAL, 8.0 * per * L.g.N * L.P,
+            launch_residual(c->s, L.g, L.st, L.co, 0, L.P, yb, L.res_part, L.res_nblk, L.res_out,
+                            c->Rt, Mc, RI, (int64_t)Mc * NF * L.g.Np));
+  }
   HIPC(hipMemcpyAsync(L.res_out_host, L.res_out, 2 * L.P * sizeof(double), hipMemcpyDeviceToHost,
                       c->s));
   HIPC(hipStreamSynchronize(c->s));
@@ -591,14 +597,22 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
 // ---------------------------------------------------------------------------
 void restrict_fine_to_coarse(hsdc_ctx *c) {
   Level &F = c->L[0], &Cc = c->L[1];
-  HIPC(launch_restrict_stages(c->s, F.g, Cc.g, c->meth.space_coarsen, F.st.Y, F.st.sY(), F.co.M,
-                              c->Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
+  const double bytes = 8.0 * F.P * NF *
+                       ((F.co.M + 1.0) * F.g.N + 2.0 * (Cc.co.M + 1.0) * Cc.g.N);
+  PLAUNCH(c, PC_TRANSFER, bytes,
+          launch_restrict_stages(c->s, F.g, Cc.g, c->meth.space_coarsen, F.st.Y, F.st.sY(),
+                                 F.co.M, c->Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
 }
 
 void coarse_correct_fine(hsdc_ctx *c) {
   Level &F = c->L[0], &Cc = c->L[1];
-  HIPC(launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz, Cc.st.sY(),
-                              Cc.co.M, c->Tt, F.co.M, F.st.Y, F.st.sY(), F.P, Cc.D));
+  // z_c - S z into D (3 coarse passes), then read D once and update the fine stages
+  const double bytes = 8.0 * F.P * NF *
+                       (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0) * F.g.N);
+  PLAUNCH(c, PC_TRANSFER, bytes,
+          launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz,
+                                 Cc.st.sY(), Cc.co.M, c->Tt, F.co.M, F.st.Y, F.st.sY(), F.P,
+                                 Cc.D));
 }
 
 // start values u_n of a sweep over slices [s0, s0+ns) from the stage-M values
@@ -608,14 +622,16 @@ void gather_starts(hsdc_ctx *c, int lev, int s0, int ns) {
   const int64_t sS = L.st.sS();
   const double *blk0 = (lev == 0) ? c->y0blk : L.y0c;
   int n = s0;
+  const double per = 16.0 * NF * L.g.N;
   if (n == 0) {
-    HIPC(launch_copy_fields(c->s, L.g.Np, L.U, sS, blk0, sS, NF, 1));
+    PLAUNCH(c, PC_COPY, per, launch_copy_fields(c->s, L.g.Np, L.U, sS, blk0, sS, NF, 1));
     ++n;
   }
   if (n < s0 + ns)
-    HIPC(launch_copy_fields(c->s, L.g.Np, L.U + n * sS, sS,
-                            L.st.Y + (n - 1) * L.st.sY() + (int64_t)L.co.M * sS, L.st.sY(), NF,
-                            s0 + ns - n));
+    PLAUNCH(c, PC_COPY, per * (s0 + ns - n),
+            launch_copy_fields(c->s, L.g.Np, L.U + n * sS, sS,
+                               L.st.Y + (n - 1) * L.st.sY() + (int64_t)L.co.M * sS, L.st.sY(),
+                               NF, s0 + ns - n));
 }
 
 // Staggered coarse predictor: at stage s every slice n >= s takes one coarse
@@ -662,11 +678,12 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
       if (st != HSDC_OK) return st;
     }
     const int64_t sRIc = (int64_t)Mc * NF * Cc.g.Np;
-    HIPC(launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
-                                (int64_t)Mc * NF * F.g.Np, Cc.RI, sRIc, Mc * NF, P));
+    PLAUNCH(c, PC_TRANSFER, 8.0 * P * Mc * NF * ((double)F.g.N + Cc.g.N),
+            launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
+                                   (int64_t)Mc * NF * F.g.Np, Cc.RI, sRIc, Mc * NF, P));
     restrict_fine_to_coarse(c);
     evaluate_all(c, 1, 0, P);
-    PLAUNCH(c, PC_ASSEMBLE, 8.0 * ((Mc + 1) * NF + NG + 2 * Mc * NF) * Cc.g.N * P,
+    PLAUNCH(c, PC_FAS, 8.0 * (3.0 * Mc * NF + Mc + NG) * Cc.g.N * P,
             launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, 0, P, Cc.RI, sRIc));
     for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
       gather_starts(c, 1, n, 1);
