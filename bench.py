@@ -47,6 +47,8 @@ def _args():
                     help="slab3d: space coarsening factor of the coarse level")
     ap.add_argument("--tol", type=float, default=1e-9, help="slab3d: PFASST residual tolerance")
     ap.add_argument("--max-iter", type=int, default=60, help="slab3d: PFASST iterations cap")
+    ap.add_argument("--coarse-fp32", action="store_true",
+                    help="slab3d: coarse level in FP32 (fine level, residual and tau in FP64)")
     return ap.parse_args()
 
 
@@ -139,7 +141,7 @@ def bench_slab3d(a):
     def pfasst_method():
         return H.make_method(M=(w["M"], w["Mc"]), levels=2, space_coarsen=a.coarsen, P=P, dt=dt,
                              max_iter=a.max_iter, tol=a.tol, burn_in=1, cg_rtol=w["cg_rtol"],
-                             cg_maxit=500)
+                             cg_maxit=500, coarse_fp32=a.coarse_fp32)
 
     def serial_method(K, rtol):
         return H.make_method(M=(w["M"], 1), dt=dt, max_iter=K, cg_rtol=rtol, cg_maxit=500)
@@ -195,7 +197,8 @@ def bench_slab3d(a):
     fine_sweeps = st_pf["sweeps"]
     value = T / wall_pf
     out = {
-        "metric": "simulated ms per wall-s at fixed error (two-level PFASST, FP64)",
+        "metric": "simulated ms per wall-s at fixed error (two-level PFASST, "
+                  + ("FP32 coarse level)" if a.coarse_fp32 else "FP64)"),
         "value": value,
         "unit": "sim-ms/s",
         "n_gpus": 1,
@@ -205,11 +208,12 @@ def bench_slab3d(a):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if a.coarse_fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": "slab3d 192x96x48, 7-point sigma (3,1,1), TTP06, PFASST P16 "
                                f"M 6/3, coarse mesh /{a.coarsen}, dt 0.1 ms, tol {a.tol:g}",
                    "nodes": N, "P": P, "M": [w["M"], w["Mc"]], "space_coarsen": a.coarsen,
+                   "coarse_fp32": bool(a.coarse_fp32),
                    "blocks": a.blocks, "t_simulated_ms": T},
         "pfasst_iters_per_block": st_pf["pfasst_iters"] / a.blocks,
         "error_vs_collocation": err_pf,

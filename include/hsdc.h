@@ -90,6 +90,15 @@ typedef struct {
   int32_t burn_in;           /* 1: staggered coarse burn-in before a block, P > 1 */
   double cg_rtol;            /* diffusion solve: ||b - A x||_2 <= cg_rtol ||b||_2 */
   int32_t cg_maxit;          /* iteration cap per diffusion solve                 */
+  int32_t coarse_fp32;       /* levels = 2: 1 runs the coarse level's cell model  */
+                             /* and stores its reaction terms, Lambda and CG work */
+                             /* vectors in FP32; states, K V, right-hand sides,   */
+                             /* collocation integrals, phi functions, reductions, */
+                             /* tau and the fine level stay FP64, so the fixed    */
+                             /* point is the FP64 fine collocation solution       */
+  double coarse_cg_rtol;     /* coarse diffusion solves; <= 0: cg_rtol (FP64      */
+                             /* coarse level) or 1e-5 (FP32 coarse level, where   */
+                             /* it is relative to the warm start's residual)      */
 } hsdc_method;
 
 /* Counters since init (host copy). */

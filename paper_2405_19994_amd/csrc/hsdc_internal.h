@@ -36,14 +36,19 @@ struct Colloc {
   double invfact[MAXM + 10];    // 1/k!, k = 0..MAXM+9
 };
 
-// Strided view of a set of stage vectors on one level.
-struct Stages {
-  double *Y;    // [P][M+1][NF][Np]
-  double *G;    // [P][M+1][NF][Np]  reaction part of g at each stage
-  double *FV;   // [P][M+1][Np]      K V at each stage
-  double *RH;   // [P][M][NF][Np]    assembled right-hand-side differences
-  double *L0;   // [P][NG][Np]       Lambda(y_{n,0}) of the current iterate
-  double *B;    // [P][Np]           diffusion right-hand side
+// Strided view of a set of stage vectors on one level.  States, K V, the
+// assembled right-hand side and the diffusion right-hand side are FP64 on every
+// level; the cell-model terms (G, Lambda) are stored and computed in T (float
+// on an FP32 coarse level).  Every T-valued term enters both sides of a sweep
+// from the same inputs, so its rounding cancels at the fixed point.
+template <class T>
+struct StagesT {
+  double *Y;   // [P][M+1][NF][Np]
+  T *G;        // [P][M+1][NF][Np]  reaction part of g at each stage
+  double *FV;  // [P][M+1][Np]      K V at each stage
+  double *RH;  // [P][M][NF][Np]    assembled right-hand-side differences
+  T *L0;       // [P][NG][Np]       Lambda(y_{n,0}) of the current iterate
+  double *B;   // [P][Np]           diffusion right-hand side
   int64_t Np;
   int M;
   __host__ __device__ int64_t sY() const { return (int64_t)(M + 1) * NF * Np; }
@@ -52,6 +57,7 @@ struct Stages {
   __host__ __device__ int64_t sRH() const { return (int64_t)M * NF * Np; }
   __host__ __device__ int64_t sL() const { return (int64_t)NG * Np; }
 };
+using Stages = StagesT<double>;
 
 struct Stim {
   const double *w;  // [Np] or null
@@ -70,32 +76,42 @@ struct CgScalars {
 };
 
 // ---- kernel launch wrappers (defined in hsdc_kernels.hip) -------------------
-hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+// Kernels templated on T run on both storage types; arithmetic follows the
+// storage type except where noted (collocation integrals, phi functions and
+// reductions are FP64 throughout).
+template <class T>
+hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
                               int nslices, int stage0, int nstages, int64_t step0,
-                              double *L_anchor_out, const double *L_anchor_in);
-hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
+                              T *L_anchor_out, const T *L_anchor_in);
+template <class T>
+hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, int slice0,
                               int nslices, int stage0, int nstages);
 hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                          const Stim &stim, int slice0, int nslices, int64_t step0,
                          bool copy_Y_from_stage0);
 // spread != 0: stages 1..M are the spread of stage 0 (y^0 = 1 (x) y_n) and are
 // read from stage 0 (the stimulus part of the V reaction term follows t_{n,j}).
-hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+template <class T>
+hipError_t launch_assemble(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                            int slice0, int nslices, const double *RI, int64_t sRI, int spread,
                            const Stim &stim, int64_t step0);
 // RI[n][i][f] -= (A G)_i of the stage vector held by st (coarse FAS term of tau).
-hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                                int slice0, int nslices, double *RI, int64_t sRI);
+template <class T>
+hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const StagesT<T> &st,
+                                const Colloc &co, int slice0, int nslices, double *RI,
+                                int64_t sRI);
 // The node update also forms the CG start residual r_0 = b - x_0 + a K x_0 from
 // the cached K x_0 (x_0 = V^k_i) and writes the partials of ||b||^2, ||r_0||^2.
-struct CgBatch;
+template <class T>
+struct CgBatchT;
 // store_g = 0 skips storing the reaction term (its caller discards it);
 // spread != 0 takes K x_0 from stage 0 (first sweep after a spread).
-hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                              const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int i, int64_t step0, const CgBatch &cb, int store_g,
-                              int spread);
+template <class T>
+hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
+                              const Colloc &co, const Stim &stim, double gs0, double gs1,
+                              double gs2, int slice0, int nslices, int i, int64_t step0,
+                              const CgBatchT<T> &cb, int store_g, int spread);
 hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
                                    int nslices);
 int node_blocks(const Grid &g);
@@ -109,11 +125,16 @@ hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sd
 
 // CG on (I - a K) x = b, batched over slices with strided vectors
 // (Chronopoulos-Gear single-reduction form: one stencil kernel per iteration).
-struct CgBatch {
+// The solution and right-hand side are FP64; the work vectors are stored in T;
+// scalars, stencil sums and reductions are FP64.  rel_r0 = 1 stops on
+// ||r_k|| <= rtol ||r_0|| (a correction solved to relative accuracy), else on
+// ||r_k|| <= rtol ||b||.
+template <class T>
+struct CgBatchT {
   double *x; int64_t sx;        // solution (in place), slice stride
   const double *b; int64_t sb;
-  double *r[2], *w[2], *s[2];   // ping-pong [nslices][Np]
-  double *p;                    // [nslices][Np]
+  T *r[2], *w[2], *s[2];        // ping-pong [nslices][Np]
+  T *p;                         // [nslices][Np]
   double *part;                 // [nslices][5][pstride] partial sums:
                                 //   gamma par0 | delta par0 | gamma par1 | delta par1 | bb
   int64_t pstride;
@@ -124,11 +145,16 @@ struct CgBatch {
   int nblk0;                    // partials of gamma_0 and bb (written by the producer of r_0)
   double a, tol2;
   int maxit;
+  int rel_r0;
 };
+using CgBatch = CgBatchT<double>;
 int cg_blocks(const Grid &g, int cap = 512);
-hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb);
-hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatch &cb);
-hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k);
+template <class T>
+hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatchT<T> &cb);
+template <class T>
+hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatchT<T> &cb);
+template <class T>
+hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatchT<T> &cb, int k);
 hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out);
 
 // transfers (space coarsening 2x or identity) between a fine and a coarse level
@@ -141,7 +167,7 @@ hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc,
 hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *Yc, const double *Sz, int64_t sYc, int Mc,
                                   const double *Tt, int Mf, double *Yf, int64_t sYf,
-                                  int nslices, double *scratch);
+                                  int nslices);
 
 // building blocks exported for tests
 hipError_t launch_ionic_test(hipStream_t s, int64_t n, const double *y, double gs0, double gs1,

@@ -292,9 +292,10 @@ __device__ __forceinline__ double stim_value(const Stim &st, double t, int64_t p
   return on ? st.amp * st.w[p] : 0.0;
 }
 
+template <class T>
 __global__ void __launch_bounds__(BLOCK)
-k_eval_stages(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int stage0, int64_t step0, double *Lout, const double *Lin) {
+k_eval_stages(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
+              int slice0, int stage0, int64_t step0, T *Lout, const T *Lin) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= g.N) return;
   const int n = slice0 + blockIdx.z;
@@ -302,43 +303,45 @@ k_eval_stages(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, d
   const int64_t Np = st.Np;
   const double *y = st.Y + n * st.sY() + j * st.sS();
   const double *u = st.Y + n * st.sY();
-  double *G = st.G + n * st.sY() + j * st.sS();
-  double yv[NF];
+  T *G = st.G + n * st.sY() + j * st.sS();
+  T yv[NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) yv[f] = y[f * Np + p];
+  for (int f = 0; f < NF; ++f) yv[f] = T(y[f * Np + p]);
   const double cj = (j == 0) ? 0.0 : co.c[j - 1];
   const double t = ((double)(step0 + n) + cj) * co.dt;
-  const double *La = (j == 0) ? nullptr : Lin + n * st.sL();
-  double *Lo = (j == 0 && Lout) ? Lout + n * st.sL() : nullptr;
-  ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
-    const double lam = -1.0 / tau;
-    const double w = yv[GATE0 + k];
-    double gv = lam * (w - inf);
-    if (La) gv += La[k * Np + p] * (u[(GATE0 + k) * Np + p] - w);
+  const T *La = (j == 0) ? nullptr : Lin + n * st.sL();
+  T *Lo = (j == 0 && Lout) ? Lout + n * st.sL() : nullptr;
+  ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T tau) {
+    const T lam = T(-1) / tau;
+    const T w = yv[GATE0 + k];
+    T gv = lam * (w - inf);
+    if (La) gv += La[k * Np + p] * (T(u[(GATE0 + k) * Np + p]) - w);
     G[(GATE0 + k) * Np + p] = gv;
     if (Lo) Lo[k * Np + p] = lam;
   });
-  double I_ion, ha[6];
-  ttp06::currents(yv, gs0, gs1, gs2, I_ion, ha);
-  G[p] = (stim_value(stim, t, p) - stim.Cm * I_ion) / stim.Cm;
+  T I_ion, ha[6];
+  ttp06::currents<T>(yv, T(gs0), T(gs1), T(gs2), I_ion, ha);
+  G[p] = (T(stim_value(stim, t, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
 #pragma unroll
   for (int k = 0; k < 6; ++k) G[(1 + k) * Np + p] = ha[k];
 }
 
-hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+template <class T>
+hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
                               int nslices, int stage0, int nstages, int64_t step0,
-                              double *L_anchor_out, const double *L_anchor_in) {
+                              T *L_anchor_out, const T *L_anchor_in) {
   if (nslices <= 0 || nstages <= 0) return hipSuccess;
   dim3 grid(nblocks(g.N), nstages, nslices);
-  hipLaunchKernelGGL(k_eval_stages, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
+  hipLaunchKernelGGL(k_eval_stages<T>, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
                      slice0, stage0, step0, L_anchor_out, L_anchor_in);
   return hipGetLastError();
 }
 
 // FV_j = K V_j at stages.
-template <int DIM, bool PN>
-__global__ void __launch_bounds__(BLOCK) k_spmv_stages(Grid g, Stages st, int slice0, int stage0) {
+template <int DIM, bool PN, class T>
+__global__ void __launch_bounds__(BLOCK) k_spmv_stages(Grid g, StagesT<T> st, int slice0,
+                                                       int stage0) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= g.N) return;
   const int n = slice0 + blockIdx.z;
@@ -346,15 +349,17 @@ __global__ void __launch_bounds__(BLOCK) k_spmv_stages(Grid g, Stages st, int sl
   const double *v = st.Y + n * st.sY() + j * st.sS();
   const Ijk c = ijk(g, p);
   const double vc = v[p];
-  st.FV[n * st.sFV() + j * st.Np + p] = applyK<DIM, PN>(g, p, c, vc, [&](int64_t k) { return v[k]; });
+  st.FV[n * st.sFV() + j * st.Np + p] =
+      applyK<DIM, PN>(g, p, c, vc, [&](int64_t k) { return v[k]; });
 }
 
-hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
+template <class T>
+hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, int slice0,
                               int nslices, int stage0, int nstages) {
   if (nslices <= 0 || nstages <= 0) return hipSuccess;
   dim3 grid(nblocks(g.N), nstages, nslices);
-  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_spmv_stages<DIM, PN>), grid, dim3(BLOCK), 0, s, g, st,
-                                         slice0, stage0));
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_spmv_stages<DIM, PN, T>), grid, dim3(BLOCK), 0, s, g,
+                                         st, slice0, stage0));
   return hipGetLastError();
 }
 
@@ -402,16 +407,16 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
 // (per unit dt, from k_fas_integrals) is added to them.
 // ---------------------------------------------------------------------------
 
-template <int M>
+template <int M, class T>
 __global__ void __launch_bounds__(BLOCK)
-k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t sRI, int spread,
+k_assemble(Grid g, StagesT<T> st, Colloc co, int slice0, const double *RI, int64_t sRI, int spread,
            Stim stim, int64_t step0) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= g.N) return;
   const int f = blockIdx.y;  // one field per block row: no divergence between field kinds
   const int n = slice0 + blockIdx.z;
   const int64_t Np = st.Np;
-  const double *G = st.G + n * st.sY() + f * Np + p;
+  const T *G = st.G + n * st.sY() + f * Np + p;
   const double *FV = st.FV + n * st.sFV() + p;
   double *RH = st.RH + n * st.sRH() + f * Np + p;
   const double dt = co.dt;
@@ -455,11 +460,12 @@ k_assemble(Grid g, Stages st, Colloc co, int slice0, const double *RI, int64_t s
   }
 }
 
-hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+template <class T>
+hipError_t launch_assemble(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                            int slice0, int nslices, const double *RI, int64_t sRI, int spread,
                            const Stim &stim, int64_t step0) {
   dim3 grid(nblocks(g.N), NF, nslices);
-  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_assemble<M>), grid, dim3(BLOCK), 0, s, g, st, co,
+  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_assemble<M, T>), grid, dim3(BLOCK), 0, s, g, st, co,
                                            slice0, RI, sRI, spread, stim, step0));
   return hipGetLastError();
 }
@@ -470,19 +476,20 @@ hipError_t launch_assemble(hipStream_t s, const Grid &g, const Stages &st, const
 // part arrives in RI (fine integrals restricted in time and space), the second
 // is computed here from the reaction terms, K V and Lambda of S z.
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, class T>
 __global__ void __launch_bounds__(BLOCK)
-k_fas_integrals(Grid g, Stages st, Colloc co, int slice0, double *RI, int64_t sRI) {
+k_fas_integrals(Grid g, StagesT<T> st, Colloc co, int slice0, double *RI, int64_t sRI) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= g.N) return;
   const int f = blockIdx.y;
   const int n = slice0 + blockIdx.z;
   const int64_t Np = st.Np;
-  const double *G = st.G + n * st.sY() + f * Np + p;
+  const T *G = st.G + n * st.sY() + f * Np + p;
   const double *FV = st.FV + n * st.sFV() + p;
   double gfull[M], I[M];
 #pragma unroll
-  for (int j = 0; j < M; ++j) gfull[j] = G[(j + 1) * st.sS()] + (f == 0 ? FV[(j + 1) * Np] : 0.0);
+  for (int j = 0; j < M; ++j)
+    gfull[j] = (double)G[(j + 1) * st.sS()] + (f == 0 ? FV[(j + 1) * Np] : 0.0);
   const double z = (f >= GATE0) ? co.dt * st.L0[n * st.sL() + (f - GATE0) * Np + p] : 0.0;
   colloc_integrals<M>(co, z, gfull, I);
   double *R = RI + n * sRI + (int64_t)f * Np + p;
@@ -490,11 +497,13 @@ k_fas_integrals(Grid g, Stages st, Colloc co, int slice0, double *RI, int64_t sR
   for (int i = 0; i < M; ++i) R[(int64_t)i * NF * Np] -= I[i];
 }
 
-hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                                int slice0, int nslices, double *RI, int64_t sRI) {
+template <class T>
+hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const StagesT<T> &st,
+                                const Colloc &co, int slice0, int nslices, double *RI,
+                                int64_t sRI) {
   dim3 grid(nblocks(g.N), NF, nslices);
-  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_fas_integrals<M>), grid, dim3(BLOCK), 0, s, g, st,
-                                           co, slice0, RI, sRI));
+  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_fas_integrals<M, T>), grid, dim3(BLOCK), 0, s, g,
+                                           st, co, slice0, RI, sRI));
   return hipGetLastError();
 }
 
@@ -504,9 +513,10 @@ hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const Stages &st, 
 // side of the implicit diffusion solve for V.
 // ---------------------------------------------------------------------------
 
+template <class T>
 __global__ void __launch_bounds__(BLOCK)
-k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int i, int64_t step0, CgBatch cb, int store_g, int spread) {
+k_node_update(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
+              int slice0, int i, int64_t step0, CgBatchT<T> cb, int store_g, int spread) {
   __shared__ double lds[BLOCK / 64];
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
@@ -518,47 +528,51 @@ k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, d
     double *Yi = st.Y + n * st.sY() + (int64_t)i * st.sS();
     const double *u = st.Y + n * st.sY();
     const double *RH = st.RH + n * st.sRH() + (int64_t)(i - 1) * st.sS();
-    const double *Lu = st.L0 + n * st.sL();  // Lambda of the anchor u
-    double *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
-    double yv[NF];
+    const T *Lu = st.L0 + n * st.sL();  // Lambda of the anchor u
+    T *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
+    // the state accumulates in FP64; the cell model runs in T
+    double yd[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) yv[f] = Yp[f * Np + p];
-    double gV;
+    for (int f = 0; f < NF; ++f) yd[f] = Yp[f * Np + p];
+    T gV;
     if (i == 1) {
       // y_{n,0} = u: its reaction term was evaluated with the anchor
 #pragma unroll
       for (int f = 1; f < NF; ++f) {
-        const double gv = Gp[f * Np + p];
-        const double ph = (f >= GATE0) ? phi1(ddt * Lu[(f - GATE0) * Np + p]) : 1.0;
-        Yi[f * Np + p] = yv[f] + RH[f * Np + p] + ddt * ph * gv;
+        const T gv = Gp[f * Np + p];
+        const T ph = (f >= GATE0) ? T(phi1(ddt * (double)Lu[(f - GATE0) * Np + p])) : T(1);
+        Yi[f * Np + p] = yd[f] + RH[f * Np + p] + ddt * (double)ph * (double)gv;
       }
       gV = Gp[p];
     } else {
+      T yv[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) yv[f] = T(yd[f]);
       const double t = ((double)(step0 + n) + co.c[i - 2]) * co.dt;
-      ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
+      ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T tau) {
         const int f = GATE0 + k;
-        const double lu = Lu[k * Np + p];
-        const double w = yv[f];
-        const double gv = (-1.0 / tau) * (w - inf) + lu * (u[f * Np + p] - w);
+        const T lu = Lu[k * Np + p];
+        const T w = yv[f];
+        const T gv = (T(-1) / tau) * (w - inf) + lu * (T(u[f * Np + p]) - w);
         if (store_g) Gp[f * Np + p] = gv;
-        Yi[f * Np + p] = w + RH[f * Np + p] + ddt * phi1(ddt * lu) * gv;
+        Yi[f * Np + p] = yd[f] + RH[f * Np + p] + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv;
       });
-      double I_ion, ha[6];
-      ttp06::currents(yv, gs0, gs1, gs2, I_ion, ha);
-      gV = (stim_value(stim, t, p) - stim.Cm * I_ion) / stim.Cm;
+      T I_ion, ha[6];
+      ttp06::currents<T>(yv, T(gs0), T(gs1), T(gs2), I_ion, ha);
+      gV = (T(stim_value(stim, t, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
       if (store_g) Gp[p] = gV;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         if (store_g) Gp[(1 + k) * Np + p] = ha[k];
-        Yi[(1 + k) * Np + p] = yv[1 + k] + RH[(1 + k) * Np + p] + ddt * ha[k];
+        Yi[(1 + k) * Np + p] = yd[1 + k] + RH[(1 + k) * Np + p] + ddt * (double)ha[k];
       }
     }
     // right-hand side of (I - dt d_i K) V_i = b and the CG start residual for
     // the warm start x_0 = V^k_i, whose K x_0 is cached from the previous sweep
-    const double bv = yv[0] + RH[p] + ddt * gV;
+    const double bv = yd[0] + RH[p] + ddt * (double)gV;
     const double x0 = Yi[p];
     const double r0 = bv - x0 + cb.a * st.FV[n * st.sFV() + (int64_t)(spread ? 0 : i) * Np + p];
-    cb.r[0][(int64_t)(n - slice0) * Np + p] = r0;
+    cb.r[0][(int64_t)(n - slice0) * Np + p] = T(r0);
     bb = bv * bv;
     rr = r0 * r0;
   }
@@ -573,12 +587,13 @@ k_node_update(Grid g, Stages st, Colloc co, Stim stim, double gs0, double gs1, d
 
 int node_blocks(const Grid &g) { return (int)nblocks(g.N); }
 
-hipError_t launch_node_update(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                              const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int i, int64_t step0, const CgBatch &cb, int store_g,
-                              int spread) {
+template <class T>
+hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
+                              const Colloc &co, const Stim &stim, double gs0, double gs1,
+                              double gs2, int slice0, int nslices, int i, int64_t step0,
+                              const CgBatchT<T> &cb, int store_g, int spread) {
   dim3 grid(nblocks(g.N), 1, nslices);
-  hipLaunchKernelGGL(k_node_update, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
+  hipLaunchKernelGGL(k_node_update<T>, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
                      slice0, i, step0, cb, store_g, spread);
   return hipGetLastError();
 }
@@ -725,13 +740,13 @@ int cg_blocks(const Grid &g, int cap) {
 
 // Start residual r_0 = b - A x_0 with the partials of ||r_0||^2 and ||b||^2
 // (used when r_0 is not produced by the node update).
-template <int DIM, bool PN>
-__global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g, CgBatch cb) {
+template <int DIM, bool PN, class T>
+__global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g, CgBatchT<T> cb) {
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
   const double *x = cb.x + n * cb.sx;
   const double *b = cb.b + n * cb.sb;
-  double *r = cb.r[0] + n * g.Np;
+  T *r = cb.r[0] + n * g.Np;
   double rr = 0.0, bb = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
@@ -752,17 +767,17 @@ __global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g, CgBatch cb) {
 }
 
 // w_0 = A r_0 and the partials of delta_0 = (w_0, r_0); resets the scalars.
-template <int DIM, bool PN>
-__global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatch cb) {
+template <int DIM, bool PN, class T>
+__global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatchT<T> cb) {
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
-  const double *r = cb.r[0] + n * g.Np;
-  double *w = cb.w[0] + n * g.Np;
+  const T *r = cb.r[0] + n * g.Np;
+  T *w = cb.w[0] + n * g.Np;
   double del = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
     const double rc = r[p];
-    const double wv = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, [&](int64_t k) { return r[k]; });
+    const double wv = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, [&](int64_t k) { return (double)r[k]; });
     w[p] = wv;
     del += wv * rc;
   }
@@ -782,8 +797,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatch cb) {
   }
 }
 
-template <int DIM, bool PN>
-__global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
+template <int DIM, bool PN, class T>
+__global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatchT<T> cb, int k) {
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
   const int in = k & 1, out = in ^ 1;
@@ -797,9 +812,9 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
     return;
   }
   double *part = cb.part + (int64_t)n * 5 * cb.pstride;
-  const double *r = cb.r[in] + n * g.Np;
-  const double *w = cb.w[in] + n * g.Np;
-  const double *s = cb.s[in] + n * g.Np;
+  const T *r = cb.r[in] + n * g.Np;
+  const T *w = cb.w[in] + n * g.Np;
+  const T *s = cb.s[in] + n * g.Np;
   double gamma, delta;
   // first owned node: its stencil loads are issued before the partial sums
   // are combined, so the reduction latency overlaps the memory traffic
@@ -807,8 +822,9 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
   double r_c = 0.0, w_c = 0.0, s_c = 0.0, rn_[2 * DIM], wn_[2 * DIM], sn_[2 * DIM];
   Ijk c0{0, 0, 0};
   if (si.it == 0) {
-    si.bb = reduce_partials(part + 4 * cb.pstride, cb.nblk0, lds);
     gamma = reduce_partials(part, cb.nblk0, lds);
+    // stop relative to ||b|| or, for a correction solve, to ||r_0||
+    si.bb = cb.rel_r0 ? gamma : reduce_partials(part + 4 * cb.pstride, cb.nblk0, lds);
     delta = reduce_partials(part + cb.pstride, cb.nblk, lds);
   } else {
     const double *pg = part + (2 * in) * cb.pstride, *pd = part + (2 * in + 1) * cb.pstride;
@@ -848,10 +864,10 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
   const bool first = si.it == 0;
   const double beta = first ? 0.0 : gamma / si.gamma;
   const double alpha = first ? gamma / delta : gamma / (delta - beta * gamma / si.alpha);
-  double *ro = cb.r[out] + n * g.Np;
-  double *wo = cb.w[out] + n * g.Np;
-  double *sout = cb.s[out] + n * g.Np;
-  double *pp = cb.p + n * g.Np;
+  T *ro = cb.r[out] + n * g.Np;
+  T *wo = cb.w[out] + n * g.Np;
+  T *sout = cb.s[out] + n * g.Np;
+  T *pp = cb.p + n * g.Np;
   double *x = cb.x + n * cb.sx;
   double gam = 0.0, del = 0.0;
   // iteration 0 takes p = r, s = w (p and s hold nothing yet)
@@ -919,21 +935,26 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatch cb, int k) {
   }
 }
 
-hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatch &cb) {
+template <class T>
+hipError_t launch_cg_init(hipStream_t s, const Grid &g, const CgBatchT<T> &cb) {
   dim3 grid(cb.nblk, cb.nslices);
-  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_init<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb));
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_init<DIM, PN, T>), grid, dim3(BLOCK), 0, s, g, cb));
   return hipGetLastError();
 }
 
-hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatch &cb) {
+template <class T>
+hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatchT<T> &cb) {
   dim3 grid(cb.nblk, cb.nslices);
-  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_resid0<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb));
+  HSDC_DISPATCH_OP(g,
+                   hipLaunchKernelGGL((k_cg_resid0<DIM, PN, T>), grid, dim3(BLOCK), 0, s, g, cb));
   return hipGetLastError();
 }
 
-hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k) {
+template <class T>
+hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatchT<T> &cb, int k) {
   dim3 grid(cb.nblk, cb.nslices);
-  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_iter<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb, k));
+  HSDC_DISPATCH_OP(
+      g, hipLaunchKernelGGL((k_cg_iter<DIM, PN, T>), grid, dim3(BLOCK), 0, s, g, cb, k));
   return hipGetLastError();
 }
 
@@ -980,6 +1001,8 @@ __device__ __forceinline__ Children children(const Grid &gf, const Grid &gc, int
   return ch;
 }
 
+// Stage loops run to the compile-time maximum with predication, so the per-node
+// stage values stay in registers.
 __global__ void __launch_bounds__(BLOCK)
 k_restrict_stages(Grid gf, Grid gc, int scf, const double *Yf, int64_t sYf, int Mf,
                   const double *Rt, int Mc, double *Yc, int64_t sYc, double *Yc2) {
@@ -990,17 +1013,24 @@ k_restrict_stages(Grid gf, Grid gc, int scf, const double *Yf, int64_t sYf, int 
   const double inv = 1.0 / ch.n;
   for (int f = 0; f < NF; ++f) {
     double av[MAXM + 1];
-    for (int l = 0; l <= Mf; ++l) {
+#pragma unroll
+    for (int l = 0; l <= MAXM; ++l) {
       double s = 0.0;
-      for (int k = 0; k < ch.n; ++k) s += Yf[n * sYf + ((int64_t)l * NF + f) * gf.Np + ch.idx[k]];
+      if (l <= Mf)
+        for (int k = 0; k < ch.n; ++k) s += Yf[n * sYf + ((int64_t)l * NF + f) * gf.Np + ch.idx[k]];
       av[l] = s * inv;
     }
-    for (int i = 0; i <= Mc; ++i) {
-      double s = 0.0;
-      for (int l = 0; l <= Mf; ++l) s += Rt[i * (Mf + 1) + l] * av[l];
-      const int64_t o = n * sYc + ((int64_t)i * NF + f) * gc.Np + pc;
-      Yc[o] = s;
-      if (Yc2) Yc2[o] = s;
+#pragma unroll
+    for (int i = 0; i <= MAXM; ++i) {
+      if (i <= Mc) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l <= MAXM; ++l)
+          if (l <= Mf) s += Rt[i * (Mf + 1) + l] * av[l];
+        const int64_t o = n * sYc + ((int64_t)i * NF + f) * gc.Np + pc;
+        Yc[o] = s;
+        if (Yc2) Yc2[o] = s;
+      }
     }
   }
 }
@@ -1009,8 +1039,8 @@ hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc,
                                   const double *Yf, int64_t sYf, int Mf, const double *Rt,
                                   int Mc, double *Yc, int64_t sYc, double *Yc_copy, int nslices) {
   dim3 grid(nblocks(gc.N), 1, nslices);
-  hipLaunchKernelGGL(k_restrict_stages, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, Yf, sYf, Mf,
-                     Rt, Mc, Yc, sYc, Yc_copy);
+  hipLaunchKernelGGL(k_restrict_stages, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, Yf, sYf,
+                     Mf, Rt, Mc, Yc, sYc, Yc_copy);
   return hipGetLastError();
 }
 
@@ -1033,28 +1063,16 @@ hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc,
                                   const double *src, int64_t ssrc, double *dst, int64_t sdst,
                                   int nrows, int nslices) {
   dim3 grid(nblocks(gc.N), 1, nslices);
-  hipLaunchKernelGGL(k_restrict_fields, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, src, ssrc,
-                     dst, sdst, nrows);
+  hipLaunchKernelGGL(k_restrict_fields, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, src,
+                     ssrc, dst, sdst, nrows);
   return hipGetLastError();
 }
 
-// D = Yc - Sz on the coarse level (in the scratch buffer).
+// y_f += T P(z_c - S z): the coarse difference is formed on the fly at the (up
+// to 8) coarse cells that interpolate onto fine node p.
 __global__ void __launch_bounds__(BLOCK)
-k_coarse_diff(int64_t Ncp, const double *Yc, const double *Sz, double *D, int64_t sYc, int rows) {
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= Ncp) return;
-  const int n = blockIdx.z;
-  for (int r = 0; r < rows; ++r) {
-    const int64_t o = n * sYc + (int64_t)r * Ncp + p;
-    D[o] = Yc[o] - Sz[o];
-  }
-}
-
-// Yf_i += sum_j T_ij Ps(D_j) with Ps the cell-centred multilinear interpolation
-// (weights 3/4 and 1/4 per coarsened axis, mirror at the walls).
-__global__ void __launch_bounds__(BLOCK)
-k_prolong_correct(Grid gf, Grid gc, int scf, const double *D, int64_t sYc, int Mc,
-                  const double *Tt, int Mf, double *Yf, int64_t sYf) {
+k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz, int64_t sYc,
+                  int Mc, const double *Tt, int Mf, double *Yf, int64_t sYf) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= gf.N) return;
   const int n = blockIdx.z;
@@ -1101,15 +1119,25 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *D, int64_t sYc, int M
   }
   for (int f = 0; f < NF; ++f) {
     double dc[MAXM + 1];
-    for (int j = 0; j <= Mc; ++j) {
+#pragma unroll
+    for (int j = 0; j <= MAXM; ++j) {
       double s = 0.0;
-      for (int k = 0; k < nn; ++k) s += wt[k] * D[n * sYc + ((int64_t)j * NF + f) * gc.Np + idx[k]];
+      if (j <= Mc) {
+        const int64_t o = n * sYc + ((int64_t)j * NF + f) * gc.Np;
+        for (int k = 0; k < nn; ++k)
+          s += wt[k] * (Yc[o + idx[k]] - Sz[o + idx[k]]);
+      }
       dc[j] = s;
     }
-    for (int i = 0; i <= Mf; ++i) {
-      double s = 0.0;
-      for (int j = 0; j <= Mc; ++j) s += Tt[i * (Mc + 1) + j] * dc[j];
-      Yf[n * sYf + ((int64_t)i * NF + f) * gf.Np + p] += s;
+#pragma unroll
+    for (int i = 0; i <= MAXM; ++i) {
+      if (i <= Mf) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j <= MAXM; ++j)
+          if (j <= Mc) s += Tt[i * (Mc + 1) + j] * dc[j];
+        Yf[n * sYf + ((int64_t)i * NF + f) * gf.Np + p] += s;
+      }
     }
   }
 }
@@ -1117,12 +1145,9 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *D, int64_t sYc, int M
 hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *Yc, const double *Sz, int64_t sYc, int Mc,
                                   const double *Tt, int Mf, double *Yf, int64_t sYf,
-                                  int nslices, double *scratch) {
-  const int rows = (Mc + 1) * NF;
-  hipLaunchKernelGGL(k_coarse_diff, dim3(nblocks(gc.Np), 1, nslices), dim3(BLOCK), 0, s, gc.Np,
-                     Yc, Sz, scratch, sYc, rows);
-  hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks(gf.N), 1, nslices), dim3(BLOCK), 0, s, gf,
-                     gc, sc_factor, scratch, sYc, Mc, Tt, Mf, Yf, sYf);
+                                  int nslices) {
+  hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks(gf.N), 1, nslices), dim3(BLOCK), 0, s,
+                     gf, gc, sc_factor, Yc, Sz, sYc, Mc, Tt, Mf, Yf, sYf);
   return hipGetLastError();
 }
 
@@ -1209,4 +1234,27 @@ hipError_t launch_fill_rest(hipStream_t s, int64_t N, int64_t Np, double *y) {
   return hipGetLastError();
 }
 
+// ---- instantiations for the two storage types -------------------------------
+#define HSDC_INSTANTIATE(T)                                                                   \
+  template hipError_t launch_eval_stages<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
+                                            const Colloc &, const Stim &, double, double,    \
+                                            double, int, int, int, int, int64_t, T *,        \
+                                            const T *);                                      \
+  template hipError_t launch_spmv_stages<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
+                                            int, int, int, int);                             \
+  template hipError_t launch_assemble<T>(hipStream_t, const Grid &, const StagesT<T> &,       \
+                                         const Colloc &, int, int, const double *, int64_t,  \
+                                         int, const Stim &, int64_t);                        \
+  template hipError_t launch_fas_integrals<T>(hipStream_t, const Grid &, const StagesT<T> &,  \
+                                              const Colloc &, int, int, double *, int64_t);  \
+  template hipError_t launch_node_update<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
+                                            const Colloc &, const Stim &, double, double,    \
+                                            double, int, int, int, int64_t,                  \
+                                            const CgBatchT<T> &, int, int);                  \
+  template hipError_t launch_cg_init<T>(hipStream_t, const Grid &, const CgBatchT<T> &);      \
+  template hipError_t launch_cg_resid0<T>(hipStream_t, const Grid &, const CgBatchT<T> &);    \
+  template hipError_t launch_cg_iter<T>(hipStream_t, const Grid &, const CgBatchT<T> &, int);
+HSDC_INSTANTIATE(double)
+HSDC_INSTANTIATE(float)
+#undef HSDC_INSTANTIATE
 }  // namespace hsdc

@@ -10,8 +10,16 @@
 //                    + Lambda(u)(u - y^{k+1}_{i-1})) ]
 // where R_i - R_{i-1} = dt sum_j (a_ij - a_{i-1,j}) g_j(y^k) - dt d_i Phi_i(y^k)
 // + tau_i - tau_{i-1} uses only the previous iterate (kernel k_assemble) and
-// the implicit part acts on V only (a CG solve).  (P - C)(y^k) is evaluated with
-// the anchor y^k_{n,0} and Lambda(y^k_{n,0}); P^-1 with the new start value u.
+// the implicit part acts on V only (a CG solve).  Both sides use the start value
+// u of the new iterate as anchor: y^k enters with y^k_{n,0} replaced by u.
+//
+// FP32 coarse level (coarse_fp32): the cell model, its stored terms (G,
+// Lambda) and the CG work vectors are FP32, while states, K V, the assembled
+// right-hand side and the CG solution accumulate in FP64.  An FP32 term enters
+// both sides of a sweep from identical inputs at the fixed point and cancels
+// there, and the coarse CG solves the warm-start correction to a relative
+// accuracy, so FP32 rounding shrinks with the PFASST defect instead of
+// setting a floor.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,22 +48,30 @@ struct HipFail {
   const char *what;
 };
 
+// A failed status raised inside a level callback (the message is already set).
+struct StatusFail {
+  hsdc_status st;
+};
+
 #define HIPC(call)                                  \
   do {                                              \
     hipError_t e_ = (call);                         \
     if (e_ != hipSuccess) throw HipFail{e_, #call}; \
   } while (0)
 
-struct Level {
+// One level's workspace; T is the type of its cell-model terms and CG work
+// vectors (float only on an FP32 coarse level); states are FP64 on every level.
+template <class T>
+struct LevelT {
   Grid g{};
   Colloc co{};
-  Stages st{};
+  StagesT<T> st{};
   int P = 0;
   double *stim_w = nullptr;
   double *kface[3] = {nullptr, nullptr, nullptr};
   // CG workspace
-  double *cg_r[2] = {nullptr, nullptr}, *cg_w[2] = {nullptr, nullptr};
-  double *cg_s[2] = {nullptr, nullptr}, *cg_p = nullptr;
+  T *cg_r[2] = {nullptr, nullptr}, *cg_w[2] = {nullptr, nullptr};
+  T *cg_s[2] = {nullptr, nullptr}, *cg_p = nullptr;
   double *cg_part = nullptr;
   CgScalars *cg_sc = nullptr;       // [P][2]
   CgScalars *cg_sc_host = nullptr;  // [P][2]
@@ -67,11 +83,11 @@ struct Level {
   // PFASST
   double *U = nullptr;    // [P][NF][Np] start values of a Q sweep
   double *Sz = nullptr;   // coarse: copy of the restricted fine iterate
-  double *RI = nullptr;   // fine: time-restricted integrals [P][Mc][NF][Np]; coarse: restricted
-  double *D = nullptr;    // coarse scratch
+  double *RI = nullptr;   // fine: time-restricted integrals [P][Mc][NF][Np]; coarse: FAS term
   double *y0c = nullptr;  // coarse: restricted block start value [NF][Np]
   int cg_pred[16][MAXM];  // iteration budget per (sweep index, node)
 };
+using Level = LevelT<double>;
 
 // A diffusion solve whose outcome is checked later (budgeted mode).
 struct CgLogEntry {
@@ -105,7 +121,9 @@ struct hsdc_ctx {
   hipStream_t s = nullptr;
   hsdc_problem prob{};
   hsdc_method meth{};
-  Level L[2];
+  Level L[2];             // fine level and (FP64) coarse level
+  LevelT<float> Lf;       // coarse level when coarse_fp32
+  bool cf32 = false;
   int nlev = 1;
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
   double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices
@@ -145,6 +163,27 @@ hsdc_status fail(hsdc_ctx *c, hsdc_status st, const std::string &msg) {
   else
     g_free_error = msg;
   return st;
+}
+
+// Calls fn with the coarse level in its storage type.
+template <class Fn>
+void with_coarse(hsdc_ctx *c, Fn &&fn) {
+  if (c->cf32)
+    fn(c->Lf);
+  else
+    fn(c->L[1]);
+}
+
+// Relative tolerance of the diffusion solves on level lev (an FP32 coarse level
+// measures it against the warm start's residual).
+double level_rtol(const hsdc_ctx *c, int lev) {
+  if (lev == 0) return c->meth.cg_rtol;
+  if (c->meth.coarse_cg_rtol > 0) return c->meth.coarse_cg_rtol;
+  return c->cf32 ? 1e-5 : c->meth.cg_rtol;
+}
+
+int (&pred_table(hsdc_ctx *c, int lev))[16][MAXM] {
+  return (lev == 1 && c->cf32) ? c->Lf.cg_pred : c->L[lev].cg_pred;
 }
 
 // ---- kernel timing -----------------------------------------------------------
@@ -265,6 +304,9 @@ bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why)
   if (!std::isfinite(m->tol)) return why = "tol must be finite", false;
   if (!(m->cg_rtol > 0) || !(m->cg_rtol < 1)) return why = "cg_rtol must be in (0, 1)", false;
   if (m->cg_maxit < 1) return why = "cg_maxit must be >= 1", false;
+  if (m->coarse_fp32 != 0 && m->coarse_fp32 != 1) return why = "coarse_fp32 must be 0 or 1", false;
+  if (!std::isfinite(m->coarse_cg_rtol) || !(m->coarse_cg_rtol < 1))
+    return why = "coarse_cg_rtol must be finite and < 1", false;
   return true;
 }
 
@@ -285,7 +327,8 @@ Grid make_grid(const hsdc_problem &p, int nx, int ny, int nz, double dx) {
 
 // Per-node conductivity: face coefficient between p and p + e_axis is the
 // harmonic mean of the two node values over dx^2 chi Cm (0 on the last layer).
-void build_faces(hsdc_ctx *c, Level &L, const double *sigma_node_dev) {
+template <class T>
+void build_faces(hsdc_ctx *c, LevelT<T> &L, const double *sigma_node_dev) {
   const Grid &g = L.g;
   std::vector<double> s(g.N);
   HIPC(hipMemcpyAsync(s.data(), sigma_node_dev, g.N * sizeof(double), hipMemcpyDeviceToHost, c->s));
@@ -312,37 +355,39 @@ void build_faces(hsdc_ctx *c, Level &L, const double *sigma_node_dev) {
   L.g.kz = g.dim >= 3 ? L.kface[2] : nullptr;
 }
 
-void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc_for_RI) {
+template <class T>
+void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, int Mc_for_RI) {
   const int64_t Np = L.g.Np;
   L.P = P;
   L.st.Np = Np;
   L.st.M = M;
   L.st.Y = dalloc<double>(c, (size_t)P * L.st.sY());
-  L.st.G = dalloc<double>(c, (size_t)P * L.st.sY());
+  L.st.G = dalloc<T>(c, (size_t)P * L.st.sY());
   L.st.FV = dalloc<double>(c, (size_t)P * L.st.sFV());
   L.st.RH = dalloc<double>(c, (size_t)P * L.st.sRH());
-  L.st.L0 = dalloc<double>(c, (size_t)P * L.st.sL());
+  L.st.L0 = dalloc<T>(c, (size_t)P * L.st.sL());
   L.st.B = dalloc<double>(c, (size_t)P * Np);
   L.cg_nblk = cg_blocks(L.g, c->tune_cg_blocks);
   for (int k = 0; k < 2; ++k) {
-    L.cg_r[k] = dalloc<double>(c, (size_t)P * Np);
-    L.cg_w[k] = dalloc<double>(c, (size_t)P * Np);
-    L.cg_s[k] = dalloc<double>(c, (size_t)P * Np);
+    L.cg_r[k] = dalloc<T>(c, (size_t)P * Np);
+    L.cg_w[k] = dalloc<T>(c, (size_t)P * Np);
+    L.cg_s[k] = dalloc<T>(c, (size_t)P * Np);
   }
-  L.cg_p = dalloc<double>(c, (size_t)P * Np);
+  L.cg_p = dalloc<T>(c, (size_t)P * Np);
   L.cg_pstride = std::max(L.cg_nblk, node_blocks(L.g));
   L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
-  L.res_nblk = residual_blocks(L.g);
-  L.res_part = dalloc<double>(c, (size_t)P * 2 * L.res_nblk);
-  L.res_out = dalloc<double>(c, (size_t)2 * P);
-  L.res_out_host = halloc<double>(c, 2 * P);
+  if (!coarse_extras) {  // the residual is taken on the fine level only
+    L.res_nblk = residual_blocks(L.g);
+    L.res_part = dalloc<double>(c, (size_t)P * 2 * L.res_nblk);
+    L.res_out = dalloc<double>(c, (size_t)2 * P);
+    L.res_out_host = halloc<double>(c, 2 * P);
+  }
   L.U = dalloc<double>(c, (size_t)P * NF * Np);
   if (Mc_for_RI > 0) L.RI = dalloc<double>(c, (size_t)P * Mc_for_RI * NF * Np);
   if (coarse_extras) {
     L.Sz = dalloc<double>(c, (size_t)P * L.st.sY());
-    L.D = dalloc<double>(c, (size_t)P * L.st.sY());
     L.y0c = dalloc<double>(c, (size_t)NF * Np);
   }
   for (auto &row : L.cg_pred)
@@ -352,8 +397,9 @@ void alloc_level(hsdc_ctx *c, Level &L, int M, int P, bool coarse_extras, int Mc
 // ---------------------------------------------------------------------------
 // diffusion solve for node i of a sweep, slices [s0, s0+ns)
 // ---------------------------------------------------------------------------
-CgBatch make_batch(hsdc_ctx *c, Level &L, int s0, int ns, int i) {
-  CgBatch cb{};
+template <class T>
+CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i) {
+  CgBatchT<T> cb{};
   const int64_t Np = L.g.Np;
   cb.x = L.st.Y + s0 * L.st.sY() + (int64_t)i * L.st.sS();
   cb.sx = L.st.sY();
@@ -374,8 +420,12 @@ CgBatch make_batch(hsdc_ctx *c, Level &L, int s0, int ns, int i) {
   cb.nblk = L.cg_nblk;
   cb.nblk0 = node_blocks(L.g);  // r_0 and its partials come from the node update
   cb.a = L.co.dt * L.co.d[i - 1];
-  cb.tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
+  const double rt = level_rtol(c, lev);
+  cb.tol2 = rt * rt;
   cb.maxit = c->meth.cg_maxit;
+  // FP32 work vectors: solve the correction from the warm start to a relative
+  // accuracy, so that the solve error shrinks with the defect
+  cb.rel_r0 = (lev == 1 && c->cf32) ? 1 : 0;
   return cb;
 }
 
@@ -390,10 +440,9 @@ void flush_cg_log(hsdc_ctx *c) {
   HIPC(hipMemcpyAsync(c->cg_log, c->cg_dlog, c->cg_log_used * sizeof(CgScalars),
                       hipMemcpyDeviceToHost, c->s));
   HIPC(hipStreamSynchronize(c->s));
-  const double tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
   int fails = 0;
   for (const CgLogEntry &e : c->cg_pending) {
-    Level &L = c->L[e.lev];
+    const double rt = level_rtol(c, e.lev), tol2 = rt * rt;
     int used = 0;
     bool ok_all = true;
     for (int n = 0; n < e.ns; ++n) {
@@ -407,7 +456,7 @@ void flush_cg_log(hsdc_ctx *c) {
     }
     // budget = iterations needed + 2, lowered by at most one per check; doubled
     // after a miss (a spare no-op iteration costs far less than a recomputed step)
-    int &pred = L.cg_pred[e.row & 15][e.i - 1];
+    int &pred = pred_table(c, e.lev)[e.row & 15][e.i - 1];
     if (ok_all)
       pred = std::max(used + c->tune_cg_margin, pred - 1);
     else
@@ -418,9 +467,9 @@ void flush_cg_log(hsdc_ctx *c) {
   c->cg_fails += fails;
 }
 
-void cg_solve(hsdc_ctx *c, int lev, int s0, int ns, int i, int pred_row) {
-  Level &L = c->L[lev];
-  CgBatch cb = make_batch(c, L, s0, ns, i);
+template <class T>
+void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pred_row) {
+  CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
   const double nodes = (double)L.g.N * ns;
   PLAUNCH(c, PC_CGINIT, 16.0 * nodes, launch_cg_init(c->s, L.g, cb));
   int &pred = L.cg_pred[pred_row & 15][i - 1];
@@ -465,19 +514,19 @@ void cg_solve(hsdc_ctx *c, int lev, int s0, int ns, int i, int pred_row) {
 }
 
 // Reaction terms, Lambda(y_{n,0}) and K V of every stage of slices [s0, s0+ns).
-void evaluate_all(hsdc_ctx *c, int lev, int s0, int ns) {
-  Level &L = c->L[lev];
+template <class T>
+void evaluate_all(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns) {
   const hsdc_problem &p = c->prob;
   const int M = L.co.M;
   const double N = (double)L.g.N;
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N * ns,
-          launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+          launch_eval_stages<T>(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                              p.g_scale[2], s0, ns, 0, 1, c->step, L.st.L0, nullptr));
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns * M,
-          launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+          launch_eval_stages<T>(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                              p.g_scale[2], s0, ns, 1, M, c->step, nullptr, L.st.L0));
   PLAUNCH(c, PC_SPMV, 16.0 * (M + 1) * N * ns,
-          launch_spmv_stages(c->s, L.g, L.st, s0, ns, 0, M + 1));
+          launch_spmv_stages<T>(c->s, L.g, L.st, s0, ns, 0, M + 1));
   c->stats.ionic_evals += L.g.N * ns * (M + 1);
 }
 
@@ -493,9 +542,9 @@ void evaluate_all(hsdc_ctx *c, int lev, int s0, int ns) {
 //   (last sweep of a serial step, every coarse and burn-in sweep); otherwise
 //   the postcondition is the precondition for the new iterate.
 // ---------------------------------------------------------------------------
-void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const double *RI,
+template <class T>
+void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_src, const double *RI,
            int pred_row, bool drop_terms = false) {
-  Level &L = c->L[lev];
   const Colloc &co = L.co;
   const hsdc_problem &p = c->prob;
   const int M = co.M;
@@ -507,7 +556,7 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
     PLAUNCH(c, PC_COPY, 16.0 * NF * N * ns,
             launch_copy_fields(c->s, L.g.Np, L.st.Y + s0 * L.st.sY(), L.st.sY(), u_src,
                                (int64_t)NF * L.g.Np, NF, ns));
-    evaluate_all(c, lev, s0, ns);
+    evaluate_all(c, L, lev, s0, ns);
   }
   {
     const double per = spread ? (NF + 1 + NG + M * NF)
@@ -516,23 +565,23 @@ void sweep(hsdc_ctx *c, int lev, int s0, int ns, const double *u_src, const doub
             launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI, spread, c->stim[lev], step0));
   }
   for (int i = 1; i <= M; ++i) {
-    const CgBatch cb = make_batch(c, L, s0, ns, i);
-    const double per = (i == 1) ? 90.0 : (drop_terms ? 83.0 : 102.0);
+    const CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
+    const double per = ((i == 1) ? 90.0 : (drop_terms ? 83.0 : 102.0)) * sizeof(T) / 8.0;
     PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
             launch_node_update(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                                p.g_scale[2], s0, ns, i, step0, cb, drop_terms ? 0 : 1, spread));
     if (i > 1) c->stats.ionic_evals += N * ns;
-    cg_solve(c, lev, s0, ns, i, pred_row);
+    cg_solve(c, L, lev, s0, ns, i, pred_row);
   }
   if (lev == 0) c->spread_pending = false;
   if (!drop_terms) {
     // reaction terms and K V of the new iterate's last stage, for the next
     // sweep or the residual (stages 1..M-1 were stored by the node updates)
     PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns,
-            launch_eval_stages(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
+            launch_eval_stages<T>(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                                p.g_scale[2], s0, ns, M, 1, step0, nullptr, L.st.L0));
     c->stats.ionic_evals += N * ns;
-    PLAUNCH(c, PC_SPMV, 16.0 * M * N * ns, launch_spmv_stages(c->s, L.g, L.st, s0, ns, 1, M));
+    PLAUNCH(c, PC_SPMV, 16.0 * M * N * ns, launch_spmv_stages<T>(c->s, L.g, L.st, s0, ns, 1, M));
   }
   if (lev == 0)
     c->stats.sweeps += ns;
@@ -546,9 +595,9 @@ void begin_serial_step(hsdc_ctx *c) {
   const hsdc_problem &p = c->prob;
   const double N = (double)L.g.N;
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N,
-          launch_eval_stages(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0], p.g_scale[1],
+          launch_eval_stages<double>(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0], p.g_scale[1],
                              p.g_scale[2], 0, 1, 0, 1, c->step, L.st.L0, nullptr));
-  PLAUNCH(c, PC_SPMV, 16.0 * N, launch_spmv_stages(c->s, L.g, L.st, 0, 1, 0, 1));
+  PLAUNCH(c, PC_SPMV, 16.0 * N, launch_spmv_stages<double>(c->s, L.g, L.st, 0, 1, 0, 1));
   PLAUNCH(c, PC_COPY, 8.0 * (1 + L.co.M) * N, launch_copy_V_to_stages(c->s, L.g, L.st, 0, 1));
   c->spread_pending = true;
   c->stats.ionic_evals += L.g.N;
@@ -569,7 +618,7 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
   materialize(c);
   Level &L = c->L[0];
   const double *yb = c->pfasst ? c->y0blk : L.st.Y;  // serial: u = y_{n,0}
-  const int Mc = c->nlev == 2 ? c->L[1].co.M : 0;
+  const int Mc = c->nlev == 2 ? c->meth.M[1] : 0;
   double *RI = (want_RI && c->nlev == 2) ? L.RI : nullptr;
   {
     const double M = L.co.M;
@@ -595,32 +644,30 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
 // ---------------------------------------------------------------------------
 // PFASST (two levels)
 // ---------------------------------------------------------------------------
-void restrict_fine_to_coarse(hsdc_ctx *c) {
-  Level &F = c->L[0], &Cc = c->L[1];
-  const double bytes = 8.0 * F.P * NF *
-                       ((F.co.M + 1.0) * F.g.N + 2.0 * (Cc.co.M + 1.0) * Cc.g.N);
+template <class T>
+void restrict_fine_to_coarse(hsdc_ctx *c, LevelT<T> &Cc) {
+  Level &F = c->L[0];
+  const double bytes = 8.0 * F.P * NF * ((F.co.M + 1.0) * F.g.N + 2.0 * (Cc.co.M + 1.0) * Cc.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
           launch_restrict_stages(c->s, F.g, Cc.g, c->meth.space_coarsen, F.st.Y, F.st.sY(),
                                  F.co.M, c->Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
 }
 
-void coarse_correct_fine(hsdc_ctx *c) {
-  Level &F = c->L[0], &Cc = c->L[1];
-  // z_c - S z into D (3 coarse passes), then read D once and update the fine stages
-  const double bytes = 8.0 * F.P * NF *
-                       (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0) * F.g.N);
+template <class T>
+void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc) {
+  Level &F = c->L[0];
+  // z_c and S z read once at the coarse cells, fine stages read and written
+  const double bytes = 8.0 * F.P * NF * (2.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0) * F.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
           launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz,
-                                 Cc.st.sY(), Cc.co.M, c->Tt, F.co.M, F.st.Y, F.st.sY(), F.P,
-                                 Cc.D));
+                                 Cc.st.sY(), Cc.co.M, c->Tt, F.co.M, F.st.Y, F.st.sY(), F.P));
 }
 
 // start values u_n of a sweep over slices [s0, s0+ns) from the stage-M values
-// of slices n-1 (ends) and the level's block start value for n = 0
-void gather_starts(hsdc_ctx *c, int lev, int s0, int ns) {
-  Level &L = c->L[lev];
+// of slices n-1 (ends) and the block start value blk0 for n = 0
+template <class T>
+void gather_starts(hsdc_ctx *c, LevelT<T> &L, const double *blk0, int s0, int ns) {
   const int64_t sS = L.st.sS();
-  const double *blk0 = (lev == 0) ? c->y0blk : L.y0c;
   int n = s0;
   const double per = 16.0 * NF * L.g.N;
   if (n == 0) {
@@ -630,21 +677,21 @@ void gather_starts(hsdc_ctx *c, int lev, int s0, int ns) {
   if (n < s0 + ns)
     PLAUNCH(c, PC_COPY, per * (s0 + ns - n),
             launch_copy_fields(c->s, L.g.Np, L.U + n * sS, sS,
-                               L.st.Y + (n - 1) * L.st.sY() + (int64_t)L.co.M * sS, L.st.sY(),
-                               NF, s0 + ns - n));
+                               L.st.Y + (n - 1) * L.st.sY() + (int64_t)L.co.M * sS,
+                               L.st.sY(), NF, s0 + ns - n));
 }
 
 // Staggered coarse predictor: at stage s every slice n >= s takes one coarse
 // sweep (tau = 0) from the end value slice n-1 held after stage s-1.
-void burn_in(hsdc_ctx *c) {
-  Level &Cc = c->L[1];
+template <class T>
+void burn_in(hsdc_ctx *c, LevelT<T> &Cc) {
   const int P = Cc.P;
-  restrict_fine_to_coarse(c);
+  restrict_fine_to_coarse(c, Cc);
   for (int s = 0; s < P; ++s) {
-    gather_starts(c, 1, s, P - s);
-    sweep(c, 1, s, P - s, Cc.U + s * Cc.st.sS(), nullptr, 15, true);
+    gather_starts(c, Cc, Cc.y0c, s, P - s);
+    sweep(c, Cc, 1, s, P - s, Cc.U + s * Cc.st.sS(), nullptr, 15, true);
   }
-  coarse_correct_fine(c);
+  coarse_correct_fine(c, Cc);
 }
 
 void begin_block(hsdc_ctx *c) {
@@ -652,15 +699,16 @@ void begin_block(hsdc_ctx *c) {
   const int P = F.P;
   // spread y0 over every stage of every slice
   for (int j = 0; j <= F.co.M; ++j)
-    HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y + (int64_t)j * F.st.sS(), F.st.sY(), c->y0blk, 0,
-                            NF, P));
+    HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y + (int64_t)j * F.st.sS(), F.st.sY(),
+                            c->y0blk, 0, NF, P));
   if (c->nlev == 2) {
-    Level &Cc = c->L[1];
-    HIPC(launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, c->y0blk, 0, Cc.y0c, 0, NF,
-                                1));
-    if (P > 1 && c->meth.burn_in) burn_in(c);
+    with_coarse(c, [&](auto &Cc) {
+      HIPC(launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen,
+                                  c->y0blk, 0, Cc.y0c, 0, NF, 1));
+      if (P > 1 && c->meth.burn_in) burn_in(c, Cc);
+    });
   }
-  evaluate_all(c, 0, 0, P);
+  evaluate_all(c, F, 0, 0, P);
   c->block_ready = true;
   c->ri_fresh = false;
 }
@@ -668,32 +716,31 @@ void begin_block(hsdc_ctx *c) {
 hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
   Level &F = c->L[0];
   const int P = F.P;
-  if (c->nlev == 2) {
-    Level &Cc = c->L[1];
+  if (c->nlev == 2) with_coarse(c, [&](auto &Cc) {
     const int Mc = Cc.co.M;
     // tau (Algorithm 1): its rows i >= 1 are dt (S (A G)_f(z) - (A G)_c(S z))_i,
     // the row-0 and H parts cancel; the fine integrals come with the residual
     if (!c->ri_fresh) {
-      hsdc_status st = residual_pass(c, nullptr, true);
-      if (st != HSDC_OK) return st;
+      const hsdc_status st = residual_pass(c, nullptr, true);
+      if (st != HSDC_OK) throw StatusFail{st};
     }
     const int64_t sRIc = (int64_t)Mc * NF * Cc.g.Np;
     PLAUNCH(c, PC_TRANSFER, 8.0 * P * Mc * NF * ((double)F.g.N + Cc.g.N),
             launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
                                    (int64_t)Mc * NF * F.g.Np, Cc.RI, sRIc, Mc * NF, P));
-    restrict_fine_to_coarse(c);
-    evaluate_all(c, 1, 0, P);
+    restrict_fine_to_coarse(c, Cc);
+    evaluate_all(c, Cc, 1, 0, P);
     PLAUNCH(c, PC_FAS, 8.0 * (3.0 * Mc * NF + Mc + NG) * Cc.g.N * P,
             launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, 0, P, Cc.RI, sRIc));
     for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
-      gather_starts(c, 1, n, 1);
-      sweep(c, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14, true);
+      gather_starts(c, Cc, Cc.y0c, n, 1);
+      sweep(c, Cc, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14, true);
     }
-    coarse_correct_fine(c);
-  }
+    coarse_correct_fine(c, Cc);
+  });
   // Q^par on the fine level: start values from the (corrected) iterate
-  gather_starts(c, 0, 0, P);
-  sweep(c, 0, 0, P, F.U, nullptr, c->sweep_index++);
+  gather_starts(c, F, c->y0blk, 0, P);
+  sweep(c, F, 0, 0, P, F.U, nullptr, c->sweep_index++);
   c->stats.pfasst_iters += 1;
   std::vector<double> rel(P);
   hsdc_status st = residual_pass(c, rel.data(), c->nlev == 2);
@@ -716,6 +763,8 @@ template <class Fn>
 hsdc_status run_guarded(hsdc_ctx *c, Fn &&fn) {
   try {
     return fn();
+  } catch (const StatusFail &f) {
+    return f.st;
   } catch (const HipFail &h) {
     std::string m = std::string("HIP error in ") + h.what + ": " + hipGetErrorString(h.e);
     if (h.e == hipErrorOutOfMemory || h.e == hipErrorMemoryAllocation) return fail(c, HSDC_ENOMEM, m);
@@ -744,6 +793,7 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
   c->prob = *prob;
   c->meth = *meth;
   c->nlev = meth->levels;
+  c->cf32 = meth->levels == 2 && meth->coarse_fp32 != 0;
   c->pfasst = !(meth->levels == 1 && meth->P == 1);
   hsdc_status st = run_guarded(c, [&]() -> hsdc_status {
     const int P = meth->P;
@@ -772,24 +822,31 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
     }
     c->stim[0].w = F.stim_w;
     if (c->nlev == 2) {
-      Level &Cc = c->L[1];
       const int f = meth->space_coarsen;
       const int cnx = prob->nx > 1 ? prob->nx / f : 1;
       const int cny = prob->ny > 1 ? prob->ny / f : 1;
       const int cnz = prob->nz > 1 ? prob->nz / f : 1;
-      Cc.g = make_grid(*prob, cnx, cny, cnz, prob->dx * f);
-      if (!make_colloc(meth->M[1], meth->dt, Cc.co))
-        return fail(c, HSDC_EINVAL, "Radau node computation failed");
-      alloc_level(c, Cc, meth->M[1], P, true, Mc);
-      if (prob->sigma_node) build_faces(c, Cc, prob->sigma_node);  // f == 1 only
-      if (F.stim_w) {
-        Cc.stim_w = dalloc<double>(c, Cc.g.Np);
-        HIPC(launch_restrict_fields(c->s, F.g, Cc.g, f, F.stim_w, 0, Cc.stim_w, 0, 1, 1));
-      }
-      c->stim[1].w = Cc.stim_w;
+      bool ok = true;
+      with_coarse(c, [&](auto &Cc) {
+        Cc.g = make_grid(*prob, cnx, cny, cnz, prob->dx * f);
+        if (!make_colloc(meth->M[1], meth->dt, Cc.co)) {
+          ok = false;
+          return;
+        }
+        alloc_level(c, Cc, meth->M[1], P, true, Mc);
+        if (prob->sigma_node) build_faces(c, Cc, prob->sigma_node);  // f == 1 only
+        if (F.stim_w) {
+          Cc.stim_w = dalloc<double>(c, Cc.g.Np);
+          HIPC(launch_restrict_fields(c->s, F.g, Cc.g, f, F.stim_w, 0,
+                                      Cc.stim_w, 0, 1, 1));
+        }
+        c->stim[1].w = Cc.stim_w;
+      });
+      if (!ok) return fail(c, HSDC_EINVAL, "Radau node computation failed");
+      const Colloc &cco = c->cf32 ? c->Lf.co : c->L[1].co;
       std::vector<double> R((Mc + 1) * (meth->M[0] + 1)), T((meth->M[0] + 1) * (Mc + 1));
-      transfer_matrix(meth->M[0], F.co.c, Mc, Cc.co.c, R.data());
-      transfer_matrix(Mc, Cc.co.c, meth->M[0], F.co.c, T.data());
+      transfer_matrix(meth->M[0], F.co.c, Mc, cco.c, R.data());
+      transfer_matrix(Mc, cco.c, meth->M[0], F.co.c, T.data());
       c->Rt = dalloc<double>(c, R.size());
       c->Tt = dalloc<double>(c, T.size());
       HIPC(hipMemcpyAsync(c->Rt, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
@@ -828,7 +885,7 @@ hsdc_status hsdc_sdc_sweep(hsdc_ctx *c, int32_t level, int32_t slice, int32_t ns
   if (nsweeps < 0) return fail(c, HSDC_EINVAL, "nsweeps must be >= 0");
   return run_guarded(c, [&]() -> hsdc_status {
     for (int k = 0; k < nsweeps; ++k) {
-      sweep(c, 0, slice, 1, nullptr, nullptr, c->pfasst ? 13 : c->sweep_index++);
+      sweep(c, c->L[0], 0, slice, 1, nullptr, nullptr, c->pfasst ? 13 : c->sweep_index++);
       if (!c->pfasst) c->sweeps_done += 1;
     }
     if (nsweeps > 0) c->ri_fresh = false;
@@ -850,7 +907,7 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
         c->cg_fails = 0;
         while (c->sweeps_done < c->meth.max_iter) {
           const bool last = c->sweeps_done == c->meth.max_iter - 1;
-          sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
+          sweep(c, F, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
           c->sweeps_done += 1;
         }
         flush_cg_log(c);
@@ -861,13 +918,13 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
           begin_serial_step(c);
           while (c->sweeps_done < c->meth.max_iter) {
             const bool last = c->sweeps_done == c->meth.max_iter - 1;
-            sweep(c, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
+            sweep(c, F, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
             c->sweeps_done += 1;
           }
         }
         // y_{n+1} = y_{n,M}
-        HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0, F.st.Y + (int64_t)F.co.M * F.st.sS(), 0,
-                                NF, 1));
+        HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0,
+                                F.st.Y + (int64_t)F.co.M * F.st.sS(), 0, NF, 1));
         c->step += 1;
         c->stats.steps += 1;
         begin_serial_step(c);
@@ -910,35 +967,43 @@ static hsdc_status state_copy(hsdc_ctx *c, int32_t level, int32_t slice, int32_t
                               bool get) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
   if (level < 0 || level >= c->nlev) return fail(c, HSDC_EINVAL, "level out of range");
-  Level &L = c->L[level];
-  if (slice < 0 || slice >= L.P) return fail(c, HSDC_EINVAL, "slice out of range");
-  if (node < 0 || node > L.co.M) return fail(c, HSDC_EINVAL, "node out of range");
+  const int P = c->L[0].P;
+  const int Ml = (level == 1 && c->cf32) ? c->Lf.co.M : c->L[level].co.M;
+  if (slice < 0 || slice >= P) return fail(c, HSDC_EINVAL, "slice out of range");
+  if (node < 0 || node > Ml) return fail(c, HSDC_EINVAL, "node out of range");
   if (!dev) return fail(c, HSDC_EINVAL, "buffer is NULL");
   return run_guarded(c, [&]() -> hsdc_status {
     if (node != 0 || !get) materialize(c);
-    double *base = L.st.Y + slice * L.st.sY() + (int64_t)node * L.st.sS();
-    for (int f = 0; f < NF; ++f) {
-      if (get)
-        HIPC(hipMemcpyAsync(dev + f * L.g.N, base + f * L.g.Np, L.g.N * sizeof(double),
-                            hipMemcpyDeviceToDevice, c->s));
-      else
-        HIPC(hipMemcpyAsync(base + f * L.g.Np, dev + f * L.g.N, L.g.N * sizeof(double),
-                            hipMemcpyDeviceToDevice, c->s));
-    }
+    auto copy = [&](auto &L) {
+      double *base = L.st.Y + slice * L.st.sY() + (int64_t)node * L.st.sS();
+      for (int f = 0; f < NF; ++f) {
+        if (get)
+          HIPC(hipMemcpyAsync(dev + f * L.g.N, base + f * L.g.Np, L.g.N * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->s));
+        else
+          HIPC(hipMemcpyAsync(base + f * L.g.Np, dev + f * L.g.N, L.g.N * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->s));
+      }
+      if (!get && c->pfasst) evaluate_all(c, L, level, slice, 1);
+    };
+    if (level == 1)
+      with_coarse(c, copy);
+    else
+      copy(c->L[0]);
     if (!get) {
       c->ri_fresh = false;
       // keep the cached stage terms consistent with the new state
+      Level &F = c->L[0];
       if (c->pfasst) {
         if (level == 0 && node == 0 && slice == 0) {
           for (int f = 0; f < NF; ++f)
-            HIPC(hipMemcpyAsync(c->y0blk + f * L.g.Np, dev + f * L.g.N, L.g.N * sizeof(double),
+            HIPC(hipMemcpyAsync(c->y0blk + f * F.g.Np, dev + f * F.g.N, F.g.N * sizeof(double),
                                 hipMemcpyDeviceToDevice, c->s));
         }
-        evaluate_all(c, level, slice, 1);
       } else if (node == 0) {
         begin_serial_step(c);
       } else {
-        evaluate_all(c, 0, 0, 1);
+        evaluate_all(c, F, 0, 0, 1);
       }
     }
     HIPC(hipStreamSynchronize(c->s));

@@ -1,5 +1,6 @@
 // ttp06_device.h -- ten Tusscher-Panfilov 2006 epicardial cell model as
-// device functions, one mesh node per lane, FP64.
+// device functions, one mesh node per lane, templated on the arithmetic type
+// (double on the fine level, float on an FP32 coarse level).
 //
 // The paper integrates this model (m1 = 6 auxiliary, m2 = 12 gating variables,
 // Sec. 5 model setup) without printing it; the equations follow the model's
@@ -45,134 +46,135 @@ __constant__ double kRest[19] = {
     0.00172, 0.7444, 0.7045, 0.00621, 0.4712, 0.0095,
     2.42e-8, 0.999998, 3.373e-5, 0.7888, 0.9755, 0.9953};
 
-__device__ __forceinline__ double logistic(double x) { return 1.0 / (1.0 + exp(x)); }
+template <class R>
+__device__ __forceinline__ R logistic(R x) { return R(1) / (R(1) + exp(x)); }
 
 // Steady state and time constant of every gate; calls sink(g, w_inf, tau)
 // for g = 0..11 in state order (m, h, j, xr1, xr2, xs, r, s, d, f, f2, fCass).
-template <class Sink>
-__device__ __forceinline__ void gates(double V, double Ca_ss, Sink &&sink) {
+template <class R, class Sink>
+__device__ __forceinline__ void gates(R V, R Ca_ss, Sink &&sink) {
   {  // m
-    const double s = logistic((-56.86 - V) / 9.03);
-    const double am = logistic((-60.0 - V) / 5.0);
-    const double bm = 0.1 * logistic((V + 35.0) / 5.0) + 0.1 * logistic((V - 50.0) / 200.0);
+    const R s = logistic((-R(56.86) - V) / R(9.03));
+    const R am = logistic((-R(60.0) - V) / R(5.0));
+    const R bm = R(0.1) * logistic((V + R(35.0)) / R(5.0)) + R(0.1) * logistic((V - R(50.0)) / R(200.0));
     sink(0, s * s, am * bm);
   }
-  const double sh = logistic((V + 71.55) / 7.43);
-  const double hj_inf = sh * sh;
-  if (V < -40.0) {
-    const double ah = 0.057 * exp(-(V + 80.0) / 6.8);
-    const double bh = 2.7 * exp(0.079 * V) + 3.1e5 * exp(0.3485 * V);
-    sink(1, hj_inf, 1.0 / (ah + bh));
-    const double aj = (-2.5428e4 * exp(0.2444 * V) - 6.948e-6 * exp(-0.04391 * V)) * (V + 37.78) /
-                      (1.0 + exp(0.311 * (V + 79.23)));
-    const double bj = 0.02424 * exp(-0.01052 * V) / (1.0 + exp(-0.1378 * (V + 40.14)));
-    sink(2, hj_inf, 1.0 / (aj + bj));
+  const R sh = logistic((V + R(71.55)) / R(7.43));
+  const R hj_inf = sh * sh;
+  if (V < -R(40.0)) {
+    const R ah = R(0.057) * exp(-(V + R(80.0)) / R(6.8));
+    const R bh = R(2.7) * exp(R(0.079) * V) + R(3.1e5) * exp(R(0.3485) * V);
+    sink(1, hj_inf, R(1.0) / (ah + bh));
+    const R aj = (-R(2.5428e4) * exp(R(0.2444) * V) - R(6.948e-6) * exp(-R(0.04391) * V)) * (V + R(37.78)) /
+                      (R(1.0) + exp(R(0.311) * (V + R(79.23))));
+    const R bj = R(0.02424) * exp(-R(0.01052) * V) / (R(1.0) + exp(-R(0.1378) * (V + R(40.14))));
+    sink(2, hj_inf, R(1.0) / (aj + bj));
   } else {
-    const double bh = 0.77 / (0.13 * (1.0 + exp(-(V + 10.66) / 11.1)));
-    sink(1, hj_inf, 1.0 / bh);
-    const double bj = 0.6 * exp(0.057 * V) / (1.0 + exp(-0.1 * (V + 32.0)));
-    sink(2, hj_inf, 1.0 / bj);
+    const R bh = R(0.77) / (R(0.13) * (R(1.0) + exp(-(V + R(10.66)) / R(11.1))));
+    sink(1, hj_inf, R(1.0) / bh);
+    const R bj = R(0.6) * exp(R(0.057) * V) / (R(1.0) + exp(-R(0.1) * (V + R(32.0))));
+    sink(2, hj_inf, R(1.0) / bj);
   }
-  sink(3, logistic((-26.0 - V) / 7.0),
-       (450.0 * logistic((-45.0 - V) / 10.0)) * (6.0 * logistic((V + 30.0) / 11.5)));
-  sink(4, logistic((V + 88.0) / 24.0),
-       (3.0 * logistic((-60.0 - V) / 20.0)) * (1.12 * logistic((V - 60.0) / 20.0)));
+  sink(3, logistic((-R(26.0) - V) / R(7.0)),
+       (R(450.0) * logistic((-R(45.0) - V) / R(10.0))) * (R(6.0) * logistic((V + R(30.0)) / R(11.5))));
+  sink(4, logistic((V + R(88.0)) / R(24.0)),
+       (R(3.0) * logistic((-R(60.0) - V) / R(20.0))) * (R(1.12) * logistic((V - R(60.0)) / R(20.0))));
   {  // xs
-    const double axs = 1400.0 / sqrt(1.0 + exp((5.0 - V) / 6.0));
-    const double bxs = logistic((V - 35.0) / 15.0);
-    sink(5, logistic((-5.0 - V) / 14.0), axs * bxs + 80.0);
+    const R axs = R(1400.0) / sqrt(R(1.0) + exp((R(5.0) - V) / R(6.0)));
+    const R bxs = logistic((V - R(35.0)) / R(15.0));
+    sink(5, logistic((-R(5.0) - V) / R(14.0)), axs * bxs + R(80.0));
   }
   {  // r, s (epicardium)
-    const double v40 = V + 40.0, v45 = V + 45.0;
-    sink(6, logistic((20.0 - V) / 6.0), 9.5 * exp(-(v40 * v40) / 1800.0) + 0.8);
-    sink(7, logistic((V + 20.0) / 5.0),
-         85.0 * exp(-(v45 * v45) / 320.0) + 5.0 * logistic((V - 20.0) / 5.0) + 3.0);
+    const R v40 = V + R(40.0), v45 = V + R(45.0);
+    sink(6, logistic((R(20.0) - V) / R(6.0)), R(9.5) * exp(-(v40 * v40) / R(1800.0)) + R(0.8));
+    sink(7, logistic((V + R(20.0)) / R(5.0)),
+         R(85.0) * exp(-(v45 * v45) / R(320.0)) + R(5.0) * logistic((V - R(20.0)) / R(5.0)) + R(3.0));
   }
   {  // d
-    const double ad = 1.4 * logistic((-35.0 - V) / 13.0) + 0.25;
-    const double bd = 1.4 * logistic((V + 5.0) / 5.0);
-    const double gd = logistic((50.0 - V) / 20.0);
-    sink(8, logistic((-8.0 - V) / 7.5), ad * bd + gd);
+    const R ad = R(1.4) * logistic((-R(35.0) - V) / R(13.0)) + R(0.25);
+    const R bd = R(1.4) * logistic((V + R(5.0)) / R(5.0));
+    const R gd = logistic((R(50.0) - V) / R(20.0));
+    sink(8, logistic((-R(8.0) - V) / R(7.5)), ad * bd + gd);
   }
   {  // f, f2
-    const double v27 = V + 27.0, v25 = V + 25.0;
-    sink(9, logistic((V + 20.0) / 7.0),
-         1102.5 * exp(-(v27 * v27) / 225.0) + 200.0 * logistic((13.0 - V) / 10.0) +
-             180.0 * logistic((V + 30.0) / 10.0) + 20.0);
-    sink(10, 0.67 * logistic((V + 35.0) / 7.0) + 0.33,
-         600.0 * exp(-(v25 * v25) / 170.0) + 31.0 * logistic((25.0 - V) / 10.0) +
-             16.0 * logistic((V + 30.0) / 10.0));
+    const R v27 = V + R(27.0), v25 = V + R(25.0);
+    sink(9, logistic((V + R(20.0)) / R(7.0)),
+         R(1102.5) * exp(-(v27 * v27) / R(225.0)) + R(200.0) * logistic((R(13.0) - V) / R(10.0)) +
+             R(180.0) * logistic((V + R(30.0)) / R(10.0)) + R(20.0));
+    sink(10, R(0.67) * logistic((V + R(35.0)) / R(7.0)) + R(0.33),
+         R(600.0) * exp(-(v25 * v25) / R(170.0)) + R(31.0) * logistic((R(25.0) - V) / R(10.0)) +
+             R(16.0) * logistic((V + R(30.0)) / R(10.0)));
   }
   {  // fCass
-    const double q = (Ca_ss / 0.05) * (Ca_ss / 0.05);
-    sink(11, 0.6 / (1.0 + q) + 0.4, 80.0 / (1.0 + q) + 2.0);
+    const R q = (Ca_ss / R(0.05)) * (Ca_ss / R(0.05));
+    sink(11, R(0.6) / (R(1.0) + q) + R(0.4), R(80.0) / (R(1.0) + q) + R(2.0));
   }
 }
 
 // Total ionic current I_ion (pA/pF) and the auxiliary derivatives h_a
 // (Ca_i, Ca_SR, Ca_ss, Na_i, K_i, Rbar).  gs scales G_Na, G_CaL, G_Kr.
-__device__ __forceinline__ void currents(const double *y, double gs0, double gs1, double gs2,
-                                         double &I_ion, double *ha) {
-  const double V = y[0], Ca_i = y[1], Ca_sr = y[2], Ca_ss = y[3], Na_i = y[4], K_i = y[5];
-  const double Rbar = y[6];
-  const double m = y[7], h = y[8], jg = y[9], xr1 = y[10], xr2 = y[11], xs = y[12];
-  const double r = y[13], s = y[14], d = y[15], f = y[16], f2 = y[17], fcass = y[18];
+template <class R>
+__device__ __forceinline__ void currents(const R *y, R gs0, R gs1, R gs2, R &I_ion, R *ha) {
+  const R V = y[0], Ca_i = y[1], Ca_sr = y[2], Ca_ss = y[3], Na_i = y[4], K_i = y[5];
+  const R Rbar = y[6];
+  const R m = y[7], h = y[8], jg = y[9], xr1 = y[10], xr2 = y[11], xs = y[12];
+  const R r = y[13], s = y[14], d = y[15], f = y[16], f2 = y[17], fcass = y[18];
 
-  const double E_Na = kRTF * log(kNao / Na_i);
-  const double E_K = kRTF * log(kKo / K_i);
-  const double E_Ks = kRTF * log((kKo + kPKNa * kNao) / (K_i + kPKNa * Na_i));
-  const double E_Ca = 0.5 * kRTF * log(kCao / Ca_i);
+  const R E_Na = R(kRTF) * log(R(kNao) / Na_i);
+  const R E_K = R(kRTF) * log(R(kKo) / K_i);
+  const R E_Ks = R(kRTF) * log((R(kKo) + R(kPKNa) * R(kNao)) / (K_i + R(kPKNa) * Na_i));
+  const R E_Ca = R(0.5) * R(kRTF) * log(R(kCao) / Ca_i);
 
-  const double I_Na = gs0 * kGNa * (m * m * m) * h * jg * (V - E_Na);
-  const double vek = V - E_K;
-  const double a_k1 = 0.1 / (1.0 + exp(0.06 * (vek - 200.0)));
-  const double b_k1 = (3.0 * exp(0.0002 * (vek + 100.0)) + exp(0.1 * (vek - 10.0))) /
-                      (1.0 + exp(-0.5 * vek));
-  const double sq = sqrt(kKo / 5.4);
-  const double I_K1 = kGK1 * sq * (a_k1 / (a_k1 + b_k1)) * vek;
-  const double I_to = kGto * r * s * vek;
-  const double I_Kr = gs2 * kGKr * sq * xr1 * xr2 * vek;
-  const double I_Ks = kGKs * xs * xs * (V - E_Ks);
+  const R I_Na = gs0 * R(kGNa) * (m * m * m) * h * jg * (V - E_Na);
+  const R vek = V - E_K;
+  const R a_k1 = R(0.1) / (R(1.0) + exp(R(0.06) * (vek - R(200.0))));
+  const R b_k1 = (R(3.0) * exp(R(0.0002) * (vek + R(100.0))) + exp(R(0.1) * (vek - R(10.0)))) /
+                      (R(1.0) + exp(-R(0.5) * vek));
+  const R sq = sqrt(R(kKo) / R(5.4));
+  const R I_K1 = R(kGK1) * sq * (a_k1 / (a_k1 + b_k1)) * vek;
+  const R I_to = R(kGto) * r * s * vek;
+  const R I_Kr = gs2 * R(kGKr) * sq * xr1 * xr2 * vek;
+  const R I_Ks = R(kGKs) * xs * xs * (V - E_Ks);
   // L-type: (V - 15)/(e^u - 1) with u = 2 (V - 15)/RTF is (RTF/2) u/(e^u - 1),
   // written through expm1 so that u = 0 is regular.
-  const double u = 2.0 * (V - 15.0) / kRTF;
-  const double ratio = (u == 0.0) ? 1.0 : expm1(u) / u;
-  const double I_CaL = gs1 * kGCaL * d * f * f2 * fcass * 4.0 * kF * (0.5 / ratio) *
-                       (0.25 * Ca_ss * exp(u) - kCao);
-  const double vfrt = V / kRTF;
-  const double e_g = exp(kGammaNaCa * vfrt), e_g1 = exp((kGammaNaCa - 1.0) * vfrt);
-  const double nai3 = Na_i * Na_i * Na_i;
-  const double I_NaCa =
-      kNaCa * (e_g * nai3 * kCao - e_g1 * (kNao * kNao * kNao) * Ca_i * kAlphaNaCa) /
-      ((kKmNai * kKmNai * kKmNai + kNao * kNao * kNao) * (kKmCa + kCao) * (1.0 + kKsat * e_g1));
-  const double I_NaK = kPNaK * kKo / (kKo + kKmK) * Na_i / (Na_i + kKmNa) /
-                       (1.0 + 0.1245 * exp(-0.1 * vfrt) + 0.0353 * exp(-vfrt));
-  const double I_pCa = kGpCa * Ca_i / (kKpCa + Ca_i);
-  const double I_pK = kGpK * vek / (1.0 + exp((25.0 - V) / 5.98));
-  const double I_bNa = kGbNa * (V - E_Na);
-  const double I_bCa = kGbCa * (V - E_Ca);
+  const R u = R(2.0) * (V - R(15.0)) / R(kRTF);
+  const R ratio = (u == R(0.0)) ? R(1.0) : expm1(u) / u;
+  const R I_CaL = gs1 * R(kGCaL) * d * f * f2 * fcass * R(4.0) * R(kF) * (R(0.5) / ratio) *
+                       (R(0.25) * Ca_ss * exp(u) - R(kCao));
+  const R vfrt = V / R(kRTF);
+  const R e_g = exp(R(kGammaNaCa) * vfrt), e_g1 = exp((R(kGammaNaCa) - R(1.0)) * vfrt);
+  const R nai3 = Na_i * Na_i * Na_i;
+  const R I_NaCa =
+      R(kNaCa) * (e_g * nai3 * R(kCao) - e_g1 * (R(kNao) * R(kNao) * R(kNao)) * Ca_i * R(kAlphaNaCa)) /
+      ((R(kKmNai) * R(kKmNai) * R(kKmNai) + R(kNao) * R(kNao) * R(kNao)) * (R(kKmCa) + R(kCao)) * (R(1.0) + R(kKsat) * e_g1));
+  const R I_NaK = R(kPNaK) * R(kKo) / (R(kKo) + R(kKmK)) * Na_i / (Na_i + R(kKmNa)) /
+                       (R(1.0) + R(0.1245) * exp(-R(0.1) * vfrt) + R(0.0353) * exp(-vfrt));
+  const R I_pCa = R(kGpCa) * Ca_i / (R(kKpCa) + Ca_i);
+  const R I_pK = R(kGpK) * vek / (R(1.0) + exp((R(25.0) - V) / R(5.98)));
+  const R I_bNa = R(kGbNa) * (V - E_Na);
+  const R I_bCa = R(kGbCa) * (V - E_Ca);
   I_ion = I_Na + I_K1 + I_to + I_Kr + I_Ks + I_CaL + I_NaCa + I_NaK + I_pCa + I_pK + I_bNa + I_bCa;
 
-  const double k_casr = kMaxSR - (kMaxSR - kMinSR) / (1.0 + (kEC / Ca_sr) * (kEC / Ca_sr));
-  const double k1 = kK1p / k_casr, k2 = kK2p * k_casr;
-  const double css2 = Ca_ss * Ca_ss;
-  const double O = k1 * css2 * Rbar / (kK3 + k1 * css2);
-  const double I_rel = kVrel * O * (Ca_sr - Ca_ss);
-  const double I_up = kVmaxUp / (1.0 + (kKup * kKup) / (Ca_i * Ca_i));
-  const double I_leak = kVleak * (Ca_sr - Ca_i);
-  const double I_xfer = kVxfer * (Ca_ss - Ca_i);
-  const double ci_k = Ca_i + kKbufc, csr_k = Ca_sr + kKbufsr, css_k = Ca_ss + kKbufss;
-  const double buf_c = 1.0 / (1.0 + kBufc * kKbufc / (ci_k * ci_k));
-  const double buf_sr = 1.0 / (1.0 + kBufsr * kKbufsr / (csr_k * csr_k));
-  const double buf_ss = 1.0 / (1.0 + kBufss * kKbufss / (css_k * css_k));
-  const double cvf = kCap / (kVc * kF);
-  ha[0] = buf_c * ((I_leak - I_up) * kVsr / kVc + I_xfer -
-                   (I_bCa + I_pCa - 2.0 * I_NaCa) * kCap / (2.0 * kVc * kF));
+  const R k_casr = R(kMaxSR) - (R(kMaxSR) - R(kMinSR)) / (R(1.0) + (R(kEC) / Ca_sr) * (R(kEC) / Ca_sr));
+  const R k1 = R(kK1p) / k_casr, k2 = R(kK2p) * k_casr;
+  const R css2 = Ca_ss * Ca_ss;
+  const R O = k1 * css2 * Rbar / (R(kK3) + k1 * css2);
+  const R I_rel = R(kVrel) * O * (Ca_sr - Ca_ss);
+  const R I_up = R(kVmaxUp) / (R(1.0) + (R(kKup) * R(kKup)) / (Ca_i * Ca_i));
+  const R I_leak = R(kVleak) * (Ca_sr - Ca_i);
+  const R I_xfer = R(kVxfer) * (Ca_ss - Ca_i);
+  const R ci_k = Ca_i + R(kKbufc), csr_k = Ca_sr + R(kKbufsr), css_k = Ca_ss + R(kKbufss);
+  const R buf_c = R(1.0) / (R(1.0) + R(kBufc) * R(kKbufc) / (ci_k * ci_k));
+  const R buf_sr = R(1.0) / (R(1.0) + R(kBufsr) * R(kKbufsr) / (csr_k * csr_k));
+  const R buf_ss = R(1.0) / (R(1.0) + R(kBufss) * R(kKbufss) / (css_k * css_k));
+  const R cvf = R(kCap) / (R(kVc) * R(kF));
+  ha[0] = buf_c * ((I_leak - I_up) * R(kVsr) / R(kVc) + I_xfer -
+                   (I_bCa + I_pCa - R(2.0) * I_NaCa) * R(kCap) / (R(2.0) * R(kVc) * R(kF)));
   ha[1] = buf_sr * (I_up - (I_rel + I_leak));
-  ha[2] = buf_ss * (-I_CaL * kCap / (2.0 * kVss * kF) + I_rel * kVsr / kVss - I_xfer * kVc / kVss);
-  ha[3] = -(I_Na + I_bNa + 3.0 * I_NaK + 3.0 * I_NaCa) * cvf;
-  ha[4] = -(I_K1 + I_to + I_Kr + I_Ks - 2.0 * I_NaK + I_pK) * cvf;
-  ha[5] = -k2 * Ca_ss * Rbar + kK4 * (1.0 - Rbar);
+  ha[2] = buf_ss * (-I_CaL * R(kCap) / (R(2.0) * R(kVss) * R(kF)) + I_rel * R(kVsr) / R(kVss) - I_xfer * R(kVc) / R(kVss));
+  ha[3] = -(I_Na + I_bNa + R(3.0) * I_NaK + R(3.0) * I_NaCa) * cvf;
+  ha[4] = -(I_K1 + I_to + I_Kr + I_Ks - R(2.0) * I_NaK + I_pK) * cvf;
+  ha[5] = -k2 * Ca_ss * Rbar + R(kK4) * (R(1.0) - Rbar);
 }
 
 }  // namespace ttp06

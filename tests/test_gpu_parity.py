@@ -237,6 +237,44 @@ def test_pfasst_converges_to_serial_collocation():
     assert np.max(np.abs(g - y)) < 1e-11 * np.max(np.abs(y))
 
 
+@pytest.mark.parametrize("dims,coarsen", [((8, 6, 4), 2), ((16,), 1)])
+def test_pfasst_fp32_coarse_converges_to_serial_collocation(dims, coarsen):
+    """Coarse level in FP32 (cell model, sweep, CG vectors): the fixed point is
+    still the FP64 fine collocation solution.  PFASST iterated to stagnation
+    matches serial collocation (oracle) to 1e-8 per field, and reaches a
+    residual of 1e-7 in at most three iterations more than with an FP64 coarse
+    level."""
+    P = 4
+    Mf, Mc = (6, 3) if coarsen == 2 else (4, 2)
+    w, h, y0, m = _pfasst_case(dims, Mf, Mc, coarsen, P, 0.1)
+
+    def run(fp32):
+        m.coarse_fp32 = int(fp32)
+        m.tol, m.max_iter = 1e-10, 80
+        ctx = H.Context(lib_problem(w), m, dev(y0))
+        hist = []
+        for _ in range(80):
+            res, conv = ctx.pfasst_iter()
+            hist.append(float(np.max(res)))
+            if conv or (len(hist) > 8 and hist[-1] >= 0.9 * hist[-4]):
+                break
+        g = host(ctx.get_state(0, P - 1, Mf))
+        ctx.destroy()
+        return g, hist
+
+    g32, h32 = run(True)
+    _, h64 = run(False)
+    assert np.all(np.isfinite(g32))
+    y = y0
+    for n in range(P):
+        Y, _ = collocation_solve(h.levels[0], n, y, tol=1e-14)
+        y = Y[-1]
+    assert np.max(field_errors(g32, y)) < 1e-8, (np.max(field_errors(g32, y)), h32)
+    k32 = next(k for k, r in enumerate(h32) if r < 1e-7)
+    k64 = next(k for k, r in enumerate(h64) if r < 1e-7)
+    assert k32 <= k64 + 3, (h32, h64)
+
+
 def test_pfasst_advance_blocks():
     """hsdc_advance in PFASST mode: two blocks iterated to tol, chained."""
     from oracle.pfasst import run_pfasst
