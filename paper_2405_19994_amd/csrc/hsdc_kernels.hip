@@ -1001,17 +1001,19 @@ __device__ __forceinline__ Children children(const Grid &gf, const Grid &gc, int
   return ch;
 }
 
-// Stage loops run to the compile-time maximum with predication, so the per-node
-// stage values stay in registers.
+// One thread per (node, field): the field is the grid's y index.  Stage loops
+// run to the compile-time maximum with predication, so the per-node stage
+// values stay in registers.
 __global__ void __launch_bounds__(BLOCK)
 k_restrict_stages(Grid gf, Grid gc, int scf, const double *Yf, int64_t sYf, int Mf,
                   const double *Rt, int Mc, double *Yc, int64_t sYc, double *Yc2) {
   const int64_t pc = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (pc >= gc.N) return;
   const int n = blockIdx.z;
+  const int f = blockIdx.y;
   const Children ch = children(gf, gc, pc, scf);
   const double inv = 1.0 / ch.n;
-  for (int f = 0; f < NF; ++f) {
+  {
     double av[MAXM + 1];
 #pragma unroll
     for (int l = 0; l <= MAXM; ++l) {
@@ -1038,7 +1040,7 @@ k_restrict_stages(Grid gf, Grid gc, int scf, const double *Yf, int64_t sYf, int 
 hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *Yf, int64_t sYf, int Mf, const double *Rt,
                                   int Mc, double *Yc, int64_t sYc, double *Yc_copy, int nslices) {
-  dim3 grid(nblocks(gc.N), 1, nslices);
+  dim3 grid(nblocks(gc.N), NF, nslices);
   hipLaunchKernelGGL(k_restrict_stages, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, Yf, sYf,
                      Mf, Rt, Mc, Yc, sYc, Yc_copy);
   return hipGetLastError();
@@ -1050,19 +1052,19 @@ k_restrict_fields(Grid gf, Grid gc, int scf, const double *src, int64_t ssrc, do
   const int64_t pc = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (pc >= gc.N) return;
   const int n = blockIdx.z;
+  const int r = blockIdx.y;  // one row per grid row
   const Children ch = children(gf, gc, pc, scf);
   const double inv = 1.0 / ch.n;
-  for (int r = 0; r < nrows; ++r) {
-    double s = 0.0;
-    for (int k = 0; k < ch.n; ++k) s += src[n * ssrc + (int64_t)r * gf.Np + ch.idx[k]];
-    dst[n * sdst + (int64_t)r * gc.Np + pc] = s * inv;
-  }
+  double s = 0.0;
+  for (int k = 0; k < ch.n; ++k) s += src[n * ssrc + (int64_t)r * gf.Np + ch.idx[k]];
+  dst[n * sdst + (int64_t)r * gc.Np + pc] = s * inv;
 }
 
 hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *src, int64_t ssrc, double *dst, int64_t sdst,
                                   int nrows, int nslices) {
-  dim3 grid(nblocks(gc.N), 1, nslices);
+  if (nrows <= 0 || nslices <= 0) return hipSuccess;
+  dim3 grid(nblocks(gc.N), nrows, nslices);
   hipLaunchKernelGGL(k_restrict_fields, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, src,
                      ssrc, dst, sdst, nrows);
   return hipGetLastError();
@@ -1117,7 +1119,8 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz,
           ++nn;
         }
   }
-  for (int f = 0; f < NF; ++f) {
+  const int f = blockIdx.y;
+  {
     double dc[MAXM + 1];
 #pragma unroll
     for (int j = 0; j <= MAXM; ++j) {
@@ -1146,7 +1149,7 @@ hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc,
                                   const double *Yc, const double *Sz, int64_t sYc, int Mc,
                                   const double *Tt, int Mf, double *Yf, int64_t sYf,
                                   int nslices) {
-  hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks(gf.N), 1, nslices), dim3(BLOCK), 0, s,
+  hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks(gf.N), NF, nslices), dim3(BLOCK), 0, s,
                      gf, gc, sc_factor, Yc, Sz, sYc, Mc, Tt, Mf, Yf, sYf);
   return hipGetLastError();
 }
