@@ -20,6 +20,13 @@ swept to its collocation solution (K = 40), and serial hybrid SDC is timed
 with the fewest sweeps per step that reach the same error.
 
     python bench.py --workload slab3d [--blocks 2] [--coarsen 2] [--tol 1e-9]
+
+With --workload batch2d: 64 independent 2D tissues (sides uniform in 64..512,
+per-node lognormal sigma, an 8 x 8 stimulus patch each; M 4, K 4, dt 0.05 ms)
+advanced as one ragged batch, every launch covering every tissue; reported
+beside the same tissues stepped one context at a time.
+
+    python bench.py --workload batch2d [--steps 50]
 """
 import argparse
 import json
@@ -41,7 +48,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("slab2d", "slab3d"), default="slab2d")
+    ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d"), default="slab2d")
+    ap.add_argument("--tissues", type=int, default=64, help="batch2d: tissues in the batch")
     ap.add_argument("--blocks", type=int, default=2, help="slab3d: PFASST blocks timed")
     ap.add_argument("--coarsen", type=int, choices=(1, 2), default=2,
                     help="slab3d: space coarsening factor of the coarse level")
@@ -229,6 +237,96 @@ def bench_slab3d(a):
     print(json.dumps(out))
 
 
+def bench_batch2d(a):
+    """64 independent 2D tissues (sides uniform in 64..512, per-node lognormal
+    sigma, an 8 x 8 stimulus patch each; M 4, K 4, dt 0.05 ms) advanced by
+    serial hybrid SDC as one batch (every launch covers every tissue), against
+    the same tissues stepped one context at a time."""
+    import torch
+
+    import synthetic_inputs as si
+    from paper_2405_19994_amd import hsdc as H
+
+    ws = si.batch2d_tissues(a.tissues, seed=0)
+    steps = a.steps if a.steps != 400 else 50
+    dev = torch.device("cuda:0")
+
+    def t(x):
+        return torch.tensor(x, dtype=torch.float64, device=dev)
+
+    probs = [H.make_problem(w["dims"], w["dx"], w["sigma"], t(w["sigma_node"]), w["chi"], w["Cm"],
+                            (1, 1, 1), t(w["stim_w"]), w["stim_amp"], w["stim_t0"], w["stim_dur"])
+             for w in ws]
+    m = H.make_method(M=ws[0]["M"], dt=ws[0]["dt"], max_iter=ws[0]["K"], cg_rtol=ws[0]["cg_rtol"],
+                      cg_maxit=500)
+    Ns = [p.N for p in probs]
+    upd_per_step = sum(Ns) * ws[0]["M"] * ws[0]["K"]
+    if a.warmup > 0:
+        ctx = H.BatchContext(probs, m)
+        ctx.advance(min(a.warmup, 5))
+        torch.cuda.synchronize()
+        ctx.destroy()
+    ctx = H.BatchContext(probs, m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.destroy()
+    # the same tissues one context at a time (each context's launches cover one tissue)
+    loop_steps = max(1, steps // 5)
+    t0 = time.perf_counter()
+    for p in probs:
+        c1 = H.Context(p, m)
+        c1.advance(loop_steps)
+        c1.destroy()
+    torch.cuda.synchronize()
+    wall_loop = time.perf_counter() - t0
+    # profiled pass: per-class kernel durations of the batch
+    ctx = H.BatchContext(probs, m)
+    ctx.profile(True)
+    ctx.advance(min(steps, 20))
+    torch.cuda.synchronize()
+    kp = ctx.profile_read()
+    pst = ctx.stats()
+    ctx.destroy()
+    b_cg = (pst["cg_iters"] - pst["cg_solves"]) * 80.0 * sum(Ns) / len(Ns) \
+        + pst["cg_solves"] * 64.0 * sum(Ns) / len(Ns)
+    kernels = _kernel_table(kp, {"cg_iter": b_cg})
+    dom = max(kernels, key=lambda k: kernels[k]["time_share"])
+    value = upd_per_step * steps / wall
+    loop_value = upd_per_step * loop_steps / wall_loop
+    out = {
+        "metric": "SDC node-updates/s (serial hybrid SDC, FP64, ragged batch of tissues)",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch2d {a.tissues} tissues, sides 64..512, lognormal sigma, "
+                               "8x8 patch, TTP06, M4 K4, dt 0.05 ms, CG 1e-12",
+                   "tissues": a.tissues, "nodes_total": int(sum(Ns)), "nodes_min": int(min(Ns)),
+                   "nodes_max": int(max(Ns)), "M": ws[0]["M"], "sweeps": ws[0]["K"],
+                   "dt_ms": ws[0]["dt"]},
+        "one_context_per_tissue": {"node_updates_per_s": loop_value, "steps": loop_steps,
+                                   "wall_s": wall_loop},
+        "vs_one_context_per_tissue": value / loop_value,
+        "cg_iters_per_solve": st["cg_iters"] / max(1, st["cg_solves"]),
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["GBps"],
+                     "peak": 8000.0, "unit": "GB/s", "frac": kernels[dom]["GBps"] / 8000.0,
+                     "traffic": None},
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -236,6 +334,9 @@ def main():
         sys.exit(2)
     if a.workload == "slab3d":
         bench_slab3d(a)
+        return
+    if a.workload == "batch2d":
+        bench_batch2d(a)
         return
     import torch
 

@@ -124,9 +124,26 @@ typedef struct {
 hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth,
                             const double *y0, void *hip_stream, hsdc_ctx **out);
 
+/* A batch of count independent tissues stepped together by serial hybrid SDC
+ * (Sec. 3.1; every kernel launch covers every tissue).  probs[n] describes
+ * tissue n; the tissues may differ only in nx, ny, nz, sigma_node and stim_w
+ * (dim, dx, sigma, chi, Cm, g_scale and the stimulus timing and amplitude are
+ * shared; sigma_node and stim_w are given for all tissues or for none).  meth
+ * must have levels = 1 and P = 1; count is 1..4096.  y0: host array of count
+ * device pointers, y0[n] device [19][N_n], or NULL (or a NULL entry) for the
+ * TTP06 rest state.  The context then behaves as a serial context whose slice
+ * n is tissue n: hsdc_advance steps every tissue, hsdc_sdc_sweep (slice 0)
+ * sweeps every tissue, hsdc_residual returns one residual per tissue, and
+ * get/set_state take the tissue as the slice (arrays of N_n nodes).  Device
+ * rows are padded to the largest tissue.  Errors as hsdc_init_state, and
+ * HSDC_EINVAL naming the first tissue whose shared fields differ. */
+hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc_method *meth,
+                            const double *const *y0, void *hip_stream, hsdc_ctx **out);
+
 /* Apply nsweeps preconditioned Picard iterations (eq. prec_picard, one forward
  * substitution with P^-1 of eq. def_P each) to the stage vector of one slice of
- * the fine level, keeping its start value y_{n,0}.  level must be 0. */
+ * the fine level.  PFASST contexts keep the slice's start value y_{n,0}; serial
+ * and batch contexts take slice 0 and sweep every tissue.  level must be 0. */
 hsdc_status hsdc_sdc_sweep(hsdc_ctx *ctx, int32_t level, int32_t slice, int32_t nsweeps);
 
 /* Serial mode: nsteps times {max_iter sweeps; y_{n+1} = y_{n,M}; spread y_{n+1}}

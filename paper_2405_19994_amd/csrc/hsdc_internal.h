@@ -16,12 +16,16 @@ constexpr int MAXM = HSDC_MAX_M;
 constexpr int BLOCK = 512;
 
 // Mesh and diffusion operator K = (chi Cm)^-1 A (cell-centred, no-flux).
+// A ragged batch of independent tissues (one per slice) sets rag: slice n then
+// has the dimensions rag[3n..3n+2] (N <= Np), and its face coefficients start
+// at kx + n Np (likewise ky, kz).
 struct Grid {
   int dim, nx, ny, nz;
-  int64_t N;    // nodes
+  int64_t N;    // nodes (largest tissue of a batch)
   int64_t Np;   // padded row length (multiple of 64 doubles)
   double cx, cy, cz;           // sigma_axis / (dx^2 chi Cm) for uniform sigma
   const double *kx, *ky, *kz;  // per-node face coefficients (face p -> p+e_axis), or null
+  const int32_t *rag;          // device [P][3] tissue dimensions, or null
 };
 
 // Collocation data of one level (host-computed in FP64, passed by value).
@@ -59,8 +63,12 @@ struct StagesT {
 };
 using Stages = StagesT<double>;
 
+// Also carries the time of slice n: step (step0 + n tn), tn = 1 for the
+// consecutive time slices of PFASST, 0 for the tissues of a batch.
 struct Stim {
-  const double *w;  // [Np] or null
+  const double *w;  // [Np] (shared by the slices, sw = 0) or [P][Np] (sw = Np), or null
+  int64_t sw;
+  int64_t tn;
   double amp, t0, dur, eps;
   double Cm;
 };
@@ -141,6 +149,7 @@ struct CgBatchT {
   CgScalars *sc;                // [nslices][2] by parity
   CgScalars *log;               // [nslices] final scalars (written by the kernel k == last_k) or null
   int last_k;
+  int slice0;                   // absolute index of the batch's first slice
   int nslices, nblk;            // blocks of the CG kernels (<= 512)
   int nblk0;                    // partials of gamma_0 and bb (written by the producer of r_0)
   double a, tol2;

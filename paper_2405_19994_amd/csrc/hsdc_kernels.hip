@@ -211,6 +211,20 @@ __device__ __forceinline__ Ijk ijk(const Grid &g, int64_t p) {
   return r;
 }
 
+// Mesh of slice n: the launch's grid, or the tissue's own for a ragged batch.
+__device__ __forceinline__ Grid slice_grid(const Grid &g, int n) {
+  if (g.rag == nullptr) return g;
+  Grid r = g;
+  r.nx = g.rag[3 * n];
+  r.ny = g.rag[3 * n + 1];
+  r.nz = g.rag[3 * n + 2];
+  r.N = (int64_t)r.nx * r.ny * r.nz;
+  if (g.kx) r.kx = g.kx + n * g.Np;
+  if (g.ky) r.ky = g.ky + n * g.Np;
+  if (g.kz) r.kz = g.kz + n * g.Np;
+  return r;
+}
+
 // (K v)_p with v given through val(k) (so callers can form v on the fly).
 template <int DIM, bool PN, class Val>
 __device__ __forceinline__ double applyK(const Grid &g, int64_t p, const Ijk &c, double vc,
@@ -286,19 +300,20 @@ static inline unsigned nblocks(int64_t n) { return (unsigned)((n + BLOCK - 1) / 
 // cell model at stages: G_j = f_E + f_e + Lambda(u)(u - y_j) (reaction part of g)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double stim_value(const Stim &st, double t, int64_t p) {
+__device__ __forceinline__ double stim_value(const Stim &st, double t, int n, int64_t p) {
   if (st.w == nullptr) return 0.0;
   const bool on = (t > st.t0 + st.eps) && (t <= st.t0 + st.dur + st.eps);
-  return on ? st.amp * st.w[p] : 0.0;
+  return on ? st.amp * st.w[n * st.sw + p] : 0.0;
 }
 
 template <class T>
 __global__ void __launch_bounds__(BLOCK)
-k_eval_stages(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
+k_eval_stages(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
               int slice0, int stage0, int64_t step0, T *Lout, const T *Lin) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= g.N) return;
   const int n = slice0 + blockIdx.z;
+  const Grid g = slice_grid(g0, n);
+  if (p >= g.N) return;
   const int j = stage0 + blockIdx.y;
   const int64_t Np = st.Np;
   const double *y = st.Y + n * st.sY() + j * st.sS();
@@ -308,7 +323,7 @@ k_eval_stages(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs
 #pragma unroll
   for (int f = 0; f < NF; ++f) yv[f] = T(y[f * Np + p]);
   const double cj = (j == 0) ? 0.0 : co.c[j - 1];
-  const double t = ((double)(step0 + n) + cj) * co.dt;
+  const double t = ((double)(step0 + n * stim.tn) + cj) * co.dt;
   const T *La = (j == 0) ? nullptr : Lin + n * st.sL();
   T *Lo = (j == 0 && Lout) ? Lout + n * st.sL() : nullptr;
   ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T tau) {
@@ -321,7 +336,7 @@ k_eval_stages(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs
   });
   T I_ion, ha[6];
   ttp06::currents<T>(yv, T(gs0), T(gs1), T(gs2), I_ion, ha);
-  G[p] = (T(stim_value(stim, t, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
+  G[p] = (T(stim_value(stim, t, n, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
 #pragma unroll
   for (int k = 0; k < 6; ++k) G[(1 + k) * Np + p] = ha[k];
 }
@@ -340,11 +355,12 @@ hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const StagesT<T> &st
 
 // FV_j = K V_j at stages.
 template <int DIM, bool PN, class T>
-__global__ void __launch_bounds__(BLOCK) k_spmv_stages(Grid g, StagesT<T> st, int slice0,
+__global__ void __launch_bounds__(BLOCK) k_spmv_stages(Grid g0, StagesT<T> st, int slice0,
                                                        int stage0) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= g.N) return;
   const int n = slice0 + blockIdx.z;
+  const Grid g = slice_grid(g0, n);
+  if (p >= g.N) return;
   const int j = stage0 + blockIdx.y;
   const double *v = st.Y + n * st.sY() + j * st.sS();
   const Ijk c = ijk(g, p);
@@ -366,20 +382,20 @@ hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const StagesT<T> &st
 // Spread stage 0 (Y optionally, G, FV) to stages 1..M; the stimulus part of the
 // V entry of G follows the stage time.
 __global__ void __launch_bounds__(BLOCK)
-k_spread(Grid g, Stages st, Colloc co, Stim stim, int slice0, int64_t step0, int copyY) {
+k_spread(Grid g0, Stages st, Colloc co, Stim stim, int slice0, int64_t step0, int copyY) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= g.N) return;
   const int n = slice0 + blockIdx.z;
+  if (p >= slice_grid(g0, n).N) return;
   const int64_t Np = st.Np;
   double *Y = st.Y + n * st.sY();
   double *G = st.G + n * st.sY();
   double *FV = st.FV + n * st.sFV();
-  const double t0 = ((double)(step0 + n)) * co.dt;
-  const double s0 = stim_value(stim, t0, p);
+  const double t0 = ((double)(step0 + n * stim.tn)) * co.dt;
+  const double s0 = stim_value(stim, t0, n, p);
   const double fv = FV[p];
   for (int j = 1; j <= st.M; ++j) {
-    const double tj = ((double)(step0 + n) + co.c[j - 1]) * co.dt;
-    const double sj = stim_value(stim, tj, p);
+    const double tj = ((double)(step0 + n * stim.tn) + co.c[j - 1]) * co.dt;
+    const double sj = stim_value(stim, tj, n, p);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       double gv = G[f * Np + p];
@@ -409,12 +425,12 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
 
 template <int M, class T>
 __global__ void __launch_bounds__(BLOCK)
-k_assemble(Grid g, StagesT<T> st, Colloc co, int slice0, const double *RI, int64_t sRI, int spread,
+k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int64_t sRI, int spread,
            Stim stim, int64_t step0) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= g.N) return;
   const int f = blockIdx.y;  // one field per block row: no divergence between field kinds
   const int n = slice0 + blockIdx.z;
+  if (p >= slice_grid(g0, n).N) return;
   const int64_t Np = st.Np;
   const T *G = st.G + n * st.sY() + f * Np + p;
   const double *FV = st.FV + n * st.sFV() + p;
@@ -424,14 +440,14 @@ k_assemble(Grid g, StagesT<T> st, Colloc co, int slice0, const double *RI, int64
   if (spread) {
     const double g0 = G[0];
     const double f0 = (f == 0) ? FV[0] : 0.0;
-    const double s0 = (f == 0) ? stim_value(stim, ((double)(step0 + n)) * co.dt, p) : 0.0;
+    const double s0 = (f == 0) ? stim_value(stim, ((double)(step0 + n * stim.tn)) * co.dt, n, p) : 0.0;
     Gv[0] = g0;
     fv[0] = 0.0;
 #pragma unroll
     for (int j = 1; j <= M; ++j) {
       double gv = g0;
       if (f == 0) {
-        const double sj = stim_value(stim, ((double)(step0 + n) + co.c[j - 1]) * co.dt, p);
+        const double sj = stim_value(stim, ((double)(step0 + n * stim.tn) + co.c[j - 1]) * co.dt, n, p);
         if (sj != s0) gv += (sj - s0) / stim.Cm;
       }
       Gv[j] = gv;
@@ -478,11 +494,11 @@ hipError_t launch_assemble(hipStream_t s, const Grid &g, const StagesT<T> &st, c
 // ---------------------------------------------------------------------------
 template <int M, class T>
 __global__ void __launch_bounds__(BLOCK)
-k_fas_integrals(Grid g, StagesT<T> st, Colloc co, int slice0, double *RI, int64_t sRI) {
+k_fas_integrals(Grid g0, StagesT<T> st, Colloc co, int slice0, double *RI, int64_t sRI) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= g.N) return;
   const int f = blockIdx.y;
   const int n = slice0 + blockIdx.z;
+  if (p >= slice_grid(g0, n).N) return;
   const int64_t Np = st.Np;
   const T *G = st.G + n * st.sY() + f * Np + p;
   const double *FV = st.FV + n * st.sFV() + p;
@@ -515,11 +531,12 @@ hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const StagesT<T> &
 
 template <class T>
 __global__ void __launch_bounds__(BLOCK)
-k_node_update(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
+k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
               int slice0, int i, int64_t step0, CgBatchT<T> cb, int store_g, int spread) {
   __shared__ double lds[BLOCK / 64];
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
+  const Grid g = slice_grid(g0, n);
   const int64_t Np = st.Np;
   const double ddt = co.dt * co.d[i - 1];
   double bb = 0.0, rr = 0.0;
@@ -548,7 +565,7 @@ k_node_update(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs
       T yv[NF];
 #pragma unroll
       for (int f = 0; f < NF; ++f) yv[f] = T(yd[f]);
-      const double t = ((double)(step0 + n) + co.c[i - 2]) * co.dt;
+      const double t = ((double)(step0 + n * stim.tn) + co.c[i - 2]) * co.dt;
       ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T tau) {
         const int f = GATE0 + k;
         const T lu = Lu[k * Np + p];
@@ -559,7 +576,7 @@ k_node_update(Grid g, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs
       });
       T I_ion, ha[6];
       ttp06::currents<T>(yv, T(gs0), T(gs1), T(gs2), I_ion, ha);
-      gV = (T(stim_value(stim, t, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
+      gV = (T(stim_value(stim, t, n, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
       if (store_g) Gp[p] = gV;
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
@@ -599,9 +616,9 @@ hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st
 }
 
 // V of stage 0 to stages 1..M (the CG warm starts of the first sweep of a step).
-__global__ void __launch_bounds__(BLOCK) k_copy_V_to_stages(Grid g, Stages st, int slice0) {
+__global__ void __launch_bounds__(BLOCK) k_copy_V_to_stages(Grid g0, Stages st, int slice0) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (p >= g.N) return;
+  if (p >= slice_grid(g0, slice0 + blockIdx.z).N) return;
   double *Y = st.Y + (slice0 + blockIdx.z) * st.sY();
   const double v = Y[p];
   for (int j = 1; j <= st.M; ++j) Y[(int64_t)j * st.sS() + p] = v;
@@ -621,11 +638,12 @@ hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &s
 
 template <int M>
 __global__ void __launch_bounds__(BLOCK)
-k_residual(Grid g, Stages st, Colloc co, int slice0, const double *yblk0, double *part, int nblk,
+k_residual(Grid g0, Stages st, Colloc co, int slice0, const double *yblk0, double *part, int nblk,
            const double *Rt, int Mc, double *RI, int64_t sRI) {
   __shared__ double lds[BLOCK / 64];
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
+  const Grid g = slice_grid(g0, n);
   const int64_t Np = st.Np;
   double rmax = 0.0, ymax = 0.0;
   if (p < g.N) {
@@ -633,7 +651,11 @@ k_residual(Grid g, Stages st, Colloc co, int slice0, const double *yblk0, double
     const double *G = st.G + n * st.sY();
     const double *FV = st.FV + n * st.sFV();
     const double *L0 = st.L0 + n * st.sL();
-    const double *up = (n == 0) ? yblk0 : st.Y + (n - 1) * st.sY() + (int64_t)M * st.sS();
+    // u: the block start (slice 0), the previous slice's end, or, for independent
+    // slices (yblk0 == NULL: serial steps, tissues of a batch), the own start value
+    const double *up = (yblk0 == nullptr) ? st.Y + n * st.sY()
+                       : (n == 0)         ? yblk0
+                                          : st.Y + (n - 1) * st.sY() + (int64_t)M * st.sS();
     double fv[M + 1];
 #pragma unroll
     for (int j = 1; j <= M; ++j) fv[j] = FV[j * Np + p];
@@ -738,12 +760,22 @@ int cg_blocks(const Grid &g, int cap) {
   return (int)(nb < cap ? nb : cap);
 }
 
+// Blocks of a CG launch that own nodes of a slice with g.N nodes: a small
+// tissue of a batch needs fewer than the launch has, and the others exit at
+// once; every reduction reads the partials of the active blocks only.
+__device__ __forceinline__ int active_blocks(const Grid &g, int nblk) {
+  const int64_t nb = (g.N + BLOCK - 1) / BLOCK;
+  return nb < nblk ? (int)nb : nblk;
+}
+
 // Start residual r_0 = b - A x_0 with the partials of ||r_0||^2 and ||b||^2
 // (used when r_0 is not produced by the node update).
 template <int DIM, bool PN, class T>
-__global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g, CgBatchT<T> cb) {
+__global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g0, CgBatchT<T> cb) {
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
+  const Grid g = slice_grid(g0, cb.slice0 + n);
+  if ((int)blockIdx.x >= active_blocks(g, cb.nblk)) return;
   const double *x = cb.x + n * cb.sx;
   const double *b = cb.b + n * cb.sb;
   T *r = cb.r[0] + n * g.Np;
@@ -768,9 +800,11 @@ __global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g, CgBatchT<T> cb) {
 
 // w_0 = A r_0 and the partials of delta_0 = (w_0, r_0); resets the scalars.
 template <int DIM, bool PN, class T>
-__global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatchT<T> cb) {
+__global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g0, CgBatchT<T> cb) {
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
+  const Grid g = slice_grid(g0, cb.slice0 + n);
+  if ((int)blockIdx.x >= active_blocks(g, cb.nblk)) return;
   const T *r = cb.r[0] + n * g.Np;
   T *w = cb.w[0] + n * g.Np;
   double del = 0.0;
@@ -798,9 +832,12 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g, CgBatchT<T> cb) {
 }
 
 template <int DIM, bool PN, class T>
-__global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatchT<T> cb, int k) {
+__global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int k) {
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
+  const Grid g = slice_grid(g0, cb.slice0 + n);
+  const int nba = active_blocks(g, cb.nblk), nba0 = active_blocks(g, cb.nblk0);
+  if ((int)blockIdx.x >= nba) return;
   const int in = k & 1, out = in ^ 1;
   CgScalars si = cb.sc[2 * n + in];
   CgScalars *so = cb.sc + 2 * n + out;
@@ -822,15 +859,15 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g, CgBatchT<T> cb, int k
   double r_c = 0.0, w_c = 0.0, s_c = 0.0, rn_[2 * DIM], wn_[2 * DIM], sn_[2 * DIM];
   Ijk c0{0, 0, 0};
   if (si.it == 0) {
-    gamma = reduce_partials(part, cb.nblk0, lds);
+    gamma = reduce_partials(part, nba0, lds);
     // stop relative to ||b|| or, for a correction solve, to ||r_0||
-    si.bb = cb.rel_r0 ? gamma : reduce_partials(part + 4 * cb.pstride, cb.nblk0, lds);
-    delta = reduce_partials(part + cb.pstride, cb.nblk, lds);
+    si.bb = cb.rel_r0 ? gamma : reduce_partials(part + 4 * cb.pstride, nba0, lds);
+    delta = reduce_partials(part + cb.pstride, nba, lds);
   } else {
     const double *pg = part + (2 * in) * cb.pstride, *pd = part + (2 * in + 1) * cb.pstride;
     const int t = threadIdx.x;
-    const double g0 = t < cb.nblk ? pg[t] : 0.0, g1 = t + BLOCK < cb.nblk ? pg[t + BLOCK] : 0.0;
-    const double d0 = t < cb.nblk ? pd[t] : 0.0, d1 = t + BLOCK < cb.nblk ? pd[t + BLOCK] : 0.0;
+    const double g0 = t < nba ? pg[t] : 0.0, g1 = t + BLOCK < nba ? pg[t + BLOCK] : 0.0;
+    const double d0 = t < nba ? pd[t] : 0.0, d1 = t + BLOCK < nba ? pd[t + BLOCK] : 0.0;
     if (!PN && p0 < g.N) {
       c0 = ijk(g, p0);
       r_c = r[p0];

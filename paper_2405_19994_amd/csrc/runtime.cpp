@@ -124,6 +124,10 @@ struct hsdc_ctx {
   Level L[2];             // fine level and (FP64) coarse level
   LevelT<float> Lf;       // coarse level when coarse_fp32
   bool cf32 = false;
+  // ragged batch of independent tissues (one per slice of a serial context)
+  bool batch = false;
+  std::vector<int64_t> tissue_N;  // nodes per slice (batch)
+  int32_t *rag = nullptr;         // device [P][3] tissue dimensions
   int nlev = 1;
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
   double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices
@@ -172,6 +176,15 @@ void with_coarse(hsdc_ctx *c, Fn &&fn) {
     fn(c->Lf);
   else
     fn(c->L[1]);
+}
+
+// Mesh nodes of slices [s0, s0+ns) of level L (a batch's tissues differ).
+template <class T>
+double slice_nodes(const hsdc_ctx *c, const LevelT<T> &L, int s0, int ns) {
+  if (!c->batch) return (double)L.g.N * ns;
+  double n = 0.0;
+  for (int k = s0; k < s0 + ns; ++k) n += (double)c->tissue_N[k];
+  return n;
 }
 
 // Relative tolerance of the diffusion solves on level lev (an FP32 coarse level
@@ -327,6 +340,23 @@ Grid make_grid(const hsdc_problem &p, int nx, int ny, int nz, double dx) {
 
 // Per-node conductivity: face coefficient between p and p + e_axis is the
 // harmonic mean of the two node values over dx^2 chi Cm (0 on the last layer).
+// Face coefficients along axis a of an nx x ny x nz mesh from host sigma.
+std::vector<double> face_coeffs(int a, int nx, int ny, int nz, const std::vector<double> &s,
+                                double sc) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t strides[3] = {1, nx, (int64_t)nx * ny};
+  const int sizes[3] = {nx, ny, nz};
+  std::vector<double> k(N, 0.0);
+  for (int64_t p = 0; p < N; ++p) {
+    const int coord = (int)((p / strides[a]) % sizes[a]);
+    if (coord < sizes[a] - 1) {
+      const double sp = s[p], sq = s[p + strides[a]];
+      k[p] = (sp + sq > 0) ? 2.0 * sp * sq / (sp + sq) * sc : 0.0;
+    }
+  }
+  return k;
+}
+
 template <class T>
 void build_faces(hsdc_ctx *c, LevelT<T> &L, const double *sigma_node_dev) {
   const Grid &g = L.g;
@@ -334,18 +364,8 @@ void build_faces(hsdc_ctx *c, LevelT<T> &L, const double *sigma_node_dev) {
   HIPC(hipMemcpyAsync(s.data(), sigma_node_dev, g.N * sizeof(double), hipMemcpyDeviceToHost, c->s));
   HIPC(hipStreamSynchronize(c->s));
   const double sc = 1.0 / (c->prob.dx * c->prob.dx * c->prob.chi * c->prob.Cm);
-  const int64_t strides[3] = {1, g.nx, (int64_t)g.nx * g.ny};
-  const int sizes[3] = {g.nx, g.ny, g.nz};
   for (int a = 0; a < g.dim; ++a) {
-    std::vector<double> k(g.N, 0.0);
-    for (int64_t p = 0; p < g.N; ++p) {
-      const int64_t q = p + strides[a];
-      const int coord = (int)((p / strides[a]) % sizes[a]);
-      if (coord < sizes[a] - 1) {
-        const double sp = s[p], sq = s[q];
-        k[p] = (sp + sq > 0) ? 2.0 * sp * sq / (sp + sq) * sc : 0.0;
-      }
-    }
+    const std::vector<double> k = face_coeffs(a, g.nx, g.ny, g.nz, s, sc);
     L.kface[a] = dalloc<double>(c, g.N);
     HIPC(hipMemcpyAsync(L.kface[a], k.data(), g.N * sizeof(double), hipMemcpyHostToDevice, c->s));
   }
@@ -416,6 +436,7 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
   cb.sc = L.cg_sc + 2 * s0;
   cb.log = nullptr;
   cb.last_k = -1;
+  cb.slice0 = s0;
   cb.nslices = ns;
   cb.nblk = L.cg_nblk;
   cb.nblk0 = node_blocks(L.g);  // r_0 and its partials come from the node update
@@ -470,7 +491,7 @@ void flush_cg_log(hsdc_ctx *c) {
 template <class T>
 void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pred_row) {
   CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
-  const double nodes = (double)L.g.N * ns;
+  const double nodes = slice_nodes(c, L, s0, ns);
   PLAUNCH(c, PC_CGINIT, 16.0 * nodes, launch_cg_init(c->s, L.g, cb));
   int &pred = L.cg_pred[pred_row & 15][i - 1];
   if (!c->safe_cg) {
@@ -518,7 +539,7 @@ template <class T>
 void evaluate_all(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns) {
   const hsdc_problem &p = c->prob;
   const int M = L.co.M;
-  const double N = (double)L.g.N;
+  const double N = slice_nodes(c, L, s0, ns) / ns;
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N * ns,
           launch_eval_stages<T>(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                              p.g_scale[2], s0, ns, 0, 1, c->step, L.st.L0, nullptr));
@@ -527,7 +548,7 @@ void evaluate_all(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns) {
                              p.g_scale[2], s0, ns, 1, M, c->step, nullptr, L.st.L0));
   PLAUNCH(c, PC_SPMV, 16.0 * (M + 1) * N * ns,
           launch_spmv_stages<T>(c->s, L.g, L.st, s0, ns, 0, M + 1));
-  c->stats.ionic_evals += L.g.N * ns * (M + 1);
+  c->stats.ionic_evals += (int64_t)(N * ns) * (M + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,7 +569,7 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
   const Colloc &co = L.co;
   const hsdc_problem &p = c->prob;
   const int M = co.M;
-  const int64_t N = L.g.N;
+  const double N = slice_nodes(c, L, s0, ns) / ns;
   const int64_t step0 = c->step;
   const int64_t sRI = (int64_t)M * NF * L.g.Np;
   const int spread = (lev == 0 && c->spread_pending) ? 1 : 0;
@@ -570,7 +591,7 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
     PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
             launch_node_update(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                                p.g_scale[2], s0, ns, i, step0, cb, drop_terms ? 0 : 1, spread));
-    if (i > 1) c->stats.ionic_evals += N * ns;
+    if (i > 1) c->stats.ionic_evals += (int64_t)(N * ns);
     cg_solve(c, L, lev, s0, ns, i, pred_row);
   }
   if (lev == 0) c->spread_pending = false;
@@ -580,7 +601,7 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
     PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns,
             launch_eval_stages<T>(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                                p.g_scale[2], s0, ns, M, 1, step0, nullptr, L.st.L0));
-    c->stats.ionic_evals += N * ns;
+    c->stats.ionic_evals += (int64_t)(N * ns);
     PLAUNCH(c, PC_SPMV, 16.0 * M * N * ns, launch_spmv_stages<T>(c->s, L.g, L.st, s0, ns, 1, M));
   }
   if (lev == 0)
@@ -590,17 +611,20 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
 }
 
 // Serial step start: y^0 = 1 (x) y_n from Y[0][0].
+// (every slice of a serial context: one, or the tissues of a batch)
 void begin_serial_step(hsdc_ctx *c) {
   Level &L = c->L[0];
   const hsdc_problem &p = c->prob;
-  const double N = (double)L.g.N;
+  const int P = L.P;
+  const double N = slice_nodes(c, L, 0, P);
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N,
-          launch_eval_stages<double>(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0], p.g_scale[1],
-                             p.g_scale[2], 0, 1, 0, 1, c->step, L.st.L0, nullptr));
-  PLAUNCH(c, PC_SPMV, 16.0 * N, launch_spmv_stages<double>(c->s, L.g, L.st, 0, 1, 0, 1));
-  PLAUNCH(c, PC_COPY, 8.0 * (1 + L.co.M) * N, launch_copy_V_to_stages(c->s, L.g, L.st, 0, 1));
+          launch_eval_stages<double>(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0],
+                                     p.g_scale[1], p.g_scale[2], 0, P, 0, 1, c->step, L.st.L0,
+                                     nullptr));
+  PLAUNCH(c, PC_SPMV, 16.0 * N, launch_spmv_stages<double>(c->s, L.g, L.st, 0, P, 0, 1));
+  PLAUNCH(c, PC_COPY, 8.0 * (1 + L.co.M) * N, launch_copy_V_to_stages(c->s, L.g, L.st, 0, P));
   c->spread_pending = true;
-  c->stats.ionic_evals += L.g.N;
+  c->stats.ionic_evals += (int64_t)N;
   c->sweeps_done = 0;
   c->sweep_index = 0;
 }
@@ -610,20 +634,20 @@ void begin_serial_step(hsdc_ctx *c) {
 void materialize(hsdc_ctx *c) {
   if (!c->spread_pending) return;
   Level &L = c->L[0];
-  HIPC(launch_spread(c->s, L.g, L.st, L.co, c->stim[0], 0, 1, c->step, true));
+  HIPC(launch_spread(c->s, L.g, L.st, L.co, c->stim[0], 0, L.P, c->step, true));
   c->spread_pending = false;
 }
 
 hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
   materialize(c);
   Level &L = c->L[0];
-  const double *yb = c->pfasst ? c->y0blk : L.st.Y;  // serial: u = y_{n,0}
+  const double *yb = c->pfasst ? c->y0blk : nullptr;  // serial, batch: u = y_{n,0}
   const int Mc = c->nlev == 2 ? c->meth.M[1] : 0;
   double *RI = (want_RI && c->nlev == 2) ? L.RI : nullptr;
   {
     const double M = L.co.M;
     const double per = (M + 1) * NF + M * NF + M + NG + NF + (RI ? Mc * NF : 0);
-    PLAUNCH(c, PC_RESIDUAL, 8.0 * per * L.g.N * L.P,
+    PLAUNCH(c, PC_RESIDUAL, 8.0 * per * slice_nodes(c, L, 0, L.P),
             launch_residual(c->s, L.g, L.st, L.co, 0, L.P, yb, L.res_part, L.res_nblk, L.res_out,
                             c->Rt, Mc, RI, (int64_t)Mc * NF * L.g.Np));
   }
@@ -814,6 +838,7 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
                           hipMemcpyDeviceToDevice, c->s));
     }
     for (int l = 0; l < 2; ++l) {
+      c->stim[l].tn = 1;  // slice n is time step step + n
       c->stim[l].amp = prob->stim_amp;
       c->stim[l].t0 = prob->stim_t0;
       c->stim[l].dur = prob->stim_dur;
@@ -878,14 +903,138 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
   return HSDC_OK;
 }
 
+hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc_method *meth,
+                            const double *const *y0, void *hip_stream, hsdc_ctx **out) {
+  if (!out) return fail(nullptr, HSDC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!probs || count < 1 || count > 4096)
+    return fail(nullptr, HSDC_EINVAL, "count must be in 1..4096 and probs non-NULL");
+  std::string why;
+  for (int n = 0; n < count; ++n)
+    if (!check_problem(&probs[n], why))
+      return fail(nullptr, HSDC_EINVAL, "tissue " + std::to_string(n) + ": " + why);
+  if (!check_method(meth, &probs[0], why)) return fail(nullptr, HSDC_EINVAL, why);
+  if (meth->levels != 1 || meth->P != 1)
+    return fail(nullptr, HSDC_EINVAL, "a batch takes levels = 1 and P = 1 (serial steps)");
+  const hsdc_problem &p0 = probs[0];
+  for (int n = 1; n < count; ++n) {
+    const hsdc_problem &q = probs[n];
+    bool same = q.dim == p0.dim && q.dx == p0.dx && q.chi == p0.chi && q.Cm == p0.Cm &&
+                q.stim_amp == p0.stim_amp && q.stim_t0 == p0.stim_t0 &&
+                q.stim_dur == p0.stim_dur && (q.sigma_node == nullptr) == (p0.sigma_node == nullptr) &&
+                (q.stim_w == nullptr) == (p0.stim_w == nullptr);
+    for (int a = 0; a < 3; ++a)
+      same = same && q.sigma[a] == p0.sigma[a] && q.g_scale[a] == p0.g_scale[a];
+    if (!same)
+      return fail(nullptr, HSDC_EINVAL,
+                  "tissue " + std::to_string(n) +
+                      ": tissues of a batch differ only in nx, ny, nz, sigma_node and stim_w");
+  }
+  hsdc_ctx *c = new hsdc_ctx();
+  if (const char *e = std::getenv("HSDC_CG_BLOCKS")) c->tune_cg_blocks = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("HSDC_CG_MARGIN")) c->tune_cg_margin = std::max(1, std::atoi(e));
+  c->s = (hipStream_t)hip_stream;
+  c->prob = p0;
+  c->meth = *meth;
+  c->meth.P = count;
+  c->nlev = 1;
+  c->pfasst = false;
+  c->batch = true;
+  hsdc_status st = run_guarded(c, [&]() -> hsdc_status {
+    Level &F = c->L[0];
+    int big = 0;
+    std::vector<int32_t> dims(3 * count);
+    for (int n = 0; n < count; ++n) {
+      const hsdc_problem &q = probs[n];
+      c->tissue_N.push_back((int64_t)q.nx * q.ny * q.nz);
+      dims[3 * n] = q.nx;
+      dims[3 * n + 1] = q.ny;
+      dims[3 * n + 2] = q.nz;
+      if (c->tissue_N[n] > c->tissue_N[big]) big = n;
+    }
+    // rows padded to the largest tissue; slice n holds tissue n
+    F.g = make_grid(p0, probs[big].nx, probs[big].ny, probs[big].nz, p0.dx);
+    if (!make_colloc(meth->M[0], meth->dt, F.co))
+      return fail(c, HSDC_EINVAL, "Radau node computation failed");
+    alloc_level(c, F, meth->M[0], count, false, 0);
+    const int64_t Np = F.g.Np;
+    c->rag = dalloc<int32_t>(c, dims.size());
+    HIPC(hipMemcpyAsync(c->rag, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                        c->s));
+    F.g.rag = c->rag;
+    if (p0.sigma_node) {
+      const double sc = 1.0 / (p0.dx * p0.dx * p0.chi * p0.Cm);
+      for (int a = 0; a < p0.dim; ++a) F.kface[a] = dalloc<double>(c, (size_t)count * Np);
+      for (int n = 0; n < count; ++n) {
+        const hsdc_problem &q = probs[n];
+        std::vector<double> s(c->tissue_N[n]);
+        HIPC(hipMemcpyAsync(s.data(), q.sigma_node, s.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, c->s));
+        HIPC(hipStreamSynchronize(c->s));
+        for (int a = 0; a < p0.dim; ++a) {
+          const std::vector<double> k = face_coeffs(a, q.nx, q.ny, q.nz, s, sc);
+          HIPC(hipMemcpyAsync(F.kface[a] + n * Np, k.data(), k.size() * sizeof(double),
+                              hipMemcpyHostToDevice, c->s));
+        }
+        HIPC(hipStreamSynchronize(c->s));
+      }
+      F.g.kx = F.kface[0];
+      F.g.ky = p0.dim >= 2 ? F.kface[1] : nullptr;
+      F.g.kz = p0.dim >= 3 ? F.kface[2] : nullptr;
+    }
+    c->cg_log_cap = std::max(8192, 64 * count);
+    c->cg_log = halloc<CgScalars>(c, c->cg_log_cap);
+    c->cg_dlog = dalloc<CgScalars>(c, c->cg_log_cap);
+    if (p0.stim_w) {
+      F.stim_w = dalloc<double>(c, (size_t)count * Np);
+      for (int n = 0; n < count; ++n)
+        HIPC(hipMemcpyAsync(F.stim_w + n * Np, probs[n].stim_w, c->tissue_N[n] * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->s));
+    }
+    c->stim[0].w = F.stim_w;
+    c->stim[0].sw = Np;
+    c->stim[0].tn = 0;  // every tissue is at the same time step
+    c->stim[0].amp = p0.stim_amp;
+    c->stim[0].t0 = p0.stim_t0;
+    c->stim[0].dur = p0.stim_dur;
+    c->stim[0].eps = 1e-9 * meth->dt;
+    c->stim[0].Cm = p0.Cm;
+    for (int n = 0; n < count; ++n) {
+      double *Y0 = F.st.Y + n * F.st.sY();
+      if (y0 && y0[n]) {
+        for (int f = 0; f < NF; ++f)
+          HIPC(hipMemcpyAsync(Y0 + f * Np, y0[n] + f * c->tissue_N[n],
+                              c->tissue_N[n] * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+      } else {
+        HIPC(launch_fill_rest(c->s, c->tissue_N[n], Np, Y0));
+      }
+    }
+    begin_serial_step(c);
+    HIPC(hipStreamSynchronize(c->s));
+    return HSDC_OK;
+  });
+  if (st != HSDC_OK) {
+    g_free_error = c->err;
+    hsdc_destroy(c);
+    return st;
+  }
+  *out = c;
+  return HSDC_OK;
+}
+
 hsdc_status hsdc_sdc_sweep(hsdc_ctx *c, int32_t level, int32_t slice, int32_t nsweeps) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
   if (level != 0) return fail(c, HSDC_EINVAL, "level must be 0");
   if (slice < 0 || slice >= c->L[0].P) return fail(c, HSDC_EINVAL, "slice out of range");
+  if (!c->pfasst && slice != 0)
+    return fail(c, HSDC_EINVAL, "serial and batch contexts take slice 0 (a sweep covers every tissue)");
   if (nsweeps < 0) return fail(c, HSDC_EINVAL, "nsweeps must be >= 0");
   return run_guarded(c, [&]() -> hsdc_status {
     for (int k = 0; k < nsweeps; ++k) {
-      sweep(c, c->L[0], 0, slice, 1, nullptr, nullptr, c->pfasst ? 13 : c->sweep_index++);
+      if (c->pfasst)
+        sweep(c, c->L[0], 0, slice, 1, nullptr, nullptr, 13);
+      else  // serial and batch contexts: every slice (tissue) takes the sweep
+        sweep(c, c->L[0], 0, 0, c->L[0].P, nullptr, nullptr, c->sweep_index++);
       if (!c->pfasst) c->sweeps_done += 1;
     }
     if (nsweeps > 0) c->ri_fresh = false;
@@ -907,7 +1056,7 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
         c->cg_fails = 0;
         while (c->sweeps_done < c->meth.max_iter) {
           const bool last = c->sweeps_done == c->meth.max_iter - 1;
-          sweep(c, F, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
+          sweep(c, F, 0, 0, F.P, nullptr, nullptr, c->sweep_index++, last);
           c->sweeps_done += 1;
         }
         flush_cg_log(c);
@@ -918,13 +1067,13 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
           begin_serial_step(c);
           while (c->sweeps_done < c->meth.max_iter) {
             const bool last = c->sweeps_done == c->meth.max_iter - 1;
-            sweep(c, F, 0, 0, 1, nullptr, nullptr, c->sweep_index++, last);
+            sweep(c, F, 0, 0, F.P, nullptr, nullptr, c->sweep_index++, last);
             c->sweeps_done += 1;
           }
         }
         // y_{n+1} = y_{n,M}
-        HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0,
-                                F.st.Y + (int64_t)F.co.M * F.st.sS(), 0, NF, 1));
+        HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, F.st.sY(),
+                                F.st.Y + (int64_t)F.co.M * F.st.sS(), F.st.sY(), NF, F.P));
         c->step += 1;
         c->stats.steps += 1;
         begin_serial_step(c);
@@ -976,12 +1125,13 @@ static hsdc_status state_copy(hsdc_ctx *c, int32_t level, int32_t slice, int32_t
     if (node != 0 || !get) materialize(c);
     auto copy = [&](auto &L) {
       double *base = L.st.Y + slice * L.st.sY() + (int64_t)node * L.st.sS();
+      const int64_t N = c->batch ? c->tissue_N[slice] : L.g.N;
       for (int f = 0; f < NF; ++f) {
         if (get)
-          HIPC(hipMemcpyAsync(dev + f * L.g.N, base + f * L.g.Np, L.g.N * sizeof(double),
+          HIPC(hipMemcpyAsync(dev + f * N, base + f * L.g.Np, N * sizeof(double),
                               hipMemcpyDeviceToDevice, c->s));
         else
-          HIPC(hipMemcpyAsync(base + f * L.g.Np, dev + f * L.g.N, L.g.N * sizeof(double),
+          HIPC(hipMemcpyAsync(base + f * L.g.Np, dev + f * N, N * sizeof(double),
                               hipMemcpyDeviceToDevice, c->s));
       }
       if (!get && c->pfasst) evaluate_all(c, L, level, slice, 1);
@@ -1003,7 +1153,7 @@ static hsdc_status state_copy(hsdc_ctx *c, int32_t level, int32_t slice, int32_t
       } else if (node == 0) {
         begin_serial_step(c);
       } else {
-        evaluate_all(c, F, 0, 0, 1);
+        evaluate_all(c, F, 0, slice, 1);
       }
     }
     HIPC(hipStreamSynchronize(c->s));

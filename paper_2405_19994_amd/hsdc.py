@@ -70,6 +70,8 @@ def lib():
         sig = {
             "hsdc_init_state": [ctypes.POINTER(Problem), ctypes.POINTER(Method), vp, vp,
                                 ctypes.POINTER(vp)],
+            "hsdc_init_batch": [ctypes.POINTER(Problem), i32, ctypes.POINTER(Method), vp, vp,
+                                ctypes.POINTER(vp)],
             "hsdc_sdc_sweep": [vp, i32, i32, i32],
             "hsdc_advance": [vp, i32],
             "hsdc_pfasst_iter": [vp, vp, vp],
@@ -257,6 +259,44 @@ class Context:
             self.destroy()
         except Exception:
             pass
+
+
+class BatchContext(Context):
+    """hsdc_init_batch: independent tissues stepped together by serial HSDC;
+    slice n is tissue n (get_state / set_state take arrays of that tissue's size)."""
+
+    def __init__(self, problems, method, y0s=None, stream=None):
+        self.problems = list(problems)
+        self.problem, self.method = self.problems[0], method
+        self.Ns = [p.N for p in self.problems]
+        self.N = max(self.Ns)
+        self.P = len(self.problems)
+        self._stream_obj = stream
+        arr = (Problem * self.P)(*self.problems)
+        y0p = None
+        if y0s is not None:
+            ptrs = [None if y is None else _dev(y, "y0", (NF, n)) for y, n in zip(y0s, self.Ns)]
+            y0p = ctypes.cast((ctypes.c_void_p * self.P)(*ptrs), ctypes.c_void_p)
+        ptr = ctypes.c_void_p()
+        _check(lib().hsdc_init_batch(arr, self.P, ctypes.byref(method), y0p, _stream(stream),
+                                     ctypes.byref(ptr)))
+        self._ctx = ptr
+
+    def _level_n(self, level):
+        raise HsdcError(-1, "batch contexts take the tissue size per slice")
+
+    def get_state(self, level=0, slice=0, node=0, out=None):
+        n = self.Ns[slice]
+        if out is None:
+            out = torch.empty((NF, n), dtype=torch.float64, device="cuda")
+        _check(lib().hsdc_get_state(self.handle, level, slice, node, _dev(out, "out", (NF, n))),
+               self.handle)
+        return out
+
+    def set_state(self, src, level=0, slice=0, node=0):
+        n = self.Ns[slice]
+        _check(lib().hsdc_set_state(self.handle, level, slice, node, _dev(src, "src", (NF, n))),
+               self.handle)
 
 
 def ionic_eval(y, g_scale=(1.0, 1.0, 1.0), stream=None):

@@ -67,3 +67,32 @@ def test_null_context_calls_are_einval():
     L.hsdc_destroy(None)
     assert L.hsdc_phi(10, None, 0, None, None) == -1
     assert L.hsdc_colloc_coefficients(0, 1, None, None, None, None) == -1
+
+
+def _batch(probs, m):
+    arr = (H.Problem * len(probs))(*probs)
+    ptr = ctypes.c_void_p()
+    code = H.lib().hsdc_init_batch(arr, len(probs), ctypes.byref(m), None, None, ctypes.byref(ptr))
+    return code, ptr
+
+
+@pytest.mark.parametrize("bad", ["dx", "levels", "count", "sigma"])
+def test_bad_batch_is_einval(bad):
+    """Tissues of a batch share everything but their mesh, sigma field and
+    stimulus weights; the method is serial.  Rejected before any device call."""
+    probs = [H.make_problem((12, 10), 0.025), H.make_problem((8, 14), 0.025)]
+    m = H.make_method(M=4, max_iter=4)
+    if bad == "dx":
+        probs[1] = H.make_problem((8, 14), 0.03)
+    elif bad == "levels":
+        m = H.make_method(M=(4, 2), levels=2, P=2)
+    elif bad == "sigma":
+        probs[1] = H.make_problem((8, 14), 0.025, sigma=(2.0, 1.0, 1.0))
+    if bad == "count":
+        ptr = ctypes.c_void_p()
+        code = H.lib().hsdc_init_batch(None, 0, ctypes.byref(m), None, None, ctypes.byref(ptr))
+    else:
+        code, ptr = _batch(probs, m)
+    assert code == -1 and not ptr.value
+    assert H.lib().hsdc_last_error(None)
+

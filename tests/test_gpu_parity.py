@@ -290,6 +290,52 @@ def test_pfasst_advance_blocks():
 
 
 # ---------------------------------------------------------------------------
+# ragged batch of independent tissues in one set of launches
+# ---------------------------------------------------------------------------
+
+def test_batch_matches_oracle_per_tissue():
+    """Three ragged tissues (per-node lognormal sigma, an 8 x 8 stimulus patch
+    each) stepped together through the stimulus (24 steps of dt 0.05 ms, M 4,
+    K 4): every tissue equals the oracle's serial HSDC run of that tissue alone."""
+    ws = si.batch2d_tissues(3, seed=3, lo=12, hi=28)
+    m = H.make_method(M=4, dt=ws[0]["dt"], max_iter=4, cg_rtol=1e-14, cg_maxit=300)
+    ctx = H.BatchContext([lib_problem(w) for w in ws], m)
+    nsteps = 24
+    ctx.advance(nsteps)
+    assert ctx.step == nsteps
+    for n, w in enumerate(ws):
+        po = oracle_problem(w)
+        y = run_serial(Level(po, 4, w["dt"]), rest(po.N), nsteps, 4)
+        g = host(ctx.get_state(0, n, 0))
+        assert np.max(field_errors(g, y)) < 1e-10, (n, w["dims"], np.max(field_errors(g, y)))
+
+
+def test_batch_matches_single_contexts():
+    """Five ragged tissues (20..60 nodes a side): the batch equals five separate
+    contexts (up to the order of the CG reductions), including set_state on one
+    tissue and a sweep applied to all."""
+    ws = si.batch2d_tissues(5, seed=7, lo=20, hi=60)
+    m = H.make_method(M=4, dt=ws[0]["dt"], max_iter=4, cg_rtol=1e-14, cg_maxit=300)
+    probs = [lib_problem(w) for w in ws]
+    y0 = [None] * 5
+    y0[2] = dev(si.random_states(ws[2]["dims"][0] * ws[2]["dims"][1], seed=5))
+    ctx = H.BatchContext(probs, m, y0)
+    ctx.advance(10)
+    ctx.sdc_sweep(2)
+    for n, w in enumerate(ws):
+        single = H.Context(probs[n], m, y0[n])
+        single.advance(10)
+        single.sdc_sweep(2)
+        for j in (0, 4):
+            a = host(ctx.get_state(0, n, j))
+            b = host(single.get_state(0, 0, j))
+            assert np.max(field_errors(a, b)) < 1e-11, (n, j)
+        single.destroy()
+    with pytest.raises(H.HsdcError):
+        ctx.sdc_sweep(1, slice=1)
+
+
+# ---------------------------------------------------------------------------
 # full size: the 512 x 512 slab in the benchmark's launch configuration
 # ---------------------------------------------------------------------------
 
