@@ -46,10 +46,15 @@ def _args():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="slab2d: keep the default CG launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d"), default="slab2d")
     ap.add_argument("--tissues", type=int, default=64, help="batch2d: tissues in the batch")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
+                         "WRITE_SIZE) of a --calibrate-copy run into profiles/hbm_traffic_slab2d.json")
     ap.add_argument("--blocks", type=int, default=2, help="slab3d: PFASST blocks timed")
     ap.add_argument("--coarsen", type=int, choices=(1, 2), default=2,
                     help="slab3d: space coarsening factor of the coarse level")
@@ -327,8 +332,60 @@ def bench_batch2d(a):
     print(json.dumps(out))
 
 
+_KERNEL_CLASS = (("k_node_update", "node_update"), ("k_cg_iter", "cg_iter"),
+                 ("k_cg_init", "cg_init"), ("k_assemble", "assemble"),
+                 ("k_eval_stages", "eval_stages"), ("k_spmv_stages", "spmv"),
+                 ("k_copy_fields", "copy"), ("k_copy_V_to_stages", "copy"))
+
+
+def summarize_counters(fetch_csv, write_csv):
+    """Per kernel class: average FETCH_SIZE and WRITE_SIZE per dispatch (KiB),
+    each scaled by the ratio the same counter reads for the calibration copy
+    (the largest device copy of the run: 512 MiB from a cache-cold source), and
+    their sum in bytes per launch."""
+    import csv
+
+    def load(path):
+        per, calib = {}, 0.0
+        for r in csv.DictReader(open(path)):
+            name, v = r["Kernel_Name"], float(r["Counter_Value"])
+            if "copyBuffer" in name:
+                calib = max(calib, v)
+                continue
+            for key, cls in _KERNEL_CLASS:
+                if key in name:
+                    per.setdefault(cls, []).append(v)
+                    break
+        return per, calib
+
+    fetch, cf = load(fetch_csv)
+    write, cw = load(write_csv)
+    copy_bytes = 512 * 1024 * 1024
+    ff, fw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    kernels = {}
+    for cls in fetch:
+        if cls not in write:
+            continue
+        f = sum(fetch[cls]) / len(fetch[cls])
+        w = sum(write[cls]) / len(write[cls])
+        kernels[cls] = {"fetch_KiB": f, "write_KiB": w, "dispatches": len(fetch[cls]),
+                        "bytes_per_launch": 1024.0 * (f * ff + w * fw)}
+    rec = {"workload": "slab2d 512x512, M 6, K 6, dt 0.05 ms",
+           "sources_digest": _kernel_sources_digest(),
+           "calibration": {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": cf, "WRITE_SIZE_KiB": cw,
+                           "fetch_factor": ff, "write_factor": fw},
+           "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_slab2d.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def main():
     a = _args()
+    if a.summarize_counters:
+        summarize_counters(*a.summarize_counters)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -353,14 +410,29 @@ def main():
                          cg_maxit=500)
     stream = torch.cuda.current_stream()
 
+    # launch-shape tuning before the timed region (cached per shape)
+    tuning = None
+    if not a.no_autotune:
+        from paper_2405_19994_amd import autotune
+        key = autotune.shape_key(prob, meth)
+        setting, timings = autotune.tune(lambda: H.Context(prob, meth, None, stream), key,
+                                         use_cache=False)
+        tuning = {"setting": setting, "candidates": timings}
+
+    def new_context():
+        c = H.Context(prob, meth, None, stream)
+        if tuning:
+            c.tune(tuning["setting"]["cg_blocks"], tuning["setting"]["cg_margin"])
+        return c
+
     # warm-up on its own context (JIT of code objects, allocator, CG predictors)
     if a.warmup > 0:
-        ctx_w = H.Context(prob, meth, None, stream)
+        ctx_w = new_context()
         ctx_w.advance(a.warmup)
         torch.cuda.synchronize()
         ctx_w.destroy()
 
-    ctx = H.Context(prob, meth, None, stream)
+    ctx = new_context()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -377,7 +449,7 @@ def main():
     # second pass, same workload and launch configuration, with every kernel
     # bracketed by HIP events on the library's stream: per-class durations
     prof_steps = min(a.steps, 100)
-    ctx = H.Context(prob, meth, None, stream)
+    ctx = new_context()
     ctx.profile(True)
     ctx.advance(prof_steps)
     torch.cuda.synchronize()
@@ -419,6 +491,7 @@ def main():
         "V_max_end_mV": Vmax,
         "roofline": roofline,
         "kernels": kernels,
+        "tuning": tuning,
     }
     if a.calibrate_copy:
         # a plain copy of known size whose source is not cache resident: the

@@ -140,6 +140,14 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth,
 hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc_method *meth,
                             const double *const *y0, void *hip_stream, hsdc_ctx **out);
 
+/* Launch tuning of a context (results are unchanged up to the order of the CG
+ * reductions): cg_blocks caps the blocks of each CG kernel (1..1024, <= 0
+ * keeps the current cap, default 512); cg_margin is the number of spare
+ * iterations added to a predicted CG iteration budget (1..64, <= 0 keeps the
+ * current margin, default 2).  Takes effect from the next solve; call it
+ * between steps, not concurrently with work on the context. */
+hsdc_status hsdc_tune(hsdc_ctx *ctx, int32_t cg_blocks, int32_t cg_margin);
+
 /* Apply nsweeps preconditioned Picard iterations (eq. prec_picard, one forward
  * substitution with P^-1 of eq. def_P each) to the stage vector of one slice of
  * the fine level.  PFASST contexts keep the slice's start value y_{n,0}; serial

@@ -1,0 +1,108 @@
+"""Launch-shape autotuner for libhsdc.
+
+The CG kernels are latency bound on small meshes and bandwidth bound on large
+ones, and the spare iterations of a predicted CG budget trade a no-op launch
+against the risk of recomputing a step.  For one problem shape the tuner times
+a few steps with every candidate (CG block cap, budget margin) on fresh
+contexts, keeps the fastest, and caches it per shape key, so that later runs
+of the same shape apply it without timing anything.  Tuning changes launch
+shapes only: results agree up to the order of the CG reductions.
+
+The cache is a JSON file, by default ~/.cache/paper_2405_19994_amd/tuning.json
+(HSDC_TUNE_CACHE overrides the path).
+"""
+import json
+import os
+import time
+
+CG_BLOCKS = (128, 256, 512, 1024)
+CG_MARGINS = (1, 2, 3)
+DEFAULT = {"cg_blocks": 512, "cg_margin": 2}
+
+
+def cache_path():
+    return os.environ.get("HSDC_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_2405_19994_amd", "tuning.json")
+
+
+def shape_key(problems, method):
+    """Mesh sizes, per-node sigma, stepping and level structure: what decides
+    the launch shapes of a context."""
+    probs = problems if isinstance(problems, (list, tuple)) else [problems]
+    dims = sorted((p.nx, p.ny, p.nz) for p in probs)
+    pernode = bool(probs[0].sigma_node)
+    return json.dumps({"dims": dims if len(dims) <= 4 else [len(dims), dims[0], dims[-1]],
+                       "pernode": pernode, "levels": method.levels, "M": list(method.M),
+                       "P": method.P, "sweeps": method.max_iter,
+                       "coarsen": method.space_coarsen, "fp32": method.coarse_fp32},
+                      sort_keys=True)
+
+
+def _load():
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(table):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(key):
+    """Cached setting for key, or None."""
+    return _load().get(key)
+
+
+def tune(make_context, key, steps=6, warm=2, candidates=None, use_cache=True, sync=None,
+         min_gain=0.02):
+    """Time `steps` steps after `warm` untimed ones on a fresh context from
+    make_context() for every candidate; return (best setting, timings).  The
+    default setting is kept unless a candidate is faster by more than
+    min_gain (relative), so timing noise does not pick the launch shapes.
+
+    sync: callable that waits for the device (torch.cuda.synchronize)."""
+    if use_cache:
+        hit = lookup(key)
+        if hit is not None:
+            return hit, None
+    if sync is None:
+        import torch
+        sync = torch.cuda.synchronize
+    cands = candidates or [{"cg_blocks": b, "cg_margin": m} for b in CG_BLOCKS for m in CG_MARGINS]
+    timings = []
+    for cand in cands:
+        ctx = make_context()
+        ctx.tune(cand["cg_blocks"], cand["cg_margin"])
+        ctx.advance(warm)
+        sync()
+        t0 = time.perf_counter()
+        ctx.advance(steps)
+        sync()
+        dt = time.perf_counter() - t0
+        ctx.destroy()
+        timings.append(dict(cand, s_per_step=dt / steps))
+    best = min(timings, key=lambda r: r["s_per_step"])
+    base = [r for r in timings if r["cg_blocks"] == DEFAULT["cg_blocks"]
+            and r["cg_margin"] == DEFAULT["cg_margin"]]
+    if base and best["s_per_step"] > (1.0 - min_gain) * base[0]["s_per_step"]:
+        best = base[0]
+    setting = {"cg_blocks": best["cg_blocks"], "cg_margin": best["cg_margin"]}
+    if use_cache:
+        table = _load()
+        table[key] = setting
+        _store(table)
+    return setting, timings
+
+
+def apply(ctx, key):
+    """Apply the cached setting for key to ctx (the defaults when none)."""
+    s = lookup(key) or DEFAULT
+    ctx.tune(s["cg_blocks"], s["cg_margin"])
+    return s

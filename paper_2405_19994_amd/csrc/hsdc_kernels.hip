@@ -1014,28 +1014,32 @@ hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double 
 // 2^d children / cell-centred multilinear interpolation), or time only.
 // ---------------------------------------------------------------------------
 
-struct Children {
-  int64_t idx[8];
-  int n;
-};
-__device__ __forceinline__ Children children(const Grid &gf, const Grid &gc, int64_t pc, int f) {
-  Children ch;
-  if (f == 1) {
-    ch.idx[0] = pc;
-    ch.n = 1;
-    return ch;
-  }
+// Mean of val(q) over the fine children q of coarse node pc (2 per coarsened
+// axis, or pc itself without space coarsening); indices are formed in
+// registers with the child loops unrolled.
+template <class Val>
+__device__ __forceinline__ double child_mean(const Grid &gf, const Grid &gc, int64_t pc, int scf,
+                                             Val &&val) {
+  if (scf == 1) return val(pc);
   const Ijk c = ijk(gc, pc);
   const int ax = gf.nx > 1 ? 2 : 1, ay = gf.ny > 1 ? 2 : 1, az = gf.nz > 1 ? 2 : 1;
-  ch.n = 0;
-  for (int c2 = 0; c2 < az; ++c2)
-    for (int b = 0; b < ay; ++b)
-      for (int a = 0; a < ax; ++a) {
-        const int64_t ix = (int64_t)c.ix * ax + a, iy = (int64_t)c.iy * ay + b,
-                      iz = (int64_t)c.iz * az + c2;
-        ch.idx[ch.n++] = ix + gf.nx * (iy + gf.ny * iz);
+  const int64_t sy = gf.nx, sz = (int64_t)gf.nx * gf.ny;
+  const int64_t base = (int64_t)c.ix * ax + sy * ((int64_t)c.iy * ay) + sz * ((int64_t)c.iz * az);
+  double s = 0.0;
+#pragma unroll
+  for (int c2 = 0; c2 < 2; ++c2) {
+    if (c2 < az) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (b < ay) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+            if (a < ax) s += val(base + a + sy * b + sz * c2);
+        }
       }
-  return ch;
+    }
+  }
+  return s * (1.0 / (ax * ay * az));
 }
 
 // One thread per (node, field): the field is the grid's y index.  Stage loops
@@ -1048,16 +1052,12 @@ k_restrict_stages(Grid gf, Grid gc, int scf, const double *Yf, int64_t sYf, int 
   if (pc >= gc.N) return;
   const int n = blockIdx.z;
   const int f = blockIdx.y;
-  const Children ch = children(gf, gc, pc, scf);
-  const double inv = 1.0 / ch.n;
   {
     double av[MAXM + 1];
 #pragma unroll
     for (int l = 0; l <= MAXM; ++l) {
-      double s = 0.0;
-      if (l <= Mf)
-        for (int k = 0; k < ch.n; ++k) s += Yf[n * sYf + ((int64_t)l * NF + f) * gf.Np + ch.idx[k]];
-      av[l] = s * inv;
+      const double *y = Yf + n * sYf + ((int64_t)l * NF + f) * gf.Np;
+      av[l] = (l <= Mf) ? child_mean(gf, gc, pc, scf, [&](int64_t q) { return y[q]; }) : 0.0;
     }
 #pragma unroll
     for (int i = 0; i <= MAXM; ++i) {
@@ -1090,11 +1090,8 @@ k_restrict_fields(Grid gf, Grid gc, int scf, const double *src, int64_t ssrc, do
   if (pc >= gc.N) return;
   const int n = blockIdx.z;
   const int r = blockIdx.y;  // one row per grid row
-  const Children ch = children(gf, gc, pc, scf);
-  const double inv = 1.0 / ch.n;
-  double s = 0.0;
-  for (int k = 0; k < ch.n; ++k) s += src[n * ssrc + (int64_t)r * gf.Np + ch.idx[k]];
-  dst[n * sdst + (int64_t)r * gc.Np + pc] = s * inv;
+  const double *x = src + n * ssrc + (int64_t)r * gf.Np;
+  dst[n * sdst + (int64_t)r * gc.Np + pc] = child_mean(gf, gc, pc, scf, [&](int64_t q) { return x[q]; });
 }
 
 hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
@@ -1108,76 +1105,86 @@ hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc,
 }
 
 // y_f += T P(z_c - S z): the coarse difference is formed on the fly at the (up
-// to 8) coarse cells that interpolate onto fine node p.
+// to 8) coarse cells that interpolate onto fine node p.  Per axis the two cells
+// and weights are kept in registers and the 2 x 2 x 2 taps are unrolled (an
+// axis of one node has weight 0 on its second cell and is skipped).
 __global__ void __launch_bounds__(BLOCK)
 k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz, int64_t sYc,
                   int Mc, const double *Tt, int Mf, double *Yf, int64_t sYf) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= gf.N) return;
   const int n = blockIdx.z;
-  int64_t idx[8];
-  double wt[8];
-  int nn = 0;
+  const int f = blockIdx.y;
+  int64_t ax0[3], ax1[3];  // coarse index offsets per axis (cell I and neighbour J)
+  double w0[3], w1[3];
   if (scf == 1) {
-    idx[0] = p;
-    wt[0] = 1.0;
-    nn = 1;
+    ax0[0] = p;
+    ax1[0] = p;
+    w0[0] = 1.0;
+    w1[0] = 0.0;
+    ax0[1] = ax1[1] = ax0[2] = ax1[2] = 0;
+    w0[1] = w0[2] = 1.0;
+    w1[1] = w1[2] = 0.0;
   } else {
     const Ijk c = ijk(gf, p);
-    int I0[3], I1[3];
-    double w0[3], w1[3];
     const int fi[3] = {c.ix, c.iy, c.iz};
     const int nf_[3] = {gf.nx, gf.ny, gf.nz};
     const int nc_[3] = {gc.nx, gc.ny, gc.nz};
+    const int64_t st[3] = {1, gc.nx, (int64_t)gc.nx * gc.ny};
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (nf_[a] > 1) {
         const int I = fi[a] >> 1;
-        const int side = fi[a] & 1;
-        int J = side ? I + 1 : I - 1;
+        int J = (fi[a] & 1) ? I + 1 : I - 1;
         J = J < 0 ? 0 : (J > nc_[a] - 1 ? nc_[a] - 1 : J);
-        I0[a] = I;
-        I1[a] = J;
+        ax0[a] = I * st[a];
+        ax1[a] = J * st[a];
         w0[a] = 0.75;
         w1[a] = 0.25;
       } else {
-        I0[a] = I1[a] = 0;
+        ax0[a] = ax1[a] = 0;
         w0[a] = 1.0;
         w1[a] = 0.0;
       }
     }
-    for (int cz = 0; cz < 2; ++cz)
-      for (int cy = 0; cy < 2; ++cy)
-        for (int cx = 0; cx < 2; ++cx) {
-          const double w = (cx ? w1[0] : w0[0]) * (cy ? w1[1] : w0[1]) * (cz ? w1[2] : w0[2]);
-          if (w == 0.0) continue;
-          const int ix = cx ? I1[0] : I0[0], iy = cy ? I1[1] : I0[1], iz = cz ? I1[2] : I0[2];
-          idx[nn] = ix + (int64_t)gc.nx * (iy + (int64_t)gc.ny * iz);
-          wt[nn] = w;
-          ++nn;
-        }
   }
-  const int f = blockIdx.y;
-  {
-    double dc[MAXM + 1];
+  double dc[MAXM + 1];
 #pragma unroll
-    for (int j = 0; j <= MAXM; ++j) {
-      double s = 0.0;
-      if (j <= Mc) {
-        const int64_t o = n * sYc + ((int64_t)j * NF + f) * gc.Np;
-        for (int k = 0; k < nn; ++k)
-          s += wt[k] * (Yc[o + idx[k]] - Sz[o + idx[k]]);
+  for (int j = 0; j <= MAXM; ++j) {
+    double s = 0.0;
+    if (j <= Mc) {
+      const int64_t o = n * sYc + ((int64_t)j * NF + f) * gc.Np;
+      const double *yc = Yc + o, *sz = Sz + o;
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        const double wz = cz ? w1[2] : w0[2];
+        if (wz == 0.0) continue;
+        const int64_t oz = cz ? ax1[2] : ax0[2];
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+          const double wy = cy ? w1[1] : w0[1];
+          if (wy == 0.0) continue;
+          const int64_t oy = oz + (cy ? ax1[1] : ax0[1]);
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) {
+            const double wx = cx ? w1[0] : w0[0];
+            if (wx == 0.0) continue;
+            const int64_t q = oy + (cx ? ax1[0] : ax0[0]);
+            s += (wx * wy * wz) * (yc[q] - sz[q]);
+          }
+        }
       }
-      dc[j] = s;
     }
+    dc[j] = s;
+  }
 #pragma unroll
-    for (int i = 0; i <= MAXM; ++i) {
-      if (i <= Mf) {
-        double s = 0.0;
+  for (int i = 0; i <= MAXM; ++i) {
+    if (i <= Mf) {
+      double s = 0.0;
 #pragma unroll
-        for (int j = 0; j <= MAXM; ++j)
-          if (j <= Mc) s += Tt[i * (Mc + 1) + j] * dc[j];
-        Yf[n * sYf + ((int64_t)i * NF + f) * gf.Np + p] += s;
-      }
+      for (int j = 0; j <= MAXM; ++j)
+        if (j <= Mc) s += Tt[i * (Mc + 1) + j] * dc[j];
+      Yf[n * sYf + ((int64_t)i * NF + f) * gf.Np + p] += s;
     }
   }
 }

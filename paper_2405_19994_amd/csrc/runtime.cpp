@@ -154,7 +154,7 @@ struct hsdc_ctx {
   int cg_fails = 0;  // unconverged budgeted solves found by flush_cg_log
   std::vector<CgLogEntry> cg_pending;
   Profiler prof;
-  // launch tuning (environment: HSDC_CG_BLOCKS, HSDC_CG_MARGIN)
+  // launch tuning (hsdc_tune): CG block cap and iteration-budget margin
   int tune_cg_blocks = 512;
   int tune_cg_margin = 2;
 };
@@ -394,7 +394,8 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
     L.cg_s[k] = dalloc<T>(c, (size_t)P * Np);
   }
   L.cg_p = dalloc<T>(c, (size_t)P * Np);
-  L.cg_pstride = std::max(L.cg_nblk, node_blocks(L.g));
+  // partials sized for the largest block cap hsdc_tune accepts
+  L.cg_pstride = std::max(cg_blocks(L.g, 2 * BLOCK), node_blocks(L.g));
   L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
@@ -811,8 +812,6 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
   if (meth->levels == 1 && meth->P > 1)
     return fail(nullptr, HSDC_EINVAL, "P > 1 needs levels = 2");
   hsdc_ctx *c = new hsdc_ctx();
-  if (const char *e = std::getenv("HSDC_CG_BLOCKS")) c->tune_cg_blocks = std::max(1, std::atoi(e));
-  if (const char *e = std::getenv("HSDC_CG_MARGIN")) c->tune_cg_margin = std::max(1, std::atoi(e));
   c->s = (hipStream_t)hip_stream;
   c->prob = *prob;
   c->meth = *meth;
@@ -931,8 +930,6 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
                       ": tissues of a batch differ only in nx, ny, nz, sigma_node and stim_w");
   }
   hsdc_ctx *c = new hsdc_ctx();
-  if (const char *e = std::getenv("HSDC_CG_BLOCKS")) c->tune_cg_blocks = std::max(1, std::atoi(e));
-  if (const char *e = std::getenv("HSDC_CG_MARGIN")) c->tune_cg_margin = std::max(1, std::atoi(e));
   c->s = (hipStream_t)hip_stream;
   c->prob = p0;
   c->meth = *meth;
@@ -1019,6 +1016,23 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
     return st;
   }
   *out = c;
+  return HSDC_OK;
+}
+
+hsdc_status hsdc_tune(hsdc_ctx *c, int32_t cg_blocks_cap, int32_t cg_margin) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (cg_blocks_cap > 2 * BLOCK) return fail(c, HSDC_EINVAL, "cg_blocks must be <= 1024");
+  if (cg_margin > 64) return fail(c, HSDC_EINVAL, "cg_margin must be <= 64");
+  if (cg_blocks_cap > 0) {
+    c->tune_cg_blocks = cg_blocks_cap;
+    for (int l = 0; l < c->nlev; ++l) {
+      if (l == 1 && c->cf32)
+        c->Lf.cg_nblk = cg_blocks(c->Lf.g, cg_blocks_cap);
+      else
+        c->L[l].cg_nblk = cg_blocks(c->L[l].g, cg_blocks_cap);
+    }
+  }
+  if (cg_margin > 0) c->tune_cg_margin = cg_margin;
   return HSDC_OK;
 }
 

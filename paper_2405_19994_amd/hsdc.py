@@ -73,6 +73,7 @@ def lib():
             "hsdc_init_batch": [ctypes.POINTER(Problem), i32, ctypes.POINTER(Method), vp, vp,
                                 ctypes.POINTER(vp)],
             "hsdc_sdc_sweep": [vp, i32, i32, i32],
+            "hsdc_tune": [vp, i32, i32],
             "hsdc_advance": [vp, i32],
             "hsdc_pfasst_iter": [vp, vp, vp],
             "hsdc_residual": [vp, i32, vp],
@@ -187,6 +188,10 @@ class Context:
         if self._ctx is None:
             raise HsdcError(-6, "context destroyed")
         return self._ctx
+
+    def tune(self, cg_blocks=0, cg_margin=0):
+        """CG block cap and budget margin for the following solves (0 keeps)."""
+        _check(lib().hsdc_tune(self.handle, int(cg_blocks), int(cg_margin)), self.handle)
 
     def sdc_sweep(self, nsweeps=1, level=0, slice=0):
         _check(lib().hsdc_sdc_sweep(self.handle, level, slice, nsweeps), self.handle)

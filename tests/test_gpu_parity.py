@@ -335,6 +335,25 @@ def test_batch_matches_single_contexts():
         ctx.sdc_sweep(1, slice=1)
 
 
+def test_tuned_launch_shapes_give_the_same_run():
+    """CG block cap and budget margin change launch shapes only: a context tuned
+    to 128 blocks and margin 3 matches an untuned one up to the order of the CG
+    reductions; out-of-range values are rejected."""
+    w = si.workload("slab2d", dims=(61, 47))
+    m = H.make_method(M=6, dt=w["dt"], max_iter=6, cg_rtol=1e-13, cg_maxit=300)
+    a = H.Context(lib_problem(w), m)
+    b = H.Context(lib_problem(w), m)
+    b.tune(128, 3)
+    with pytest.raises(H.HsdcError):
+        b.tune(4096, 0)
+    with pytest.raises(H.HsdcError):
+        b.tune(0, 100)
+    a.advance(12)
+    b.advance(12)
+    e = field_errors(host(b.get_state(0, 0, 0)), host(a.get_state(0, 0, 0)))
+    assert np.max(e) < 1e-11
+
+
 # ---------------------------------------------------------------------------
 # full size: the 512 x 512 slab in the benchmark's launch configuration
 # ---------------------------------------------------------------------------
