@@ -46,6 +46,8 @@ def _args():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="slab2d: replay each step from a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
                     help="slab2d: keep the default CG launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -408,7 +410,8 @@ def main():
                           w["stim_amp"], w["stim_t0"], w["stim_dur"])
     meth = H.make_method(M=(w["M"], 1), dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"],
                          cg_maxit=500)
-    stream = torch.cuda.current_stream()
+    # graph replay needs a stream other than the null stream
+    stream = torch.cuda.Stream() if a.graph else torch.cuda.current_stream()
 
     # launch-shape tuning before the timed region (cached per shape)
     tuning = None
@@ -423,6 +426,8 @@ def main():
         c = H.Context(prob, meth, None, stream)
         if tuning:
             c.tune(tuning["setting"]["cg_blocks"], tuning["setting"]["cg_margin"])
+        if a.graph:
+            c.use_graph(True)
         return c
 
     # warm-up on its own context (JIT of code objects, allocator, CG predictors)
@@ -485,6 +490,7 @@ def main():
                    "nodes": N, "M": w["M"], "sweeps": w["K"], "dt_ms": w["dt"],
                    "t_simulated_ms": a.steps * w["dt"]},
         "sim_ms_per_wall_s": a.steps * w["dt"] / wall,
+        "graph_replay": bool(a.graph),
         "gpu_event_ms": gpu_ms,
         "cg_iters_per_solve": st["cg_iters"] / max(1, st["cg_solves"]),
         "cg_unconverged": st["cg_unconverged"],

@@ -148,6 +148,19 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
  * between steps, not concurrently with work on the context. */
 hsdc_status hsdc_tune(hsdc_ctx *ctx, int32_t cg_blocks, int32_t cg_margin);
 
+/* Graph replay of serial steps (serial and batch contexts created on a
+ * non-null stream): hsdc_advance then captures one whole step (max_iter
+ * sweeps with their CG solves at predicted iteration budgets, y_{n+1} =
+ * y_{n,M}, the start of the next step) into a HIP graph and replays it once
+ * per step; the step number the kernels use is kept in device memory.  Every
+ * replay's solves are still verified; a step with a solve that missed cg_rtol
+ * is recomputed from the saved y_n with every solve checked, as without
+ * graphs.  Budgets rise at once and are lowered every 16 steps (to the most
+ * iterations used since, plus the margin); a step is captured again when they
+ * change.  Results equal those of stepping without graphs.  Kernel timing
+ * (hsdc_profile_enable) steps without graphs.  on = 0 releases the graph. */
+hsdc_status hsdc_use_graph(hsdc_ctx *ctx, int32_t on);
+
 /* Apply nsweeps preconditioned Picard iterations (eq. prec_picard, one forward
  * substitution with P^-1 of eq. def_P each) to the stage vector of one slice of
  * the fine level.  PFASST contexts keep the slice's start value y_{n,0}; serial

@@ -69,6 +69,7 @@ struct Stim {
   const double *w;  // [Np] (shared by the slices, sw = 0) or [P][Np] (sw = Np), or null
   int64_t sw;
   int64_t tn;
+  const int64_t *step;  // device: the current step (slice 0), read by the kernels
   double amp, t0, dur, eps;
   double Cm;
 };
@@ -90,20 +91,19 @@ struct CgScalars {
 template <class T>
 hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int stage0, int nstages, int64_t step0,
-                              T *L_anchor_out, const T *L_anchor_in);
+                              int nslices, int stage0, int nstages, T *L_anchor_out,
+                              const T *L_anchor_in);
 template <class T>
 hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, int slice0,
                               int nslices, int stage0, int nstages);
 hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                         const Stim &stim, int slice0, int nslices, int64_t step0,
-                         bool copy_Y_from_stage0);
+                         const Stim &stim, int slice0, int nslices, bool copy_Y_from_stage0);
 // spread != 0: stages 1..M are the spread of stage 0 (y^0 = 1 (x) y_n) and are
 // read from stage 0 (the stimulus part of the V reaction term follows t_{n,j}).
 template <class T>
 hipError_t launch_assemble(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                            int slice0, int nslices, const double *RI, int64_t sRI, int spread,
-                           const Stim &stim, int64_t step0);
+                           const Stim &stim);
 // RI[n][i][f] -= (A G)_i of the stage vector held by st (coarse FAS term of tau).
 template <class T>
 hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const StagesT<T> &st,
@@ -118,7 +118,7 @@ struct CgBatchT;
 template <class T>
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
                               const Colloc &co, const Stim &stim, double gs0, double gs1,
-                              double gs2, int slice0, int nslices, int i, int64_t step0,
+                              double gs2, int slice0, int nslices, int i,
                               const CgBatchT<T> &cb, int store_g, int spread);
 hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
                                    int nslices);
@@ -185,5 +185,8 @@ hipError_t launch_phi_test(hipStream_t s, int64_t n, const double *x, int kmax, 
 hipError_t launch_aij_test(hipStream_t s, int64_t n, const double *z, const Colloc &co,
                            double *out);
 hipError_t launch_fill_rest(hipStream_t s, int64_t N, int64_t Np, double *y);
+// device step counter: *step = value, or *step += add
+hipError_t launch_step_set(hipStream_t s, int64_t *step, int64_t value);
+hipError_t launch_step_add(hipStream_t s, int64_t *step, int64_t add);
 
 }  // namespace hsdc

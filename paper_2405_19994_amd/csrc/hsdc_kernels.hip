@@ -309,7 +309,8 @@ __device__ __forceinline__ double stim_value(const Stim &st, double t, int n, in
 template <class T>
 __global__ void __launch_bounds__(BLOCK)
 k_eval_stages(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int stage0, int64_t step0, T *Lout, const T *Lin) {
+              int slice0, int stage0, T *Lout, const T *Lin) {
+  const int64_t step0 = *stim.step;
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
   const Grid g = slice_grid(g0, n);
@@ -344,12 +345,12 @@ k_eval_stages(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
 template <class T>
 hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int slice0,
-                              int nslices, int stage0, int nstages, int64_t step0,
-                              T *L_anchor_out, const T *L_anchor_in) {
+                              int nslices, int stage0, int nstages, T *L_anchor_out,
+                              const T *L_anchor_in) {
   if (nslices <= 0 || nstages <= 0) return hipSuccess;
   dim3 grid(nblocks(g.N), nstages, nslices);
   hipLaunchKernelGGL(k_eval_stages<T>, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
-                     slice0, stage0, step0, L_anchor_out, L_anchor_in);
+                     slice0, stage0, L_anchor_out, L_anchor_in);
   return hipGetLastError();
 }
 
@@ -382,7 +383,8 @@ hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const StagesT<T> &st
 // Spread stage 0 (Y optionally, G, FV) to stages 1..M; the stimulus part of the
 // V entry of G follows the stage time.
 __global__ void __launch_bounds__(BLOCK)
-k_spread(Grid g0, Stages st, Colloc co, Stim stim, int slice0, int64_t step0, int copyY) {
+k_spread(Grid g0, Stages st, Colloc co, Stim stim, int slice0, int copyY) {
+  const int64_t step0 = *stim.step;
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
   if (p >= slice_grid(g0, n).N) return;
@@ -408,10 +410,9 @@ k_spread(Grid g0, Stages st, Colloc co, Stim stim, int slice0, int64_t step0, in
 }
 
 hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
-                         const Stim &stim, int slice0, int nslices, int64_t step0,
-                         bool copy_Y_from_stage0) {
+                         const Stim &stim, int slice0, int nslices, bool copy_Y_from_stage0) {
   dim3 grid(nblocks(g.N), 1, nslices);
-  hipLaunchKernelGGL(k_spread, grid, dim3(BLOCK), 0, s, g, st, co, stim, slice0, step0,
+  hipLaunchKernelGGL(k_spread, grid, dim3(BLOCK), 0, s, g, st, co, stim, slice0,
                      copy_Y_from_stage0 ? 1 : 0);
   return hipGetLastError();
 }
@@ -426,7 +427,8 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
 template <int M, class T>
 __global__ void __launch_bounds__(BLOCK)
 k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int64_t sRI, int spread,
-           Stim stim, int64_t step0) {
+           Stim stim) {
+  const int64_t step0 = *stim.step;
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int f = blockIdx.y;  // one field per block row: no divergence between field kinds
   const int n = slice0 + blockIdx.z;
@@ -479,10 +481,10 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
 template <class T>
 hipError_t launch_assemble(hipStream_t s, const Grid &g, const StagesT<T> &st, const Colloc &co,
                            int slice0, int nslices, const double *RI, int64_t sRI, int spread,
-                           const Stim &stim, int64_t step0) {
+                           const Stim &stim) {
   dim3 grid(nblocks(g.N), NF, nslices);
   HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_assemble<M, T>), grid, dim3(BLOCK), 0, s, g, st, co,
-                                           slice0, RI, sRI, spread, stim, step0));
+                                           slice0, RI, sRI, spread, stim));
   return hipGetLastError();
 }
 
@@ -532,8 +534,9 @@ hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const StagesT<T> &
 template <class T>
 __global__ void __launch_bounds__(BLOCK)
 k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int i, int64_t step0, CgBatchT<T> cb, int store_g, int spread) {
+              int slice0, int i, CgBatchT<T> cb, int store_g, int spread) {
   __shared__ double lds[BLOCK / 64];
+  const int64_t step0 = *stim.step;
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
   const Grid g = slice_grid(g0, n);
@@ -607,11 +610,11 @@ int node_blocks(const Grid &g) { return (int)nblocks(g.N); }
 template <class T>
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
                               const Colloc &co, const Stim &stim, double gs0, double gs1,
-                              double gs2, int slice0, int nslices, int i, int64_t step0,
+                              double gs2, int slice0, int nslices, int i,
                               const CgBatchT<T> &cb, int store_g, int spread) {
   dim3 grid(nblocks(g.N), 1, nslices);
   hipLaunchKernelGGL(k_node_update<T>, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
-                     slice0, i, step0, cb, store_g, spread);
+                     slice0, i, cb, store_g, spread);
   return hipGetLastError();
 }
 
@@ -1281,23 +1284,38 @@ hipError_t launch_fill_rest(hipStream_t s, int64_t N, int64_t Np, double *y) {
   return hipGetLastError();
 }
 
+// The device step counter read by the time-dependent kernels (a captured
+// step advances it inside the graph).
+__global__ void k_step_set(int64_t *step, int64_t value, int64_t add) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *step = (add != 0) ? *step + add : value;
+}
+
+hipError_t launch_step_set(hipStream_t s, int64_t *step, int64_t value) {
+  hipLaunchKernelGGL(k_step_set, dim3(1), dim3(64), 0, s, step, value, (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_add(hipStream_t s, int64_t *step, int64_t add) {
+  hipLaunchKernelGGL(k_step_set, dim3(1), dim3(64), 0, s, step, (int64_t)0, add);
+  return hipGetLastError();
+}
+
 // ---- instantiations for the two storage types -------------------------------
 #define HSDC_INSTANTIATE(T)                                                                   \
   template hipError_t launch_eval_stages<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
                                             const Colloc &, const Stim &, double, double,    \
-                                            double, int, int, int, int, int64_t, T *,        \
-                                            const T *);                                      \
+                                            double, int, int, int, int, T *, const T *);     \
   template hipError_t launch_spmv_stages<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
                                             int, int, int, int);                             \
   template hipError_t launch_assemble<T>(hipStream_t, const Grid &, const StagesT<T> &,       \
                                          const Colloc &, int, int, const double *, int64_t,  \
-                                         int, const Stim &, int64_t);                        \
+                                         int, const Stim &);                                 \
   template hipError_t launch_fas_integrals<T>(hipStream_t, const Grid &, const StagesT<T> &,  \
                                               const Colloc &, int, int, double *, int64_t);  \
   template hipError_t launch_node_update<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
                                             const Colloc &, const Stim &, double, double,    \
-                                            double, int, int, int, int64_t,                  \
-                                            const CgBatchT<T> &, int, int);                  \
+                                            double, int, int, int, const CgBatchT<T> &, int, \
+                                            int);                                            \
   template hipError_t launch_cg_init<T>(hipStream_t, const Grid &, const CgBatchT<T> &);      \
   template hipError_t launch_cg_resid0<T>(hipStream_t, const Grid &, const CgBatchT<T> &);    \
   template hipError_t launch_cg_iter<T>(hipStream_t, const Grid &, const CgBatchT<T> &, int);

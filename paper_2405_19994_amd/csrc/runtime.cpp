@@ -86,6 +86,7 @@ struct LevelT {
   double *RI = nullptr;   // fine: time-restricted integrals [P][Mc][NF][Np]; coarse: FAS term
   double *y0c = nullptr;  // coarse: restricted block start value [NF][Np]
   int cg_pred[16][MAXM];  // iteration budget per (sweep index, node)
+  int cg_umax[16][MAXM];  // most iterations used since the last relaxation (graph mode)
 };
 using Level = LevelT<double>;
 
@@ -132,6 +133,7 @@ struct hsdc_ctx {
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
   double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices
   int64_t step = 0;
+  int64_t *d_step = nullptr;  // device copy of step, read by the kernels
   int sweeps_done = 0;  // serial: sweeps applied to the current step
   int sweep_index = 0;
   bool pfasst = false;
@@ -154,6 +156,17 @@ struct hsdc_ctx {
   int cg_fails = 0;  // unconverged budgeted solves found by flush_cg_log
   std::vector<CgLogEntry> cg_pending;
   Profiler prof;
+  // graph replay of serial steps (hsdc_use_graph): one captured step, replayed
+  // while the CG budgets it was captured with stay in force
+  bool graph_on = false;
+  bool graph_dirty = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<CgLogEntry> graph_pending;
+  int graph_log_used = 0;
+  int64_t graph_sweeps = 0, graph_ionic = 0;  // counters of one captured step
+  int64_t graph_steps = 0;
+  double *ybak = nullptr;  // [P][NF][Np] start value of the step being replayed
   // launch tuning (hsdc_tune): CG block cap and iteration-budget margin
   int tune_cg_blocks = 512;
   int tune_cg_margin = 2;
@@ -413,6 +426,8 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   }
   for (auto &row : L.cg_pred)
     for (int &v : row) v = 8;
+  for (auto &row : L.cg_umax)
+    for (int &v : row) v = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -479,10 +494,15 @@ void flush_cg_log(hsdc_ctx *c) {
     // budget = iterations needed + 2, lowered by at most one per check; doubled
     // after a miss (a spare no-op iteration costs far less than a recomputed step)
     int &pred = pred_table(c, e.lev)[e.row & 15][e.i - 1];
-    if (ok_all)
-      pred = std::max(used + c->tune_cg_margin, pred - 1);
-    else
+    if (!ok_all)
       pred = std::min(c->meth.cg_maxit + 1, std::max(2 * e.budget, used + 4));
+    else if (c->graph_on && e.lev == 0) {
+      // graph replay: raise at once, lower only at a relaxation (every 16 steps)
+      pred = std::max(pred, used + c->tune_cg_margin);
+      int &um = c->L[0].cg_umax[e.row & 15][e.i - 1];
+      um = std::max(um, used);
+    } else
+      pred = std::max(used + c->tune_cg_margin, pred - 1);
   }
   c->cg_pending.clear();
   c->cg_log_used = 0;
@@ -543,10 +563,10 @@ void evaluate_all(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns) {
   const double N = slice_nodes(c, L, s0, ns) / ns;
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N * ns,
           launch_eval_stages<T>(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                             p.g_scale[2], s0, ns, 0, 1, c->step, L.st.L0, nullptr));
+                             p.g_scale[2], s0, ns, 0, 1, L.st.L0, nullptr));
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns * M,
           launch_eval_stages<T>(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                             p.g_scale[2], s0, ns, 1, M, c->step, nullptr, L.st.L0));
+                             p.g_scale[2], s0, ns, 1, M, nullptr, L.st.L0));
   PLAUNCH(c, PC_SPMV, 16.0 * (M + 1) * N * ns,
           launch_spmv_stages<T>(c->s, L.g, L.st, s0, ns, 0, M + 1));
   c->stats.ionic_evals += (int64_t)(N * ns) * (M + 1);
@@ -571,7 +591,6 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
   const hsdc_problem &p = c->prob;
   const int M = co.M;
   const double N = slice_nodes(c, L, s0, ns) / ns;
-  const int64_t step0 = c->step;
   const int64_t sRI = (int64_t)M * NF * L.g.Np;
   const int spread = (lev == 0 && c->spread_pending) ? 1 : 0;
   if (u_src) {
@@ -584,14 +603,14 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
     const double per = spread ? (NF + 1 + NG + M * NF)
                               : ((M + 1) * NF + M + NG + M * NF + (RI ? M * NF : 0));
     PLAUNCH(c, PC_ASSEMBLE, 8.0 * per * N * ns,
-            launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI, spread, c->stim[lev], step0));
+            launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI, spread, c->stim[lev]));
   }
   for (int i = 1; i <= M; ++i) {
     const CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
     const double per = ((i == 1) ? 90.0 : (drop_terms ? 83.0 : 102.0)) * sizeof(T) / 8.0;
     PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
             launch_node_update(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                               p.g_scale[2], s0, ns, i, step0, cb, drop_terms ? 0 : 1, spread));
+                               p.g_scale[2], s0, ns, i, cb, drop_terms ? 0 : 1, spread));
     if (i > 1) c->stats.ionic_evals += (int64_t)(N * ns);
     cg_solve(c, L, lev, s0, ns, i, pred_row);
   }
@@ -601,7 +620,7 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
     // sweep or the residual (stages 1..M-1 were stored by the node updates)
     PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns,
             launch_eval_stages<T>(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                               p.g_scale[2], s0, ns, M, 1, step0, nullptr, L.st.L0));
+                               p.g_scale[2], s0, ns, M, 1, nullptr, L.st.L0));
     c->stats.ionic_evals += (int64_t)(N * ns);
     PLAUNCH(c, PC_SPMV, 16.0 * M * N * ns, launch_spmv_stages<T>(c->s, L.g, L.st, s0, ns, 1, M));
   }
@@ -620,7 +639,7 @@ void begin_serial_step(hsdc_ctx *c) {
   const double N = slice_nodes(c, L, 0, P);
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N,
           launch_eval_stages<double>(c->s, L.g, L.st, L.co, c->stim[0], p.g_scale[0],
-                                     p.g_scale[1], p.g_scale[2], 0, P, 0, 1, c->step, L.st.L0,
+                                     p.g_scale[1], p.g_scale[2], 0, P, 0, 1, L.st.L0,
                                      nullptr));
   PLAUNCH(c, PC_SPMV, 16.0 * N, launch_spmv_stages<double>(c->s, L.g, L.st, 0, P, 0, 1));
   PLAUNCH(c, PC_COPY, 8.0 * (1 + L.co.M) * N, launch_copy_V_to_stages(c->s, L.g, L.st, 0, P));
@@ -635,7 +654,7 @@ void begin_serial_step(hsdc_ctx *c) {
 void materialize(hsdc_ctx *c) {
   if (!c->spread_pending) return;
   Level &L = c->L[0];
-  HIPC(launch_spread(c->s, L.g, L.st, L.co, c->stim[0], 0, L.P, c->step, true));
+  HIPC(launch_spread(c->s, L.g, L.st, L.co, c->stim[0], 0, L.P, true));
   c->spread_pending = false;
 }
 
@@ -781,6 +800,109 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// graph replay of serial steps
+// ---------------------------------------------------------------------------
+void graph_release(hsdc_ctx *c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+// Capture one serial step from the state begin_serial_step leaves: save y_n,
+// max_iter budgeted sweeps, y_{n+1} = y_{n,M}, advance the device step
+// counter, begin the next step.  The host-side counters and the CG log
+// entries of the step are kept for the replays.
+void capture_serial_step(hsdc_ctx *c) {
+  Level &F = c->L[0];
+  graph_release(c);
+  c->cg_pending.clear();
+  c->cg_log_used = 0;
+  const hsdc_stats before = c->stats;
+  const int K = c->meth.max_iter;
+  HIPC(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+  try {
+    HIPC(launch_copy_fields(c->s, F.g.Np, c->ybak, F.st.sS(), F.st.Y, F.st.sY(), NF, F.P));
+    c->safe_cg = false;
+    for (int k = 0; k < K; ++k)
+      sweep(c, F, 0, 0, F.P, nullptr, nullptr, c->sweep_index++, k == K - 1);
+    HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, F.st.sY(), F.st.Y + (int64_t)F.co.M * F.st.sS(),
+                            F.st.sY(), NF, F.P));
+    HIPC(launch_step_add(c->s, c->d_step, 1));
+    begin_serial_step(c);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    hipStreamEndCapture(c->s, &g);
+    if (g) hipGraphDestroy(g);
+    c->cg_pending.clear();
+    c->cg_log_used = 0;
+    c->stats = before;
+    throw;
+  }
+  HIPC(hipStreamEndCapture(c->s, &c->graph));
+  HIPC(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->graph_pending = c->cg_pending;
+  c->graph_log_used = c->cg_log_used;
+  c->cg_pending.clear();
+  c->cg_log_used = 0;
+  c->graph_sweeps = c->stats.sweeps - before.sweeps;
+  c->graph_ionic = c->stats.ionic_evals - before.ionic_evals;
+  c->stats = before;
+  c->graph_dirty = false;
+}
+
+// One serial step by graph replay; a step whose budgeted solve missed cg_rtol
+// is recomputed from the saved y_n with every solve checked.
+void graph_step(hsdc_ctx *c) {
+  Level &F = c->L[0];
+  if (c->graph_dirty || !c->gexec) capture_serial_step(c);
+  c->cg_pending = c->graph_pending;
+  c->cg_log_used = c->graph_log_used;
+  c->cg_fails = 0;
+  int pred0[16][MAXM];
+  std::memcpy(pred0, F.cg_pred, sizeof(pred0));
+  HIPC(hipGraphLaunch(c->gexec, c->s));
+  c->stats.sweeps += c->graph_sweeps;
+  c->stats.ionic_evals += c->graph_ionic;
+  flush_cg_log(c);
+  if (c->cg_fails > 0) {
+    c->stats.cg_redo_steps += 1;
+    c->cg_fails = 0;
+    HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, F.st.sY(), c->ybak, F.st.sS(), NF, F.P));
+    HIPC(launch_step_set(c->s, c->d_step, c->step));
+    c->safe_cg = true;
+    begin_serial_step(c);
+    while (c->sweeps_done < c->meth.max_iter) {
+      const bool last = c->sweeps_done == c->meth.max_iter - 1;
+      sweep(c, F, 0, 0, F.P, nullptr, nullptr, c->sweep_index++, last);
+      c->sweeps_done += 1;
+    }
+    HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, F.st.sY(), F.st.Y + (int64_t)F.co.M * F.st.sS(),
+                            F.st.sY(), NF, F.P));
+    HIPC(launch_step_add(c->s, c->d_step, 1));
+    begin_serial_step(c);
+  }
+  // host flags as begin_serial_step leaves them (a replay does not rerun host code)
+  c->spread_pending = true;
+  c->sweeps_done = 0;
+  c->sweep_index = 0;
+  c->safe_cg = true;
+  c->step += 1;
+  c->stats.steps += 1;
+  c->graph_steps += 1;
+  if (c->graph_steps % 16 == 0) {
+    // relaxation: budgets down to the most iterations used since the last one
+    for (int r = 0; r < 16; ++r)
+      for (int i = 0; i < MAXM; ++i)
+        if (F.cg_umax[r][i] > 0) {
+          F.cg_pred[r][i] = F.cg_umax[r][i] + c->tune_cg_margin;
+          F.cg_umax[r][i] = 0;
+        }
+  }
+  if (std::memcmp(pred0, F.cg_pred, sizeof(pred0)) != 0) c->graph_dirty = true;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 namespace {
@@ -828,6 +950,7 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
     alloc_level(c, F, meth->M[0], P, false, Mc);
     if (prob->sigma_node) build_faces(c, F, prob->sigma_node);
     c->y0blk = dalloc<double>(c, (size_t)NF * F.g.Np);
+    c->d_step = dalloc<int64_t>(c, 1);  // step 0
     c->cg_log_cap = 8192;
     c->cg_log = halloc<CgScalars>(c, c->cg_log_cap);
     c->cg_dlog = dalloc<CgScalars>(c, c->cg_log_cap);
@@ -837,6 +960,7 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
                           hipMemcpyDeviceToDevice, c->s));
     }
     for (int l = 0; l < 2; ++l) {
+      c->stim[l].step = c->d_step;
       c->stim[l].tn = 1;  // slice n is time step step + n
       c->stim[l].amp = prob->stim_amp;
       c->stim[l].t0 = prob->stim_t0;
@@ -979,6 +1103,7 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
       F.g.ky = p0.dim >= 2 ? F.kface[1] : nullptr;
       F.g.kz = p0.dim >= 3 ? F.kface[2] : nullptr;
     }
+    c->d_step = dalloc<int64_t>(c, 1);  // step 0
     c->cg_log_cap = std::max(8192, 64 * count);
     c->cg_log = halloc<CgScalars>(c, c->cg_log_cap);
     c->cg_dlog = dalloc<CgScalars>(c, c->cg_log_cap);
@@ -991,6 +1116,7 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
     c->stim[0].w = F.stim_w;
     c->stim[0].sw = Np;
     c->stim[0].tn = 0;  // every tissue is at the same time step
+    c->stim[0].step = c->d_step;
     c->stim[0].amp = p0.stim_amp;
     c->stim[0].t0 = p0.stim_t0;
     c->stim[0].dur = p0.stim_dur;
@@ -1036,6 +1162,23 @@ hsdc_status hsdc_tune(hsdc_ctx *c, int32_t cg_blocks_cap, int32_t cg_margin) {
   return HSDC_OK;
 }
 
+hsdc_status hsdc_use_graph(hsdc_ctx *c, int32_t on) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (on && c->pfasst) return fail(c, HSDC_EINVAL, "graph replay is for serial and batch contexts");
+  if (on && c->s == nullptr)
+    return fail(c, HSDC_EINVAL, "graph replay needs a context created on a non-null stream");
+  Level &F = c->L[0];
+  if (on && (int64_t)c->meth.max_iter * F.co.M * F.P > c->cg_log_cap)
+    return fail(c, HSDC_EINVAL, "a step has more solves than the CG log holds");
+  return run_guarded(c, [&]() -> hsdc_status {
+    if (on && !c->ybak) c->ybak = dalloc<double>(c, (size_t)F.P * NF * F.g.Np);
+    if (!on) graph_release(c);
+    c->graph_on = on != 0;
+    c->graph_dirty = true;
+    return HSDC_OK;
+  });
+}
+
 hsdc_status hsdc_sdc_sweep(hsdc_ctx *c, int32_t level, int32_t slice, int32_t nsweeps) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
   if (level != 0) return fail(c, HSDC_EINVAL, "level must be 0");
@@ -1063,7 +1206,9 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
   return run_guarded(c, [&]() -> hsdc_status {
     Level &F = c->L[0];
     for (int s = 0; s < nsteps; ++s) {
-      if (!c->pfasst) {
+      if (!c->pfasst && c->graph_on && !c->prof.on && c->sweeps_done == 0) {
+        graph_step(c);
+      } else if (!c->pfasst) {
         // budgeted solves, verified once per step; a step with a solve that
         // missed cg_rtol is recomputed from y_n with every solve checked
         c->safe_cg = false;
@@ -1089,6 +1234,7 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
         HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, F.st.sY(),
                                 F.st.Y + (int64_t)F.co.M * F.st.sS(), F.st.sY(), NF, F.P));
         c->step += 1;
+        HIPC(launch_step_add(c->s, c->d_step, 1));
         c->stats.steps += 1;
         begin_serial_step(c);
       } else {
@@ -1103,6 +1249,7 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
                                     (int64_t)F.co.M * F.st.sS(),
                                 0, NF, 1));
         c->step += F.P;
+        HIPC(launch_step_add(c->s, c->d_step, F.P));
         c->stats.steps += F.P;
         begin_block(c);
       }
@@ -1235,6 +1382,7 @@ void hsdc_destroy(hsdc_ctx *c) {
   } catch (...) {
   }
   for (hipEvent_t e : c->prof.pool) hipEventDestroy(e);
+  graph_release(c);
   if (c->s) hipStreamSynchronize(c->s);
   else hipDeviceSynchronize();
   for (void *p : c->allocs) hipFree(p);

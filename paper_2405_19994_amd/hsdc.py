@@ -74,6 +74,7 @@ def lib():
                                 ctypes.POINTER(vp)],
             "hsdc_sdc_sweep": [vp, i32, i32, i32],
             "hsdc_tune": [vp, i32, i32],
+            "hsdc_use_graph": [vp, i32],
             "hsdc_advance": [vp, i32],
             "hsdc_pfasst_iter": [vp, vp, vp],
             "hsdc_residual": [vp, i32, vp],
@@ -192,6 +193,10 @@ class Context:
     def tune(self, cg_blocks=0, cg_margin=0):
         """CG block cap and budget margin for the following solves (0 keeps)."""
         _check(lib().hsdc_tune(self.handle, int(cg_blocks), int(cg_margin)), self.handle)
+
+    def use_graph(self, on=True):
+        """Replay serial steps from a captured HIP graph (needs a non-null stream)."""
+        _check(lib().hsdc_use_graph(self.handle, 1 if on else 0), self.handle)
 
     def sdc_sweep(self, nsweeps=1, level=0, slice=0):
         _check(lib().hsdc_sdc_sweep(self.handle, level, slice, nsweeps), self.handle)
