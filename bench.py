@@ -52,7 +52,8 @@ def _args():
                     help="slab2d: keep the default CG launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d"), default="slab2d")
+    ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d", "cable1d"),
+                    default="slab2d")
     ap.add_argument("--tissues", type=int, default=64, help="batch2d: tissues in the batch")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
@@ -383,6 +384,52 @@ def summarize_counters(fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
+def bench_cable1d(a):
+    """The 1D cable (128 nodes, M 4, K 4, dt 0.05 ms, T 10 ms): a latency-bound
+    serial run, timed with eager launches and with each step replayed from a
+    captured HIP graph."""
+    import torch
+
+    import synthetic_inputs as si
+    from paper_2405_19994_amd import hsdc as H
+
+    w = si.workload("cable1d")
+    N = int(np.prod(w["dims"]))
+    steps = a.steps if a.steps != 400 else int(round(w["t_end"] / w["dt"]))
+    dev = torch.device("cuda:0")
+    stim = torch.tensor(w["stim_w"], dtype=torch.float64, device=dev)
+    prob = H.make_problem(w["dims"], w["dx"], w["sigma"], None, w["chi"], w["Cm"], (1, 1, 1), stim,
+                          w["stim_amp"], w["stim_t0"], w["stim_dur"])
+    meth = H.make_method(M=w["M"], dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"], cg_maxit=300)
+    stream = torch.cuda.Stream()
+    res = {}
+    for graph in (False, True):
+        for rep in range(2):  # the first pass warms up
+            ctx = H.Context(prob, meth, None, stream)
+            if graph:
+                ctx.use_graph(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.advance(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = ctx.stats()
+            ctx.destroy()
+        res[graph] = {"wall_s": wall, "ms_per_step": 1e3 * wall / steps,
+                      "node_updates_per_s": N * w["M"] * w["K"] * steps / wall,
+                      "cg_redo_steps": st["cg_redo_steps"]}
+    value = res[True]["node_updates_per_s"]
+    print(json.dumps({
+        "metric": "SDC node-updates/s (serial hybrid SDC, FP64, steps replayed from a HIP graph)",
+        "value": value, "unit": "node-updates/s", "n_gpus": 1, "steps": steps, "warmup": steps,
+        "ms_per_step": res[True]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "cable1d 128 nodes, dx 0.01 cm, TTP06, M4 K4, dt 0.05 ms, T 10 ms",
+                   "nodes": N, "M": w["M"], "sweeps": w["K"], "dt_ms": w["dt"]},
+        "eager": res[False], "graph": res[True],
+        "graph_speedup": res[False]["wall_s"] / res[True]["wall_s"]}))
+
+
 def main():
     a = _args()
     if a.summarize_counters:
@@ -396,6 +443,9 @@ def main():
         return
     if a.workload == "batch2d":
         bench_batch2d(a)
+        return
+    if a.workload == "cable1d":
+        bench_cable1d(a)
         return
     import torch
 
