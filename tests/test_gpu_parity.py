@@ -443,3 +443,52 @@ def test_slab2d_full_size_uniform_state_is_a_single_cell():
     cell = oracle_problem(dict(w, dims=(1,), stim_w=np.zeros(1)))
     ref = run_serial(Level(cell, 6, w["dt"]), y1[:, None], 20, 6)
     assert np.max(field_errors(g[:, :1], ref)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# full size: the 3D PFASST workload and the 64-tissue batch
+# ---------------------------------------------------------------------------
+
+def test_slab3d_full_size_pfasst_reaches_serial_collocation():
+    """At full size (192 x 96 x 48, 16 slices, fine M 6, coarse M 3 on the 2x
+    coarser mesh, dt 0.1 ms) one block iterated to tol 1e-10 reaches the same
+    state as serial HSDC swept to its collocation solution (40 sweeps a step):
+    the fixed point of Algorithm 1 is the serial collocation solution at any
+    size."""
+    w = si.workload("slab3d")
+    prob = lib_problem(w)
+    m = H.make_method(M=(6, 3), levels=2, space_coarsen=2, P=16, dt=w["dt"], max_iter=60,
+                      tol=1e-10, burn_in=1, cg_rtol=1e-13, cg_maxit=500)
+    ctx = H.Context(prob, m)
+    ctx.advance(1)
+    assert ctx.step == 16
+    y_pf = host(ctx.get_state(0, 0, 0))
+    ctx.destroy()
+    ref = H.Context(prob, H.make_method(M=6, dt=w["dt"], max_iter=40, cg_rtol=1e-13, cg_maxit=500))
+    ref.advance(16)
+    y_ref = host(ref.get_state(0, 0, 0))
+    ref.destroy()
+    assert np.all(np.isfinite(y_pf))
+    assert np.max(field_errors(y_pf, y_ref)) < 1e-6
+    assert y_ref[0].max() > 0.0  # the face stimulus started an action potential
+
+
+def test_batch2d_full_size_tissues_equal_single_contexts():
+    """The 64-tissue batch at full size (sides 64..512, 6.05M nodes, M 4, K 4):
+    after 4 steps through the stimulus onset, sampled tissues (the smallest, the
+    largest and two others) equal their own single contexts bitwise."""
+    ws = si.batch2d_tissues(64, seed=0)
+    m = H.make_method(M=4, dt=ws[0]["dt"], max_iter=4, cg_rtol=1e-12, cg_maxit=500)
+    probs = [lib_problem(w) for w in ws]
+    ctx = H.BatchContext(probs, m)
+    ctx.advance(4)
+    sizes = [p.N for p in probs]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 42})
+    for n in picks:
+        single = H.Context(probs[n], m)
+        single.advance(4)
+        a = host(ctx.get_state(0, n, 0))
+        b = host(single.get_state(0, 0, 0))
+        single.destroy()
+        assert np.array_equal(a, b), (n, ws[n]["dims"])
+
