@@ -1107,14 +1107,29 @@ hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc,
   return hipGetLastError();
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin in launch order, and each XCD
+// has its own L2.  For a grid whose x extent nbx is a multiple of 8, block x
+// runs on XCD x % 8; mapping it to node block (x % 8) nbx/8 + x / 8 gives every
+// XCD one contiguous range of nodes, so data shared by neighbouring node blocks
+// stays in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_node_block(int64_t bx, int64_t nbx) {
+  return (bx % kXcds) * (nbx / kXcds) + bx / kXcds;
+}
+static inline unsigned nblocks_xcd(int64_t n) {
+  const unsigned nb = nblocks(n);
+  return (nb + kXcds - 1) / kXcds * kXcds;
+}
+
 // y_f += T P(z_c - S z): the coarse difference is formed on the fly at the (up
 // to 8) coarse cells that interpolate onto fine node p.  Per axis the two cells
 // and weights are kept in registers and the 2 x 2 x 2 taps are unrolled (an
-// axis of one node has weight 0 on its second cell and is skipped).
+// axis of one node has weight 0 on its second cell and is skipped).  Fine node
+// blocks sharing coarse cells run on one XCD (xcd_node_block).
 __global__ void __launch_bounds__(BLOCK)
 k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz, int64_t sYc,
                   int Mc, const double *Tt, int Mf, double *Yf, int64_t sYf) {
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t p = xcd_node_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (p >= gf.N) return;
   const int n = blockIdx.z;
   const int f = blockIdx.y;
@@ -1196,7 +1211,7 @@ hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc,
                                   const double *Yc, const double *Sz, int64_t sYc, int Mc,
                                   const double *Tt, int Mf, double *Yf, int64_t sYf,
                                   int nslices) {
-  hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks(gf.N), NF, nslices), dim3(BLOCK), 0, s,
+  hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks_xcd(gf.N), NF, nslices), dim3(BLOCK), 0, s,
                      gf, gc, sc_factor, Yc, Sz, sYc, Mc, Tt, Mf, Yf, sYf);
   return hipGetLastError();
 }
