@@ -296,6 +296,28 @@ __device__ __forceinline__ double applyK(const Grid &g, int64_t p, const Ijk &c,
 
 static inline unsigned nblocks(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
+// Workgroups are dealt to the 8 XCDs round-robin in launch order, and each XCD
+// has its own L2.  For a grid whose x extent nbx is a multiple of 8, block x
+// runs on XCD x % 8; mapping it to node block (x % 8) nbx/8 + x / 8 gives every
+// XCD one contiguous range of nodes, so data shared by neighbouring node blocks
+// stays in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_node_block(int64_t bx, int64_t nbx) {
+  return (bx % kXcds) * (nbx / kXcds) + bx / kXcds;
+}
+static inline unsigned nblocks_xcd(int64_t n) {
+  const unsigned nb = nblocks(n);
+  return (nb + kXcds - 1) / kXcds * kXcds;
+}
+
+// Node block of a stencil kernel's block: XCD-ordered (the stencil's neighbour
+// rows are read by adjacent node blocks) unless the grid's x extent is not a
+// multiple of 8 or the slices are a ragged batch (whose partial sums are read
+// in launch order by active block).
+__device__ __forceinline__ int64_t stencil_node_block(const Grid &g0, int64_t bx, int64_t nbx) {
+  return (g0.rag == nullptr && nbx % kXcds == 0) ? xcd_node_block(bx, nbx) : bx;
+}
+
 // ---------------------------------------------------------------------------
 // cell model at stages: G_j = f_E + f_e + Lambda(u)(u - y_j) (reaction part of g)
 // ---------------------------------------------------------------------------
@@ -358,7 +380,7 @@ hipError_t launch_eval_stages(hipStream_t s, const Grid &g, const StagesT<T> &st
 template <int DIM, bool PN, class T>
 __global__ void __launch_bounds__(BLOCK) k_spmv_stages(Grid g0, StagesT<T> st, int slice0,
                                                        int stage0) {
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t p = stencil_node_block(g0, blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
   const Grid g = slice_grid(g0, n);
   if (p >= g.N) return;
@@ -374,7 +396,7 @@ template <class T>
 hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, int slice0,
                               int nslices, int stage0, int nstages) {
   if (nslices <= 0 || nstages <= 0) return hipSuccess;
-  dim3 grid(nblocks(g.N), nstages, nslices);
+  dim3 grid(g.rag ? nblocks(g.N) : nblocks_xcd(g.N), nstages, nslices);
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_spmv_stages<DIM, PN, T>), grid, dim3(BLOCK), 0, s, g,
                                          st, slice0, stage0));
   return hipGetLastError();
@@ -783,7 +805,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g0, CgBatchT<T> cb) {
   const double *b = cb.b + n * cb.sb;
   T *r = cb.r[0] + n * g.Np;
   double rr = 0.0, bb = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
+  for (int64_t p = stencil_node_block(g0, blockIdx.x, cb.nblk) * BLOCK + threadIdx.x; p < g.N;
+       p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
     const double xc = x[p];
     const double bv = b[p];
@@ -811,7 +834,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g0, CgBatchT<T> cb) {
   const T *r = cb.r[0] + n * g.Np;
   T *w = cb.w[0] + n * g.Np;
   double del = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
+  for (int64_t p = stencil_node_block(g0, blockIdx.x, cb.nblk) * BLOCK + threadIdx.x; p < g.N;
+       p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
     const double rc = r[p];
     const double wv = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, [&](int64_t k) { return (double)r[k]; });
@@ -858,7 +882,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   double gamma, delta;
   // first owned node: its stencil loads are issued before the partial sums
   // are combined, so the reduction latency overlaps the memory traffic
-  const int64_t p0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t p0 = stencil_node_block(g0, blockIdx.x, cb.nblk) * BLOCK + threadIdx.x;
   double r_c = 0.0, w_c = 0.0, s_c = 0.0, rn_[2 * DIM], wn_[2 * DIM], sn_[2 * DIM];
   Ijk c0{0, 0, 0};
   if (si.it == 0) {
@@ -1105,20 +1129,6 @@ hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc,
   hipLaunchKernelGGL(k_restrict_fields, grid, dim3(BLOCK), 0, s, gf, gc, sc_factor, src,
                      ssrc, dst, sdst, nrows);
   return hipGetLastError();
-}
-
-// Workgroups are dealt to the 8 XCDs round-robin in launch order, and each XCD
-// has its own L2.  For a grid whose x extent nbx is a multiple of 8, block x
-// runs on XCD x % 8; mapping it to node block (x % 8) nbx/8 + x / 8 gives every
-// XCD one contiguous range of nodes, so data shared by neighbouring node blocks
-// stays in one L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int64_t xcd_node_block(int64_t bx, int64_t nbx) {
-  return (bx % kXcds) * (nbx / kXcds) + bx / kXcds;
-}
-static inline unsigned nblocks_xcd(int64_t n) {
-  const unsigned nb = nblocks(n);
-  return (nb + kXcds - 1) / kXcds * kXcds;
 }
 
 // y_f += T P(z_c - S z): the coarse difference is formed on the fly at the (up
