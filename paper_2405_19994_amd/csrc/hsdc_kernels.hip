@@ -310,10 +310,14 @@ static inline unsigned nblocks_xcd(int64_t n) {
   return (nb + kXcds - 1) / kXcds * kXcds;
 }
 
-// Node block of a stencil kernel's block: XCD-ordered (the stencil's neighbour
-// rows are read by adjacent node blocks) unless the grid's x extent is not a
-// multiple of 8 or the slices are a ragged batch (whose partial sums are read
-// in launch order by active block).
+// Node block of a kernel's block: XCD-ordered (a stencil's neighbour rows are
+// read by adjacent node blocks, and the node update, the CG start and the CG
+// iterations then place each node block on the same XCD) unless the grid's x
+// extent is not a multiple of 8 or the slices are a ragged batch (whose partial
+// sums are read in launch order by active block).  A block stores its partial
+// sums at its node block's index, so every reduction adds the same partials in
+// the same order whatever the placement (a batch's tissue and its own single
+// context agree bitwise).
 __device__ __forceinline__ int64_t stencil_node_block(const Grid &g0, int64_t bx, int64_t nbx) {
   return (g0.rag == nullptr && nbx % kXcds == 0) ? xcd_node_block(bx, nbx) : bx;
 }
@@ -559,7 +563,8 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
               int slice0, int i, CgBatchT<T> cb, int store_g, int spread) {
   __shared__ double lds[BLOCK / 64];
   const int64_t step0 = *stim.step;
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t qb = stencil_node_block(g0, blockIdx.x, gridDim.x);
+  const int64_t p = qb * BLOCK + threadIdx.x;
   const int n = slice0 + blockIdx.z;
   const Grid g = slice_grid(g0, n);
   const int64_t Np = st.Np;
@@ -622,19 +627,21 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
   const double tr = block_sum(rr, lds);
   if (threadIdx.x == 0) {
     double *part = cb.part + (int64_t)(n - slice0) * 5 * cb.pstride;
-    part[4 * cb.pstride + blockIdx.x] = tb;
-    part[blockIdx.x] = tr;
+    part[4 * cb.pstride + qb] = tb;
+    part[qb] = tr;
   }
 }
 
-int node_blocks(const Grid &g) { return (int)nblocks(g.N); }
+// Blocks of a node-update launch (XCD-padded unless the slices are a ragged batch);
+// the first CG iteration reduces this many partials.
+int node_blocks(const Grid &g) { return (int)(g.rag ? nblocks(g.N) : nblocks_xcd(g.N)); }
 
 template <class T>
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
                               const Colloc &co, const Stim &stim, double gs0, double gs1,
                               double gs2, int slice0, int nslices, int i,
                               const CgBatchT<T> &cb, int store_g, int spread) {
-  dim3 grid(nblocks(g.N), 1, nslices);
+  dim3 grid(node_blocks(g), 1, nslices);
   hipLaunchKernelGGL(k_node_update<T>, grid, dim3(BLOCK), 0, s, g, st, co, stim, gs0, gs1, gs2,
                      slice0, i, cb, store_g, spread);
   return hipGetLastError();
@@ -805,8 +812,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g0, CgBatchT<T> cb) {
   const double *b = cb.b + n * cb.sb;
   T *r = cb.r[0] + n * g.Np;
   double rr = 0.0, bb = 0.0;
-  for (int64_t p = stencil_node_block(g0, blockIdx.x, cb.nblk) * BLOCK + threadIdx.x; p < g.N;
-       p += (int64_t)cb.nblk * BLOCK) {
+  const int64_t qb = stencil_node_block(g0, blockIdx.x, cb.nblk);
+  for (int64_t p = qb * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
     const double xc = x[p];
     const double bv = b[p];
@@ -819,8 +826,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g0, CgBatchT<T> cb) {
   const double tr = block_sum(rr, lds);
   const double tb = block_sum(bb, lds);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = tr;
-    part[4 * cb.pstride + blockIdx.x] = tb;
+    part[qb] = tr;
+    part[4 * cb.pstride + qb] = tb;
   }
 }
 
@@ -834,8 +841,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g0, CgBatchT<T> cb) {
   const T *r = cb.r[0] + n * g.Np;
   T *w = cb.w[0] + n * g.Np;
   double del = 0.0;
-  for (int64_t p = stencil_node_block(g0, blockIdx.x, cb.nblk) * BLOCK + threadIdx.x; p < g.N;
-       p += (int64_t)cb.nblk * BLOCK) {
+  const int64_t qb = stencil_node_block(g0, blockIdx.x, cb.nblk);
+  for (int64_t p = qb * BLOCK + threadIdx.x; p < g.N; p += (int64_t)cb.nblk * BLOCK) {
     const Ijk c = ijk(g, p);
     const double rc = r[p];
     const double wv = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, [&](int64_t k) { return (double)r[k]; });
@@ -845,7 +852,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g0, CgBatchT<T> cb) {
   double *part = cb.part + (int64_t)n * 5 * cb.pstride;
   const double td = block_sum(del, lds);
   if (threadIdx.x == 0) {
-    part[cb.pstride + blockIdx.x] = td;
+    part[cb.pstride + qb] = td;
     if (blockIdx.x == 0) {
       CgScalars o;
       o.bb = -1.0;  // reduced by the first iteration kernel
@@ -863,7 +870,10 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   __shared__ double lds[BLOCK / 64];
   const int n = blockIdx.y;
   const Grid g = slice_grid(g0, cb.slice0 + n);
-  const int nba = active_blocks(g, cb.nblk), nba0 = active_blocks(g, cb.nblk0);
+  // a ragged batch skips the blocks past a small tissue; otherwise every block of
+  // the producing launch wrote a partial (padding blocks write zeros)
+  const int nba = active_blocks(g, cb.nblk);
+  const int nba0 = g0.rag ? active_blocks(g, cb.nblk0) : cb.nblk0;
   if ((int)blockIdx.x >= nba) return;
   const int in = k & 1, out = in ^ 1;
   CgScalars si = cb.sc[2 * n + in];
@@ -882,7 +892,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   double gamma, delta;
   // first owned node: its stencil loads are issued before the partial sums
   // are combined, so the reduction latency overlaps the memory traffic
-  const int64_t p0 = stencil_node_block(g0, blockIdx.x, cb.nblk) * BLOCK + threadIdx.x;
+  const int64_t qb = stencil_node_block(g0, blockIdx.x, cb.nblk);
+  const int64_t p0 = qb * BLOCK + threadIdx.x;
   double r_c = 0.0, w_c = 0.0, s_c = 0.0, rn_[2 * DIM], wn_[2 * DIM], sn_[2 * DIM];
   Ijk c0{0, 0, 0};
   if (si.it == 0) {
@@ -985,8 +996,8 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   const double tg = block_sum(gam, lds);
   const double td = block_sum(del, lds);
   if (threadIdx.x == 0) {
-    part[(2 * out) * cb.pstride + blockIdx.x] = tg;
-    part[(2 * out + 1) * cb.pstride + blockIdx.x] = td;
+    part[(2 * out) * cb.pstride + qb] = tg;
+    part[(2 * out + 1) * cb.pstride + qb] = td;
   }
   if (publish) {
     CgScalars o = si;
