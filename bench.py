@@ -48,6 +48,11 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="slab2d: replay each step from a captured HIP graph")
+    ap.add_argument("--solver", choices=("cg", "chebyshev"), default="cg",
+                    help="slab2d: diffusion solver of the reported line (the workload names CG); "
+                         "the other solver is timed beside it as an option study")
+    ap.add_argument("--no-solver-option", action="store_true",
+                    help="slab2d: skip timing the other diffusion solver")
     ap.add_argument("--no-autotune", action="store_true",
                     help="slab2d: keep the default CG launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -458,8 +463,11 @@ def main():
     stim = torch.tensor(w["stim_w"], dtype=torch.float64, device=dev)
     prob = H.make_problem(w["dims"], w["dx"], w["sigma"], None, w["chi"], w["Cm"], (1, 1, 1), stim,
                           w["stim_amp"], w["stim_t0"], w["stim_dur"])
-    meth = H.make_method(M=(w["M"], 1), dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"],
-                         cg_maxit=500)
+    def method(solver):
+        return H.make_method(M=(w["M"], 1), dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"],
+                             cg_maxit=500, solver=solver)
+
+    meth = method(a.solver)
     # graph replay needs a stream other than the null stream
     stream = torch.cuda.Stream() if a.graph else torch.cuda.current_stream()
 
@@ -472,8 +480,8 @@ def main():
                                          use_cache=False)
         tuning = {"setting": setting, "candidates": timings}
 
-    def new_context():
-        c = H.Context(prob, meth, None, stream)
+    def new_context(m=None):
+        c = H.Context(prob, m or meth, None, stream)
         if tuning:
             c.tune(tuning["setting"]["cg_blocks"], tuning["setting"]["cg_margin"])
         if a.graph:
@@ -511,11 +519,7 @@ def main():
     kp = ctx.profile_read()
     pst = ctx.stats()
     ctx.destroy()
-    # CG iterations that did work move 80 B/node (r, w, s, p, x read and
-    # written); the first of a solve reads neither s nor p (64 B); early-exit
-    # launches move nothing
-    b_cg = (pst["cg_iters"] - pst["cg_solves"]) * 80.0 * N + pst["cg_solves"] * 64.0 * N
-    kernels = _kernel_table(kp, {"cg_iter": b_cg})
+    kernels = _kernel_table(kp, _solver_bytes(pst, N))
     dom = max(kernels, key=lambda k: kernels[k]["time_share"])
     traffic = _traffic(dom)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["GBps"], "peak": 8000.0,
@@ -536,7 +540,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "slab2d 512x512, 5-point, TTP06, M6 K6, dt 0.05 ms, CG 1e-12",
+        "config": {"workload": "slab2d 512x512, 5-point, TTP06, M6 K6, dt 0.05 ms, "
+                               + ("CG" if a.solver == "cg" else "Chebyshev") + " 1e-12",
                    "nodes": N, "M": w["M"], "sweeps": w["K"], "dt_ms": w["dt"],
                    "t_simulated_ms": a.steps * w["dt"]},
         "sim_ms_per_wall_s": a.steps * w["dt"] / wall,
@@ -561,9 +566,52 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = src.numel() * 8
         del evict
+    if not a.no_solver_option:
+        # option study: the same workload and tolerance with the other solver
+        other = "chebyshev" if a.solver == "cg" else "cg"
+        m2 = method(other)
+        if a.warmup > 0:
+            cw = new_context(m2)
+            cw.advance(a.warmup)
+            torch.cuda.synchronize()
+            cw.destroy()
+        c2 = new_context(m2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c2.advance(a.steps)
+        torch.cuda.synchronize()
+        wall2 = time.perf_counter() - t0
+        st2 = c2.stats()
+        V2 = c2.get_state(0, 0, 0)
+        c2.destroy()
+        c2 = new_context(m2)
+        c2.profile(True)
+        c2.advance(prof_steps)
+        torch.cuda.synchronize()
+        kp2, pst2 = c2.profile_read(), c2.stats()
+        c2.destroy()
+        out["solver_option"] = {
+            "solver": other, "value": updates / wall2, "ms_per_step": 1e3 * wall2 / a.steps,
+            "iters_per_solve": st2["cg_iters"] / max(1, st2["cg_solves"]),
+            "unconverged": st2["cg_unconverged"], "redo_steps": st2["cg_redo_steps"],
+            "V_max_end_mV": float(V2[0].max()),
+            "kernels": _kernel_table(kp2, _solver_bytes(pst2, N)),
+        }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
+
+
+def _solver_bytes(pst, N):
+    """Algorithmic bytes of the diffusion-solver classes of a profiled serial run
+    on N nodes.  CG iterations that did work move 80 B/node (r, w, s, p, x read
+    and written); the first of a solve reads neither s nor p (64 B); early-exit
+    launches move nothing.  A Chebyshev iterate beyond x_1 (which the node update
+    forms) reads x_k, x_{k-1} and b and writes x_{k+1}: 32 B/node.  Only the
+    class the run used appears in its table."""
+    iters, solves = pst["cg_iters"], pst["cg_solves"]
+    return {"cg_iter": (iters - solves) * 80.0 * N + solves * 64.0 * N,
+            "cheb_iter": max(0, iters - solves) * 32.0 * N}
 
 
 if __name__ == "__main__":

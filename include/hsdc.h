@@ -88,6 +88,13 @@ typedef struct {
   double tol;                /* PFASST stop: all ||r_n||_inf < tol ||y_n||_inf;   */
                              /* tol <= 0 runs exactly max_iter iterations         */
   int32_t burn_in;           /* 1: staggered coarse burn-in before a block, P > 1 */
+  int32_t solver;            /* diffusion solves on FP64 levels: 0 conjugate      */
+                             /* gradients; 1 Chebyshev iteration over the         */
+                             /* Gershgorin interval of I - a K (no inner          */
+                             /* products: the iteration count comes from the      */
+                             /* residual bound of the Chebyshev polynomial, the   */
+                             /* same ||b - A x||_2 <= cg_rtol ||b||_2).  An FP32  */
+                             /* coarse level always runs CG.                      */
   double cg_rtol;            /* diffusion solve: ||b - A x||_2 <= cg_rtol ||b||_2 */
   int32_t cg_maxit;          /* iteration cap per diffusion solve                 */
   int32_t coarse_fp32;       /* levels = 2: 1 runs the coarse level's cell model  */
@@ -107,7 +114,8 @@ typedef struct {
   int64_t sweeps;            /* sweeps on the fine level                          */
   int64_t coarse_sweeps;     /* sweeps on the coarse level (incl. burn-in)        */
   int64_t cg_solves;         /* diffusion solves                                  */
-  int64_t cg_iters;          /* CG iterations over all solves                     */
+  int64_t cg_iters;          /* solver iterations over all solves (Chebyshev:    */
+                             /* the degree of the residual polynomial)            */
   int64_t cg_unconverged;    /* solves that hit cg_maxit                          */
   int64_t pfasst_iters;      /* PFASST iterations                                 */
   int64_t ionic_evals;       /* node-wise cell-model evaluations (x mesh nodes)   */
@@ -200,7 +208,7 @@ hsdc_status hsdc_get_stats(const hsdc_ctx *ctx, hsdc_stats *out);
  * (the distinct bytes the launch must read and write, counted from the sizes)
  * are accumulated.  Enabling adds a small per-launch overhead.  Classes:
  * "node_update", "assemble", "cg_init", "cg_iter", "eval_stages", "spmv",
- * "residual", "transfer", "copy", "fas_integrals" (at most 16). */
+ * "residual", "transfer", "copy", "fas_integrals", "cheb_iter" (at most 16). */
 typedef struct {
   char name[32];
   int64_t launches;

@@ -131,6 +131,18 @@ int residual_blocks(const Grid &g);
 hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sdst,
                               const double *src, int64_t ssrc, int nf, int nslices);
 
+// Chebyshev parameters of one diffusion operator I - a K whose spectrum lies in
+// [1, 1 + a lam] (lam bounds the spectrum of -K): theta and delta are the
+// centre and half-width of that interval, sigma = theta / delta, s =
+// acosh(sigma) (s = 0 when delta = 0, A = I), and omega[k - 1] =
+// omega_{k+1} = 2 sigma T_k(sigma) / T_{k+1}(sigma) for k = 1..CHEB_KT
+// (host-computed per slice and collocation node).
+constexpr int CHEB_KT = 61;
+struct ChebTab {
+  double inv_theta, sigma, s;
+  double omega[CHEB_KT];
+};
+
 // CG on (I - a K) x = b, batched over slices with strided vectors
 // (Chronopoulos-Gear single-reduction form: one stencil kernel per iteration).
 // The solution and right-hand side are FP64; the work vectors are stored in T;
@@ -155,6 +167,14 @@ struct CgBatchT {
   double a, tol2;
   int maxit;
   int rel_r0;
+  // Chebyshev iteration (FP64 levels; xt == null selects CG): the node update
+  // stores b in bout and x_1 = x_0 + r_0 / theta in xt, x_0 staying in x;
+  // iterate k overwrites x_{k-1} with x_{k+1}, so x_k alternates between x (k
+  // even) and xt (k odd) and the iteration count is rounded up to even.
+  double *xt;                   // [nslices][Np]
+  double *bout;                 // [nslices][Np] (the memory b points to)
+  const struct ChebTab *tab;    // this node's entry of absolute slice n: tab[n * tab_stride]
+  int tab_stride;
 };
 using CgBatch = CgBatchT<double>;
 int cg_blocks(const Grid &g, int cap = 512);
@@ -165,6 +185,9 @@ hipError_t launch_cg_resid0(hipStream_t s, const Grid &g, const CgBatchT<T> &cb)
 template <class T>
 hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatchT<T> &cb, int k);
 hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out);
+// Chebyshev iterate k >= 1 (one launch per k; launch k = 1 also derives the
+// iteration count from the node update's partials of ||r_0||^2 and ||b||^2).
+hipError_t launch_cheb_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k);
 
 // transfers (space coarsening 2x or identity) between a fine and a coarse level
 hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,

@@ -619,7 +619,13 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
     const double bv = yd[0] + RH[p] + ddt * (double)gV;
     const double x0 = Yi[p];
     const double r0 = bv - x0 + cb.a * st.FV[n * st.sFV() + (int64_t)(spread ? 0 : i) * Np + p];
-    cb.r[0][(int64_t)(n - slice0) * Np + p] = T(r0);
+    if (cb.xt) {
+      // Chebyshev: b and the first iterate x_1 = x_0 + r_0 / theta
+      cb.bout[(int64_t)(n - slice0) * Np + p] = bv;
+      cb.xt[(int64_t)(n - slice0) * Np + p] = x0 + r0 * cb.tab[n * cb.tab_stride].inv_theta;
+    } else {
+      cb.r[0][(int64_t)(n - slice0) * Np + p] = T(r0);
+    }
     bb = bv * bv;
     rr = r0 * r0;
   }
@@ -1044,6 +1050,106 @@ __global__ void __launch_bounds__(BLOCK) k_apply_K(Grid g, const double *v, doub
 hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out) {
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_apply_K<DIM, PN>), dim3(nblocks(g.N)), dim3(BLOCK), 0,
                                          s, g, v, out));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev iteration on A x = b, A = I - a K.  The spectrum of A lies in
+// [1, 1 + a lam] (lam: Gershgorin bound on the spectrum of -K); theta and delta
+// are the centre and half-width of that interval and sigma = theta / delta.
+// After m steps the residual is r_m = T_m((theta - A) / delta) r_0 / T_m(sigma),
+// so ||r_m|| <= ||r_0|| / T_m(sigma) for symmetric A: the iteration needs no
+// inner products, and the count follows from ||r_0|| and ||b|| alone.  Three-
+// term form: x_1 = x_0 + r_0 / theta,
+//   x_{k+1} = x_{k-1} + omega_{k+1} (x_k - x_{k-1} + (b - A x_k) / theta),
+//   omega_{k+1} = 2 sigma T_k(sigma) / T_{k+1}(sigma).
+// ---------------------------------------------------------------------------
+
+// omega_{k+1}, k >= 1, from the table or, past it, with T_k(sigma) = cosh(k s):
+// cosh(k s) / cosh((k+1) s) = e^{-s} (1 + e^{-2ks}) / (1 + e^{-2(k+1)s}).
+__device__ __forceinline__ double cheb_omega(const ChebTab &t, int k) {
+  if (k <= CHEB_KT) return t.omega[k - 1];
+  if (t.s == 0.0) return 1.0;
+  return 2.0 * t.sigma * exp(-t.s) * (1.0 + exp(-2.0 * k * t.s)) / (1.0 + exp(-2.0 * (k + 1) * t.s));
+}
+
+// Iteration count: the smallest even m >= 2 with T_m(sigma) >= 2 ||r_0|| / (rtol
+// ref) (ref = ||b||, or ||r_0|| for a solve relative to the warm start; the
+// factor 2 covers rounding), capped at maxit.  *bound receives the bound
+// ||r_0||^2 / T_m(sigma)^2 on ||r_m||^2 (NaN inputs give NaN).  The first
+// launch forms x_2 whatever the count, so m is at least 2 (x_2 only improves
+// on x_0).
+__device__ __forceinline__ int cheb_count(const ChebTab &t, double rr0, double ref2, double tol2,
+                                          int maxit, double *bound) {
+  int m = 2;
+  if (rr0 == rr0 && ref2 == ref2 && t.s > 0.0 && rr0 > tol2 * ref2) {
+    const double ratio = 2.0 * sqrt(rr0 / (tol2 * ref2));  // > 2, also for ref2 = 0 (inf)
+    const double mr = acosh(ratio) / t.s;
+    m = mr < (double)maxit ? (int)ceil(mr) : maxit;
+    m = (m + 1) & ~1;
+    if (m > maxit) m = maxit & ~1;
+    if (m < 2) m = 2;
+  }
+  const double tm = t.s == 0.0 ? INFINITY : cosh(m * t.s);
+  *bound = (rr0 == rr0 && ref2 == ref2) ? rr0 / (tm * tm) : rr0 + ref2;
+  return m;
+}
+
+// Launch k >= 1 forms x_{k+1} over x_{k-1}.  Blocks [0, nbx) own nodes; launch 1
+// has one more block per slice that reduces the node update's partials of
+// ||r_0||^2 and ||b||^2 and publishes the count while the others iterate.
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(BLOCK) k_cheb_iter(Grid g0, CgBatch cb, int k, int nbx) {
+  __shared__ double lds[BLOCK / 64];
+  const int n = blockIdx.y;
+  const ChebTab &t = cb.tab[(cb.slice0 + n) * cb.tab_stride];
+  CgScalars *sc = cb.sc + 2 * n;
+  if ((int)blockIdx.x >= nbx) {
+    const double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+    const double rr0 = reduce_partials(part, cb.nblk0, lds);
+    const double ref2 = cb.rel_r0 ? rr0 : reduce_partials(part + 4 * cb.pstride, cb.nblk0, lds);
+    if (threadIdx.x == 0) {
+      double bound;
+      CgScalars o;
+      o.it = cheb_count(t, rr0, ref2, cb.tol2, cb.maxit, &bound);
+      o.bb = ref2;
+      o.gamma = bound;
+      o.alpha = 0.0;
+      o.done = o.it <= 2;  // x_2, written by this launch, is in x
+      sc[0] = o;
+      if (cb.log && k == cb.last_k) cb.log[n] = o;
+    }
+    return;
+  }
+  if (k > 1) {
+    const int m = sc[0].it;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[0].done = k + 1 >= m;
+      if (cb.log && k == cb.last_k) cb.log[n] = sc[0];
+    }
+    if (k >= m) return;
+  }
+  const Grid g = slice_grid(g0, cb.slice0 + n);
+  const int64_t p = stencil_node_block(g0, blockIdx.x, nbx) * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int64_t Np = g0.Np;
+  const double *xk = (k & 1) ? cb.xt + (int64_t)n * Np : cb.x + n * cb.sx;
+  double *xm = (k & 1) ? cb.x + n * cb.sx : cb.xt + (int64_t)n * Np;
+  const double *b = cb.b + n * cb.sb;
+  const double om = cheb_omega(t, k);
+  const Ijk c = ijk(g, p);
+  const double xc = xk[p];
+  const double r = b[p] - (xc - cb.a * applyK<DIM, PN>(g, p, c, xc, [&](int64_t q) { return xk[q]; }));
+  const double xo = xm[p];
+  xm[p] = xo + om * (xc - xo + t.inv_theta * r);
+}
+
+hipError_t launch_cheb_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k) {
+  if (cb.nslices <= 0) return hipSuccess;
+  const int nbx = (int)(g.rag ? nblocks(g.N) : nblocks_xcd(g.N));
+  dim3 grid(nbx + (k == 1 ? 1 : 0), cb.nslices);
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cheb_iter<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb,
+                                         k, nbx));
   return hipGetLastError();
 }
 

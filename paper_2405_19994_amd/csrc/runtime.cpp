@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "hsdc_internal.h"
@@ -73,6 +74,10 @@ struct LevelT {
   T *cg_r[2] = {nullptr, nullptr}, *cg_w[2] = {nullptr, nullptr};
   T *cg_s[2] = {nullptr, nullptr}, *cg_p = nullptr;
   double *cg_part = nullptr;
+  // Chebyshev solver (FP64 levels with solver 1): second iterate buffer and the
+  // parameters of every (slice, collocation node) operator
+  double *cheb_x = nullptr;      // [P][Np]
+  ChebTab *cheb_tab = nullptr;   // [P][M]
   CgScalars *cg_sc = nullptr;       // [P][2]
   CgScalars *cg_sc_host = nullptr;  // [P][2]
   int cg_nblk = 0;
@@ -93,15 +98,17 @@ using Level = LevelT<double>;
 // A diffusion solve whose outcome is checked later (budgeted mode).
 struct CgLogEntry {
   int lev, s0, ns, i, row, parity, off, budget;
+  bool cheb;
 };
 
 }  // namespace
 
 namespace {
 enum ProfClass { PC_NODE, PC_ASSEMBLE, PC_CGINIT, PC_CGITER, PC_EVAL, PC_SPMV, PC_RESIDUAL,
-                 PC_TRANSFER, PC_COPY, PC_FAS, PC_COUNT };
+                 PC_TRANSFER, PC_COPY, PC_FAS, PC_CHEB, PC_COUNT };
 const char *kProfNames[PC_COUNT] = {"node_update", "assemble", "cg_init", "cg_iter", "eval_stages",
-                                    "spmv", "residual", "transfer", "copy", "fas_integrals"};
+                                    "spmv", "residual", "transfer", "copy", "fas_integrals",
+                                    "cheb_iter"};
 struct ProfPending {
   int cls;
   int launches;
@@ -331,6 +338,7 @@ bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why)
   if (!(m->cg_rtol > 0) || !(m->cg_rtol < 1)) return why = "cg_rtol must be in (0, 1)", false;
   if (m->cg_maxit < 1) return why = "cg_maxit must be >= 1", false;
   if (m->coarse_fp32 != 0 && m->coarse_fp32 != 1) return why = "coarse_fp32 must be 0 or 1", false;
+  if (m->solver != 0 && m->solver != 1) return why = "solver must be 0 (CG) or 1 (Chebyshev)", false;
   if (!std::isfinite(m->coarse_cg_rtol) || !(m->coarse_cg_rtol < 1))
     return why = "coarse_cg_rtol must be finite and < 1", false;
   return true;
@@ -370,6 +378,60 @@ std::vector<double> face_coeffs(int a, int nx, int ny, int nz, const std::vector
   return k;
 }
 
+// Gershgorin bound on the spectrum of -K (symmetric, positive semidefinite):
+// twice the largest sum of the face coefficients around a node.
+double lam_uniform(int dim, int nx, int ny, int nz, double cx, double cy, double cz) {
+  const int n[3] = {nx, ny, nz};
+  const double k[3] = {cx, cy, cz};
+  double row = 0.0;
+  for (int a = 0; a < dim; ++a) row += k[a] * std::min(2, n[a] - 1);
+  return 2.0 * row;
+}
+
+double lam_faces(int dim, int nx, int ny, int nz, const std::vector<double> *k) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t strides[3] = {1, nx, (int64_t)nx * ny};
+  const int sizes[3] = {nx, ny, nz};
+  double best = 0.0;
+  for (int64_t p = 0; p < N; ++p) {
+    double row = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      row += k[a][p];  // face p -> p + e_a (0 on the last layer)
+      if ((p / strides[a]) % sizes[a] > 0) row += k[a][p - strides[a]];
+    }
+    best = std::max(best, row);
+  }
+  return 2.0 * best;
+}
+
+// Chebyshev parameters of I - a K with lam bounding the spectrum of -K.
+ChebTab cheb_entry(double a, double lam) {
+  ChebTab t{};
+  const double delta = 0.5 * a * lam, theta = 1.0 + delta;
+  t.inv_theta = 1.0 / theta;
+  t.sigma = delta > 0.0 ? theta / delta : 0.0;
+  t.s = delta > 0.0 ? std::acosh(t.sigma) : 0.0;
+  for (int k = 1; k <= CHEB_KT; ++k)
+    t.omega[k - 1] = t.s == 0.0 ? 1.0
+                                : 2.0 * t.sigma * std::exp(-t.s) * (1.0 + std::exp(-2.0 * k * t.s)) /
+                                      (1.0 + std::exp(-2.0 * (k + 1) * t.s));
+  return t;
+}
+
+// Per-slice spectral bounds -> the level's Chebyshev table (levels running
+// Chebyshev; a = dt d_i for collocation node i).
+template <class T>
+void set_lam(hsdc_ctx *c, LevelT<T> &L, const std::vector<double> &lam) {
+  if (!L.cheb_tab) return;
+  const int M = L.co.M;
+  std::vector<ChebTab> tab((size_t)L.P * M);
+  for (int n = 0; n < L.P; ++n)
+    for (int i = 0; i < M; ++i) tab[(size_t)n * M + i] = cheb_entry(L.co.dt * L.co.d[i], lam[n]);
+  HIPC(hipMemcpyAsync(L.cheb_tab, tab.data(), tab.size() * sizeof(ChebTab), hipMemcpyHostToDevice,
+                      c->s));
+  HIPC(hipStreamSynchronize(c->s));
+}
+
 template <class T>
 void build_faces(hsdc_ctx *c, LevelT<T> &L, const double *sigma_node_dev) {
   const Grid &g = L.g;
@@ -377,12 +439,14 @@ void build_faces(hsdc_ctx *c, LevelT<T> &L, const double *sigma_node_dev) {
   HIPC(hipMemcpyAsync(s.data(), sigma_node_dev, g.N * sizeof(double), hipMemcpyDeviceToHost, c->s));
   HIPC(hipStreamSynchronize(c->s));
   const double sc = 1.0 / (c->prob.dx * c->prob.dx * c->prob.chi * c->prob.Cm);
+  std::vector<double> kh[3];
   for (int a = 0; a < g.dim; ++a) {
-    const std::vector<double> k = face_coeffs(a, g.nx, g.ny, g.nz, s, sc);
+    kh[a] = face_coeffs(a, g.nx, g.ny, g.nz, s, sc);
     L.kface[a] = dalloc<double>(c, g.N);
-    HIPC(hipMemcpyAsync(L.kface[a], k.data(), g.N * sizeof(double), hipMemcpyHostToDevice, c->s));
+    HIPC(hipMemcpyAsync(L.kface[a], kh[a].data(), g.N * sizeof(double), hipMemcpyHostToDevice, c->s));
   }
   HIPC(hipStreamSynchronize(c->s));
+  set_lam(c, L, std::vector<double>(L.P, lam_faces(g.dim, g.nx, g.ny, g.nz, kh)));
   L.g.kx = L.kface[0];
   L.g.ky = g.dim >= 2 ? L.kface[1] : nullptr;
   L.g.kz = g.dim >= 3 ? L.kface[2] : nullptr;
@@ -412,6 +476,12 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
+  if (std::is_same<T, double>::value && c->meth.solver == 1) {
+    L.cheb_x = dalloc<double>(c, (size_t)P * Np);
+    L.cheb_tab = dalloc<ChebTab>(c, (size_t)P * M);
+    set_lam(c, L, std::vector<double>(P, lam_uniform(L.g.dim, L.g.nx, L.g.ny, L.g.nz, L.g.cx,
+                                                     L.g.cy, L.g.cz)));
+  }
   if (!coarse_extras) {  // the residual is taken on the fine level only
     L.res_nblk = residual_blocks(L.g);
     L.res_part = dalloc<double>(c, (size_t)P * 2 * L.res_nblk);
@@ -463,11 +533,28 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
   // FP32 work vectors: solve the correction from the warm start to a relative
   // accuracy, so that the solve error shrinks with the defect
   cb.rel_r0 = (lev == 1 && c->cf32) ? 1 : 0;
+  if (L.cheb_x) {
+    cb.xt = L.cheb_x + s0 * Np;
+    cb.bout = L.st.B + s0 * Np;
+    cb.tab = L.cheb_tab + (i - 1);
+    cb.tab_stride = L.co.M;
+  }
   return cb;
 }
 
+// A finished solve met the tolerance (Chebyshev: gamma is the bound on the
+// final ||r||^2 and bb the reference).
 bool cg_ok(const CgScalars &sc, double tol2) {
   return sc.done && (sc.gamma <= tol2 * sc.bb || sc.gamma == 0.0);
+}
+
+// Launches a solve needed, minus one, as the budget predictor counts them: CG
+// ends with the launch that finds convergence (it + 1 launches).  Chebyshev's
+// launch k forms x_{k+1} and the node update x_1, so an even count m takes
+// max(1, m - 1) launches; since m moves in steps of 2 it is counted as m (one
+// spare launch more than CG).
+int budget_use(const CgScalars &sc, bool cheb) {
+  return cheb ? std::max(0, sc.it - 1) : sc.it;
 }
 
 // Check every budgeted solve enqueued since the last check (one host
@@ -486,7 +573,7 @@ void flush_cg_log(hsdc_ctx *c) {
       const CgScalars &sc = c->cg_log[e.off + n];
       const bool ok = cg_ok(sc, tol2);
       ok_all = ok_all && ok;
-      used = std::max(used, sc.it);
+      used = std::max(used, budget_use(sc, e.cheb));
       c->stats.cg_iters += sc.it;
       c->stats.cg_solves += 1;
       if (!ok) ++fails;
@@ -509,9 +596,62 @@ void flush_cg_log(hsdc_ctx *c) {
   c->cg_fails += fails;
 }
 
+// Chebyshev solve of node i (the node update stored b and x_1).  Budgeted mode
+// enqueues the predicted number of launches (those past the count the first
+// launch derives exit at once) and logs the outcome; safe mode launches until
+// every slice is done, checking on the host.
+void cheb_solve(hsdc_ctx *c, Level &L, int lev, int s0, int ns, int i, int pred_row, CgBatch cb) {
+  const double nodes = slice_nodes(c, L, s0, ns);
+  int &pred = L.cg_pred[pred_row & 15][i - 1];
+  const int cap = std::max(1, cb.maxit);
+  if (!c->safe_cg) {
+    if (c->cg_log_used + ns > c->cg_log_cap) flush_cg_log(c);  // log full: verify now
+    const int budget = std::max(1, std::min(pred, cap));
+    cb.log = c->cg_dlog + c->cg_log_used;
+    cb.last_k = budget;
+    ProfScope ps(c, PC_CHEB, 32.0 * nodes * budget);
+    for (int k = 1; k <= budget; ++k) HIPC(launch_cheb_iter(c->s, L.g, cb, k));
+    ps.end(budget);
+    c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget, true});
+    c->cg_log_used += ns;
+    return;
+  }
+  int k = 1;
+  int batch = std::max(1, std::min(pred, cap));
+  for (;;) {
+    int nl = 0;
+    ProfScope ps(c, PC_CHEB, 0.0);
+    for (int q = 0; q < batch && k <= cap; ++q, ++k, ++nl) HIPC(launch_cheb_iter(c->s, L.g, cb, k));
+    ps.bytes = 32.0 * nodes * nl;
+    ps.end(nl);
+    HIPC(hipMemcpyAsync(L.cg_sc_host + 2 * s0, L.cg_sc + 2 * s0, 2 * ns * sizeof(CgScalars),
+                        hipMemcpyDeviceToHost, c->s));
+    HIPC(hipStreamSynchronize(c->s));
+    bool all = true;
+    for (int n = 0; n < ns; ++n) all = all && L.cg_sc_host[2 * (s0 + n)].done;
+    if (all || k > cap) break;
+    batch = 2;
+  }
+  int used = 0;
+  for (int n = 0; n < ns; ++n) {
+    const CgScalars &sc = L.cg_sc_host[2 * (s0 + n)];
+    used = std::max(used, budget_use(sc, true));
+    c->stats.cg_iters += sc.it;
+    c->stats.cg_solves += 1;
+    if (!cg_ok(sc, cb.tol2)) c->stats.cg_unconverged += 1;
+  }
+  pred = std::max(used + 2, pred - 1);
+}
+
 template <class T>
 void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pred_row) {
   CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
+  if constexpr (std::is_same<T, double>::value) {
+    if (cb.xt) {
+      cheb_solve(c, L, lev, s0, ns, i, pred_row, cb);
+      return;
+    }
+  }
   const double nodes = slice_nodes(c, L, s0, ns);
   PLAUNCH(c, PC_CGINIT, 16.0 * nodes, launch_cg_init(c->s, L.g, cb));
   int &pred = L.cg_pred[pred_row & 15][i - 1];
@@ -523,7 +663,7 @@ void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pre
     ProfScope ps(c, PC_CGITER, 0.0);
     for (int k = 0; k < budget; ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
     ps.end(budget);
-    c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget});
+    c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget, false});
     c->cg_log_used += ns;
     return;
   }
@@ -1083,6 +1223,10 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
     HIPC(hipMemcpyAsync(c->rag, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                         c->s));
     F.g.rag = c->rag;
+    // per-tissue spectral bounds (each tissue gets the bound of its own context)
+    std::vector<double> lam(count);
+    for (int n = 0; n < count; ++n)
+      lam[n] = lam_uniform(p0.dim, probs[n].nx, probs[n].ny, probs[n].nz, F.g.cx, F.g.cy, F.g.cz);
     if (p0.sigma_node) {
       const double sc = 1.0 / (p0.dx * p0.dx * p0.chi * p0.Cm);
       for (int a = 0; a < p0.dim; ++a) F.kface[a] = dalloc<double>(c, (size_t)count * Np);
@@ -1092,17 +1236,20 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
         HIPC(hipMemcpyAsync(s.data(), q.sigma_node, s.size() * sizeof(double),
                             hipMemcpyDeviceToHost, c->s));
         HIPC(hipStreamSynchronize(c->s));
+        std::vector<double> kh[3];
         for (int a = 0; a < p0.dim; ++a) {
-          const std::vector<double> k = face_coeffs(a, q.nx, q.ny, q.nz, s, sc);
-          HIPC(hipMemcpyAsync(F.kface[a] + n * Np, k.data(), k.size() * sizeof(double),
+          kh[a] = face_coeffs(a, q.nx, q.ny, q.nz, s, sc);
+          HIPC(hipMemcpyAsync(F.kface[a] + n * Np, kh[a].data(), kh[a].size() * sizeof(double),
                               hipMemcpyHostToDevice, c->s));
         }
+        lam[n] = lam_faces(p0.dim, q.nx, q.ny, q.nz, kh);
         HIPC(hipStreamSynchronize(c->s));
       }
       F.g.kx = F.kface[0];
       F.g.ky = p0.dim >= 2 ? F.kface[1] : nullptr;
       F.g.kz = p0.dim >= 3 ? F.kface[2] : nullptr;
     }
+    set_lam(c, F, lam);
     c->d_step = dalloc<int64_t>(c, 1);  // step 0
     c->cg_log_cap = std::max(8192, 64 * count);
     c->cg_log = halloc<CgScalars>(c, c->cg_log_cap);
