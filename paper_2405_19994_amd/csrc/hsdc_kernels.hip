@@ -353,8 +353,8 @@ k_eval_stages(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
   const double t = ((double)(step0 + n * stim.tn) + cj) * co.dt;
   const T *La = (j == 0) ? nullptr : Lin + n * st.sL();
   T *Lo = (j == 0 && Lout) ? Lout + n * st.sL() : nullptr;
-  ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T tau) {
-    const T lam = T(-1) / tau;
+  ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T rate) {
+    const T lam = -rate;
     const T w = yv[GATE0 + k];
     T gv = lam * (w - inf);
     if (La) gv += La[k * Np + p] * (T(u[(GATE0 + k) * Np + p]) - w);
@@ -596,11 +596,11 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
 #pragma unroll
       for (int f = 0; f < NF; ++f) yv[f] = T(yd[f]);
       const double t = ((double)(step0 + n * stim.tn) + co.c[i - 2]) * co.dt;
-      ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T tau) {
+      ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T rate) {
         const int f = GATE0 + k;
         const T lu = Lu[k * Np + p];
         const T w = yv[f];
-        const T gv = (T(-1) / tau) * (w - inf) + lu * (T(u[f * Np + p]) - w);
+        const T gv = -rate * (w - inf) + lu * (T(u[f * Np + p]) - w);
         if (store_g) Gp[f * Np + p] = gv;
         Yi[f * Np + p] = yd[f] + RH[f * Np + p] + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv;
       });
@@ -1355,8 +1355,8 @@ k_ionic_test(int64_t n, const double *y, double gs0, double gs1, double gs2, dou
   double yv[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) yv[f] = y[f * n + p];
-  ttp06::gates(yv[0], yv[3], [&](int k, double inf, double tau) {
-    lam[k * n + p] = -1.0 / tau;
+  ttp06::gates(yv[0], yv[3], [&](int k, double inf, double rate) {
+    lam[k * n + p] = -rate;
     winf[k * n + p] = inf;
   });
   double I, h[6];

@@ -49,65 +49,71 @@ __constant__ double kRest[19] = {
 template <class R>
 __device__ __forceinline__ R logistic(R x) { return R(1) / (R(1) + exp(x)); }
 
-// Steady state and time constant of every gate; calls sink(g, w_inf, tau)
-// for g = 0..11 in state order (m, h, j, xr1, xr2, xs, r, s, d, f, f2, fCass).
+// Divisions by model constants are written as products with the constant's
+// reciprocal (folded at compile time), and quotients are combined where the
+// algebra allows: an FP64 division costs about ten instructions, and the
+// results differ from the printed forms by rounding only.
+
+// Steady state and rate 1/tau of every gate; calls sink(g, w_inf, 1/tau) for
+// g = 0..11 in state order (m, h, j, xr1, xr2, xs, r, s, d, f, f2, fCass).
 template <class R, class Sink>
 __device__ __forceinline__ void gates(R V, R Ca_ss, Sink &&sink) {
   {  // m
-    const R s = logistic((-R(56.86) - V) / R(9.03));
-    const R am = logistic((-R(60.0) - V) / R(5.0));
-    const R bm = R(0.1) * logistic((V + R(35.0)) / R(5.0)) + R(0.1) * logistic((V - R(50.0)) / R(200.0));
-    sink(0, s * s, am * bm);
+    const R s = logistic((-R(56.86) - V) * R(1.0 / 9.03));
+    const R am = logistic((-R(60.0) - V) * R(0.2));
+    const R bm = R(0.1) * logistic((V + R(35.0)) * R(0.2)) + R(0.1) * logistic((V - R(50.0)) * R(0.005));
+    sink(0, s * s, R(1.0) / (am * bm));
   }
-  const R sh = logistic((V + R(71.55)) / R(7.43));
+  const R sh = logistic((V + R(71.55)) * R(1.0 / 7.43));
   const R hj_inf = sh * sh;
   if (V < -R(40.0)) {
-    const R ah = R(0.057) * exp(-(V + R(80.0)) / R(6.8));
+    const R ah = R(0.057) * exp((V + R(80.0)) * R(-1.0 / 6.8));
     const R bh = R(2.7) * exp(R(0.079) * V) + R(3.1e5) * exp(R(0.3485) * V);
-    sink(1, hj_inf, R(1.0) / (ah + bh));
+    sink(1, hj_inf, ah + bh);
     const R aj = (-R(2.5428e4) * exp(R(0.2444) * V) - R(6.948e-6) * exp(-R(0.04391) * V)) * (V + R(37.78)) /
-                      (R(1.0) + exp(R(0.311) * (V + R(79.23))));
+                 (R(1.0) + exp(R(0.311) * (V + R(79.23))));
     const R bj = R(0.02424) * exp(-R(0.01052) * V) / (R(1.0) + exp(-R(0.1378) * (V + R(40.14))));
-    sink(2, hj_inf, R(1.0) / (aj + bj));
+    sink(2, hj_inf, aj + bj);
   } else {
-    const R bh = R(0.77) / (R(0.13) * (R(1.0) + exp(-(V + R(10.66)) / R(11.1))));
-    sink(1, hj_inf, R(1.0) / bh);
-    const R bj = R(0.6) * exp(R(0.057) * V) / (R(1.0) + exp(-R(0.1) * (V + R(32.0))));
-    sink(2, hj_inf, R(1.0) / bj);
+    // beta_h = 0.77 / (0.13 (1 + e^{-(V + 10.66)/11.1})), alpha_h = 0
+    sink(1, hj_inf, R(0.77 / 0.13) / (R(1.0) + exp((V + R(10.66)) * R(-1.0 / 11.1))));
+    sink(2, hj_inf, R(0.6) * exp(R(0.057) * V) / (R(1.0) + exp(-R(0.1) * (V + R(32.0)))));
   }
-  sink(3, logistic((-R(26.0) - V) / R(7.0)),
-       (R(450.0) * logistic((-R(45.0) - V) / R(10.0))) * (R(6.0) * logistic((V + R(30.0)) / R(11.5))));
-  sink(4, logistic((V + R(88.0)) / R(24.0)),
-       (R(3.0) * logistic((-R(60.0) - V) / R(20.0))) * (R(1.12) * logistic((V - R(60.0)) / R(20.0))));
+  sink(3, logistic((-R(26.0) - V) * R(1.0 / 7.0)),
+       R(1.0) / ((R(450.0) * logistic((-R(45.0) - V) * R(0.1))) * (R(6.0) * logistic((V + R(30.0)) * R(1.0 / 11.5)))));
+  sink(4, logistic((V + R(88.0)) * R(1.0 / 24.0)),
+       R(1.0) / ((R(3.0) * logistic((-R(60.0) - V) * R(0.05))) * (R(1.12) * logistic((V - R(60.0)) * R(0.05)))));
   {  // xs
-    const R axs = R(1400.0) / sqrt(R(1.0) + exp((R(5.0) - V) / R(6.0)));
-    const R bxs = logistic((V - R(35.0)) / R(15.0));
-    sink(5, logistic((-R(5.0) - V) / R(14.0)), axs * bxs + R(80.0));
+    const R axs = R(1400.0) / sqrt(R(1.0) + exp((R(5.0) - V) * R(1.0 / 6.0)));
+    const R bxs = logistic((V - R(35.0)) * R(1.0 / 15.0));
+    sink(5, logistic((-R(5.0) - V) * R(1.0 / 14.0)), R(1.0) / (axs * bxs + R(80.0)));
   }
   {  // r, s (epicardium)
     const R v40 = V + R(40.0), v45 = V + R(45.0);
-    sink(6, logistic((R(20.0) - V) / R(6.0)), R(9.5) * exp(-(v40 * v40) / R(1800.0)) + R(0.8));
-    sink(7, logistic((V + R(20.0)) / R(5.0)),
-         R(85.0) * exp(-(v45 * v45) / R(320.0)) + R(5.0) * logistic((V - R(20.0)) / R(5.0)) + R(3.0));
+    sink(6, logistic((R(20.0) - V) * R(1.0 / 6.0)),
+         R(1.0) / (R(9.5) * exp((v40 * v40) * R(-1.0 / 1800.0)) + R(0.8)));
+    sink(7, logistic((V + R(20.0)) * R(0.2)),
+         R(1.0) / (R(85.0) * exp((v45 * v45) * R(-1.0 / 320.0)) + R(5.0) * logistic((V - R(20.0)) * R(0.2)) + R(3.0)));
   }
   {  // d
-    const R ad = R(1.4) * logistic((-R(35.0) - V) / R(13.0)) + R(0.25);
-    const R bd = R(1.4) * logistic((V + R(5.0)) / R(5.0));
-    const R gd = logistic((R(50.0) - V) / R(20.0));
-    sink(8, logistic((-R(8.0) - V) / R(7.5)), ad * bd + gd);
+    const R ad = R(1.4) * logistic((-R(35.0) - V) * R(1.0 / 13.0)) + R(0.25);
+    const R bd = R(1.4) * logistic((V + R(5.0)) * R(0.2));
+    const R gd = logistic((R(50.0) - V) * R(0.05));
+    sink(8, logistic((-R(8.0) - V) * R(1.0 / 7.5)), R(1.0) / (ad * bd + gd));
   }
   {  // f, f2
     const R v27 = V + R(27.0), v25 = V + R(25.0);
-    sink(9, logistic((V + R(20.0)) / R(7.0)),
-         R(1102.5) * exp(-(v27 * v27) / R(225.0)) + R(200.0) * logistic((R(13.0) - V) / R(10.0)) +
-             R(180.0) * logistic((V + R(30.0)) / R(10.0)) + R(20.0));
-    sink(10, R(0.67) * logistic((V + R(35.0)) / R(7.0)) + R(0.33),
-         R(600.0) * exp(-(v25 * v25) / R(170.0)) + R(31.0) * logistic((R(25.0) - V) / R(10.0)) +
-             R(16.0) * logistic((V + R(30.0)) / R(10.0)));
+    sink(9, logistic((V + R(20.0)) * R(1.0 / 7.0)),
+         R(1.0) / (R(1102.5) * exp((v27 * v27) * R(-1.0 / 225.0)) + R(200.0) * logistic((R(13.0) - V) * R(0.1)) +
+                   R(180.0) * logistic((V + R(30.0)) * R(0.1)) + R(20.0)));
+    sink(10, R(0.67) * logistic((V + R(35.0)) * R(1.0 / 7.0)) + R(0.33),
+         R(1.0) / (R(600.0) * exp((v25 * v25) * R(-1.0 / 170.0)) + R(31.0) * logistic((R(25.0) - V) * R(0.1)) +
+                   R(16.0) * logistic((V + R(30.0)) * R(0.1))));
   }
-  {  // fCass
-    const R q = (Ca_ss / R(0.05)) * (Ca_ss / R(0.05));
-    sink(11, R(0.6) / (R(1.0) + q) + R(0.4), R(80.0) / (R(1.0) + q) + R(2.0));
+  {  // fCass: w_inf = 0.6 / (1 + q) + 0.4, tau = 80 / (1 + q) + 2, q = (Ca_ss / 0.05)^2
+    const R q = (Ca_ss * R(20.0)) * (Ca_ss * R(20.0));
+    const R iq = R(1.0) / (R(1.0) + q);
+    sink(11, R(0.6) * iq + R(0.4), (R(1.0) + q) / (R(82.0) + R(2.0) * q));
   }
 }
 
@@ -130,48 +136,54 @@ __device__ __forceinline__ void currents(const R *y, R gs0, R gs1, R gs2, R &I_i
   const R a_k1 = R(0.1) / (R(1.0) + exp(R(0.06) * (vek - R(200.0))));
   const R b_k1 = (R(3.0) * exp(R(0.0002) * (vek + R(100.0))) + exp(R(0.1) * (vek - R(10.0)))) /
                       (R(1.0) + exp(-R(0.5) * vek));
-  const R sq = sqrt(R(kKo) / R(5.4));
+  const R sq = R(1.0);  // sqrt(K_o / 5.4) with K_o = 5.4 mM
   const R I_K1 = R(kGK1) * sq * (a_k1 / (a_k1 + b_k1)) * vek;
   const R I_to = R(kGto) * r * s * vek;
   const R I_Kr = gs2 * R(kGKr) * sq * xr1 * xr2 * vek;
   const R I_Ks = R(kGKs) * xs * xs * (V - E_Ks);
   // L-type: (V - 15)/(e^u - 1) with u = 2 (V - 15)/RTF is (RTF/2) u/(e^u - 1),
   // written through expm1 so that u = 0 is regular.
-  const R u = R(2.0) * (V - R(15.0)) / R(kRTF);
-  const R ratio = (u == R(0.0)) ? R(1.0) : expm1(u) / u;
-  const R I_CaL = gs1 * R(kGCaL) * d * f * f2 * fcass * R(4.0) * R(kF) * (R(0.5) / ratio) *
+  const R u = (V - R(15.0)) * R(2.0 / kRTF);
+  const R inv_ratio = (u == R(0.0)) ? R(1.0) : u / expm1(u);
+  const R I_CaL = gs1 * R(kGCaL) * d * f * f2 * fcass * R(4.0) * R(kF) * (R(0.5) * inv_ratio) *
                        (R(0.25) * Ca_ss * exp(u) - R(kCao));
-  const R vfrt = V / R(kRTF);
+  const R vfrt = V * R(1.0 / kRTF);
   const R e_g = exp(R(kGammaNaCa) * vfrt), e_g1 = exp((R(kGammaNaCa) - R(1.0)) * vfrt);
   const R nai3 = Na_i * Na_i * Na_i;
   const R I_NaCa =
-      R(kNaCa) * (e_g * nai3 * R(kCao) - e_g1 * (R(kNao) * R(kNao) * R(kNao)) * Ca_i * R(kAlphaNaCa)) /
-      ((R(kKmNai) * R(kKmNai) * R(kKmNai) + R(kNao) * R(kNao) * R(kNao)) * (R(kKmCa) + R(kCao)) * (R(1.0) + R(kKsat) * e_g1));
-  const R I_NaK = R(kPNaK) * R(kKo) / (R(kKo) + R(kKmK)) * Na_i / (Na_i + R(kKmNa)) /
-                       (R(1.0) + R(0.1245) * exp(-R(0.1) * vfrt) + R(0.0353) * exp(-vfrt));
+      (e_g * nai3 * R(kCao) - e_g1 * (R(kNao) * R(kNao) * R(kNao)) * Ca_i * R(kAlphaNaCa)) *
+      R(kNaCa / ((kKmNai * kKmNai * kKmNai + kNao * kNao * kNao) * (kKmCa + kCao))) /
+      (R(1.0) + R(kKsat) * e_g1);
+  const R I_NaK = R(kPNaK * kKo / (kKo + kKmK)) * Na_i /
+                  ((Na_i + R(kKmNa)) * (R(1.0) + R(0.1245) * exp(-R(0.1) * vfrt) + R(0.0353) * exp(-vfrt)));
   const R I_pCa = R(kGpCa) * Ca_i / (R(kKpCa) + Ca_i);
-  const R I_pK = R(kGpK) * vek / (R(1.0) + exp((R(25.0) - V) / R(5.98)));
+  const R I_pK = R(kGpK) * vek / (R(1.0) + exp((R(25.0) - V) * R(1.0 / 5.98)));
   const R I_bNa = R(kGbNa) * (V - E_Na);
   const R I_bCa = R(kGbCa) * (V - E_Ca);
   I_ion = I_Na + I_K1 + I_to + I_Kr + I_Ks + I_CaL + I_NaCa + I_NaK + I_pCa + I_pK + I_bNa + I_bCa;
 
-  const R k_casr = R(kMaxSR) - (R(kMaxSR) - R(kMinSR)) / (R(1.0) + (R(kEC) / Ca_sr) * (R(kEC) / Ca_sr));
+  // k_casr = max_SR - (max_SR - min_SR) / (1 + (EC / Ca_SR)^2)
+  const R csr2 = Ca_sr * Ca_sr;
+  const R k_casr = R(kMaxSR) - R(kMaxSR - kMinSR) * csr2 / (csr2 + R(kEC * kEC));
   const R k1 = R(kK1p) / k_casr, k2 = R(kK2p) * k_casr;
   const R css2 = Ca_ss * Ca_ss;
   const R O = k1 * css2 * Rbar / (R(kK3) + k1 * css2);
   const R I_rel = R(kVrel) * O * (Ca_sr - Ca_ss);
-  const R I_up = R(kVmaxUp) / (R(1.0) + (R(kKup) * R(kKup)) / (Ca_i * Ca_i));
+  const R ci2 = Ca_i * Ca_i;
+  const R I_up = R(kVmaxUp) * ci2 / (ci2 + R(kKup * kKup));
   const R I_leak = R(kVleak) * (Ca_sr - Ca_i);
   const R I_xfer = R(kVxfer) * (Ca_ss - Ca_i);
+  // buffer factors 1 / (1 + B K / (c + K)^2) = (c + K)^2 / ((c + K)^2 + B K)
   const R ci_k = Ca_i + R(kKbufc), csr_k = Ca_sr + R(kKbufsr), css_k = Ca_ss + R(kKbufss);
-  const R buf_c = R(1.0) / (R(1.0) + R(kBufc) * R(kKbufc) / (ci_k * ci_k));
-  const R buf_sr = R(1.0) / (R(1.0) + R(kBufsr) * R(kKbufsr) / (csr_k * csr_k));
-  const R buf_ss = R(1.0) / (R(1.0) + R(kBufss) * R(kKbufss) / (css_k * css_k));
-  const R cvf = R(kCap) / (R(kVc) * R(kF));
-  ha[0] = buf_c * ((I_leak - I_up) * R(kVsr) / R(kVc) + I_xfer -
-                   (I_bCa + I_pCa - R(2.0) * I_NaCa) * R(kCap) / (R(2.0) * R(kVc) * R(kF)));
+  const R ci_k2 = ci_k * ci_k, csr_k2 = csr_k * csr_k, css_k2 = css_k * css_k;
+  const R buf_c = ci_k2 / (ci_k2 + R(kBufc * kKbufc));
+  const R buf_sr = csr_k2 / (csr_k2 + R(kBufsr * kKbufsr));
+  const R buf_ss = css_k2 / (css_k2 + R(kBufss * kKbufss));
+  const R cvf = R(kCap / (kVc * kF));
+  ha[0] = buf_c * ((I_leak - I_up) * R(kVsr / kVc) + I_xfer -
+                   (I_bCa + I_pCa - R(2.0) * I_NaCa) * R(kCap / (2.0 * kVc * kF)));
   ha[1] = buf_sr * (I_up - (I_rel + I_leak));
-  ha[2] = buf_ss * (-I_CaL * R(kCap) / (R(2.0) * R(kVss) * R(kF)) + I_rel * R(kVsr) / R(kVss) - I_xfer * R(kVc) / R(kVss));
+  ha[2] = buf_ss * (I_CaL * R(-kCap / (2.0 * kVss * kF)) + I_rel * R(kVsr / kVss) - I_xfer * R(kVc / kVss));
   ha[3] = -(I_Na + I_bNa + R(3.0) * I_NaK + R(3.0) * I_NaCa) * cvf;
   ha[4] = -(I_K1 + I_to + I_Kr + I_Ks - R(2.0) * I_NaK + I_pK) * cvf;
   ha[5] = -k2 * Ca_ss * Rbar + R(kK4) * (R(1.0) - Rbar);
