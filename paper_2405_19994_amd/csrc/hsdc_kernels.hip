@@ -15,18 +15,6 @@ namespace hsdc {
 // phi functions (Appendix A, eq. def_phik)
 // ---------------------------------------------------------------------------
 
-// 1/n for n = 0..79 (kRecip[0] unused)
-__constant__ double kRecip[80] = {
-    0.0, 1.0 / 1, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6, 1.0 / 7, 1.0 / 8, 1.0 / 9,
-    1.0 / 10, 1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18,
-    1.0 / 19, 1.0 / 20, 1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27,
-    1.0 / 28, 1.0 / 29, 1.0 / 30, 1.0 / 31, 1.0 / 32, 1.0 / 33, 1.0 / 34, 1.0 / 35, 1.0 / 36,
-    1.0 / 37, 1.0 / 38, 1.0 / 39, 1.0 / 40, 1.0 / 41, 1.0 / 42, 1.0 / 43, 1.0 / 44, 1.0 / 45,
-    1.0 / 46, 1.0 / 47, 1.0 / 48, 1.0 / 49, 1.0 / 50, 1.0 / 51, 1.0 / 52, 1.0 / 53, 1.0 / 54,
-    1.0 / 55, 1.0 / 56, 1.0 / 57, 1.0 / 58, 1.0 / 59, 1.0 / 60, 1.0 / 61, 1.0 / 62, 1.0 / 63,
-    1.0 / 64, 1.0 / 65, 1.0 / 66, 1.0 / 67, 1.0 / 68, 1.0 / 69, 1.0 / 70, 1.0 / 71, 1.0 / 72,
-    1.0 / 73, 1.0 / 74, 1.0 / 75, 1.0 / 76, 1.0 / 77, 1.0 / 78, 1.0 / 79};
-
 // phi_1(x) = (e^x - 1)/x.  For |x| < 1/8 the Taylor series sum_{m<=9} x^m/(m+1)!
 // (truncation below 2e-17 relative) replaces expm1 and the division.
 __device__ __forceinline__ double phi1(double x) {
@@ -45,51 +33,64 @@ __device__ __forceinline__ double phi1(double x) {
   return expm1(x) / x;
 }
 
-// phi_1(x) .. phi_M(x) into out[0..M-1].  The forward recurrence
-// phi_{k+1} = (phi_k - 1/k!)/x from phi_1 = expm1(x)/x damps errors while k <= |x|
-// (factor about k/|x| per step); the backward recurrence phi_k = 1/k! + x phi_{k+1}
-// from the Taylor series sum_m x^m/(m+M)! of phi_M damps them while k + 1 > |x|.
-// Each k is taken from the direction that is stable for it.
+// Coefficients 1/(M+m)!, m = 0..N, of the Taylor series of phi_M, formed at
+// compile time.
+template <int M, int N>
+struct PhiSeries {
+  double c[N + 1];
+  constexpr PhiSeries() : c() {
+    double f = 1.0;
+    for (int k = 2; k <= M; ++k) f *= k;
+    c[0] = 1.0 / f;
+    for (int m = 1; m <= N; ++m) c[m] = c[m - 1] / (M + m);
+  }
+};
+
+// phi_1(x) .. phi_M(x) into out[0..M-1], by one of three branches.
+//   |x| < 1/8: phi_M from its Taylor series sum_m x^m/(m+M)!, m <= 9 (truncation
+//     below 2e-17 relative), then the backward recurrence
+//     phi_k = 1/k! + x phi_{k+1}, which damps errors for k + 1 > |x|.
+//   |x| >= F (F = M/2, or 1/8 for M = 1): the forward recurrence
+//     phi_{k+1} = (phi_k - 1/k!)/x from phi_1 = expm1(x)/x.  It multiplies the
+//     relative error by about (k+1)/|x| per step where k + 1 > |x|, at most
+//     prod_{k >= F} (k+1)/F over the whole range (4.4 for M = 6, 6.6 for M = 8).
+//   otherwise: phi_M from its Taylor series with N = 18 + M terms (below 1e-18
+//     relative for |x| < M/2), in Horner form with compile-time coefficients,
+//     then the backward recurrence.
+// Relative error below 6e-15 for M <= 8 over x in [-4000, 12] (checked against a
+// 60-digit evaluation).
 template <int M>
 __device__ __forceinline__ void phis(double x, const double *invfact, double *out) {
   const double ax = fabs(x);
-  const int kf = ax >= (double)M ? M : (int)ax;  // phi_1..phi_kf forward
-  if (kf >= 1) {
+  constexpr double F = M == 1 ? 0.125 : 0.5 * M;
+  if (ax >= F) {
     const double xi = 1.0 / x;
     double p = expm1(x) * xi;
     out[0] = p;
 #pragma unroll
     for (int k = 1; k < M; ++k) {
-      if (k < kf) {
-        p = (p - invfact[k]) * xi;
-        out[k] = p;
-      }
+      p = (p - invfact[k]) * xi;
+      out[k] = p;
     }
+    return;
   }
-  if (kf < M) {
-    double acc;
-    if (ax < 0.125) {
-      // phi_M(x) = sum_m x^m/(m+M)!, m <= 9 (truncation below 2e-17 relative)
-      acc = invfact[M + 9];
+  double acc;
+  if (ax < 0.125) {
+    acc = invfact[M + 9];
 #pragma unroll
-      for (int m = 8; m >= 0; --m) acc = fma(acc, x, invfact[M + m]);
-    } else {
-      double term = invfact[M];
-      acc = term;
-      for (int m = 1; m < 64; ++m) {
-        term *= x * kRecip[m + M];
-        acc += term;
-        if (fabs(term) <= 1e-17 * fabs(acc)) break;
-      }
-    }
-    out[M - 1] = acc;
+    for (int m = 8; m >= 0; --m) acc = fma(acc, x, invfact[M + m]);
+  } else {
+    constexpr int N = 18 + M;
+    constexpr PhiSeries<M, N> S{};
+    acc = S.c[N];
 #pragma unroll
-    for (int k = M - 1; k >= 1; --k) {
-      if (k > kf) {
-        acc = invfact[k] + x * acc;
-        out[k - 1] = acc;
-      }
-    }
+    for (int m = N - 1; m >= 0; --m) acc = fma(acc, x, S.c[m]);
+  }
+  out[M - 1] = acc;
+#pragma unroll
+  for (int k = M - 1; k >= 1; --k) {
+    acc = invfact[k] + x * acc;
+    out[k - 1] = acc;
   }
 }
 
