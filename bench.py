@@ -343,7 +343,8 @@ def bench_batch2d(a):
 _KERNEL_CLASS = (("k_node_update", "node_update"), ("k_cg_iter", "cg_iter"),
                  ("k_cg_init", "cg_init"), ("k_assemble", "assemble"),
                  ("k_eval_stages", "eval_stages"), ("k_spmv_stages", "spmv"),
-                 ("k_copy_fields", "copy"), ("k_copy_V_to_stages", "copy"))
+                 ("k_copy_fields", "copy"), ("k_copy_V_to_stages", "copy"),
+                 ("k_cheb_iter", "cheb_iter"))
 
 
 def summarize_counters(fetch_csv, write_csv):
