@@ -49,8 +49,8 @@ def _args():
     ap.add_argument("--graph", action="store_true",
                     help="slab2d: replay each step from a captured HIP graph")
     ap.add_argument("--solver", choices=("cg", "chebyshev"), default="cg",
-                    help="slab2d: diffusion solver of the reported line (the workload names CG); "
-                         "the other solver is timed beside it as an option study")
+                    help="diffusion solver (the slab workloads name CG); slab2d also times "
+                         "the other solver beside its line as an option study")
     ap.add_argument("--no-solver-option", action="store_true",
                     help="slab2d: skip timing the other diffusion solver")
     ap.add_argument("--no-autotune", action="store_true",
@@ -162,10 +162,11 @@ def bench_slab3d(a):
     def pfasst_method():
         return H.make_method(M=(w["M"], w["Mc"]), levels=2, space_coarsen=a.coarsen, P=P, dt=dt,
                              max_iter=a.max_iter, tol=a.tol, burn_in=1, cg_rtol=w["cg_rtol"],
-                             cg_maxit=500, coarse_fp32=a.coarse_fp32)
+                             cg_maxit=500, coarse_fp32=a.coarse_fp32, solver=a.solver)
 
     def serial_method(K, rtol):
-        return H.make_method(M=(w["M"], 1), dt=dt, max_iter=K, cg_rtol=rtol, cg_maxit=500)
+        return H.make_method(M=(w["M"], 1), dt=dt, max_iter=K, cg_rtol=rtol, cg_maxit=500,
+                             solver=a.solver)
 
     def timed(method, n):
         ctx = H.Context(prob, method, None)
@@ -234,7 +235,7 @@ def bench_slab3d(a):
         "config": {"workload": "slab3d 192x96x48, 7-point sigma (3,1,1), TTP06, PFASST P16 "
                                f"M 6/3, coarse mesh /{a.coarsen}, dt 0.1 ms, tol {a.tol:g}",
                    "nodes": N, "P": P, "M": [w["M"], w["Mc"]], "space_coarsen": a.coarsen,
-                   "coarse_fp32": bool(a.coarse_fp32),
+                   "coarse_fp32": bool(a.coarse_fp32), "solver": a.solver,
                    "blocks": a.blocks, "t_simulated_ms": T},
         "pfasst_iters_per_block": st_pf["pfasst_iters"] / a.blocks,
         "error_vs_collocation": err_pf,
@@ -271,7 +272,7 @@ def bench_batch2d(a):
                             (1, 1, 1), t(w["stim_w"]), w["stim_amp"], w["stim_t0"], w["stim_dur"])
              for w in ws]
     m = H.make_method(M=ws[0]["M"], dt=ws[0]["dt"], max_iter=ws[0]["K"], cg_rtol=ws[0]["cg_rtol"],
-                      cg_maxit=500)
+                      cg_maxit=500, solver=a.solver)
     Ns = [p.N for p in probs]
     upd_per_step = sum(Ns) * ws[0]["M"] * ws[0]["K"]
     if a.warmup > 0:
@@ -324,7 +325,8 @@ def bench_batch2d(a):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"batch2d {a.tissues} tissues, sides 64..512, lognormal sigma, "
-                               "8x8 patch, TTP06, M4 K4, dt 0.05 ms, CG 1e-12",
+                               "8x8 patch, TTP06, M4 K4, dt 0.05 ms, "
+                               + ("CG" if a.solver == "cg" else "Chebyshev") + " 1e-12",
                    "tissues": a.tissues, "nodes_total": int(sum(Ns)), "nodes_min": int(min(Ns)),
                    "nodes_max": int(max(Ns)), "M": ws[0]["M"], "sweeps": ws[0]["K"],
                    "dt_ms": ws[0]["dt"]},
@@ -406,7 +408,8 @@ def bench_cable1d(a):
     stim = torch.tensor(w["stim_w"], dtype=torch.float64, device=dev)
     prob = H.make_problem(w["dims"], w["dx"], w["sigma"], None, w["chi"], w["Cm"], (1, 1, 1), stim,
                           w["stim_amp"], w["stim_t0"], w["stim_dur"])
-    meth = H.make_method(M=w["M"], dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"], cg_maxit=300)
+    meth = H.make_method(M=w["M"], dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"], cg_maxit=300,
+                         solver=a.solver)
     stream = torch.cuda.Stream()
     res = {}
     for graph in (False, True):
@@ -431,7 +434,7 @@ def bench_cable1d(a):
         "ms_per_step": res[True]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "cable1d 128 nodes, dx 0.01 cm, TTP06, M4 K4, dt 0.05 ms, T 10 ms",
-                   "nodes": N, "M": w["M"], "sweeps": w["K"], "dt_ms": w["dt"]},
+                   "nodes": N, "M": w["M"], "sweeps": w["K"], "dt_ms": w["dt"], "solver": a.solver},
         "eager": res[False], "graph": res[True],
         "graph_speedup": res[False]["wall_s"] / res[True]["wall_s"]}))
 
