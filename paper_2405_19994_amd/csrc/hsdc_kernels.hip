@@ -354,11 +354,21 @@ k_eval_stages(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
   const double t = ((double)(step0 + n * stim.tn) + cj) * co.dt;
   const T *La = (j == 0) ? nullptr : Lin + n * st.sL();
   T *Lo = (j == 0 && Lout) ? Lout + n * st.sL() : nullptr;
+  // software-pipelined by one gate (the anchor's Lambda and value of gate k + 1
+  // are loaded when gate k is stored)
+  T nla = La ? La[p] : T(0);
+  double nuf = La ? u[GATE0 * Np + p] : 0.0;
   ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T rate) {
+    const T la = nla;
+    const double uf = nuf;
+    if (La && k + 1 < NG) {
+      nla = La[(k + 1) * Np + p];
+      nuf = u[(GATE0 + k + 1) * Np + p];
+    }
     const T lam = -rate;
     const T w = yv[GATE0 + k];
     T gv = lam * (w - inf);
-    if (La) gv += La[k * Np + p] * (T(u[(GATE0 + k) * Np + p]) - w);
+    if (La) gv += la * (T(uf) - w);
     G[(GATE0 + k) * Np + p] = gv;
     if (Lo) Lo[k * Np + p] = lam;
   });
@@ -558,8 +568,11 @@ hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const StagesT<T> &
 // side of the implicit diffusion solve for V.
 // ---------------------------------------------------------------------------
 
+// Four waves per SIMD (at most 128 VGPRs): the launch has exactly that many
+// waves on the 512 x 512 slab, so a fifth register would halve its occupancy.
 template <class T>
 __global__ void __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(4)))
 k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
               int slice0, int i, CgBatchT<T> cb, int store_g, int spread) {
   __shared__ double lds[BLOCK / 64];
@@ -583,13 +596,32 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
 #pragma unroll
     for (int f = 0; f < NF; ++f) yd[f] = Yp[f * Np + p];
     T gV;
+    // operands of the V row: right-hand side, warm start x_0 = V^k_i and its
+    // cached K x_0 (loaded first on node 1, after the cell model otherwise)
+    const double *fvp = st.FV + n * st.sFV() + (int64_t)(spread ? 0 : i) * Np + p;
+    double rh0, x0, kx0;
     if (i == 1) {
       // y_{n,0} = u: its reaction term was evaluated with the anchor
+      rh0 = RH[p];
+      x0 = Yi[p];
+      kx0 = *fvp;
 #pragma unroll
-      for (int f = 1; f < NF; ++f) {
-        const T gv = Gp[f * Np + p];
-        const T ph = (f >= GATE0) ? T(phi1(ddt * (double)Lu[(f - GATE0) * Np + p])) : T(1);
-        Yi[f * Np + p] = yd[f] + RH[f * Np + p] + ddt * (double)ph * (double)gv;
+      for (int f = 1; f < GATE0; ++f)
+        Yi[f * Np + p] = yd[f] + RH[f * Np + p] + ddt * (double)Gp[f * Np + p];
+      // gates, software-pipelined by one gate like the cell-model path below
+      T nlu = Lu[p], ngv = Gp[GATE0 * Np + p];
+      double nrh = RH[GATE0 * Np + p];
+#pragma unroll
+      for (int k = 0; k < NG; ++k) {
+        const int f = GATE0 + k;
+        const T lu = nlu, gv = ngv;
+        const double rh = nrh;
+        if (k + 1 < NG) {
+          nlu = Lu[(k + 1) * Np + p];
+          ngv = Gp[(f + 1) * Np + p];
+          nrh = RH[(f + 1) * Np + p];
+        }
+        Yi[f * Np + p] = yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv;
       }
       gV = Gp[p];
     } else {
@@ -597,14 +629,30 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
 #pragma unroll
       for (int f = 0; f < NF; ++f) yv[f] = T(yd[f]);
       const double t = ((double)(step0 + n * stim.tn) + co.c[i - 2]) * co.dt;
+      // software-pipelined by one gate: the operands of gate k + 1 (Lambda and
+      // value of the anchor, right-hand side) are loaded when gate k is
+      // applied, so they are in flight while the cell model computes gate k + 1
+      T nlu = Lu[p];
+      double nuf = u[GATE0 * Np + p], nrh = RH[GATE0 * Np + p];
       ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T rate) {
         const int f = GATE0 + k;
-        const T lu = Lu[k * Np + p];
+        const T lu = nlu;
+        const double uf = nuf, rh = nrh;
+        if (k + 1 < NG) {
+          nlu = Lu[(k + 1) * Np + p];
+          nuf = u[(f + 1) * Np + p];
+          nrh = RH[(f + 1) * Np + p];
+        }
         const T w = yv[f];
-        const T gv = -rate * (w - inf) + lu * (T(u[f * Np + p]) - w);
+        const T gv = -rate * (w - inf) + lu * (T(uf) - w);
         if (store_g) Gp[f * Np + p] = gv;
-        Yi[f * Np + p] = yd[f] + RH[f * Np + p] + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv;
+        Yi[f * Np + p] = yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv;
       });
+      // right-hand sides of the rows after the cell model, in flight during the
+      // currents (the V row's operands follow them: registers are the limit)
+      double rha[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rha[k] = RH[(1 + k) * Np + p];
       T I_ion, ha[6];
       ttp06::currents<T>(yv, T(gs0), T(gs1), T(gs2), I_ion, ha);
       gV = (T(stim_value(stim, t, n, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
@@ -612,14 +660,16 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         if (store_g) Gp[(1 + k) * Np + p] = ha[k];
-        Yi[(1 + k) * Np + p] = yd[1 + k] + RH[(1 + k) * Np + p] + ddt * (double)ha[k];
+        Yi[(1 + k) * Np + p] = yd[1 + k] + rha[k] + ddt * (double)ha[k];
       }
+      rh0 = RH[p];
+      x0 = Yi[p];
+      kx0 = *fvp;
     }
     // right-hand side of (I - dt d_i K) V_i = b and the CG start residual for
     // the warm start x_0 = V^k_i, whose K x_0 is cached from the previous sweep
-    const double bv = yd[0] + RH[p] + ddt * (double)gV;
-    const double x0 = Yi[p];
-    const double r0 = bv - x0 + cb.a * st.FV[n * st.sFV() + (int64_t)(spread ? 0 : i) * Np + p];
+    const double bv = yd[0] + rh0 + ddt * (double)gV;
+    const double r0 = bv - x0 + cb.a * kx0;
     if (cb.xt) {
       // Chebyshev: b and the first iterate x_1 = x_0 + r_0 / theta
       cb.bout[(int64_t)(n - slice0) * Np + p] = bv;
