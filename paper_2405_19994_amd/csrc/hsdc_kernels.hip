@@ -11,6 +11,13 @@
 
 namespace hsdc {
 
+// Store with a streaming (non-temporal) hint: for values that only a later
+// kernel reads.
+template <class V>
+__device__ __forceinline__ void stream_store(V *dst, V v) {
+  __builtin_nontemporal_store(v, dst);
+}
+
 // ---------------------------------------------------------------------------
 // phi functions (Appendix A, eq. def_phik)
 // ---------------------------------------------------------------------------
@@ -510,7 +517,9 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     const double ph = (f >= GATE0) ? phi1(co.d[i] * z) : 1.0;
-    RH[(int64_t)i * st.sS()] = dt * (I[i] - prevI) - dt * co.d[i] * (fv[i + 1] + ph * Gv[i]);
+    // streaming store: read once, by a later kernel
+    stream_store<double>(&RH[(int64_t)i * st.sS()],
+                         dt * (I[i] - prevI) - dt * co.d[i] * (fv[i + 1] + ph * Gv[i]));
     prevI = I[i];
   }
 }
@@ -591,7 +600,9 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
     const double *RH = st.RH + n * st.sRH() + (int64_t)(i - 1) * st.sS();
     const T *Lu = st.L0 + n * st.sL();  // Lambda of the anchor u
     T *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
-    // the state accumulates in FP64; the cell model runs in T
+    // the state accumulates in FP64; the cell model runs in T.  The new stage's
+    // rows and reaction terms are stored with a streaming hint (read again only
+    // by later kernels)
     double yd[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) yd[f] = Yp[f * Np + p];
@@ -607,7 +618,8 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
       kx0 = *fvp;
 #pragma unroll
       for (int f = 1; f < GATE0; ++f)
-        Yi[f * Np + p] = yd[f] + RH[f * Np + p] + ddt * (double)Gp[f * Np + p];
+        stream_store<double>(&Yi[f * Np + p],
+                             yd[f] + RH[f * Np + p] + ddt * (double)Gp[f * Np + p]);
       // gates, software-pipelined by one gate like the cell-model path below
       T nlu = Lu[p], ngv = Gp[GATE0 * Np + p];
       double nrh = RH[GATE0 * Np + p];
@@ -621,7 +633,8 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
           ngv = Gp[(f + 1) * Np + p];
           nrh = RH[(f + 1) * Np + p];
         }
-        Yi[f * Np + p] = yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv;
+        stream_store<double>(&Yi[f * Np + p],
+                             yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv);
       }
       gV = Gp[p];
     } else {
@@ -645,8 +658,9 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
         }
         const T w = yv[f];
         const T gv = -rate * (w - inf) + lu * (T(uf) - w);
-        if (store_g) Gp[f * Np + p] = gv;
-        Yi[f * Np + p] = yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv;
+        if (store_g) stream_store<T>(&Gp[f * Np + p], gv);
+        stream_store<double>(&Yi[f * Np + p],
+                             yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv);
       });
       // right-hand sides of the rows after the cell model, in flight during the
       // currents (the V row's operands follow them: registers are the limit)
@@ -656,11 +670,11 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
       T I_ion, ha[6];
       ttp06::currents<T>(yv, T(gs0), T(gs1), T(gs2), I_ion, ha);
       gV = (T(stim_value(stim, t, n, p)) - T(stim.Cm) * I_ion) / T(stim.Cm);
-      if (store_g) Gp[p] = gV;
+      if (store_g) stream_store<T>(&Gp[p], gV);
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        if (store_g) Gp[(1 + k) * Np + p] = ha[k];
-        Yi[(1 + k) * Np + p] = yd[1 + k] + rha[k] + ddt * (double)ha[k];
+        if (store_g) stream_store<T>(&Gp[(1 + k) * Np + p], ha[k]);
+        stream_store<double>(&Yi[(1 + k) * Np + p], yd[1 + k] + rha[k] + ddt * (double)ha[k]);
       }
       rh0 = RH[p];
       x0 = Yi[p];
