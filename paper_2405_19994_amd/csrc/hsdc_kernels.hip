@@ -140,26 +140,52 @@ __device__ __forceinline__ void colloc_integrals(const Colloc &co, double z, con
 // reductions
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+// DPP copy of a double between lanes of a wave (two 32-bit moves); a lane
+// whose source lies outside its row, or whose row the mask leaves out, reads
+// `fill`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v, double fill) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long f = (unsigned long long)__double_as_longlong(fill);
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)f, (int)(unsigned)b, CTRL, ROW_MASK,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(f >> 32), (int)(unsigned)(b >> 32),
+                                             CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(
+      (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo));
+}
+
+// Wave reduction in registers (DPP, no LDS), in a fixed order, result in lane
+// 63: windows of 2, 4, 8 and 16 lanes within each row of 16 (row_shr 1, 2, 4,
+// 8), then row 0's total into row 1 and row 2's into row 3 (row_bcast 15), then
+// rows 0-1 into row 3 (row_bcast 31).
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v, double id, Op op) {
+  v = op(v, dpp_d<0x111, 0xf>(v, id));
+  v = op(v, dpp_d<0x112, 0xf>(v, id));
+  v = op(v, dpp_d<0x114, 0xf>(v, id));
+  v = op(v, dpp_d<0x118, 0xf>(v, id));
+  v = op(v, dpp_d<0x142, 0xa>(v, id));
+  v = op(v, dpp_d<0x143, 0xc>(v, id));
   return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  return wave_reduce(v, 0.0, [](double a, double b) { return a + b; });
 }
 
 // NaN-propagating maximum
 __device__ __forceinline__ double nmax(double a, double b) { return (b != b || b > a) ? b : a; }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = nmax(v, __shfl_down(v, o, 64));
-  return v;
+  return wave_reduce(v, -INFINITY, nmax);
 }
 
 // Sum over the block (BLOCK threads); the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double *lds) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) lds[w] = v;
+  if (lane == 63) lds[w] = v;
   __syncthreads();
   double t = 0.0;
   if (threadIdx.x == 0) {
@@ -173,7 +199,7 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 __device__ __forceinline__ double block_max(double v, double *lds) {
   v = wave_max(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) lds[w] = v;
+  if (lane == 63) lds[w] = v;
   __syncthreads();
   double t = 0.0;
   if (threadIdx.x == 0) {
