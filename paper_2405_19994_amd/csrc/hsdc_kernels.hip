@@ -211,22 +211,32 @@ __device__ __forceinline__ double block_max(double v, double *lds) {
   return t;
 }
 
-// Block-wide sum broadcast to every thread of the block.
-__device__ __forceinline__ double block_sum_all(double v, double *lds) {
-  __shared__ double out;
-  const double t = block_sum(v, lds);
-  if (threadIdx.x == 0) out = t;
+// N sums over the block at once, every thread receiving all of them (the wave
+// reductions interleave; one exchange through lds, which holds N * BLOCK/64
+// doubles; the waves' totals are added in wave order, as block_sum does).
+// Partial sums over blocks are combined the same way: each block of a kernel
+// writes its partials, and every block of the next kernel adds them in the same
+// fixed order and obtains the same value, so reductions need no atomics and no
+// cross-block fences.
+template <int N>
+__device__ __forceinline__ void block_sums(double (&v)[N], double *lds) {
+  constexpr int NW = BLOCK / 64;
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) lds[q * NW + w] = v[q];
+  }
   __syncthreads();
-  return out;
-}
-
-// Sum of n partials in a fixed order; every block of a kernel obtains the same
-// value, so reductions need no atomics and no cross-block fences: partials are
-// written by one kernel and combined by each block of the next one.
-__device__ __forceinline__ double reduce_partials(const double *part, int n, double *lds) {
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < n; k += BLOCK) acc += part[k];
-  return block_sum_all(acc, lds);
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += lds[q * NW + k];
+    v[q] = t;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -610,7 +620,7 @@ __global__ void __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(4)))
 k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
               int slice0, int i, CgBatchT<T> cb, int store_g, int spread) {
-  __shared__ double lds[BLOCK / 64];
+  __shared__ double lds[3 * (BLOCK / 64)];
   const int64_t step0 = *stim.step;
   const int64_t qb = stencil_node_block(g0, blockIdx.x, gridDim.x);
   const int64_t p = qb * BLOCK + threadIdx.x;
@@ -720,12 +730,12 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
     bb = bv * bv;
     rr = r0 * r0;
   }
-  const double tb = block_sum(bb, lds);
-  const double tr = block_sum(rr, lds);
+  double t2[2] = {bb, rr};
+  block_sums<2>(t2, lds);
   if (threadIdx.x == 0) {
     double *part = cb.part + (int64_t)(n - slice0) * 5 * cb.pstride;
-    part[4 * cb.pstride + qb] = tb;
-    part[qb] = tr;
+    part[4 * cb.pstride + qb] = t2[0];
+    part[qb] = t2[1];
   }
 }
 
@@ -901,7 +911,7 @@ __device__ __forceinline__ int active_blocks(const Grid &g, int nblk) {
 // (used when r_0 is not produced by the node update).
 template <int DIM, bool PN, class T>
 __global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g0, CgBatchT<T> cb) {
-  __shared__ double lds[BLOCK / 64];
+  __shared__ double lds[3 * (BLOCK / 64)];
   const int n = blockIdx.y;
   const Grid g = slice_grid(g0, cb.slice0 + n);
   if ((int)blockIdx.x >= active_blocks(g, cb.nblk)) return;
@@ -920,11 +930,11 @@ __global__ void __launch_bounds__(BLOCK) k_cg_resid0(Grid g0, CgBatchT<T> cb) {
     bb += bv * bv;
   }
   double *part = cb.part + (int64_t)n * 5 * cb.pstride;
-  const double tr = block_sum(rr, lds);
-  const double tb = block_sum(bb, lds);
+  double t2[2] = {rr, bb};
+  block_sums<2>(t2, lds);
   if (threadIdx.x == 0) {
-    part[qb] = tr;
-    part[4 * cb.pstride + qb] = tb;
+    part[qb] = t2[0];
+    part[4 * cb.pstride + qb] = t2[1];
   }
 }
 
@@ -964,7 +974,7 @@ __global__ void __launch_bounds__(BLOCK) k_cg_init(Grid g0, CgBatchT<T> cb) {
 
 template <int DIM, bool PN, class T>
 __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int k) {
-  __shared__ double lds[BLOCK / 64];
+  __shared__ double lds[3 * (BLOCK / 64)];
   const int n = blockIdx.y;
   const Grid g = slice_grid(g0, cb.slice0 + n);
   // a ragged batch skips the blocks past a small tissue; otherwise every block of
@@ -994,10 +1004,17 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   double r_c = 0.0, w_c = 0.0, s_c = 0.0, rn_[2 * DIM], wn_[2 * DIM], sn_[2 * DIM];
   Ijk c0{0, 0, 0};
   if (si.it == 0) {
-    gamma = reduce_partials(part, nba0, lds);
+    double t3[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < nba0; k += BLOCK) {
+      t3[0] += part[k];
+      t3[1] += part[4 * cb.pstride + k];
+    }
+    for (int k = threadIdx.x; k < nba; k += BLOCK) t3[2] += part[cb.pstride + k];
+    block_sums<3>(t3, lds);
+    gamma = t3[0];
     // stop relative to ||b|| or, for a correction solve, to ||r_0||
-    si.bb = cb.rel_r0 ? gamma : reduce_partials(part + 4 * cb.pstride, nba0, lds);
-    delta = reduce_partials(part + cb.pstride, nba, lds);
+    si.bb = cb.rel_r0 ? gamma : t3[1];
+    delta = t3[2];
   } else {
     const double *pg = part + (2 * in) * cb.pstride, *pd = part + (2 * in + 1) * cb.pstride;
     const int t = threadIdx.x;
@@ -1020,8 +1037,10 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
         sn_[q] = s[idx];
       }
     }
-    gamma = block_sum_all(g0 + g1, lds);
-    delta = block_sum_all(d0 + d1, lds);
+    double t2[2] = {g0 + g1, d0 + d1};
+    block_sums<2>(t2, lds);
+    gamma = t2[0];
+    delta = t2[1];
   }
   if (gamma <= cb.tol2 * si.bb || gamma == 0.0 || si.it >= cb.maxit) {
     if (publish) {
@@ -1090,11 +1109,11 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
     const Ijk c = ijk(g, p);
     update(p, c, r[p], w[p], s[p], rfull);
   }
-  const double tg = block_sum(gam, lds);
-  const double td = block_sum(del, lds);
+  double t2[2] = {gam, del};
+  block_sums<2>(t2, lds);
   if (threadIdx.x == 0) {
-    part[(2 * out) * cb.pstride + qb] = tg;
-    part[(2 * out + 1) * cb.pstride + qb] = td;
+    part[(2 * out) * cb.pstride + qb] = t2[0];
+    part[(2 * out + 1) * cb.pstride + qb] = t2[1];
   }
   if (publish) {
     CgScalars o = si;
@@ -1191,14 +1210,20 @@ __device__ __forceinline__ int cheb_count(const ChebTab &t, double rr0, double r
 // ||r_0||^2 and ||b||^2 and publishes the count while the others iterate.
 template <int DIM, bool PN>
 __global__ void __launch_bounds__(BLOCK) k_cheb_iter(Grid g0, CgBatch cb, int k, int nbx) {
-  __shared__ double lds[BLOCK / 64];
+  __shared__ double lds[3 * (BLOCK / 64)];
   const int n = blockIdx.y;
   const ChebTab &t = cb.tab[(cb.slice0 + n) * cb.tab_stride];
   CgScalars *sc = cb.sc + 2 * n;
   if ((int)blockIdx.x >= nbx) {
     const double *part = cb.part + (int64_t)n * 5 * cb.pstride;
-    const double rr0 = reduce_partials(part, cb.nblk0, lds);
-    const double ref2 = cb.rel_r0 ? rr0 : reduce_partials(part + 4 * cb.pstride, cb.nblk0, lds);
+    double t2[2] = {0.0, 0.0};
+    for (int k = threadIdx.x; k < cb.nblk0; k += BLOCK) {
+      t2[0] += part[k];
+      t2[1] += part[4 * cb.pstride + k];
+    }
+    block_sums<2>(t2, lds);
+    const double rr0 = t2[0];
+    const double ref2 = cb.rel_r0 ? rr0 : t2[1];
     if (threadIdx.x == 0) {
       double bound;
       CgScalars o;
