@@ -196,8 +196,9 @@ hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc,
 hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *src, int64_t ssrc, double *dst, int64_t sdst,
                                   int nrows, int nslices);
+// Yf += T (P_space (Yc - Sz)) on every stage; Sz is overwritten with Yc - Sz.
 hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
-                                  const double *Yc, const double *Sz, int64_t sYc, int Mc,
+                                  const double *Yc, double *Sz, int64_t sYc, int Mc,
                                   const double *Tt, int Mf, double *Yf, int64_t sYf,
                                   int nslices);
 

@@ -1389,8 +1389,8 @@ hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc,
 // axis of one node has weight 0 on its second cell and is skipped).  Fine node
 // blocks sharing coarse cells run on one XCD (xcd_node_block).
 __global__ void __launch_bounds__(BLOCK)
-k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz, int64_t sYc,
-                  int Mc, const double *Tt, int Mf, double *Yf, int64_t sYf) {
+k_prolong_correct(Grid gf, Grid gc, int scf, const double *Dc, int64_t sYc, int Mc,
+                  const double *Tt, int Mf, double *Yf, int64_t sYf) {
   const int64_t p = xcd_node_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (p >= gf.N) return;
   const int n = blockIdx.z;
@@ -1433,8 +1433,7 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz,
   for (int j = 0; j <= MAXM; ++j) {
     double s = 0.0;
     if (j <= Mc) {
-      const int64_t o = n * sYc + ((int64_t)j * NF + f) * gc.Np;
-      const double *yc = Yc + o, *sz = Sz + o;
+      const double *dc_ = Dc + n * sYc + ((int64_t)j * NF + f) * gc.Np;
 #pragma unroll
       for (int cz = 0; cz < 2; ++cz) {
         const double wz = cz ? w1[2] : w0[2];
@@ -1450,7 +1449,7 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz,
             const double wx = cx ? w1[0] : w0[0];
             if (wx == 0.0) continue;
             const int64_t q = oy + (cx ? ax1[0] : ax0[0]);
-            s += (wx * wy * wz) * (yc[q] - sz[q]);
+            s += (wx * wy * wz) * dc_[q];
           }
         }
       }
@@ -1469,12 +1468,21 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *Yc, const double *Sz,
   }
 }
 
+// d = y - d over n values (the coarse correction z_c - S z, formed once per
+// coarse value rather than at each of the 2^d fine taps that read it)
+__global__ void __launch_bounds__(BLOCK) k_sub_from(double *d, const double *y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) d[i] = y[i] - d[i];
+}
+
 hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
-                                  const double *Yc, const double *Sz, int64_t sYc, int Mc,
+                                  const double *Yc, double *Sz, int64_t sYc, int Mc,
                                   const double *Tt, int Mf, double *Yf, int64_t sYf,
                                   int nslices) {
+  const int64_t nc = (int64_t)nslices * sYc;
+  hipLaunchKernelGGL(k_sub_from, dim3(nblocks(nc)), dim3(BLOCK), 0, s, Sz, Yc, nc);
   hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks_xcd(gf.N), NF, nslices), dim3(BLOCK), 0, s,
-                     gf, gc, sc_factor, Yc, Sz, sYc, Mc, Tt, Mf, Yf, sYf);
+                     gf, gc, sc_factor, Sz, sYc, Mc, Tt, Mf, Yf, sYf);
   return hipGetLastError();
 }
 

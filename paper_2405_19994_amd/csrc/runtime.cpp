@@ -840,8 +840,9 @@ void restrict_fine_to_coarse(hsdc_ctx *c, LevelT<T> &Cc) {
 template <class T>
 void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc) {
   Level &F = c->L[0];
-  // z_c and S z read once at the coarse cells, fine stages read and written
-  const double bytes = 8.0 * F.P * NF * (2.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0) * F.g.N);
+  // z_c - S z formed in S z (z_c and S z read, the difference written), then
+  // read once at the coarse cells; fine stages read and written
+  const double bytes = 8.0 * F.P * NF * (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0) * F.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
           launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz,
                                  Cc.st.sY(), Cc.co.M, c->Tt, F.co.M, F.st.Y, F.st.sY(), F.P));
