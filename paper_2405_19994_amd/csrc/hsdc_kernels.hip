@@ -794,61 +794,62 @@ hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &s
 // and y; optionally the time-restricted integrals RI_i = sum_l R_il I_l.
 // ---------------------------------------------------------------------------
 
-template <int M>
-__global__ void __launch_bounds__(BLOCK)
-k_residual(Grid g0, Stages st, Colloc co, int slice0, const double *yblk0, double *part, int nblk,
+// One thread per (node, field) like the assembly, instantiated separately for
+// the rows V .. Rbar and the gate rows (held to four waves per SIMD); each
+// block writes the maxima of its row, reduced per slice by k_reduce_max2.
+template <int M, bool GATES>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_residual(Grid g0, Stages st, Colloc co, int slice0, const double *yblk0, double *part, int nbx,
            const double *Rt, int Mc, double *RI, int64_t sRI) {
   __shared__ double lds[BLOCK / 64];
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int f = GATES ? GATE0 + (int)blockIdx.y : (int)blockIdx.y;
   const int n = slice0 + blockIdx.z;
   const Grid g = slice_grid(g0, n);
   const int64_t Np = st.Np;
   double rmax = 0.0, ymax = 0.0;
   if (p < g.N) {
-    const double *Y = st.Y + n * st.sY();
-    const double *G = st.G + n * st.sY();
-    const double *FV = st.FV + n * st.sFV();
-    const double *L0 = st.L0 + n * st.sL();
+    const double *Y = st.Y + n * st.sY() + f * Np + p;
+    const double *G = st.G + n * st.sY() + f * Np + p;
     // u: the block start (slice 0), the previous slice's end, or, for independent
     // slices (yblk0 == NULL: serial steps, tissues of a batch), the own start value
     const double *up = (yblk0 == nullptr) ? st.Y + n * st.sY()
                        : (n == 0)         ? yblk0
                                           : st.Y + (n - 1) * st.sY() + (int64_t)M * st.sS();
-    double fv[M + 1];
+    double gfull[M], I[M];
 #pragma unroll
-    for (int j = 1; j <= M; ++j) fv[j] = FV[j * Np + p];
-    for (int f = 0; f < NF; ++f) {
-      double gfull[M], I[M];
+    for (int j = 0; j < M; ++j)
+      gfull[j] = G[(j + 1) * st.sS()] + (f == 0 ? st.FV[n * st.sFV() + (j + 1) * Np + p] : 0.0);
+    if constexpr (GATES) {
+      colloc_integrals<M>(co, co.dt * st.L0[n * st.sL() + (f - GATE0) * Np + p], gfull, I);
+    } else {
+      colloc_weights<M>(co, gfull, I);
+    }
+    const double u = up[f * Np + p];
+    const double y0 = Y[0];
+    rmax = nmax(rmax, fabs(y0 - u));
+    ymax = nmax(ymax, fabs(y0));
 #pragma unroll
-      for (int j = 0; j < M; ++j)
-        gfull[j] = G[(j + 1) * st.sS() + f * Np + p] + (f == 0 ? fv[j + 1] : 0.0);
-      const double z = (f >= GATE0) ? co.dt * L0[(f - GATE0) * Np + p] : 0.0;
-      colloc_integrals<M>(co, z, gfull, I);
-      const double u = up[f * Np + p];
-      const double y0 = Y[f * Np + p];
-      rmax = nmax(rmax, fabs(y0 - u));
-      ymax = nmax(ymax, fabs(y0));
+    for (int i = 0; i < M; ++i) {
+      const double yi = Y[(i + 1) * st.sS()];
+      rmax = nmax(rmax, fabs(yi - co.dt * I[i] - u));
+      ymax = nmax(ymax, fabs(yi));
+    }
+    if (RI) {
+      for (int ic = 0; ic < Mc; ++ic) {
+        double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < M; ++i) {
-        const double yi = Y[(i + 1) * st.sS() + f * Np + p];
-        rmax = nmax(rmax, fabs(yi - co.dt * I[i] - u));
-        ymax = nmax(ymax, fabs(yi));
-      }
-      if (RI) {
-        for (int ic = 0; ic < Mc; ++ic) {
-          double s = 0.0;
-#pragma unroll
-          for (int l = 0; l < M; ++l) s += Rt[(ic + 1) * (M + 1) + (l + 1)] * I[l];
-          RI[n * sRI + ((int64_t)ic * NF + f) * Np + p] = s;
-        }
+        for (int l = 0; l < M; ++l) s += Rt[(ic + 1) * (M + 1) + (l + 1)] * I[l];
+        RI[n * sRI + ((int64_t)ic * NF + f) * Np + p] = s;
       }
     }
   }
   const double br = block_max(rmax, lds);
   const double by = block_max(ymax, lds);
   if (threadIdx.x == 0) {
-    part[((int64_t)blockIdx.z * nblk + blockIdx.x) * 2 + 0] = br;
-    part[((int64_t)blockIdx.z * nblk + blockIdx.x) * 2 + 1] = by;
+    const int64_t k = ((int64_t)blockIdx.z * NF + f) * nbx + blockIdx.x;
+    part[2 * k + 0] = br;
+    part[2 * k + 1] = by;
   }
 }
 
@@ -868,15 +869,22 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_max2(const double *part, int n
   }
 }
 
-int residual_blocks(const Grid &g) { return (int)nblocks(g.N); }
+// Partials per slice of a residual launch: one per (field, node block).
+int residual_blocks(const Grid &g) { return NF * (int)nblocks(g.N); }
 
 hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *y_block0, double *part,
                            int nblk, double *out2, const double *Rt, int Mc, double *RI,
                            int64_t sRI) {
-  dim3 grid(nblocks(g.N), 1, nslices);
-  HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL((k_residual<M>), grid, dim3(BLOCK), 0, s, g, st, co,
-                                           slice0, y_block0, part, nblk, Rt, Mc, RI, sRI));
+  // nblk = NF node-block rows per slice (residual_blocks)
+  const int nbx = (int)nblocks(g.N);
+  const dim3 rows(nbx, GATE0, nslices), gates(nbx, NG, nslices);
+  HSDC_DISPATCH_M(co.M, {
+    hipLaunchKernelGGL((k_residual<M, false>), rows, dim3(BLOCK), 0, s, g, st, co, slice0,
+                       y_block0, part, nbx, Rt, Mc, RI, sRI);
+    hipLaunchKernelGGL((k_residual<M, true>), gates, dim3(BLOCK), 0, s, g, st, co, slice0,
+                       y_block0, part, nbx, Rt, Mc, RI, sRI);
+  });
   hipLaunchKernelGGL(k_reduce_max2, dim3(nslices), dim3(BLOCK), 0, s, part, nblk, out2);
   return hipGetLastError();
 }
