@@ -179,6 +179,23 @@ def test_chebyshev_solver_serial_parity(case):
         _serial_parity(si.workload("slab3d", dims=(10, 8, 6)), 12, 4, 3, 3, solver="chebyshev")
 
 
+@pytest.mark.parametrize("solver", ["cg", "chebyshev"])
+def test_solver_iteration_cap_reports_enoconv(solver):
+    """A solve that cannot reach cg_rtol within cg_maxit (2 iterations to 1e-14,
+    through the stimulus) ends in HSDC_ENOCONV after the step, counted in
+    cg_unconverged, with the state advanced and finite."""
+    w = si.workload("slab2d", dims=(31, 23))
+    ctx = H.Context(lib_problem(w), H.make_method(M=(4, 1), dt=w["dt"], max_iter=2, cg_rtol=1e-14,
+                                                  cg_maxit=2, solver=solver))
+    with pytest.raises(H.HsdcError) as e:
+        ctx.advance(3)
+    assert e.value.code == -4
+    st = ctx.stats()
+    assert st["cg_unconverged"] > 0 and st["steps"] == 3
+    assert np.all(np.isfinite(host(ctx.get_state(0, 0, 0))))
+    ctx.destroy()
+
+
 def test_sweep_and_residual_parity():
     """hsdc_sdc_sweep applies eq. prec_picard sweeps to the current step;
     hsdc_residual returns ||C(y_n) - 1 (x) y_n||_inf / ||y_n||_inf."""
@@ -236,9 +253,10 @@ def test_pfasst_iterates_parity(dims, coarsen, solver):
         assert np.max(np.abs(np.array(hist[-1]) - res)) < 1e-9 * max(1.0, np.max(hist[-1]))
 
 
-def test_pfasst_converges_to_serial_collocation():
+@pytest.mark.parametrize("solver", ["cg", "chebyshev"])
+def test_pfasst_converges_to_serial_collocation(solver):
     P = 4
-    w, h, y0, m = _pfasst_case((8, 6, 4), 6, 3, 2, P, 0.1)
+    w, h, y0, m = _pfasst_case((8, 6, 4), 6, 3, 2, P, 0.1, solver=solver)
     m.tol, m.max_iter = 1e-13, 60
     ctx = H.Context(lib_problem(w), m, dev(y0))
     conv = False
