@@ -96,7 +96,8 @@ typedef struct {
                              /* same ||b - A x||_2 <= cg_rtol ||b||_2).  An FP32  */
                              /* coarse level always runs CG.                      */
   double cg_rtol;            /* diffusion solve: ||b - A x||_2 <= cg_rtol ||b||_2 */
-  int32_t cg_maxit;          /* iteration cap per diffusion solve                 */
+  int32_t cg_maxit;          /* iteration cap per diffusion solve (Chebyshev:     */
+                             /* cap on the polynomial degree)                     */
   int32_t coarse_fp32;       /* levels = 2: 1 runs the coarse level's cell model  */
                              /* and stores its reaction terms, Lambda and CG work */
                              /* vectors in FP32; states, K V, right-hand sides,   */
@@ -152,8 +153,10 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
  * reductions): cg_blocks caps the blocks of each CG kernel (1..1024, <= 0
  * keeps the current cap, default 512); cg_margin is the number of spare
  * iterations added to a predicted CG iteration budget (1..64, <= 0 keeps the
- * current margin, default 2).  Takes effect from the next solve; call it
- * between steps, not concurrently with work on the context. */
+ * current margin, default 2; a Chebyshev budget gets one spare launch more,
+ * since its iteration count moves in steps of two).  Takes effect from the
+ * next solve; call it between steps, not concurrently with work on the
+ * context. */
 hsdc_status hsdc_tune(hsdc_ctx *ctx, int32_t cg_blocks, int32_t cg_margin);
 
 /* Graph replay of serial steps (serial and batch contexts created on a
