@@ -48,11 +48,12 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true",
                     help="slab2d: replay each step from a captured HIP graph")
-    ap.add_argument("--solver", choices=("cg", "chebyshev"), default="cg",
-                    help="diffusion solver (the slab workloads name CG); slab2d also times "
-                         "the other solver beside its line as an option study")
+    ap.add_argument("--solver", choices=tuple(SOLVER_NAMES), default="cg",
+                    help="diffusion solver (the slab workloads name CG): cg starts from three "
+                         "Chebyshev steps, cg_plain from the warm start; slab2d also times "
+                         "the other solvers beside its line as an option study")
     ap.add_argument("--no-solver-option", action="store_true",
-                    help="slab2d: skip timing the other diffusion solver")
+                    help="slab2d: skip timing the other diffusion solvers")
     ap.add_argument("--no-autotune", action="store_true",
                     help="slab2d: keep the default CG launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -326,7 +327,7 @@ def bench_batch2d(a):
         "data": "synthetic",
         "config": {"workload": f"batch2d {a.tissues} tissues, sides 64..512, lognormal sigma, "
                                "8x8 patch, TTP06, M4 K4, dt 0.05 ms, "
-                               + ("CG" if a.solver == "cg" else "Chebyshev") + " 1e-12",
+                               + SOLVER_NAMES[a.solver] + " 1e-12",
                    "tissues": a.tissues, "nodes_total": int(sum(Ns)), "nodes_min": int(min(Ns)),
                    "nodes_max": int(max(Ns)), "M": ws[0]["M"], "sweeps": ws[0]["K"],
                    "dt_ms": ws[0]["dt"]},
@@ -346,7 +347,7 @@ _KERNEL_CLASS = (("k_node_update", "node_update"), ("k_cg_iter", "cg_iter"),
                  ("k_cg_init", "cg_init"), ("k_assemble", "assemble"),
                  ("k_eval_stages", "eval_stages"), ("k_spmv_stages", "spmv"),
                  ("k_copy_fields", "copy"), ("k_copy_V_to_stages", "copy"),
-                 ("k_cheb_iter", "cheb_iter"))
+                 ("k_cheb_iter", "cheb_iter"), ("k_cg_start", "cg_start"))
 
 
 def summarize_counters(fetch_csv, write_csv):
@@ -545,7 +546,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "slab2d 512x512, 5-point, TTP06, M6 K6, dt 0.05 ms, "
-                               + ("CG" if a.solver == "cg" else "Chebyshev") + " 1e-12",
+                               + SOLVER_NAMES[a.solver] + " 1e-12",
                    "nodes": N, "M": w["M"], "sweeps": w["K"], "dt_ms": w["dt"],
                    "t_simulated_ms": a.steps * w["dt"]},
         "sim_ms_per_wall_s": a.steps * w["dt"] / wall,
@@ -570,9 +571,8 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = src.numel() * 8
         del evict
-    if not a.no_solver_option:
-        # option study: the same workload and tolerance with the other solver
-        other = "chebyshev" if a.solver == "cg" else "cg"
+    # option study: the same workload and tolerance with the other solvers
+    for other in ([] if a.no_solver_option else [o for o in SOLVER_NAMES if o != a.solver]):
         m2 = method(other)
         if a.warmup > 0:
             cw = new_context(m2)
@@ -594,16 +594,20 @@ def main():
         torch.cuda.synchronize()
         kp2, pst2 = c2.profile_read(), c2.stats()
         c2.destroy()
-        out["solver_option"] = {
+        out.setdefault("solver_options", []).append({
             "solver": other, "value": updates / wall2, "ms_per_step": 1e3 * wall2 / a.steps,
             "iters_per_solve": st2["cg_iters"] / max(1, st2["cg_solves"]),
             "unconverged": st2["cg_unconverged"], "redo_steps": st2["cg_redo_steps"],
             "V_max_end_mV": float(V2[0].max()),
             "kernels": _kernel_table(kp2, _solver_bytes(pst2, N)),
-        }
+        })
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))
+
+
+SOLVER_NAMES = {"cg": "CG from three Chebyshev steps", "chebyshev": "Chebyshev",
+                "cg_plain": "CG from the warm start"}
 
 
 def _solver_bytes(pst, N):

@@ -89,12 +89,17 @@ typedef struct {
                              /* tol <= 0 runs exactly max_iter iterations         */
   int32_t burn_in;           /* 1: staggered coarse burn-in before a block, P > 1 */
   int32_t solver;            /* diffusion solves on FP64 levels: 0 conjugate      */
-                             /* gradients; 1 Chebyshev iteration over the         */
-                             /* Gershgorin interval of I - a K (no inner          */
-                             /* products: the iteration count comes from the      */
-                             /* residual bound of the Chebyshev polynomial, the   */
-                             /* same ||b - A x||_2 <= cg_rtol ||b||_2).  An FP32  */
-                             /* coarse level always runs CG.                      */
+                             /* gradients started from the third Chebyshev        */
+                             /* iterate over the Gershgorin interval of I - a K   */
+                             /* (three steps from the warm start without inner    */
+                             /* products, the first one inside the node update);  */
+                             /* 1 Chebyshev iteration over that                   */
+                             /* interval (no inner products: the iteration count  */
+                             /* comes from the residual bound of the Chebyshev    */
+                             /* polynomial, the same ||b - A x||_2 <= cg_rtol     */
+                             /* ||b||_2); 2 conjugate gradients from the warm     */
+                             /* start.  An FP32 coarse level always runs CG from  */
+                             /* the warm start.                                   */
   double cg_rtol;            /* diffusion solve: ||b - A x||_2 <= cg_rtol ||b||_2 */
   int32_t cg_maxit;          /* iteration cap per diffusion solve (Chebyshev:     */
                              /* cap on the polynomial degree)                     */

@@ -175,6 +175,11 @@ struct CgBatchT {
   double *bout;                 // [nslices][Np] (the memory b points to)
   const struct ChebTab *tab;    // this node's entry of absolute slice n: tab[n * tab_stride]
   int tab_stride;
+  // cstart = D >= 2 (with xt set): CG from the Chebyshev iterate x_D.  The node
+  // update stores b and x_1 as above, D - 1 Chebyshev launches form x_2 .. x_D,
+  // and launch_cg_start forms r_D = b - A x_D and w_D = A r_D in the parity-1
+  // vectors (and x_D in x), so the CG launches run k = 1, 2, ...
+  int cstart;
 };
 using CgBatch = CgBatchT<double>;
 int cg_blocks(const Grid &g, int cap = 512);
@@ -188,6 +193,12 @@ hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double 
 // Chebyshev iterate k >= 1 (one launch per k; launch k = 1 also derives the
 // iteration count from the node update's partials of ||r_0||^2 and ||b||^2).
 hipError_t launch_cheb_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int k);
+// Chebyshev steps k = 1 .. kmax alone, x_{k+1} = x_{k-1} + omega_{k+1} (x_k -
+// x_{k-1} + (b - A x_k) / theta) (no iteration count derived or checked).
+hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, int kmax);
+// CG start from x_D (cstart = D): r_D, w_D, the partials of (r_D, r_D) and
+// (w_D, r_D), the parity-1 scalars, and x_D in x.
+hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb);
 
 // transfers (space coarsening 2x or identity) between a fine and a coarse level
 hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
@@ -196,10 +207,11 @@ hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc,
 hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *src, int64_t ssrc, double *dst, int64_t sdst,
                                   int nrows, int nslices);
-// Yf += T (P_space (Yc - Sz)) on every stage; Sz is overwritten with Yc - Sz.
+// Yf += T (P_space (Yc - Sz)) on fine stages i0..Mf; Sz is overwritten with
+// Yc - Sz.
 hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *Yc, double *Sz, int64_t sYc, int Mc,
-                                  const double *Tt, int Mf, double *Yf, int64_t sYf,
+                                  const double *Tt, int Mf, int i0, double *Yf, int64_t sYf,
                                   int nslices);
 
 // building blocks exported for tests

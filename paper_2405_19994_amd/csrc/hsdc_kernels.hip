@@ -274,43 +274,54 @@ __device__ __forceinline__ Grid slice_grid(const Grid &g, int n) {
   return r;
 }
 
-// (K v)_p with v given through val(k) (so callers can form v on the fly).
+// (K v)_p with v given through val(k, c_k), c_k the grid coordinates of
+// neighbour k (so callers can form v on the fly, also from its own stencil).
 template <int DIM, bool PN, class Val>
-__device__ __forceinline__ double applyK(const Grid &g, int64_t p, const Ijk &c, double vc,
-                                         Val &&val) {
+__device__ __forceinline__ double applyK_nb(const Grid &g, int64_t p, const Ijk &c, double vc,
+                                            Val &&val) {
+  const Ijk xm{c.ix - 1, c.iy, c.iz}, xp{c.ix + 1, c.iy, c.iz};
+  const Ijk ym{c.ix, c.iy - 1, c.iz}, yp{c.ix, c.iy + 1, c.iz};
+  const Ijk zm{c.ix, c.iy, c.iz - 1}, zp{c.ix, c.iy, c.iz + 1};
   if (PN) {
     double acc = 0.0;
-    if (c.ix > 0) acc += g.kx[p - 1] * (val(p - 1) - vc);
-    if (c.ix < g.nx - 1) acc += g.kx[p] * (val(p + 1) - vc);
+    if (c.ix > 0) acc += g.kx[p - 1] * (val(p - 1, xm) - vc);
+    if (c.ix < g.nx - 1) acc += g.kx[p] * (val(p + 1, xp) - vc);
     if (DIM >= 2) {
-      if (c.iy > 0) acc += g.ky[p - g.nx] * (val(p - g.nx) - vc);
-      if (c.iy < g.ny - 1) acc += g.ky[p] * (val(p + g.nx) - vc);
+      if (c.iy > 0) acc += g.ky[p - g.nx] * (val(p - g.nx, ym) - vc);
+      if (c.iy < g.ny - 1) acc += g.ky[p] * (val(p + g.nx, yp) - vc);
     }
     if (DIM >= 3) {
       const int64_t pl = (int64_t)g.nx * g.ny;
-      if (c.iz > 0) acc += g.kz[p - pl] * (val(p - pl) - vc);
-      if (c.iz < g.nz - 1) acc += g.kz[p] * (val(p + pl) - vc);
+      if (c.iz > 0) acc += g.kz[p - pl] * (val(p - pl, zm) - vc);
+      if (c.iz < g.nz - 1) acc += g.kz[p] * (val(p + pl, zp) - vc);
     }
     return acc;
   }
   double ax = 0.0;
-  if (c.ix > 0) ax += val(p - 1) - vc;
-  if (c.ix < g.nx - 1) ax += val(p + 1) - vc;
+  if (c.ix > 0) ax += val(p - 1, xm) - vc;
+  if (c.ix < g.nx - 1) ax += val(p + 1, xp) - vc;
   double acc = g.cx * ax;
   if (DIM >= 2) {
     double ay = 0.0;
-    if (c.iy > 0) ay += val(p - g.nx) - vc;
-    if (c.iy < g.ny - 1) ay += val(p + g.nx) - vc;
+    if (c.iy > 0) ay += val(p - g.nx, ym) - vc;
+    if (c.iy < g.ny - 1) ay += val(p + g.nx, yp) - vc;
     acc += g.cy * ay;
   }
   if (DIM >= 3) {
     const int64_t pl = (int64_t)g.nx * g.ny;
     double az = 0.0;
-    if (c.iz > 0) az += val(p - pl) - vc;
-    if (c.iz < g.nz - 1) az += val(p + pl) - vc;
+    if (c.iz > 0) az += val(p - pl, zm) - vc;
+    if (c.iz < g.nz - 1) az += val(p + pl, zp) - vc;
     acc += g.cz * az;
   }
   return acc;
+}
+
+// (K v)_p with v given through val(k) (so callers can form v on the fly).
+template <int DIM, bool PN, class Val>
+__device__ __forceinline__ double applyK(const Grid &g, int64_t p, const Ijk &c, double vc,
+                                         Val &&val) {
+  return applyK_nb<DIM, PN>(g, p, c, vc, [&](int64_t k, const Ijk &) { return val(k); });
 }
 
 #define HSDC_DISPATCH_OP(g, ...)                                    \
@@ -1040,11 +1051,22 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   Ijk c0{0, 0, 0};
   if (si.it == 0) {
     double t3[3] = {0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < nba0; k += BLOCK) {
-      t3[0] += part[k];
-      t3[1] += part[4 * cb.pstride + k];
+    if (cb.cstart) {
+      // gamma and delta of the Chebyshev start (this parity) and ||b||^2, all
+      // over the node update's blocks
+      const double *pg = part + (2 * in) * cb.pstride, *pd = part + (2 * in + 1) * cb.pstride;
+      for (int k = threadIdx.x; k < nba0; k += BLOCK) {
+        t3[0] += pg[k];
+        t3[1] += part[4 * cb.pstride + k];
+        t3[2] += pd[k];
+      }
+    } else {
+      for (int k = threadIdx.x; k < nba0; k += BLOCK) {
+        t3[0] += part[k];
+        t3[1] += part[4 * cb.pstride + k];
+      }
+      for (int k = threadIdx.x; k < nba; k += BLOCK) t3[2] += part[cb.pstride + k];
     }
-    for (int k = threadIdx.x; k < nba; k += BLOCK) t3[2] += part[cb.pstride + k];
     block_sums<3>(t3, lds);
     gamma = t3[0];
     // stop relative to ||b|| or, for a correction solve, to ||r_0||
@@ -1184,6 +1206,97 @@ hipError_t launch_cg_iter(hipStream_t s, const Grid &g, const CgBatchT<T> &cb, i
   return hipGetLastError();
 }
 
+// CG start from the Chebyshev iterate x_D, D = cb.cstart (in x for D even, in
+// xt for D odd, then copied to x): r_D = b - A x_D and w_D = A r_D, with r_D at
+// the stencil neighbours formed from x_D at radius 2.  One node per thread in
+// node-update blocks, so the partials of (r_D, r_D) and (w_D, r_D) (parity-1
+// slots) line up with the node update's partials of ||b||^2; the parity-1
+// scalars are reset for the CG launch k = 1.
+// Uniform coefficients: every stencil read goes through clamped coordinates,
+// so a neighbour missing at the boundary reads the node itself and its term
+// v_q - v_p is exactly 0, as applyK's omitted term; the loads carry no
+// branches.
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(NUB) k_cg_start(Grid g0, CgBatch cb) {
+  __shared__ double lds[2 * (NUB / 64)];
+  const int n = blockIdx.y;
+  const Grid g = slice_grid(g0, cb.slice0 + n);
+  const int64_t qb = stencil_node_block(g0, blockIdx.x, gridDim.x);
+  const int64_t p = qb * NUB + threadIdx.x;
+  const bool odd = cb.cstart & 1;
+  const double *x = odd ? cb.xt + (int64_t)n * g0.Np : cb.x + n * cb.sx;
+  const double *b = cb.b + n * cb.sb;
+  double gam = 0.0, del = 0.0;
+  if (p < g.N) {
+    const Ijk c = ijk(g, p);
+    if (odd) cb.x[n * cb.sx + p] = x[p];
+    double rc, wv;
+    if constexpr (!PN) {
+      const int nx = g.nx, ny = g.ny, nz = g.nz;
+      auto cl = [](int v, int m) { return v < 0 ? 0 : (v > m - 1 ? m - 1 : v); };
+      auto at = [&](int ix, int iy, int iz) {
+        return (int64_t)ix + (int64_t)nx * ((int64_t)iy + (int64_t)ny * iz);
+      };
+      // b - A x at the node (ix, iy, iz), the sums grouped per axis as applyK
+      auto resid = [&](int ix, int iy, int iz) {
+        const double xq = x[at(ix, iy, iz)];
+        const double ax = (x[at(cl(ix - 1, nx), iy, iz)] - xq) + (x[at(cl(ix + 1, nx), iy, iz)] - xq);
+        double acc = g.cx * ax;
+        if (DIM >= 2)
+          acc += g.cy * ((x[at(ix, cl(iy - 1, ny), iz)] - xq) + (x[at(ix, cl(iy + 1, ny), iz)] - xq));
+        if (DIM >= 3)
+          acc += g.cz * ((x[at(ix, iy, cl(iz - 1, nz))] - xq) + (x[at(ix, iy, cl(iz + 1, nz))] - xq));
+        return b[at(ix, iy, iz)] - (xq - cb.a * acc);
+      };
+      rc = resid(c.ix, c.iy, c.iz);
+      const double ax = (resid(cl(c.ix - 1, nx), c.iy, c.iz) - rc) +
+                        (resid(cl(c.ix + 1, nx), c.iy, c.iz) - rc);
+      double acc = g.cx * ax;
+      if (DIM >= 2)
+        acc += g.cy * ((resid(c.ix, cl(c.iy - 1, ny), c.iz) - rc) +
+                       (resid(c.ix, cl(c.iy + 1, ny), c.iz) - rc));
+      if (DIM >= 3)
+        acc += g.cz * ((resid(c.ix, c.iy, cl(c.iz - 1, nz)) - rc) +
+                       (resid(c.ix, c.iy, cl(c.iz + 1, nz)) - rc));
+      wv = rc - cb.a * acc;
+    } else {
+      auto resid = [&](int64_t q, const Ijk &cq) {
+        const double xq = x[q];
+        return b[q] - (xq - cb.a * applyK<DIM, PN>(g, q, cq, xq, [&](int64_t k) { return x[k]; }));
+      };
+      rc = resid(p, c);
+      wv = rc - cb.a * applyK_nb<DIM, PN>(g, p, c, rc, resid);
+    }
+    cb.r[1][n * g.Np + p] = rc;
+    cb.w[1][n * g.Np + p] = wv;
+    gam = rc * rc;
+    del = wv * rc;
+  }
+  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+  double t2[2] = {gam, del};
+  block_sums<2, NUB>(t2, lds);
+  if (threadIdx.x == 0) {
+    part[2 * cb.pstride + qb] = t2[0];
+    part[3 * cb.pstride + qb] = t2[1];
+    if (blockIdx.x == 0) {
+      CgScalars o;
+      o.bb = -1.0;  // reduced by the first iteration kernel
+      o.gamma = 1.0;
+      o.alpha = 1.0;
+      o.it = 0;
+      o.done = 0;
+      cb.sc[2 * n + 1] = o;
+    }
+  }
+}
+
+hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb) {
+  // the node update's block count (every block writes its partials)
+  dim3 grid(node_blocks(g), cb.nslices);
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_start<DIM, PN>), grid, dim3(NUB), 0, s, g, cb));
+  return hipGetLastError();
+}
+
 template <int DIM, bool PN>
 __global__ void __launch_bounds__(BLOCK) k_apply_K(Grid g, const double *v, double *out) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -1244,7 +1357,8 @@ __device__ __forceinline__ int cheb_count(const ChebTab &t, double rr0, double r
 // has one more block per slice that reduces the node update's partials of
 // ||r_0||^2 and ||b||^2 and publishes the count while the others iterate.
 template <int DIM, bool PN>
-__global__ void __launch_bounds__(BLOCK) k_cheb_iter(Grid g0, CgBatch cb, int k, int nbx) {
+__global__ void __launch_bounds__(BLOCK) k_cheb_iter(Grid g0, CgBatch cb, int k, int nbx,
+                                                     int step_only) {
   __shared__ double lds[3 * (BLOCK / 64)];
   const int n = blockIdx.y;
   const ChebTab &t = cb.tab[(cb.slice0 + n) * cb.tab_stride];
@@ -1272,7 +1386,7 @@ __global__ void __launch_bounds__(BLOCK) k_cheb_iter(Grid g0, CgBatch cb, int k,
     }
     return;
   }
-  if (k > 1) {
+  if (k > 1 && !step_only) {
     const int m = sc[0].it;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc[0].done = k + 1 >= m;
@@ -1300,7 +1414,17 @@ hipError_t launch_cheb_iter(hipStream_t s, const Grid &g, const CgBatch &cb, int
   const int nbx = (int)(g.rag ? nblocks(g.N) : nblocks_xcd(g.N));
   dim3 grid(nbx + (k == 1 ? 1 : 0), cb.nslices);
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cheb_iter<DIM, PN>), grid, dim3(BLOCK), 0, s, g, cb,
-                                         k, nbx));
+                                         k, nbx, 0));
+  return hipGetLastError();
+}
+
+hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, int kmax) {
+  if (cb.nslices <= 0) return hipSuccess;
+  const int nbx = (int)(g.rag ? nblocks(g.N) : nblocks_xcd(g.N));
+  dim3 grid(nbx, cb.nslices);
+  for (int k = 1; k <= kmax; ++k)
+    HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cheb_iter<DIM, PN>), grid, dim3(BLOCK), 0, s, g,
+                                           cb, k, nbx, 1));
   return hipGetLastError();
 }
 
@@ -1399,14 +1523,15 @@ hipError_t launch_restrict_fields(hipStream_t s, const Grid &gf, const Grid &gc,
   return hipGetLastError();
 }
 
-// y_f += T P(z_c - S z): the coarse difference is formed on the fly at the (up
-// to 8) coarse cells that interpolate onto fine node p.  Per axis the two cells
-// and weights are kept in registers and the 2 x 2 x 2 taps are unrolled (an
-// axis of one node has weight 0 on its second cell and is skipped).  Fine node
-// blocks sharing coarse cells run on one XCD (xcd_node_block).
+// y_f += T P(z_c - S z) at fine stages i0..Mf: the coarse difference Dc is read
+// at the (up to 8) coarse cells that interpolate onto fine node p.  Per axis
+// the two cells and weights are kept in registers and the 2 x 2 x 2 taps are
+// unrolled (an axis of one node has weight 0 on its second cell and is
+// skipped).  Fine node blocks sharing coarse cells run on one XCD
+// (xcd_node_block).
 __global__ void __launch_bounds__(BLOCK)
 k_prolong_correct(Grid gf, Grid gc, int scf, const double *Dc, int64_t sYc, int Mc,
-                  const double *Tt, int Mf, double *Yf, int64_t sYf) {
+                  const double *Tt, int Mf, int i0, double *Yf, int64_t sYf) {
   const int64_t p = xcd_node_block(blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (p >= gf.N) return;
   const int n = blockIdx.z;
@@ -1474,12 +1599,14 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *Dc, int64_t sYc, int 
   }
 #pragma unroll
   for (int i = 0; i <= MAXM; ++i) {
-    if (i <= Mf) {
+    if (i >= i0 && i <= Mf) {
       double s = 0.0;
 #pragma unroll
       for (int j = 0; j <= MAXM; ++j)
         if (j <= Mc) s += Tt[i * (Mc + 1) + j] * dc[j];
-      Yf[n * sYf + ((int64_t)i * NF + f) * gf.Np + p] += s;
+      double *yf = Yf + n * sYf + ((int64_t)i * NF + f) * gf.Np + p;
+      // streaming store: the fine stages are read next by a later kernel
+      stream_store<double>(yf, *yf + s);
     }
   }
 }
@@ -1493,12 +1620,12 @@ __global__ void __launch_bounds__(BLOCK) k_sub_from(double *d, const double *y, 
 
 hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *Yc, double *Sz, int64_t sYc, int Mc,
-                                  const double *Tt, int Mf, double *Yf, int64_t sYf,
+                                  const double *Tt, int Mf, int i0, double *Yf, int64_t sYf,
                                   int nslices) {
   const int64_t nc = (int64_t)nslices * sYc;
   hipLaunchKernelGGL(k_sub_from, dim3(nblocks(nc)), dim3(BLOCK), 0, s, Sz, Yc, nc);
   hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks_xcd(gf.N), NF, nslices), dim3(BLOCK), 0, s,
-                     gf, gc, sc_factor, Sz, sYc, Mc, Tt, Mf, Yf, sYf);
+                     gf, gc, sc_factor, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);
   return hipGetLastError();
 }
 

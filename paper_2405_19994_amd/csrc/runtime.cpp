@@ -74,8 +74,8 @@ struct LevelT {
   T *cg_r[2] = {nullptr, nullptr}, *cg_w[2] = {nullptr, nullptr};
   T *cg_s[2] = {nullptr, nullptr}, *cg_p = nullptr;
   double *cg_part = nullptr;
-  // Chebyshev solver (FP64 levels with solver 1): second iterate buffer and the
-  // parameters of every (slice, collocation node) operator
+  // Chebyshev steps (FP64 levels with solver 0 or 1): second iterate buffer and
+  // the parameters of every (slice, collocation node) operator
   double *cheb_x = nullptr;      // [P][Np]
   ChebTab *cheb_tab = nullptr;   // [P][M]
   CgScalars *cg_sc = nullptr;       // [P][2]
@@ -338,7 +338,8 @@ bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why)
   if (!(m->cg_rtol > 0) || !(m->cg_rtol < 1)) return why = "cg_rtol must be in (0, 1)", false;
   if (m->cg_maxit < 1) return why = "cg_maxit must be >= 1", false;
   if (m->coarse_fp32 != 0 && m->coarse_fp32 != 1) return why = "coarse_fp32 must be 0 or 1", false;
-  if (m->solver != 0 && m->solver != 1) return why = "solver must be 0 (CG) or 1 (Chebyshev)", false;
+  if (m->solver < 0 || m->solver > 2)
+    return why = "solver must be 0 (CG), 1 (Chebyshev) or 2 (CG from the warm start)", false;
   if (!std::isfinite(m->coarse_cg_rtol) || !(m->coarse_cg_rtol < 1))
     return why = "coarse_cg_rtol must be finite and < 1", false;
   return true;
@@ -476,7 +477,7 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
-  if (std::is_same<T, double>::value && c->meth.solver == 1) {
+  if (std::is_same<T, double>::value && (c->meth.solver == 0 || c->meth.solver == 1)) {
     L.cheb_x = dalloc<double>(c, (size_t)P * Np);
     L.cheb_tab = dalloc<ChebTab>(c, (size_t)P * M);
     set_lam(c, L, std::vector<double>(P, lam_uniform(L.g.dim, L.g.nx, L.g.ny, L.g.nz, L.g.cx,
@@ -503,6 +504,12 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
 // ---------------------------------------------------------------------------
 // diffusion solve for node i of a sweep, slices [s0, s0+ns)
 // ---------------------------------------------------------------------------
+// Degree of the Chebyshev start of CG (solver 0): each step shrinks the
+// residual bound by about 2 sigma (sigma = 1 + 2 / (a lam), 4 to 100 on these
+// workloads) for one stencil launch without inner products, cheaper than a CG
+// iteration.
+constexpr int kChebStartDegree = 3;
+
 template <class T>
 CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i) {
   CgBatchT<T> cb{};
@@ -538,6 +545,7 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
     cb.bout = L.st.B + s0 * Np;
     cb.tab = L.cheb_tab + (i - 1);
     cb.tab_stride = L.co.M;
+    cb.cstart = c->meth.solver == 0 ? kChebStartDegree : 0;
   }
   return cb;
 }
@@ -646,22 +654,33 @@ void cheb_solve(hsdc_ctx *c, Level &L, int lev, int s0, int ns, int i, int pred_
 template <class T>
 void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pred_row) {
   CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
+  const double nodes = slice_nodes(c, L, s0, ns);
+  // first CG launch index: 1 after a Chebyshev start (its vectors have parity 1)
+  int k0 = 0;
   if constexpr (std::is_same<T, double>::value) {
-    if (cb.xt) {
+    if (cb.xt && !cb.cstart) {
       cheb_solve(c, L, lev, s0, ns, i, pred_row, cb);
       return;
     }
+    if (cb.cstart) {
+      // x_2 .. x_D (x_k, x_{k-1}, b read, x_{k+1} written); r_D and w_D (x_D and
+      // b read, r, w and for D odd x written)
+      PLAUNCH(c, PC_CGINIT, 32.0 * nodes * (cb.cstart - 1),
+              launch_cheb_steps(c->s, L.g, cb, cb.cstart - 1));
+      PLAUNCH(c, PC_CGINIT, (32.0 + 8.0 * (cb.cstart & 1)) * nodes,
+              launch_cg_start(c->s, L.g, cb));
+      k0 = 1;
+    }
   }
-  const double nodes = slice_nodes(c, L, s0, ns);
-  PLAUNCH(c, PC_CGINIT, 16.0 * nodes, launch_cg_init(c->s, L.g, cb));
+  if (k0 == 0) PLAUNCH(c, PC_CGINIT, 16.0 * nodes, launch_cg_init(c->s, L.g, cb));
   int &pred = L.cg_pred[pred_row & 15][i - 1];
   if (!c->safe_cg) {
     if (c->cg_log_used + ns > c->cg_log_cap) flush_cg_log(c);  // log full: verify now
     const int budget = std::max(1, std::min(pred, cb.maxit + 1));
     cb.log = c->cg_dlog + c->cg_log_used;
-    cb.last_k = budget - 1;
+    cb.last_k = budget - 1 + k0;
     ProfScope ps(c, PC_CGITER, 0.0);
-    for (int k = 0; k < budget; ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+    for (int k = k0; k < budget + k0; ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
     ps.end(budget);
     c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget, false});
     c->cg_log_used += ns;
@@ -669,19 +688,20 @@ void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pre
   }
   // safe mode: iterate until every slice has converged, checking on the host
   const double tol2 = cb.tol2;
-  int k = 0;
+  int k = k0;
   int batch = std::max(1, std::min(pred, cb.maxit + 1));
   for (;;) {
     ProfScope ps(c, PC_CGITER, 0.0);
     int nl = 0;
-    for (int q = 0; q < batch && k <= cb.maxit; ++q, ++k, ++nl) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+    for (int q = 0; q < batch && k <= cb.maxit + k0; ++q, ++k, ++nl)
+      HIPC(launch_cg_iter(c->s, L.g, cb, k));
     ps.end(nl);
     HIPC(hipMemcpyAsync(L.cg_sc_host + 2 * s0, L.cg_sc + 2 * s0, 2 * ns * sizeof(CgScalars),
                         hipMemcpyDeviceToHost, c->s));
     HIPC(hipStreamSynchronize(c->s));
     bool all = true;
     for (int n = 0; n < ns; ++n) all = all && L.cg_sc_host[2 * (s0 + n) + (k & 1)].done;
-    if (all || k > cb.maxit) break;
+    if (all || k > cb.maxit + k0) break;
     batch = 2;
   }
   int used = 0;
@@ -837,15 +857,19 @@ void restrict_fine_to_coarse(hsdc_ctx *c, LevelT<T> &Cc) {
                                  F.co.M, c->Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
 }
 
+// Fine stages from stage i0 on take the coarse correction.  i0 = 1 where a
+// fine sweep follows at once: it overwrites every slice's stage 0 with its
+// start value before reading it.
 template <class T>
-void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc) {
+void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc, int i0) {
   Level &F = c->L[0];
   // z_c - S z formed in S z (z_c and S z read, the difference written), then
-  // read once at the coarse cells; fine stages read and written
-  const double bytes = 8.0 * F.P * NF * (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0) * F.g.N);
+  // read once at the coarse cells; fine stages i0..M read and written
+  const double bytes =
+      8.0 * F.P * NF * (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0 - i0) * F.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
           launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz,
-                                 Cc.st.sY(), Cc.co.M, c->Tt, F.co.M, F.st.Y, F.st.sY(), F.P));
+                                 Cc.st.sY(), Cc.co.M, c->Tt, F.co.M, i0, F.st.Y, F.st.sY(), F.P));
 }
 
 // start values u_n of a sweep over slices [s0, s0+ns) from the stage-M values
@@ -876,7 +900,7 @@ void burn_in(hsdc_ctx *c, LevelT<T> &Cc) {
     gather_starts(c, Cc, Cc.y0c, s, P - s);
     sweep(c, Cc, 1, s, P - s, Cc.U + s * Cc.st.sS(), nullptr, 15, true);
   }
-  coarse_correct_fine(c, Cc);
+  coarse_correct_fine(c, Cc, 0);
 }
 
 void begin_block(hsdc_ctx *c) {
@@ -921,7 +945,7 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
       gather_starts(c, Cc, Cc.y0c, n, 1);
       sweep(c, Cc, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14, true);
     }
-    coarse_correct_fine(c, Cc);
+    coarse_correct_fine(c, Cc, 1);
   });
   // Q^par on the fine level: start values from the (corrected) iterate
   gather_starts(c, F, c->y0blk, 0, P);

@@ -157,7 +157,7 @@ def make_problem(dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None, chi=1400.0, C
     return p
 
 
-SOLVERS = {"cg": 0, "chebyshev": 1}
+SOLVERS = {"cg": 0, "chebyshev": 1, "cg_plain": 2}
 
 
 def make_method(M=(4, 2), levels=1, space_coarsen=1, P=1, dt=0.05, max_iter=4, tol=0.0,

@@ -51,7 +51,7 @@ def test_bad_problem_is_einval(bad):
     dict(M=(0, 1)), dict(M=(9, 1)), dict(dt=0.0), dict(max_iter=0), dict(cg_rtol=0.0),
     dict(levels=3), dict(levels=1, P=4), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
     dict(levels=2, M=(4, 2), P=2, coarse_fp32=2), dict(levels=2, M=(4, 2), P=2, coarse_cg_rtol=1.0),
-    dict(solver=2), dict(solver=-1),
+    dict(solver=3), dict(solver=-1),
 ])
 def test_bad_method_is_einval(bad):
     p = H.make_problem((15,), 0.01)

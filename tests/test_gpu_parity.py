@@ -179,7 +179,23 @@ def test_chebyshev_solver_serial_parity(case):
         _serial_parity(si.workload("slab3d", dims=(10, 8, 6)), 12, 4, 3, 3, solver="chebyshev")
 
 
-@pytest.mark.parametrize("solver", ["cg", "chebyshev"])
+@pytest.mark.parametrize("case", ["cable1d", "slab2d", "pernode", "slab3d"])
+def test_plain_cg_serial_parity(case):
+    """CG from the warm start alone (no Chebyshev steps first) on every stencil
+    and on per-node sigma: serial runs match the oracle's exact solves to
+    1e-10."""
+    if case == "cable1d":
+        _serial_parity(si.workload("cable1d"), 60, 20, 4, 4, solver="cg_plain")
+    elif case == "slab2d":
+        _serial_parity(si.workload("slab2d", dims=(31, 23)), 30, 10, 6, 6, solver="cg_plain")
+    elif case == "pernode":
+        t = si.batch2d_tissues(1, seed=3, lo=20, hi=40)[0]
+        _serial_parity(t, 24, 8, 4, 4, solver="cg_plain")
+    else:
+        _serial_parity(si.workload("slab3d", dims=(10, 8, 6)), 12, 4, 3, 3, solver="cg_plain")
+
+
+@pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])
 def test_solver_iteration_cap_reports_enoconv(solver):
     """A solve that cannot reach cg_rtol within cg_maxit (2 iterations to 1e-14,
     through the stimulus) ends in HSDC_ENOCONV after the step, counted in
@@ -234,7 +250,8 @@ def _pfasst_case(dims, Mf, Mc, coarsen, P, dt, seed_state=False, solver="cg"):
 
 
 @pytest.mark.parametrize("dims,coarsen,solver", [((8, 6, 4), 2, "cg"), ((16,), 1, "cg"),
-                                                ((8, 6, 4), 2, "chebyshev")])
+                                                ((8, 6, 4), 2, "chebyshev"),
+                                                ((8, 6, 4), 2, "cg_plain")])
 def test_pfasst_iterates_parity(dims, coarsen, solver):
     """Every iterate of Algorithm 1 (burn-in, tau, Q^seq coarse sweep, coarse
     grid correction, Q^par fine sweep) matches the oracle, slice by slice (with
@@ -347,7 +364,7 @@ def test_batch_matches_oracle_per_tissue(solver):
         assert np.max(field_errors(g, y)) < 1e-10, (n, w["dims"], np.max(field_errors(g, y)))
 
 
-@pytest.mark.parametrize("solver", ["cg", "chebyshev"])
+@pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])
 def test_batch_matches_single_contexts(solver):
     """Five ragged tissues (20..60 nodes a side): the batch equals five separate
     contexts bitwise (every reduction adds the same partials in the same order,
@@ -393,7 +410,7 @@ def test_tuned_launch_shapes_give_the_same_run():
     assert np.max(e) < 1e-11
 
 
-@pytest.mark.parametrize("solver", ["cg", "chebyshev"])
+@pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])
 def test_graph_replay_equals_eager_steps(solver):
     """Serial steps replayed from a captured HIP graph (device step counter,
     budgeted solves verified per replay) give the same states as eager steps,
@@ -435,7 +452,7 @@ def test_graph_replay_equals_eager_steps(solver):
 # full size: the 512 x 512 slab in the benchmark's launch configuration
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("solver", ["cg", "chebyshev"])
+@pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])
 def test_slab2d_full_size_sweep_equation_at_sampled_nodes(solver):
     """At full size, after 30 steps (through the stimulus), two more sweeps of
     the 31st step; the oracle evaluates eq. prec_picard at 3000 sampled nodes
@@ -517,7 +534,7 @@ def test_slab3d_full_size_pfasst_reaches_serial_collocation():
     assert y_ref[0].max() > 0.0  # the face stimulus started an action potential
 
 
-@pytest.mark.parametrize("solver", ["cg", "chebyshev"])
+@pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])
 def test_batch2d_full_size_tissues_equal_single_contexts(solver):
     """The 64-tissue batch at full size (sides 64..512, 6.05M nodes, M 4, K 4):
     after 4 steps through the stimulus onset, sampled tissues (the smallest, the
