@@ -61,6 +61,10 @@ def _args():
     ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d", "cable1d"),
                     default="slab2d")
     ap.add_argument("--tissues", type=int, default=64, help="batch2d: tissues in the batch")
+    ap.add_argument("--summarize-valu", metavar="COUNTER_CSV",
+                    help="write the VALU instruction counters (SQ_WAVES, SQ_INSTS_VALU and its "
+                         "FP64 FMA/ADD/MUL/TRANS parts) of a rocprofv3 --pmc run into "
+                         "profiles/valu_slab2d.json")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, "
                          "WRITE_SIZE) of a --calibrate-copy run into profiles/hbm_traffic_slab2d.json")
@@ -120,6 +124,30 @@ def _traffic(kernel):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def _valu(kernel, avg_us):
+    """FP64 VALU work of `kernel` per launch from rocprofv3 instruction
+    counters (profiles/valu_slab2d.json): FLOP = 64 lanes x (2 FMA + ADD + MUL
+    + transcendental) per wave instruction, over the event-timed launch
+    duration, against the FP64 vector peak; also the issue-slot fraction of
+    all VALU instructions (four cycles per wave instruction on a 16-lane SIMD,
+    1024 SIMDs at 2.4 GHz).  None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "valu_slab2d.json")
+    if not os.path.exists(path) or not avg_us:
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_digest") != _kernel_sources_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None:
+        return None
+    t = avg_us * 1e-6
+    tf = k["flop_f64"] / t / 1e12
+    issue = k["valu"] * 4.0 / (1024 * 2.4e9 * t)
+    return {"kernel": kernel, "bound": "alu", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
+            "frac": tf / 78.6, "valu_issue_frac": issue, "flop_per_launch": k["flop_f64"]}
 
 
 def _kernel_table(kp, overrides=None):
@@ -393,6 +421,43 @@ def summarize_counters(fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
+def summarize_valu(csv_path):
+    """Per kernel class: average per dispatch of the VALU instruction counters
+    (all VALU, FP64 FMA, ADD, MUL and transcendental, waves) and the FP64 FLOP
+    they make, into profiles/valu_slab2d.json."""
+    import csv
+
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        name = r["Kernel_Name"]
+        for key, cls in _KERNEL_CLASS:
+            if key in name:
+                d = per.setdefault(cls, {})
+                d.setdefault((r["Dispatch_Id"], r["Counter_Name"]), 0.0)
+                d[(r["Dispatch_Id"], r["Counter_Name"])] += float(r["Counter_Value"])
+                break
+    kernels = {}
+    for cls, d in per.items():
+        disp = sorted({k[0] for k in d})
+        avg = {}
+        for cn in ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+                   "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64"):
+            avg[cn] = sum(d.get((i, cn), 0.0) for i in disp) / len(disp)
+        flop = 64.0 * (2.0 * avg["SQ_INSTS_VALU_FMA_F64"] + avg["SQ_INSTS_VALU_ADD_F64"]
+                       + avg["SQ_INSTS_VALU_MUL_F64"] + avg["SQ_INSTS_VALU_TRANS_F64"])
+        kernels[cls] = {"dispatches": len(disp), "waves": avg["SQ_WAVES"],
+                        "valu": avg["SQ_INSTS_VALU"], "fma_f64": avg["SQ_INSTS_VALU_FMA_F64"],
+                        "add_f64": avg["SQ_INSTS_VALU_ADD_F64"],
+                        "mul_f64": avg["SQ_INSTS_VALU_MUL_F64"],
+                        "trans_f64": avg["SQ_INSTS_VALU_TRANS_F64"], "flop_f64": flop}
+    rec = {"workload": "slab2d 512x512, M 6, K 6, dt 0.05 ms",
+           "sources_digest": _kernel_sources_digest(), "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", "valu_slab2d.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def bench_cable1d(a):
     """The 1D cable (128 nodes, M 4, K 4, dt 0.05 ms, T 10 ms): a latency-bound
     serial run, timed with eager launches and with each step replayed from a
@@ -444,6 +509,9 @@ def main():
     a = _args()
     if a.summarize_counters:
         summarize_counters(*a.summarize_counters)
+        return
+    if a.summarize_valu:
+        summarize_valu(a.summarize_valu)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -556,6 +624,7 @@ def main():
         "cg_unconverged": st["cg_unconverged"],
         "V_max_end_mV": Vmax,
         "roofline": roofline,
+        "roofline_valu": _valu("node_update", kernels.get("node_update", {}).get("avg_us")),
         "kernels": kernels,
         "tuning": tuning,
     }
