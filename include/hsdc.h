@@ -89,10 +89,11 @@ typedef struct {
                              /* tol <= 0 runs exactly max_iter iterations         */
   int32_t burn_in;           /* 1: staggered coarse burn-in before a block, P > 1 */
   int32_t solver;            /* diffusion solves on FP64 levels: 0 conjugate      */
-                             /* gradients started from the third Chebyshev        */
-                             /* iterate over the Gershgorin interval of I - a K   */
-                             /* (three steps from the warm start without inner    */
-                             /* products, the first one inside the node update);  */
+                             /* gradients started from a Chebyshev iterate over   */
+                             /* the Gershgorin interval of I - a K (steps from    */
+                             /* the warm start without inner products, the first  */
+                             /* inside the node update: degree 5 on 2D meshes     */
+                             /* with uniform sigma, in one tiled launch, else 3); */
                              /* 1 Chebyshev iteration over that                   */
                              /* interval (no inner products: the iteration count  */
                              /* comes from the residual bound of the Chebyshev    */

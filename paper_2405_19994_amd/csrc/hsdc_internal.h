@@ -180,6 +180,12 @@ struct CgBatchT {
   // and launch_cg_start forms r_D = b - A x_D and w_D = A r_D in the parity-1
   // vectors (and x_D in x), so the CG launches run k = 1, 2, ...
   int cstart;
+  // partials of (r_D, r_D) and (w_D, r_D) written by the start (first CG
+  // launch), and xin_p = 1 when the start left x_D in p rather than x (the
+  // tiled start, launch_cg_start_tiled: the first CG launch forms x from p,
+  // or copies p to x if it finds x_D converged)
+  int nblk_s;
+  int xin_p;
 };
 using CgBatch = CgBatchT<double>;
 int cg_blocks(const Grid &g, int cap = 512);
@@ -199,6 +205,11 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // CG start from x_D (cstart = D): r_D, w_D, the partials of (r_D, r_D) and
 // (w_D, r_D), the parity-1 scalars, and x_D in x.
 hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb);
+// The whole CG start of degree 3 in one launch on 2D meshes with uniform
+// coefficients (x_2, x_3, r_3, w_3 in LDS tiles with a halo of 4); x_3 goes to
+// p.  cg_start_tiles(g) = its block count per slice (0: not applicable).
+int cg_start_tiles(const Grid &g, int degree);
+hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb);
 
 // transfers (space coarsening 2x or identity) between a fine and a coarse level
 hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,

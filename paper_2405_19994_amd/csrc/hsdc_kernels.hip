@@ -1052,14 +1052,14 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   if (si.it == 0) {
     double t3[3] = {0.0, 0.0, 0.0};
     if (cb.cstart) {
-      // gamma and delta of the Chebyshev start (this parity) and ||b||^2, all
-      // over the node update's blocks
+      // gamma and delta of the Chebyshev start (this parity, over the start's
+      // blocks) and ||b||^2 (over the node update's)
       const double *pg = part + (2 * in) * cb.pstride, *pd = part + (2 * in + 1) * cb.pstride;
-      for (int k = threadIdx.x; k < nba0; k += BLOCK) {
+      for (int k = threadIdx.x; k < cb.nblk_s; k += BLOCK) {
         t3[0] += pg[k];
-        t3[1] += part[4 * cb.pstride + k];
         t3[2] += pd[k];
       }
+      for (int k = threadIdx.x; k < nba0; k += BLOCK) t3[1] += part[4 * cb.pstride + k];
     } else {
       for (int k = threadIdx.x; k < nba0; k += BLOCK) {
         t3[0] += part[k];
@@ -1100,6 +1100,14 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
     delta = t2[1];
   }
   if (gamma <= cb.tol2 * si.bb || gamma == 0.0 || si.it >= cb.maxit) {
+    if constexpr (std::is_same<T, double>::value) {
+      if (si.it == 0 && cb.xin_p) {
+        // the start's x_D is the solution: move it from p to x
+        const double *xs = cb.p + n * g.Np;
+        double *xd = cb.x + n * cb.sx;
+        for (int64_t q = p0; q < g.N; q += (int64_t)cb.nblk * BLOCK) xd[q] = xs[q];
+      }
+    }
     if (publish) {
       CgScalars o = si;
       o.gamma = gamma;
@@ -1119,11 +1127,13 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   double *x = cb.x + n * cb.sx;
   double gam = 0.0, del = 0.0;
   // iteration 0 takes p = r, s = w (p and s hold nothing yet)
+  // (after a tiled start, iteration 0 finds x_D in p)
+  const bool x_from_p = first && cb.xin_p;
   auto update = [&](int64_t p, const Ijk &c, double rc0, double wc0, double sc0, auto &&rn) {
     const double pn = first ? rc0 : rc0 + beta * pp[p];
     const double sn = first ? wc0 : wc0 + beta * sc0;
     const double rc = rc0 - alpha * sn;
-    x[p] += alpha * pn;
+    x[p] = (x_from_p ? (double)pp[p] : x[p]) + alpha * pn;
     const double wn = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, rn);
     pp[p] = pn;
     sout[p] = sn;
@@ -1425,6 +1435,142 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
   for (int k = 1; k <= kmax; ++k)
     HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cheb_iter<DIM, PN>), grid, dim3(BLOCK), 0, s, g,
                                            cb, k, nbx, 1));
+  return hipGetLastError();
+}
+
+// The CG start of degree D in one launch (2D, uniform coefficients, one mesh
+// for every slice): a block holds a 32 x 16 tile of nodes with a halo of D + 1
+// in LDS and runs the Chebyshev steps x_2 .. x_D there (x_k on the tile's
+// radius D + 1 - k), then r_D = b - A x_D (radius 1) and w_D = A r_D (tile),
+// from x_1 (xt), x_0 (x) and b, in the arithmetic of the Chebyshev and start
+// kernels (a neighbour missing at the boundary reads the node itself, so its
+// term is exactly 0).  x_{k+1} overwrites x_{k-1} cell by cell, so two LDS
+// vectors and b suffice.  x_D goes to p, not x: other tiles still read x_0
+// from x.  Partials of (r_D, r_D) and (w_D, r_D) per tile.
+constexpr int CTX = 32, CTY = 16, CT_THREADS = 256;
+
+int cg_start_tiles(const Grid &g, int degree) {
+  if (degree < 3 || degree > 5 || g.dim != 2 || g.kx != nullptr || g.rag != nullptr) return 0;
+  return ((g.nx + CTX - 1) / CTX) * ((g.ny + CTY - 1) / CTY);
+}
+
+template <int D>
+__global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g, CgBatch cb, int tiles_x) {
+  constexpr int H = D + 1, W = CTX + 2 * H, HH = CTY + 2 * H;
+  __shared__ double sa[HH][W], sk[HH][W], sb[HH][W];
+  __shared__ double lds[2 * (CT_THREADS / 64)];
+  const int n = blockIdx.y;
+  const int nt = gridDim.x;
+  const int t = (nt % kXcds == 0) ? (int)xcd_node_block(blockIdx.x, nt) : (int)blockIdx.x;
+  const int X0 = (t % tiles_x) * CTX - H, Y0 = (t / tiles_x) * CTY - H;
+  const int nx = g.nx, ny = g.ny;
+  const double *x1g = cb.xt + (int64_t)n * g.Np;
+  const double *x0g = cb.x + n * cb.sx;
+  const double *bg = cb.b + n * cb.sb;
+  const ChebTab &tb = cb.tab[(cb.slice0 + n) * cb.tab_stride];
+  const double ith = tb.inv_theta, a = cb.a;
+  // sa: x_{k-1}, sk: x_k (x_0 and x_1 to start with)
+  double (*xm)[W] = sa, (*xk)[W] = sk;
+  for (int q = threadIdx.x; q < W * HH; q += CT_THREADS) {
+    const int u = q % W, v = q / W, gx = X0 + u, gy = Y0 + v;
+    double v1 = 0.0, v0 = 0.0, vb = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const int64_t p = gx + (int64_t)nx * gy;
+      v1 = x1g[p];
+      v0 = x0g[p];
+      vb = bg[p];
+    }
+    sk[v][u] = v1;
+    sa[v][u] = v0;
+    sb[v][u] = vb;
+  }
+  __syncthreads();
+  // K S at cell (u, v), grouped per axis as applyK
+  auto Kat = [&](double (*S)[W], int u, int v) {
+    const int gx = X0 + u, gy = Y0 + v;
+    const double c = S[v][u];
+    const double l = gx > 0 ? S[v][u - 1] : c, r = gx < nx - 1 ? S[v][u + 1] : c;
+    const double d = gy > 0 ? S[v - 1][u] : c, up = gy < ny - 1 ? S[v + 1][u] : c;
+    double acc = g.cx * ((l - c) + (r - c));
+    acc += g.cy * ((d - c) + (up - c));
+    return acc;
+  };
+  auto inside = [&](int u, int v) {
+    const int gx = X0 + u, gy = Y0 + v;
+    return gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+  };
+  // x_{k+1} = x_{k-1} + omega_{k+1} (x_k - x_{k-1} + (b - A x_k) / theta) on
+  // radius D - k, written over x_{k-1}
+#pragma unroll
+  for (int k = 1; k < D; ++k) {
+    const double om = cheb_omega(tb, k);
+    const int m = k, w = W - 2 * m, h = HH - 2 * m;
+    for (int q = threadIdx.x; q < w * h; q += CT_THREADS) {
+      const int u = m + q % w, v = m + q / w;
+      if (!inside(u, v)) continue;
+      const double xc = xk[v][u], xo = xm[v][u];
+      const double r = sb[v][u] - (xc - a * Kat(xk, u, v));
+      xm[v][u] = xo + om * (xc - xo + ith * r);
+    }
+    __syncthreads();
+    double (*tmp)[W] = xm;
+    xm = xk;
+    xk = tmp;
+  }
+  // r_D = b - A x_D on radius 1, over x_{D-1}
+  {
+    const int m = D, w = W - 2 * m, h = HH - 2 * m;
+    for (int q = threadIdx.x; q < w * h; q += CT_THREADS) {
+      const int u = m + q % w, v = m + q / w;
+      if (!inside(u, v)) continue;
+      const double xq = xk[v][u];
+      xm[v][u] = sb[v][u] - (xq - a * Kat(xk, u, v));
+    }
+  }
+  __syncthreads();
+  // w_D = A r_D on the tile; x_D to p, r_D and w_D to the parity-1 vectors
+  double gam = 0.0, del = 0.0;
+  for (int q = threadIdx.x; q < CTX * CTY; q += CT_THREADS) {
+    const int u = H + q % CTX, v = H + q / CTX;
+    if (!inside(u, v)) continue;
+    const double rc = xm[v][u];
+    const double wv = rc - a * Kat(xm, u, v);
+    const int64_t p = (X0 + u) + (int64_t)nx * (Y0 + v);
+    cb.p[n * g.Np + p] = xk[v][u];
+    cb.r[1][n * g.Np + p] = rc;
+    cb.w[1][n * g.Np + p] = wv;
+    gam += rc * rc;
+    del += wv * rc;
+  }
+  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+  double t2[2] = {gam, del};
+  block_sums<2, CT_THREADS>(t2, lds);
+  if (threadIdx.x == 0) {
+    part[2 * cb.pstride + t] = t2[0];
+    part[3 * cb.pstride + t] = t2[1];
+    if (blockIdx.x == 0) {
+      CgScalars o;
+      o.bb = -1.0;  // reduced by the first iteration kernel
+      o.gamma = 1.0;
+      o.alpha = 1.0;
+      o.it = 0;
+      o.done = 0;
+      cb.sc[2 * n + 1] = o;
+    }
+  }
+}
+
+hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb) {
+  const int nt = cg_start_tiles(g, cb.cstart);
+  if (nt <= 0 || cb.nslices <= 0) return hipErrorInvalidValue;
+  const dim3 grid(nt, cb.nslices);
+  const int tx = (g.nx + CTX - 1) / CTX;
+  if (cb.cstart == 3)
+    hipLaunchKernelGGL(k_cg_start_tiled<3>, grid, dim3(CT_THREADS), 0, s, g, cb, tx);
+  else if (cb.cstart == 4)
+    hipLaunchKernelGGL(k_cg_start_tiled<4>, grid, dim3(CT_THREADS), 0, s, g, cb, tx);
+  else
+    hipLaunchKernelGGL(k_cg_start_tiled<5>, grid, dim3(CT_THREADS), 0, s, g, cb, tx);
   return hipGetLastError();
 }
 

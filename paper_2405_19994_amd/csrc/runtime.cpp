@@ -509,6 +509,9 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
 // workloads) for one stencil launch without inner products, cheaper than a CG
 // iteration.
 constexpr int kChebStartDegree = 3;
+// On 2D meshes with uniform coefficients the whole start is one tiled launch,
+// where a step costs far less than a launch: more steps, fewer CG iterations.
+constexpr int kChebStartDegreeTiled = 5;
 
 template <class T>
 CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i) {
@@ -533,6 +536,7 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
   cb.nslices = ns;
   cb.nblk = L.cg_nblk;
   cb.nblk0 = node_blocks(L.g);  // r_0 and its partials come from the node update
+  cb.nblk_s = cb.nblk0;
   cb.a = L.co.dt * L.co.d[i - 1];
   const double rt = level_rtol(c, lev);
   cb.tol2 = rt * rt;
@@ -663,12 +667,21 @@ void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pre
       return;
     }
     if (cb.cstart) {
-      // x_2 .. x_D (x_k, x_{k-1}, b read, x_{k+1} written); r_D and w_D (x_D and
-      // b read, r, w and for D odd x written)
-      PLAUNCH(c, PC_CGINIT, 32.0 * nodes * (cb.cstart - 1),
-              launch_cheb_steps(c->s, L.g, cb, cb.cstart - 1));
-      PLAUNCH(c, PC_CGINIT, (32.0 + 8.0 * (cb.cstart & 1)) * nodes,
-              launch_cg_start(c->s, L.g, cb));
+      const int tiles = cg_start_tiles(L.g, kChebStartDegreeTiled);
+      if (tiles > 0) {
+        // one launch: x_1, x_0, b read (with the tiles' halos), x_D to p, r_D, w_D
+        cb.cstart = kChebStartDegreeTiled;
+        cb.nblk_s = tiles;
+        cb.xin_p = 1;
+        PLAUNCH(c, PC_CGINIT, 48.0 * nodes, launch_cg_start_tiled(c->s, L.g, cb));
+      } else {
+        // x_2 .. x_D (x_k, x_{k-1}, b read, x_{k+1} written); r_D and w_D (x_D
+        // and b read, r, w and for D odd x written)
+        PLAUNCH(c, PC_CGINIT, 32.0 * nodes * (cb.cstart - 1),
+                launch_cheb_steps(c->s, L.g, cb, cb.cstart - 1));
+        PLAUNCH(c, PC_CGINIT, (32.0 + 8.0 * (cb.cstart & 1)) * nodes,
+                launch_cg_start(c->s, L.g, cb));
+      }
       k0 = 1;
     }
   }
