@@ -56,12 +56,23 @@ __device__ __forceinline__ R logistic(R x) { return R(1) / (R(1) + exp(x)); }
 
 // Steady state and rate 1/tau of every gate; calls sink(g, w_inf, 1/tau) for
 // g = 0..11 in state order (m, h, j, xr1, xr2, xs, r, s, d, f, f2, fCass).
+// Exponentials of V with slopes 1/20, 1/10, 1/5 (e^{V/20} and its square and
+// fourth power), 1/7 and -1/6 are formed once and scaled by constant factors
+// e^{b} (written out below as literals): e^{aV + b} = e^{b} e^{aV}, and
+// 1/(1 + e^{b} / E) = E / (E + e^{b}) needs no reciprocal of E.  An FP64
+// exponential costs about thirty instructions, a product one.
 template <class R, class Sink>
 __device__ __forceinline__ void gates(R V, R Ca_ss, Sink &&sink) {
-  {  // m
+  const R E20 = exp(V * R(0.05));  // e^{V/20}
+  const R E10 = E20 * E20;         // e^{V/10}
+  const R E5 = E10 * E10;          // e^{V/5}
+  const R E7 = exp(V * R(1.0 / 7.0));
+  const R E6m = exp(V * R(-1.0 / 6.0));
+  {  // m: alpha = 1/(1 + e^{(-60 - V)/5}), beta's first term 0.1/(1 + e^{(V + 35)/5})
     const R s = logistic((-R(56.86) - V) * R(1.0 / 9.03));
-    const R am = logistic((-R(60.0) - V) * R(0.2));
-    const R bm = R(0.1) * logistic((V + R(35.0)) * R(0.2)) + R(0.1) * logistic((V - R(50.0)) * R(0.005));
+    const R am = E5 / (E5 + R(6.14421235332821e-06));  // e^-12
+    const R bm = R(0.1) / (R(1.0) + R(1096.6331584284585) * E5) +  // e^7
+                 R(0.1) * logistic((V - R(50.0)) * R(0.005));
     sink(0, s * s, R(1.0) / (am * bm));
   }
   const R sh = logistic((V + R(71.55)) * R(1.0 / 7.43));
@@ -77,38 +88,48 @@ __device__ __forceinline__ void gates(R V, R Ca_ss, Sink &&sink) {
   } else {
     // beta_h = 0.77 / (0.13 (1 + e^{-(V + 10.66)/11.1})), alpha_h = 0
     sink(1, hj_inf, R(0.77 / 0.13) / (R(1.0) + exp((V + R(10.66)) * R(-1.0 / 11.1))));
-    sink(2, hj_inf, R(0.6) * exp(R(0.057) * V) / (R(1.0) + exp(-R(0.1) * (V + R(32.0)))));
+    // beta_j = 0.6 e^{0.057 V} / (1 + e^{-(V + 32)/10}), alpha_j = 0
+    sink(2, hj_inf, R(0.6) * exp(R(0.057) * V) * E10 / (E10 + R(0.04076220397836621)));  // e^-3.2
   }
-  sink(3, logistic((-R(26.0) - V) * R(1.0 / 7.0)),
-       R(1.0) / ((R(450.0) * logistic((-R(45.0) - V) * R(0.1))) * (R(6.0) * logistic((V + R(30.0)) * R(1.0 / 11.5)))));
+  // xr1: w_inf = 1/(1 + e^{(-26 - V)/7}); 1/tau = 1/(alpha beta) with alpha =
+  // 450/(1 + e^{(-45 - V)/10}), beta = 6/(1 + e^{(V + 30)/11.5})
+  sink(3, E7 / (E7 + R(0.0243728440732796)),  // e^{-26/7}
+       (E10 + R(0.011108996538242306)) *      // e^-4.5
+           (R(1.0) + exp((V + R(30.0)) * R(1.0 / 11.5))) / (R(2700.0) * E10));
+  // xr2: alpha = 3/(1 + e^{(-60 - V)/20}), beta = 1.12/(1 + e^{(V - 60)/20})
   sink(4, logistic((V + R(88.0)) * R(1.0 / 24.0)),
-       R(1.0) / ((R(3.0) * logistic((-R(60.0) - V) * R(0.05))) * (R(1.12) * logistic((V - R(60.0)) * R(0.05)))));
-  {  // xs
-    const R axs = R(1400.0) / sqrt(R(1.0) + exp((R(5.0) - V) * R(1.0 / 6.0)));
+       (E20 + R(0.049787068367863944)) * (R(1.0) + R(0.049787068367863944) * E20) /  // e^-3
+           (R(3.36) * E20));
+  {  // xs: alpha = 1400/sqrt(1 + e^{(5 - V)/6})
+    const R axs = R(1400.0) / sqrt(R(1.0) + R(2.300975890892825) * E6m);  // e^{5/6}
     const R bxs = logistic((V - R(35.0)) * R(1.0 / 15.0));
     sink(5, logistic((-R(5.0) - V) * R(1.0 / 14.0)), R(1.0) / (axs * bxs + R(80.0)));
   }
   {  // r, s (epicardium)
     const R v40 = V + R(40.0), v45 = V + R(45.0);
-    sink(6, logistic((R(20.0) - V) * R(1.0 / 6.0)),
+    sink(6, R(1.0) / (R(1.0) + R(28.03162489452614) * E6m),  // e^{20/6}
          R(1.0) / (R(9.5) * exp((v40 * v40) * R(-1.0 / 1800.0)) + R(0.8)));
-    sink(7, logistic((V + R(20.0)) * R(0.2)),
-         R(1.0) / (R(85.0) * exp((v45 * v45) * R(-1.0 / 320.0)) + R(5.0) * logistic((V - R(20.0)) * R(0.2)) + R(3.0)));
+    sink(7, R(1.0) / (R(1.0) + R(54.598150033144236) * E5),  // e^4
+         R(1.0) / (R(85.0) * exp((v45 * v45) * R(-1.0 / 320.0)) +
+                   R(5.0) / (R(1.0) + R(0.01831563888873418) * E5) + R(3.0)));  // e^-4
   }
-  {  // d
+  {  // d: beta = 1.4/(1 + e^{(V + 5)/5}), gamma = 1/(1 + e^{(50 - V)/20})
     const R ad = R(1.4) * logistic((-R(35.0) - V) * R(1.0 / 13.0)) + R(0.25);
-    const R bd = R(1.4) * logistic((V + R(5.0)) * R(0.2));
-    const R gd = logistic((R(50.0) - V) * R(0.05));
+    const R bd = R(1.4) / (R(1.0) + R(2.718281828459045) * E5);  // e^1
+    const R gd = E20 / (E20 + R(12.182493960703473));            // e^2.5
     sink(8, logistic((-R(8.0) - V) * R(1.0 / 7.5)), R(1.0) / (ad * bd + gd));
   }
-  {  // f, f2
+  {  // f, f2: terms 1/(1 + e^{(13 - V)/10}), 1/(1 + e^{(25 - V)/10}), 1/(1 + e^{(V + 30)/10})
     const R v27 = V + R(27.0), v25 = V + R(25.0);
-    sink(9, logistic((V + R(20.0)) * R(1.0 / 7.0)),
-         R(1.0) / (R(1102.5) * exp((v27 * v27) * R(-1.0 / 225.0)) + R(200.0) * logistic((R(13.0) - V) * R(0.1)) +
-                   R(180.0) * logistic((V + R(30.0)) * R(0.1)) + R(20.0)));
-    sink(10, R(0.67) * logistic((V + R(35.0)) * R(1.0 / 7.0)) + R(0.33),
-         R(1.0) / (R(600.0) * exp((v25 * v25) * R(-1.0 / 170.0)) + R(31.0) * logistic((R(25.0) - V) * R(0.1)) +
-                   R(16.0) * logistic((V + R(30.0)) * R(0.1))));
+    const R l30 = R(1.0) / (R(1.0) + R(20.085536923187668) * E10);  // e^3
+    sink(9, R(1.0) / (R(1.0) + R(17.41170806332765) * E7),         // e^{20/7}
+         R(1.0) / (R(1102.5) * exp((v27 * v27) * R(-1.0 / 225.0)) +
+                   R(200.0) * E10 / (E10 + R(3.6692966676192444)) +  // e^1.3
+                   R(180.0) * l30 + R(20.0)));
+    sink(10, R(0.67) / (R(1.0) + R(148.4131591025766) * E7) + R(0.33),  // e^5
+         R(1.0) / (R(600.0) * exp((v25 * v25) * R(-1.0 / 170.0)) +
+                   R(31.0) * E10 / (E10 + R(12.182493960703473)) +  // e^2.5
+                   R(16.0) * l30));
   }
   {  // fCass: w_inf = 0.6 / (1 + q) + 0.4, tau = 80 / (1 + q) + 2, q = (Ca_ss / 0.05)^2
     const R q = (Ca_ss * R(20.0)) * (Ca_ss * R(20.0));
@@ -134,28 +155,38 @@ __device__ __forceinline__ void currents(const R *y, R gs0, R gs1, R gs2, R &I_i
   const R I_Na = gs0 * R(kGNa) * (m * m * m) * h * jg * (V - E_Na);
   const R vek = V - E_K;
   const R a_k1 = R(0.1) / (R(1.0) + exp(R(0.06) * (vek - R(200.0))));
-  const R b_k1 = (R(3.0) * exp(R(0.0002) * (vek + R(100.0))) + exp(R(0.1) * (vek - R(10.0)))) /
-                      (R(1.0) + exp(-R(0.5) * vek));
+  // beta_K1 = (3 e^{0.0002 (vek + 100)} + e^{0.1 (vek - 10)}) / (1 + e^{-0.5 vek}),
+  // with e^{-0.5 vek} = 1 / EK^5, EK = e^{0.1 vek}
+  const R EK = exp(R(0.1) * vek);
+  const R EK2 = EK * EK;
+  const R EK5 = EK2 * EK2 * EK;
+  const R b_k1 = (R(3.0) * exp(R(0.0002) * (vek + R(100.0))) + R(0.36787944117144233) * EK) *  // e^-1
+                 EK5 / (EK5 + R(1.0));
   const R sq = R(1.0);  // sqrt(K_o / 5.4) with K_o = 5.4 mM
   const R I_K1 = R(kGK1) * sq * (a_k1 / (a_k1 + b_k1)) * vek;
   const R I_to = R(kGto) * r * s * vek;
   const R I_Kr = gs2 * R(kGKr) * sq * xr1 * xr2 * vek;
   const R I_Ks = R(kGKs) * xs * xs * (V - E_Ks);
+  // Ev = e^{V F/RT} serves three exponentials: e^u = Ev^2 e^{-30 F/RT} in
+  // I_CaL, e^{(gamma - 1) V F/RT} = e^{gamma V F/RT} / Ev in I_NaCa and
+  // e^{-V F/RT} = 1 / Ev in I_NaK (the quotients are cleared by multiplying
+  // numerator and denominator by Ev).
+  const R vfrt = V * R(1.0 / kRTF);
+  const R Ev = exp(vfrt);
   // L-type: (V - 15)/(e^u - 1) with u = 2 (V - 15)/RTF is (RTF/2) u/(e^u - 1),
   // written through expm1 so that u = 0 is regular.
   const R u = (V - R(15.0)) * R(2.0 / kRTF);
   const R inv_ratio = (u == R(0.0)) ? R(1.0) : u / expm1(u);
   const R I_CaL = gs1 * R(kGCaL) * d * f * f2 * fcass * R(4.0) * R(kF) * (R(0.5) * inv_ratio) *
-                       (R(0.25) * Ca_ss * exp(u) - R(kCao));
-  const R vfrt = V * R(1.0 / kRTF);
-  const R e_g = exp(R(kGammaNaCa) * vfrt), e_g1 = exp((R(kGammaNaCa) - R(1.0)) * vfrt);
+                       (R(0.25) * Ca_ss * (Ev * Ev) * R(0.3252969814969026) - R(kCao));  // e^{-30/RTF}
+  const R e_g = exp(R(kGammaNaCa) * vfrt);
   const R nai3 = Na_i * Na_i * Na_i;
   const R I_NaCa =
-      (e_g * nai3 * R(kCao) - e_g1 * (R(kNao) * R(kNao) * R(kNao)) * Ca_i * R(kAlphaNaCa)) *
+      (e_g * nai3 * R(kCao) * Ev - e_g * (R(kNao) * R(kNao) * R(kNao)) * Ca_i * R(kAlphaNaCa)) *
       R(kNaCa / ((kKmNai * kKmNai * kKmNai + kNao * kNao * kNao) * (kKmCa + kCao))) /
-      (R(1.0) + R(kKsat) * e_g1);
-  const R I_NaK = R(kPNaK * kKo / (kKo + kKmK)) * Na_i /
-                  ((Na_i + R(kKmNa)) * (R(1.0) + R(0.1245) * exp(-R(0.1) * vfrt) + R(0.0353) * exp(-vfrt)));
+      (Ev + R(kKsat) * e_g);
+  const R I_NaK = R(kPNaK * kKo / (kKo + kKmK)) * Na_i * Ev /
+                  ((Na_i + R(kKmNa)) * (Ev * (R(1.0) + R(0.1245) * exp(-R(0.1) * vfrt)) + R(0.0353)));
   const R I_pCa = R(kGpCa) * Ca_i / (R(kKpCa) + Ca_i);
   const R I_pK = R(kGpK) * vek / (R(1.0) + exp((R(25.0) - V) * R(1.0 / 5.98)));
   const R I_bNa = R(kGbNa) * (V - E_Na);

@@ -238,7 +238,8 @@ def test_sweep_and_residual_parity():
 # ---------------------------------------------------------------------------
 
 def _pfasst_case(dims, Mf, Mc, coarsen, P, dt, seed_state=False, solver="cg"):
-    w = dict(si.workload("slab3d" if len(dims) == 3 else "cable1d", dims=dims))
+    kind = {1: "cable1d", 2: "slab2d", 3: "slab3d"}[len(dims)]
+    w = dict(si.workload(kind, dims=dims))
     w["dt"] = dt
     if len(dims) == 1:
         w["stim_w"] = si.corner_weights(dims, (2,))
@@ -251,11 +252,13 @@ def _pfasst_case(dims, Mf, Mc, coarsen, P, dt, seed_state=False, solver="cg"):
 
 @pytest.mark.parametrize("dims,coarsen,solver", [((8, 6, 4), 2, "cg"), ((16,), 1, "cg"),
                                                 ((8, 6, 4), 2, "chebyshev"),
-                                                ((8, 6, 4), 2, "cg_plain")])
+                                                ((8, 6, 4), 2, "cg_plain"),
+                                                ((36, 18), 2, "cg")])
 def test_pfasst_iterates_parity(dims, coarsen, solver):
     """Every iterate of Algorithm 1 (burn-in, tau, Q^seq coarse sweep, coarse
     grid correction, Q^par fine sweep) matches the oracle, slice by slice (with
-    either diffusion solver on both levels)."""
+    every diffusion solver on both levels; the 2D case runs the tiled CG start
+    over several slices, with tiles cut by the mesh edge)."""
     P = 4
     w, h, y0, m = _pfasst_case(dims, 6 if coarsen == 2 else 4, 3 if coarsen == 2 else 2,
                                 coarsen, P, 0.1, solver=solver)
