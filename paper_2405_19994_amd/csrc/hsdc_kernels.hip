@@ -22,20 +22,30 @@ __device__ __forceinline__ void stream_store(V *dst, V v) {
 // phi functions (Appendix A, eq. def_phik)
 // ---------------------------------------------------------------------------
 
+// Polynomial sum_{m=0..N} c_m x^m as a sum of powers, each coefficient after
+// c_0 a multiplier: an FP64 constant cannot be an immediate operand, and
+// Horner's form, which adds the constants, spends two VALU moves per term on
+// them, while a multiplying constant is held in scalar registers.  The terms
+// decrease in size here, so the rounding stays at a few ulp.
+template <int N, class C>
+__device__ __forceinline__ double power_sum(double x, C &&c) {
+  double acc = c(0), xp = x;
+#pragma unroll
+  for (int m = 1; m <= N; ++m) {
+    acc = fma(c(m), xp, acc);
+    if (m < N) xp *= x;
+  }
+  return acc;
+}
+
 // phi_1(x) = (e^x - 1)/x.  For |x| < 1/8 the Taylor series sum_{m<=9} x^m/(m+1)!
 // (truncation below 2e-17 relative) replaces expm1 and the division.
 __device__ __forceinline__ double phi1(double x) {
   if (fabs(x) < 0.125) {
-    double t = 1.0 / 3628800.0;  // 1/10!
-    t = fma(t, x, 1.0 / 362880.0);
-    t = fma(t, x, 1.0 / 40320.0);
-    t = fma(t, x, 1.0 / 5040.0);
-    t = fma(t, x, 1.0 / 720.0);
-    t = fma(t, x, 1.0 / 120.0);
-    t = fma(t, x, 1.0 / 24.0);
-    t = fma(t, x, 1.0 / 6.0);
-    t = fma(t, x, 0.5);
-    return fma(t, x, 1.0);
+    constexpr double c[10] = {1.0,           1.0 / 2.0,      1.0 / 6.0,      1.0 / 24.0,
+                              1.0 / 120.0,   1.0 / 720.0,    1.0 / 5040.0,   1.0 / 40320.0,
+                              1.0 / 362880.0, 1.0 / 3628800.0};
+    return power_sum<9>(x, [&](int m) { return c[m]; });
   }
   return expm1(x) / x;
 }
@@ -62,8 +72,8 @@ struct PhiSeries {
 //     relative error by about (k+1)/|x| per step where k + 1 > |x|, at most
 //     prod_{k >= F} (k+1)/F over the whole range (4.4 for M = 6, 6.6 for M = 8).
 //   otherwise: phi_M from its Taylor series with N = 18 + M terms (below 1e-18
-//     relative for |x| < M/2), in Horner form with compile-time coefficients,
-//     then the backward recurrence.
+//     relative for |x| < M/2), as a sum of powers with compile-time
+//     coefficients (power_sum), then the backward recurrence.
 // Relative error below 6e-15 for M <= 8 over x in [-4000, 12] (checked against a
 // 60-digit evaluation).
 template <int M>
@@ -89,9 +99,7 @@ __device__ __forceinline__ void phis(double x, const double *invfact, double *ou
   } else {
     constexpr int N = 18 + M;
     constexpr PhiSeries<M, N> S{};
-    acc = S.c[N];
-#pragma unroll
-    for (int m = N - 1; m >= 0; --m) acc = fma(acc, x, S.c[m]);
+    acc = power_sum<N>(x, [&](int m) { return S.c[m]; });
   }
   out[M - 1] = acc;
 #pragma unroll
