@@ -622,6 +622,7 @@ def main():
         "gpu_event_ms": gpu_ms,
         "cg_iters_per_solve": st["cg_iters"] / max(1, st["cg_solves"]),
         "cg_unconverged": st["cg_unconverged"],
+        "cg_redo_steps": st["cg_redo_steps"],
         "V_max_end_mV": Vmax,
         "roofline": roofline,
         "roofline_valu": _valu("node_update", kernels.get("node_update", {}).get("avg_us")),
