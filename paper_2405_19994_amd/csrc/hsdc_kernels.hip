@@ -1723,6 +1723,13 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *Dc, int64_t sYc, int 
       }
     }
   }
+  // the fine values first: every load of the thread is issued before its first
+  // store (a store would order the later loads behind it)
+  double yv[MAXM + 1];
+  double *yf0 = Yf + n * sYf + (int64_t)f * gf.Np + p;
+#pragma unroll
+  for (int i = 0; i <= MAXM; ++i)
+    yv[i] = (i >= i0 && i <= Mf) ? yf0[(int64_t)i * NF * gf.Np] : 0.0;
   double dc[MAXM + 1];
 #pragma unroll
   for (int j = 0; j <= MAXM; ++j) {
@@ -1758,9 +1765,8 @@ k_prolong_correct(Grid gf, Grid gc, int scf, const double *Dc, int64_t sYc, int 
 #pragma unroll
       for (int j = 0; j <= MAXM; ++j)
         if (j <= Mc) s += Tt[i * (Mc + 1) + j] * dc[j];
-      double *yf = Yf + n * sYf + ((int64_t)i * NF + f) * gf.Np + p;
       // streaming store: the fine stages are read next by a later kernel
-      stream_store<double>(yf, *yf + s);
+      stream_store<double>(yf0 + (int64_t)i * NF * gf.Np, yv[i] + s);
     }
   }
 }
