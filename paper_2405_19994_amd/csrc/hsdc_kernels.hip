@@ -1778,12 +1778,132 @@ __global__ void __launch_bounds__(BLOCK) k_sub_from(double *d, const double *y, 
   if (i < n) d[i] = y[i] - d[i];
 }
 
+// The same correction for a mesh coarsened 2x, by tiles: a block takes a tile
+// of TX x TY x TZ fine nodes of one field and slice, stages the coarse values
+// its taps read (the tile's coarse cells and one more on each side, clamped at
+// the mesh edge as the taps are) in LDS, and forms each fine node's taps from
+// there, in the order and arithmetic of k_prolong_correct.  Every coarse value
+// is read from memory about once per tile instead of once per tap.  An axis
+// of the mesh with more than one node needs a tile extent above one.
+template <int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TX * TY * TZ)
+k_prolong_tiled(Grid gf, Grid gc, const double *Dc, int64_t sYc, int Mc, const double *Tt, int Mf,
+                int i0, double *Yf, int64_t sYf) {
+  constexpr int CW = TX > 1 ? TX / 2 + 2 : 1, CH = TY > 1 ? TY / 2 + 2 : 1,
+                CD = TZ > 1 ? TZ / 2 + 2 : 1;
+  __shared__ double lc[MAXM + 1][CD][CH][CW];
+  const int n = blockIdx.z;
+  const int f = blockIdx.y;
+  const int ntx = (gf.nx + TX - 1) / TX, nty = (gf.ny + TY - 1) / TY;
+  const int t = blockIdx.x;
+  const int fx0 = (t % ntx) * TX, fy0 = ((t / ntx) % nty) * TY, fz0 = (t / (ntx * nty)) * TZ;
+  // coarse origin of the staged block (one cell before the tile's first)
+  const int cx0 = TX > 1 ? (fx0 >> 1) - 1 : 0, cy0 = TY > 1 ? (fy0 >> 1) - 1 : 0,
+            cz0 = TZ > 1 ? (fz0 >> 1) - 1 : 0;
+  const int tid = threadIdx.x;
+  const int fx = fx0 + tid % TX, fy = fy0 + (tid / TX) % TY, fz = fz0 + tid / (TX * TY);
+  const bool in = fx < gf.nx && fy < gf.ny && fz < gf.nz;
+  const int64_t p = fx + (int64_t)gf.nx * (fy + (int64_t)gf.ny * fz);
+  // the fine values first, in flight while the coarse block is staged
+  double yv[MAXM + 1];
+  double *yf0 = Yf + n * sYf + (int64_t)f * gf.Np + p;
+#pragma unroll
+  for (int i = 0; i <= MAXM; ++i)
+    yv[i] = (in && i >= i0 && i <= Mf) ? yf0[(int64_t)i * NF * gf.Np] : 0.0;
+  const int per = CD * CH * CW;
+  for (int q = tid; q < (Mc + 1) * per; q += TX * TY * TZ) {
+    const int j = q / per, r = q % per;
+    const int a = r % CW, b = (r / CW) % CH, c = r / (CW * CH);
+    const int gx = min(max(cx0 + a, 0), gc.nx - 1), gy = min(max(cy0 + b, 0), gc.ny - 1),
+              gz = min(max(cz0 + c, 0), gc.nz - 1);
+    lc[j][c][b][a] = Dc[n * sYc + ((int64_t)j * NF + f) * gc.Np + gx +
+                        (int64_t)gc.nx * (gy + (int64_t)gc.ny * gz)];
+  }
+  __syncthreads();
+  if (!in) return;
+  // per axis: the cell I and its neighbour J (clamped), as block-local indices
+  int aI[3], aJ[3];
+  double w0[3], w1[3];
+  {
+    const int fi[3] = {fx, fy, fz}, nf_[3] = {gf.nx, gf.ny, gf.nz}, nc_[3] = {gc.nx, gc.ny, gc.nz};
+    const int c0[3] = {cx0, cy0, cz0};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (nf_[ax] > 1) {
+        const int I = fi[ax] >> 1;
+        int J = (fi[ax] & 1) ? I + 1 : I - 1;
+        J = J < 0 ? 0 : (J > nc_[ax] - 1 ? nc_[ax] - 1 : J);
+        aI[ax] = I - c0[ax];
+        aJ[ax] = J - c0[ax];
+        w0[ax] = 0.75;
+        w1[ax] = 0.25;
+      } else {
+        aI[ax] = aJ[ax] = 0;
+        w0[ax] = 1.0;
+        w1[ax] = 0.0;
+      }
+    }
+  }
+  double dc[MAXM + 1];
+#pragma unroll
+  for (int j = 0; j <= MAXM; ++j) {
+    double sum = 0.0;
+    if (j <= Mc) {
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        const double wz = cz ? w1[2] : w0[2];
+        if (wz == 0.0) continue;
+        const int oz = cz ? aJ[2] : aI[2];
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy) {
+          const double wy = cy ? w1[1] : w0[1];
+          if (wy == 0.0) continue;
+          const int oy = cy ? aJ[1] : aI[1];
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx) {
+            const double wx = cx ? w1[0] : w0[0];
+            if (wx == 0.0) continue;
+            sum += (wx * wy * wz) * lc[j][oz][oy][cx ? aJ[0] : aI[0]];
+          }
+        }
+      }
+    }
+    dc[j] = sum;
+  }
+#pragma unroll
+  for (int i = 0; i <= MAXM; ++i) {
+    if (i >= i0 && i <= Mf) {
+      double sum = 0.0;
+#pragma unroll
+      for (int j = 0; j <= MAXM; ++j)
+        if (j <= Mc) sum += Tt[i * (Mc + 1) + j] * dc[j];
+      stream_store<double>(yf0 + (int64_t)i * NF * gf.Np, yv[i] + sum);
+    }
+  }
+}
+
 hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,
                                   const double *Yc, double *Sz, int64_t sYc, int Mc,
                                   const double *Tt, int Mf, int i0, double *Yf, int64_t sYf,
                                   int nslices) {
   const int64_t nc = (int64_t)nslices * sYc;
   hipLaunchKernelGGL(k_sub_from, dim3(nblocks(nc)), dim3(BLOCK), 0, s, Sz, Yc, nc);
+  if (sc_factor == 2 && gf.rag == nullptr) {
+    if (gf.nz > 1) {
+      const unsigned nt = ((gf.nx + 31) / 32) * ((gf.ny + 3) / 4) * ((gf.nz + 1) / 2);
+      hipLaunchKernelGGL((k_prolong_tiled<32, 4, 2>), dim3(nt, NF, nslices), dim3(256), 0, s, gf,
+                         gc, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);
+    } else if (gf.ny > 1) {
+      const unsigned nt = ((gf.nx + 31) / 32) * ((gf.ny + 7) / 8);
+      hipLaunchKernelGGL((k_prolong_tiled<32, 8, 1>), dim3(nt, NF, nslices), dim3(256), 0, s, gf,
+                         gc, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);
+    } else {
+      const unsigned nt = (gf.nx + 255) / 256;
+      hipLaunchKernelGGL((k_prolong_tiled<256, 1, 1>), dim3(nt, NF, nslices), dim3(256), 0, s, gf,
+                         gc, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);
+    }
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_prolong_correct, dim3(nblocks_xcd(gf.N), NF, nslices), dim3(BLOCK), 0, s,
                      gf, gc, sc_factor, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);
   return hipGetLastError();
