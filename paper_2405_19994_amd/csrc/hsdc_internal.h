@@ -205,11 +205,14 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // CG start from x_D (cstart = D): r_D, w_D, the partials of (r_D, r_D) and
 // (w_D, r_D), the parity-1 scalars, and x_D in x.
 hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb);
-// The whole CG start of degree 3 in one launch on 2D meshes with uniform
-// coefficients (x_2, x_3, r_3, w_3 in LDS tiles with a halo of 4); x_3 goes to
-// p.  cg_start_tiles(g) = its block count per slice (0: not applicable).
+// The whole CG start of degree D = cb.cstart (3..5) in one launch on 2D meshes
+// (x_2 .. x_D, r_D, w_D in LDS tiles of 32 x 16 nodes with a halo of D + 1);
+// x_D goes to p.  cg_start_tiles(g, D) = its tiles per slice on a mesh that is
+// not a ragged batch (0: not applicable); ntiles = the launch's tiles per
+// slice (a ragged batch: the most of any tissue, cg_start_tiles_of).
 int cg_start_tiles(const Grid &g, int degree);
-hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb);
+int cg_start_tiles_of(int nx, int ny);
+hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb, int ntiles);
 
 // transfers (space coarsening 2x or identity) between a fine and a coarse level
 hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,

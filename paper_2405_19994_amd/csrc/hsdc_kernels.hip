@@ -1446,32 +1446,50 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
   return hipGetLastError();
 }
 
-// The CG start of degree D in one launch (2D, uniform coefficients, one mesh
-// for every slice): a block holds a 32 x 16 tile of nodes with a halo of D + 1
-// in LDS and runs the Chebyshev steps x_2 .. x_D there (x_k on the tile's
-// radius D + 1 - k), then r_D = b - A x_D (radius 1) and w_D = A r_D (tile),
-// from x_1 (xt), x_0 (x) and b, in the arithmetic of the Chebyshev and start
-// kernels (a neighbour missing at the boundary reads the node itself, so its
-// term is exactly 0).  x_{k+1} overwrites x_{k-1} cell by cell, so two LDS
-// vectors and b suffice.  x_D goes to p, not x: other tiles still read x_0
-// from x.  Partials of (r_D, r_D) and (w_D, r_D) per tile.
+// The CG start of degree D in one launch on 2D meshes: a block holds a 32 x 16
+// tile of nodes with a halo of D + 1 in LDS and runs the Chebyshev steps x_2
+// .. x_D there (x_k on the tile's radius D + 1 - k), then r_D = b - A x_D
+// (radius 1) and w_D = A r_D (tile), from x_1 (xt), x_0 (x) and b, in the
+// arithmetic of the Chebyshev and start kernels (a neighbour missing at the
+// boundary reads the node itself, so its term is exactly 0; with per-node
+// sigma the face coefficients come along in LDS and a missing face adds 0).
+// x_{k+1} overwrites x_{k-1} cell by cell, so two LDS vectors and b suffice.
+// x_D goes to p, not x: other tiles still read x_0 from x.  Partials of (r_D,
+// r_D) and (w_D, r_D) per tile, numbered within each tissue (tile t at (t %
+// tiles_x, t / tiles_x) of the tissue's own tiles_x), so that a tissue of a
+// ragged batch and its own context reduce the same partials in the same order;
+// blocks past a smaller tissue's tiles write zeros.
 constexpr int CTX = 32, CTY = 16, CT_THREADS = 256;
 
+int cg_start_tiles_of(int nx, int ny) { return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY); }
+
 int cg_start_tiles(const Grid &g, int degree) {
-  if (degree < 3 || degree > 5 || g.dim != 2 || g.kx != nullptr || g.rag != nullptr) return 0;
-  return ((g.nx + CTX - 1) / CTX) * ((g.ny + CTY - 1) / CTY);
+  if (degree < 3 || degree > 5 || g.dim != 2 || g.rag != nullptr) return 0;
+  return cg_start_tiles_of(g.nx, g.ny);
 }
 
-template <int D>
-__global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g, CgBatch cb, int tiles_x) {
+template <int D, bool PN>
+__global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch cb) {
   constexpr int H = D + 1, W = CTX + 2 * H, HH = CTY + 2 * H;
+  constexpr int WK = PN ? W : 1, HK = PN ? HH : 1;
   __shared__ double sa[HH][W], sk[HH][W], sb[HH][W];
+  __shared__ double skx[HK][WK], sky[HK][WK];
   __shared__ double lds[2 * (CT_THREADS / 64)];
   const int n = blockIdx.y;
-  const int nt = gridDim.x;
-  const int t = (nt % kXcds == 0) ? (int)xcd_node_block(blockIdx.x, nt) : (int)blockIdx.x;
-  const int X0 = (t % tiles_x) * CTX - H, Y0 = (t / tiles_x) * CTY - H;
+  const Grid g = slice_grid(g0, cb.slice0 + n);
   const int nx = g.nx, ny = g.ny;
+  const int tiles_x = (nx + CTX - 1) / CTX;
+  const int t = (int)blockIdx.x;
+  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+  if (t >= tiles_x * ((ny + CTY - 1) / CTY)) {
+    // past this tissue's tiles (a smaller tissue of a ragged batch)
+    if (threadIdx.x == 0) {
+      part[2 * cb.pstride + t] = 0.0;
+      part[3 * cb.pstride + t] = 0.0;
+    }
+    return;
+  }
+  const int X0 = (t % tiles_x) * CTX - H, Y0 = (t / tiles_x) * CTY - H;
   const double *x1g = cb.xt + (int64_t)n * g.Np;
   const double *x0g = cb.x + n * cb.sx;
   const double *bg = cb.b + n * cb.sb;
@@ -1481,22 +1499,38 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g, CgBatch c
   double (*xm)[W] = sa, (*xk)[W] = sk;
   for (int q = threadIdx.x; q < W * HH; q += CT_THREADS) {
     const int u = q % W, v = q / W, gx = X0 + u, gy = Y0 + v;
-    double v1 = 0.0, v0 = 0.0, vb = 0.0;
+    double v1 = 0.0, v0 = 0.0, vb = 0.0, fx = 0.0, fy = 0.0;
     if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
       const int64_t p = gx + (int64_t)nx * gy;
       v1 = x1g[p];
       v0 = x0g[p];
       vb = bg[p];
+      if (PN) {
+        fx = g.kx[p];
+        fy = g.ky[p];
+      }
     }
     sk[v][u] = v1;
     sa[v][u] = v0;
     sb[v][u] = vb;
+    if (PN) {
+      skx[v % HK][u % WK] = fx;
+      sky[v % HK][u % WK] = fy;
+    }
   }
   __syncthreads();
-  // K S at cell (u, v), grouped per axis as applyK
+  // K S at cell (u, v), in applyK's order
   auto Kat = [&](double (*S)[W], int u, int v) {
     const int gx = X0 + u, gy = Y0 + v;
     const double c = S[v][u];
+    if (PN) {
+      double acc = 0.0;
+      if (gx > 0) acc += skx[v % HK][(u - 1) % WK] * (S[v][u - 1] - c);
+      if (gx < nx - 1) acc += skx[v % HK][u % WK] * (S[v][u + 1] - c);
+      if (gy > 0) acc += sky[(v - 1) % HK][u % WK] * (S[v - 1][u] - c);
+      if (gy < ny - 1) acc += sky[v % HK][u % WK] * (S[v + 1][u] - c);
+      return acc;
+    }
     const double l = gx > 0 ? S[v][u - 1] : c, r = gx < nx - 1 ? S[v][u + 1] : c;
     const double d = gy > 0 ? S[v - 1][u] : c, up = gy < ny - 1 ? S[v + 1][u] : c;
     double acc = g.cx * ((l - c) + (r - c));
@@ -1550,7 +1584,6 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g, CgBatch c
     gam += rc * rc;
     del += wv * rc;
   }
-  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
   double t2[2] = {gam, del};
   block_sums<2, CT_THREADS>(t2, lds);
   if (threadIdx.x == 0) {
@@ -1568,17 +1601,24 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g, CgBatch c
   }
 }
 
-hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb) {
-  const int nt = cg_start_tiles(g, cb.cstart);
-  if (nt <= 0 || cb.nslices <= 0) return hipErrorInvalidValue;
-  const dim3 grid(nt, cb.nslices);
-  const int tx = (g.nx + CTX - 1) / CTX;
+hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb, int ntiles) {
+  if (ntiles <= 0 || cb.nslices <= 0 || g.dim != 2) return hipErrorInvalidValue;
+  const dim3 grid(ntiles, cb.nslices);
+  const bool pn = g.kx != nullptr;
+#define HSDC_CT_LAUNCH(D_)                                                                   \
+  do {                                                                                       \
+    if (pn)                                                                                  \
+      hipLaunchKernelGGL((k_cg_start_tiled<D_, true>), grid, dim3(CT_THREADS), 0, s, g, cb); \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_cg_start_tiled<D_, false>), grid, dim3(CT_THREADS), 0, s, g, cb); \
+  } while (0)
   if (cb.cstart == 3)
-    hipLaunchKernelGGL(k_cg_start_tiled<3>, grid, dim3(CT_THREADS), 0, s, g, cb, tx);
+    HSDC_CT_LAUNCH(3);
   else if (cb.cstart == 4)
-    hipLaunchKernelGGL(k_cg_start_tiled<4>, grid, dim3(CT_THREADS), 0, s, g, cb, tx);
+    HSDC_CT_LAUNCH(4);
   else
-    hipLaunchKernelGGL(k_cg_start_tiled<5>, grid, dim3(CT_THREADS), 0, s, g, cb, tx);
+    HSDC_CT_LAUNCH(5);
+#undef HSDC_CT_LAUNCH
   return hipGetLastError();
 }
 

@@ -136,6 +136,7 @@ struct hsdc_ctx {
   bool batch = false;
   std::vector<int64_t> tissue_N;  // nodes per slice (batch)
   int32_t *rag = nullptr;         // device [P][3] tissue dimensions
+  int batch_start_tiles = 0;      // most CG-start tiles of any tissue (2D batch)
   int nlev = 1;
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
   double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices
@@ -667,13 +668,15 @@ void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pre
       return;
     }
     if (cb.cstart) {
-      const int tiles = cg_start_tiles(L.g, kChebStartDegreeTiled);
-      if (tiles > 0) {
+      // tiles per slice: the mesh's, or for a ragged 2D batch the most of any tissue
+      const int tiles = L.g.rag ? (L.g.dim == 2 ? c->batch_start_tiles : 0)
+                                : cg_start_tiles(L.g, kChebStartDegreeTiled);
+      if (tiles > 0 && tiles <= L.cg_pstride) {
         // one launch: x_1, x_0, b read (with the tiles' halos), x_D to p, r_D, w_D
         cb.cstart = kChebStartDegreeTiled;
         cb.nblk_s = tiles;
         cb.xin_p = 1;
-        PLAUNCH(c, PC_CGINIT, 48.0 * nodes, launch_cg_start_tiled(c->s, L.g, cb));
+        PLAUNCH(c, PC_CGINIT, 48.0 * nodes, launch_cg_start_tiled(c->s, L.g, cb, tiles));
       } else {
         // x_2 .. x_D (x_k, x_{k-1}, b read, x_{k+1} written); r_D and w_D (x_D
         // and b read, r, w and for D odd x written)
@@ -1261,6 +1264,9 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
     HIPC(hipMemcpyAsync(c->rag, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                         c->s));
     F.g.rag = c->rag;
+    for (int n = 0; n < count; ++n)
+      c->batch_start_tiles =
+          std::max(c->batch_start_tiles, cg_start_tiles_of(probs[n].nx, probs[n].ny));
     // per-tissue spectral bounds (each tissue gets the bound of its own context)
     std::vector<double> lam(count);
     for (int n = 0; n < count; ++n)
