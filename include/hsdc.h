@@ -92,8 +92,8 @@ typedef struct {
                              /* gradients started from a Chebyshev iterate over   */
                              /* the Gershgorin interval of I - a K (steps from    */
                              /* the warm start without inner products, the first  */
-                             /* inside the node update: degree 5 on 2D meshes     */
-                             /* with uniform sigma, in one tiled launch, else 3); */
+                             /* inside the node update: degree 5 on 2D meshes,    */
+                             /* in one tiled launch, else 3);                     */
                              /* 1 Chebyshev iteration over that                   */
                              /* interval (no inner products: the iteration count  */
                              /* comes from the residual bound of the Chebyshev    */

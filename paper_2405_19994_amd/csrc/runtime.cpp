@@ -510,8 +510,8 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
 // workloads) for one stencil launch without inner products, cheaper than a CG
 // iteration.
 constexpr int kChebStartDegree = 3;
-// On 2D meshes with uniform coefficients the whole start is one tiled launch,
-// where a step costs far less than a launch: more steps, fewer CG iterations.
+// On 2D meshes the whole start is one tiled launch, where a step costs far less
+// than a launch: more steps, fewer CG iterations.
 constexpr int kChebStartDegreeTiled = 5;
 
 template <class T>
