@@ -474,7 +474,11 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   }
   L.cg_p = dalloc<T>(c, (size_t)P * Np);
   // partials sized for the largest block cap hsdc_tune accepts
+  // (and the tiles of the CG start on a 2D mesh, or of any tissue of a batch)
   L.cg_pstride = std::max(cg_blocks(L.g, 2 * BLOCK), node_blocks(L.g));
+  if (L.g.dim == 2)
+    L.cg_pstride = std::max<int64_t>(
+        L.cg_pstride, std::max(cg_start_tiles_of(L.g.nx, L.g.ny), c->batch_start_tiles));
   L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
@@ -1258,15 +1262,15 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
     F.g = make_grid(p0, probs[big].nx, probs[big].ny, probs[big].nz, p0.dx);
     if (!make_colloc(meth->M[0], meth->dt, F.co))
       return fail(c, HSDC_EINVAL, "Radau node computation failed");
+    for (int n = 0; n < count; ++n)
+      c->batch_start_tiles =
+          std::max(c->batch_start_tiles, cg_start_tiles_of(probs[n].nx, probs[n].ny));
     alloc_level(c, F, meth->M[0], count, false, 0);
     const int64_t Np = F.g.Np;
     c->rag = dalloc<int32_t>(c, dims.size());
     HIPC(hipMemcpyAsync(c->rag, dims.data(), dims.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                         c->s));
     F.g.rag = c->rag;
-    for (int n = 0; n < count; ++n)
-      c->batch_start_tiles =
-          std::max(c->batch_start_tiles, cg_start_tiles_of(probs[n].nx, probs[n].ny));
     // per-tissue spectral bounds (each tissue gets the bound of its own context)
     std::vector<double> lam(count);
     for (int n = 0; n < count; ++n)
