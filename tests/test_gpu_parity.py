@@ -152,6 +152,14 @@ def test_slab2d_reduced_parity():
     _serial_parity(w, 30, 10, 6, 6)
 
 
+def test_narrow_slab_parity():
+    """A long, narrow 2D mesh (700 x 3): the tiled CG start has more tiles (22)
+    than the node update has blocks (16 with the XCD padding), so the CG
+    partial buffers must be sized for the tiles."""
+    w = si.workload("slab2d", dims=(700, 3))
+    _serial_parity(w, 12, 6, 4, 4)
+
+
 def test_pernode_sigma_parity():
     """Per-node lognormal conductivity (the batched-tissue workload's field)."""
     t = si.batch2d_tissues(1, seed=3, lo=20, hi=40)[0]
