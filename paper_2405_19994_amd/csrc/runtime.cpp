@@ -91,7 +91,8 @@ struct LevelT {
   double *RI = nullptr;   // fine: time-restricted integrals [P][Mc][NF][Np]; coarse: FAS term
   double *y0c = nullptr;  // coarse: restricted block start value [NF][Np]
   int cg_pred[16][MAXM];  // iteration budget per (sweep index, node)
-  int cg_umax[16][MAXM];  // most iterations used since the last relaxation (graph mode)
+  int cg_umax[16][MAXM];  // most iterations used since the last relaxation (graph mode;
+                          // -1: no solve checked since)
 };
 using Level = LevelT<double>;
 
@@ -503,7 +504,7 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   for (auto &row : L.cg_pred)
     for (int &v : row) v = 8;
   for (auto &row : L.cg_umax)
-    for (int &v : row) v = 0;
+    for (int &v : row) v = -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -600,8 +601,9 @@ void flush_cg_log(hsdc_ctx *c) {
     int &pred = pred_table(c, e.lev)[e.row & 15][e.i - 1];
     if (!ok_all)
       pred = std::min(c->meth.cg_maxit + 1, std::max(2 * e.budget, used + 4));
-    else if (c->graph_on && e.lev == 0) {
-      // graph replay: raise at once, lower only at a relaxation (every 16 steps)
+    else if (c->graph_on && !c->prof.on && e.lev == 0) {
+      // graph replay (profiled steps run eagerly): raise at once, lower only at
+      // a relaxation (every 16 steps)
       pred = std::max(pred, used + c->tune_cg_margin);
       int &um = c->L[0].cg_umax[e.row & 15][e.i - 1];
       um = std::max(um, used);
@@ -1077,11 +1079,12 @@ void graph_step(hsdc_ctx *c) {
   c->graph_steps += 1;
   if (c->graph_steps % 16 == 0) {
     // relaxation: budgets down to the most iterations used since the last one
+    // (also to none: after a Chebyshev start most solves need no iteration)
     for (int r = 0; r < 16; ++r)
       for (int i = 0; i < MAXM; ++i)
-        if (F.cg_umax[r][i] > 0) {
+        if (F.cg_umax[r][i] >= 0) {
           F.cg_pred[r][i] = F.cg_umax[r][i] + c->tune_cg_margin;
-          F.cg_umax[r][i] = 0;
+          F.cg_umax[r][i] = -1;
         }
   }
   if (std::memcmp(pred0, F.cg_pred, sizeof(pred0)) != 0) c->graph_dirty = true;
