@@ -529,9 +529,10 @@ hipError_t launch_spread(hipStream_t s, const Grid &g, const Stages &st, const C
 // ---------------------------------------------------------------------------
 
 // Instantiated separately for the rows V .. Rbar (GATES = false: collocation
-// weights, memory streams only) and the gate rows (exponential coefficients),
-// whose phi work would take 130 VGPRs (three waves per SIMD); held to 128 (four
-// waves), the gate rows run in 20% less time.
+// weights, memory streams only) and the gate rows (exponential coefficients).
+// The gate rows form, complete and store one I_i at a time, so only the moments
+// stay live across the phi evaluations (46 VGPRs at M = 6, eight waves per
+// SIMD); with all I_i formed first they took 128 VGPRs and spilled.
 template <int M, class T, bool GATES>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int64_t sRI, int spread,
@@ -547,6 +548,50 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
   const double *FV = st.FV + n * st.sFV() + p;
   double *RH = st.RH + n * st.sRH() + f * Np + p;
   const double dt = co.dt;
+  if constexpr (GATES) {
+    // Gate rows: no K V term.  Each I_i is formed, completed and stored in
+    // turn, so only the moments stay live across the phi evaluations.
+    double Gv[M + 1];
+    if (spread) {
+#pragma unroll
+      for (int j = 0; j <= M; ++j) Gv[j] = G[0];
+    } else {
+#pragma unroll
+      for (int j = 0; j <= M; ++j) Gv[j] = G[j * st.sS()];
+    }
+    const double z = dt * st.L0[n * st.sL() + (f - GATE0) * Np + p];
+    double mom[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) s += co.W[k][j] * Gv[j + 1];
+      mom[k] = s;
+    }
+    double prevI = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      double Ii;
+      if (z == 0.0) {  // a(0) = Q
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) s += co.Q[i][j] * Gv[j + 1];
+        Ii = s;
+      } else {
+        double ph[M];
+        phis<M>(co.c[i] * z, co.invfact, ph);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < M; ++k) s += co.cpow[i][k + 1] * ph[k] * mom[k];
+        Ii = s;
+      }
+      if (RI) Ii += RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
+      stream_store<double>(&RH[(int64_t)i * st.sS()],
+                           dt * (Ii - prevI) - dt * co.d[i] * (0.0 + phi1(co.d[i] * z) * Gv[i]));
+      prevI = Ii;
+    }
+    return;
+  }
   double Gv[M + 1], fv[M + 1], gfull[M], I[M];
   if (spread) {
     const double g0 = G[0];
