@@ -206,7 +206,7 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // (w_D, r_D), the parity-1 scalars, and x_D in x.
 hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb);
 // The whole CG start of degree D = cb.cstart (3..5) in one launch on 2D meshes
-// (x_2 .. x_D, r_D, w_D in LDS tiles of 32 x 8 nodes with a halo of D + 1);
+// (x_2 .. x_D, r_D, w_D in LDS tiles of 64 x 16 nodes with a halo of D + 1);
 // x_D goes to p.  cg_start_tiles(g, D) = its tiles per slice on a mesh that is
 // not a ragged batch (0: not applicable); ntiles = the launch's tiles per
 // slice (a ragged batch: the most of any tissue, cg_start_tiles_of).

@@ -1491,7 +1491,7 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
   return hipGetLastError();
 }
 
-// The CG start of degree D in one launch on 2D meshes: a block holds a 32 x 8
+// The CG start of degree D in one launch on 2D meshes: a block holds a 64 x 16
 // tile of nodes with a halo of D + 1 in LDS and runs the Chebyshev steps x_2
 // .. x_D there (x_k on the tile's radius D + 1 - k), then r_D = b - A x_D
 // (radius 1) and w_D = A r_D (tile), from x_1 (xt), x_0 (x) and b, in the
@@ -1504,7 +1504,7 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // tiles_x, t / tiles_x) of the tissue's own tiles_x), so that a tissue of a
 // ragged batch and its own context reduce the same partials in the same order;
 // blocks past a smaller tissue's tiles write zeros.
-constexpr int CTX = 32, CTY = 8, CT_THREADS = 256;
+constexpr int CTX = 64, CTY = 16, CT_THREADS = 1024;
 
 int cg_start_tiles_of(int nx, int ny) { return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY); }
 
