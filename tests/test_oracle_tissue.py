@@ -126,3 +126,42 @@ def test_ttp06_conductance_scalings():
     assert np.allclose(sc["CaL"], 0.9 * base["CaL"], rtol=1e-14)
     assert np.allclose(sc["Kr"], 1.2 * base["Kr"], rtol=1e-14)
     assert np.allclose(sc["K1"], base["K1"], rtol=0)
+
+
+def test_ttp06_jacobian_spectral_radius_is_of_order_1000():
+    """Sec. 5 (model setup) gives the spectral radius of the Jacobian of the
+    ionic right-hand side f_E + f_e of the TTP06 model as about 1000 (1/ms) for
+    states away from equilibrium.  Along a stimulated single-cell action
+    potential (0..400 ms) the largest spectral radius of the central-difference
+    Jacobian of the oracle's 19-state right-hand side must be of that order
+    (within a factor 2); a rate constant of the fastest gate written wrong by a
+    factor of ten, or an ionic current with a wrong sign, fails this."""
+    from scipy.integrate import solve_ivp
+
+    from oracle.problems import Monodomain
+
+    p = Monodomain((1,), 0.01, stim_w=np.ones(1), stim_amp=50.0, stim_t0=0.0, stim_dur=1.0)
+
+    def rhs(t, y):
+        y = y.reshape(19, 1)
+        return (p.f_E(t, y) + p.lam(y) * (y - p.y_inf(y))).ravel()
+
+    sol = solve_ivp(rhs, (0.0, 400.0), ttp06.rest_state(), method="LSODA", rtol=1e-8,
+                    atol=1e-10, dense_output=True, max_step=0.5)
+    assert sol.y[0].max() > 20.0  # the stimulus triggered an action potential
+
+    def rho(y):
+        J = np.empty((19, 19))
+        for m in range(19):
+            h = 1e-6 * max(1.0, abs(y[m]))
+            e = np.zeros(19)
+            e[m] = h
+            J[:, m] = (rhs(5.0, y + e) - rhs(5.0, y - e)) / (2.0 * h)  # t = 5: no stimulus
+        return np.max(np.abs(np.linalg.eigvals(J)))
+
+    times = np.concatenate([np.linspace(0.25, 20.0, 40), np.linspace(25.0, 400.0, 76)])
+    rhos = np.array([rho(sol.sol(t)) for t in times])
+    Vs = np.array([sol.sol(t)[0] for t in times])
+    off_eq = Vs > -84.0  # away from the rest potential (-85.2 mV)
+    assert off_eq.sum() > 50
+    assert 500.0 < rhos[off_eq].max() < 2000.0
