@@ -113,6 +113,12 @@ typedef struct {
   double coarse_cg_rtol;     /* coarse diffusion solves; <= 0: cg_rtol (FP64      */
                              /* coarse level) or 1e-5 (FP32 coarse level, where   */
                              /* it is relative to the warm start's residual)      */
+  int32_t residual_norm;     /* relative residual of slice n (stop test, residual */
+                             /* calls): 0 ||r_n||_inf / ||y_n||_inf over all      */
+                             /* fields and nodes (Algorithm 1); 1 the largest     */
+                             /* per-field ratio ||r_{n,f}||_inf / ||y_{n,f}||_inf */
+                             /* (fields of very different magnitude: Ca_i is      */
+                             /* about 1e-4 mM beside K_i about 136 mM)            */
 } hsdc_method;
 
 /* Counters since init (host copy). */
@@ -187,7 +193,11 @@ hsdc_status hsdc_sdc_sweep(hsdc_ctx *ctx, int32_t level, int32_t slice, int32_t 
 /* Serial mode: nsteps times {max_iter sweeps; y_{n+1} = y_{n,M}; spread y_{n+1}}
  * (the step applies the sweeps the current step has not had yet).
  * PFASST mode: nsteps blocks, each iterated until converged or max_iter
- * (Algorithm 1), then the next block starts from y_{P-1,M}. */
+ * (Algorithm 1), then the next block starts from y_{P-1,M}.
+ * The status describes this call only: HSDC_ENONFINITE when a solve or the
+ * residual met a NaN or Inf (the state is not finite; stepping stops at the
+ * step where it was found), else HSDC_ENOCONV when a solve of this call
+ * reached cg_maxit (the state was still advanced). */
 hsdc_status hsdc_advance(hsdc_ctx *ctx, int32_t nsteps);
 
 /* One iteration of Algorithm 1 on the current block: FAS correction tau,
@@ -198,7 +208,11 @@ hsdc_status hsdc_pfasst_iter(hsdc_ctx *ctx, double *res_host, int32_t *all_conve
 
 /* Relative residual ||r_n||_inf / ||y_n||_inf of every slice of the fine level,
  * r_n = C(y_n) - 1 (x) y_{n-1,M} (rows of D(z) - b in Algorithm 1; y_{-1,M} is
- * the block start value).  level must be 0.  res_host: host [P]. */
+ * the block start value).  res_host: host [P].  level must be 0: Algorithm 1
+ * tests convergence on the fine level only, and the coarse level's equations
+ * carry the FAS correction tau of the current iteration (its iterate is an
+ * intermediate of one iteration, not a solution of C(y) = 1 (x) u).
+ * HSDC_ENONFINITE when a residual or state norm is NaN or Inf. */
 hsdc_status hsdc_residual(hsdc_ctx *ctx, int32_t level, double *res_host);
 
 /* Copy stage `node` (0..M) of `slice` of `level` to / from device [19][N_level]. */

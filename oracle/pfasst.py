@@ -109,10 +109,13 @@ def burn_in(h, y0, P, step0, b):
     return z[0]
 
 
-def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None):
+def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None, callback=None):
     """Algorithm 1: P steps from y0.  Returns (z_fine, residual history, k).
 
-    residual history: list over iterations of the P relative residuals."""
+    residual history: list over iterations of the P relative residuals.
+    callback(k, z_fine, z_coarsest), if given, sees every iterate k = 1, 2, ...
+    (z_coarsest: the coarsest level's iterate after its Q^seq sweep, or None
+    for one level)."""
     L = len(h.levels)
     b = block_rhs(h, y0, P)
     if z_init is not None:
@@ -125,6 +128,7 @@ def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None):
     k = 0
     converged = False
     while not converged and k < K:
+        zc = None
         if L == 1:
             z = h.solve_Q(0, step0, z, b[0], seq=True)
         else:
@@ -140,6 +144,7 @@ def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None):
                 extra = [b[l][n] + tau[l][n] for n in range(P)]
                 zh[l] = h.solve_Q(l, step0, Sz, extra, seq=(l == L - 1))
             znew = zh[L - 1]
+            zc = znew
             for l in range(L - 2, -1, -1):
                 corr = [h.U(l, znew[n] - h.S(l, zh[l][n])) for n in range(P)]
                 X = [zh[l][n] + corr[n] for n in range(P)]
@@ -153,6 +158,8 @@ def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None):
             rn = r[n] - b[0][n]
             rel.append(float(np.max(np.abs(rn)) / np.max(np.abs(z[n]))))
         hist.append(rel)
+        if callback is not None:
+            callback(k, z, zc)
         converged = tol > 0 and all(x < tol for x in rel)
     return z, hist, k
 

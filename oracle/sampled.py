@@ -62,3 +62,13 @@ def sweep_defect(full, M, dt, step, Yk, Ynew, yn, rows):
     Yo = Yk[:, :, rows]
     rhs = lev_old.P(step, Yo) - lev_old.C(step, Yo) + yn[None][:, :, rows]
     return lev_new.P(step, Yn) - rhs
+
+
+def collocation_defect(full, M, dt, step, Y, u, rows):
+    """C(Y) - 1 (x) u at the nodes `rows` (eq. def_C; row 0 is the start-value
+    jump Y_0 - u), for a whole stage vector Y of shape (M+1, nf, N) and start
+    value u of shape (nf, N).  Returns (M+1, nf, len(rows))."""
+    times = [(step + c) * dt for c in np.concatenate([[0.0], Level(full, M, dt).c])]
+    kv = [full.K[rows] @ Y[j, 0] for j in range(M + 1)]
+    lev = Level(FrozenDiffusion(full, rows, kv, times), M, dt)
+    return lev.C(step, Y[:, :, rows]) - np.asarray(u, float)[None][:, :, rows]

@@ -115,14 +115,19 @@ template <class T>
 struct CgBatchT;
 // store_g = 0 skips storing the reaction term (its caller discards it);
 // spread != 0 takes K x_0 from stage 0 (first sweep after a spread).
+// yref (T = float only; null elsewhere): stage vectors [P][M+1][NF][Np] of the
+// iterate the right-hand side was evaluated at; the FP32 cell model is then
+// evaluated at fl(yref) + fl(y - yref).
 template <class T>
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
                               const Colloc &co, const Stim &stim, double gs0, double gs1,
                               double gs2, int slice0, int nslices, int i,
-                              const CgBatchT<T> &cb, int store_g, int spread);
+                              const CgBatchT<T> &cb, int store_g, int spread, const double *yref);
 hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
                                    int nslices);
 int node_blocks(const Grid &g);
+// out2[2 (n NF + f)] = max |r_{n,f}|, out2[2 (n NF + f) + 1] = max |y_{n,f}| per
+// slice n and field f.
 hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *y_block0, double *part,
                            int nblk, double *out2, const double *Rt, int Mc, double *RI,

@@ -706,7 +706,7 @@ template <class T>
 __global__ void __launch_bounds__(NUB)
 __attribute__((amdgpu_waves_per_eu(4)))
 k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int i, CgBatchT<T> cb, int store_g, int spread) {
+              int slice0, int i, CgBatchT<T> cb, int store_g, int spread, const double *yref) {
   __shared__ double lds[3 * (BLOCK / 64)];
   const int64_t step0 = *stim.step;
   const int64_t qb = stencil_node_block(g0, blockIdx.x, gridDim.x);
@@ -757,13 +757,33 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
           nrh = RH[(f + 1) * Np + p];
         }
         stream_store<double>(&Yi[f * Np + p],
-                             yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv);
+                             yd[f] + rh + ddt * phi1(ddt * (double)lu) * (double)gv);
       }
       gV = Gp[p];
     } else {
       T yv[NF];
+      if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) yv[f] = T(yd[f]);
+        for (int f = 0; f < NF; ++f) yv[f] = yd[f];
+      } else {
+        // A cell model in FP32 rounds its inputs, and that rounding jumps: two
+        // FP64 states 1e-16 apart can round to neighbouring FP32 values.  With a
+        // reference state (the iterate whose terms the right-hand side holds)
+        // the model is evaluated at fl(ref) + fl(y - ref), which equals fl(ref)
+        // exactly once y has converged to ref, so the FP32 terms of both sides
+        // of the sweep cancel bitwise at the fixed point.
+        if (yref) {
+          const double *yr = yref + n * st.sY() + (int64_t)(i - 1) * st.sS();
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const double r = yr[f * Np + p];
+            yv[f] = T(r) + T(yd[f] - r);
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) yv[f] = T(yd[f]);
+        }
+      }
       const double t = ((double)(step0 + n * stim.tn) + co.c[i - 2]) * co.dt;
       // software-pipelined by one gate: the operands of gate k + 1 (Lambda and
       // value of the anchor, right-hand side) are loaded when gate k is
@@ -783,7 +803,7 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
         const T gv = -rate * (w - inf) + lu * (T(uf) - w);
         if (store_g) stream_store<T>(&Gp[f * Np + p], gv);
         stream_store<double>(&Yi[f * Np + p],
-                             yd[f] + rh + ddt * (double)T(phi1(ddt * (double)lu)) * (double)gv);
+                             yd[f] + rh + ddt * phi1(ddt * (double)lu) * (double)gv);
       });
       // right-hand sides of the rows after the cell model, in flight during the
       // currents (the V row's operands follow them: registers are the limit)
@@ -837,10 +857,11 @@ template <class T>
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
                               const Colloc &co, const Stim &stim, double gs0, double gs1,
                               double gs2, int slice0, int nslices, int i,
-                              const CgBatchT<T> &cb, int store_g, int spread) {
+                              const CgBatchT<T> &cb, int store_g, int spread,
+                              const double *yref) {
   dim3 grid(node_blocks(g), 1, nslices);
   hipLaunchKernelGGL(k_node_update<T>, grid, dim3(NUB), 0, s, g, st, co, stim, gs0, gs1, gs2,
-                     slice0, i, cb, store_g, spread);
+                     slice0, i, cb, store_g, spread, yref);
   return hipGetLastError();
 }
 
@@ -867,7 +888,7 @@ hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &s
 
 // One thread per (node, field) like the assembly, instantiated separately for
 // the rows V .. Rbar and the gate rows (held to four waves per SIMD); each
-// block writes the maxima of its row, reduced per slice by k_reduce_max2.
+// block writes the maxima of its row, reduced per (slice, field) by k_reduce_max2.
 template <int M, bool GATES>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_residual(Grid g0, Stages st, Colloc co, int slice0, const double *yblk0, double *part, int nbx,
@@ -956,7 +977,9 @@ hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const
     hipLaunchKernelGGL((k_residual<M, true>), gates, dim3(BLOCK), 0, s, g, st, co, slice0,
                        y_block0, part, nbx, Rt, Mc, RI, sRI);
   });
-  hipLaunchKernelGGL(k_reduce_max2, dim3(nslices), dim3(BLOCK), 0, s, part, nblk, out2);
+  // one reduction per (slice, field): the partials of a slice are laid out
+  // field by field, nbx per field
+  hipLaunchKernelGGL(k_reduce_max2, dim3(nslices * NF), dim3(BLOCK), 0, s, part, nbx, out2);
   return hipGetLastError();
 }
 
@@ -1152,7 +1175,10 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
     gamma = t2[0];
     delta = t2[1];
   }
-  if (gamma <= cb.tol2 * si.bb || gamma == 0.0 || si.it >= cb.maxit) {
+  // a NaN or Inf residual or right-hand side (a non-finite state) ends the
+  // solve at once: no iteration can recover, and the host reports it
+  const bool nonfinite = !(gamma - gamma == 0.0) || !(si.bb - si.bb == 0.0);
+  if (gamma <= cb.tol2 * si.bb || gamma == 0.0 || si.it >= cb.maxit || nonfinite) {
     if constexpr (std::is_same<T, double>::value) {
       if (si.it == 0 && cb.xin_p) {
         // the start's x_D is the solution: move it from p to x
@@ -2108,7 +2134,7 @@ hipError_t launch_step_add(hipStream_t s, int64_t *step, int64_t add) {
   template hipError_t launch_node_update<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
                                             const Colloc &, const Stim &, double, double,    \
                                             double, int, int, int, const CgBatchT<T> &, int, \
-                                            int);                                            \
+                                            int, const double *);                            \
   template hipError_t launch_cg_init<T>(hipStream_t, const Grid &, const CgBatchT<T> &);      \
   template hipError_t launch_cg_resid0<T>(hipStream_t, const Grid &, const CgBatchT<T> &);    \
   template hipError_t launch_cg_iter<T>(hipStream_t, const Grid &, const CgBatchT<T> &, int);

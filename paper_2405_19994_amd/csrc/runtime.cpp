@@ -163,6 +163,7 @@ struct hsdc_ctx {
   CgScalars *cg_dlog = nullptr;  // device: final scalars of every budgeted solve
   int cg_log_cap = 0, cg_log_used = 0;
   int cg_fails = 0;  // unconverged budgeted solves found by flush_cg_log
+  bool nonfinite = false;  // a solve met a NaN or Inf (reset by every stepping call)
   std::vector<CgLogEntry> cg_pending;
   Profiler prof;
   // graph replay of serial steps (hsdc_use_graph): one captured step, replayed
@@ -344,6 +345,8 @@ bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why)
     return why = "solver must be 0 (CG), 1 (Chebyshev) or 2 (CG from the warm start)", false;
   if (!std::isfinite(m->coarse_cg_rtol) || !(m->coarse_cg_rtol < 1))
     return why = "coarse_cg_rtol must be finite and < 1", false;
+  if (m->residual_norm != 0 && m->residual_norm != 1)
+    return why = "residual_norm must be 0 (over all fields) or 1 (per field)", false;
   return true;
 }
 
@@ -492,8 +495,8 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   if (!coarse_extras) {  // the residual is taken on the fine level only
     L.res_nblk = residual_blocks(L.g);
     L.res_part = dalloc<double>(c, (size_t)P * 2 * L.res_nblk);
-    L.res_out = dalloc<double>(c, (size_t)2 * P);
-    L.res_out_host = halloc<double>(c, 2 * P);
+    L.res_out = dalloc<double>(c, (size_t)2 * NF * P);
+    L.res_out_host = halloc<double>(c, 2 * NF * P);
   }
   L.U = dalloc<double>(c, (size_t)P * NF * Np);
   if (Mc_for_RI > 0) L.RI = dalloc<double>(c, (size_t)P * Mc_for_RI * NF * Np);
@@ -566,6 +569,10 @@ bool cg_ok(const CgScalars &sc, double tol2) {
   return sc.done && (sc.gamma <= tol2 * sc.bb || sc.gamma == 0.0);
 }
 
+// A solve whose residual or right-hand-side norm is NaN or Inf: the state it
+// was given is not finite (no further iteration or recomputation helps).
+bool cg_nonfinite(const CgScalars &sc) { return !std::isfinite(sc.gamma) || !std::isfinite(sc.bb); }
+
 // Launches a solve needed, minus one, as the budget predictor counts them: CG
 // ends with the launch that finds convergence (it + 1 launches).  Chebyshev's
 // launch k forms x_{k+1} and the node update x_1, so an even count m takes
@@ -590,6 +597,7 @@ void flush_cg_log(hsdc_ctx *c) {
     for (int n = 0; n < e.ns; ++n) {
       const CgScalars &sc = c->cg_log[e.off + n];
       const bool ok = cg_ok(sc, tol2);
+      if (cg_nonfinite(sc)) c->nonfinite = true;
       ok_all = ok_all && ok;
       used = std::max(used, budget_use(sc, e.cheb));
       c->stats.cg_iters += sc.it;
@@ -658,6 +666,7 @@ void cheb_solve(hsdc_ctx *c, Level &L, int lev, int s0, int ns, int i, int pred_
     c->stats.cg_iters += sc.it;
     c->stats.cg_solves += 1;
     if (!cg_ok(sc, cb.tol2)) c->stats.cg_unconverged += 1;
+    if (cg_nonfinite(sc)) c->nonfinite = true;
   }
   pred = std::max(used + 2, pred - 1);
 }
@@ -733,6 +742,7 @@ void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pre
     c->stats.cg_iters += sc.it;
     c->stats.cg_solves += 1;
     if (!cg_ok(sc, tol2)) c->stats.cg_unconverged += 1;
+    if (cg_nonfinite(sc)) c->nonfinite = true;
   }
   pred = std::max(used + 2, pred - 1);
 }
@@ -768,7 +778,7 @@ void evaluate_all(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns) {
 // ---------------------------------------------------------------------------
 template <class T>
 void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_src, const double *RI,
-           int pred_row, bool drop_terms = false) {
+           int pred_row, bool drop_terms = false, const double *yref = nullptr) {
   const Colloc &co = L.co;
   const hsdc_problem &p = c->prob;
   const int M = co.M;
@@ -792,7 +802,8 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
     const double per = ((i == 1) ? 90.0 : (drop_terms ? 83.0 : 102.0)) * sizeof(T) / 8.0;
     PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
             launch_node_update(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
-                               p.g_scale[2], s0, ns, i, cb, drop_terms ? 0 : 1, spread));
+                               p.g_scale[2], s0, ns, i, cb, drop_terms ? 0 : 1, spread,
+                               std::is_same<T, double>::value ? nullptr : yref));
     if (i > 1) c->stats.ionic_evals += (int64_t)(N * ns);
     cg_solve(c, L, lev, s0, ns, i, pred_row);
   }
@@ -853,15 +864,24 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
             launch_residual(c->s, L.g, L.st, L.co, 0, L.P, yb, L.res_part, L.res_nblk, L.res_out,
                             c->Rt, Mc, RI, (int64_t)Mc * NF * L.g.Np));
   }
-  HIPC(hipMemcpyAsync(L.res_out_host, L.res_out, 2 * L.P * sizeof(double), hipMemcpyDeviceToHost,
-                      c->s));
+  HIPC(hipMemcpyAsync(L.res_out_host, L.res_out, 2 * NF * L.P * sizeof(double),
+                      hipMemcpyDeviceToHost, c->s));
   HIPC(hipStreamSynchronize(c->s));
   bool finite = true;
   for (int n = 0; n < L.P; ++n) {
-    const double r = L.res_out_host[2 * n], y = L.res_out_host[2 * n + 1];
-    const double rel = y > 0 ? r / y : r;
-    if (!std::isfinite(rel) || !std::isfinite(y)) finite = false;
-    if (res_host) res_host[n] = rel;
+    // ||r_n||_inf / ||y_n||_inf over every field (Algorithm 1), or the largest
+    // of the per-field ratios ||r_{n,f}||_inf / ||y_{n,f}||_inf
+    double r = 0.0, y = 0.0, worst = 0.0;
+    for (int f = 0; f < NF; ++f) {
+      const double rf = L.res_out_host[2 * (n * NF + f)], yf = L.res_out_host[2 * (n * NF + f) + 1];
+      if (!std::isfinite(rf) || !std::isfinite(yf)) finite = false;
+      r = std::max(r, rf);
+      y = std::max(y, yf);
+      worst = std::max(worst, yf > 0 ? rf / yf : rf);
+    }
+    const double rel = c->meth.residual_norm == 1 ? worst : (y > 0 ? r / y : r);
+    if (!std::isfinite(rel)) finite = false;
+    if (res_host) res_host[n] = finite ? rel : NAN;
   }
   if (!finite) return fail(c, HSDC_ENONFINITE, "non-finite residual or state");
   return HSDC_OK;
@@ -965,7 +985,8 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
             launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, 0, P, Cc.RI, sRIc));
     for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
       gather_starts(c, Cc, Cc.y0c, n, 1);
-      sweep(c, Cc, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14, true);
+      // the right-hand side is evaluated at S z (kept in Sz until the correction)
+      sweep(c, Cc, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14, true, Cc.Sz);
     }
     coarse_correct_fine(c, Cc, 1);
   });
@@ -1052,7 +1073,7 @@ void graph_step(hsdc_ctx *c) {
   c->stats.sweeps += c->graph_sweeps;
   c->stats.ionic_evals += c->graph_ionic;
   flush_cg_log(c);
-  if (c->cg_fails > 0) {
+  if (c->cg_fails > 0 && !c->nonfinite) {
     c->stats.cg_redo_steps += 1;
     c->cg_fails = 0;
     HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, F.st.sY(), c->ybak, F.st.sS(), NF, F.P));
@@ -1401,9 +1422,13 @@ hsdc_status hsdc_sdc_sweep(hsdc_ctx *c, int32_t level, int32_t slice, int32_t ns
 hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
   if (nsteps < 0) return fail(c, HSDC_EINVAL, "nsteps must be >= 0");
+  // the status describes this call: solves of earlier calls do not count
+  const int64_t unconverged0 = c->stats.cg_unconverged;
+  c->nonfinite = false;
   return run_guarded(c, [&]() -> hsdc_status {
     Level &F = c->L[0];
     for (int s = 0; s < nsteps; ++s) {
+      if (c->nonfinite) break;  // a non-finite state: no further step helps
       if (!c->pfasst && c->graph_on && !c->prof.on && c->sweeps_done == 0) {
         graph_step(c);
       } else if (!c->pfasst) {
@@ -1418,7 +1443,7 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
         }
         flush_cg_log(c);
         c->safe_cg = true;
-        if (c->cg_fails > 0) {
+        if (c->cg_fails > 0 && !c->nonfinite) {
           c->stats.cg_redo_steps += 1;
           c->cg_fails = 0;
           begin_serial_step(c);
@@ -1452,7 +1477,8 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
         begin_block(c);
       }
     }
-    if (c->stats.cg_unconverged > 0)
+    if (c->nonfinite) return fail(c, HSDC_ENONFINITE, "a diffusion solve met a non-finite state");
+    if (c->stats.cg_unconverged > unconverged0)
       return fail(c, HSDC_ENOCONV, "a diffusion solve reached cg_maxit");
     return HSDC_OK;
   });

@@ -42,7 +42,8 @@ class Method(ctypes.Structure):
                 ("space_coarsen", ctypes.c_int32), ("P", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("burn_in", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
-                ("coarse_fp32", ctypes.c_int32), ("coarse_cg_rtol", ctypes.c_double)]
+                ("coarse_fp32", ctypes.c_int32), ("coarse_cg_rtol", ctypes.c_double),
+                ("residual_norm", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -158,11 +159,12 @@ def make_problem(dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None, chi=1400.0, C
 
 
 SOLVERS = {"cg": 0, "chebyshev": 1, "cg_plain": 2}
+RESIDUAL_NORMS = {"global": 0, "per_field": 1}
 
 
 def make_method(M=(4, 2), levels=1, space_coarsen=1, P=1, dt=0.05, max_iter=4, tol=0.0,
                 burn_in=1, cg_rtol=1e-12, cg_maxit=200, coarse_fp32=False, coarse_cg_rtol=0.0,
-                solver="cg"):
+                solver="cg", residual_norm="global"):
     m = Method()
     m.levels = int(levels)
     Ms = (tuple(M) + (1, 1))[:2] if not isinstance(M, int) else (M, 1)
@@ -172,6 +174,8 @@ def make_method(M=(4, 2), levels=1, space_coarsen=1, P=1, dt=0.05, max_iter=4, t
     m.cg_rtol, m.cg_maxit = float(cg_rtol), int(cg_maxit)
     m.coarse_fp32, m.coarse_cg_rtol = int(coarse_fp32), float(coarse_cg_rtol)
     m.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    m.residual_norm = RESIDUAL_NORMS[residual_norm] if isinstance(residual_norm, str) \
+        else int(residual_norm)
     return m
 
 

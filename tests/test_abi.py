@@ -21,10 +21,11 @@ def test_struct_layout_matches_header():
     assert [f for f, _ in H.Problem._fields_][:5] == ["dim", "nx", "ny", "nz", "dx"]
     assert ctypes.sizeof(H.Stats) == 9 * 8
     # levels, M[2], space_coarsen, P | dt | max_iter | tol | burn_in, solver |
-    # cg_rtol | cg_maxit, coarse_fp32 | coarse_cg_rtol
-    assert ctypes.sizeof(H.Method) == 80
+    # cg_rtol | cg_maxit, coarse_fp32 | coarse_cg_rtol | residual_norm (+ padding)
+    assert ctypes.sizeof(H.Method) == 88
     assert H.Method.solver.offset == 52
     assert H.Method.coarse_cg_rtol.offset == 72
+    assert H.Method.residual_norm.offset == 80
 
 
 def _init(p, m):
@@ -51,7 +52,7 @@ def test_bad_problem_is_einval(bad):
     dict(M=(0, 1)), dict(M=(9, 1)), dict(dt=0.0), dict(max_iter=0), dict(cg_rtol=0.0),
     dict(levels=3), dict(levels=1, P=4), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
     dict(levels=2, M=(4, 2), P=2, coarse_fp32=2), dict(levels=2, M=(4, 2), P=2, coarse_cg_rtol=1.0),
-    dict(solver=3), dict(solver=-1),
+    dict(solver=3), dict(solver=-1), dict(residual_norm=2),
 ])
 def test_bad_method_is_einval(bad):
     p = H.make_problem((15,), 0.01)

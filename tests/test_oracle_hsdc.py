@@ -325,6 +325,30 @@ def test_sampled_sweep_defect_vanishes_on_oracle_sweeps():
     assert np.abs(D[3, 9, 2]) > 5e-7
 
 
+def test_sampled_collocation_defect_vanishes_on_collocation_solution():
+    """oracle.sampled evaluates C(Y) - 1 (x) u (eq. def_C) at chosen nodes: it
+    equals the whole-mesh operator there, vanishes (to the solve tolerance) on
+    the collocation solution, and sees a planted error."""
+    import synthetic_inputs as si
+    from oracle.sampled import collocation_defect
+    w = si.workload("slab2d", dims=(20, 16))
+    po = Monodomain(w["dims"], w["dx"], w["sigma"], None, w["chi"], w["Cm"], w["stim_w"],
+                    w["stim_amp"], w["stim_t0"], w["stim_dur"], dt_ref=w["dt"])
+    lev = Level(po, 6, w["dt"])
+    y0 = np.repeat(ttp06.rest_state()[:, None], po.N, axis=1)
+    Y1 = lev.sweep(0, lev.spread(y0), lev.spread(y0))
+    rows = np.array([0, 5, 17, 100, 319])
+    D = collocation_defect(po, 6, w["dt"], 0, Y1, y0, rows)
+    full = lev.C(0, Y1) - y0[None]
+    assert np.max(np.abs(D - full[:, :, rows])) < 1e-13 * np.max(np.abs(Y1))
+    Y, _ = collocation_solve(lev, 0, y0, tol=1e-14)
+    D = collocation_defect(po, 6, w["dt"], 0, Y, y0, rows)
+    assert np.max(np.abs(D)) < 1e-12 * np.max(np.abs(Y))
+    Y[4, 2, 100] += 1e-6
+    D = collocation_defect(po, 6, w["dt"], 0, Y, y0, rows)
+    assert np.abs(D[4, 2, 3]) > 5e-7
+
+
 def test_pfasst_sixteen_slices_space_coarsened_stays_finite():
     """Algorithm 1 with the staggered burn-in, P = 16, M = 6,3, dt = 0.1 and the
     coarse level also coarsened 2x in space, on a small 3D slab through the
