@@ -272,6 +272,21 @@ hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const doubl
                                  double rtol, int32_t maxit, int32_t *iters_host,
                                  void *hip_stream);
 
+/* The same solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * arguments, results and errors as hsdc_diffusion_solve, but the CG vectors,
+ * the face coefficients of sigma_node, the partial sums and the CG scalars
+ * live in one static device array of the library (about 40 MiB, held by
+ * every device the library runs on until the process ends), so the call
+ * allocates nothing.  Meshes of more than HSDC_NOALLOC_MAX_NODES nodes are
+ * rejected with HSDC_EINVAL before any device work.  Every call on a device
+ * shares that device's array: calls that overlap on one device (other host
+ * threads, or other streams) race and must be serialised by the caller. */
+#define HSDC_NOALLOC_MAX_NODES 524288
+hsdc_status hsdc_diffusion_solve_noalloc(const hsdc_problem *prob, double a, const double *b,
+                                         double *x, double rtol, int32_t maxit,
+                                         int32_t *iters_host, void *hip_stream);
+
 /* Exponential collocation coefficients a_ij(z) (eq. def_aij), computed on the
  * device as sum_k c_i^k w_j^{k-1} phi_k(c_i z) (eq. def_aij_computable) with
  * the Radau IIA nodes and Fornberg weights of the library: z device [n],

@@ -240,6 +240,10 @@ hipError_t launch_phi_test(hipStream_t s, int64_t n, const double *x, int kmax, 
 hipError_t launch_aij_test(hipStream_t s, int64_t n, const double *z, const Colloc &co,
                            double *out);
 hipError_t launch_fill_rest(hipStream_t s, int64_t N, int64_t Np, double *y);
+// face coefficients kx, ky (dim >= 2), kz (dim 3) of a per-node sigma field on
+// the device: harmonic mean of the two nodes times sc, 0 on the last layer
+hipError_t launch_faces(hipStream_t s, const Grid &g, const double *sigma_node, double sc,
+                        double *kx, double *ky, double *kz);
 // device step counter: *step = value, or *step += add
 hipError_t launch_step_set(hipStream_t s, int64_t *step, int64_t value);
 hipError_t launch_step_add(hipStream_t s, int64_t *step, int64_t add);

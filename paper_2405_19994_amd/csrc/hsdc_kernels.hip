@@ -2091,6 +2091,31 @@ hipError_t launch_aij_test(hipStream_t s, int64_t n, const double *z, const Coll
   return hipGetLastError();
 }
 
+// Face coefficients of a per-node conductivity field: the face p -> p + e_axis
+// takes the harmonic mean of the two node values times sc = 1/(dx^2 chi Cm),
+// 0 on the last layer of the axis (the same expression as the host's).
+__global__ void __launch_bounds__(BLOCK)
+k_faces(Grid g, const double *sig, double sc, double *kx, double *ky, double *kz) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const Ijk c = ijk(g, p);
+  const double sp = sig[p];
+  auto face = [&](bool last, int64_t q) {
+    if (last) return 0.0;
+    const double sq = sig[q];
+    return (sp + sq > 0) ? 2.0 * sp * sq / (sp + sq) * sc : 0.0;
+  };
+  kx[p] = face(c.ix == g.nx - 1, p + 1);
+  if (g.dim >= 2) ky[p] = face(c.iy == g.ny - 1, p + g.nx);
+  if (g.dim >= 3) kz[p] = face(c.iz == g.nz - 1, p + (int64_t)g.nx * g.ny);
+}
+
+hipError_t launch_faces(hipStream_t s, const Grid &g, const double *sigma_node, double sc,
+                        double *kx, double *ky, double *kz) {
+  hipLaunchKernelGGL(k_faces, dim3(nblocks(g.N)), dim3(BLOCK), 0, s, g, sigma_node, sc, kx, ky, kz);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(BLOCK) k_fill_rest(int64_t N, int64_t Np, double *y) {
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   if (p >= N) return;

@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1665,6 +1666,130 @@ hsdc_status hsdc_apply_diffusion(const hsdc_problem *prob, const double *v, doub
   return st;
 }
 
+}  // extern "C"
+
+namespace {
+// One CG solve from the initial guess in cb.x, checked on the host every four
+// launches (the building-block solves: no budget, no log).
+void run_cg(hipStream_t s, const Grid &g, const CgBatch &cb, int *used, bool *conv) {
+  HIPC(launch_cg_resid0(s, g, cb));
+  HIPC(launch_cg_init(s, g, cb));
+  CgScalars sc2[2];
+  int k = 0;
+  for (;;) {
+    for (int q = 0; q < 4 && k <= cb.maxit; ++q, ++k) HIPC(launch_cg_iter(s, g, cb, k));
+    HIPC(hipMemcpyAsync(sc2, cb.sc, sizeof(sc2), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    if (sc2[k & 1].done || k > cb.maxit) break;
+  }
+  const CgScalars &sc = sc2[k & 1];
+  *used = sc.it;
+  *conv = cg_ok(sc, cb.tol2);
+}
+}  // namespace
+
+// ---- the diffusion solve without allocation -------------------------------
+// Workspace of hsdc_diffusion_solve_noalloc, in doubles: the CG vectors r, w, s
+// (two each) and p, then the face coefficients kx, ky, kz, each
+// HSDC_NOALLOC_MAX_NODES long; then the 5 x kNaBlocks partial sums and the two
+// CG scalars.  Each device holds its own copy at its own address; host code
+// uses the address from hipGetSymbolAddress, never the name.
+namespace {
+constexpr int64_t kNaNodes = HSDC_NOALLOC_MAX_NODES;
+constexpr int kNaBlocks = 2 * BLOCK;
+constexpr size_t kNaVecs = 10;
+constexpr size_t kNaDoubles = kNaVecs * (size_t)kNaNodes + 5 * (size_t)kNaBlocks +
+                              2 * (sizeof(CgScalars) + 7) / 8;
+static_assert(sizeof(CgScalars) % 8 == 0, "CG scalars are whole doubles");
+constexpr int kNaMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kNaMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+namespace {
+// Address of this device's scratch array, looked up on the first call on the
+// device (with it current) and kept for the process.
+hsdc_status scratch_address(double **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, HSDC_EDEVICE, hipGetErrorString(e));
+  if (dev < 0 || dev >= kNaMaxDevices) return fail(nullptr, HSDC_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, HSDC_EDEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HSDC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hsdc_status hsdc_diffusion_solve_noalloc(const hsdc_problem *prob, double a, const double *b,
+                                         double *x, double rtol, int32_t maxit,
+                                         int32_t *iters_host, void *hip_stream) {
+  std::string why;
+  if (!check_problem(prob, why)) return fail(nullptr, HSDC_EINVAL, why);
+  if (!b || !x || !(rtol > 0) || maxit < 1 || !(a >= 0))
+    return fail(nullptr, HSDC_EINVAL, "bad arguments");
+  if ((int64_t)prob->nx * prob->ny * prob->nz > kNaNodes)
+    return fail(nullptr, HSDC_EINVAL, "mesh larger than HSDC_NOALLOC_MAX_NODES");
+  double *base = nullptr;
+  hsdc_status st = scratch_address(&base);
+  if (st != HSDC_OK) return st;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  int used = 0;
+  bool conv = false;
+  try {
+    Grid g = make_grid(*prob, prob->nx, prob->ny, prob->nz, prob->dx);
+    double *vec[kNaVecs];
+    for (size_t k = 0; k < kNaVecs; ++k) vec[k] = base + k * (size_t)kNaNodes;
+    if (prob->sigma_node) {
+      const double sc = 1.0 / (prob->dx * prob->dx * prob->chi * prob->Cm);
+      HIPC(launch_faces(s, g, prob->sigma_node, sc, vec[7], vec[8], vec[9]));
+      g.kx = vec[7];
+      g.ky = g.dim >= 2 ? vec[8] : nullptr;
+      g.kz = g.dim >= 3 ? vec[9] : nullptr;
+    }
+    CgBatch cb{};
+    cb.x = x;
+    cb.b = b;
+    for (int k = 0; k < 2; ++k) {
+      cb.r[k] = vec[k];
+      cb.w[k] = vec[2 + k];
+      cb.s[k] = vec[4 + k];
+    }
+    cb.p = vec[6];
+    cb.nslices = 1;
+    cb.nblk = cg_blocks(g);
+    cb.nblk0 = cb.nblk;
+    cb.pstride = cb.nblk;
+    cb.part = base + kNaVecs * (size_t)kNaNodes;
+    cb.sc = (CgScalars *)(cb.part + 5 * (size_t)kNaBlocks);
+    cb.log = nullptr;
+    cb.last_k = -1;
+    cb.a = a;
+    cb.tol2 = rtol * rtol;
+    cb.maxit = maxit;
+    // every partial and scalar is written before it is read (k_cg_resid0 and
+    // k_cg_init write them): nothing of an earlier call has to be cleared
+    run_cg(s, g, cb, &used, &conv);
+  } catch (const HipFail &h) {
+    return fail(nullptr, HSDC_EDEVICE, std::string("HIP error in ") + h.what + ": " +
+                                           hipGetErrorString(h.e));
+  }
+  if (iters_host) *iters_host = used;
+  if (!conv) return fail(nullptr, HSDC_ENOCONV, "CG reached maxit");
+  return HSDC_OK;
+}
+
 hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const double *b, double *x,
                                  double rtol, int32_t maxit, int32_t *iters_host,
                                  void *hip_stream) {
@@ -1707,19 +1832,7 @@ hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const doubl
     cb.a = a;
     cb.tol2 = rtol * rtol;
     cb.maxit = maxit;
-    HIPC(launch_cg_resid0(tmp.s, L.g, cb));
-    HIPC(launch_cg_init(tmp.s, L.g, cb));
-    CgScalars sc2[2];
-    int k = 0;
-    for (;;) {
-      for (int q = 0; q < 4 && k <= maxit; ++q, ++k) HIPC(launch_cg_iter(tmp.s, L.g, cb, k));
-      HIPC(hipMemcpyAsync(sc2, cb.sc, sizeof(sc2), hipMemcpyDeviceToHost, tmp.s));
-      HIPC(hipStreamSynchronize(tmp.s));
-      if (sc2[k & 1].done || k > maxit) break;
-    }
-    const CgScalars &sc = sc2[k & 1];
-    used = sc.it;
-    conv = cg_ok(sc, cb.tol2);
+    run_cg(tmp.s, L.g, cb, &used, &conv);
     return HSDC_OK;
   });
   for (void *p : tmp.allocs) hipFree(p);

@@ -86,6 +86,8 @@ def lib():
             "hsdc_phi": [i64, vp, i32, vp, vp],
             "hsdc_apply_diffusion": [ctypes.POINTER(Problem), vp, vp, vp],
             "hsdc_diffusion_solve": [ctypes.POINTER(Problem), dbl, vp, vp, dbl, i32, vp, vp],
+            "hsdc_diffusion_solve_noalloc": [ctypes.POINTER(Problem), dbl, vp, vp, dbl, i32, vp,
+                                             vp],
             "hsdc_colloc_coefficients": [i32, i64, vp, vp, vp, vp],
             "hsdc_profile_enable": [vp, i32],
             "hsdc_profile_read": [vp, vp, i32, vp],
@@ -355,6 +357,21 @@ def diffusion_solve(problem, a, b, x0=None, rtol=1e-12, maxit=500, stream=None):
                                       _stream(stream))
     _check(code)
     return x, it.value
+
+
+NOALLOC_MAX_NODES = 524288
+
+
+def diffusion_solve_noalloc(problem, a, b, x, rtol=1e-12, maxit=500, stream=None):
+    """hsdc_diffusion_solve_noalloc: solves in place into x (the initial guess on
+    entry) with the library's static workspace; returns the iteration count."""
+    it = ctypes.c_int32(0)
+    code = lib().hsdc_diffusion_solve_noalloc(ctypes.byref(problem), float(a),
+                                              _dev(b, "b", (problem.N,)), _dev(x, "x", (problem.N,)),
+                                              float(rtol), int(maxit), ctypes.byref(it),
+                                              _stream(stream))
+    _check(code)
+    return it.value
 
 
 def colloc_coefficients(M, z, stream=None):

@@ -99,3 +99,14 @@ def test_bad_batch_is_einval(bad):
     assert code == -1 and not ptr.value
     assert H.lib().hsdc_last_error(None)
 
+
+
+def test_noalloc_solve_rejects_large_meshes_before_device_work():
+    """The no-allocation solve checks the mesh against HSDC_NOALLOC_MAX_NODES
+    before it touches the device (the pointers are never dereferenced)."""
+    p = H.make_problem((1024, 513), 0.025)
+    code = H.lib().hsdc_diffusion_solve_noalloc(ctypes.byref(p), 0.01, ctypes.c_void_p(8),
+                                                ctypes.c_void_p(8), 1e-12, 100, None, None)
+    assert code == -1
+    assert b"HSDC_NOALLOC_MAX_NODES" in H.lib().hsdc_last_error(None)
+    assert H.NOALLOC_MAX_NODES == 524288
