@@ -123,10 +123,18 @@ __device__ __forceinline__ void colloc_weights(const Colloc &co, const double *g
   }
 }
 
+// Gate rows store their reaction terms without the anchor part: G_j holds
+// f_e(y_j) - Lambda_n y_j, and g_j = G_j + Lambda_n u (plus f_I, f_E) with u =
+// y_{n,0}.  The anchor part is the same at every stage, and sum_j a_ij(z) =
+// c_i phi_1(c_i z) (the integral of e^{(c_i - s) z} over [0, c_i]), so it adds
+// anc c_i phi_1(c_i z), anc = Lambda_n u, to I_i; phi_1(c_i z) is the first of
+// the phi values formed for row i anyway.  A node update then needs neither u
+// nor Lambda_n u: in the node-to-node form the anchor parts of R_i - R_{i-1}
+// and of the new reaction term cancel.
 template <int M>
 __device__ __forceinline__ void colloc_integrals(const Colloc &co, double z, const double *g,
-                                                 double *I) {
-  if (z == 0.0) {
+                                                 double *I, double anc = 0.0) {
+  if (z == 0.0) {  // Lambda_n = 0: no anchor part
     colloc_weights<M>(co, g, I);
     return;
   }
@@ -145,7 +153,7 @@ __device__ __forceinline__ void colloc_integrals(const Colloc &co, double z, con
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < M; ++k) s += co.cpow[i][k + 1] * ph[k] * mom[k];
-    I[i] = s;
+    I[i] = s + anc * co.c[i] * ph[0];
   }
 }
 
@@ -412,31 +420,25 @@ k_eval_stages(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
   const int j = stage0 + blockIdx.y;
   const int64_t Np = st.Np;
   const double *y = st.Y + n * st.sY() + j * st.sS();
-  const double *u = st.Y + n * st.sY();
   T *G = st.G + n * st.sY() + j * st.sS();
   T yv[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) yv[f] = T(y[f * Np + p]);
   const double cj = (j == 0) ? 0.0 : co.c[j - 1];
   const double t = ((double)(step0 + n * stim.tn) + cj) * co.dt;
+  // stage 0 is the anchor itself (its Lambda is the anchor's); later stages
+  // read Lambda_n
   const T *La = (j == 0) ? nullptr : Lin + n * st.sL();
   T *Lo = (j == 0 && Lout) ? Lout + n * st.sL() : nullptr;
-  // software-pipelined by one gate (the anchor's Lambda and value of gate k + 1
-  // are loaded when gate k is stored)
+  // gate rows without the anchor part: f_e(w) - Lambda_n w (software-pipelined
+  // by one gate: Lambda_n of gate k + 1 is loaded when gate k is stored)
   T nla = La ? La[p] : T(0);
-  double nuf = La ? u[GATE0 * Np + p] : 0.0;
   ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T rate) {
-    const T la = nla;
-    const double uf = nuf;
-    if (La && k + 1 < NG) {
-      nla = La[(k + 1) * Np + p];
-      nuf = u[(GATE0 + k + 1) * Np + p];
-    }
     const T lam = -rate;
+    const T la = La ? nla : lam;
+    if (La && k + 1 < NG) nla = La[(k + 1) * Np + p];
     const T w = yv[GATE0 + k];
-    T gv = lam * (w - inf);
-    if (La) gv += la * (T(uf) - w);
-    G[(GATE0 + k) * Np + p] = gv;
+    G[(GATE0 + k) * Np + p] = lam * (w - inf) - la * w;
     if (Lo) Lo[k * Np + p] = lam;
   });
   T I_ion, ha[6];
@@ -550,7 +552,11 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
   const double dt = co.dt;
   if constexpr (GATES) {
     // Gate rows: no K V term.  Each I_i is formed, completed and stored in
-    // turn, so only the moments stay live across the phi evaluations.
+    // turn, so only the moments stay live across the phi evaluations.  G holds
+    // the reaction terms without the anchor part Lambda_n u; that part enters
+    // I_i as Lambda_n u c_i phi_1(c_i z), while the Phi term takes the stored
+    // G alone: the new stage's node update adds its own reaction term without
+    // the anchor part, and the two anchor parts cancel in R_i - R_{i-1}.
     double Gv[M + 1];
     if (spread) {
 #pragma unroll
@@ -559,7 +565,9 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
 #pragma unroll
       for (int j = 0; j <= M; ++j) Gv[j] = G[j * st.sS()];
     }
-    const double z = dt * st.L0[n * st.sL() + (f - GATE0) * Np + p];
+    const double lam_n = st.L0[n * st.sL() + (f - GATE0) * Np + p];
+    const double z = dt * lam_n;
+    const double anc = lam_n * st.Y[n * st.sY() + f * Np + p];
     double mom[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -583,7 +591,7 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < M; ++k) s += co.cpow[i][k + 1] * ph[k] * mom[k];
-        Ii = s;
+        Ii = s + anc * co.c[i] * ph[0];
       }
       if (RI) Ii += RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
       stream_store<double>(&RH[(int64_t)i * st.sS()],
@@ -617,13 +625,7 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
   }
 #pragma unroll
   for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + fv[j + 1];
-  double z = 0.0;
-  if constexpr (GATES) {
-    z = dt * st.L0[n * st.sL() + (f - GATE0) * Np + p];
-    colloc_integrals<M>(co, z, gfull, I);
-  } else {
-    colloc_weights<M>(co, gfull, I);
-  }
+  colloc_weights<M>(co, gfull, I);
   if (RI) {
 #pragma unroll
     for (int i = 0; i < M; ++i) I[i] += RI[n * sRI + ((int64_t)i * NF + f) * Np + p];
@@ -631,10 +633,9 @@ k_assemble(Grid g0, StagesT<T> st, Colloc co, int slice0, const double *RI, int6
   double prevI = 0.0;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    const double ph = GATES ? phi1(co.d[i] * z) : 1.0;
     // streaming store: read once, by a later kernel
     stream_store<double>(&RH[(int64_t)i * st.sS()],
-                         dt * (I[i] - prevI) - dt * co.d[i] * (fv[i + 1] + ph * Gv[i]));
+                         dt * (I[i] - prevI) - dt * co.d[i] * (fv[i + 1] + Gv[i]));
     prevI = I[i];
   }
 }
@@ -673,8 +674,10 @@ k_fas_integrals(Grid g0, StagesT<T> st, Colloc co, int slice0, double *RI, int64
 #pragma unroll
   for (int j = 0; j < M; ++j)
     gfull[j] = (double)G[(j + 1) * st.sS()] + (f == 0 ? FV[(j + 1) * Np] : 0.0);
-  const double z = (f >= GATE0) ? co.dt * st.L0[n * st.sL() + (f - GATE0) * Np + p] : 0.0;
-  colloc_integrals<M>(co, z, gfull, I);
+  // gate rows: Lambda_n and the anchor part (G holds the reaction terms without it)
+  const double lam_n = (f >= GATE0) ? (double)st.L0[n * st.sL() + (f - GATE0) * Np + p] : 0.0;
+  const double anc = (f >= GATE0) ? lam_n * st.Y[n * st.sY() + f * Np + p] : 0.0;
+  colloc_integrals<M>(co, co.dt * lam_n, gfull, I, anc);
   double *R = RI + n * sRI + (int64_t)f * Np + p;
 #pragma unroll
   for (int i = 0; i < M; ++i) R[(int64_t)i * NF * Np] -= I[i];
@@ -719,7 +722,6 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
   if (p < g.N) {
     const double *Yp = st.Y + n * st.sY() + (int64_t)(i - 1) * st.sS();
     double *Yi = st.Y + n * st.sY() + (int64_t)i * st.sS();
-    const double *u = st.Y + n * st.sY();
     const double *RH = st.RH + n * st.sRH() + (int64_t)(i - 1) * st.sS();
     const T *Lu = st.L0 + n * st.sL();  // Lambda of the anchor u
     T *Gp = st.G + n * st.sY() + (int64_t)(i - 1) * st.sS();
@@ -735,7 +737,8 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
     const double *fvp = st.FV + n * st.sFV() + (int64_t)(spread ? 0 : i) * Np + p;
     double rh0, x0, kx0;
     if (i == 1) {
-      // y_{n,0} = u: its reaction term was evaluated with the anchor
+      // y_{n,0} = u: its reaction term is the stored one (gates without the
+      // anchor part, like every gate reaction term)
       rh0 = RH[p];
       x0 = Yi[p];
       kx0 = *fvp;
@@ -785,22 +788,22 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
         }
       }
       const double t = ((double)(step0 + n * stim.tn) + co.c[i - 2]) * co.dt;
-      // software-pipelined by one gate: the operands of gate k + 1 (Lambda and
-      // value of the anchor, right-hand side) are loaded when gate k is
-      // applied, so they are in flight while the cell model computes gate k + 1
+      // software-pipelined by one gate: the operands of gate k + 1 (Lambda_n
+      // and right-hand side) are loaded when gate k is applied, so they are in
+      // flight while the cell model computes gate k + 1.  The reaction term is
+      // formed without the anchor part Lambda_n u (the right-hand side holds it)
       T nlu = Lu[p];
-      double nuf = u[GATE0 * Np + p], nrh = RH[GATE0 * Np + p];
+      double nrh = RH[GATE0 * Np + p];
       ttp06::gates<T>(yv[0], yv[3], [&](int k, T inf, T rate) {
         const int f = GATE0 + k;
         const T lu = nlu;
-        const double uf = nuf, rh = nrh;
+        const double rh = nrh;
         if (k + 1 < NG) {
           nlu = Lu[(k + 1) * Np + p];
-          nuf = u[(f + 1) * Np + p];
           nrh = RH[(f + 1) * Np + p];
         }
         const T w = yv[f];
-        const T gv = -rate * (w - inf) + lu * (T(uf) - w);
+        const T gv = -rate * (w - inf) - lu * w;
         if (store_g) stream_store<T>(&Gp[f * Np + p], gv);
         stream_store<double>(&Yi[f * Np + p],
                              yd[f] + rh + ddt * phi1(ddt * (double)lu) * (double)gv);
@@ -912,13 +915,15 @@ k_residual(Grid g0, Stages st, Colloc co, int slice0, const double *yblk0, doubl
 #pragma unroll
     for (int j = 0; j < M; ++j)
       gfull[j] = G[(j + 1) * st.sS()] + (f == 0 ? st.FV[n * st.sFV() + (j + 1) * Np + p] : 0.0);
+    const double y0 = Y[0];
     if constexpr (GATES) {
-      colloc_integrals<M>(co, co.dt * st.L0[n * st.sL() + (f - GATE0) * Np + p], gfull, I);
+      // G holds the gate reaction terms without the anchor part Lambda_n y_{n,0}
+      const double lam_n = st.L0[n * st.sL() + (f - GATE0) * Np + p];
+      colloc_integrals<M>(co, co.dt * lam_n, gfull, I, lam_n * y0);
     } else {
       colloc_weights<M>(co, gfull, I);
     }
     const double u = up[f * Np + p];
-    const double y0 = Y[0];
     rmax = nmax(rmax, fabs(y0 - u));
     ymax = nmax(ymax, fabs(y0));
 #pragma unroll

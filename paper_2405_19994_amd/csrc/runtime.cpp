@@ -757,7 +757,7 @@ void evaluate_all(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns) {
   PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N * ns,
           launch_eval_stages<T>(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                              p.g_scale[2], s0, ns, 0, 1, L.st.L0, nullptr));
-  PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns * M,
+  PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N * ns * M,
           launch_eval_stages<T>(c->s, L.g, L.st, L.co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                              p.g_scale[2], s0, ns, 1, M, nullptr, L.st.L0));
   PLAUNCH(c, PC_SPMV, 16.0 * (M + 1) * N * ns,
@@ -793,14 +793,19 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
     evaluate_all(c, L, lev, s0, ns);
   }
   {
-    const double per = spread ? (NF + 1 + NG + M * NF)
-                              : ((M + 1) * NF + M + NG + M * NF + (RI ? M * NF : 0));
+    // G of every stage (stage 0 only after a spread), K V, Lambda_n and the
+    // anchor's gate values read; RH written
+    const double per = spread ? (NF + 1 + 2 * NG + M * NF)
+                              : ((M + 1) * NF + M + 2 * NG + M * NF + (RI ? M * NF : 0));
     PLAUNCH(c, PC_ASSEMBLE, 8.0 * per * N * ns,
             launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI, spread, c->stim[lev]));
   }
   for (int i = 1; i <= M; ++i) {
     const CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
-    const double per = ((i == 1) ? 90.0 : (drop_terms ? 83.0 : 102.0)) * sizeof(T) / 8.0;
+    // doubles per node: stage i-1, RH_i, Lambda_n, x_0 and K x_0 read; stage i
+    // (but V), b, x_1 and (unless dropped) the reaction terms of stage i-1
+    // written; node 1 reads the stored reaction terms of stage 0 instead
+    const double per = ((i == 1) ? 90.0 : (drop_terms ? 71.0 : 90.0)) * sizeof(T) / 8.0;
     PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
             launch_node_update(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                                p.g_scale[2], s0, ns, i, cb, drop_terms ? 0 : 1, spread,
@@ -812,7 +817,7 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
   if (!drop_terms) {
     // reaction terms and K V of the new iterate's last stage, for the next
     // sweep or the residual (stages 1..M-1 were stored by the node updates)
-    PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + 2 * NG) * N * ns,
+    PLAUNCH(c, PC_EVAL, 8.0 * (2 * NF + NG) * N * ns,
             launch_eval_stages<T>(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                                p.g_scale[2], s0, ns, M, 1, nullptr, L.st.L0));
     c->stats.ionic_evals += (int64_t)(N * ns);
