@@ -164,11 +164,14 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
 /* Launch tuning of a context (results are unchanged up to the order of the CG
  * reductions): cg_blocks caps the blocks of each CG kernel (1..1024, <= 0
  * keeps the current cap, default 512); cg_margin is the number of spare
- * iterations added to a predicted CG iteration budget (1..64, <= 0 keeps the
- * current margin, default 2; a Chebyshev budget gets one spare launch more,
- * since its iteration count moves in steps of two).  Takes effect from the
- * next solve; call it between steps, not concurrently with work on the
- * context. */
+ * launches added to a predicted CG budget (0..64, negative keeps the current
+ * margin, default 1).  A budgeted solve gets one CG launch per iteration it is
+ * predicted to need plus the margin, none when its start is predicted to meet
+ * cg_rtol and the margin is 0; its convergence is checked from the residual's
+ * partial sums by the kernel that follows it, and a step with a missed solve
+ * is recomputed.  A Chebyshev budget gets one spare launch more, since its
+ * iteration count moves in steps of two.  Takes effect from the next solve;
+ * call it between steps, not concurrently with work on the context. */
 hsdc_status hsdc_tune(hsdc_ctx *ctx, int32_t cg_blocks, int32_t cg_margin);
 
 /* Graph replay of serial steps (serial and batch contexts created on a

@@ -16,8 +16,9 @@ import os
 import time
 
 CG_BLOCKS = (128, 256, 512, 1024)
-CG_MARGINS = (1, 2, 3)
-DEFAULT = {"cg_blocks": 512, "cg_margin": 2}
+# -1: the library's default margin (none after the tiled CG start, one otherwise)
+CG_MARGINS = (-1, 1, 2)
+DEFAULT = {"cg_blocks": 512, "cg_margin": -1}
 
 
 def cache_path():

@@ -118,11 +118,15 @@ struct CgBatchT;
 // yref (T = float only; null elsewhere): stage vectors [P][M+1][NF][Np] of the
 // iterate the right-hand side was evaluated at; the FP32 cell model is then
 // evaluated at fl(yref) + fl(y - yref).
+// lg: the previous solve of the same slices to log (lg.log null: none); block 0
+// of each slice writes its entry before its own work.
+struct CgLogArgs;
 template <class T>
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
                               const Colloc &co, const Stim &stim, double gs0, double gs1,
                               double gs2, int slice0, int nslices, int i,
-                              const CgBatchT<T> &cb, int store_g, int spread, const double *yref);
+                              const CgBatchT<T> &cb, int store_g, int spread, const double *yref,
+                              const CgLogArgs &lg);
 hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
                                    int nslices);
 int node_blocks(const Grid &g);
@@ -186,12 +190,33 @@ struct CgBatchT {
   // vectors (and x_D in x), so the CG launches run k = 1, 2, ...
   int cstart;
   // partials of (r_D, r_D) and (w_D, r_D) written by the start (first CG
-  // launch), and xin_p = 1 when the start left x_D in p rather than x (the
-  // tiled start, launch_cg_start_tiled: the first CG launch forms x from p,
-  // or copies p to x if it finds x_D converged)
+  // launch); x0_to_p = 1: the node update also stores the warm start x_0 in p,
+  // where the tiled start (launch_cg_start_tiled) reads it, so that the start
+  // can write x_D into x while other tiles still read x_0
   int nblk_s;
-  int xin_p;
+  int x0_to_p;
 };
+
+// A budgeted solve whose outcome a later kernel writes to the solve log (the
+// next node update of the same slices, or launch_cg_log): the final scalars
+// when a CG launch found convergence, else the residual reduced from the
+// partial sums of the last writer (the start, or a CG launch that iterated).
+struct CgLogArgs {
+  const double *part;   // the solve's partial sums [nslices][5][pstride]
+  int64_t pstride;
+  const CgScalars *sc;  // the solve's scalars [nslices][2]
+  CgScalars *log;       // [nslices] log entries, or null (nothing to log)
+  int par;              // parity of the scalars and partials holding the final state
+  int ngamma;           // partials of the final (r, r) (start tiles or blocks, or
+                        // node-update blocks); -1: the CG blocks active for the mesh
+  int cg_nblk;          // blocks of the solve's CG launches
+  int nbb;              // partials of ||b||^2 (node-update blocks)
+  int slice0;
+  double tol2;
+  int rel_r0;
+};
+// Writes the log entries of lg (one block per slice).
+hipError_t launch_cg_log(hipStream_t s, const Grid &g, const CgLogArgs &lg, int nslices);
 using CgBatch = CgBatchT<double>;
 int cg_blocks(const Grid &g, int cap = 512);
 template <class T>
@@ -212,7 +237,8 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb);
 // The whole CG start of degree D = cb.cstart (3..5) in one launch on 2D meshes
 // (x_2 .. x_D, r_D, w_D in LDS tiles of 64 x 16 nodes with a halo of D + 1);
-// x_D goes to p.  cg_start_tiles(g, D) = its tiles per slice on a mesh that is
+// x_0 is read from p (cb.x0_to_p) and x_D written to x.  cg_start_tiles(g, D) =
+// its tiles per slice on a mesh that is
 // not a ragged batch (0: not applicable); ntiles = the launch's tiles per
 // slice (a ragged batch: the most of any tissue, cg_start_tiles_of).
 int cg_start_tiles(const Grid &g, int degree);

@@ -699,6 +699,51 @@ hipError_t launch_fas_integrals(hipStream_t s, const Grid &g, const StagesT<T> &
 // side of the implicit diffusion solve for V.
 // ---------------------------------------------------------------------------
 
+// Log entry of slice n (absolute) of a budgeted solve, written by a whole
+// block of NT threads (every thread takes part in the reductions).  When a CG
+// launch published convergence its scalars are final; otherwise the residual
+// is reduced here from the partial sums of the last writer and compared with
+// the tolerance, so a solve needs no launch of its own to be checked.
+template <int NT>
+__device__ __forceinline__ void cg_log_entry(const Grid &g0, const CgLogArgs &lg, int n,
+                                             double *lds) {
+  const int q = n - lg.slice0;
+  const CgScalars si = lg.sc[2 * q + lg.par];
+  const double *part = lg.part + (int64_t)q * 5 * lg.pstride;
+  int ng = lg.ngamma;
+  if (ng < 0) {  // a CG launch wrote them: its blocks active on this slice's mesh
+    const int64_t nb = (slice_grid(g0, n).N + BLOCK - 1) / BLOCK;
+    ng = nb < lg.cg_nblk ? (int)nb : lg.cg_nblk;
+  }
+  double t2[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < ng; k += NT) t2[0] += part[(2 * lg.par) * lg.pstride + k];
+  for (int k = threadIdx.x; k < lg.nbb; k += NT) t2[1] += part[4 * lg.pstride + k];
+  block_sums<2, NT>(t2, lds);
+  if (threadIdx.x == 0) {
+    CgScalars o = si;
+    if (!si.done) {
+      // bb: published by the first CG launch, or (no launch ran) the node
+      // update's partials; a correction solve compares with its start residual
+      const double ref = si.bb >= 0.0 ? si.bb : (lg.rel_r0 ? t2[0] : t2[1]);
+      o.gamma = t2[0];
+      o.bb = ref;
+      o.done = (t2[0] <= lg.tol2 * ref || t2[0] == 0.0) ? 1 : 0;
+    }
+    lg.log[q] = o;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_cg_log(Grid g0, CgLogArgs lg) {
+  __shared__ double lds[2 * (256 / 64)];
+  cg_log_entry<256>(g0, lg, lg.slice0 + blockIdx.x, lds);
+}
+
+hipError_t launch_cg_log(hipStream_t s, const Grid &g, const CgLogArgs &lg, int nslices) {
+  if (!lg.log || nslices <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_log, dim3(nslices), dim3(256), 0, s, g, lg);
+  return hipGetLastError();
+}
+
 // Four waves per SIMD (at most 128 VGPRs): the launch has exactly that many
 // waves on the 512 x 512 slab, so a fifth register would halve its occupancy.
 // Node-update blocks of 256 threads (four waves): on the 512 x 512 slab the
@@ -709,12 +754,16 @@ template <class T>
 __global__ void __launch_bounds__(NUB)
 __attribute__((amdgpu_waves_per_eu(4)))
 k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
-              int slice0, int i, CgBatchT<T> cb, int store_g, int spread, const double *yref) {
+              int slice0, int i, CgBatchT<T> cb, int store_g, int spread, const double *yref,
+              CgLogArgs lg) {
   __shared__ double lds[3 * (BLOCK / 64)];
   const int64_t step0 = *stim.step;
   const int64_t qb = stencil_node_block(g0, blockIdx.x, gridDim.x);
   const int64_t p = qb * NUB + threadIdx.x;
   const int n = slice0 + blockIdx.z;
+  // the previous solve of this slice is checked by one block (its partial sums
+  // are the other stage parity's, which this launch does not write)
+  if (lg.log && blockIdx.x == 0) cg_log_entry<NUB>(g0, lg, n, lds);
   const Grid g = slice_grid(g0, n);
   const int64_t Np = st.Np;
   const double ddt = co.dt * co.d[i - 1];
@@ -831,9 +880,11 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
     const double bv = yd[0] + rh0 + ddt * (double)gV;
     const double r0 = bv - x0 + cb.a * kx0;
     if (cb.xt) {
-      // Chebyshev: b and the first iterate x_1 = x_0 + r_0 / theta
+      // Chebyshev: b and the first iterate x_1 = x_0 + r_0 / theta (and x_0 for
+      // the tiled start, which writes x_D over x)
       cb.bout[(int64_t)(n - slice0) * Np + p] = bv;
       cb.xt[(int64_t)(n - slice0) * Np + p] = x0 + r0 * cb.tab[n * cb.tab_stride].inv_theta;
+      if (cb.x0_to_p) cb.p[(int64_t)(n - slice0) * Np + p] = x0;
     } else {
       cb.r[0][(int64_t)(n - slice0) * Np + p] = T(r0);
     }
@@ -861,10 +912,10 @@ hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st
                               const Colloc &co, const Stim &stim, double gs0, double gs1,
                               double gs2, int slice0, int nslices, int i,
                               const CgBatchT<T> &cb, int store_g, int spread,
-                              const double *yref) {
+                              const double *yref, const CgLogArgs &lg) {
   dim3 grid(node_blocks(g), 1, nslices);
   hipLaunchKernelGGL(k_node_update<T>, grid, dim3(NUB), 0, s, g, st, co, stim, gs0, gs1, gs2,
-                     slice0, i, cb, store_g, spread, yref);
+                     slice0, i, cb, store_g, spread, yref, lg);
   return hipGetLastError();
 }
 
@@ -1184,14 +1235,6 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   // solve at once: no iteration can recover, and the host reports it
   const bool nonfinite = !(gamma - gamma == 0.0) || !(si.bb - si.bb == 0.0);
   if (gamma <= cb.tol2 * si.bb || gamma == 0.0 || si.it >= cb.maxit || nonfinite) {
-    if constexpr (std::is_same<T, double>::value) {
-      if (si.it == 0 && cb.xin_p) {
-        // the start's x_D is the solution: move it from p to x
-        const double *xs = cb.p + n * g.Np;
-        double *xd = cb.x + n * cb.sx;
-        for (int64_t q = p0; q < g.N; q += (int64_t)cb.nblk * BLOCK) xd[q] = xs[q];
-      }
-    }
     if (publish) {
       CgScalars o = si;
       o.gamma = gamma;
@@ -1211,13 +1254,11 @@ __global__ void __launch_bounds__(BLOCK) k_cg_iter(Grid g0, CgBatchT<T> cb, int 
   double *x = cb.x + n * cb.sx;
   double gam = 0.0, del = 0.0;
   // iteration 0 takes p = r, s = w (p and s hold nothing yet)
-  // (after a tiled start, iteration 0 finds x_D in p)
-  const bool x_from_p = first && cb.xin_p;
   auto update = [&](int64_t p, const Ijk &c, double rc0, double wc0, double sc0, auto &&rn) {
     const double pn = first ? rc0 : rc0 + beta * pp[p];
     const double sn = first ? wc0 : wc0 + beta * sc0;
     const double rc = rc0 - alpha * sn;
-    x[p] = (x_from_p ? (double)pp[p] : x[p]) + alpha * pn;
+    x[p] += alpha * pn;
     const double wn = rc - cb.a * applyK<DIM, PN>(g, p, c, rc, rn);
     pp[p] = pn;
     sout[p] = sn;
@@ -1530,7 +1571,8 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // boundary reads the node itself, so its term is exactly 0; with per-node
 // sigma the face coefficients come along in LDS and a missing face adds 0).
 // x_{k+1} overwrites x_{k-1} cell by cell, so two LDS vectors and b suffice.
-// x_D goes to p, not x: other tiles still read x_0 from x.  Partials of (r_D,
+// x_0 comes from p (the node update stores it there) and x_D goes to x, so no
+// tile overwrites what a neighbouring tile still reads.  Partials of (r_D,
 // r_D) and (w_D, r_D) per tile, numbered within each tissue (tile t at (t %
 // tiles_x, t / tiles_x) of the tissue's own tiles_x), so that a tissue of a
 // ragged batch and its own context reduce the same partials in the same order;
@@ -1540,7 +1582,7 @@ constexpr int CTX = 64, CTY = 16, CT_THREADS = 1024;
 int cg_start_tiles_of(int nx, int ny) { return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY); }
 
 int cg_start_tiles(const Grid &g, int degree) {
-  if (degree < 3 || degree > 5 || g.dim != 2 || g.rag != nullptr) return 0;
+  if (degree < 3 || degree > 7 || g.dim != 2 || g.rag != nullptr) return 0;
   return cg_start_tiles_of(g.nx, g.ny);
 }
 
@@ -1567,7 +1609,7 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch 
   }
   const int X0 = (t % tiles_x) * CTX - H, Y0 = (t / tiles_x) * CTY - H;
   const double *x1g = cb.xt + (int64_t)n * g.Np;
-  const double *x0g = cb.x + n * cb.sx;
+  const double *x0g = cb.p + (int64_t)n * g.Np;  // x_0, stored there by the node update
   const double *bg = cb.b + n * cb.sb;
   const ChebTab &tb = cb.tab[(cb.slice0 + n) * cb.tab_stride];
   const double ith = tb.inv_theta, a = cb.a;
@@ -1646,7 +1688,7 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch 
     }
   }
   __syncthreads();
-  // w_D = A r_D on the tile; x_D to p, r_D and w_D to the parity-1 vectors
+  // w_D = A r_D on the tile; x_D to x, r_D and w_D to the parity-1 vectors
   double gam = 0.0, del = 0.0;
   for (int q = threadIdx.x; q < CTX * CTY; q += CT_THREADS) {
     const int u = H + q % CTX, v = H + q / CTX;
@@ -1654,7 +1696,7 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch 
     const double rc = xm[v][u];
     const double wv = rc - a * Kat(xm, u, v);
     const int64_t p = (X0 + u) + (int64_t)nx * (Y0 + v);
-    cb.p[n * g.Np + p] = xk[v][u];
+    cb.x[n * cb.sx + p] = xk[v][u];
     cb.r[1][n * g.Np + p] = rc;
     cb.w[1][n * g.Np + p] = wv;
     gam += rc * rc;
@@ -1688,12 +1730,13 @@ hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb
     else                                                                                     \
       hipLaunchKernelGGL((k_cg_start_tiled<D_, false>), grid, dim3(CT_THREADS), 0, s, g, cb); \
   } while (0)
-  if (cb.cstart == 3)
-    HSDC_CT_LAUNCH(3);
-  else if (cb.cstart == 4)
-    HSDC_CT_LAUNCH(4);
-  else
-    HSDC_CT_LAUNCH(5);
+  switch (cb.cstart) {
+    case 3: HSDC_CT_LAUNCH(3); break;
+    case 4: HSDC_CT_LAUNCH(4); break;
+    case 5: HSDC_CT_LAUNCH(5); break;
+    case 6: HSDC_CT_LAUNCH(6); break;
+    default: HSDC_CT_LAUNCH(7); break;
+  }
 #undef HSDC_CT_LAUNCH
   return hipGetLastError();
 }
@@ -2164,7 +2207,7 @@ hipError_t launch_step_add(hipStream_t s, int64_t *step, int64_t add) {
   template hipError_t launch_node_update<T>(hipStream_t, const Grid &, const StagesT<T> &,    \
                                             const Colloc &, const Stim &, double, double,    \
                                             double, int, int, int, const CgBatchT<T> &, int, \
-                                            int, const double *);                            \
+                                            int, const double *, const CgLogArgs &);         \
   template hipError_t launch_cg_init<T>(hipStream_t, const Grid &, const CgBatchT<T> &);      \
   template hipError_t launch_cg_resid0<T>(hipStream_t, const Grid &, const CgBatchT<T> &);    \
   template hipError_t launch_cg_iter<T>(hipStream_t, const Grid &, const CgBatchT<T> &, int);

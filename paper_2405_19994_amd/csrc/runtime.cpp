@@ -83,6 +83,7 @@ struct LevelT {
   CgScalars *cg_sc_host = nullptr;  // [P][2]
   int cg_nblk = 0;
   int64_t cg_pstride = 0;
+  bool tiled_start = false;  // CG starts with the tiled Chebyshev launch (2D meshes)
   // residual
   double *res_part = nullptr, *res_out = nullptr, *res_out_host = nullptr;
   int res_nblk = 0;
@@ -101,6 +102,7 @@ using Level = LevelT<double>;
 struct CgLogEntry {
   int lev, s0, ns, i, row, parity, off, budget;
   bool cheb;
+  int margin;  // spare launches of the solve's budget
 };
 
 }  // namespace
@@ -180,7 +182,7 @@ struct hsdc_ctx {
   double *ybak = nullptr;  // [P][NF][Np] start value of the step being replayed
   // launch tuning (hsdc_tune): CG block cap and iteration-budget margin
   int tune_cg_blocks = 512;
-  int tune_cg_margin = 2;
+  int tune_cg_margin = -1;  // < 0: the default of each level (cg_margin())
 };
 
 namespace {
@@ -217,6 +219,12 @@ double level_rtol(const hsdc_ctx *c, int lev) {
   if (lev == 0) return c->meth.cg_rtol;
   if (c->meth.coarse_cg_rtol > 0) return c->meth.coarse_cg_rtol;
   return c->cf32 ? 1e-5 : c->meth.cg_rtol;
+}
+
+// Spare launches of a budget: the tuned margin, or by default none after the
+// tiled start (whose solves have needed no CG iteration) and one otherwise.
+int cg_margin(const hsdc_ctx *c, bool tiled) {
+  return c->tune_cg_margin >= 0 ? c->tune_cg_margin : (tiled ? 0 : 1);
 }
 
 int (&pred_table(hsdc_ctx *c, int lev))[16][MAXM] {
@@ -459,6 +467,32 @@ void build_faces(hsdc_ctx *c, LevelT<T> &L, const double *sigma_node_dev) {
   L.g.kz = g.dim >= 3 ? L.kface[2] : nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// diffusion solve for node i of a sweep, slices [s0, s0+ns)
+// ---------------------------------------------------------------------------
+// Degree of the Chebyshev start of CG (solver 0): each step shrinks the
+// residual bound by about 2 sigma (sigma = 1 + 2 / (a lam), 4 to 100 on these
+// workloads) for one stencil launch without inner products, cheaper than a CG
+// iteration.
+constexpr int kChebStartDegree = 3;
+// On 2D meshes the whole start is one tiled launch, where a step costs far less
+// than a launch: more steps, fewer CG iterations.
+// Degree 7: on the 512 x 512 slab no solve needed a CG iteration after it in
+// 400 steps (degree 5: 0.1 iterations per solve, degree 6: 0.001), at 14 us
+// per launch against 12 us for degree 5; its solves then get no CG launch.
+constexpr int kChebStartDegreeTiled = 7;
+
+// Tiles per slice of the one-launch CG start on level L (0: none): FP64 levels
+// whose solver starts CG from Chebyshev steps, on 2D meshes (a ragged batch:
+// the most tiles of any tissue).
+template <class T>
+int level_start_tiles(const hsdc_ctx *c, const LevelT<T> &L) {
+  if (!std::is_same<T, double>::value || c->meth.solver != 0) return 0;
+  const int tiles = L.g.rag ? (L.g.dim == 2 ? c->batch_start_tiles : 0)
+                            : cg_start_tiles(L.g, kChebStartDegreeTiled);
+  return (tiles > 0 && tiles <= L.cg_pstride) ? tiles : 0;
+}
+
 template <class T>
 void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, int Mc_for_RI) {
   const int64_t Np = L.g.Np;
@@ -484,7 +518,9 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   if (L.g.dim == 2)
     L.cg_pstride = std::max<int64_t>(
         L.cg_pstride, std::max(cg_start_tiles_of(L.g.nx, L.g.ny), c->batch_start_tiles));
-  L.cg_part = dalloc<double>(c, (size_t)P * 5 * L.cg_pstride);
+  // two sets, by the parity of the collocation node: a node update writes its
+  // solve's set while the previous solve's set is still read (its log entry)
+  L.cg_part = dalloc<double>(c, (size_t)2 * P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
   if (std::is_same<T, double>::value && (c->meth.solver == 0 || c->meth.solver == 1)) {
@@ -505,23 +541,14 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
     L.Sz = dalloc<double>(c, (size_t)P * L.st.sY());
     L.y0c = dalloc<double>(c, (size_t)NF * Np);
   }
+  // first budgets: two launches after the tiled start (its solves have needed
+  // none), eight otherwise; the predictor adjusts them from the first steps on
+  L.tiled_start = level_start_tiles(c, L) > 0;
   for (auto &row : L.cg_pred)
-    for (int &v : row) v = 8;
+    for (int &v : row) v = L.tiled_start ? 2 : 8;
   for (auto &row : L.cg_umax)
     for (int &v : row) v = -1;
 }
-
-// ---------------------------------------------------------------------------
-// diffusion solve for node i of a sweep, slices [s0, s0+ns)
-// ---------------------------------------------------------------------------
-// Degree of the Chebyshev start of CG (solver 0): each step shrinks the
-// residual bound by about 2 sigma (sigma = 1 + 2 / (a lam), 4 to 100 on these
-// workloads) for one stencil launch without inner products, cheaper than a CG
-// iteration.
-constexpr int kChebStartDegree = 3;
-// On 2D meshes the whole start is one tiled launch, where a step costs far less
-// than a launch: more steps, fewer CG iterations.
-constexpr int kChebStartDegreeTiled = 5;
 
 template <class T>
 CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i) {
@@ -538,7 +565,7 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
   }
   cb.p = L.cg_p + s0 * Np;
   cb.pstride = L.cg_pstride;
-  cb.part = L.cg_part + (int64_t)s0 * 5 * L.cg_pstride;
+  cb.part = L.cg_part + ((int64_t)(i & 1) * L.P + s0) * 5 * L.cg_pstride;
   cb.sc = L.cg_sc + 2 * s0;
   cb.log = nullptr;
   cb.last_k = -1;
@@ -560,6 +587,14 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
     cb.tab = L.cheb_tab + (i - 1);
     cb.tab_stride = L.co.M;
     cb.cstart = c->meth.solver == 0 ? kChebStartDegree : 0;
+    // on 2D meshes the whole start is one tiled launch; the node update then
+    // also stores x_0 in p for it
+    const int tiles = level_start_tiles(c, L);
+    if (tiles > 0) {
+      cb.cstart = kChebStartDegreeTiled;
+      cb.nblk_s = tiles;
+      cb.x0_to_p = 1;
+    }
   }
   return cb;
 }
@@ -574,14 +609,13 @@ bool cg_ok(const CgScalars &sc, double tol2) {
 // was given is not finite (no further iteration or recomputation helps).
 bool cg_nonfinite(const CgScalars &sc) { return !std::isfinite(sc.gamma) || !std::isfinite(sc.bb); }
 
-// Launches a solve needed, minus one, as the budget predictor counts them: CG
-// ends with the launch that finds convergence (it + 1 launches).  Chebyshev's
-// launch k forms x_{k+1} and the node update x_1, so an even count m takes
-// max(1, m - 1) launches; since m moves in steps of 2 it is counted as m (one
-// spare launch more than CG).
-int budget_use(const CgScalars &sc, bool cheb) {
-  return cheb ? std::max(0, sc.it - 1) : sc.it;
-}
+// Launches a solve needed, as the budget predictor counts them (the budget is
+// this plus the margin): CG needs one launch per iteration (convergence is
+// checked by the kernel that writes the log entry).  Chebyshev's launch k
+// forms x_{k+1} and the node update x_1, so an even count m takes max(1, m -
+// 1) launches; since m moves in steps of 2 it is counted as m (one spare launch
+// more than CG).
+int budget_use(const CgScalars &sc, bool cheb) { return sc.it; }
 
 // Check every budgeted solve enqueued since the last check (one host
 // synchronisation); slices whose solve missed cg_rtol are added to cg_fails.
@@ -605,19 +639,20 @@ void flush_cg_log(hsdc_ctx *c) {
       c->stats.cg_solves += 1;
       if (!ok) ++fails;
     }
-    // budget = iterations needed + 2, lowered by at most one per check; doubled
-    // after a miss (a spare no-op iteration costs far less than a recomputed step)
+    // budget = launches needed + margin, lowered by at most one per check;
+    // doubled after a miss (a spare no-op launch costs far less than a
+    // recomputed step)
     int &pred = pred_table(c, e.lev)[e.row & 15][e.i - 1];
     if (!ok_all)
       pred = std::min(c->meth.cg_maxit + 1, std::max(2 * e.budget, used + 4));
     else if (c->graph_on && !c->prof.on && e.lev == 0) {
       // graph replay (profiled steps run eagerly): raise at once, lower only at
       // a relaxation (every 16 steps)
-      pred = std::max(pred, used + c->tune_cg_margin);
+      pred = std::max(pred, used + e.margin);
       int &um = c->L[0].cg_umax[e.row & 15][e.i - 1];
       um = std::max(um, used);
     } else
-      pred = std::max(used + c->tune_cg_margin, pred - 1);
+      pred = std::max(used + e.margin, pred - 1);
   }
   c->cg_pending.clear();
   c->cg_log_used = 0;
@@ -640,7 +675,8 @@ void cheb_solve(hsdc_ctx *c, Level &L, int lev, int s0, int ns, int i, int pred_
     ProfScope ps(c, PC_CHEB, 32.0 * nodes * budget);
     for (int k = 1; k <= budget; ++k) HIPC(launch_cheb_iter(c->s, L.g, cb, k));
     ps.end(budget);
-    c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget, true});
+    c->cg_pending.push_back(
+        CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget, true, cg_margin(c, false)});
     c->cg_log_used += ns;
     return;
   }
@@ -669,30 +705,31 @@ void cheb_solve(hsdc_ctx *c, Level &L, int lev, int s0, int ns, int i, int pred_
     if (!cg_ok(sc, cb.tol2)) c->stats.cg_unconverged += 1;
     if (cg_nonfinite(sc)) c->nonfinite = true;
   }
-  pred = std::max(used + 2, pred - 1);
+  pred = std::max(used + cg_margin(c, false), pred - 1);
 }
 
+// Diffusion solve of node i whose node update has run (cb: that update's batch).
+// In budgeted mode the solve gets the predicted number of CG launches (none
+// when the start is predicted to meet the tolerance) and is checked by a
+// later kernel: the returned arguments name its log entry, to be passed to the
+// next node update of the same slices or to launch_cg_log.  Otherwise (safe
+// mode, Chebyshev) nothing is left to log.
 template <class T>
-void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pred_row) {
-  CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
+CgLogArgs cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pred_row,
+                   CgBatchT<T> cb) {
   const double nodes = slice_nodes(c, L, s0, ns);
+  CgLogArgs lg{};
   // first CG launch index: 1 after a Chebyshev start (its vectors have parity 1)
   int k0 = 0;
   if constexpr (std::is_same<T, double>::value) {
     if (cb.xt && !cb.cstart) {
       cheb_solve(c, L, lev, s0, ns, i, pred_row, cb);
-      return;
+      return lg;
     }
     if (cb.cstart) {
-      // tiles per slice: the mesh's, or for a ragged 2D batch the most of any tissue
-      const int tiles = L.g.rag ? (L.g.dim == 2 ? c->batch_start_tiles : 0)
-                                : cg_start_tiles(L.g, kChebStartDegreeTiled);
-      if (tiles > 0 && tiles <= L.cg_pstride) {
-        // one launch: x_1, x_0, b read (with the tiles' halos), x_D to p, r_D, w_D
-        cb.cstart = kChebStartDegreeTiled;
-        cb.nblk_s = tiles;
-        cb.xin_p = 1;
-        PLAUNCH(c, PC_CGINIT, 48.0 * nodes, launch_cg_start_tiled(c->s, L.g, cb, tiles));
+      if (cb.x0_to_p) {
+        // one launch: x_1, x_0, b read (with the tiles' halos), x_D, r_D, w_D written
+        PLAUNCH(c, PC_CGINIT, 48.0 * nodes, launch_cg_start_tiled(c->s, L.g, cb, cb.nblk_s));
       } else {
         // x_2 .. x_D (x_k, x_{k-1}, b read, x_{k+1} written); r_D and w_D (x_D
         // and b read, r, w and for D odd x written)
@@ -708,15 +745,30 @@ void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pre
   int &pred = L.cg_pred[pred_row & 15][i - 1];
   if (!c->safe_cg) {
     if (c->cg_log_used + ns > c->cg_log_cap) flush_cg_log(c);  // log full: verify now
-    const int budget = std::max(1, std::min(pred, cb.maxit + 1));
-    cb.log = c->cg_dlog + c->cg_log_used;
-    cb.last_k = budget - 1 + k0;
-    ProfScope ps(c, PC_CGITER, 0.0);
-    for (int k = k0; k < budget + k0; ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
-    ps.end(budget);
-    c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget, false});
+    // budget = CG launches, each one iteration unless it finds convergence
+    const int budget = std::max(0, std::min(pred, cb.maxit + 1));
+    if (budget > 0) {
+      ProfScope ps(c, PC_CGITER, 0.0);
+      for (int k = k0; k < budget + k0; ++k) HIPC(launch_cg_iter(c->s, L.g, cb, k));
+      ps.end(budget);
+    }
+    lg.part = cb.part;
+    lg.pstride = cb.pstride;
+    lg.sc = cb.sc;
+    lg.log = c->cg_dlog + c->cg_log_used;
+    lg.par = (k0 + budget) & 1;  // the last launch k0 + budget - 1 publishes parity (k + 1) & 1
+    // the final residual's partials: a CG launch's, the start's, or (plain CG,
+    // no launch) the node update's ||r_0||^2
+    lg.ngamma = budget > 0 ? -1 : (k0 == 1 ? cb.nblk_s : cb.nblk0);
+    lg.cg_nblk = cb.nblk;
+    lg.nbb = cb.nblk0;
+    lg.slice0 = s0;
+    lg.tol2 = cb.tol2;
+    lg.rel_r0 = cb.rel_r0;
+    c->cg_pending.push_back(CgLogEntry{lev, s0, ns, i, pred_row, 0, c->cg_log_used, budget, false,
+                                       cg_margin(c, cb.x0_to_p)});
     c->cg_log_used += ns;
-    return;
+    return lg;
   }
   // safe mode: iterate until every slice has converged, checking on the host
   const double tol2 = cb.tol2;
@@ -745,7 +797,8 @@ void cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, int pre
     if (!cg_ok(sc, tol2)) c->stats.cg_unconverged += 1;
     if (cg_nonfinite(sc)) c->nonfinite = true;
   }
-  pred = std::max(used + 2, pred - 1);
+  pred = std::max(used + cg_margin(c, cb.x0_to_p), pred - 1);
+  return lg;
 }
 
 // Reaction terms, Lambda(y_{n,0}) and K V of every stage of slices [s0, s0+ns).
@@ -800,19 +853,22 @@ void sweep(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, const double *u_s
     PLAUNCH(c, PC_ASSEMBLE, 8.0 * per * N * ns,
             launch_assemble(c->s, L.g, L.st, co, s0, ns, RI, sRI, spread, c->stim[lev]));
   }
+  CgLogArgs pending{};  // the previous budgeted solve, logged by the next node update
   for (int i = 1; i <= M; ++i) {
     const CgBatchT<T> cb = make_batch(c, L, lev, s0, ns, i);
     // doubles per node: stage i-1, RH_i, Lambda_n, x_0 and K x_0 read; stage i
     // (but V), b, x_1 and (unless dropped) the reaction terms of stage i-1
     // written; node 1 reads the stored reaction terms of stage 0 instead
-    const double per = ((i == 1) ? 90.0 : (drop_terms ? 71.0 : 90.0)) * sizeof(T) / 8.0;
+    const double per = ((i == 1) ? 90.0 : (drop_terms ? 71.0 : 90.0)) * sizeof(T) / 8.0 +
+                       (cb.x0_to_p ? 1.0 : 0.0);
     PLAUNCH(c, PC_NODE, 8.0 * per * N * ns,
             launch_node_update(c->s, L.g, L.st, co, c->stim[lev], p.g_scale[0], p.g_scale[1],
                                p.g_scale[2], s0, ns, i, cb, drop_terms ? 0 : 1, spread,
-                               std::is_same<T, double>::value ? nullptr : yref));
+                               std::is_same<T, double>::value ? nullptr : yref, pending));
     if (i > 1) c->stats.ionic_evals += (int64_t)(N * ns);
-    cg_solve(c, L, lev, s0, ns, i, pred_row);
+    pending = cg_solve(c, L, lev, s0, ns, i, pred_row, cb);
   }
+  if (pending.log) PLAUNCH(c, PC_CGITER, 0.0, launch_cg_log(c->s, L.g, pending, ns));
   if (lev == 0) c->spread_pending = false;
   if (!drop_terms) {
     // reaction terms and K V of the new iterate's last stage, for the next
@@ -1110,7 +1166,7 @@ void graph_step(hsdc_ctx *c) {
     for (int r = 0; r < 16; ++r)
       for (int i = 0; i < MAXM; ++i)
         if (F.cg_umax[r][i] >= 0) {
-          F.cg_pred[r][i] = F.cg_umax[r][i] + c->tune_cg_margin;
+          F.cg_pred[r][i] = F.cg_umax[r][i] + cg_margin(c, F.tiled_start);
           F.cg_umax[r][i] = -1;
         }
   }
@@ -1383,7 +1439,7 @@ hsdc_status hsdc_tune(hsdc_ctx *c, int32_t cg_blocks_cap, int32_t cg_margin) {
         c->L[l].cg_nblk = cg_blocks(c->L[l].g, cg_blocks_cap);
     }
   }
-  if (cg_margin > 0) c->tune_cg_margin = cg_margin;
+  if (cg_margin >= 0) c->tune_cg_margin = cg_margin;
   return HSDC_OK;
 }
 

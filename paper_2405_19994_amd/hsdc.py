@@ -201,8 +201,9 @@ class Context:
             raise HsdcError(-6, "context destroyed")
         return self._ctx
 
-    def tune(self, cg_blocks=0, cg_margin=0):
-        """CG block cap and budget margin for the following solves (0 keeps)."""
+    def tune(self, cg_blocks=0, cg_margin=-1):
+        """CG block cap (0 keeps) and budget margin (negative keeps) for the
+        following solves."""
         _check(lib().hsdc_tune(self.handle, int(cg_blocks), int(cg_margin)), self.handle)
 
     def use_graph(self, on=True):

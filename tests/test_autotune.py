@@ -33,10 +33,11 @@ def test_tuner_picks_fastest_and_caches(tmp_path, monkeypatch):
     m = H.make_method(M=6, max_iter=6)
     key = autotune.shape_key(p, m)
     best, timings = autotune.tune(_FakeContext, key, sync=lambda: None)
-    assert best == {"cg_blocks": 256, "cg_margin": 1}
+    assert best == {"cg_blocks": 256, "cg_margin": -1}
     # within the noise margin of the default, the default is kept
-    _FakeContext.cost[(512, 2)] = 0.99 * _FakeContext.cost[(256, 1)]
-    _FakeContext.cost[(256, 1)] = 0.985 * _FakeContext.cost[(512, 2)]
+    d = (autotune.DEFAULT["cg_blocks"], autotune.DEFAULT["cg_margin"])
+    _FakeContext.cost[d] = 0.99 * _FakeContext.cost[(256, -1)]
+    _FakeContext.cost[(256, -1)] = 0.985 * _FakeContext.cost[d]
     kept, _ = autotune.tune(_FakeContext, key + "b", sync=lambda: None, use_cache=False)
     assert kept == autotune.DEFAULT
     assert len(timings) == len(autotune.CG_BLOCKS) * len(autotune.CG_MARGINS)
@@ -44,7 +45,7 @@ def test_tuner_picks_fastest_and_caches(tmp_path, monkeypatch):
     again, t2 = autotune.tune(_FakeContext, key, sync=lambda: None)
     assert again == best and t2 is None
     ctx = _FakeContext()
-    assert autotune.apply(ctx, key) == best and ctx.setting == (256, 1)
+    assert autotune.apply(ctx, key) == best and ctx.setting == (256, -1)
     # another shape has its own entry (defaults until tuned)
     other = autotune.shape_key(H.make_problem((64, 50), 0.025), m)
     assert other != key and autotune.lookup(other) is None

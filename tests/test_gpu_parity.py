@@ -205,7 +205,7 @@ def test_plain_cg_serial_parity(case):
 
 @pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])
 def test_solver_iteration_cap_reports_enoconv(solver):
-    """A solve that cannot reach cg_rtol within cg_maxit (2 iterations to 1e-14,
+    """A solve that cannot reach cg_rtol within cg_maxit (2 iterations to 1e-16,
     through the stimulus) ends in HSDC_ENOCONV after the step, counted in
     cg_unconverged, with the state advanced and finite.  The status describes
     the call that returns it: with a uniform state after the stimulus (a
@@ -213,7 +213,7 @@ def test_solver_iteration_cap_reports_enoconv(solver):
     returns OK."""
     w = dict(si.workload("slab2d", dims=(31, 23)))
     w["stim_dur"] = 0.15  # the first three steps
-    ctx = H.Context(lib_problem(w), H.make_method(M=(4, 1), dt=w["dt"], max_iter=2, cg_rtol=1e-14,
+    ctx = H.Context(lib_problem(w), H.make_method(M=(4, 1), dt=w["dt"], max_iter=2, cg_rtol=1e-16,
                                                   cg_maxit=2, solver=solver))
     with pytest.raises(H.HsdcError) as e:
         ctx.advance(3)
