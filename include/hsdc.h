@@ -264,7 +264,9 @@ hsdc_status hsdc_ionic_eval(int64_t n, const double *y, const double *g_scale_ho
 /* phi_k(x) for k = 1..kmax (Appendix A, eq. def_phik): out device [kmax][n]. */
 hsdc_status hsdc_phi(int64_t n, const double *x, int32_t kmax, double *out, void *hip_stream);
 
-/* out = (chi Cm)^-1 A v for the operator of *prob (device [N] each). */
+/* out = (chi Cm)^-1 A v for the operator of *prob (device [N] each), enqueued
+ * on hip_stream; the call returns at once for a uniform sigma and after the
+ * kernel when it built (and frees) the face coefficients of sigma_node. */
 hsdc_status hsdc_apply_diffusion(const hsdc_problem *prob, const double *v, double *out,
                                  void *hip_stream);
 

@@ -15,17 +15,45 @@ constexpr int GATE0 = 7;  // first gate field
 constexpr int MAXM = HSDC_MAX_M;
 constexpr int BLOCK = 512;
 
+// Division of a 32-bit unsigned value by a divisor d fixed per mesh, as a
+// multiply-high, a subtraction and two shifts (Granlund and Montgomery,
+// division by invariant integers using multiplication, 1994):
+//   n / d = (t + ((n - t) >> s1)) >> s2,  t = hi32(m n),  l = ceil(log2 d),
+//   m = floor(2^32 (2^l - d) / d) + 1,  s1 = min(l, 1),  s2 = max(l - 1, 0),
+// exact for every n < 2^32.  Node indices are below 2^31, so the mesh
+// coordinates of a node cost a few instructions instead of 64-bit divisions.
+struct FastDiv {
+  uint32_t m;
+  int32_t s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  FastDiv f;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  f.s1 = l < 1 ? l : 1;
+  f.s2 = l > 1 ? l - 1 : 0;
+  return f;
+}
+__host__ __device__ inline uint32_t fastdiv(uint32_t n, FastDiv f) {
+  const uint32_t t = (uint32_t)(((uint64_t)f.m * n) >> 32);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 // Mesh and diffusion operator K = (chi Cm)^-1 A (cell-centred, no-flux).
 // A ragged batch of independent tissues (one per slice) sets rag: slice n then
-// has the dimensions rag[3n..3n+2] (N <= Np), and its face coefficients start
+// has the dimensions rag[RAG * n + 0..2] (N <= Np) and the divisors of nx and
+// ny at rag[RAG * n + 3..8] (m, s1, s2 each), and its face coefficients start
 // at kx + n Np (likewise ky, kz).
+constexpr int RAG = 9;
 struct Grid {
   int dim, nx, ny, nz;
+  FastDiv fx, fy;  // division by nx and by ny
   int64_t N;    // nodes (largest tissue of a batch)
   int64_t Np;   // padded row length (multiple of 64 doubles)
   double cx, cy, cz;           // sigma_axis / (dx^2 chi Cm) for uniform sigma
   const double *kx, *ky, *kz;  // per-node face coefficients (face p -> p+e_axis), or null
-  const int32_t *rag;          // device [P][3] tissue dimensions, or null
+  const int32_t *rag;          // device [P][RAG] tissue dimensions and divisors, or null
 };
 
 // Collocation data of one level (host-computed in FP64, passed by value).

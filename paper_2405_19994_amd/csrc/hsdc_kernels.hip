@@ -269,10 +269,12 @@ struct Ijk {
 };
 __device__ __forceinline__ Ijk ijk(const Grid &g, int64_t p) {
   Ijk r;
-  r.ix = (int)(p % g.nx);
-  const int64_t q = p / g.nx;
-  r.iy = (int)(q % g.ny);
-  r.iz = (int)(q / g.ny);
+  const uint32_t pu = (uint32_t)p;  // node indices are below 2^31
+  const uint32_t q = fastdiv(pu, g.fx);
+  r.ix = (int)(pu - q * (uint32_t)g.nx);
+  const uint32_t q2 = fastdiv(q, g.fy);
+  r.iy = (int)(q - q2 * (uint32_t)g.ny);
+  r.iz = (int)q2;
   return r;
 }
 
@@ -280,9 +282,12 @@ __device__ __forceinline__ Ijk ijk(const Grid &g, int64_t p) {
 __device__ __forceinline__ Grid slice_grid(const Grid &g, int n) {
   if (g.rag == nullptr) return g;
   Grid r = g;
-  r.nx = g.rag[3 * n];
-  r.ny = g.rag[3 * n + 1];
-  r.nz = g.rag[3 * n + 2];
+  const int32_t *d = g.rag + RAG * n;
+  r.nx = d[0];
+  r.ny = d[1];
+  r.nz = d[2];
+  r.fx = FastDiv{(uint32_t)d[3], d[4], d[5]};
+  r.fy = FastDiv{(uint32_t)d[6], d[7], d[8]};
   r.N = (int64_t)r.nx * r.ny * r.nz;
   if (g.kx) r.kx = g.kx + n * g.Np;
   if (g.ky) r.ky = g.ky + n * g.Np;
@@ -1432,17 +1437,67 @@ hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb) {
   return hipGetLastError();
 }
 
+// out = K v, one node per thread in XCD block order (a neighbour row is then
+// read by a block of the same XCD, from its L2), as k_spmv_stages.
 template <int DIM, bool PN>
 __global__ void __launch_bounds__(BLOCK) k_apply_K(Grid g, const double *v, double *out) {
-  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t p = stencil_node_block(g, blockIdx.x, gridDim.x) * BLOCK + threadIdx.x;
   if (p >= g.N) return;
   const Ijk c = ijk(g, p);
   out[p] = applyK<DIM, PN>(g, p, c, v[p], [&](int64_t k) { return v[k]; });
 }
 
+// out = K v on a 2D mesh with uniform sigma, streamed along y: a thread owns
+// two neighbouring nodes of a row (16-byte loads and stores) and walks SY
+// rows, keeping the rows below and above its own in registers, so v is read
+// from memory about once (plus one row per SY); the x neighbours come from
+// the adjacent lanes by shuffles, the wave's edge lanes read them from memory.
+// A neighbour missing at the wall is the node itself (its term is exactly 0),
+// and the sums are grouped as applyK groups them, so the result is the same.
+// Lanes past the mesh (nx not a multiple of the block's width) load the last
+// pair and store nothing.  nx must be even and v, out 16-byte aligned.
+typedef double d2v __attribute__((ext_vector_type(2)));
+constexpr int SPX = 256, SY = 16;
+__global__ void __launch_bounds__(SPX) k_apply_K2d(Grid g, const double *v, double *out) {
+  const int nx = g.nx, ny = g.ny;
+  const int ix = 2 * (blockIdx.x * SPX + threadIdx.x);
+  const bool own = ix < nx;
+  const int ixc = own ? ix : nx - 2;
+  const int lane = threadIdx.x & 63;
+  const int y0 = blockIdx.y * SY;
+  const d2v *v2 = (const d2v *)v;
+  d2v *o2 = (d2v *)out;
+  const int64_t hr = nx / 2;  // a row in pairs
+  int64_t q = ((int64_t)y0 * nx + ixc) >> 1;
+  d2v cur = v2[q];
+  d2v below = y0 > 0 ? v2[q - hr] : cur;
+  for (int k = 0; k < SY; ++k, q += hr) {
+    const int iy = y0 + k;
+    if (iy >= ny) break;  // uniform over the block
+    const d2v above = iy < ny - 1 ? v2[q + hr] : cur;
+    double l = __shfl_up(cur.y, 1), r = __shfl_down(cur.x, 1);
+    if (lane == 0) l = ixc > 0 ? v[2 * q - 1] : cur.x;
+    if (lane == 63 || ixc + 2 >= nx) r = ixc + 2 < nx ? v[2 * q + 2] : cur.y;
+    if (ixc == 0) l = cur.x;
+    double acc0 = g.cx * ((l - cur.x) + (cur.y - cur.x));
+    double acc1 = g.cx * ((cur.x - cur.y) + (r - cur.y));
+    acc0 += g.cy * ((below.x - cur.x) + (above.x - cur.x));
+    acc1 += g.cy * ((below.y - cur.y) + (above.y - cur.y));
+    if (own) __builtin_nontemporal_store(d2v{acc0, acc1}, &o2[q]);
+    below = cur;
+    cur = above;
+  }
+}
+
 hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out) {
-  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_apply_K<DIM, PN>), dim3(nblocks(g.N)), dim3(BLOCK), 0,
-                                         s, g, v, out));
+  const bool aligned = (((uintptr_t)v | (uintptr_t)out) & 15) == 0;  // 16-byte accesses
+  if (g.dim == 2 && g.kx == nullptr && g.nx % 2 == 0 && g.nx >= 2 && aligned) {
+    const dim3 grid((g.nx / 2 + SPX - 1) / SPX, (g.ny + SY - 1) / SY);
+    hipLaunchKernelGGL(k_apply_K2d, grid, dim3(SPX), 0, s, g, v, out);
+    return hipGetLastError();
+  }
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_apply_K<DIM, PN>), dim3(nblocks_xcd(g.N)), dim3(BLOCK),
+                                         0, s, g, v, out));
   return hipGetLastError();
 }
 

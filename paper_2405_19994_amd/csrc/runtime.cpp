@@ -139,7 +139,7 @@ struct hsdc_ctx {
   // ragged batch of independent tissues (one per slice of a serial context)
   bool batch = false;
   std::vector<int64_t> tissue_N;  // nodes per slice (batch)
-  int32_t *rag = nullptr;         // device [P][3] tissue dimensions
+  int32_t *rag = nullptr;         // device [P][RAG] tissue dimensions and divisors
   int batch_start_tiles = 0;      // most CG-start tiles of any tissue (2D batch)
   int nlev = 1;
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
@@ -367,6 +367,8 @@ Grid make_grid(const hsdc_problem &p, int nx, int ny, int nz, double dx) {
   g.nz = nz;
   g.N = (int64_t)nx * ny * nz;
   g.Np = pad64(g.N);
+  g.fx = make_fastdiv((uint32_t)nx);
+  g.fy = make_fastdiv((uint32_t)ny);
   const double s = 1.0 / (dx * dx * p.chi * p.Cm);
   g.cx = p.sigma[0] * s;
   g.cy = p.sigma[1] * s;
@@ -1335,13 +1337,14 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
   hsdc_status st = run_guarded(c, [&]() -> hsdc_status {
     Level &F = c->L[0];
     int big = 0;
-    std::vector<int32_t> dims(3 * count);
+    std::vector<int32_t> dims(RAG * count);
     for (int n = 0; n < count; ++n) {
       const hsdc_problem &q = probs[n];
       c->tissue_N.push_back((int64_t)q.nx * q.ny * q.nz);
-      dims[3 * n] = q.nx;
-      dims[3 * n + 1] = q.ny;
-      dims[3 * n + 2] = q.nz;
+      const FastDiv fx = make_fastdiv((uint32_t)q.nx), fy = make_fastdiv((uint32_t)q.ny);
+      const int32_t row[RAG] = {q.nx, q.ny, q.nz, (int32_t)fx.m, fx.s1, fx.s2,
+                                (int32_t)fy.m, fy.s1, fy.s2};
+      for (int k = 0; k < RAG; ++k) dims[RAG * n + k] = row[k];
       if (c->tissue_N[n] > c->tissue_N[big]) big = n;
     }
     // rows padded to the largest tissue; slice n holds tissue n
@@ -1718,7 +1721,8 @@ hsdc_status hsdc_apply_diffusion(const hsdc_problem *prob, const double *v, doub
     L.g = make_grid(*prob, prob->nx, prob->ny, prob->nz, prob->dx);
     if (prob->sigma_node) build_faces(&tmp, L, prob->sigma_node);
     HIPC(launch_apply_K(tmp.s, L.g, v, out));
-    HIPC(hipStreamSynchronize(tmp.s));
+    // the face coefficients of sigma_node are freed below, after the kernel
+    if (!tmp.allocs.empty()) HIPC(hipStreamSynchronize(tmp.s));
     return HSDC_OK;
   });
   for (void *p : tmp.allocs) hipFree(p);

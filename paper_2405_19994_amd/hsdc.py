@@ -343,8 +343,10 @@ def phi(x, kmax, stream=None):
     return out
 
 
-def apply_diffusion(problem, v, stream=None):
-    out = torch.empty_like(v)
+def apply_diffusion(problem, v, stream=None, out=None):
+    """K v on the stream (asynchronous for a uniform sigma)."""
+    if out is None:
+        out = torch.empty_like(v)
     _check(lib().hsdc_apply_diffusion(ctypes.byref(problem), _dev(v, "v", (problem.N,)),
                                       _dev(out, "out"), _stream(stream)))
     return out
