@@ -187,7 +187,7 @@ def _traffic(kernel, path="hbm_traffic_slab2d.json"):
 # diffusion right-hand side), counted with rocprofv3 instruction counters on
 # the 512 x 512 slab: 64 lanes x (2 FMA + ADD + MUL + transcendental) per wave
 # instruction, per node.
-FLOP_PER_NODE_UPDATE = 2401.0
+FLOP_PER_NODE_UPDATE = 2391.0
 # the minimum HBM traffic of a node update: read one stage, write one stage
 FLOOR_BYTES_PER_NODE_UPDATE = 2 * 19 * 8.0
 
