@@ -292,6 +292,39 @@ hsdc_status hsdc_diffusion_solve_noalloc(const hsdc_problem *prob, double a, con
                                          double *x, double rtol, int32_t maxit,
                                          int32_t *iters_host, void *hip_stream);
 
+/* ---- discrete adjoint of serial hybrid SDC ------------------------------ */
+
+/* The gradient of a probe-voltage misfit through nsteps steps of serial hybrid
+ * SDC (Sec. 3.1.3: K = max_iter sweeps of eq. prec_picard with the
+ * preconditioner of eq. def_P, exponential collocation of eq. def_C):
+ *   L = sum_{s=1..S} sum_{q} (V(probes[q], t = s sample_every dt) - targets[s-1][q])^2,
+ * S = nsteps / sample_every, with respect to the per-node conductivity field
+ * (problem with sigma_node), the G_Na, G_CaL, G_Kr scalings and the initial
+ * state.  The gradient is the exact derivative of the discrete forward map
+ * (solves taken as exact: use cg_rtol of 1e-13 or below): the forward keeps
+ * y_n before every step, the backward recomputes each step from it and runs
+ * the transposed sweep (the cell model's Jacobian by forward-mode dual
+ * numbers, the symmetric diffusion solves, the derivatives of a_ij(z) and of
+ * phi_1 through phi_k' = phi_k - k phi_{k+1}).
+ * hsdc_misfit_forward: meth serial (levels = 1, P = 1) with M <= 6; probes
+ * device [nprobes] distinct node indices; targets device [S][nprobes] (copied);
+ * *loss_host receives L; *out an opaque handle holding the checkpoints
+ * (19 N 8 bytes per step and the final state) and the context (released by
+ * hsdc_adj_destroy).
+ * Errors as hsdc_init_state and hsdc_advance. */
+typedef struct hsdc_adj hsdc_adj;
+hsdc_status hsdc_misfit_forward(const hsdc_problem *prob, const hsdc_method *meth, const double *y0,
+                                int32_t nsteps, int32_t sample_every, int32_t nprobes,
+                                const int64_t *probes, const double *targets, double *loss_host,
+                                hsdc_adj **out, void *hip_stream);
+/* dL/dsigma_node (device [N], or NULL; needs sigma_node), dL/dg_scale (host
+ * [3], or NULL) and dL/dy0 (device [19][N], or NULL) of the forward run held by
+ * adj.  May be called more than once.  HSDC_ENOCONV when an adjoint solve
+ * reaches cg_maxit. */
+hsdc_status hsdc_misfit_backward(hsdc_adj *adj, double *grad_sigma, double *grad_gscale_host,
+                                 double *grad_y0);
+void hsdc_adj_destroy(hsdc_adj *adj);
+
 /* Exponential collocation coefficients a_ij(z) (eq. def_aij), computed on the
  * device as sum_k c_i^k w_j^{k-1} phi_k(c_i z) (eq. def_aij_computable) with
  * the Radau IIA nodes and Fornberg weights of the library: z device [n],

@@ -1,0 +1,460 @@
+// hsdc_adjoint.hip -- kernels of the discrete adjoint of a serial hybrid SDC
+// step (the transposed sweep of eqs. prec_picard, def_P and def_C), for the
+// gradient of a probe-voltage misfit with respect to the per-node
+// conductivity field and the G_Na, G_CaL, G_Kr scalings.
+//
+// One step of the forward map, in the node-to-node form the library computes
+// (anchor u = y_n, Lambda_n = Lambda(u), z = dt Lambda_n, the previous
+// iterate X = (u, X_1..X_M), the new one Z = (u, Z_1..Z_M)):
+//   g_j   = G(X_j) + e_V K X_j^V,            G the reaction terms (anchor u)
+//   p_i   = dt d_i (e_V K X_i^V + Gh_i(X_{i-1})),  Gh_i = G with its gate rows
+//           times phi_1(d_i z)
+//   RH_i  = dt sum_j (a_ij - a_{i-1,j}) g_j - p_i    (a = Q on rows V .. Rbar,
+//           a(z) on the gate rows)
+//   b_i   = Z_{i-1} + RH_i + dt d_i Gh_i(Z_{i-1}),  Z_i = b_i but
+//           Z_i^V = (I - dt d_i K)^-1 b_i^V.
+// The adjoint runs these backwards: the node-local parts here (the cell
+// model's Jacobian applied transposed, by forward-mode dual numbers), the
+// symmetric solves and stencil products with the library's operator, and the
+// derivative of a_ij(z) and phi_1 through phi_k' = phi_k - k phi_{k+1}.
+#include <hip/hip_runtime.h>
+
+#include "hsdc_device.h"
+#include "hsdc_internal.h"
+#include "ttp06_device.h"
+
+namespace hsdc {
+namespace ad {
+
+// Forward-mode dual number: a value and one directional derivative.
+struct D {
+  double v, d;
+  __device__ D() : v(0.0), d(0.0) {}
+  __device__ D(double x) : v(x), d(0.0) {}
+  __device__ D(double x, double dx) : v(x), d(dx) {}
+};
+__device__ __forceinline__ D operator+(D a, D b) { return D(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ D operator-(D a, D b) { return D(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ D operator-(D a) { return D(-a.v, -a.d); }
+__device__ __forceinline__ D operator*(D a, D b) { return D(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ D operator/(D a, D b) {
+  const double q = a.v / b.v;
+  return D(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ bool operator<(D a, D b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator==(D a, D b) { return a.v == b.v; }
+__device__ __forceinline__ D exp(D a) {
+  const double e = ::exp(a.v);
+  return D(e, e * a.d);
+}
+__device__ __forceinline__ D expm1(D a) { return D(::expm1(a.v), ::exp(a.v) * a.d); }
+__device__ __forceinline__ D log(D a) { return D(::log(a.v), a.d / a.v); }
+__device__ __forceinline__ D sqrt(D a) {
+  const double r = ::sqrt(a.v);
+  return D(r, 0.5 * a.d / r);
+}
+
+}  // namespace ad
+
+// Transposed Jacobian of the reaction terms at one node state x, anchor values
+// ug and rates lam_n of the gates (eqs. def_f_IE, def_Lambda; the gates'
+// anchor part Lambda_n (u - x)):
+//   G_V = (I_stim - Cm I_ion(x)) / Cm,  G_aux = h_a(x),
+//   G_g = Lambda_g(x) (x_g - w_inf,g(x)) + Lambda_n,g (u_g - x_g).
+// vx += (dG/dx)^T cot and vgs += (dG/dgs)^T cot (u and Lambda_n held fixed);
+// Gg receives the gate terms G_g(x).  The currents take one dual pass per
+// state and per scaling (22), the gates two (their rates and steady states
+// depend on V and Ca_ss only).
+__device__ __attribute__((noinline)) void reaction_vjp(const double *x, const double *gs,
+                                                      const double *lam_n, const double *ug,
+                                                      const double *cot, double *vx, double *vgs,
+                                                      double *Gg) {
+  double lam[NG], inf[NG], dlv[NG], div[NG], dlc[NG], dic[NG];
+  ttp06::gates<ad::D>(ad::D(x[0], 1.0), ad::D(x[3], 0.0), [&](int k, ad::D in, ad::D rate) {
+    lam[k] = -rate.v;
+    inf[k] = in.v;
+    dlv[k] = -rate.d;
+    div[k] = in.d;
+  });
+  ttp06::gates<ad::D>(ad::D(x[0], 0.0), ad::D(x[3], 1.0), [&](int k, ad::D in, ad::D rate) {
+    dlc[k] = -rate.d;
+    dic[k] = in.d;
+  });
+  for (int k = 0; k < NG; ++k) {
+    const double w = x[GATE0 + k], c = cot[GATE0 + k];
+    Gg[k] = lam[k] * (w - inf[k]) + lam_n[k] * (ug[k] - w);
+    vx[0] += c * (dlv[k] * (w - inf[k]) - lam[k] * div[k]);
+    vx[3] += c * (dlc[k] * (w - inf[k]) - lam[k] * dic[k]);
+    vx[GATE0 + k] += c * (lam[k] - lam_n[k]);
+  }
+#pragma unroll 1
+  for (int m = 0; m < NF + 3; ++m) {
+    ad::D y[NF];
+    for (int f = 0; f < NF; ++f) y[f] = ad::D(x[f], f == m ? 1.0 : 0.0);
+    const ad::D g0(gs[0], m == NF ? 1.0 : 0.0), g1(gs[1], m == NF + 1 ? 1.0 : 0.0),
+        g2(gs[2], m == NF + 2 ? 1.0 : 0.0);
+    ad::D I, ha[6];
+    ttp06::currents<ad::D>(y, g0, g1, g2, I, ha);
+    double s = -cot[0] * I.d;  // d G_V = -d I_ion
+    for (int k = 0; k < 6; ++k) s += cot[1 + k] * ha[k].d;
+    if (m < NF)
+      vx[m] += s;
+    else
+      vgs[m - NF] += s;
+  }
+}
+
+// phi_1(x) and phi_1'(x) = phi_1(x) - phi_2(x).
+__device__ __forceinline__ void phi1_d(double x, const double *invfact, double &p1, double &dp1) {
+  double ph[2];
+  phis<2>(x, invfact, ph);
+  p1 = ph[0];
+  dp1 = ph[0] - ph[1];
+}
+
+// Sums of the conductance-scaling gradient over a block, one row of partials
+// per block (reduced by k_adj_gs_reduce).
+template <int NT>
+__device__ __forceinline__ void block_gs(double (&vgs)[3], double *lds, double *part) {
+  block_sums<3, NT>(vgs, lds);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 0] = vgs[0];
+    part[3 * blockIdx.x + 1] = vgs[1];
+    part[3 * blockIdx.x + 2] = vgs[2];
+  }
+}
+
+constexpr int ADB = 256;
+
+// Node i of the forward substitution, backwards.  beta_i (the adjoint of b_i)
+// is MU_i with its V row replaced by the adjoint solve's result (in RHO_i);
+// RHO_i receives all of beta_i.  With s = Z_{i-1} and the cotangent c =
+// dt d_i beta (gate rows times phi_1(d_i z)):
+//   MU_{i-1} (or DYN for i = 1, Z_0 = u) += beta + (dG/dx)^T c,
+//   DLAM_g += c_g (u_g - s_g), DYN_g += c_g Lambda_n,g (the anchor part),
+//   DZ_g += dt d_i beta_g G_g(s) d_i phi_1'(d_i z_g).
+__global__ void __launch_bounds__(ADB)
+k_adj_backsub(AdjArgs a, int i) {
+  __shared__ double lds[3 * (ADB / 64)];
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  double vgs[3] = {0.0, 0.0, 0.0};
+  if (p < a.N) {
+    const int64_t Np = a.Np, sS = (int64_t)NF * Np;
+    const double *Zs = a.Z + (int64_t)(i - 1) * sS + p;
+    const double *U = a.Z + p;  // stage 0 = u
+    double *mu_i = a.MU + (int64_t)i * sS + p;
+    double *rho_i = a.RHO + (int64_t)i * sS + p;
+    double *tgt = (i == 1) ? a.DYN + p : a.MU + (int64_t)(i - 1) * sS + p;
+    const double ddt = a.co.dt * a.co.d[i - 1];
+    double x[NF], beta[NF], cot[NF], vx[NF], lam_n[NG], ug[NG], Gg[NG], p1[NG], dp1[NG];
+    for (int f = 0; f < NF; ++f) {
+      x[f] = Zs[f * Np];
+      beta[f] = (f == 0) ? rho_i[0] : mu_i[f * Np];
+      if (f > 0) rho_i[f * Np] = beta[f];
+      vx[f] = 0.0;
+    }
+    for (int k = 0; k < NG; ++k) {
+      lam_n[k] = a.L0[k * Np + p];
+      ug[k] = U[(GATE0 + k) * Np];
+      phi1_d(a.co.d[i - 1] * a.co.dt * lam_n[k], a.co.invfact, p1[k], dp1[k]);
+    }
+    for (int f = 0; f < NF; ++f)
+      cot[f] = ddt * beta[f] * (f >= GATE0 ? p1[f - GATE0] : 1.0);
+    const double gs[3] = {a.gs[0], a.gs[1], a.gs[2]};
+    reaction_vjp(x, gs, lam_n, ug, cot, vx, vgs, Gg);
+    for (int f = 0; f < NF; ++f) tgt[f * Np] += beta[f] + vx[f];
+    for (int k = 0; k < NG; ++k) {
+      const double c = cot[GATE0 + k];
+      a.DLAM[k * Np + p] += c * (ug[k] - x[GATE0 + k]);
+      a.DYN[(GATE0 + k) * Np + p] += c * lam_n[k];
+      a.DZ[k * Np + p] += ddt * beta[GATE0 + k] * Gg[k] * a.co.d[i - 1] * dp1[k];
+    }
+  }
+  block_gs<ADB>(vgs, lds, a.gs_part);
+}
+
+// The collocation integrals and the P terms built from the previous iterate,
+// backwards, for every stage j = 0..M of X (X_0 = u) at once:
+//   gamma_j = dt sum_i (a_ij - a_{i-1,j}) rho_i          (j >= 1; a_0j = 0)
+//   cot_j   = gamma_j - dt d_{j+1} rho_{j+1} (gate rows times phi_1(d_{j+1} z))
+//   MUX_j (or DYN for j = 0) += (dG/dx)^T cot_j at X_j, the anchor parts as
+//   in k_adj_backsub, and
+//   DZ_g += dt sum_i rho_i,g sum_j (a'_ij - a'_{i-1,j}) G_g(X_j)
+//           - rho_{j+1,g} dt d_{j+1} G_g(X_j) d_{j+1} phi_1'(d_{j+1} z),
+//   a'_ij(z) = sum_k c_i^{k+1} w_j^{k-1} phi_k'(c_i z).
+// W_j = gamma_j^V - dt d_j rho_j^V is the adjoint the stencil products K X_j^V
+// receive (applied by the host with the operator, j = 1..M).
+template <int M>
+__global__ void __launch_bounds__(ADB)
+k_adj_assemble(AdjArgs a) {
+  __shared__ double lds[3 * (ADB / 64)];
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  double vgs[3] = {0.0, 0.0, 0.0};
+  if (p < a.N) {
+    const int64_t Np = a.Np, sS = (int64_t)NF * Np;
+    const Colloc &co = a.co;
+    const double dt = co.dt;
+    const double *X = a.X + p;
+    const double *rho = a.RHO + p;
+    double gam[M + 1][NF];
+    for (int j = 0; j <= M; ++j)
+      for (int f = 0; f < NF; ++f) gam[j][f] = 0.0;
+    // rows V .. Rbar: collocation weights Q
+    for (int f = 0; f < GATE0; ++f)
+      for (int i = 1; i <= M; ++i) {
+        const double r = rho[(int64_t)i * sS + f * Np];
+        for (int j = 1; j <= M; ++j)
+          gam[j][f] += dt * (co.Q[i - 1][j - 1] - (i > 1 ? co.Q[i - 2][j - 1] : 0.0)) * r;
+      }
+    // gate rows: a_ij(z) and its derivative, with G_g(X_j) for the z terms
+    double lam_n[NG], ug[NG];
+    for (int k = 0; k < NG; ++k) {
+      lam_n[k] = a.L0[k * Np + p];
+      ug[k] = X[(GATE0 + k) * Np];
+    }
+    double Gg[M + 1][NG];
+    for (int j = 0; j <= M; ++j) {
+      const double V = X[(int64_t)j * sS], C = X[(int64_t)j * sS + 3 * Np];
+      ttp06::gates<double>(V, C, [&](int k, double in, double rate) {
+        const double w = X[(int64_t)j * sS + (GATE0 + k) * Np];
+        Gg[j][k] = -rate * (w - in) + lam_n[k] * (ug[k] - w);
+      });
+    }
+    double dz[NG];
+    for (int k = 0; k < NG; ++k) {
+      const double z = dt * lam_n[k];
+      double A[M + 1][M + 1], Ad[M + 1][M + 1];  // rows i = 0..M (row 0: zero)
+      for (int j = 0; j <= M; ++j) A[0][j] = Ad[0][j] = 0.0;
+      for (int i = 1; i <= M; ++i) {
+        double ph[M + 1];
+        if (z == 0.0) {
+          for (int j = 1; j <= M; ++j) A[i][j] = co.Q[i - 1][j - 1];
+        } else {
+          phis<M + 1>(co.c[i - 1] * z, co.invfact, ph);
+          for (int j = 1; j <= M; ++j) {
+            double s = 0.0;
+            for (int q = 0; q < M; ++q) s += co.cpow[i - 1][q + 1] * co.W[q][j - 1] * ph[q];
+            A[i][j] = s;
+          }
+        }
+        // derivative in z, also at z = 0 (phi_k(0) = 1/k!)
+        if (z == 0.0)
+          for (int q = 0; q <= M; ++q) ph[q] = co.invfact[q + 1];
+        for (int j = 1; j <= M; ++j) {
+          double s = 0.0;
+          for (int q = 0; q < M; ++q)
+            s += co.cpow[i - 1][q + 1] * co.c[i - 1] * co.W[q][j - 1] *
+                 (ph[q] - (q + 1) * ph[q + 1]);
+          Ad[i][j] = s;
+        }
+      }
+      double dzk = 0.0;
+      const int f = GATE0 + k;
+      for (int i = 1; i <= M; ++i) {
+        const double r = rho[(int64_t)i * sS + f * Np];
+        for (int j = 1; j <= M; ++j) {
+          gam[j][f] += dt * (A[i][j] - A[i - 1][j]) * r;
+          dzk += dt * r * (Ad[i][j] - Ad[i - 1][j]) * Gg[j][k];
+        }
+      }
+      dz[k] = dzk;
+    }
+    // the P terms of the previous iterate and the transposed cell model at X_j
+    for (int j = 0; j <= M; ++j) {
+      double x[NF], cot[NF], vx[NF], gtmp[NG];
+      const bool nxt = j + 1 <= M;
+      const double ddn = nxt ? dt * co.d[j] : 0.0;  // dt d_{j+1}
+      for (int f = 0; f < NF; ++f) {
+        x[f] = X[(int64_t)j * sS + f * Np];
+        vx[f] = 0.0;
+        double c = (j >= 1) ? gam[j][f] : 0.0;
+        if (nxt) {
+          double sc = 1.0;
+          if (f >= GATE0) {
+            double p1, dp1;
+            phi1_d(co.d[j] * dt * lam_n[f - GATE0], co.invfact, p1, dp1);
+            sc = p1;
+            dz[f - GATE0] -= rho[(int64_t)(j + 1) * sS + f * Np] * ddn * Gg[j][f - GATE0] *
+                             co.d[j] * dp1;
+          }
+          c -= ddn * sc * rho[(int64_t)(j + 1) * sS + f * Np];
+        }
+        cot[f] = c;
+      }
+      const double gs[3] = {a.gs[0], a.gs[1], a.gs[2]};
+      reaction_vjp(x, gs, lam_n, ug, cot, vx, vgs, gtmp);
+      double *tgt = (j == 0) ? a.DYN + p : a.MUX + (int64_t)j * sS + p;
+      for (int f = 0; f < NF; ++f) tgt[f * Np] += vx[f];
+      for (int k = 0; k < NG; ++k) {
+        const double c = cot[GATE0 + k];
+        a.DLAM[k * Np + p] += c * (ug[k] - x[GATE0 + k]);
+        a.DYN[(GATE0 + k) * Np + p] += c * lam_n[k];
+      }
+      if (j >= 1) a.W[(int64_t)j * Np + p] = gam[j][0] - dt * co.d[j - 1] * rho[(int64_t)j * sS];
+    }
+    for (int k = 0; k < NG; ++k) a.DZ[k * Np + p] += dz[k];
+  }
+  block_gs<ADB>(vgs, lds, a.gs_part);
+}
+
+// Lambda_n = Lambda(u) backwards: DYN at V and Ca_ss += (dLambda/du)^T (dt DZ + DLAM).
+__global__ void __launch_bounds__(ADB) k_adj_anchor(AdjArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  if (p >= a.N) return;
+  const int64_t Np = a.Np;
+  const double V = a.Z[p], C = a.Z[3 * Np + p];
+  double sv = 0.0, sc = 0.0;
+  ttp06::gates<ad::D>(ad::D(V, 1.0), ad::D(C, 0.0), [&](int k, ad::D, ad::D rate) {
+    sv += (a.co.dt * a.DZ[k * Np + p] + a.DLAM[k * Np + p]) * (-rate.d);
+  });
+  ttp06::gates<ad::D>(ad::D(V, 0.0), ad::D(C, 1.0), [&](int k, ad::D, ad::D rate) {
+    sc += (a.co.dt * a.DZ[k * Np + p] + a.DLAM[k * Np + p]) * (-rate.d);
+  });
+  a.DYN[p] += sv;
+  a.DYN[3 * Np + p] += sc;
+}
+
+// Gradient of u^T K v with respect to the face coefficients, scaled:
+// dk_face(p, p + e_a) += s (-(u_q - u_p)(v_q - v_p)).
+__global__ void __launch_bounds__(ADB)
+k_adj_faces(Grid g, const double *u, const double *v, double s, double *dkx, double *dky,
+            double *dkz) {
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  if (p >= g.N) return;
+  const Ijk c = ijk(g, p);
+  const double up = u[p], vp = v[p];
+  auto face = [&](int64_t q) { return -s * (u[q] - up) * (v[q] - vp); };
+  if (c.ix < g.nx - 1) dkx[p] += face(p + 1);
+  if (g.dim >= 2 && c.iy < g.ny - 1) dky[p] += face(p + g.nx);
+  if (g.dim >= 3 && c.iz < g.nz - 1) dkz[p] += face(p + (int64_t)g.nx * g.ny);
+}
+
+// out += s K v (the library's operator, per-node faces or uniform).
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(ADB) k_adj_spmv_add(Grid g, const double *v, double s, double *out) {
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  if (p >= g.N) return;
+  const Ijk c = ijk(g, p);
+  out[p] += s * applyK<DIM, PN>(g, p, c, v[p], [&](int64_t k) { return v[k]; });
+}
+
+// dsigma_p from the face gradients: a face coefficient is sc 2 s_p s_q / (s_p + s_q).
+__global__ void __launch_bounds__(ADB)
+k_adj_sigma(Grid g, const double *sig, double sc, const double *dkx, const double *dky,
+            const double *dkz, double *dsig) {
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  if (p >= g.N) return;
+  const Ijk c = ijk(g, p);
+  const double sp = sig[p];
+  double acc = 0.0;
+  // face (p, q): d k / d s_p = sc 2 s_q^2 / (s_p + s_q)^2
+  auto add = [&](const double *dk, int64_t face, int64_t other) {
+    const double so = sig[other], t = sp + so;
+    if (t > 0.0) acc += dk[face] * sc * 2.0 * so * so / (t * t);
+  };
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  if (c.ix < g.nx - 1) add(dkx, p, p + 1);
+  if (c.ix > 0) add(dkx, p - 1, p - 1);
+  if (g.dim >= 2) {
+    if (c.iy < g.ny - 1) add(dky, p, p + sy);
+    if (c.iy > 0) add(dky, p - sy, p - sy);
+  }
+  if (g.dim >= 3) {
+    if (c.iz < g.nz - 1) add(dkz, p, p + sz);
+    if (c.iz > 0) add(dkz, p - sz, p - sz);
+  }
+  dsig[p] = acc;
+}
+
+// Misfit at the probes: r_q = V(probe_q) - target_q; out_sq[q] = r_q^2, and
+// (seed) lambda[V][probe_q] += 2 r_q.
+__global__ void k_adj_probes(const double *y, const int64_t *probes, const double *target, int np,
+                             double *out_sq, double *lambda) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  const double r = y[probes[q]] - target[q];
+  if (out_sq) out_sq[q] = r * r;
+  if (lambda) lambda[probes[q]] += 2.0 * r;  // probes are distinct
+}
+
+// Sums block partials of the scaling gradient into acc[3] (one block, fixed order).
+__global__ void __launch_bounds__(ADB) k_adj_gs_reduce(const double *part, int nb, double *acc) {
+  __shared__ double lds[3 * (ADB / 64)];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < nb; k += ADB)
+    for (int q = 0; q < 3; ++q) v[q] += part[3 * k + q];
+  block_sums<3, ADB>(v, lds);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) acc[q] += v[q];
+}
+
+// y += x over n values.
+__global__ void __launch_bounds__(ADB) k_adj_axpy(double *y, const double *x, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  if (p < n) y[p] += x[p];
+}
+
+static unsigned adj_blocks(int64_t n) { return (unsigned)((n + ADB - 1) / ADB); }
+
+hipError_t launch_adj_backsub(hipStream_t s, const AdjArgs &a, int i) {
+  hipLaunchKernelGGL(k_adj_backsub, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a, i);
+  hipLaunchKernelGGL(k_adj_gs_reduce, dim3(1), dim3(ADB), 0, s, a.gs_part, (int)adj_blocks(a.N),
+                     a.gs_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_assemble(hipStream_t s, const AdjArgs &a) {
+  switch (a.co.M) {
+    case 1: hipLaunchKernelGGL(k_adj_assemble<1>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_adj_assemble<2>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_adj_assemble<3>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_adj_assemble<4>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_adj_assemble<5>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_adj_assemble<6>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_adj_gs_reduce, dim3(1), dim3(ADB), 0, s, a.gs_part, (int)adj_blocks(a.N),
+                     a.gs_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_anchor(hipStream_t s, const AdjArgs &a) {
+  hipLaunchKernelGGL(k_adj_anchor, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_faces(hipStream_t s, const Grid &g, const double *u, const double *v,
+                            double scale, double *dkx, double *dky, double *dkz) {
+  hipLaunchKernelGGL(k_adj_faces, dim3(adj_blocks(g.N)), dim3(ADB), 0, s, g, u, v, scale, dkx,
+                     dky, dkz);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_spmv_add(hipStream_t s, const Grid &g, const double *v, double scale,
+                               double *out) {
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_adj_spmv_add<DIM, PN>), dim3(adj_blocks(g.N)),
+                                         dim3(ADB), 0, s, g, v, scale, out));
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_sigma(hipStream_t s, const Grid &g, const double *sig, double sc,
+                            const double *dkx, const double *dky, const double *dkz, double *dsig) {
+  hipLaunchKernelGGL(k_adj_sigma, dim3(adj_blocks(g.N)), dim3(ADB), 0, s, g, sig, sc, dkx, dky,
+                     dkz, dsig);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_probes(hipStream_t s, const double *y, const int64_t *probes,
+                             const double *target, int np, double *out_sq, double *lambda) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_probes, dim3((np + 255) / 256), dim3(256), 0, s, y, probes, target, np,
+                     out_sq, lambda);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_axpy(hipStream_t s, double *y, const double *x, int64_t n) {
+  hipLaunchKernelGGL(k_adj_axpy, dim3(adj_blocks(n)), dim3(ADB), 0, s, y, x, n);
+  return hipGetLastError();
+}
+
+}  // namespace hsdc

@@ -287,6 +287,36 @@ hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc,
                                   const double *Tt, int Mf, int i0, double *Yf, int64_t sYf,
                                   int nslices);
 
+// ---- discrete adjoint of a serial step (hsdc_adjoint.hip) -------------------
+// Buffers of one slice: stage vectors [M+1][NF][Np], fields [NF][Np], gate
+// rows [NG][Np].  X: the sweep's previous iterate, Z: its result (stage 0 of
+// both is the anchor u = y_n); MU, MUX: adjoints of Z and X; RHO: the
+// adjoints of the right-hand sides b_i (V row from the adjoint solves); DYN:
+// adjoint of y_n; DZ, DLAM: adjoints of z = dt Lambda_n and of Lambda_n where
+// it enters explicitly; W: [M+1][Np] adjoints of K X_j^V (rows 1..M); L0:
+// Lambda_n; gs_part: per-block partials of the scaling gradient, summed into
+// gs_acc[3] after every launch.
+struct AdjArgs {
+  int64_t N, Np;
+  Colloc co;
+  double gs[3];
+  const double *X, *Z, *L0;
+  double *MU, *MUX, *RHO, *DYN, *DZ, *DLAM, *W;
+  double *gs_part, *gs_acc;
+};
+hipError_t launch_adj_backsub(hipStream_t s, const AdjArgs &a, int i);
+hipError_t launch_adj_assemble(hipStream_t s, const AdjArgs &a);  // M <= 6
+hipError_t launch_adj_anchor(hipStream_t s, const AdjArgs &a);
+hipError_t launch_adj_faces(hipStream_t s, const Grid &g, const double *u, const double *v,
+                            double scale, double *dkx, double *dky, double *dkz);
+hipError_t launch_adj_spmv_add(hipStream_t s, const Grid &g, const double *v, double scale,
+                               double *out);
+hipError_t launch_adj_sigma(hipStream_t s, const Grid &g, const double *sig, double sc,
+                            const double *dkx, const double *dky, const double *dkz, double *dsig);
+hipError_t launch_adj_probes(hipStream_t s, const double *y, const int64_t *probes,
+                             const double *target, int np, double *out_sq, double *lambda);
+hipError_t launch_adj_axpy(hipStream_t s, double *y, const double *x, int64_t n);
+
 // building blocks exported for tests
 hipError_t launch_ionic_test(hipStream_t s, int64_t n, const double *y, double gs0, double gs1,
                              double gs2, double *I_ion, double *ha, double *lam, double *winf);

@@ -1926,3 +1926,274 @@ hsdc_status hsdc_colloc_coefficients(int32_t M, int64_t n, const double *z, doub
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// discrete adjoint of serial hybrid SDC: the gradient of a probe-voltage
+// misfit L = sum over samples s and probes q of (V_q(t_s) - target_{s,q})^2
+// with respect to the per-node conductivity, the G_Na, G_CaL, G_Kr scalings
+// and the initial state.  The forward run keeps y_n before every step (the
+// per-step checkpoints); the reverse run recomputes each step from its
+// checkpoint with every sweep's iterate kept, and runs the step backwards
+// (hsdc_adjoint.hip: the transposed sweep of eqs. prec_picard, def_P, def_C).
+// ---------------------------------------------------------------------------
+struct hsdc_adj {
+  hsdc_ctx *c = nullptr;  // the forward's context; its workspace serves the recompute
+  int nsteps = 0, every = 0, np = 0, nsamples = 0;
+  double loss = 0.0;
+  double *ckpt = nullptr;     // [nsteps + 1][NF][Np] y_n before step n, and the final state
+  int64_t *probes = nullptr;  // [np]
+  double *targets = nullptr;  // [nsamples][np]
+  double *sigma = nullptr;    // [N] per-node sigma, or null
+  double *work = nullptr;     // the reverse run's buffers (allocated on first use)
+};
+
+namespace {
+
+// The adjoint of one step's sweeps; lam holds the adjoint of y_{n+1} on entry
+// and receives that of y_n.  Xs must hold the step's iterates X^0 .. X^K.
+struct AdjBuffers {
+  double *Xs, *MU, *MUX, *RHO, *lam, *DYN, *DZ, *DLAM, *W, *dk, *gs_part, *gs_acc;
+};
+
+void adjoint_step(hsdc_ctx *c, const AdjBuffers &b) {
+  Level &F = c->L[0];
+  const int M = F.co.M, K = c->meth.max_iter;
+  const int64_t Np = F.g.Np, sS = (int64_t)NF * Np, sY = (int64_t)(M + 1) * sS;
+  const hipStream_t s = c->s;
+  double *MU = b.MU, *MUX = b.MUX;
+  HIPC(hipMemsetAsync(MU, 0, sY * sizeof(double), s));
+  HIPC(hipMemsetAsync(b.DYN, 0, sS * sizeof(double), s));
+  HIPC(hipMemsetAsync(b.DZ, 0, (size_t)NG * Np * sizeof(double), s));
+  HIPC(hipMemsetAsync(b.DLAM, 0, (size_t)NG * Np * sizeof(double), s));
+  HIPC(hipMemcpyAsync(MU + (int64_t)M * sS, b.lam, sS * sizeof(double), hipMemcpyDeviceToDevice, s));
+  AdjArgs a{};
+  a.N = F.g.N;
+  a.Np = Np;
+  a.co = F.co;
+  for (int q = 0; q < 3; ++q) a.gs[q] = c->prob.g_scale[q];
+  a.L0 = F.st.L0;
+  a.RHO = b.RHO;
+  a.DYN = b.DYN;
+  a.DZ = b.DZ;
+  a.DLAM = b.DLAM;
+  a.W = b.W;
+  a.gs_part = b.gs_part;
+  a.gs_acc = b.gs_acc;
+  double *dkx = b.dk, *dky = b.dk + Np, *dkz = b.dk + 2 * Np;
+  for (int k = K; k >= 1; --k) {
+    const double *X = b.Xs + (int64_t)(k - 1) * sY, *Z = b.Xs + (int64_t)k * sY;
+    HIPC(hipMemsetAsync(MUX, 0, sY * sizeof(double), s));
+    a.X = X;
+    a.Z = Z;
+    a.MU = MU;
+    a.MUX = MUX;
+    for (int i = M; i >= 1; --i) {
+      // beta_i^V = (I - dt d_i K)^-1 MU_i^V (the operator is symmetric)
+      CgBatch cb{};
+      cb.x = b.RHO + (int64_t)i * sS;
+      cb.b = MU + (int64_t)i * sS;
+      HIPC(hipMemcpyAsync(cb.x, cb.b, Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+      for (int q = 0; q < 2; ++q) {
+        cb.r[q] = F.cg_r[q];
+        cb.w[q] = F.cg_w[q];
+        cb.s[q] = F.cg_s[q];
+      }
+      cb.p = F.cg_p;
+      cb.part = F.cg_part;
+      cb.pstride = F.cg_pstride;
+      cb.sc = F.cg_sc;
+      cb.log = nullptr;
+      cb.last_k = -1;
+      cb.nslices = 1;
+      cb.nblk = cg_blocks(F.g);
+      cb.nblk0 = cb.nblk;
+      cb.a = F.co.dt * F.co.d[i - 1];
+      cb.tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
+      cb.maxit = c->meth.cg_maxit;
+      int used = 0;
+      bool conv = false;
+      run_cg(s, F.g, cb, &used, &conv);
+      if (!conv) {
+        fail(c, HSDC_ENOCONV, "an adjoint diffusion solve reached cg_maxit");
+        throw StatusFail{HSDC_ENOCONV};
+      }
+      HIPC(launch_adj_faces(s, F.g, cb.x, Z + (int64_t)i * sS, cb.a, dkx, dky, dkz));
+      HIPC(launch_adj_backsub(s, a, i));
+    }
+    HIPC(launch_adj_assemble(s, a));
+    for (int j = 1; j <= M; ++j) {
+      HIPC(launch_adj_spmv_add(s, F.g, b.W + (int64_t)j * Np, 1.0, MUX + (int64_t)j * sS));
+      HIPC(launch_adj_faces(s, F.g, b.W + (int64_t)j * Np, X + (int64_t)j * sS, 1.0, dkx, dky, dkz));
+    }
+    if (k > 1) {
+      std::swap(MU, MUX);  // the previous sweep's result is this sweep's X
+    } else {
+      for (int j = 1; j <= M; ++j)  // X^0 = 1 (x) y_n
+        HIPC(launch_adj_axpy(s, b.DYN, MUX + (int64_t)j * sS, sS));
+    }
+  }
+  a.Z = b.Xs;  // stage 0: y_n
+  HIPC(launch_adj_anchor(s, a));
+  HIPC(hipMemcpyAsync(b.lam, b.DYN, sS * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+// Recompute step n from its checkpoint, keeping every sweep's iterate.
+void recompute_step(hsdc_ctx *c, const hsdc_adj *adj, int n, double *Xs) {
+  Level &F = c->L[0];
+  const int M = F.co.M, K = c->meth.max_iter;
+  const int64_t sY = F.st.sY();
+  c->step = n;
+  HIPC(launch_step_set(c->s, c->d_step, n));
+  HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0, adj->ckpt + (int64_t)n * NF * F.g.Np, 0, NF, 1));
+  begin_serial_step(c);
+  materialize(c);
+  c->safe_cg = true;
+  HIPC(launch_copy_fields(c->s, F.g.Np, Xs, 0, F.st.Y, 0, (M + 1) * NF, 1));
+  for (int k = 1; k <= K; ++k) {
+    sweep(c, F, 0, 0, 1, nullptr, nullptr, k - 1, false);
+    HIPC(launch_copy_fields(c->s, F.g.Np, Xs + (int64_t)k * sY, 0, F.st.Y, 0, (M + 1) * NF, 1));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+hsdc_status hsdc_misfit_forward(const hsdc_problem *prob, const hsdc_method *meth, const double *y0,
+                                int32_t nsteps, int32_t sample_every, int32_t nprobes,
+                                const int64_t *probes, const double *targets, double *loss_host,
+                                hsdc_adj **out, void *hip_stream) {
+  if (!out) return fail(nullptr, HSDC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!prob || !meth) return fail(nullptr, HSDC_EINVAL, "problem or method is NULL");
+  if (meth->levels != 1 || meth->P != 1)
+    return fail(nullptr, HSDC_EINVAL, "the adjoint is of serial hybrid SDC (levels = 1, P = 1)");
+  if (meth->M[0] > 6) return fail(nullptr, HSDC_EINVAL, "the adjoint takes M <= 6");
+  if (nsteps < 1 || sample_every < 1 || nprobes < 1 || !probes || !targets)
+    return fail(nullptr, HSDC_EINVAL, "nsteps, sample_every, nprobes >= 1 and probes, targets needed");
+  hsdc_ctx *c = nullptr;
+  hsdc_status st = hsdc_init_state(prob, meth, y0, hip_stream, &c);
+  if (st != HSDC_OK) return st;
+  hsdc_adj *adj = new hsdc_adj();
+  adj->c = c;
+  adj->nsteps = nsteps;
+  adj->every = sample_every;
+  adj->np = nprobes;
+  adj->nsamples = nsteps / sample_every;
+  st = run_guarded(c, [&]() -> hsdc_status {
+    Level &F = c->L[0];
+    const int64_t N = F.g.N, Np = F.g.Np;
+    std::vector<int64_t> hp(nprobes);
+    HIPC(hipMemcpyAsync(hp.data(), probes, nprobes * sizeof(int64_t), hipMemcpyDeviceToHost, c->s));
+    HIPC(hipStreamSynchronize(c->s));
+    std::vector<int64_t> sorted(hp);
+    std::sort(sorted.begin(), sorted.end());
+    for (int q = 0; q < nprobes; ++q)
+      if (sorted[q] < 0 || sorted[q] >= N || (q > 0 && sorted[q] == sorted[q - 1]))
+        return fail(c, HSDC_EINVAL, "probes must be distinct node indices in [0, N)");
+    adj->probes = dalloc<int64_t>(c, nprobes);
+    HIPC(hipMemcpyAsync(adj->probes, hp.data(), nprobes * sizeof(int64_t), hipMemcpyHostToDevice, c->s));
+    const int ns = adj->nsamples;
+    adj->targets = dalloc<double>(c, (size_t)std::max(1, ns) * nprobes);
+    if (ns > 0)
+      HIPC(hipMemcpyAsync(adj->targets, targets, (size_t)ns * nprobes * sizeof(double),
+                          hipMemcpyDeviceToDevice, c->s));
+    if (prob->sigma_node) {
+      adj->sigma = dalloc<double>(c, N);
+      HIPC(hipMemcpyAsync(adj->sigma, prob->sigma_node, N * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+    }
+    adj->ckpt = dalloc<double>(c, (size_t)(nsteps + 1) * NF * Np);
+    double *sq = dalloc<double>(c, (size_t)std::max(1, ns) * nprobes);
+    for (int n = 0; n < nsteps; ++n) {
+      HIPC(launch_copy_fields(c->s, Np, adj->ckpt + (int64_t)n * NF * Np, 0, F.st.Y, 0, NF, 1));
+      const hsdc_status sa = hsdc_advance(c, 1);
+      if (sa != HSDC_OK) return sa;
+      if ((n + 1) % sample_every == 0) {
+        const int smp = (n + 1) / sample_every - 1;
+        HIPC(launch_adj_probes(c->s, F.st.Y, adj->probes, adj->targets + (int64_t)smp * nprobes,
+                               nprobes, sq + (int64_t)smp * nprobes, nullptr));
+      }
+    }
+    HIPC(launch_copy_fields(c->s, Np, adj->ckpt + (int64_t)nsteps * NF * Np, 0, F.st.Y, 0, NF, 1));
+    std::vector<double> hs((size_t)std::max(1, ns) * nprobes, 0.0);
+    HIPC(hipMemcpyAsync(hs.data(), sq, hs.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPC(hipStreamSynchronize(c->s));
+    double L = 0.0;
+    for (int k = 0; k < ns * nprobes; ++k) L += hs[k];
+    adj->loss = L;
+    if (!std::isfinite(L)) return fail(c, HSDC_ENONFINITE, "non-finite misfit");
+    return HSDC_OK;
+  });
+  if (st != HSDC_OK) {
+    g_free_error = c->err;
+    hsdc_adj_destroy(adj);
+    return st;
+  }
+  if (loss_host) *loss_host = adj->loss;
+  *out = adj;
+  return HSDC_OK;
+}
+
+hsdc_status hsdc_misfit_backward(hsdc_adj *adj, double *grad_sigma, double *grad_gscale_host,
+                                 double *grad_y0) {
+  if (!adj || !adj->c) return fail(nullptr, HSDC_EINVAL, "adjoint handle is NULL");
+  hsdc_ctx *c = adj->c;
+  if (grad_sigma && !adj->sigma)
+    return fail(c, HSDC_EINVAL, "grad_sigma needs a problem with sigma_node");
+  return run_guarded(c, [&]() -> hsdc_status {
+    Level &F = c->L[0];
+    const int M = F.co.M, K = c->meth.max_iter;
+    const int64_t N = F.g.N, Np = F.g.Np, sS = (int64_t)NF * Np, sY = (int64_t)(M + 1) * sS;
+    const int64_t nbl = (N + 255) / 256;
+    const int64_t sizes[] = {(K + 1) * sY, sY, sY, sY, sS, sS, (int64_t)NG * Np, (int64_t)NG * Np,
+                             (int64_t)(M + 1) * Np, 3 * Np, 3 * nbl, 8};
+    int64_t total = 0;
+    for (int64_t v : sizes) total += v;
+    if (!adj->work) adj->work = dalloc<double>(c, total);
+    double *w = adj->work;
+    AdjBuffers b{};
+    double **slots[] = {&b.Xs, &b.MU, &b.MUX, &b.RHO, &b.lam, &b.DYN, &b.DZ, &b.DLAM, &b.W, &b.dk,
+                        &b.gs_part, &b.gs_acc};
+    for (int q = 0; q < 12; ++q) {
+      *slots[q] = w;
+      w += sizes[q];
+    }
+    HIPC(hipMemsetAsync(b.lam, 0, sS * sizeof(double), c->s));
+    HIPC(hipMemsetAsync(b.dk, 0, 3 * Np * sizeof(double), c->s));
+    HIPC(hipMemsetAsync(b.gs_acc, 0, 8 * sizeof(double), c->s));
+    const int every = adj->every, np = adj->np;
+    // the last sample is taken on y_nsteps (kept with the checkpoints)
+    if (adj->nsteps % every == 0)
+      HIPC(launch_adj_probes(c->s, adj->ckpt + (int64_t)adj->nsteps * NF * Np, adj->probes,
+                             adj->targets + (int64_t)(adj->nsteps / every - 1) * np, np, nullptr, b.lam));
+    for (int n = adj->nsteps - 1; n >= 0; --n) {
+      recompute_step(c, adj, n, b.Xs);
+      adjoint_step(c, b);
+      if (n > 0 && n % every == 0)
+        HIPC(launch_adj_probes(c->s, adj->ckpt + (int64_t)n * NF * Np, adj->probes,
+                               adj->targets + (int64_t)(n / every - 1) * np, np, nullptr, b.lam));
+    }
+    if (grad_y0)
+      for (int f = 0; f < NF; ++f)
+        HIPC(hipMemcpyAsync(grad_y0 + f * N, b.lam + f * Np, N * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->s));
+    if (grad_sigma) {
+      const double sc = 1.0 / (c->prob.dx * c->prob.dx * c->prob.chi * c->prob.Cm);
+      HIPC(launch_adj_sigma(c->s, F.g, adj->sigma, sc, b.dk, b.dk + Np, b.dk + 2 * Np, grad_sigma));
+    }
+    double gs[8];
+    HIPC(hipMemcpyAsync(gs, b.gs_acc, sizeof(gs), hipMemcpyDeviceToHost, c->s));
+    HIPC(hipStreamSynchronize(c->s));
+    if (grad_gscale_host)
+      for (int q = 0; q < 3; ++q) grad_gscale_host[q] = gs[q];
+    return HSDC_OK;
+  });
+}
+
+void hsdc_adj_destroy(hsdc_adj *adj) {
+  if (!adj) return;
+  hsdc_destroy(adj->c);
+  delete adj;
+}
+
+}  // extern "C"

@@ -89,6 +89,9 @@ def lib():
             "hsdc_diffusion_solve_noalloc": [ctypes.POINTER(Problem), dbl, vp, vp, dbl, i32, vp,
                                              vp],
             "hsdc_colloc_coefficients": [i32, i64, vp, vp, vp, vp],
+            "hsdc_misfit_forward": [ctypes.POINTER(Problem), ctypes.POINTER(Method), vp, i32, i32,
+                                    i32, vp, vp, vp, ctypes.POINTER(vp), vp],
+            "hsdc_misfit_backward": [vp, vp, vp, vp],
             "hsdc_profile_enable": [vp, i32],
             "hsdc_profile_read": [vp, vp, i32, vp],
         }
@@ -100,6 +103,8 @@ def lib():
         L.hsdc_current_step.restype = ctypes.c_int64
         L.hsdc_destroy.argtypes = [vp]
         L.hsdc_destroy.restype = None
+        L.hsdc_adj_destroy.argtypes = [vp]
+        L.hsdc_adj_destroy.restype = None
         L.hsdc_last_error.argtypes = [vp]
         L.hsdc_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -384,3 +389,51 @@ def colloc_coefficients(M, z, stream=None):
     _check(lib().hsdc_colloc_coefficients(M, z.shape[0], _dev(z, "z"), _dev(out, "out"),
                                           c.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
     return out, c
+
+
+class Misfit:
+    """hsdc_misfit_forward / hsdc_misfit_backward: the probe-voltage misfit of a
+    serial run and its gradient.  probes: int64 device tensor [Q] of distinct
+    node indices; targets: float64 device tensor [nsteps // sample_every][Q]."""
+
+    def __init__(self, problem, method, probes, targets, nsteps, sample_every, y0=None,
+                 stream=None):
+        if probes.dtype != torch.int64 or not probes.is_cuda or not probes.is_contiguous():
+            raise ValueError("probes must be a contiguous int64 device tensor")
+        nq = probes.shape[0]
+        ns = nsteps // sample_every
+        self.problem, self.N = problem, problem.N
+        y0p = None if y0 is None else _dev(y0, "y0", (NF, self.N))
+        loss = ctypes.c_double(0.0)
+        ptr = ctypes.c_void_p()
+        _check(lib().hsdc_misfit_forward(ctypes.byref(problem), ctypes.byref(method), y0p,
+                                         int(nsteps), int(sample_every), int(nq),
+                                         ctypes.c_void_p(probes.data_ptr()),
+                                         _dev(targets, "targets", (ns, nq)),
+                                         ctypes.byref(loss), ctypes.byref(ptr), _stream(stream)))
+        self._adj = ptr
+        self.loss = loss.value
+
+    def backward(self, sigma=True, y0=False):
+        """(dL/dsigma_node [N] or None, dL/dg_scale numpy [3], dL/dy0 [19, N] or None)."""
+        if self._adj is None:
+            raise HsdcError(-6, "misfit handle destroyed")
+        ds = torch.empty(self.N, dtype=torch.float64, device="cuda") if sigma else None
+        dy = torch.empty((NF, self.N), dtype=torch.float64, device="cuda") if y0 else None
+        dg = np.zeros(3)
+        code = lib().hsdc_misfit_backward(self._adj, None if ds is None else _dev(ds, "ds"),
+                                          dg.ctypes.data_as(ctypes.c_void_p),
+                                          None if dy is None else _dev(dy, "dy"))
+        _check(code)
+        return ds, dg, dy
+
+    def destroy(self):
+        if self._adj is not None:
+            lib().hsdc_adj_destroy(self._adj)
+            self._adj = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
