@@ -101,8 +101,9 @@ def test_apply_diffusion_parity(case):
 def test_apply_diffusion_streamed_2d(dims, sigma):
     """The column-streamed operator of 2D meshes with uniform sigma and even nx
     (two nodes per lane, 16-byte accesses; partial blocks in x and y, a mesh
-    two nodes wide) equals the oracle's K v and, bitwise, the node-per-thread
-    kernel (taken for vectors that are not 16-byte aligned)."""
+    two nodes wide) equals the oracle's K v and, to rounding (the compiler may
+    fuse a product into an add differently), the node-per-thread kernel (taken
+    for vectors that are not 16-byte aligned)."""
     rng = np.random.default_rng(5)
     N = int(np.prod(dims))
     v = rng.standard_normal(N)
@@ -114,7 +115,7 @@ def test_apply_diffusion_streamed_2d(dims, sigma):
     vb[1:] = dev(v)
     ob = torch.zeros(N + 1, dtype=torch.float64, device="cuda")
     H.apply_diffusion(p, vb[1:], out=ob[1:])
-    assert np.array_equal(host(ob[1:]), got)
+    assert np.max(np.abs(host(ob[1:]) - got)) <= 4e-16 * np.max(np.abs(got))
 
 
 @pytest.mark.parametrize("case", ["2d", "3d_aniso", "2d_pernode"])
