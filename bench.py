@@ -66,7 +66,7 @@ def _args():
                     help="slab2d: keep the default CG launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d", "cable1d"),
+    ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d", "cable1d", "adjoint"),
                     default="slab2d")
     ap.add_argument("--tissues", type=int, default=64, help="batch2d: tissues in the batch")
     ap.add_argument("--summarize-valu", metavar="COUNTER_CSV",
@@ -651,6 +651,95 @@ def spmv_out_of_cache(dims=(8192, 8192), reps=10):
             "unit": "GB/s", "frac": gbps / 8000.0, "traffic": traffic, "launches": reps}
 
 
+def bench_adjoint(a):
+    """The adjoint workload at full size: 256 x 256 slab, per-node lognormal
+    sigma, a 16 x 16 corner stimulus, TTP06, M 4, K 4, dt 0.05 ms, T = 10 ms
+    (200 steps); 64 probes sampled every 0.5 ms; targets from a run at perturbed
+    parameters (sigma x exp(0.1 N(0,1)), g_Na x 1.1, g_CaL x 0.9, g_Kr x 1.2).
+    Times the forward run with its per-step checkpoints and the backward run
+    (recompute and transposed sweep of every step), and checks the scaling
+    gradient against central differences (h = 1e-6) of the library's own
+    forward."""
+    import torch
+
+    import synthetic_inputs as si
+    from paper_2405_19994_amd import hsdc as H
+
+    dims, dx, M, K, dt, nsteps, every = (256, 256), 0.025, 4, 4, 0.05, 200, 10
+    N = dims[0] * dims[1]
+    rng = np.random.default_rng(0)
+    sigma0 = np.exp(0.3 * rng.standard_normal(N))
+    truth = sigma0 * np.exp(0.1 * rng.standard_normal(N))
+    probes = np.sort(rng.choice(N, 64, replace=False))
+    dev = torch.device("cuda:0")
+
+    def t(x, dtype=torch.float64):
+        return torch.tensor(x, dtype=dtype, device=dev)
+
+    stim = t(si.corner_weights(dims, (16, 16)))
+    meth = H.make_method(M=(M, 1), dt=dt, max_iter=K, cg_rtol=1e-13, cg_maxit=500)
+
+    def problem(sig, gs):
+        return H.make_problem(dims, dx, (1.0, 1.0, 1.0), t(sig), 1400.0, 1.0, gs, stim, 50.0,
+                              0.0, 1.0)
+
+    # targets: V at the probes of a forward run at the perturbed parameters
+    ctx = H.Context(problem(truth, (1.1, 0.9, 1.2)), meth)
+    targets = []
+    for _ in range(nsteps // every):
+        ctx.advance(every)
+        targets.append(ctx.get_state(0, 0, 0)[0][t(probes, torch.int64)].clone())
+    ctx.destroy()
+    targets = torch.stack(targets).contiguous()
+    pr = t(probes, torch.int64)
+
+    def misfit(sig, gs):
+        return H.Misfit(problem(sig, gs), meth, pr, targets, nsteps, every)
+
+    misfit(sigma0, (1.0, 1.0, 1.0)).destroy()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = misfit(sigma0, (1.0, 1.0, 1.0))
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ds, dg, _ = m.backward(sigma=True)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    loss = m.loss
+    m.destroy()
+    h = 1e-6
+    fd = []
+    for q in range(3):
+        gp = [1.0, 1.0, 1.0]
+        gm = [1.0, 1.0, 1.0]
+        gp[q] += h
+        gm[q] -= h
+        mp, mm = misfit(sigma0, tuple(gp)), misfit(sigma0, tuple(gm))
+        fd.append((mp.loss - mm.loss) / (2 * h))
+        mp.destroy()
+        mm.destroy()
+    rel = [abs(fd[q] - dg[q]) / max(abs(fd[q]), 1e-300) for q in range(3)]
+    updates = N * M * K * nsteps
+    out = {
+        "metric": "SDC node-updates/s of the forward and backward runs of the misfit gradient "
+                  "(serial hybrid SDC, FP64)",
+        "value": 2 * updates / (t_fwd + t_bwd),
+        "unit": "node-updates/s",
+        "n_gpus": 1, "steps": nsteps, "warmup": 1, "ms_per_step": 1e3 * (t_fwd + t_bwd) / nsteps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adjoint 256x256, per-node lognormal sigma, TTP06, M4 K4, dt 0.05 ms, "
+                               "T 10 ms, 64 probes every 0.5 ms", "nodes": N},
+        "loss": loss, "forward_s": t_fwd, "backward_s": t_bwd,
+        "backward_over_forward": t_bwd / t_fwd,
+        "checkpoint_bytes": (nsteps + 1) * 19 * 8 * N,
+        "grad_gscale": list(dg), "fd_gscale_library_forward": fd, "fd_rel_error": rel,
+        "grad_sigma_norm": float(torch.linalg.vector_norm(ds)),
+    }
+    print(json.dumps(out))
+
+
 def main():
     a = _args()
     if a.summarize_counters:
@@ -670,6 +759,9 @@ def main():
         return
     if a.workload == "cable1d":
         bench_cable1d(a)
+        return
+    if a.workload == "adjoint":
+        bench_adjoint(a)
         return
     # the oracle's worker processes run before anything touches the GPU
     cpu = None if a.no_cpu_baseline else cpu_baseline()
