@@ -92,7 +92,7 @@ typedef struct {
                              /* gradients started from a Chebyshev iterate over   */
                              /* the Gershgorin interval of I - a K (steps from    */
                              /* the warm start without inner products, the first  */
-                             /* inside the node update: degree 5 on 2D meshes,    */
+                             /* inside the node update: degree 7 on 2D meshes,    */
                              /* in one tiled launch, else 3);                     */
                              /* 1 Chebyshev iteration over that                   */
                              /* interval (no inner products: the iteration count  */
