@@ -66,7 +66,8 @@ def _args():
                     help="slab2d: keep the default CG launch shapes instead of tuning them first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d", "cable1d", "adjoint"),
+    ap.add_argument("--workload", choices=("slab2d", "slab3d", "batch2d", "cable1d", "adjoint",
+                                           "slab2d_fd4"),
                     default="slab2d")
     ap.add_argument("--tissues", type=int, default=64, help="batch2d: tissues in the batch")
     ap.add_argument("--summarize-valu", metavar="COUNTER_CSV",
@@ -293,8 +294,12 @@ def bench_slab3d(a):
         return H.make_method(M=(w["M"], 1), dt=dt, max_iter=K, cg_rtol=rtol, cg_maxit=500,
                              solver=a.solver)
 
-    def run(method, n):
-        ctx = H.Context(prob, method, None)
+    stream = torch.cuda.Stream()
+
+    def run(method, n, graph=a.graph):
+        ctx = H.Context(prob, method, None, stream)
+        if graph and method.levels == 2:
+            ctx.use_graph(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx.advance(n)
@@ -326,6 +331,12 @@ def bench_slab3d(a):
         chosen = a.tols[-1]
     y_pf, wall_pf, st_pf = median_run(pfasst_method(chosen), a.blocks)
     err_pf = _field_error(y_pf, ref)
+    # the other launch mode once: the coarse part of each iteration from a
+    # captured graph, or eagerly
+    y_o, wall_o, st_o = run(pfasst_method(chosen), a.blocks, graph=not a.graph)
+    other_mode = {"graph_replay": not a.graph, "wall_s": wall_o,
+                  "sim_ms_per_wall_s": T / wall_o, "pfasst_iters": st_o["pfasst_iters"],
+                  "same_result": bool(torch.equal(y_o, y_pf))}
     serial = None
     for K in range(2, 21):
         y_s, wall_s, _ = run(serial_method(K, w["cg_rtol"]), nsteps)
@@ -386,9 +397,105 @@ def bench_slab3d(a):
         "vs_serial_same_error": None if serial is None else value / serial["sim_ms_per_wall_s"],
         "reference_wall_s": wall_ref,
         "median_of": max(1, a.runs),
+        "graph_replay": bool(a.graph),
+        "other_launch_mode": other_mode,
+        "coarse_redo": st_pf["cg_redo_steps"],
         "profiled_block": {"pfasst_iters": pst["pfasst_iters"], "cg_iters": pst["cg_iters"],
                            "cg_solves": pst["cg_solves"], "cg_redo_steps": pst["cg_redo_steps"]},
         "roofline": roofline,
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
+def bench_slab2d_fd4(a):
+    """The paper's own spatial setup on the 512 x 512 slab: the fourth-order
+    stencil with direct DCT-II solves of every diffusion system (M 6, K 6, dt
+    0.05 ms), beside the second-order stencil with the same DCT-II solver and
+    with CG from its Chebyshev start.  Median of --runs runs of --steps steps
+    (default 100) after a warm-up; a profiled pass gives the kernel classes,
+    the DCT-II transforms against the FP64 matrix-core peak."""
+    import torch
+
+    import synthetic_inputs as si
+    from paper_2405_19994_amd import hsdc as H
+
+    w = si.workload("slab2d")
+    steps = a.steps if a.steps != 400 else 100
+    dev = torch.device("cuda:0")
+    stim = torch.tensor(w["stim_w"], dtype=torch.float64, device=dev)
+    N = int(np.prod(w["dims"]))
+
+    def problem(order):
+        return H.make_problem(w["dims"], w["dx"], w["sigma"], None, w["chi"], w["Cm"], (1, 1, 1),
+                              stim, w["stim_amp"], w["stim_t0"], w["stim_dur"], fd_order=order)
+
+    def method(solver):
+        return H.make_method(M=w["M"], dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"],
+                             cg_maxit=500, solver=solver)
+
+    def timed(order, solver, nsteps, runs):
+        res = []
+        for _ in range(max(1, runs)):
+            ctx = H.Context(problem(order), method(solver))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.advance(nsteps)
+            torch.cuda.synchronize()
+            res.append(time.perf_counter() - t0)
+            ctx.destroy()
+        res.sort()
+        return res[len(res) // 2]
+
+    upd = N * w["M"] * w["K"]
+    timed(4, "dct", min(a.warmup, 10) or 1, 1)  # warm-up
+    wall = timed(4, "dct", steps, a.runs)
+    others = {}
+    for order, solver in ((2, "dct"), (2, "cg")):
+        wl = timed(order, solver, steps, 1)
+        others[f"order{order}_{solver}"] = {"node_updates_per_s": upd * steps / wl,
+                                           "ms_per_step": 1e3 * wl / steps}
+    ctx = H.Context(problem(4), method("dct"))
+    ctx.profile(True)
+    ctx.advance(min(steps, 20))
+    torch.cuda.synchronize()
+    kp = ctx.profile_read()
+    ctx.destroy()
+    kernels = _kernel_table(kp)
+    dct = None
+    if "dct_solve" in kernels:
+        # this class counts FLOPs: 4 n per node and transformed axis (both ways)
+        kd = kernels["dct_solve"]
+        kd["TFLOPs"] = kd.pop("GBps") / 1e3
+        kd["flop_per_launch"] = kd.pop("bytes_per_launch")
+        dct = {"kernel": "dct_solve", "bound": "mfma", "achieved": kd["TFLOPs"], "peak": 78.6,
+               "unit": "TFLOP/s", "frac": kd["TFLOPs"] / 78.6, "traffic": None}
+    nu = kernels.get("node_update")
+    roof = None
+    if nu:
+        ach = FLOP_PER_NODE_UPDATE * N / (nu["avg_us"] * 1e-6) / 1e12
+        roof = {"kernel": "node_update", "bound": "alu", "achieved": ach, "peak": 78.6,
+                "unit": "TFLOP/s", "frac": ach / 78.6, "traffic": None}
+    out = {
+        "metric": "SDC node-updates/s (serial hybrid SDC, FP64, fourth-order stencil, DCT-II solves)",
+        "value": upd * steps / wall,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "slab2d 512x512, fourth-order stencil, TTP06, M6 K6, dt 0.05 ms, "
+                               "DCT-II direct solves", "nodes": N, "M": w["M"], "sweeps": w["K"],
+                   "dt_ms": w["dt"]},
+        "median_of": max(1, a.runs),
+        "other_configurations": others,
+        "roofline": roof,
+        "dct_roofline": dct,
         "kernels": kernels,
     }
     print(json.dumps(out))
@@ -418,12 +525,26 @@ def bench_batch2d(a):
                       cg_maxit=500, solver=a.solver)
     Ns = [p.N for p in probs]
     upd_per_step = sum(Ns) * ws[0]["M"] * ws[0]["K"]
+    # block and tile shapes tuned for this batch (cached per shape)
+    tuning = None
+    if not a.no_autotune:
+        from paper_2405_19994_amd import autotune
+        setting, timings = autotune.tune(lambda: H.BatchContext(probs, m), "batch", steps=4,
+                                         warm=2, axes=("node_block", "cg_tile"), use_cache=False)
+        tuning = {"setting": setting, "candidates": timings}
+
+    def new_batch():
+        c = H.BatchContext(probs, m)
+        if tuning:
+            autotune._apply(c, tuning["setting"])
+        return c
+
     if a.warmup > 0:
-        ctx = H.BatchContext(probs, m)
+        ctx = new_batch()
         ctx.advance(min(a.warmup, 5))
         torch.cuda.synchronize()
         ctx.destroy()
-    ctx = H.BatchContext(probs, m)
+    ctx = new_batch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.advance(steps)
@@ -441,7 +562,7 @@ def bench_batch2d(a):
     torch.cuda.synchronize()
     wall_loop = time.perf_counter() - t0
     # profiled pass: per-class kernel durations of the batch
-    ctx = H.BatchContext(probs, m)
+    ctx = new_batch()
     ctx.profile(True)
     ctx.advance(min(steps, 20))
     torch.cuda.synchronize()
@@ -476,6 +597,7 @@ def bench_batch2d(a):
         "one_context_per_tissue": {"node_updates_per_s": loop_value, "steps": loop_steps,
                                    "wall_s": wall_loop},
         "vs_one_context_per_tissue": value / loop_value,
+        "tuning": tuning,
         "cg_iters_per_solve": st["cg_iters"] / max(1, st["cg_solves"]),
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["GBps"],
                      "peak": 8000.0, "unit": "GB/s", "frac": kernels[dom]["GBps"] / 8000.0,
@@ -763,6 +885,9 @@ def main():
     if a.workload == "adjoint":
         bench_adjoint(a)
         return
+    if a.workload == "slab2d_fd4":
+        bench_slab2d_fd4(a)
+        return
     # the oracle's worker processes run before anything touches the GPU
     cpu = None if a.no_cpu_baseline else cpu_baseline()
 
@@ -792,13 +917,15 @@ def main():
         from paper_2405_19994_amd import autotune
         key = autotune.shape_key(prob, meth)
         setting, timings = autotune.tune(lambda: H.Context(prob, meth, None, stream), key,
-                                         use_cache=False)
+                                         axes=autotune.relevant_axes(prob, meth), use_cache=False)
         tuning = {"setting": setting, "candidates": timings}
 
     def new_context(m=None):
         c = H.Context(prob, m or meth, None, stream)
         if tuning:
-            c.tune(tuning["setting"]["cg_blocks"], tuning["setting"]["cg_margin"])
+            s = tuning["setting"]
+            c.tune(s["cg_blocks"], s["cg_margin"])
+            c.tune_shapes(s["node_block"], s["cg_tile"], s["prolong_tile"])
         if a.graph:
             c.use_graph(True)
         return c

@@ -74,6 +74,12 @@ typedef struct {
   double stim_amp;           /* uA/cm^2; I_stim = stim_amp * stim_w(x) while      */
   double stim_t0;            /*   stim_t0 < t <= stim_t0 + stim_dur (window open  */
   double stim_dur;           /*   on the left, closed on the right)               */
+  int32_t fd_order;          /* finite differences of A: 2 (or 0) the 3/5/7-point */
+                             /* stencil above; 4 the fourth-order stencil of      */
+                             /* Sec. 2.2, per axis sigma_axis (-V_{p-2} + 16      */
+                             /* V_{p-1} - 30 V_p + 16 V_{p+1} - V_{p+2}) /        */
+                             /* (12 dx^2) with the same mirror at the walls       */
+                             /* (V_{-1} = V_0, V_{-2} = V_1); uniform sigma only  */
 } hsdc_problem;
 
 /* Method (Sec. 3, Algorithm 1). */
@@ -99,8 +105,11 @@ typedef struct {
                              /* comes from the residual bound of the Chebyshev    */
                              /* polynomial, the same ||b - A x||_2 <= cg_rtol     */
                              /* ||b||_2); 2 conjugate gradients from the warm     */
-                             /* start.  An FP32 coarse level always runs CG from  */
-                             /* the warm start.                                   */
+                             /* start; 3 direct solve in the DCT-II eigenbasis of */
+                             /* A (Sec. 5: the paper's Laplacian solves), exact   */
+                             /* up to rounding, for uniform sigma and FP64 levels */
+                             /* (required with fd_order 4).  An FP32 coarse level */
+                             /* always runs CG from the warm start.               */
   double cg_rtol;            /* diffusion solve: ||b - A x||_2 <= cg_rtol ||b||_2 */
   int32_t cg_maxit;          /* iteration cap per diffusion solve (Chebyshev:     */
                              /* cap on the polynomial degree)                     */
@@ -132,8 +141,9 @@ typedef struct {
   int64_t cg_unconverged;    /* solves that hit cg_maxit                          */
   int64_t pfasst_iters;      /* PFASST iterations                                 */
   int64_t ionic_evals;       /* node-wise cell-model evaluations (x mesh nodes)   */
-  int64_t cg_redo_steps;     /* serial steps recomputed because a solve run with  */
-                             /* a predicted iteration budget missed cg_rtol       */
+  int64_t cg_redo_steps;     /* serial steps, and coarse parts of PFASST          */
+                             /* iterations, recomputed because a solve run with   */
+                             /* a predicted iteration budget missed its tolerance */
 } hsdc_stats;
 
 /* Create a context and its initial state (Sec. 3.1: y(0) = y_0).
@@ -165,7 +175,8 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
  * reductions): cg_blocks caps the blocks of each CG kernel (1..1024, <= 0
  * keeps the current cap, default 512); cg_margin is the number of spare
  * launches added to a predicted CG budget (0..64, negative keeps the current
- * margin, default 1).  A budgeted solve gets one CG launch per iteration it is
+ * margin; by default none after the one-launch CG start of 2D meshes, one
+ * otherwise).  A budgeted solve gets one CG launch per iteration it is
  * predicted to need plus the margin, none when its start is predicted to meet
  * cg_rtol and the margin is 0; its convergence is checked from the residual's
  * partial sums by the kernel that follows it, and a step with a missed solve
@@ -174,8 +185,28 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
  * call it between steps, not concurrently with work on the context. */
 hsdc_status hsdc_tune(hsdc_ctx *ctx, int32_t cg_blocks, int32_t cg_margin);
 
-/* Graph replay of serial steps (serial and batch contexts created on a
- * non-null stream): hsdc_advance then captures one whole step (max_iter
+/* Launch shapes of a context's FP64 levels (an FP32 coarse level keeps the
+ * defaults); results are unchanged up to the order of the reductions over
+ * blocks and tiles.
+ *   node_block:   threads per block of the node update (the cell model and
+ *                 the diffusion right-hand side, eq. def_P): 64, 128, 256
+ *                 (default) or 512; 0 keeps the current size.
+ *   cg_tile:      tile of the one-launch CG start on 2D meshes (solver 0):
+ *                 0: 64 x 16 nodes, 1024 threads (default); 1: 32 x 32, 1024;
+ *                 2: 32 x 16, 512; 3: 32 x 8, 256; 4: 16 x 16, 256; -1 keeps.
+ *   prolong_tile: tile of the coarse-to-fine correction into the fine level
+ *                 (Algorithm 1, space coarsening 2), 256 fine nodes per tile:
+ *                 3D 0: 32 x 4 x 2 (default), 1: 64 x 2 x 2, 2: 16 x 8 x 2,
+ *                 3: 16 x 4 x 4; 2D 0: 32 x 8 (default), 1: 64 x 4,
+ *                 2: 16 x 16, 3: 128 x 2; -1 keeps.
+ * HSDC_EINVAL for any other value.  Takes effect from the next launch (a
+ * captured step graph is captured again); call it between steps, not
+ * concurrently with work on the context. */
+hsdc_status hsdc_tune_shapes(hsdc_ctx *ctx, int32_t node_block, int32_t cg_tile,
+                             int32_t prolong_tile);
+
+/* Graph replay (contexts created on a non-null stream).  Serial and batch
+ * contexts: hsdc_advance then captures one whole step (max_iter
  * sweeps with their CG solves at predicted iteration budgets, y_{n+1} =
  * y_{n,M}, the start of the next step) into a HIP graph and replays it once
  * per step; the step number the kernels use is kept in device memory.  Every
@@ -183,8 +214,15 @@ hsdc_status hsdc_tune(hsdc_ctx *ctx, int32_t cg_blocks, int32_t cg_margin);
  * is recomputed from the saved y_n with every solve checked, as without
  * graphs.  Budgets rise at once and are lowered every 16 steps (to the most
  * iterations used since, plus the margin); a step is captured again when they
- * change.  Results equal those of stepping without graphs.  Kernel timing
- * (hsdc_profile_enable) steps without graphs.  on = 0 releases the graph. */
+ * change.  Two-level PFASST contexts: the coarse part of every iteration (the
+ * FAS restriction, the coarse evaluations and the Q^seq chain of coarse
+ * sweeps, whose solves run at predicted budgets in any case and are verified
+ * once at the part's end) is captured once and replayed per iteration; a part
+ * with a missed solve runs again with every solve checked; budgets are lowered
+ * every 8 iterations.  The fine Q^par sweep, the coarse-grid correction and
+ * the residual run as without graphs.  Results equal those without graphs.
+ * Kernel timing (hsdc_profile_enable) runs without graphs.  on = 0 releases
+ * the graph. */
 hsdc_status hsdc_use_graph(hsdc_ctx *ctx, int32_t on);
 
 /* Apply nsweeps preconditioned Picard iterations (eq. prec_picard, one forward

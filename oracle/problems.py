@@ -59,7 +59,7 @@ class Monodomain:
 
     def __init__(self, dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None, chi=1400.0,
                  Cm=1.0, stim_w=None, stim_amp=0.0, stim_t0=0.0, stim_dur=0.0,
-                 g_scale=(1.0, 1.0, 1.0), dt_ref=0.05):
+                 g_scale=(1.0, 1.0, 1.0), dt_ref=0.05, fd_order=2):
         self.dims = tuple(int(n) for n in dims)
         self.N = int(np.prod(self.dims))
         self.dx = float(dx)
@@ -70,7 +70,8 @@ class Monodomain:
         self.stim_amp, self.stim_t0, self.stim_dur = float(stim_amp), float(stim_t0), float(stim_dur)
         self.g_scale = tuple(float(g) for g in g_scale)
         self.eps_t = 1e-9 * dt_ref
-        A = laplacian(self.dims, self.dx, self.sigma, self.sigma_node)
+        self.fd_order = int(fd_order)
+        A = laplacian(self.dims, self.dx, self.sigma, self.sigma_node, self.fd_order)
         self.K = A / (self.chi * self.Cm)
         self.solver = ImplicitSolver(self.K)
 

@@ -16,16 +16,54 @@ space-coarsened PFASST level; the paper coarsens in time only): restriction is
 the average of the 2^d children, prolongation is cell-centred multilinear
 interpolation with weights 3/4 and 1/4 per axis and a mirror at the walls.
 
-The Laplacian is pinned by its exact DCT-II diagonalisation for uniform sigma;
-the transfers by exactness on constants and linear fields.
+The paper's own discretisation is fourth order (Sec. 2.2) with DCT-II solves
+(Sec. 5, computational setup); order = 4 builds it for uniform sigma: per axis
+the centred five-point second difference (-1, 16, -30, 16, -1)/(12 dx^2), with
+the no-flux wall as the same even mirror (V_{-1} = V_0, V_{-2} = V_1 on the
+cell-centred mesh).  That mirror makes the operator symmetric and diagonal in
+the DCT-II basis, which is what the paper's DCT solves need.
+
+The Laplacian is pinned by its exact DCT-II diagonalisation for uniform sigma
+(both orders) and by its order of accuracy on smooth no-flux fields; the
+transfers by exactness on constants and linear fields.
 """
 import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
-def laplacian(dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None):
-    """Sparse symmetric A (CSR) with (A V)_p = sum_faces k_pq (V_q - V_p)."""
+def second_difference_4(n):
+    """The 1D fourth-order second difference on n cell-centred nodes with the
+    even mirror at both walls, times dx^2 (dense n x n)."""
+    c = {-2: -1.0 / 12.0, -1: 16.0 / 12.0, 0: -30.0 / 12.0, 1: 16.0 / 12.0, 2: -1.0 / 12.0}
+    D = np.zeros((n, n))
+    for p in range(n):
+        for m, w in c.items():
+            q = p + m
+            while q < 0 or q >= n:  # mirror about the walls at -1/2 and n - 1/2
+                q = -1 - q if q < 0 else 2 * n - 1 - q
+            D[p, q] += w
+    return D
+
+
+def laplacian(dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None, order=2):
+    """Sparse symmetric A (CSR) with (A V)_p = sum_faces k_pq (V_q - V_p)
+    (order 2), or the fourth-order stencil above (order 4, uniform sigma)."""
+    if order == 4:
+        if sigma_node is not None:
+            raise ValueError("the fourth-order stencil takes a uniform sigma")
+        dims = tuple(int(n) for n in dims)
+        nx, ny, nz = (dims + (1, 1, 1))[:3]
+        A = sp.csr_matrix((nx * ny * nz, nx * ny * nz))
+        for axis, n in enumerate((nx, ny, nz)):
+            if n < 2:
+                continue
+            ops = [sp.identity(m, format="csr") for m in (nz, ny, nx)]
+            ops[2 - axis] = sp.csr_matrix(second_difference_4(n))
+            A = A + (float(sigma[axis]) / dx ** 2) * sp.kron(sp.kron(ops[0], ops[1]), ops[2])
+        return A.tocsr()
+    if order != 2:
+        raise ValueError("order must be 2 or 4")
     dims = tuple(int(n) for n in dims)
     nx, ny, nz = (dims + (1, 1, 1))[:3]
     N = nx * ny * nz
@@ -69,11 +107,22 @@ class ImplicitSolver:
         return self._lu[key].solve(np.asarray(b, float))
 
 
-def dct_solve_uniform(dims, dx, sigma, a, b):
+def dct_eigenvalues(n, order=2):
+    """Eigenvalues (times dx^2) of the 1D no-flux second difference for the
+    DCT-II mode k = 0..n-1, theta = pi k / n: the stencil's symbol at theta,
+    2 cos(theta) - 2 = -4 sin^2(theta / 2) (order 2) and
+    (-30 + 32 cos(theta) - 2 cos(2 theta)) / 12 (order 4)."""
+    th = np.pi * np.arange(n) / n
+    if order == 2:
+        return -4.0 * np.sin(th / 2.0) ** 2
+    return (-30.0 + 32.0 * np.cos(th) - 2.0 * np.cos(2.0 * th)) / 12.0
+
+
+def dct_solve_uniform(dims, dx, sigma, a, b, order=2):
     """Exact solve of (I - a A) x = b for uniform diagonal sigma through the
     DCT-II eigenbasis of the no-flux cell-centred stencil (the solver family
     the paper uses for its Laplacian solves, Sec. 5 computational setup).
-    Eigenvalues per axis: -(4 sigma/dx^2) sin^2(pi k / (2 n))."""
+    Eigenvalues per axis: sigma/dx^2 times dct_eigenvalues(n, order)."""
     import scipy.fft as sfft
     dims = tuple(int(n) for n in dims)
     shape = tuple(reversed(dims))  # (nz, ny, nx)
@@ -81,8 +130,7 @@ def dct_solve_uniform(dims, dx, sigma, a, b):
     lam = np.zeros(shape)
     for ax_arr, n in enumerate(shape):
         s = sigma[len(shape) - 1 - ax_arr]
-        k = np.arange(n)
-        ev = -(4.0 * s / dx ** 2) * np.sin(np.pi * k / (2.0 * n)) ** 2
+        ev = (s / dx ** 2) * dct_eigenvalues(n, order)
         sh = [1] * len(shape)
         sh[ax_arr] = n
         lam = lam + ev.reshape(sh)

@@ -1,0 +1,260 @@
+// hsdc_dct.hip -- the fourth-order diffusion stencil and the direct solve of
+// (I - a K) x = b in the DCT-II eigenbasis, for meshes with a uniform
+// conductivity tensor (Sec. 2.2: fourth-order finite differences; Sec. 5,
+// computational setup: Laplacian solves by DCT-II).
+//
+// Both stencils (second and fourth order) take the even mirror at the no-flux
+// walls of the cell-centred mesh (V_{-1} = V_0, V_{-2} = V_1), so K is
+// diagonal in the orthonormal DCT-II basis of every axis: with C[k][p] =
+// s_k cos(pi k (p + 1/2) / n) (s_0 = 1/sqrt(n), s_k = sqrt(2/n)),
+//   x = (C_z C_y C_x)^T diag(1 / (1 - a (l_x + l_y + l_z))) (C_z C_y C_x) b,
+// l_axis the eigenvalue of the axis mode (the stencil's symbol at theta =
+// pi k / n times sigma_axis / (dx^2 chi Cm)).  Each axis transform is a dense
+// product of the n x n matrix with the mesh lines along that axis, run on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64): 32 x 32 output tiles per block of
+// four waves, the contraction split over the waves and summed in LDS.
+#include <hip/hip_runtime.h>
+
+#include "hsdc_device.h"
+#include "hsdc_internal.h"
+
+namespace hsdc {
+
+// ---------------------------------------------------------------------------
+// fourth-order stencil, uniform sigma
+// ---------------------------------------------------------------------------
+
+// Mirror of index q into [0, n) about the walls at -1/2 and n - 1/2 (n >= 2).
+__device__ __forceinline__ int mirror(int q, int n) {
+  return q < 0 ? -1 - q : (q >= n ? 2 * n - 1 - q : q);
+}
+
+// (K v)_p: per active axis c_axis (16 ((v_-1 - v_0) + (v_+1 - v_0))
+// - ((v_-2 - v_0) + (v_+2 - v_0))) / 12 over the mirrored neighbours.
+template <int DIM>
+__device__ __forceinline__ double applyK4(const Grid &g, int64_t p, const Ijk &c, const double *v) {
+  const double vc = v[p];
+  double acc = 0.0;
+  const int nn[3] = {g.nx, g.ny, g.nz}, ci[3] = {c.ix, c.iy, c.iz};
+  const int64_t st[3] = {1, (int64_t)g.nx, (int64_t)g.nx * g.ny};
+  const double ca[3] = {g.cx, g.cy, g.cz};
+#pragma unroll
+  for (int ax = 0; ax < DIM; ++ax) {
+    const int n = nn[ax];
+    if (n < 2) continue;
+    const int i = ci[ax];
+    const int64_t base = p - (int64_t)i * st[ax];
+    const double m1 = v[base + mirror(i - 1, n) * st[ax]] - vc;
+    const double p1 = v[base + mirror(i + 1, n) * st[ax]] - vc;
+    const double m2 = v[base + mirror(mirror(i - 2, n), n) * st[ax]] - vc;
+    const double p2 = v[base + mirror(mirror(i + 2, n), n) * st[ax]] - vc;
+    acc += ca[ax] * ((16.0 * (m1 + p1) - (m2 + p2)) * (1.0 / 12.0));
+  }
+  return acc;
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(BLOCK) k_spmv4_stages(Grid g, const double *Y, int64_t sY,
+                                                        int64_t sS, double *FV, int64_t sFV,
+                                                        int slice0, int stage0) {
+  const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= g.N) return;
+  const int n = slice0 + blockIdx.z, j = stage0 + blockIdx.y;
+  const double *v = Y + n * sY + j * sS;
+  FV[n * sFV + j * g.Np + p] = applyK4<DIM>(g, p, ijk(g, p), v);
+}
+
+hipError_t launch_spmv4_stages(hipStream_t s, const Grid &g, const double *Y, int64_t sY,
+                               int64_t sS, double *FV, int64_t sFV, int slice0, int nslices,
+                               int stage0, int nstages) {
+  if (nslices <= 0 || nstages <= 0) return hipSuccess;
+  if (g.kx != nullptr || g.rag != nullptr) return hipErrorInvalidValue;
+  const dim3 grid(nblocks(g.N), nstages, nslices);
+  if (g.dim == 1)
+    hipLaunchKernelGGL(k_spmv4_stages<1>, grid, dim3(BLOCK), 0, s, g, Y, sY, sS, FV, sFV, slice0,
+                       stage0);
+  else if (g.dim == 2)
+    hipLaunchKernelGGL(k_spmv4_stages<2>, grid, dim3(BLOCK), 0, s, g, Y, sY, sS, FV, sFV, slice0,
+                       stage0);
+  else
+    hipLaunchKernelGGL(k_spmv4_stages<3>, grid, dim3(BLOCK), 0, s, g, Y, sY, sS, FV, sFV, slice0,
+                       stage0);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_K4(hipStream_t s, const Grid &g, const double *v, double *out) {
+  return launch_spmv4_stages(s, g, v, 0, 0, out, 0, 0, 1, 0, 1);
+}
+
+// ---------------------------------------------------------------------------
+// axis transforms on the FP64 matrix cores
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// out = T applied along one axis of n nodes, T given as its transpose TT
+// (row-major n x n: TT[p][k] = T[k][p]), so that the lanes of a matrix-core
+// fragment read consecutive addresses.
+//   ROWS (the x axis, lines contiguous): D[r][k] = sum_p In[r][p] T[k][p] over
+//     the rows r of a slice (outer of them);
+//   COLS (a slower axis with stride inner): D_o[k][i] = sum_p T[k][p] In_o[p][i]
+//     for each of the outer groups o of n x inner values.
+// With scale, the result at spectral index (ix, iy, iz) is divided by
+// 1 - a (lam_x[ix] + lam_y[iy] + lam_z[iz]).
+struct Xform {
+  const double *in;
+  int64_t sin;  // slice stride of in
+  double *out;
+  int64_t sout;  // slice stride of out
+  const double *TT;
+  int n;
+  int64_t inner, outer;
+  const double *lam[3];
+  int nx, ny;
+  double a;
+  int scale;
+};
+
+constexpr int XT = 32;  // output tile edge
+
+template <bool ROWS>
+__global__ void __launch_bounds__(256) k_xform(Xform f) {
+  __shared__ double red[4][XT * XT];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t M = ROWS ? f.outer : f.n;
+  const int64_t Nn = ROWS ? (int64_t)f.n : f.inner;
+  const int K = f.n;
+  const int64_t tiles_n = (Nn + XT - 1) / XT;
+  const int64_t m0 = (int64_t)(blockIdx.x / tiles_n) * XT, n0 = (int64_t)(blockIdx.x % tiles_n) * XT;
+  const int64_t slice = ROWS ? blockIdx.y : blockIdx.y / f.outer;
+  const int64_t grp = ROWS ? 0 : (blockIdx.y % f.outer) * (int64_t)f.n * f.inner;
+  const double *in = f.in + slice * f.sin + grp;
+  double *out = f.out + slice * f.sout + grp;
+  // the contraction split over the four waves, in steps of 4
+  const int kq = (K + 15) / 16 * 4;
+  const int kb = w * kq, ke = min(K, kb + kq);
+  const int lr = l & 15, lk = l >> 4;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += 4) {
+    const int k = k0 + lk;
+    const bool kin = k < ke;
+    double av[2], bv[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t m = m0 + t * 16 + lr, nn = n0 + t * 16 + lr;
+      if (ROWS) {
+        av[t] = (kin && m < M) ? in[m * f.n + k] : 0.0;                   // In[r][p]
+        bv[t] = (kin && nn < Nn) ? f.TT[(int64_t)k * f.n + nn] : 0.0;     // T[k][p] as TT[p][k]
+      } else {
+        av[t] = (kin && m < M) ? f.TT[(int64_t)k * f.n + m] : 0.0;        // T[k][p] as TT[p][k]
+        bv[t] = (kin && nn < Nn) ? in[(int64_t)k * f.inner + nn] : 0.0;   // In_o[p][i]
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+  }
+  // D[m][n] of a 16 x 16 tile: lane n + 16 (m % 4), register m / 4 (operands:
+  // A[m][k] in lane m + 16 k, B[k][n] in lane n + 16 k)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        red[w][(i * 16 + 4 * r + lk) * XT + j * 16 + lr] = acc[i][j][r];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < XT * XT / 256; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int64_t m = m0 + e / XT, nn = n0 + e % XT;
+    if (m >= M || nn >= Nn) continue;
+    double v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    const int64_t lin = ROWS ? m * f.n + nn : grp + m * f.inner + nn;
+    if (f.scale) {
+      const int64_t q1 = lin / f.nx;
+      const int ix = (int)(lin - q1 * f.nx);
+      const int64_t q2 = q1 / f.ny;
+      const int iy = (int)(q1 - q2 * f.ny), iz = (int)q2;
+      v = v / (1.0 - f.a * ((f.lam[0][ix] + f.lam[1][iy]) + f.lam[2][iz]));
+    }
+    out[ROWS ? m * f.n + nn : m * f.inner + nn] = v;
+  }
+}
+
+static hipError_t launch_xform(hipStream_t s, const Xform &f, bool rows, int nslices) {
+  const int64_t M = rows ? f.outer : f.n, Nn = rows ? (int64_t)f.n : f.inner;
+  const int64_t tiles = ((M + XT - 1) / XT) * ((Nn + XT - 1) / XT);
+  const int64_t batch = rows ? nslices : (int64_t)nslices * f.outer;
+  if (tiles > 0x7fffffff || batch > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tiles, (unsigned)batch);
+  if (rows)
+    hipLaunchKernelGGL(k_xform<true>, grid, dim3(256), 0, s, f);
+  else
+    hipLaunchKernelGGL(k_xform<false>, grid, dim3(256), 0, s, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_dct_solve(hipStream_t s, const Grid &g, const DctPlan &d, double a,
+                            const double *b, int64_t sb, double *x, int64_t sx, double *t1,
+                            double *t2, int64_t st, int nslices) {
+  if (nslices <= 0) return hipSuccess;
+  if (g.kx != nullptr || g.rag != nullptr) return hipErrorInvalidValue;
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  // axes transformed: x always, y and z when they have more than one node
+  int axes[3], na = 0;
+  for (int ax = 0; ax < 3; ++ax)
+    if (ax == 0 || nn[ax] > 1) axes[na++] = ax;
+  const int64_t N = g.N;
+  auto make = [&](int ax, bool forward, const double *in, int64_t sin, double *out, int64_t sout,
+                  bool scale) {
+    Xform f{};
+    f.in = in;
+    f.sin = sin;
+    f.out = out;
+    f.sout = sout;
+    // forward: T = C, given as TT = C^T; inverse: T = C^T, given as TT = C
+    f.TT = forward ? d.CT[ax] : d.C[ax];
+    f.n = nn[ax];
+    f.inner = ax == 0 ? 1 : (ax == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny);
+    f.outer = ax == 0 ? N / g.nx : N / ((int64_t)nn[ax] * f.inner);
+    for (int q = 0; q < 3; ++q) f.lam[q] = d.lam[q];
+    f.nx = g.nx;
+    f.ny = g.ny;
+    f.a = a;
+    f.scale = scale ? 1 : 0;
+    return f;
+  };
+  // forward over the axes, the last one scaling; then back in reverse order
+  const double *cur = b;
+  int64_t scur = sb;
+  double *bufs[2] = {t1, t2};
+  int nb = 0;
+  for (int q = 0; q < na; ++q) {
+    double *o = bufs[nb];
+    nb ^= 1;
+    hipError_t e = launch_xform(s, make(axes[q], true, cur, scur, o, st, q == na - 1),
+                                axes[q] == 0, nslices);
+    if (e != hipSuccess) return e;
+    cur = o;
+    scur = st;
+  }
+  for (int q = na - 1; q >= 0; --q) {
+    double *o = q == 0 ? x : bufs[nb];
+    const int64_t so = q == 0 ? sx : st;
+    nb ^= 1;
+    hipError_t e = launch_xform(s, make(axes[q], false, cur, scur, o, so, false), axes[q] == 0,
+                                nslices);
+    if (e != hipSuccess) return e;
+    cur = o;
+    scur = so;
+  }
+  return hipSuccess;
+}
+
+}  // namespace hsdc

@@ -54,7 +54,26 @@ struct Grid {
   double cx, cy, cz;           // sigma_axis / (dx^2 chi Cm) for uniform sigma
   const double *kx, *ky, *kz;  // per-node face coefficients (face p -> p+e_axis), or null
   const int32_t *rag;          // device [P][RAG] tissue dimensions and divisors, or null
+  // launch shapes (tunable per level): node-update block size (64, 128, 256 or
+  // 512 threads), tile of the one-launch CG start (an index into kCgTiles),
+  // tile of the coarse-to-fine correction on this mesh as the fine level (an
+  // index into kProlongTiles2D / 3D)
+  int nub, ctile, ptile;
+  int order;  // finite-difference order of K: 2, or 4 (uniform sigma; hsdc_dct.hip)
 };
+
+// Tiles of the one-launch CG start (x by y nodes, threads per block).
+struct TileShape {
+  int tx, ty, threads;
+};
+constexpr int kNumCgTiles = 5;
+constexpr TileShape kCgTiles[kNumCgTiles] = {
+    {64, 16, 1024}, {32, 32, 1024}, {32, 16, 512}, {32, 8, 256}, {16, 16, 256}};
+// Tiles of the coarse-to-fine correction (fine nodes x, y, z; 256 threads).
+constexpr int kNumProlongTiles = 4;
+constexpr int kProlongTiles3D[kNumProlongTiles][3] = {{32, 4, 2}, {64, 2, 2}, {16, 8, 2}, {16, 4, 4}};
+constexpr int kProlongTiles2D[kNumProlongTiles][2] = {{32, 8}, {64, 4}, {16, 16}, {128, 2}};
+constexpr int kDefaultNodeBlock = 256;
 
 // Collocation data of one level (host-computed in FP64, passed by value).
 struct Colloc {
@@ -157,7 +176,10 @@ hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st
                               const CgLogArgs &lg);
 hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &st, int slice0,
                                    int nslices);
+// Blocks of a node-update launch of g.nub threads, and of any launch of nb
+// threads per node block (XCD-padded unless the slices are a ragged batch).
 int node_blocks(const Grid &g);
+int node_blocks_of(const Grid &g, int nb);
 // out2[2 (n NF + f)] = max |r_{n,f}|, out2[2 (n NF + f) + 1] = max |y_{n,f}| per
 // slice n and field f.
 hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
@@ -217,6 +239,9 @@ struct CgBatchT {
   // and launch_cg_start forms r_D = b - A x_D and w_D = A r_D in the parity-1
   // vectors (and x_D in x), so the CG launches run k = 1, 2, ...
   int cstart;
+  // direct = 1: the level solves by DCT-II (hsdc_dct.hip); the node update only
+  // stores b in bout
+  int direct;
   // partials of (r_D, r_D) and (w_D, r_D) written by the start (first CG
   // launch); x0_to_p = 1: the node update also stores the warm start x_0 in p,
   // where the tiled start (launch_cg_start_tiled) reads it, so that the start
@@ -263,15 +288,35 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // CG start from x_D (cstart = D): r_D, w_D, the partials of (r_D, r_D) and
 // (w_D, r_D), the parity-1 scalars, and x_D in x.
 hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb);
-// The whole CG start of degree D = cb.cstart (3..5) in one launch on 2D meshes
-// (x_2 .. x_D, r_D, w_D in LDS tiles of 64 x 16 nodes with a halo of D + 1);
-// x_0 is read from p (cb.x0_to_p) and x_D written to x.  cg_start_tiles(g, D) =
-// its tiles per slice on a mesh that is
-// not a ragged batch (0: not applicable); ntiles = the launch's tiles per
-// slice (a ragged batch: the most of any tissue, cg_start_tiles_of).
+// The whole CG start of degree D = cb.cstart (7) in one launch on 2D meshes
+// (x_2 .. x_D, r_D, w_D in LDS tiles of kCgTiles[g.ctile] with a halo of
+// D + 1); x_0 is read from p (cb.x0_to_p) and x_D written to x.
+// cg_start_tiles(g, D) = its tiles per slice on a mesh that is not a ragged
+// batch (0: not applicable); ntiles = the launch's tiles per slice (a ragged
+// batch: the most of any tissue, cg_start_tiles_of).
 int cg_start_tiles(const Grid &g, int degree);
-int cg_start_tiles_of(int nx, int ny);
+int cg_start_tiles_of(int nx, int ny, int tile);
 hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb, int ntiles);
+
+// DCT-II data of a mesh with uniform sigma (hsdc_dct.hip): per axis the
+// orthonormal DCT-II matrix C[k][p] = s_k cos(pi k (p + 1/2) / n) and its
+// transpose CT, row-major n x n, and the eigenvalue of K for each mode,
+// lam[k] = sigma_axis / (dx^2 chi Cm) times the stencil's symbol at
+// theta = pi k / n (one entry 0 for an axis of one node).
+struct DctPlan {
+  const double *C[3], *CT[3], *lam[3];
+};
+// x = (I - a K)^-1 b for nslices slices (slice strides sb, sx; t1, t2 scratch
+// [nslices][st]); g uniform, not a batch.
+hipError_t launch_dct_solve(hipStream_t s, const Grid &g, const DctPlan &d, double a,
+                            const double *b, int64_t sb, double *x, int64_t sx, double *t1,
+                            double *t2, int64_t st, int nslices);
+// K V with the fourth-order stencil (g.order 4): stages stage0.. of slices
+// slice0.. of Y into FV (strides as StagesT), or one vector v into out.
+hipError_t launch_spmv4_stages(hipStream_t s, const Grid &g, const double *Y, int64_t sY,
+                               int64_t sS, double *FV, int64_t sFV, int slice0, int nslices,
+                               int stage0, int nstages);
+hipError_t launch_apply_K4(hipStream_t s, const Grid &g, const double *v, double *out);
 
 // transfers (space coarsening 2x or identity) between a fine and a coarse level
 hipError_t launch_restrict_stages(hipStream_t s, const Grid &gf, const Grid &gc, int sc_factor,

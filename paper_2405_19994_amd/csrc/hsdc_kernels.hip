@@ -94,6 +94,12 @@ template <class T>
 hipError_t launch_spmv_stages(hipStream_t s, const Grid &g, const StagesT<T> &st, int slice0,
                               int nslices, int stage0, int nstages) {
   if (nslices <= 0 || nstages <= 0) return hipSuccess;
+  if (g.order == 4) {  // fourth-order stencil: FP64 levels with uniform sigma
+    if constexpr (std::is_same<T, double>::value)
+      return launch_spmv4_stages(s, g, st.Y, st.sY(), st.sS(), st.FV, st.sFV(), slice0, nslices,
+                                 stage0, nstages);
+    return hipErrorInvalidValue;
+  }
   dim3 grid(g.rag ? nblocks(g.N) : nblocks_xcd(g.N), nstages, nslices);
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_spmv_stages<DIM, PN, T>), grid, dim3(BLOCK), 0, s, g,
                                          st, slice0, stage0));
@@ -360,24 +366,25 @@ hipError_t launch_cg_log(hipStream_t s, const Grid &g, const CgLogArgs &lg, int 
 
 // Four waves per SIMD (at most 128 VGPRs): the launch has exactly that many
 // waves on the 512 x 512 slab, so a fifth register would halve its occupancy.
-// Node-update blocks of 256 threads (four waves): on the 512 x 512 slab the
-// launch is one round of four waves per SIMD, and smaller blocks spread it
-// more evenly (3% faster than 512).
+// Node-update blocks of NB threads (g.nub; 256 by default): on the 512 x 512
+// slab the launch is one round of four waves per SIMD, and blocks of 256
+// spread it more evenly than 512 (3% faster); small meshes may fill more
+// compute units with smaller blocks.  Other stencil launches keep NUB.
 constexpr int NUB = 256;
-template <class T>
-__global__ void __launch_bounds__(NUB)
+template <class T, int NB>
+__global__ void __launch_bounds__(NB)
 __attribute__((amdgpu_waves_per_eu(4)))
 k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double gs1, double gs2,
               int slice0, int i, CgBatchT<T> cb, int store_g, int spread, const double *yref,
               CgLogArgs lg) {
-  __shared__ double lds[3 * (BLOCK / 64)];
+  __shared__ double lds[3 * (NB / 64)];
   const int64_t step0 = *stim.step;
   const int64_t qb = stencil_node_block(g0, blockIdx.x, gridDim.x);
-  const int64_t p = qb * NUB + threadIdx.x;
+  const int64_t p = qb * NB + threadIdx.x;
   const int n = slice0 + blockIdx.z;
   // the previous solve of this slice is checked by one block (its partial sums
   // are the other stage parity's, which this launch does not write)
-  if (lg.log && blockIdx.x == 0) cg_log_entry<NUB>(g0, lg, n, lds);
+  if (lg.log && blockIdx.x == 0) cg_log_entry<NB>(g0, lg, n, lds);
   const Grid g = slice_grid(g0, n);
   const int64_t Np = st.Np;
   const double ddt = co.dt * co.d[i - 1];
@@ -493,7 +500,9 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
     // the warm start x_0 = V^k_i, whose K x_0 is cached from the previous sweep
     const double bv = yd[0] + rh0 + ddt * (double)gV;
     const double r0 = bv - x0 + cb.a * kx0;
-    if (cb.xt) {
+    if (cb.direct) {
+      cb.bout[(int64_t)(n - slice0) * Np + p] = bv;  // the DCT-II solve takes b
+    } else if (cb.xt) {
       // Chebyshev: b and the first iterate x_1 = x_0 + r_0 / theta (and x_0 for
       // the tiled start, which writes x_D over x)
       cb.bout[(int64_t)(n - slice0) * Np + p] = bv;
@@ -506,7 +515,7 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
     rr = r0 * r0;
   }
   double t2[2] = {bb, rr};
-  block_sums<2, NUB>(t2, lds);
+  block_sums<2, NB>(t2, lds);
   if (threadIdx.x == 0) {
     double *part = cb.part + (int64_t)(n - slice0) * 5 * cb.pstride;
     part[4 * cb.pstride + qb] = t2[0];
@@ -514,12 +523,14 @@ k_node_update(Grid g0, StagesT<T> st, Colloc co, Stim stim, double gs0, double g
   }
 }
 
-// Blocks of a node-update launch (XCD-padded unless the slices are a ragged batch);
-// the first CG iteration reduces this many partials.
-int node_blocks(const Grid &g) {
-  const unsigned nb = (unsigned)((g.N + NUB - 1) / NUB);
-  return (int)(g.rag ? nb : (nb + kXcds - 1) / kXcds * kXcds);
+// Blocks of nb threads over one slice's nodes (XCD-padded unless the slices
+// are a ragged batch); the first CG iteration reduces node_blocks(g) partials
+// of the node update.
+int node_blocks_of(const Grid &g, int nb) {
+  const unsigned n = (unsigned)((g.N + nb - 1) / nb);
+  return (int)(g.rag ? n : (n + kXcds - 1) / kXcds * kXcds);
 }
+int node_blocks(const Grid &g) { return node_blocks_of(g, g.nub); }
 
 template <class T>
 hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st,
@@ -528,8 +539,22 @@ hipError_t launch_node_update(hipStream_t s, const Grid &g, const StagesT<T> &st
                               const CgBatchT<T> &cb, int store_g, int spread,
                               const double *yref, const CgLogArgs &lg) {
   dim3 grid(node_blocks(g), 1, nslices);
-  hipLaunchKernelGGL(k_node_update<T>, grid, dim3(NUB), 0, s, g, st, co, stim, gs0, gs1, gs2,
-                     slice0, i, cb, store_g, spread, yref, lg);
+#define HSDC_NU_LAUNCH(NB_)                                                                    \
+  hipLaunchKernelGGL((k_node_update<T, NB_>), grid, dim3(NB_), 0, s, g, st, co, stim, gs0, gs1, \
+                     gs2, slice0, i, cb, store_g, spread, yref, lg)
+  if constexpr (std::is_same<T, float>::value) {  // an FP32 coarse level keeps the default
+    if (g.nub != kDefaultNodeBlock) return hipErrorInvalidValue;
+    HSDC_NU_LAUNCH(kDefaultNodeBlock);
+  } else {
+    switch (g.nub) {
+      case 64: HSDC_NU_LAUNCH(64); break;
+      case 128: HSDC_NU_LAUNCH(128); break;
+      case 256: HSDC_NU_LAUNCH(256); break;
+      case 512: HSDC_NU_LAUNCH(512); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef HSDC_NU_LAUNCH
   return hipGetLastError();
 }
 
@@ -1041,7 +1066,7 @@ __global__ void __launch_bounds__(NUB) k_cg_start(Grid g0, CgBatch cb) {
 
 hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb) {
   // the node update's block count (every block writes its partials)
-  dim3 grid(node_blocks(g), cb.nslices);
+  dim3 grid(node_blocks_of(g, NUB), cb.nslices);
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_cg_start<DIM, PN>), grid, dim3(NUB), 0, s, g, cb));
   return hipGetLastError();
 }
@@ -1099,6 +1124,7 @@ __global__ void __launch_bounds__(SPX) k_apply_K2d(Grid g, const double *v, doub
 }
 
 hipError_t launch_apply_K(hipStream_t s, const Grid &g, const double *v, double *out) {
+  if (g.order == 4) return launch_apply_K4(s, g, v, out);
   const bool aligned = (((uintptr_t)v | (uintptr_t)out) & 15) == 0;  // 16-byte accesses
   if (g.dim == 2 && g.kx == nullptr && g.nx % 2 == 0 && g.nx >= 2 && aligned) {
     const dim3 grid((g.nx / 2 + SPX - 1) / SPX, (g.ny + SY - 1) / SY);
@@ -1241,16 +1267,17 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // tiles_x, t / tiles_x) of the tissue's own tiles_x), so that a tissue of a
 // ragged batch and its own context reduce the same partials in the same order;
 // blocks past a smaller tissue's tiles write zeros.
-constexpr int CTX = 64, CTY = 16, CT_THREADS = 1024;
-
-int cg_start_tiles_of(int nx, int ny) { return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY); }
-
-int cg_start_tiles(const Grid &g, int degree) {
-  if (degree < 3 || degree > 7 || g.dim != 2 || g.rag != nullptr) return 0;
-  return cg_start_tiles_of(g.nx, g.ny);
+int cg_start_tiles_of(int nx, int ny, int tile) {
+  const TileShape &ts = kCgTiles[tile];
+  return ((nx + ts.tx - 1) / ts.tx) * ((ny + ts.ty - 1) / ts.ty);
 }
 
-template <int D, bool PN>
+int cg_start_tiles(const Grid &g, int degree) {
+  if (degree != 7 || g.dim != 2 || g.rag != nullptr) return 0;
+  return cg_start_tiles_of(g.nx, g.ny, g.ctile);
+}
+
+template <int D, bool PN, int CTX, int CTY, int CT_THREADS>
 __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch cb) {
   constexpr int H = D + 1, W = CTX + 2 * H, HH = CTY + 2 * H;
   constexpr int WK = PN ? W : 1, HK = PN ? HH : 1;
@@ -1384,22 +1411,25 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch 
 }
 
 hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb, int ntiles) {
-  if (ntiles <= 0 || cb.nslices <= 0 || g.dim != 2) return hipErrorInvalidValue;
+  if (ntiles <= 0 || cb.nslices <= 0 || g.dim != 2 || cb.cstart != 7) return hipErrorInvalidValue;
   const dim3 grid(ntiles, cb.nslices);
   const bool pn = g.kx != nullptr;
-#define HSDC_CT_LAUNCH(D_)                                                                   \
-  do {                                                                                       \
-    if (pn)                                                                                  \
-      hipLaunchKernelGGL((k_cg_start_tiled<D_, true>), grid, dim3(CT_THREADS), 0, s, g, cb); \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_cg_start_tiled<D_, false>), grid, dim3(CT_THREADS), 0, s, g, cb); \
+#define HSDC_CT_LAUNCH(X_, Y_, NT_)                                                            \
+  do {                                                                                        \
+    if (pn)                                                                                   \
+      hipLaunchKernelGGL((k_cg_start_tiled<7, true, X_, Y_, NT_>), grid, dim3(NT_), 0, s, g, cb); \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_cg_start_tiled<7, false, X_, Y_, NT_>), grid, dim3(NT_), 0, s, g,   \
+                         cb);                                                                 \
   } while (0)
-  switch (cb.cstart) {
-    case 3: HSDC_CT_LAUNCH(3); break;
-    case 4: HSDC_CT_LAUNCH(4); break;
-    case 5: HSDC_CT_LAUNCH(5); break;
-    case 6: HSDC_CT_LAUNCH(6); break;
-    default: HSDC_CT_LAUNCH(7); break;
+  static_assert(kNumCgTiles == 5, "one launch per tile of kCgTiles");
+  switch (g.ctile) {
+    case 0: HSDC_CT_LAUNCH(64, 16, 1024); break;
+    case 1: HSDC_CT_LAUNCH(32, 32, 1024); break;
+    case 2: HSDC_CT_LAUNCH(32, 16, 512); break;
+    case 3: HSDC_CT_LAUNCH(32, 8, 256); break;
+    case 4: HSDC_CT_LAUNCH(16, 16, 256); break;
+    default: return hipErrorInvalidValue;
   }
 #undef HSDC_CT_LAUNCH
   return hipGetLastError();
@@ -1712,14 +1742,32 @@ hipError_t launch_prolong_correct(hipStream_t s, const Grid &gf, const Grid &gc,
   const int64_t nc = (int64_t)nslices * sYc;
   hipLaunchKernelGGL(k_sub_from, dim3(nblocks(nc)), dim3(BLOCK), 0, s, Sz, Yc, nc);
   if (sc_factor == 2 && gf.rag == nullptr) {
+    // tiles of 256 fine nodes (kProlongTiles3D / 2D[gf.ptile]); every active
+    // axis of a tile spans an even number of nodes (two per coarse cell)
+#define HSDC_PT_LAUNCH(X_, Y_, Z_)                                                              \
+  do {                                                                                         \
+    const unsigned nt = ((gf.nx + X_ - 1) / X_) * ((gf.ny + Y_ - 1) / Y_) * ((gf.nz + Z_ - 1) / Z_); \
+    hipLaunchKernelGGL((k_prolong_tiled<X_, Y_, Z_>), dim3(nt, NF, nslices), dim3(256), 0, s, gf, \
+                       gc, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);                                  \
+  } while (0)
+    static_assert(kNumProlongTiles == 4, "one launch per tile of kProlongTiles2D / 3D");
     if (gf.nz > 1) {
-      const unsigned nt = ((gf.nx + 31) / 32) * ((gf.ny + 3) / 4) * ((gf.nz + 1) / 2);
-      hipLaunchKernelGGL((k_prolong_tiled<32, 4, 2>), dim3(nt, NF, nslices), dim3(256), 0, s, gf,
-                         gc, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);
+      switch (gf.ptile) {
+        case 0: HSDC_PT_LAUNCH(32, 4, 2); break;
+        case 1: HSDC_PT_LAUNCH(64, 2, 2); break;
+        case 2: HSDC_PT_LAUNCH(16, 8, 2); break;
+        case 3: HSDC_PT_LAUNCH(16, 4, 4); break;
+        default: return hipErrorInvalidValue;
+      }
     } else if (gf.ny > 1) {
-      const unsigned nt = ((gf.nx + 31) / 32) * ((gf.ny + 7) / 8);
-      hipLaunchKernelGGL((k_prolong_tiled<32, 8, 1>), dim3(nt, NF, nslices), dim3(256), 0, s, gf,
-                         gc, Sz, sYc, Mc, Tt, Mf, i0, Yf, sYf);
+      switch (gf.ptile) {
+        case 0: HSDC_PT_LAUNCH(32, 8, 1); break;
+        case 1: HSDC_PT_LAUNCH(64, 4, 1); break;
+        case 2: HSDC_PT_LAUNCH(16, 16, 1); break;
+        case 3: HSDC_PT_LAUNCH(128, 2, 1); break;
+        default: return hipErrorInvalidValue;
+      }
+#undef HSDC_PT_LAUNCH
     } else {
       const unsigned nt = (gf.nx + 255) / 256;
       hipLaunchKernelGGL((k_prolong_tiled<256, 1, 1>), dim3(nt, NF, nslices), dim3(256), 0, s, gf,

@@ -79,6 +79,9 @@ struct LevelT {
   // the parameters of every (slice, collocation node) operator
   double *cheb_x = nullptr;      // [P][Np]
   ChebTab *cheb_tab = nullptr;   // [P][M]
+  // DCT-II solves (solver 3): transforms and eigenvalues of the level's mesh
+  DctPlan dct{};
+  bool direct = false;
   CgScalars *cg_sc = nullptr;       // [P][2]
   CgScalars *cg_sc_host = nullptr;  // [P][2]
   int cg_nblk = 0;
@@ -109,10 +112,10 @@ struct CgLogEntry {
 
 namespace {
 enum ProfClass { PC_NODE, PC_ASSEMBLE, PC_CGINIT, PC_CGITER, PC_EVAL, PC_SPMV, PC_RESIDUAL,
-                 PC_TRANSFER, PC_COPY, PC_FAS, PC_CHEB, PC_COUNT };
+                 PC_TRANSFER, PC_COPY, PC_FAS, PC_CHEB, PC_DCT, PC_COUNT };
 const char *kProfNames[PC_COUNT] = {"node_update", "assemble", "cg_init", "cg_iter", "eval_stages",
                                     "spmv", "residual", "transfer", "copy", "fas_integrals",
-                                    "cheb_iter"};
+                                    "cheb_iter", "dct_solve"};
 struct ProfPending {
   int cls;
   int launches;
@@ -140,7 +143,7 @@ struct hsdc_ctx {
   bool batch = false;
   std::vector<int64_t> tissue_N;  // nodes per slice (batch)
   int32_t *rag = nullptr;         // device [P][RAG] tissue dimensions and divisors
-  int batch_start_tiles = 0;      // most CG-start tiles of any tissue (2D batch)
+  std::vector<std::pair<int, int>> tissue_dims;  // nx, ny per slice (batch)
   int nlev = 1;
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
   double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices
@@ -180,6 +183,8 @@ struct hsdc_ctx {
   int64_t graph_sweeps = 0, graph_ionic = 0;  // counters of one captured step
   int64_t graph_steps = 0;
   double *ybak = nullptr;  // [P][NF][Np] start value of the step being replayed
+  hsdc_stats graph_delta{};  // PFASST: counters of one captured coarse part
+  int64_t coarse_redo = 0;   // PFASST coarse parts run again (a missed budgeted solve)
   // launch tuning (hsdc_tune): CG block cap and iteration-budget margin
   int tune_cg_blocks = 512;
   int tune_cg_margin = -1;  // < 0: the default of each level (cg_margin())
@@ -230,6 +235,12 @@ int cg_margin(const hsdc_ctx *c, bool tiled) {
 int (&pred_table(hsdc_ctx *c, int lev))[16][MAXM] {
   return (lev == 1 && c->cf32) ? c->Lf.cg_pred : c->L[lev].cg_pred;
 }
+int (&umax_table(hsdc_ctx *c, int lev))[16][MAXM] {
+  return (lev == 1 && c->cf32) ? c->Lf.cg_umax : c->L[lev].cg_umax;
+}
+// The level whose budgeted solves a graph replays: the fine level of a serial
+// step, the coarse level of a PFASST iteration's coarse part.
+int graph_level(const hsdc_ctx *c) { return c->pfasst ? 1 : 0; }
 
 // ---- kernel timing -----------------------------------------------------------
 void prof_harvest(hsdc_ctx *c) {
@@ -326,6 +337,10 @@ bool check_problem(const hsdc_problem *p, std::string &why) {
     if (!std::isfinite(p->g_scale[a])) return why = "g_scale must be finite", false;
   if (!std::isfinite(p->stim_amp) || !std::isfinite(p->stim_t0) || !(p->stim_dur >= 0))
     return why = "stimulus parameters must be finite, stim_dur >= 0", false;
+  if (p->fd_order != 0 && p->fd_order != 2 && p->fd_order != 4)
+    return why = "fd_order must be 2 (or 0) or 4", false;
+  if (p->fd_order == 4 && p->sigma_node)
+    return why = "fd_order 4 takes a uniform sigma (sigma_node NULL)", false;
   const double N = (double)p->nx * p->ny * p->nz;
   if (N > 2.0e9) return why = "mesh too large", false;
   return true;
@@ -350,8 +365,15 @@ bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why)
   if (!(m->cg_rtol > 0) || !(m->cg_rtol < 1)) return why = "cg_rtol must be in (0, 1)", false;
   if (m->cg_maxit < 1) return why = "cg_maxit must be >= 1", false;
   if (m->coarse_fp32 != 0 && m->coarse_fp32 != 1) return why = "coarse_fp32 must be 0 or 1", false;
-  if (m->solver < 0 || m->solver > 2)
-    return why = "solver must be 0 (CG), 1 (Chebyshev) or 2 (CG from the warm start)", false;
+  if (m->solver < 0 || m->solver > 3)
+    return why = "solver must be 0 (CG), 1 (Chebyshev), 2 (CG from the warm start) or 3 (DCT-II)",
+           false;
+  if (m->solver == 3 && p->sigma_node)
+    return why = "solver 3 (DCT-II) needs a uniform sigma", false;
+  if (m->solver == 3 && m->levels == 2 && m->coarse_fp32)
+    return why = "solver 3 (DCT-II) needs FP64 levels (coarse_fp32 0)", false;
+  if (p->fd_order == 4 && m->solver != 3)
+    return why = "fd_order 4 is solved by solver 3 (DCT-II)", false;
   if (!std::isfinite(m->coarse_cg_rtol) || !(m->coarse_cg_rtol < 1))
     return why = "coarse_cg_rtol must be finite and < 1", false;
   if (m->residual_norm != 0 && m->residual_norm != 1)
@@ -369,6 +391,10 @@ Grid make_grid(const hsdc_problem &p, int nx, int ny, int nz, double dx) {
   g.Np = pad64(g.N);
   g.fx = make_fastdiv((uint32_t)nx);
   g.fy = make_fastdiv((uint32_t)ny);
+  g.nub = kDefaultNodeBlock;
+  g.ctile = 0;
+  g.ptile = 0;
+  g.order = p.fd_order == 4 ? 4 : 2;
   const double s = 1.0 / (dx * dx * p.chi * p.Cm);
   g.cx = p.sigma[0] * s;
   g.cy = p.sigma[1] * s;
@@ -484,15 +510,59 @@ constexpr int kChebStartDegree = 3;
 // per launch against 12 us for degree 5; its solves then get no CG launch.
 constexpr int kChebStartDegreeTiled = 7;
 
+// The most CG-start tiles of any tissue of a 2D batch for tile shape `tile`
+// (0 for a context that is not a batch).
+int batch_tiles(const hsdc_ctx *c, int tile) {
+  int t = 0;
+  for (const auto &d : c->tissue_dims) t = std::max(t, cg_start_tiles_of(d.first, d.second, tile));
+  return t;
+}
+
 // Tiles per slice of the one-launch CG start on level L (0: none): FP64 levels
 // whose solver starts CG from Chebyshev steps, on 2D meshes (a ragged batch:
 // the most tiles of any tissue).
 template <class T>
 int level_start_tiles(const hsdc_ctx *c, const LevelT<T> &L) {
   if (!std::is_same<T, double>::value || c->meth.solver != 0) return 0;
-  const int tiles = L.g.rag ? (L.g.dim == 2 ? c->batch_start_tiles : 0)
+  const int tiles = L.g.rag ? (L.g.dim == 2 ? batch_tiles(c, L.g.ctile) : 0)
                             : cg_start_tiles(L.g, kChebStartDegreeTiled);
   return (tiles > 0 && tiles <= L.cg_pstride) ? tiles : 0;
+}
+
+// DCT-II transforms and eigenvalues of K on mesh g (uniform sigma), computed in
+// long double and rounded (DctPlan in hsdc_internal.h).
+DctPlan make_dct_plan(hsdc_ctx *c, const Grid &g) {
+  DctPlan d{};
+  const int nn[3] = {g.nx, g.ny, g.nz};
+  const double ca[3] = {g.cx, g.cy, g.cz};
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = nn[ax];
+    std::vector<double> C((size_t)n * n), CT((size_t)n * n), lam(n);
+    for (int k = 0; k < n; ++k) {
+      const long double sk = std::sqrt((k == 0 ? 1.0L : 2.0L) / n);
+      for (int q = 0; q < n; ++q) {
+        const double v = (double)(sk * std::cos(pi * k * (2 * q + 1) / (2.0L * n)));
+        C[(size_t)k * n + q] = v;
+        CT[(size_t)q * n + k] = v;
+      }
+      const long double th = pi * k / n;
+      const long double sym = g.order == 4
+                                  ? (-30.0L + 32.0L * std::cos(th) - 2.0L * std::cos(2.0L * th)) / 12.0L
+                                  : 2.0L * std::cos(th) - 2.0L;
+      lam[k] = n > 1 ? (double)(ca[ax] * sym) : 0.0;
+    }
+    double *dC = dalloc<double>(c, C.size()), *dCT = dalloc<double>(c, CT.size());
+    double *dl = dalloc<double>(c, lam.size());
+    HIPC(hipMemcpyAsync(dC, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+    HIPC(hipMemcpyAsync(dCT, CT.data(), CT.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+    HIPC(hipMemcpyAsync(dl, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+    HIPC(hipStreamSynchronize(c->s));  // the host vectors go out of scope
+    d.C[ax] = dC;
+    d.CT[ax] = dCT;
+    d.lam[ax] = dl;
+  }
+  return d;
 }
 
 template <class T>
@@ -516,15 +586,21 @@ void alloc_level(hsdc_ctx *c, LevelT<T> &L, int M, int P, bool coarse_extras, in
   L.cg_p = dalloc<T>(c, (size_t)P * Np);
   // partials sized for the largest block cap hsdc_tune accepts
   // (and the tiles of the CG start on a 2D mesh, or of any tissue of a batch)
-  L.cg_pstride = std::max(cg_blocks(L.g, 2 * BLOCK), node_blocks(L.g));
+  // (and the smallest node-update block and start tile hsdc_tune_shapes accepts)
+  L.cg_pstride = std::max(cg_blocks(L.g, 2 * BLOCK), node_blocks_of(L.g, 64));
   if (L.g.dim == 2)
-    L.cg_pstride = std::max<int64_t>(
-        L.cg_pstride, std::max(cg_start_tiles_of(L.g.nx, L.g.ny), c->batch_start_tiles));
+    for (int t = 0; t < kNumCgTiles; ++t)
+      L.cg_pstride = std::max<int64_t>(
+          L.cg_pstride, std::max(cg_start_tiles_of(L.g.nx, L.g.ny, t), batch_tiles(c, t)));
   // two sets, by the parity of the collocation node: a node update writes its
   // solve's set while the previous solve's set is still read (its log entry)
   L.cg_part = dalloc<double>(c, (size_t)2 * P * 5 * L.cg_pstride);
   L.cg_sc = dalloc<CgScalars>(c, (size_t)2 * P);
   L.cg_sc_host = halloc<CgScalars>(c, (size_t)2 * P);
+  if (std::is_same<T, double>::value && c->meth.solver == 3) {
+    L.dct = make_dct_plan(c, L.g);
+    L.direct = true;
+  }
   if (std::is_same<T, double>::value && (c->meth.solver == 0 || c->meth.solver == 1)) {
     L.cheb_x = dalloc<double>(c, (size_t)P * Np);
     L.cheb_tab = dalloc<ChebTab>(c, (size_t)P * M);
@@ -575,7 +651,7 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
   cb.nslices = ns;
   cb.nblk = L.cg_nblk;
   cb.nblk0 = node_blocks(L.g);  // r_0 and its partials come from the node update
-  cb.nblk_s = cb.nblk0;
+  cb.nblk_s = node_blocks_of(L.g, kDefaultNodeBlock);  // those of k_cg_start (3D meshes)
   cb.a = L.co.dt * L.co.d[i - 1];
   const double rt = level_rtol(c, lev);
   cb.tol2 = rt * rt;
@@ -583,6 +659,10 @@ CgBatchT<T> make_batch(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i
   // FP32 work vectors: solve the correction from the warm start to a relative
   // accuracy, so that the solve error shrinks with the defect
   cb.rel_r0 = (lev == 1 && c->cf32) ? 1 : 0;
+  if (L.direct) {
+    cb.direct = 1;
+    cb.bout = L.st.B + s0 * Np;
+  }
   if (L.cheb_x) {
     cb.xt = L.cheb_x + s0 * Np;
     cb.bout = L.st.B + s0 * Np;
@@ -647,11 +727,11 @@ void flush_cg_log(hsdc_ctx *c) {
     int &pred = pred_table(c, e.lev)[e.row & 15][e.i - 1];
     if (!ok_all)
       pred = std::min(c->meth.cg_maxit + 1, std::max(2 * e.budget, used + 4));
-    else if (c->graph_on && !c->prof.on && e.lev == 0) {
+    else if (c->graph_on && !c->prof.on && e.lev == graph_level(c)) {
       // graph replay (profiled steps run eagerly): raise at once, lower only at
-      // a relaxation (every 16 steps)
+      // a relaxation
       pred = std::max(pred, used + e.margin);
-      int &um = c->L[0].cg_umax[e.row & 15][e.i - 1];
+      int &um = umax_table(c, e.lev)[e.row & 15][e.i - 1];
       um = std::max(um, used);
     } else
       pred = std::max(used + e.margin, pred - 1);
@@ -721,6 +801,20 @@ CgLogArgs cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, in
                    CgBatchT<T> cb) {
   const double nodes = slice_nodes(c, L, s0, ns);
   CgLogArgs lg{};
+  if constexpr (std::is_same<T, double>::value) {
+    if (cb.direct) {
+      // exact solve in the DCT-II eigenbasis: b to the stage's V, through two
+      // [P][Np] work vectors; algorithmic work 2 n FLOP per node and axis, each way
+      const int64_t Np = L.g.Np;
+      const double fl = 4.0 * (L.g.nx + (L.g.ny > 1 ? L.g.ny : 0) + (L.g.nz > 1 ? L.g.nz : 0));
+      // (the dct_solve class counts FLOPs where the others count bytes)
+      PLAUNCH(c, PC_DCT, fl * nodes,
+              launch_dct_solve(c->s, L.g, L.dct, cb.a, cb.bout, Np, cb.x, cb.sx,
+                               L.cg_r[0] + s0 * Np, L.cg_w[0] + s0 * Np, Np, ns));
+      c->stats.cg_solves += ns;
+      return lg;
+    }
+  }
   // first CG launch index: 1 after a Chebyshev start (its vectors have parity 1)
   int k0 = 0;
   if constexpr (std::is_same<T, double>::value) {
@@ -1028,6 +1122,108 @@ void begin_block(hsdc_ctx *c) {
   c->ri_fresh = false;
 }
 
+void graph_release(hsdc_ctx *c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+void stats_add(hsdc_stats &a, const hsdc_stats &d, int sign) {
+  a.steps += sign * d.steps;
+  a.sweeps += sign * d.sweeps;
+  a.coarse_sweeps += sign * d.coarse_sweeps;
+  a.cg_solves += sign * d.cg_solves;
+  a.cg_iters += sign * d.cg_iters;
+  a.cg_unconverged += sign * d.cg_unconverged;
+  a.pfasst_iters += sign * d.pfasst_iters;
+  a.ionic_evals += sign * d.ionic_evals;
+  a.cg_redo_steps += sign * d.cg_redo_steps;
+}
+
+// Capture part() (enqueued with budgeted solves) into the context's graph; the
+// host-side counters and CG log entries it leaves are kept for the replays.
+template <class Fn>
+void capture_part(hsdc_ctx *c, Fn &&part) {
+  graph_release(c);
+  c->cg_pending.clear();
+  c->cg_log_used = 0;
+  const hsdc_stats before = c->stats;
+  HIPC(hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+  try {
+    c->safe_cg = false;
+    part();
+    c->safe_cg = true;
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    hipStreamEndCapture(c->s, &g);
+    if (g) hipGraphDestroy(g);
+    c->cg_pending.clear();
+    c->cg_log_used = 0;
+    c->stats = before;
+    c->safe_cg = true;
+    throw;
+  }
+  HIPC(hipStreamEndCapture(c->s, &c->graph));
+  HIPC(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->graph_pending = c->cg_pending;
+  c->graph_log_used = c->cg_log_used;
+  c->cg_pending.clear();
+  c->cg_log_used = 0;
+  c->graph_delta = c->stats;
+  stats_add(c->graph_delta, before, -1);
+  c->stats = before;
+  c->graph_dirty = false;
+}
+
+// The coarse part of a PFASST iteration (FAS restriction, coarse evaluations,
+// the Q^seq chain) reads the fine level and writes the coarse level only, so
+// it can run again from its start: its solves run at predicted budgets,
+// verified once at its end, and a part with a missed solve runs again with
+// every solve checked.  With graph replay on, the part is captured once and
+// replayed while the budgets it was captured with stay in force (raised at
+// once after a miss, lowered every 8 replays to the most iterations used).
+template <class T, class Fn>
+void run_coarse_part(hsdc_ctx *c, LevelT<T> &Cc, Fn &&part) {
+  int pred0[16][MAXM];
+  std::memcpy(pred0, Cc.cg_pred, sizeof(pred0));
+  const bool graph = c->graph_on && !c->prof.on;
+  c->cg_fails = 0;
+  if (graph) {
+    if (c->graph_dirty || !c->gexec) capture_part(c, part);
+    c->cg_pending = c->graph_pending;
+    c->cg_log_used = c->graph_log_used;
+    HIPC(hipGraphLaunch(c->gexec, c->s));
+    stats_add(c->stats, c->graph_delta, 1);
+  } else {
+    c->safe_cg = false;
+    try {
+      part();
+    } catch (...) {
+      c->safe_cg = true;
+      throw;
+    }
+    c->safe_cg = true;
+  }
+  flush_cg_log(c);
+  if (c->cg_fails > 0 && !c->nonfinite) {
+    c->stats.cg_redo_steps += 1;
+    c->cg_fails = 0;
+    part();
+  }
+  if (graph) {
+    c->graph_steps += 1;
+    if (c->graph_steps % 8 == 0)
+      for (int r = 0; r < 16; ++r)
+        for (int i = 0; i < MAXM; ++i)
+          if (Cc.cg_umax[r][i] >= 0) {
+            Cc.cg_pred[r][i] = Cc.cg_umax[r][i] + cg_margin(c, Cc.tiled_start);
+            Cc.cg_umax[r][i] = -1;
+          }
+    if (std::memcmp(pred0, Cc.cg_pred, sizeof(pred0)) != 0) c->graph_dirty = true;
+  }
+}
+
 hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
   Level &F = c->L[0];
   const int P = F.P;
@@ -1040,18 +1236,21 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
       if (st != HSDC_OK) throw StatusFail{st};
     }
     const int64_t sRIc = (int64_t)Mc * NF * Cc.g.Np;
-    PLAUNCH(c, PC_TRANSFER, 8.0 * P * Mc * NF * ((double)F.g.N + Cc.g.N),
-            launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
-                                   (int64_t)Mc * NF * F.g.Np, Cc.RI, sRIc, Mc * NF, P));
-    restrict_fine_to_coarse(c, Cc);
-    evaluate_all(c, Cc, 1, 0, P);
-    PLAUNCH(c, PC_FAS, 8.0 * (3.0 * Mc * NF + Mc + NG) * Cc.g.N * P,
-            launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, 0, P, Cc.RI, sRIc));
-    for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
-      gather_starts(c, Cc, Cc.y0c, n, 1);
-      // the right-hand side is evaluated at S z (kept in Sz until the correction)
-      sweep(c, Cc, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, 14, true, Cc.Sz);
-    }
+    run_coarse_part(c, Cc, [&]() {
+      PLAUNCH(c, PC_TRANSFER, 8.0 * P * Mc * NF * ((double)F.g.N + Cc.g.N),
+              launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
+                                     (int64_t)Mc * NF * F.g.Np, Cc.RI, sRIc, Mc * NF, P));
+      restrict_fine_to_coarse(c, Cc);
+      evaluate_all(c, Cc, 1, 0, P);
+      PLAUNCH(c, PC_FAS, 8.0 * (3.0 * Mc * NF + Mc + NG) * Cc.g.N * P,
+              launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, 0, P, Cc.RI, sRIc));
+      for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
+        gather_starts(c, Cc, Cc.y0c, n, 1);
+        // the right-hand side is evaluated at S z (kept in Sz until the
+        // correction); budgets per slice (rows 0..13; the burn-in has row 15)
+        sweep(c, Cc, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, n % 14, true, Cc.Sz);
+      }
+    });
     coarse_correct_fine(c, Cc, 1);
   });
   // Q^par on the fine level: start values from the (corrected) iterate
@@ -1074,12 +1273,6 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
 // ---------------------------------------------------------------------------
 // graph replay of serial steps
 // ---------------------------------------------------------------------------
-void graph_release(hsdc_ctx *c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->graph) hipGraphDestroy(c->graph);
-  c->gexec = nullptr;
-  c->graph = nullptr;
-}
 
 // Capture one serial step from the state begin_serial_step leaves: save y_n,
 // max_iter budgeted sweeps, y_{n+1} = y_{n,M}, advance the device step
@@ -1312,6 +1505,8 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
   if (!check_method(meth, &probs[0], why)) return fail(nullptr, HSDC_EINVAL, why);
   if (meth->levels != 1 || meth->P != 1)
     return fail(nullptr, HSDC_EINVAL, "a batch takes levels = 1 and P = 1 (serial steps)");
+  if (meth->solver == 3)
+    return fail(nullptr, HSDC_EINVAL, "a batch solves by CG or Chebyshev (solver 0..2), not DCT-II");
   const hsdc_problem &p0 = probs[0];
   for (int n = 1; n < count; ++n) {
     const hsdc_problem &q = probs[n];
@@ -1351,9 +1546,7 @@ hsdc_status hsdc_init_batch(const hsdc_problem *probs, int32_t count, const hsdc
     F.g = make_grid(p0, probs[big].nx, probs[big].ny, probs[big].nz, p0.dx);
     if (!make_colloc(meth->M[0], meth->dt, F.co))
       return fail(c, HSDC_EINVAL, "Radau node computation failed");
-    for (int n = 0; n < count; ++n)
-      c->batch_start_tiles =
-          std::max(c->batch_start_tiles, cg_start_tiles_of(probs[n].nx, probs[n].ny));
+    for (int n = 0; n < count; ++n) c->tissue_dims.push_back({probs[n].nx, probs[n].ny});
     alloc_level(c, F, meth->M[0], count, false, 0);
     const int64_t Np = F.g.Np;
     c->rag = dalloc<int32_t>(c, dims.size());
@@ -1443,19 +1636,48 @@ hsdc_status hsdc_tune(hsdc_ctx *c, int32_t cg_blocks_cap, int32_t cg_margin) {
     }
   }
   if (cg_margin >= 0) c->tune_cg_margin = cg_margin;
+  c->graph_dirty = true;
+  return HSDC_OK;
+}
+
+hsdc_status hsdc_tune_shapes(hsdc_ctx *c, int32_t node_block, int32_t cg_tile,
+                             int32_t prolong_tile) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  if (node_block != 0 && node_block != 64 && node_block != 128 && node_block != 256 &&
+      node_block != 512)
+    return fail(c, HSDC_EINVAL, "node_block must be 0, 64, 128, 256 or 512");
+  if (cg_tile < -1 || cg_tile >= kNumCgTiles)
+    return fail(c, HSDC_EINVAL, "cg_tile must be -1 or 0..4");
+  if (prolong_tile < -1 || prolong_tile >= kNumProlongTiles)
+    return fail(c, HSDC_EINVAL, "prolong_tile must be -1 or 0..3");
+  // FP64 levels; an FP32 coarse level keeps the default shapes
+  for (int l = 0; l < c->nlev; ++l) {
+    if (l == 1 && c->cf32) continue;
+    Grid &g = c->L[l].g;
+    if (node_block > 0) g.nub = node_block;
+    if (cg_tile >= 0) g.ctile = cg_tile;
+  }
+  // the correction into the fine level
+  if (prolong_tile >= 0) c->L[0].g.ptile = prolong_tile;
+  for (int l = 0; l < c->nlev; ++l)
+    if (!(l == 1 && c->cf32)) c->L[l].tiled_start = level_start_tiles(c, c->L[l]) > 0;
+  c->graph_dirty = true;
   return HSDC_OK;
 }
 
 hsdc_status hsdc_use_graph(hsdc_ctx *c, int32_t on) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
-  if (on && c->pfasst) return fail(c, HSDC_EINVAL, "graph replay is for serial and batch contexts");
+  if (on && c->pfasst && c->nlev < 2)
+    return fail(c, HSDC_EINVAL, "PFASST graph replay captures the coarse part: needs 2 levels");
   if (on && c->s == nullptr)
     return fail(c, HSDC_EINVAL, "graph replay needs a context created on a non-null stream");
   Level &F = c->L[0];
-  if (on && (int64_t)c->meth.max_iter * F.co.M * F.P > c->cg_log_cap)
-    return fail(c, HSDC_EINVAL, "a step has more solves than the CG log holds");
+  const int64_t solves = c->pfasst ? (int64_t)c->meth.M[1] * F.P
+                                   : (int64_t)c->meth.max_iter * F.co.M * F.P;
+  if (on && solves > c->cg_log_cap)
+    return fail(c, HSDC_EINVAL, "a captured part has more solves than the CG log holds");
   return run_guarded(c, [&]() -> hsdc_status {
-    if (on && !c->ybak) c->ybak = dalloc<double>(c, (size_t)F.P * NF * F.g.Np);
+    if (on && !c->ybak && !c->pfasst) c->ybak = dalloc<double>(c, (size_t)F.P * NF * F.g.Np);
     if (!on) graph_release(c);
     c->graph_on = on != 0;
     c->graph_dirty = true;
@@ -1806,6 +2028,8 @@ hsdc_status hsdc_diffusion_solve_noalloc(const hsdc_problem *prob, double a, con
     return fail(nullptr, HSDC_EINVAL, "bad arguments");
   if ((int64_t)prob->nx * prob->ny * prob->nz > kNaNodes)
     return fail(nullptr, HSDC_EINVAL, "mesh larger than HSDC_NOALLOC_MAX_NODES");
+  if (prob->fd_order == 4)
+    return fail(nullptr, HSDC_EINVAL, "the no-allocation solve is CG on the second-order stencil");
   double *base = nullptr;
   hsdc_status st = scratch_address(&base);
   if (st != HSDC_OK) return st;
@@ -1874,6 +2098,15 @@ hsdc_status hsdc_diffusion_solve(const hsdc_problem *prob, double a, const doubl
     L.g = make_grid(*prob, prob->nx, prob->ny, prob->nz, prob->dx);
     if (prob->sigma_node) build_faces(&tmp, L, prob->sigma_node);
     const int64_t Np = L.g.Np;
+    if (L.g.order == 4) {
+      // the fourth-order stencil: the exact DCT-II solve (no iterations)
+      const DctPlan d = make_dct_plan(&tmp, L.g);
+      double *t1 = dalloc<double>(&tmp, Np), *t2 = dalloc<double>(&tmp, Np);
+      HIPC(launch_dct_solve(tmp.s, L.g, d, a, b, Np, x, Np, t1, t2, Np, 1));
+      HIPC(hipStreamSynchronize(tmp.s));  // the plan and work vectors are freed below
+      conv = true;
+      return HSDC_OK;
+    }
     L.cg_nblk = cg_blocks(L.g);
     CgBatch cb{};
     cb.x = x;
@@ -2069,6 +2302,9 @@ hsdc_status hsdc_misfit_forward(const hsdc_problem *prob, const hsdc_method *met
   if (meth->levels != 1 || meth->P != 1)
     return fail(nullptr, HSDC_EINVAL, "the adjoint is of serial hybrid SDC (levels = 1, P = 1)");
   if (meth->M[0] > 6) return fail(nullptr, HSDC_EINVAL, "the adjoint takes M <= 6");
+  if (prob->fd_order == 4 || meth->solver == 3)
+    return fail(nullptr, HSDC_EINVAL,
+                "the adjoint takes the second-order stencil and an iterative solver (0..2)");
   if (nsteps < 1 || sample_every < 1 || nprobes < 1 || !probes || !targets)
     return fail(nullptr, HSDC_EINVAL, "nsteps, sample_every, nprobes >= 1 and probes, targets needed");
   hsdc_ctx *c = nullptr;

@@ -34,7 +34,7 @@ class Problem(ctypes.Structure):
                 ("sigma_node", ctypes.c_void_p), ("chi", ctypes.c_double), ("Cm", ctypes.c_double),
                 ("g_scale", ctypes.c_double * 3), ("stim_w", ctypes.c_void_p),
                 ("stim_amp", ctypes.c_double), ("stim_t0", ctypes.c_double),
-                ("stim_dur", ctypes.c_double)]
+                ("stim_dur", ctypes.c_double), ("fd_order", ctypes.c_int32)]
 
 
 class Method(ctypes.Structure):
@@ -75,6 +75,7 @@ def lib():
                                 ctypes.POINTER(vp)],
             "hsdc_sdc_sweep": [vp, i32, i32, i32],
             "hsdc_tune": [vp, i32, i32],
+            "hsdc_tune_shapes": [vp, i32, i32, i32],
             "hsdc_use_graph": [vp, i32],
             "hsdc_advance": [vp, i32],
             "hsdc_pfasst_iter": [vp, vp, vp],
@@ -142,8 +143,10 @@ def _dev(t, name, shape=None):
 
 
 def make_problem(dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None, chi=1400.0, Cm=1.0,
-                 g_scale=(1.0, 1.0, 1.0), stim_w=None, stim_amp=0.0, stim_t0=0.0, stim_dur=0.0):
-    """hsdc_problem for a cell-centred mesh of `dims` nodes (x fastest)."""
+                 g_scale=(1.0, 1.0, 1.0), stim_w=None, stim_amp=0.0, stim_t0=0.0, stim_dur=0.0,
+                 fd_order=2):
+    """hsdc_problem for a cell-centred mesh of `dims` nodes (x fastest);
+    fd_order 4 selects the fourth-order stencil (uniform sigma)."""
     dims = tuple(int(n) for n in dims)
     p = Problem()
     p.dim = len(dims)
@@ -161,11 +164,12 @@ def make_problem(dims, dx, sigma=(1.0, 1.0, 1.0), sigma_node=None, chi=1400.0, C
         p.stim_w = _dev(stim_w, "stim_w", (N,))
         p._keep.append(stim_w)
     p.stim_amp, p.stim_t0, p.stim_dur = float(stim_amp), float(stim_t0), float(stim_dur)
+    p.fd_order = int(fd_order)
     p.N = N
     return p
 
 
-SOLVERS = {"cg": 0, "chebyshev": 1, "cg_plain": 2}
+SOLVERS = {"cg": 0, "chebyshev": 1, "cg_plain": 2, "dct": 3}
 RESIDUAL_NORMS = {"global": 0, "per_field": 1}
 
 
@@ -211,8 +215,15 @@ class Context:
         following solves."""
         _check(lib().hsdc_tune(self.handle, int(cg_blocks), int(cg_margin)), self.handle)
 
+    def tune_shapes(self, node_block=0, cg_tile=-1, prolong_tile=-1):
+        """Node-update block size (0 keeps), CG-start tile and correction tile
+        (indices of the tables in include/hsdc.h; -1 keeps)."""
+        _check(lib().hsdc_tune_shapes(self.handle, int(node_block), int(cg_tile),
+                                      int(prolong_tile)), self.handle)
+
     def use_graph(self, on=True):
-        """Replay serial steps from a captured HIP graph (needs a non-null stream)."""
+        """Replay serial steps, or the coarse part of PFASST iterations, from a
+        captured HIP graph (needs a non-null stream)."""
         _check(lib().hsdc_use_graph(self.handle, 1 if on else 0), self.handle)
 
     def sdc_sweep(self, nsweeps=1, level=0, slice=0):

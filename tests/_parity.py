@@ -14,7 +14,7 @@ def oracle_problem(w, dims=None, dx=None):
     stim = w["stim_w"] if dims == tuple(w["dims"]) else restrict_space(w["stim_w"], w["dims"])
     return Monodomain(dims, dx or w["dx"], w["sigma"], w.get("sigma_node"), w["chi"], w["Cm"], stim,
                       w["stim_amp"], w["stim_t0"], w["stim_dur"], g_scale=w.get("g_scale", (1, 1, 1)),
-                      dt_ref=w["dt"])
+                      dt_ref=w["dt"], fd_order=w.get("fd_order", 2))
 
 
 def oracle_hierarchy(w, Mf, Mc, coarsen):

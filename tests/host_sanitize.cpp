@@ -89,6 +89,9 @@ int main() {
         {1, 16, 1, 1, 0.025, 1, 1400, 1, 1, -1},  {3, 2000, 2000, 2000, 0.025, 1, 1400, 1, 1, 1},
         {1, -5, 1, 1, 0.025, 1, 1400, 1, 1, 1},
     };
+    p = problem(2, 16, 16, 1);
+    p.fd_order = 3;
+    EXPECT(rejected_init(p, m));
     for (const Bad &b : bad) {
       p = problem(b.dim, b.nx, b.ny, b.nz);
       p.dx = b.dx;
@@ -106,7 +109,9 @@ int main() {
   {
     const hsdc_problem p = problem(3, 8, 6, 4);
     const hsdc_problem podd = problem(2, 15, 16, 1);
-    for (int k = 0; k < 20; ++k) {
+    hsdc_problem p4 = problem(2, 16, 16, 1);
+    p4.fd_order = 4;
+    for (int k = 0; k < 22; ++k) {
       hsdc_method b = method();
       const hsdc_problem *pp = &p;
       switch (k) {
@@ -127,9 +132,11 @@ int main() {
         case 14: b.cg_rtol = 1.0; break;
         case 15: b.cg_maxit = 0; break;
         case 16: b.levels = 2; b.P = 2; b.coarse_fp32 = 2; break;
-        case 17: b.solver = 3; break;
+        case 17: b.solver = 4; break;
         case 18: b.coarse_cg_rtol = 2.0; break;
         case 19: b.residual_norm = 2; break;
+        case 20: b.solver = 3; b.levels = 2; b.P = 2; b.coarse_fp32 = 1; break;
+        case 21: b.solver = 0; pp = &p4; break;  // the fourth-order stencil needs DCT-II
       }
       EXPECT(rejected_init(*pp, b));
     }

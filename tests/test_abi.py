@@ -17,7 +17,7 @@ def test_header_symbols_exported():
 
 def test_struct_layout_matches_header():
     # field order and C types of the two public structs
-    assert ctypes.sizeof(H.Problem) == 4 * 4 + 8 + 24 + 8 + 8 + 8 + 24 + 8 + 24
+    assert ctypes.sizeof(H.Problem) == 4 * 4 + 8 + 24 + 8 + 8 + 8 + 24 + 8 + 24 + 8
     assert [f for f, _ in H.Problem._fields_][:5] == ["dim", "nx", "ny", "nz", "dx"]
     assert ctypes.sizeof(H.Stats) == 9 * 8
     # levels, M[2], space_coarsen, P | dt | max_iter | tol | burn_in, solver |
@@ -52,12 +52,32 @@ def test_bad_problem_is_einval(bad):
     dict(M=(0, 1)), dict(M=(9, 1)), dict(dt=0.0), dict(max_iter=0), dict(cg_rtol=0.0),
     dict(levels=3), dict(levels=1, P=4), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
     dict(levels=2, M=(4, 2), P=2, coarse_fp32=2), dict(levels=2, M=(4, 2), P=2, coarse_cg_rtol=1.0),
-    dict(solver=3), dict(solver=-1), dict(residual_norm=2),
+    dict(solver=4), dict(solver=-1), dict(residual_norm=2),
+    dict(levels=2, M=(4, 2), P=2, solver=3, coarse_fp32=1),
 ])
 def test_bad_method_is_einval(bad):
     p = H.make_problem((15,), 0.01)
     code, ptr = _init(p, H.make_method(**bad))
     assert code == -1 and not ptr.value
+
+
+@pytest.mark.parametrize("case", ["order3", "order4_cg", "order4_pernode", "dct_pernode"])
+def test_fourth_order_and_dct_arguments_are_checked(case):
+    """fd_order is 2 or 4; the fourth-order stencil needs a uniform sigma and
+    the DCT-II solver (solver 3), which needs a uniform sigma too."""
+    p = H.make_problem((16, 8), 0.025, fd_order=4)
+    m = H.make_method(M=4, solver="dct")
+    if case == "order3":
+        p.fd_order = 3
+    elif case == "order4_cg":
+        m = H.make_method(M=4)
+    else:
+        p.sigma_node = 8  # never dereferenced: rejected before any device work
+        if case == "dct_pernode":
+            p.fd_order = 2
+    code, ptr = _init(p, m)
+    assert code == -1 and not ptr.value
+    assert H.lib().hsdc_last_error(None)
 
 
 def test_null_context_calls_are_einval():

@@ -32,7 +32,8 @@ def lib_problem(w, dims=None):
     dims = tuple(dims or w["dims"])
     sn = None if w.get("sigma_node") is None else dev(w["sigma_node"])
     return H.make_problem(dims, w["dx"], w["sigma"], sn, w["chi"], w["Cm"], w.get("g_scale", (1, 1, 1)),
-                          dev(w["stim_w"]), w["stim_amp"], w["stim_t0"], w["stim_dur"])
+                          dev(w["stim_w"]), w["stim_amp"], w["stim_t0"], w["stim_dur"],
+                          fd_order=w.get("fd_order", 2))
 
 
 # ---------------------------------------------------------------------------
@@ -541,6 +542,99 @@ def test_tuned_launch_shapes_give_the_same_run():
     b.advance(12)
     e = field_errors(host(b.get_state(0, 0, 0)), host(a.get_state(0, 0, 0)))
     assert np.max(e) < 1e-11
+
+
+@pytest.mark.parametrize("pernode", [False, True])
+def test_tuned_block_and_tile_shapes_give_the_same_run(pernode):
+    """Every node-update block size and every CG-start tile (uniform and
+    per-node sigma, a mesh whose edges cut the tiles) gives the default run up
+    to the order of the reductions over blocks and tiles; bad shapes are
+    rejected before any work."""
+    # a tissue with per-node lognormal sigma, or the uniform slab, 61 x 47
+    w = si.batch2d_tissues(1, seed=3, lo=61, hi=61)[0] if pernode else si.workload("slab2d",
+                                                                                   dims=(61, 47))
+    prob = lib_problem(w)
+    m = H.make_method(M=6, dt=w["dt"], max_iter=6, cg_rtol=1e-13, cg_maxit=300)
+    ref = H.Context(prob, m)
+    ref.advance(8)
+    y_ref = host(ref.get_state(0, 0, 0))
+    ref.destroy()
+    shapes = [(nb, 0) for nb in (64, 128, 512)] + [(256, t) for t in (1, 2, 3, 4)] + [(64, 4)]
+    for nb, tile in shapes:
+        c = H.Context(prob, m)
+        c.tune_shapes(nb, tile, -1)
+        c.advance(8)
+        e = field_errors(host(c.get_state(0, 0, 0)), y_ref)
+        st = c.stats()
+        c.destroy()
+        assert np.max(e) < 1e-11, (nb, tile, np.max(e))
+        assert st["cg_unconverged"] == 0
+    c = H.Context(prob, m)
+    for bad in ((96, -1, -1), (0, 5, -1), (0, -1, 4), (1024, 0, 0)):
+        with pytest.raises(H.HsdcError):
+            c.tune_shapes(*bad)
+    c.destroy()
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 4), (36, 18)])
+def test_tuned_correction_tiles_give_the_same_iterates(dims):
+    """Every tile of the coarse-to-fine correction (3D and 2D) and a smaller
+    node-update block give the default PFASST iterates, and those match the
+    oracle's Algorithm 1 iterate by iterate."""
+    P = 4
+    w, h, y0, m = _pfasst_case(dims, 6, 3, 2, P, 0.1)
+    z, _, _ = pfasst_block(h, y0, P, 3, tol=0.0)
+    for tile in range(4):
+        ctx = H.Context(lib_problem(w), m, dev(y0))
+        ctx.tune_shapes(128 if tile == 3 else 0, -1, tile)
+        for _ in range(3):
+            ctx.pfasst_iter()
+        for n in range(P):
+            for j in (0, h.levels[0].M):
+                e = field_errors(host(ctx.get_state(0, n, j)), z[n][j])
+                assert np.max(e) < 1e-10, (tile, n, j, np.max(e))
+        ctx.destroy()
+
+
+@pytest.mark.parametrize("coarse_fp32", [False, True])
+def test_pfasst_graph_replay_equals_eager_iterations(coarse_fp32):
+    """PFASST with the coarse part of each iteration (FAS restriction, coarse
+    evaluations, the Q^seq chain with budgeted solves) replayed from a captured
+    HIP graph gives the eager iterates exactly: budgets change only how many
+    no-op CG launches follow convergence, and a missed budget reruns the part
+    with every solve checked.  Whole blocks with the stop test too."""
+    stream = torch.cuda.Stream()
+    P = 4
+    w, h, y0, m = _pfasst_case((8, 6, 4), 6, 3, 2, P, 0.1)
+    m.coarse_fp32 = int(coarse_fp32)
+    a = H.Context(lib_problem(w), m, dev(y0), stream)
+    b = H.Context(lib_problem(w), m, dev(y0), stream)
+    b.use_graph(True)
+    for k in range(12):
+        ra, _ = a.pfasst_iter()
+        rb, _ = b.pfasst_iter()
+        assert np.array_equal(ra, rb), (k, ra, rb)
+    for n in range(P):
+        for j in (0, 3, 6):
+            e = field_errors(host(b.get_state(0, n, j)), host(a.get_state(0, n, j)))
+            assert np.max(e) == 0.0, (n, j, np.max(e))
+    sa, sb = a.stats(), b.stats()
+    assert sa["pfasst_iters"] == sb["pfasst_iters"] == 12
+    assert sa["coarse_sweeps"] == sb["coarse_sweeps"]
+    assert sa["cg_unconverged"] == sb["cg_unconverged"] == 0
+    a.destroy()
+    b.destroy()
+    m.tol, m.max_iter = 1e-9, 60
+    a = H.Context(lib_problem(w), m, dev(y0), stream)
+    b = H.Context(lib_problem(w), m, dev(y0), stream)
+    b.use_graph(True)
+    a.advance(2)
+    b.advance(2)
+    e = field_errors(host(b.get_state(0, 0, 0)), host(a.get_state(0, 0, 0)))
+    assert np.max(e) == 0.0
+    assert a.stats()["pfasst_iters"] == b.stats()["pfasst_iters"]
+    a.destroy()
+    b.destroy()
 
 
 @pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])

@@ -33,7 +33,8 @@ def sanitized_exe(tmp_path_factory):
     if not (os.path.exists(CLANG) and shutil.which(B.hipcc()) or os.path.exists(B.hipcc())):
         pytest.skip("hipcc / clang++ not available")
     bdir = os.path.join(B.HERE, "_build")
-    kernels = [os.path.join(bdir, n) for n in ("hsdc_kernels.o", "hsdc_adjoint.o")]
+    kernels = [os.path.join(bdir, os.path.splitext(n)[0] + ".o") for n in B.SOURCES
+               if n.endswith(".hip")]
     if not all(os.path.exists(k) for k in kernels):
         B.build()
     out = tmp_path_factory.mktemp("san")

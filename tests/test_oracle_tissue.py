@@ -24,6 +24,58 @@ def test_laplacian_solve_matches_dct(dims, sigma):
     assert np.max(np.abs(x - x_dct)) < 1e-12 * np.max(np.abs(b))
 
 
+@pytest.mark.parametrize("dims,sigma", [((37,), (1.0,)), ((12, 9), (1.0, 2.0)),
+                                        ((8, 6, 5), (3.0, 1.0, 0.5)), ((3,), (1.0,))])
+def test_fourth_order_laplacian_solve_matches_dct(dims, sigma):
+    """The fourth-order operator is symmetric, annihilates constants, and its
+    LU solve equals the DCT-II solve with the eigenvalues of its symbol."""
+    dx = 0.025
+    sg = tuple(sigma) + (1.0,) * (3 - len(sigma))
+    A = laplacian(dims, dx, sg, order=4)
+    assert abs(A - A.T).max() < 1e-9 * abs(A).max()
+    assert np.max(np.abs(A @ np.ones(A.shape[0]))) < 1e-9
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(A.shape[0])
+    a = 0.05 * 0.2 / 1400.0
+    x = ImplicitSolver(A).solve(b, a)
+    x_dct = dct_solve_uniform(dims, dx, sg, a, b, order=4)
+    assert np.max(np.abs(x - x_dct)) < 1e-12 * np.max(np.abs(b))
+
+
+def test_fourth_order_eigenvalues_and_rows():
+    """The dense spectrum of the 1D mirrored operator equals its symbol at
+    theta = pi k / n (so the DCT-II basis diagonalises it); an interior row is
+    the five-point stencil and the first rows fold the mirror in."""
+    from oracle.tissue import dct_eigenvalues, second_difference_4
+    for n in (1, 2, 5, 12):
+        ev = np.sort(np.linalg.eigvalsh(second_difference_4(n)))
+        assert np.max(np.abs(ev - np.sort(dct_eigenvalues(n, 4)))) < 1e-12
+    D = 12.0 * second_difference_4(7)
+    assert np.allclose(D[3], [0, -1, 16, -30, 16, -1, 0], atol=0)
+    assert np.allclose(D[0], [-14, 15, -1, 0, 0, 0, 0], atol=0)   # V_-1 = V_0, V_-2 = V_1
+    assert np.allclose(D[1], [15, -30, 16, -1, 0, 0, 0], atol=0)
+    assert np.allclose(D[6], D[0][::-1], atol=0)
+
+
+@pytest.mark.parametrize("order,rate", [(2, 2.0), (4, 4.0)])
+def test_laplacian_order_of_accuracy_on_a_no_flux_field(order, rate):
+    """On V = cos(pi x / L) cos(2 pi y / L), whose odd derivatives vanish at the
+    walls (so the mirrored field is smooth), the error of A V against the
+    exact Laplacian falls with dx^order."""
+    L = 1.0
+    errs = []
+    for n in (16, 32, 64):
+        dx = L / n
+        x = (np.arange(n) + 0.5) * dx
+        X, Y = np.meshgrid(x, x)
+        V = np.cos(np.pi * X / L) * np.cos(2 * np.pi * Y / L)
+        exact = -((np.pi / L) ** 2 + (2 * np.pi / L) ** 2) * V
+        AV = laplacian((n, n), dx, order=order) @ V.ravel()
+        errs.append(np.max(np.abs(AV - exact.ravel())))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(rates - rate) < 0.15), rates
+
+
 def test_laplacian_stencil_rows():
     """Interior row of the 5-point stencil and a no-flux corner row."""
     dx = 0.5
