@@ -85,6 +85,10 @@ def _args():
     ap.add_argument("--tols", type=float, nargs="+", default=[1e-8, 3e-9, 1e-9, 3e-10, 1e-10],
                     help="slab3d: per-field PFASST residual tolerances tried, loosest first")
     ap.add_argument("--max-iter", type=int, default=80, help="slab3d: PFASST iterations cap")
+    ap.add_argument("--pfasst-only", action="store_true",
+                    help="slab3d: time the PFASST blocks alone (no reference runs; for profilers)")
+    ap.add_argument("--levels", type=int, choices=(2, 3), default=2,
+                    help="slab3d: PFASST levels (3: M 6/3/1, FP64)")
     ap.add_argument("--coarse", choices=("fp32", "fp64"), default="fp32",
                     help="slab3d: precision of the coarse level's cell model, reaction terms and "
                          "CG vectors (the fine level, residual and tau stay FP64)")
@@ -284,8 +288,12 @@ def bench_slab3d(a):
     prob = H.make_problem(w["dims"], w["dx"], w["sigma"], None, w["chi"], w["Cm"], (1, 1, 1), stim,
                           w["stim_amp"], w["stim_t0"], w["stim_dur"])
 
+    Ms = (w["M"], w["Mc"], 1) if a.levels == 3 else (w["M"], w["Mc"])
+    if a.levels == 3:
+        fp32 = False  # three levels run in FP64
+
     def pfasst_method(tol):
-        return H.make_method(M=(w["M"], w["Mc"]), levels=2, space_coarsen=a.coarsen, P=P, dt=dt,
+        return H.make_method(M=Ms, levels=a.levels, space_coarsen=a.coarsen, P=P, dt=dt,
                              max_iter=a.max_iter, tol=tol, burn_in=1, cg_rtol=w["cg_rtol"],
                              cg_maxit=500, coarse_fp32=fp32, solver=a.solver,
                              residual_norm="per_field")
@@ -315,6 +323,15 @@ def bench_slab3d(a):
         res.sort(key=lambda r: r[1])
         return res[len(res) // 2]
 
+    if a.pfasst_only:
+        # the PFASST blocks alone, at the first tolerance of --tols (for profilers)
+        run(pfasst_method(a.tols[0]), 1)  # warm-up
+        y, wall, st = run(pfasst_method(a.tols[0]), a.blocks)
+        print(json.dumps({"workload": "slab3d PFASST blocks only", "levels": a.levels,
+                          "M": list(Ms), "coarse_fp32": fp32, "tol_per_field": a.tols[0],
+                          "blocks": a.blocks, "wall_s": wall,
+                          "pfasst_iters": st["pfasst_iters"], "sim_ms_per_wall_s": T / wall}))
+        return
     # the error reference: serial hybrid SDC swept to its collocation solution
     ref, wall_ref, _ = run(serial_method(40, 1e-13), nsteps)
     tries = []
@@ -333,10 +350,12 @@ def bench_slab3d(a):
     err_pf = _field_error(y_pf, ref)
     # the other launch mode once: the coarse part of each iteration from a
     # captured graph, or eagerly
-    y_o, wall_o, st_o = run(pfasst_method(chosen), a.blocks, graph=not a.graph)
-    other_mode = {"graph_replay": not a.graph, "wall_s": wall_o,
-                  "sim_ms_per_wall_s": T / wall_o, "pfasst_iters": st_o["pfasst_iters"],
-                  "same_result": bool(torch.equal(y_o, y_pf))}
+    other_mode = None
+    if a.levels == 2:
+        y_o, wall_o, st_o = run(pfasst_method(chosen), a.blocks, graph=not a.graph)
+        other_mode = {"graph_replay": not a.graph, "wall_s": wall_o,
+                      "sim_ms_per_wall_s": T / wall_o, "pfasst_iters": st_o["pfasst_iters"],
+                      "same_result": bool(torch.equal(y_o, y_pf))}
     serial = None
     for K in range(2, 21):
         y_s, wall_s, _ = run(serial_method(K, w["cg_rtol"]), nsteps)
@@ -370,8 +389,9 @@ def bench_slab3d(a):
                 "unit": "GB/s", "frac": kernels[dom]["GBps"] / 8000.0, "traffic": None}
     value = T / wall_pf
     out = {
-        "metric": "simulated ms per wall-s at fixed error (two-level PFASST, "
-                  + ("FP32 coarse level)" if fp32 else "FP64)"),
+        "metric": "simulated ms per wall-s at fixed error ("
+                  + ("three-level PFASST, FP64)" if a.levels == 3 else
+                     "two-level PFASST, " + ("FP32 coarse level)" if fp32 else "FP64)")),
         "value": value,
         "unit": "sim-ms/s",
         "n_gpus": 1,
@@ -384,9 +404,9 @@ def bench_slab3d(a):
         "dtype": "f64+f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": "slab3d 192x96x48, 7-point sigma (3,1,1), TTP06, PFASST P16 "
-                               f"M 6/3, coarse mesh /{a.coarsen}, dt 0.1 ms, per-field error "
-                               f"<= {a.eps:g}",
-                   "nodes": N, "P": P, "M": [w["M"], w["Mc"]], "space_coarsen": a.coarsen,
+                               f"M {'/'.join(str(x) for x in Ms)}, coarse mesh /{a.coarsen} per "
+                               f"level, dt 0.1 ms, per-field error <= {a.eps:g}",
+                   "nodes": N, "P": P, "M": list(Ms), "space_coarsen": a.coarsen,
                    "coarse_fp32": fp32, "solver": a.solver, "blocks": a.blocks,
                    "t_simulated_ms": T, "eps": a.eps, "tol_per_field": chosen},
         "tol_search": tries,

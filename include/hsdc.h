@@ -84,9 +84,11 @@ typedef struct {
 
 /* Method (Sec. 3, Algorithm 1). */
 typedef struct {
-  int32_t levels;            /* 1 (serial HSDC) or 2 (two-level PFASST)           */
-  int32_t M[2];              /* Radau IIA nodes per level, M[0] fine, 1..8        */
-  int32_t space_coarsen;     /* 1, or 2: coarse level on the mesh coarsened 2x    */
+  int32_t levels;            /* 1 (serial HSDC), 2 (two-level PFASST) or 3        */
+                             /* (three levels, FP64, Sec. 5.1: M = 6, 3, 1)       */
+  int32_t M[3];              /* Radau IIA nodes per level, M[0] fine, 1..8        */
+  int32_t space_coarsen;     /* 1, or 2: every coarser level on the mesh of the   */
+                             /* finer one coarsened 2x                            */
   int32_t P;                 /* time slices per block (1 for serial HSDC)         */
   double dt;                 /* step size per slice, ms                           */
   int32_t max_iter;          /* sweeps per step (levels = 1, P = 1) or maximum    */

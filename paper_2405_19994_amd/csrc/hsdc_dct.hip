@@ -12,7 +12,8 @@
 // pi k / n times sigma_axis / (dx^2 chi Cm)).  Each axis transform is a dense
 // product of the n x n matrix with the mesh lines along that axis, run on the
 // FP64 matrix cores (v_mfma_f64_16x16x4f64): 32 x 32 output tiles per block of
-// four waves, the contraction split over the waves and summed in LDS.
+// sixteen waves, the contraction split over the waves (four waves per SIMD
+// hide each other's operand loads) and summed in LDS.
 #include <hip/hip_runtime.h>
 
 #include "hsdc_device.h"
@@ -115,10 +116,12 @@ struct Xform {
 };
 
 constexpr int XT = 32;  // output tile edge
+constexpr int XW = 16;  // waves per block, each a share of the contraction
+constexpr int KU = 4;   // steps of 4 per group of loads
 
 template <bool ROWS>
-__global__ void __launch_bounds__(256) k_xform(Xform f) {
-  __shared__ double red[4][XT * XT];
+__global__ void __launch_bounds__(64 * XW) k_xform(Xform f) {
+  __shared__ double red[XW][XT * XT];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t M = ROWS ? f.outer : f.n;
   const int64_t Nn = ROWS ? (int64_t)f.n : f.inner;
@@ -129,8 +132,8 @@ __global__ void __launch_bounds__(256) k_xform(Xform f) {
   const int64_t grp = ROWS ? 0 : (blockIdx.y % f.outer) * (int64_t)f.n * f.inner;
   const double *in = f.in + slice * f.sin + grp;
   double *out = f.out + slice * f.sout + grp;
-  // the contraction split over the four waves, in steps of 4
-  const int kq = (K + 15) / 16 * 4;
+  // the contraction split over the waves, in steps of 4
+  const int kq = (K + 4 * XW - 1) / (4 * XW) * 4;
   const int kb = w * kq, ke = min(K, kb + kq);
   const int lr = l & 15, lk = l >> 4;
   d4 acc[2][2];
@@ -138,26 +141,45 @@ __global__ void __launch_bounds__(256) k_xform(Xform f) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb; k0 < ke; k0 += 4) {
-    const int k = k0 + lk;
-    const bool kin = k < ke;
-    double av[2], bv[2];
+  // the operands of KU steps of 4 are loaded one group ahead of the matrix-core
+  // work on the current group, so a wave keeps 4 KU loads in flight
+  auto load = [&](int k0, double (&av)[KU][2], double (&bv)[KU][2]) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int64_t m = m0 + t * 16 + lr, nn = n0 + t * 16 + lr;
-      if (ROWS) {
-        av[t] = (kin && m < M) ? in[m * f.n + k] : 0.0;                   // In[r][p]
-        bv[t] = (kin && nn < Nn) ? f.TT[(int64_t)k * f.n + nn] : 0.0;     // T[k][p] as TT[p][k]
-      } else {
-        av[t] = (kin && m < M) ? f.TT[(int64_t)k * f.n + m] : 0.0;        // T[k][p] as TT[p][k]
-        bv[t] = (kin && nn < Nn) ? in[(int64_t)k * f.inner + nn] : 0.0;   // In_o[p][i]
+    for (int u = 0; u < KU; ++u) {
+      const int k = k0 + 4 * u + lk;
+      const bool kin = k < ke;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int64_t m = m0 + t * 16 + lr, nn = n0 + t * 16 + lr;
+        if (ROWS) {
+          av[u][t] = (kin && m < M) ? in[m * f.n + k] : 0.0;                // In[r][p]
+          bv[u][t] = (kin && nn < Nn) ? f.TT[(int64_t)k * f.n + nn] : 0.0;  // T[k][p] as TT[p][k]
+        } else {
+          av[u][t] = (kin && m < M) ? f.TT[(int64_t)k * f.n + m] : 0.0;     // T[k][p] as TT[p][k]
+          bv[u][t] = (kin && nn < Nn) ? in[(int64_t)k * f.inner + nn] : 0.0;  // In_o[p][i]
+        }
       }
     }
+  };
+  double an[KU][2], bn[KU][2];
+  if (kb < ke) load(kb, an, bn);
+  for (int k0 = kb; k0 < ke; k0 += 4 * KU) {
+    double ac[KU][2], bc[KU][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int u = 0; u < KU; ++u)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+      for (int t = 0; t < 2; ++t) {
+        ac[u][t] = an[u][t];
+        bc[u][t] = bn[u][t];
+      }
+    if (k0 + 4 * KU < ke) load(k0 + 4 * KU, an, bn);
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u][i], bc[u][j], acc[i][j], 0, 0, 0);
   }
   // D[m][n] of a 16 x 16 tile: lane n + 16 (m % 4), register m / 4 (operands:
   // A[m][k] in lane m + 16 k, B[k][n] in lane n + 16 k)
@@ -170,11 +192,13 @@ __global__ void __launch_bounds__(256) k_xform(Xform f) {
         red[w][(i * 16 + 4 * r + lk) * XT + j * 16 + lr] = acc[i][j][r];
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < XT * XT / 256; ++q) {
-    const int e = threadIdx.x + 256 * q;
+  for (int q = 0; q < XT * XT / (64 * XW); ++q) {
+    const int e = threadIdx.x + 64 * XW * q;
     const int64_t m = m0 + e / XT, nn = n0 + e % XT;
     if (m >= M || nn >= Nn) continue;
-    double v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    double v = red[0][e];
+#pragma unroll
+    for (int u = 1; u < XW; ++u) v += red[u][e];
     const int64_t lin = ROWS ? m * f.n + nn : grp + m * f.inner + nn;
     if (f.scale) {
       const int64_t q1 = lin / f.nx;
@@ -194,9 +218,9 @@ static hipError_t launch_xform(hipStream_t s, const Xform &f, bool rows, int nsl
   if (tiles > 0x7fffffff || batch > 65535) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tiles, (unsigned)batch);
   if (rows)
-    hipLaunchKernelGGL(k_xform<true>, grid, dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_xform<true>, grid, dim3(64 * XW), 0, s, f);
   else
-    hipLaunchKernelGGL(k_xform<false>, grid, dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_xform<false>, grid, dim3(64 * XW), 0, s, f);
   return hipGetLastError();
 }
 

@@ -181,11 +181,13 @@ hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &s
 int node_blocks(const Grid &g);
 int node_blocks_of(const Grid &g, int nb);
 // out2[2 (n NF + f)] = max |r_{n,f}|, out2[2 (n NF + f) + 1] = max |y_{n,f}| per
-// slice n and field f.
+// slice n and field f.  With RI: the collocation integrals of rows 1..M (plus
+// RIadd, a level's own FAS term, when given) restricted in time by Rt to the
+// Mc nodes of the next coarser level.
 hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *y_block0, double *part,
                            int nblk, double *out2, const double *Rt, int Mc, double *RI,
-                           int64_t sRI);
+                           int64_t sRI, const double *RIadd = nullptr, int64_t sRIadd = 0);
 int residual_blocks(const Grid &g);
 hipError_t launch_copy_fields(hipStream_t s, int64_t Np, double *dst, int64_t sdst,
                               const double *src, int64_t ssrc, int nf, int nslices);

@@ -585,7 +585,8 @@ hipError_t launch_copy_V_to_stages(hipStream_t s, const Grid &g, const Stages &s
 template <int M, bool GATES>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_residual(Grid g0, Stages st, Colloc co, int slice0, const double *yblk0, double *part, int nbx,
-           const double *Rt, int Mc, double *RI, int64_t sRI) {
+           const double *Rt, int Mc, double *RI, int64_t sRI, const double *RIadd,
+           int64_t sRIadd) {
   __shared__ double lds[BLOCK / 64];
   const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int f = GATES ? GATE0 + (int)blockIdx.y : (int)blockIdx.y;
@@ -623,6 +624,12 @@ k_residual(Grid g0, Stages st, Colloc co, int slice0, const double *yblk0, doubl
       ymax = nmax(ymax, fabs(yi));
     }
     if (RI) {
+      // the integrals, plus the level's own FAS term (a middle level of three),
+      // restricted in time to the coarser level's nodes
+      if (RIadd) {
+#pragma unroll
+        for (int l = 0; l < M; ++l) I[l] += RIadd[n * sRIadd + ((int64_t)l * NF + f) * Np + p];
+      }
       for (int ic = 0; ic < Mc; ++ic) {
         double s = 0.0;
 #pragma unroll
@@ -662,15 +669,15 @@ int residual_blocks(const Grid &g) { return NF * (int)nblocks(g.N); }
 hipError_t launch_residual(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                            int slice0, int nslices, const double *y_block0, double *part,
                            int nblk, double *out2, const double *Rt, int Mc, double *RI,
-                           int64_t sRI) {
+                           int64_t sRI, const double *RIadd, int64_t sRIadd) {
   // nblk = NF node-block rows per slice (residual_blocks)
   const int nbx = (int)nblocks(g.N);
   const dim3 rows(nbx, GATE0, nslices), gates(nbx, NG, nslices);
   HSDC_DISPATCH_M(co.M, {
     hipLaunchKernelGGL((k_residual<M, false>), rows, dim3(BLOCK), 0, s, g, st, co, slice0,
-                       y_block0, part, nbx, Rt, Mc, RI, sRI);
+                       y_block0, part, nbx, Rt, Mc, RI, sRI, RIadd, sRIadd);
     hipLaunchKernelGGL((k_residual<M, true>), gates, dim3(BLOCK), 0, s, g, st, co, slice0,
-                       y_block0, part, nbx, Rt, Mc, RI, sRI);
+                       y_block0, part, nbx, Rt, Mc, RI, sRI, RIadd, sRIadd);
   });
   // one reduction per (slice, field): the partials of a slice are laid out
   // field by field, nbx per field

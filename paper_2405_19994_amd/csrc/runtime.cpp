@@ -95,6 +95,9 @@ struct LevelT {
   double *Sz = nullptr;   // coarse: copy of the restricted fine iterate
   double *RI = nullptr;   // fine: time-restricted integrals [P][Mc][NF][Np]; coarse: FAS term
   double *y0c = nullptr;  // coarse: restricted block start value [NF][Np]
+  // middle level of three: S (I + tau) restricted in time to the coarsest
+  // level's nodes [P][M_2][NF][Np] (tau of the coarsest level before its own part)
+  double *RI2 = nullptr;
   int cg_pred[16][MAXM];  // iteration budget per (sweep index, node)
   int cg_umax[16][MAXM];  // most iterations used since the last relaxation (graph mode;
                           // -1: no solve checked since)
@@ -136,7 +139,7 @@ struct hsdc_ctx {
   hipStream_t s = nullptr;
   hsdc_problem prob{};
   hsdc_method meth{};
-  Level L[2];             // fine level and (FP64) coarse level
+  Level L[3];             // fine level, (FP64) coarse or middle level, coarsest level
   LevelT<float> Lf;       // coarse level when coarse_fp32
   bool cf32 = false;
   // ragged batch of independent tissues (one per slice of a serial context)
@@ -146,7 +149,8 @@ struct hsdc_ctx {
   std::vector<std::pair<int, int>> tissue_dims;  // nx, ny per slice (batch)
   int nlev = 1;
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
-  double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices
+  double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices, levels 0 and 1
+  double *Rt2 = nullptr, *Tt2 = nullptr;  // levels 1 and 2 (three levels)
   int64_t step = 0;
   int64_t *d_step = nullptr;  // device copy of step, read by the kernels
   int sweeps_done = 0;  // serial: sweeps applied to the current step
@@ -161,7 +165,7 @@ struct hsdc_ctx {
   std::string err;
   std::vector<void *> allocs;
   std::vector<void *> host_allocs;
-  Stim stim[2]{};
+  Stim stim[3]{};
   // budgeted CG: solves enqueued without a host synchronisation, verified in
   // bulk at the end of a step; a step with an unconverged solve is recomputed
   bool safe_cg = true;
@@ -348,16 +352,22 @@ bool check_problem(const hsdc_problem *p, std::string &why) {
 
 bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why) {
   if (!m) return why = "method is NULL", false;
-  if (m->levels < 1 || m->levels > 2) return why = "levels must be 1 or 2", false;
+  if (m->levels < 1 || m->levels > 3) return why = "levels must be 1, 2 or 3", false;
   for (int l = 0; l < m->levels; ++l)
     if (m->M[l] < 1 || m->M[l] > HSDC_MAX_M) return why = "M must be in 1..8", false;
-  if (m->levels == 2 && m->space_coarsen != 1 && m->space_coarsen != 2)
+  if (m->levels >= 2 && m->space_coarsen != 1 && m->space_coarsen != 2)
     return why = "space_coarsen must be 1 or 2", false;
-  if (m->levels == 2 && m->space_coarsen == 2) {
-    if ((p->nx > 1 && p->nx % 2) || (p->ny > 1 && p->ny % 2) || (p->nz > 1 && p->nz % 2))
-      return why = "space_coarsen 2 needs even mesh sizes", false;
+  if (m->levels >= 2 && m->space_coarsen == 2) {
+    // every coarsening halves each axis with more than one node
+    const int q = m->levels == 3 ? 4 : 2;
+    if ((p->nx > 1 && p->nx % q) || (p->ny > 1 && p->ny % q) || (p->nz > 1 && p->nz % q))
+      return why = m->levels == 3 ? "space_coarsen 2 with three levels needs mesh sizes divisible by 4"
+                                  : "space_coarsen 2 needs even mesh sizes",
+             false;
     if (p->sigma_node) return why = "space_coarsen 2 needs a uniform sigma", false;
   }
+  if (m->levels == 3 && m->coarse_fp32)
+    return why = "three levels run in FP64 (coarse_fp32 0)", false;
   if (m->P < 1 || m->P > 4096) return why = "P must be in 1..4096", false;
   if (!(m->dt > 0) || !std::isfinite(m->dt)) return why = "dt must be > 0", false;
   if (m->max_iter < 1) return why = "max_iter must be >= 1", false;
@@ -1013,8 +1023,8 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
   materialize(c);
   Level &L = c->L[0];
   const double *yb = c->pfasst ? c->y0blk : nullptr;  // serial, batch: u = y_{n,0}
-  const int Mc = c->nlev == 2 ? c->meth.M[1] : 0;
-  double *RI = (want_RI && c->nlev == 2) ? L.RI : nullptr;
+  const int Mc = c->nlev >= 2 ? c->meth.M[1] : 0;
+  double *RI = (want_RI && c->nlev >= 2) ? L.RI : nullptr;
   {
     const double M = L.co.M;
     const double per = (M + 1) * NF + M * NF + M + NG + NF + (RI ? Mc * NF : 0);
@@ -1049,27 +1059,33 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
 // PFASST (two levels)
 // ---------------------------------------------------------------------------
 template <class T>
-void restrict_fine_to_coarse(hsdc_ctx *c, LevelT<T> &Cc) {
-  Level &F = c->L[0];
+void restrict_stages_between(hsdc_ctx *c, Level &F, LevelT<T> &Cc, const double *Rt) {
   const double bytes = 8.0 * F.P * NF * ((F.co.M + 1.0) * F.g.N + 2.0 * (Cc.co.M + 1.0) * Cc.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
           launch_restrict_stages(c->s, F.g, Cc.g, c->meth.space_coarsen, F.st.Y, F.st.sY(),
-                                 F.co.M, c->Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
+                                 F.co.M, Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
+}
+template <class T>
+void restrict_fine_to_coarse(hsdc_ctx *c, LevelT<T> &Cc) {
+  restrict_stages_between(c, c->L[0], Cc, c->Rt);
 }
 
 // Fine stages from stage i0 on take the coarse correction.  i0 = 1 where a
 // fine sweep follows at once: it overwrites every slice's stage 0 with its
 // start value before reading it.
 template <class T>
-void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc, int i0) {
-  Level &F = c->L[0];
+void correct_between(hsdc_ctx *c, Level &F, LevelT<T> &Cc, const double *Tt, int i0) {
   // z_c - S z formed in S z (z_c and S z read, the difference written), then
   // read once at the coarse cells; fine stages i0..M read and written
   const double bytes =
       8.0 * F.P * NF * (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0 - i0) * F.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
           launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz,
-                                 Cc.st.sY(), Cc.co.M, c->Tt, F.co.M, i0, F.st.Y, F.st.sY(), F.P));
+                                 Cc.st.sY(), Cc.co.M, Tt, F.co.M, i0, F.st.Y, F.st.sY(), F.P));
+}
+template <class T>
+void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc, int i0) {
+  correct_between(c, c->L[0], Cc, c->Tt, i0);
 }
 
 // start values u_n of a sweep over slices [s0, s0+ns) from the stage-M values
@@ -1103,6 +1119,21 @@ void burn_in(hsdc_ctx *c, LevelT<T> &Cc) {
   coarse_correct_fine(c, Cc, 0);
 }
 
+// Three levels: the staggered burn-in on the coarsest level, its correction
+// carried to the middle and then the fine level (every stage).
+void burn_in3(hsdc_ctx *c) {
+  Level &F = c->L[0], &Mi = c->L[1], &C = c->L[2];
+  const int P = C.P;
+  restrict_stages_between(c, F, Mi, c->Rt);
+  restrict_stages_between(c, Mi, C, c->Rt2);
+  for (int s = 0; s < P; ++s) {
+    gather_starts(c, C, C.y0c, s, P - s);
+    sweep(c, C, 2, s, P - s, C.U + s * C.st.sS(), nullptr, 15, true);
+  }
+  correct_between(c, Mi, C, c->Tt2, 0);
+  correct_between(c, F, Mi, c->Tt, 0);
+}
+
 void begin_block(hsdc_ctx *c) {
   Level &F = c->L[0];
   const int P = F.P;
@@ -1116,6 +1147,13 @@ void begin_block(hsdc_ctx *c) {
                                   c->y0blk, 0, Cc.y0c, 0, NF, 1));
       if (P > 1 && c->meth.burn_in) burn_in(c, Cc);
     });
+  } else if (c->nlev == 3) {
+    Level &Mi = c->L[1], &C = c->L[2];
+    HIPC(launch_restrict_fields(c->s, F.g, Mi.g, c->meth.space_coarsen, c->y0blk, 0, Mi.y0c, 0,
+                                NF, 1));
+    HIPC(launch_restrict_fields(c->s, Mi.g, C.g, c->meth.space_coarsen, Mi.y0c, 0, C.y0c, 0, NF,
+                                1));
+    if (P > 1 && c->meth.burn_in) burn_in3(c);
   }
   evaluate_all(c, F, 0, 0, P);
   c->block_ready = true;
@@ -1224,7 +1262,76 @@ void run_coarse_part(hsdc_ctx *c, LevelT<T> &Cc, Fn &&part) {
   }
 }
 
+// The relative residuals of the fine level after an iteration (Algorithm 1's
+// stop test); the restricted integrals for the next iteration come with them.
+hsdc_status finish_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
+  Level &F = c->L[0];
+  const int P = F.P;
+  c->stats.pfasst_iters += 1;
+  std::vector<double> rel(P);
+  hsdc_status st = residual_pass(c, rel.data(), c->nlev >= 2);
+  c->ri_fresh = (st == HSDC_OK && c->nlev >= 2);
+  if (res_host)
+    for (int n = 0; n < P; ++n) res_host[n] = rel[n];
+  bool all = c->meth.tol > 0;
+  for (int n = 0; n < P; ++n) all = all && rel[n] < c->meth.tol;
+  if (conv) *conv = all ? 1 : 0;
+  return st;
+}
+
+// Algorithm 1 with three levels (FP64).  Down: level l = 1, 2 restricted from
+// level l - 1 with its FAS term tau_l = D_l(S z_{l-1}) - S D_{l-1}(z_{l-1}) +
+// S tau_{l-1}; the middle level sweeps once (Q^par), the coarsest runs Q^seq.
+// Up: the middle level corrected and swept again (Q^par), then the fine level
+// corrected and swept (Q^par); the residual of the fine level.  Rows i >= 1 of
+// tau_l / dt are S (I_{l-1} + tau_{l-1} / dt) - I_l(S z), the rest cancels
+// (restriction is linear and keeps node 0).
+hsdc_status pfasst_iteration3(hsdc_ctx *c, double *res_host, int32_t *conv) {
+  Level &F = c->L[0], &Mi = c->L[1], &C = c->L[2];
+  const int P = F.P, M1 = Mi.co.M, M2 = C.co.M, f = c->meth.space_coarsen;
+  if (!c->ri_fresh) {
+    const hsdc_status st = residual_pass(c, nullptr, true);
+    if (st != HSDC_OK) throw StatusFail{st};
+  }
+  // level 1: tau_1 / dt = S I_0(z_0) - I_1(S z_0), then one Q^par sweep from
+  // the restricted iterate
+  const int64_t sRI1 = (int64_t)M1 * NF * Mi.g.Np;
+  PLAUNCH(c, PC_TRANSFER, 8.0 * P * M1 * NF * ((double)F.g.N + Mi.g.N),
+          launch_restrict_fields(c->s, F.g, Mi.g, f, F.RI, (int64_t)M1 * NF * F.g.Np, Mi.RI,
+                                 sRI1, M1 * NF, P));
+  restrict_stages_between(c, F, Mi, c->Rt);
+  evaluate_all(c, Mi, 1, 0, P);
+  PLAUNCH(c, PC_FAS, 8.0 * (3.0 * M1 * NF + M1 + NG) * Mi.g.N * P,
+          launch_fas_integrals(c->s, Mi.g, Mi.st, Mi.co, 0, P, Mi.RI, sRI1));
+  gather_starts(c, Mi, Mi.y0c, 0, P);
+  sweep(c, Mi, 1, 0, P, Mi.U, Mi.RI, 0, false);
+  // level 2: tau_2 / dt = S (I_1(z_1) + tau_1 / dt) - I_2(S z_1), then Q^seq
+  const int64_t sRI2 = (int64_t)M2 * NF * Mi.g.Np, sRIc = (int64_t)M2 * NF * C.g.Np;
+  PLAUNCH(c, PC_RESIDUAL, 8.0 * ((2.0 * M1 + 1) * NF + M1 + NG + M2 * NF) * Mi.g.N * P,
+          launch_residual(c->s, Mi.g, Mi.st, Mi.co, 0, P, Mi.y0c, Mi.res_part, Mi.res_nblk,
+                          Mi.res_out, c->Rt2, M2, Mi.RI2, sRI2, Mi.RI, sRI1));
+  PLAUNCH(c, PC_TRANSFER, 8.0 * P * M2 * NF * ((double)Mi.g.N + C.g.N),
+          launch_restrict_fields(c->s, Mi.g, C.g, f, Mi.RI2, sRI2, C.RI, sRIc, M2 * NF, P));
+  restrict_stages_between(c, Mi, C, c->Rt2);
+  evaluate_all(c, C, 2, 0, P);
+  PLAUNCH(c, PC_FAS, 8.0 * (3.0 * M2 * NF + M2 + NG) * C.g.N * P,
+          launch_fas_integrals(c->s, C.g, C.st, C.co, 0, P, C.RI, sRIc));
+  for (int n = 0; n < P; ++n) {
+    gather_starts(c, C, C.y0c, n, 1);
+    sweep(c, C, 2, n, 1, C.U + n * C.st.sS(), C.RI, n % 14, true);
+  }
+  // up
+  correct_between(c, Mi, C, c->Tt2, 1);
+  gather_starts(c, Mi, Mi.y0c, 0, P);
+  sweep(c, Mi, 1, 0, P, Mi.U, Mi.RI, 1, true);
+  correct_between(c, F, Mi, c->Tt, 1);
+  gather_starts(c, F, c->y0blk, 0, P);
+  sweep(c, F, 0, 0, P, F.U, nullptr, c->sweep_index++);
+  return finish_iteration(c, res_host, conv);
+}
+
 hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
+  if (c->nlev == 3) return pfasst_iteration3(c, res_host, conv);
   Level &F = c->L[0];
   const int P = F.P;
   if (c->nlev == 2) with_coarse(c, [&](auto &Cc) {
@@ -1256,16 +1363,7 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
   // Q^par on the fine level: start values from the (corrected) iterate
   gather_starts(c, F, c->y0blk, 0, P);
   sweep(c, F, 0, 0, P, F.U, nullptr, c->sweep_index++);
-  c->stats.pfasst_iters += 1;
-  std::vector<double> rel(P);
-  hsdc_status st = residual_pass(c, rel.data(), c->nlev == 2);
-  c->ri_fresh = (st == HSDC_OK && c->nlev == 2);
-  if (res_host)
-    for (int n = 0; n < P; ++n) res_host[n] = rel[n];
-  bool all = c->meth.tol > 0;
-  for (int n = 0; n < P; ++n) all = all && rel[n] < c->meth.tol;
-  if (conv) *conv = all ? 1 : 0;
-  return st;
+  return finish_iteration(c, res_host, conv);
 }
 
 }  // namespace
@@ -1398,7 +1496,7 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
   if (!check_problem(prob, why)) return fail(nullptr, HSDC_EINVAL, why);
   if (!check_method(meth, prob, why)) return fail(nullptr, HSDC_EINVAL, why);
   if (meth->levels == 1 && meth->P > 1)
-    return fail(nullptr, HSDC_EINVAL, "P > 1 needs levels = 2");
+    return fail(nullptr, HSDC_EINVAL, "P > 1 needs levels >= 2");
   hsdc_ctx *c = new hsdc_ctx();
   c->s = (hipStream_t)hip_stream;
   c->prob = *prob;
@@ -1412,7 +1510,7 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
     F.g = make_grid(*prob, prob->nx, prob->ny, prob->nz, prob->dx);
     if (!make_colloc(meth->M[0], meth->dt, F.co))
       return fail(c, HSDC_EINVAL, "Radau node computation failed");
-    const int Mc = c->nlev == 2 ? meth->M[1] : 0;
+    const int Mc = c->nlev >= 2 ? meth->M[1] : 0;
     alloc_level(c, F, meth->M[0], P, false, Mc);
     if (prob->sigma_node) build_faces(c, F, prob->sigma_node);
     c->y0blk = dalloc<double>(c, (size_t)NF * F.g.Np);
@@ -1425,7 +1523,7 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
       HIPC(hipMemcpyAsync(F.stim_w, prob->stim_w, F.g.N * sizeof(double),
                           hipMemcpyDeviceToDevice, c->s));
     }
-    for (int l = 0; l < 2; ++l) {
+    for (int l = 0; l < 3; ++l) {
       c->stim[l].step = c->d_step;
       c->stim[l].tn = 1;  // slice n is time step step + n
       c->stim[l].amp = prob->stim_amp;
@@ -1465,6 +1563,43 @@ hsdc_status hsdc_init_state(const hsdc_problem *prob, const hsdc_method *meth, c
       c->Tt = dalloc<double>(c, T.size());
       HIPC(hipMemcpyAsync(c->Rt, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
       HIPC(hipMemcpyAsync(c->Tt, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+      HIPC(hipStreamSynchronize(c->s));  // R and T go out of scope
+    }
+    if (c->nlev == 3) {
+      // levels 1 and 2, FP64, each on the mesh of the one above coarsened by f
+      const int f = meth->space_coarsen;
+      Level *up = &F;
+      for (int l = 1; l < 3; ++l) {
+        Level &L = c->L[l];
+        const Grid &gu = up->g;
+        L.g = make_grid(*prob, gu.nx > 1 ? gu.nx / f : 1, gu.ny > 1 ? gu.ny / f : 1,
+                        gu.nz > 1 ? gu.nz / f : 1, prob->dx * (l == 1 ? f : f * f));
+        if (!make_colloc(meth->M[l], meth->dt, L.co))
+          return fail(c, HSDC_EINVAL, "Radau node computation failed");
+        alloc_level(c, L, meth->M[l], P, true, meth->M[l]);
+        if (prob->sigma_node) build_faces(c, L, prob->sigma_node);  // f == 1 only
+        if (up->stim_w) {
+          L.stim_w = dalloc<double>(c, L.g.Np);
+          HIPC(launch_restrict_fields(c->s, gu, L.g, f, up->stim_w, 0, L.stim_w, 0, 1, 1));
+        }
+        c->stim[l].w = L.stim_w;
+        std::vector<double> R((L.co.M + 1) * (up->co.M + 1)), T((up->co.M + 1) * (L.co.M + 1));
+        transfer_matrix(up->co.M, up->co.c, L.co.M, L.co.c, R.data());
+        transfer_matrix(L.co.M, L.co.c, up->co.M, up->co.c, T.data());
+        double *dR = dalloc<double>(c, R.size()), *dT = dalloc<double>(c, T.size());
+        HIPC(hipMemcpyAsync(dR, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+        HIPC(hipMemcpyAsync(dT, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+        HIPC(hipStreamSynchronize(c->s));
+        (l == 1 ? c->Rt : c->Rt2) = dR;
+        (l == 1 ? c->Tt : c->Tt2) = dT;
+        up = &L;
+      }
+      // the middle level's residual pass restricts its integrals to level 2
+      Level &Mi = c->L[1];
+      Mi.RI2 = dalloc<double>(c, (size_t)P * meth->M[2] * NF * Mi.g.Np);
+      Mi.res_nblk = residual_blocks(Mi.g);
+      Mi.res_part = dalloc<double>(c, (size_t)P * 2 * Mi.res_nblk);
+      Mi.res_out = dalloc<double>(c, (size_t)2 * NF * P);
     }
     // initial state
     if (y0) {
@@ -1667,8 +1802,8 @@ hsdc_status hsdc_tune_shapes(hsdc_ctx *c, int32_t node_block, int32_t cg_tile,
 
 hsdc_status hsdc_use_graph(hsdc_ctx *c, int32_t on) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
-  if (on && c->pfasst && c->nlev < 2)
-    return fail(c, HSDC_EINVAL, "PFASST graph replay captures the coarse part: needs 2 levels");
+  if (on && c->pfasst && c->nlev != 2)
+    return fail(c, HSDC_EINVAL, "PFASST graph replay captures the coarse part of two levels");
   if (on && c->s == nullptr)
     return fail(c, HSDC_EINVAL, "graph replay needs a context created on a non-null stream");
   Level &F = c->L[0];
@@ -1811,7 +1946,7 @@ static hsdc_status state_copy(hsdc_ctx *c, int32_t level, int32_t slice, int32_t
     if (level == 1)
       with_coarse(c, copy);
     else
-      copy(c->L[0]);
+      copy(c->L[level]);
     if (!get) {
       c->ri_fresh = false;
       // keep the cached stage terms consistent with the new state

@@ -38,7 +38,7 @@ class Problem(ctypes.Structure):
 
 
 class Method(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_int32), ("M", ctypes.c_int32 * 2),
+    _fields_ = [("levels", ctypes.c_int32), ("M", ctypes.c_int32 * 3),
                 ("space_coarsen", ctypes.c_int32), ("P", ctypes.c_int32), ("dt", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("burn_in", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
@@ -178,8 +178,8 @@ def make_method(M=(4, 2), levels=1, space_coarsen=1, P=1, dt=0.05, max_iter=4, t
                 solver="cg", residual_norm="global"):
     m = Method()
     m.levels = int(levels)
-    Ms = (tuple(M) + (1, 1))[:2] if not isinstance(M, int) else (M, 1)
-    m.M[:] = [int(Ms[0]), int(Ms[1])]
+    Ms = (tuple(M) + (1, 1, 1))[:3] if not isinstance(M, int) else (M, 1, 1)
+    m.M[:] = [int(x) for x in Ms]
     m.space_coarsen, m.P, m.dt = int(space_coarsen), int(P), float(dt)
     m.max_iter, m.tol, m.burn_in = int(max_iter), float(tol), int(burn_in)
     m.cg_rtol, m.cg_maxit = float(cg_rtol), int(cg_maxit)
@@ -249,7 +249,9 @@ class Context:
         if level == 0 or self.method.space_coarsen == 1:
             return self.N
         p = self.problem
-        dims = [n // 2 if n > 1 else 1 for n in (p.nx, p.ny, p.nz)]
+        dims = [p.nx, p.ny, p.nz]
+        for _ in range(level):  # each coarser level halves every axis of more than one node
+            dims = [n // 2 if n > 1 else 1 for n in dims]
         return int(np.prod(dims))
 
     def get_state(self, level=0, slice=0, node=0, out=None):

@@ -29,6 +29,28 @@ def oracle_hierarchy(w, Mf, Mc, coarsen):
     return Hierarchy([fine, Level(pf, Mc, w["dt"])])
 
 
+def oracle_hierarchy_levels(w, Ms, coarsen):
+    """Any number of levels: level l has Ms[l] nodes, on the mesh coarsened
+    coarsen**l (coarsen 1: time only)."""
+    dims = [tuple(w["dims"])]
+    for _ in Ms[1:]:
+        dims.append(coarse_dims(dims[-1]) if coarsen == 2 else dims[-1])
+    levels, rs, ps = [], [], []
+    stim = w["stim_w"]
+    for l, M in enumerate(Ms):
+        ww = dict(w)
+        ww["dims"], ww["stim_w"] = dims[l], stim
+        levels.append(Level(oracle_problem(ww, dims[l], w["dx"] * coarsen ** l), M, w["dt"]))
+        if l + 1 < len(Ms) and coarsen == 2:
+            d = dims[l]
+            rs.append(lambda u, d=d: restrict_space(u, d))
+            ps.append(lambda u, d=d: prolong_space(u, d))
+            stim = restrict_space(stim, d)
+    if coarsen == 2:
+        return Hierarchy(levels, space_restrict=rs, space_prolong=ps)
+    return Hierarchy(levels)
+
+
 def rest(N):
     return np.repeat(ttp06.rest_state()[:, None], N, axis=1)
 

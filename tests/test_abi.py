@@ -50,7 +50,8 @@ def test_bad_problem_is_einval(bad):
 
 @pytest.mark.parametrize("bad", [
     dict(M=(0, 1)), dict(M=(9, 1)), dict(dt=0.0), dict(max_iter=0), dict(cg_rtol=0.0),
-    dict(levels=3), dict(levels=1, P=4), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
+    dict(levels=4), dict(levels=1, P=4), dict(levels=3, M=(6, 3, 1), P=2, coarse_fp32=1),
+    dict(levels=3, M=(6, 3, 0), P=2), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
     dict(levels=2, M=(4, 2), P=2, coarse_fp32=2), dict(levels=2, M=(4, 2), P=2, coarse_cg_rtol=1.0),
     dict(solver=4), dict(solver=-1), dict(residual_norm=2),
     dict(levels=2, M=(4, 2), P=2, solver=3, coarse_fp32=1),
@@ -59,6 +60,14 @@ def test_bad_method_is_einval(bad):
     p = H.make_problem((15,), 0.01)
     code, ptr = _init(p, H.make_method(**bad))
     assert code == -1 and not ptr.value
+
+
+def test_three_levels_need_meshes_divisible_by_four():
+    """Two space coarsenings halve every axis twice: 12 x 6 is rejected."""
+    m = H.make_method(M=(6, 3, 1), levels=3, space_coarsen=2, P=2)
+    code, ptr = _init(H.make_problem((12, 6), 0.025), m)
+    assert code == -1 and not ptr.value
+    assert b"divisible by 4" in H.lib().hsdc_last_error(None)
 
 
 @pytest.mark.parametrize("case", ["order3", "order4_cg", "order4_pernode", "dct_pernode"])

@@ -363,6 +363,68 @@ def test_pfasst_sixteen_slices_every_stage_parity(solver):
         assert np.max(np.abs(np.array(hist[k]) - seen[k])) < 1e-9 * max(1.0, np.max(hist[k]))
 
 
+@pytest.mark.parametrize("dims,coarsen,P", [((8, 8, 4), 2, 4), ((36, 20), 2, 4), ((16,), 1, 4),
+                                           ((24, 16), 2, 1)])
+def test_three_level_pfasst_iterates_parity(dims, coarsen, P):
+    """Algorithm 1 with three levels, M 6, 3, 1 (Sec. 5.1): after each of three
+    iterations every stage of every slice on the fine level, the coarsest
+    level's iterate after its Q^seq sweep, and every slice's residual equal
+    the oracle's.  Space coarsening twice (3D, 2D) or time only (1D); P = 1 is
+    the serial multilevel case of the paper's convergence runs."""
+    from tests._parity import oracle_hierarchy_levels
+    kind = {1: "cable1d", 2: "slab2d", 3: "slab3d"}[len(dims)]
+    w = dict(si.workload(kind, dims=dims))
+    w["dt"] = 0.1
+    if len(dims) == 1:
+        w["stim_w"] = si.corner_weights(dims, (2,))
+    h = oracle_hierarchy_levels(w, (6, 3, 1), coarsen)
+    y0 = rest(h.levels[0].prob.N)
+    m = H.make_method(M=(6, 3, 1), levels=3, space_coarsen=coarsen, P=P, dt=0.1, max_iter=50,
+                      tol=0.0, burn_in=1, cg_rtol=1e-14, cg_maxit=300)
+    ctx = H.Context(lib_problem(w), m, dev(y0))
+    seen = []
+
+    def check(k, z, zc):
+        res, _ = ctx.pfasst_iter()
+        for n in range(P):
+            for j in range(7):
+                e = field_errors(host(ctx.get_state(0, n, j)), z[n][j])
+                assert np.max(e) < 1e-10, ("fine", k, n, j, np.max(e))
+            for j in range(2):
+                e = field_errors(host(ctx.get_state(2, n, j)), zc[n][j])
+                assert np.max(e) < 1e-10, ("coarsest", k, n, j, np.max(e))
+        seen.append(res)
+
+    _, hist, _ = pfasst_block(h, y0, P, 3, tol=0.0, callback=check)
+    assert len(seen) == 3
+    for k in range(3):
+        assert np.max(np.abs(np.array(hist[k]) - seen[k])) < 1e-9 * max(1.0, np.max(hist[k]))
+    ctx.destroy()
+
+
+def test_three_level_pfasst_converges_to_serial_collocation():
+    """Iterated to convergence, three-level PFASST reaches the fine level's
+    serial collocation solution (the fixed point of Algorithm 1) on every slice."""
+    P = 4
+    w = dict(si.workload("slab2d", dims=(16, 12)))
+    w["dt"] = 0.1
+    from tests._parity import oracle_hierarchy_levels
+    h = oracle_hierarchy_levels(w, (6, 3, 1), 2)
+    y0 = rest(h.levels[0].prob.N)
+    m = H.make_method(M=(6, 3, 1), levels=3, space_coarsen=2, P=P, dt=0.1, max_iter=60,
+                      tol=1e-12, burn_in=1, cg_rtol=1e-14, cg_maxit=300)
+    ctx = H.Context(lib_problem(w), m, dev(y0))
+    ctx.advance(1)
+    y = y0
+    for n in range(P):
+        Y, _ = collocation_solve(h.levels[0], n, y, tol=1e-14)
+        y = Y[-1]
+    e = field_errors(host(ctx.get_state(0, 0, 0)), y)
+    assert np.max(e) < 1e-9, np.max(e)
+    assert ctx.stats()["pfasst_iters"] < 60
+    ctx.destroy()
+
+
 def test_pfasst_sixteen_slices_fp32_coarse_converges_to_collocation():
     """The same 16 slices with the coarse level in FP32, iterated to a per-field
     residual of 5e-11: the end value of every slice equals the serial
