@@ -169,6 +169,32 @@ def test_cable1d_full_run_parity():
     assert y[0].max() > 0.0  # the stimulus launched a propagating action potential
 
 
+def test_serial_convergence_order_in_dt():
+    """Sec. 5.1: hybrid SDC with K sweeps converges in dt with order min(K, M + 1)
+    (or higher).  A 24-node cable through its upstroke (stimulus on [0, 0.5]
+    ms, T = 1 ms, M 4): the library's error against the oracle's reference
+    (64 steps, 8 sweeps) falls between the two finest step sizes at least like
+    dt^(K - 0.3), for K = 1..4."""
+    dims = (24,)
+    w = dict(si.workload("cable1d", dims=dims))
+    w["stim_w"], w["stim_t0"], w["stim_dur"] = si.corner_weights(dims, (4,)), 0.0, 0.5
+    T = 1.0
+    w["dt"] = T / 64
+    ref = run_serial(Level(oracle_problem(w), 4, T / 64), rest(24), 64, 8)
+    for K in (1, 2, 3, 4):
+        errs = []
+        for n in (16, 32):
+            w["dt"] = T / n
+            ctx = H.Context(lib_problem(w), H.make_method(M=4, dt=T / n, max_iter=K, cg_rtol=1e-14,
+                                                          cg_maxit=300))
+            ctx.advance(n)
+            y = host(ctx.get_state(0, 0, 0))
+            ctx.destroy()
+            errs.append(np.max(np.abs(y[0] - ref[0])) / np.max(np.abs(ref[0])))
+        order = np.log2(errs[0] / errs[1])
+        assert order > K - 0.3, (K, errs, order)
+
+
 def test_slab2d_reduced_parity():
     """The 2D slab workload at a reduced, ragged mesh (31 x 23), M 6, K 6."""
     w = si.workload("slab2d", dims=(31, 23))
