@@ -85,6 +85,9 @@ def _args():
     ap.add_argument("--tols", type=float, nargs="+", default=[1e-8, 3e-9, 1e-9, 3e-10, 1e-10],
                     help="slab3d: per-field PFASST residual tolerances tried, loosest first")
     ap.add_argument("--max-iter", type=int, default=80, help="slab3d: PFASST iterations cap")
+    ap.add_argument("--prefix-stop", action="store_true",
+                    help="slab3d: slices whose residual, and every earlier slice's, is below tol "
+                         "stop iterating (two levels)")
     ap.add_argument("--pfasst-only", action="store_true",
                     help="slab3d: time the PFASST blocks alone (no reference runs; for profilers)")
     ap.add_argument("--levels", type=int, choices=(2, 3), default=2,
@@ -296,7 +299,7 @@ def bench_slab3d(a):
         return H.make_method(M=Ms, levels=a.levels, space_coarsen=a.coarsen, P=P, dt=dt,
                              max_iter=a.max_iter, tol=tol, burn_in=1, cg_rtol=w["cg_rtol"],
                              cg_maxit=500, coarse_fp32=fp32, solver=a.solver,
-                             residual_norm="per_field")
+                             residual_norm="per_field", prefix_stop=a.prefix_stop)
 
     def serial_method(K, rtol):
         return H.make_method(M=(w["M"], 1), dt=dt, max_iter=K, cg_rtol=rtol, cg_maxit=500,
@@ -408,6 +411,7 @@ def bench_slab3d(a):
                                f"level, dt 0.1 ms, per-field error <= {a.eps:g}",
                    "nodes": N, "P": P, "M": list(Ms), "space_coarsen": a.coarsen,
                    "coarse_fp32": fp32, "solver": a.solver, "blocks": a.blocks,
+                   "prefix_stop": bool(a.prefix_stop),
                    "t_simulated_ms": T, "eps": a.eps, "tol_per_field": chosen},
         "tol_search": tries,
         "pfasst_iters_per_block": st_pf["pfasst_iters"] / a.blocks,

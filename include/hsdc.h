@@ -130,6 +130,13 @@ typedef struct {
                              /* per-field ratio ||r_{n,f}||_inf / ||y_{n,f}||_inf */
                              /* (fields of very different magnitude: Ca_i is      */
                              /* about 1e-4 mM beside K_i about 136 mM)            */
+  int32_t prefix_stop;       /* two levels: 0 every slice iterates until all have */
+                             /* converged (Algorithm 1); 1 the slices whose       */
+                             /* residual, and that of every earlier slice, is     */
+                             /* below tol stop iterating (the variant Sec. 3.2    */
+                             /* describes beside Algorithm 1); a stopped slice    */
+                             /* keeps its fine and coarse iterates and the first  */
+                             /* active slice starts from them                     */
 } hsdc_method;
 
 /* Counters since init (host copy). */

@@ -15,6 +15,12 @@ Readings of the paper used here:
 * Exactly one sweep per level per iteration, in the order of Algorithm 1.
 * Stop when every slice has ||r_n||_inf < tol ||y_n||_inf, or after K
   iterations (Algorithm 1); tol <= 0 runs exactly K iterations.
+* prefix_stop (two levels): the variant Sec. 3.2 describes beside Algorithm 1,
+  where the slices whose residual, and that of every earlier slice, is below
+  tol stop iterating.  A stopped slice keeps its fine and coarse iterates; the
+  first active slice takes its start value from the stopped slice before it,
+  on each level from that level's iterate (the coarse one from its last Q^seq
+  sweep).
 * L = 1 runs Q^seq sweeps on the single level (tau = 0).
 """
 import numpy as np
@@ -109,7 +115,32 @@ def burn_in(h, y0, P, step0, b):
     return z[0]
 
 
-def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None, callback=None):
+def _iterate_prefix(h, z, zc_store, a0, step0, b):
+    """One iteration of the two-level algorithm over the active slices a0..P-1
+    (prefix_stop); z and zc_store (the coarse iterates) are updated in place.
+    tau is formed without the previous-slice terms of D, which cancel in it."""
+    P = len(z)
+    lf, lc = h.levels
+    act = range(a0, P)
+    Sz = {n: h.S(0, z[n]) for n in act}
+    tau = {n: lc.C(step0 + n, Sz[n]) - h.S(0, lf.C(step0 + n, z[n])) for n in act}
+    for n in act:  # Q^seq on the coarse level
+        shift = b[1][n] + tau[n]
+        if n > 0:
+            shift = shift + zc_store[n - 1][-1][None]
+        zc_store[n] = lc.sweep(step0 + n, Sz[n], shift)
+    X = {n: z[n] + h.U(0, zc_store[n] - Sz[n]) for n in act}
+    shifts = {}
+    for n in act:  # Q^par on the fine level from the corrected iterate
+        shifts[n] = np.array(b[0][n], float, copy=True)
+        if n > 0:
+            shifts[n] = shifts[n] + (X[n - 1] if n - 1 >= a0 else z[n - 1])[-1][None]
+    for n in act:
+        z[n] = lf.sweep(step0 + n, X[n], shifts[n])
+
+
+def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None, callback=None,
+                 prefix_stop=False):
     """Algorithm 1: P steps from y0.  Returns (z_fine, residual history, k).
 
     residual history: list over iterations of the P relative residuals.
@@ -127,8 +158,30 @@ def pfasst_block(h, y0, P, K, tol, step0=0, use_burn_in=True, z_init=None, callb
     hist = []
     k = 0
     converged = False
+    if prefix_stop and L != 2:
+        raise ValueError("prefix_stop is for two levels")
+    a0 = 0
+    zc_store = [None] * P
+    rel = None
     while not converged and k < K:
         zc = None
+        if prefix_stop:
+            _iterate_prefix(h, z, zc_store, a0, step0, b)
+            zc = zc_store
+            k += 1
+            r = h.D(0, step0, z)
+            new = []
+            for n in range(P):
+                rn = r[n] - b[0][n]
+                new.append(float(np.max(np.abs(rn)) / np.max(np.abs(z[n]))))
+            rel = [rel[n] if (rel is not None and n < a0) else new[n] for n in range(P)]
+            hist.append(rel)
+            if callback is not None:
+                callback(k, z, zc)
+            while tol > 0 and a0 < P and rel[a0] < tol:
+                a0 += 1
+            converged = a0 == P
+            continue
         if L == 1:
             z = h.solve_Q(0, step0, z, b[0], seq=True)
         else:

@@ -151,6 +151,10 @@ struct hsdc_ctx {
   double *y0blk = nullptr;  // block (or step) start value [NF][Np_f]
   double *Rt = nullptr, *Tt = nullptr;  // device transfer matrices, levels 0 and 1
   double *Rt2 = nullptr, *Tt2 = nullptr;  // levels 1 and 2 (three levels)
+  // PFASST with prefix_stop: slices 0..a0-1 have stopped iterating; the last
+  // residual of every slice
+  int a0 = 0;
+  std::vector<double> rel_last;
   int64_t step = 0;
   int64_t *d_step = nullptr;  // device copy of step, read by the kernels
   int sweeps_done = 0;  // serial: sweeps applied to the current step
@@ -368,6 +372,8 @@ bool check_method(const hsdc_method *m, const hsdc_problem *p, std::string &why)
   }
   if (m->levels == 3 && m->coarse_fp32)
     return why = "three levels run in FP64 (coarse_fp32 0)", false;
+  if (m->prefix_stop != 0 && m->prefix_stop != 1) return why = "prefix_stop must be 0 or 1", false;
+  if (m->prefix_stop && m->levels != 2) return why = "prefix_stop is for two levels", false;
   if (m->P < 1 || m->P > 4096) return why = "P must be in 1..4096", false;
   if (!(m->dt > 0) || !std::isfinite(m->dt)) return why = "dt must be > 0", false;
   if (m->max_iter < 1) return why = "max_iter must be >= 1", false;
@@ -1019,29 +1025,32 @@ void materialize(hsdc_ctx *c) {
   c->spread_pending = false;
 }
 
-hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
+hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI, int s0 = 0) {
   materialize(c);
   Level &L = c->L[0];
+  const int ns = L.P - s0;
   const double *yb = c->pfasst ? c->y0blk : nullptr;  // serial, batch: u = y_{n,0}
   const int Mc = c->nlev >= 2 ? c->meth.M[1] : 0;
   double *RI = (want_RI && c->nlev >= 2) ? L.RI : nullptr;
   {
     const double M = L.co.M;
     const double per = (M + 1) * NF + M * NF + M + NG + NF + (RI ? Mc * NF : 0);
-    PLAUNCH(c, PC_RESIDUAL, 8.0 * per * slice_nodes(c, L, 0, L.P),
-            launch_residual(c->s, L.g, L.st, L.co, 0, L.P, yb, L.res_part, L.res_nblk, L.res_out,
+    PLAUNCH(c, PC_RESIDUAL, 8.0 * per * slice_nodes(c, L, s0, ns),
+            launch_residual(c->s, L.g, L.st, L.co, s0, ns, yb, L.res_part, L.res_nblk, L.res_out,
                             c->Rt, Mc, RI, (int64_t)Mc * NF * L.g.Np));
   }
-  HIPC(hipMemcpyAsync(L.res_out_host, L.res_out, 2 * NF * L.P * sizeof(double),
+  HIPC(hipMemcpyAsync(L.res_out_host, L.res_out, 2 * NF * ns * sizeof(double),
                       hipMemcpyDeviceToHost, c->s));
   HIPC(hipStreamSynchronize(c->s));
   bool finite = true;
-  for (int n = 0; n < L.P; ++n) {
+  // res_out holds slices s0..P-1 from its start; res_host[n] is slice n
+  for (int q = 0; q < ns; ++q) {
+    const int n = q;
     // ||r_n||_inf / ||y_n||_inf over every field (Algorithm 1), or the largest
     // of the per-field ratios ||r_{n,f}||_inf / ||y_{n,f}||_inf
     double r = 0.0, y = 0.0, worst = 0.0;
     for (int f = 0; f < NF; ++f) {
-      const double rf = L.res_out_host[2 * (n * NF + f)], yf = L.res_out_host[2 * (n * NF + f) + 1];
+      const double rf = L.res_out_host[2 * (q * NF + f)], yf = L.res_out_host[2 * (q * NF + f) + 1];
       if (!std::isfinite(rf) || !std::isfinite(yf)) finite = false;
       r = std::max(r, rf);
       y = std::max(y, yf);
@@ -1049,7 +1058,7 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
     }
     const double rel = c->meth.residual_norm == 1 ? worst : (y > 0 ? r / y : r);
     if (!std::isfinite(rel)) finite = false;
-    if (res_host) res_host[n] = finite ? rel : NAN;
+    if (res_host) res_host[s0 + n] = finite ? rel : NAN;
   }
   if (!finite) return fail(c, HSDC_ENONFINITE, "non-finite residual or state");
   return HSDC_OK;
@@ -1059,33 +1068,39 @@ hsdc_status residual_pass(hsdc_ctx *c, double *res_host, bool want_RI) {
 // PFASST (two levels)
 // ---------------------------------------------------------------------------
 template <class T>
-void restrict_stages_between(hsdc_ctx *c, Level &F, LevelT<T> &Cc, const double *Rt) {
-  const double bytes = 8.0 * F.P * NF * ((F.co.M + 1.0) * F.g.N + 2.0 * (Cc.co.M + 1.0) * Cc.g.N);
+void restrict_stages_between(hsdc_ctx *c, Level &F, LevelT<T> &Cc, const double *Rt, int s0 = 0,
+                             int ns = -1) {
+  if (ns < 0) ns = F.P - s0;
+  const double bytes = 8.0 * ns * NF * ((F.co.M + 1.0) * F.g.N + 2.0 * (Cc.co.M + 1.0) * Cc.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
-          launch_restrict_stages(c->s, F.g, Cc.g, c->meth.space_coarsen, F.st.Y, F.st.sY(),
-                                 F.co.M, Rt, Cc.co.M, Cc.st.Y, Cc.st.sY(), Cc.Sz, F.P));
+          launch_restrict_stages(c->s, F.g, Cc.g, c->meth.space_coarsen, F.st.Y + s0 * F.st.sY(),
+                                 F.st.sY(), F.co.M, Rt, Cc.co.M, Cc.st.Y + s0 * Cc.st.sY(),
+                                 Cc.st.sY(), Cc.Sz + s0 * Cc.st.sY(), ns));
 }
 template <class T>
-void restrict_fine_to_coarse(hsdc_ctx *c, LevelT<T> &Cc) {
-  restrict_stages_between(c, c->L[0], Cc, c->Rt);
+void restrict_fine_to_coarse(hsdc_ctx *c, LevelT<T> &Cc, int s0 = 0, int ns = -1) {
+  restrict_stages_between(c, c->L[0], Cc, c->Rt, s0, ns);
 }
 
 // Fine stages from stage i0 on take the coarse correction.  i0 = 1 where a
 // fine sweep follows at once: it overwrites every slice's stage 0 with its
 // start value before reading it.
 template <class T>
-void correct_between(hsdc_ctx *c, Level &F, LevelT<T> &Cc, const double *Tt, int i0) {
+void correct_between(hsdc_ctx *c, Level &F, LevelT<T> &Cc, const double *Tt, int i0, int s0 = 0,
+                     int ns = -1) {
+  if (ns < 0) ns = F.P - s0;
   // z_c - S z formed in S z (z_c and S z read, the difference written), then
   // read once at the coarse cells; fine stages i0..M read and written
   const double bytes =
-      8.0 * F.P * NF * (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0 - i0) * F.g.N);
+      8.0 * ns * NF * (4.0 * (Cc.co.M + 1.0) * Cc.g.N + 2.0 * (F.co.M + 1.0 - i0) * F.g.N);
   PLAUNCH(c, PC_TRANSFER, bytes,
-          launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y, Cc.Sz,
-                                 Cc.st.sY(), Cc.co.M, Tt, F.co.M, i0, F.st.Y, F.st.sY(), F.P));
+          launch_prolong_correct(c->s, F.g, Cc.g, c->meth.space_coarsen, Cc.st.Y + s0 * Cc.st.sY(),
+                                 Cc.Sz + s0 * Cc.st.sY(), Cc.st.sY(), Cc.co.M, Tt, F.co.M, i0,
+                                 F.st.Y + s0 * F.st.sY(), F.st.sY(), ns));
 }
 template <class T>
-void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc, int i0) {
-  correct_between(c, c->L[0], Cc, c->Tt, i0);
+void coarse_correct_fine(hsdc_ctx *c, LevelT<T> &Cc, int i0, int s0 = 0, int ns = -1) {
+  correct_between(c, c->L[0], Cc, c->Tt, i0, s0, ns);
 }
 
 // start values u_n of a sweep over slices [s0, s0+ns) from the stage-M values
@@ -1158,6 +1173,9 @@ void begin_block(hsdc_ctx *c) {
   evaluate_all(c, F, 0, 0, P);
   c->block_ready = true;
   c->ri_fresh = false;
+  if (c->a0 != 0) c->graph_dirty = true;  // a captured coarse part covered slices a0..P-1
+  c->a0 = 0;
+  c->rel_last.assign(P, INFINITY);
 }
 
 void graph_release(hsdc_ctx *c) {
@@ -1268,13 +1286,21 @@ hsdc_status finish_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
   Level &F = c->L[0];
   const int P = F.P;
   c->stats.pfasst_iters += 1;
-  std::vector<double> rel(P);
-  hsdc_status st = residual_pass(c, rel.data(), c->nlev >= 2);
+  if ((int)c->rel_last.size() != P) c->rel_last.assign(P, INFINITY);
+  // the residuals of the active slices (a stopped slice keeps its last one)
+  hsdc_status st = residual_pass(c, c->rel_last.data(), c->nlev >= 2, c->a0);
   c->ri_fresh = (st == HSDC_OK && c->nlev >= 2);
   if (res_host)
-    for (int n = 0; n < P; ++n) res_host[n] = rel[n];
-  bool all = c->meth.tol > 0;
-  for (int n = 0; n < P; ++n) all = all && rel[n] < c->meth.tol;
+    for (int n = 0; n < P; ++n) res_host[n] = c->rel_last[n];
+  const double tol = c->meth.tol;
+  bool all = tol > 0;
+  for (int n = 0; n < P; ++n) all = all && c->rel_last[n] < tol;
+  if (c->meth.prefix_stop && st == HSDC_OK) {
+    const int a0 = c->a0;
+    while (tol > 0 && c->a0 < P && c->rel_last[c->a0] < tol) ++c->a0;
+    if (c->a0 != a0) c->graph_dirty = true;  // a captured coarse part covers slices a0..P-1
+    all = c->a0 == P;
+  }
   if (conv) *conv = all ? 1 : 0;
   return st;
 }
@@ -1334,35 +1360,38 @@ hsdc_status pfasst_iteration(hsdc_ctx *c, double *res_host, int32_t *conv) {
   if (c->nlev == 3) return pfasst_iteration3(c, res_host, conv);
   Level &F = c->L[0];
   const int P = F.P;
+  // the active slices a0..P-1 (all of them unless prefix_stop has stopped a prefix)
+  const int a0 = c->a0, na = P - a0;
   if (c->nlev == 2) with_coarse(c, [&](auto &Cc) {
     const int Mc = Cc.co.M;
     // tau (Algorithm 1): its rows i >= 1 are dt (S (A G)_f(z) - (A G)_c(S z))_i,
     // the row-0 and H parts cancel; the fine integrals come with the residual
     if (!c->ri_fresh) {
-      const hsdc_status st = residual_pass(c, nullptr, true);
+      std::vector<double> rel(P);
+      const hsdc_status st = residual_pass(c, rel.data(), true, a0);
       if (st != HSDC_OK) throw StatusFail{st};
     }
-    const int64_t sRIc = (int64_t)Mc * NF * Cc.g.Np;
+    const int64_t sRIc = (int64_t)Mc * NF * Cc.g.Np, sRIf = (int64_t)Mc * NF * F.g.Np;
     run_coarse_part(c, Cc, [&]() {
-      PLAUNCH(c, PC_TRANSFER, 8.0 * P * Mc * NF * ((double)F.g.N + Cc.g.N),
-              launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI,
-                                     (int64_t)Mc * NF * F.g.Np, Cc.RI, sRIc, Mc * NF, P));
-      restrict_fine_to_coarse(c, Cc);
-      evaluate_all(c, Cc, 1, 0, P);
-      PLAUNCH(c, PC_FAS, 8.0 * (3.0 * Mc * NF + Mc + NG) * Cc.g.N * P,
-              launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, 0, P, Cc.RI, sRIc));
-      for (int n = 0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
+      PLAUNCH(c, PC_TRANSFER, 8.0 * na * Mc * NF * ((double)F.g.N + Cc.g.N),
+              launch_restrict_fields(c->s, F.g, Cc.g, c->meth.space_coarsen, F.RI + a0 * sRIf,
+                                     sRIf, Cc.RI + a0 * sRIc, sRIc, Mc * NF, na));
+      restrict_fine_to_coarse(c, Cc, a0, na);
+      evaluate_all(c, Cc, 1, a0, na);
+      PLAUNCH(c, PC_FAS, 8.0 * (3.0 * Mc * NF + Mc + NG) * Cc.g.N * na,
+              launch_fas_integrals(c->s, Cc.g, Cc.st, Cc.co, a0, na, Cc.RI, sRIc));
+      for (int n = a0; n < P; ++n) {  // Q^seq: slice by slice with the new end values
         gather_starts(c, Cc, Cc.y0c, n, 1);
         // the right-hand side is evaluated at S z (kept in Sz until the
         // correction); budgets per slice (rows 0..13; the burn-in has row 15)
         sweep(c, Cc, 1, n, 1, Cc.U + n * Cc.st.sS(), Cc.RI, n % 14, true, Cc.Sz);
       }
     });
-    coarse_correct_fine(c, Cc, 1);
+    coarse_correct_fine(c, Cc, 1, a0, na);
   });
   // Q^par on the fine level: start values from the (corrected) iterate
-  gather_starts(c, F, c->y0blk, 0, P);
-  sweep(c, F, 0, 0, P, F.U, nullptr, c->sweep_index++);
+  gather_starts(c, F, c->y0blk, a0, na);
+  sweep(c, F, 0, a0, na, F.U + a0 * F.st.sS(), nullptr, c->sweep_index++);
   return finish_iteration(c, res_host, conv);
 }
 

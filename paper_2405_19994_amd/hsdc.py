@@ -43,7 +43,7 @@ class Method(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("burn_in", ctypes.c_int32),
                 ("solver", ctypes.c_int32), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
                 ("coarse_fp32", ctypes.c_int32), ("coarse_cg_rtol", ctypes.c_double),
-                ("residual_norm", ctypes.c_int32)]
+                ("residual_norm", ctypes.c_int32), ("prefix_stop", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -175,7 +175,7 @@ RESIDUAL_NORMS = {"global": 0, "per_field": 1}
 
 def make_method(M=(4, 2), levels=1, space_coarsen=1, P=1, dt=0.05, max_iter=4, tol=0.0,
                 burn_in=1, cg_rtol=1e-12, cg_maxit=200, coarse_fp32=False, coarse_cg_rtol=0.0,
-                solver="cg", residual_norm="global"):
+                solver="cg", residual_norm="global", prefix_stop=False):
     m = Method()
     m.levels = int(levels)
     Ms = (tuple(M) + (1, 1, 1))[:3] if not isinstance(M, int) else (M, 1, 1)
@@ -187,6 +187,7 @@ def make_method(M=(4, 2), levels=1, space_coarsen=1, P=1, dt=0.05, max_iter=4, t
     m.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     m.residual_norm = RESIDUAL_NORMS[residual_norm] if isinstance(residual_norm, str) \
         else int(residual_norm)
+    m.prefix_stop = int(prefix_stop)
     return m
 
 

@@ -26,6 +26,7 @@ def test_struct_layout_matches_header():
     assert H.Method.solver.offset == 52
     assert H.Method.coarse_cg_rtol.offset == 72
     assert H.Method.residual_norm.offset == 80
+    assert H.Method.prefix_stop.offset == 84
 
 
 def _init(p, m):
@@ -51,7 +52,8 @@ def test_bad_problem_is_einval(bad):
 @pytest.mark.parametrize("bad", [
     dict(M=(0, 1)), dict(M=(9, 1)), dict(dt=0.0), dict(max_iter=0), dict(cg_rtol=0.0),
     dict(levels=4), dict(levels=1, P=4), dict(levels=3, M=(6, 3, 1), P=2, coarse_fp32=1),
-    dict(levels=3, M=(6, 3, 0), P=2), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
+    dict(levels=3, M=(6, 3, 0), P=2), dict(levels=2, M=(4, 2), P=2, prefix_stop=2),
+    dict(levels=3, M=(6, 3, 1), P=2, prefix_stop=1), dict(levels=2, M=(4, 2), space_coarsen=2, P=2),
     dict(levels=2, M=(4, 2), P=2, coarse_fp32=2), dict(levels=2, M=(4, 2), P=2, coarse_cg_rtol=1.0),
     dict(solver=4), dict(solver=-1), dict(residual_norm=2),
     dict(levels=2, M=(4, 2), P=2, solver=3, coarse_fp32=1),

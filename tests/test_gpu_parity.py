@@ -684,6 +684,43 @@ def test_tuned_correction_tiles_give_the_same_iterates(dims):
         ctx.destroy()
 
 
+def test_pfasst_prefix_stop_iterates_parity():
+    """prefix_stop (leading converged slices stop iterating, Sec. 3.2): every
+    iterate of every slice and every residual equal the oracle's, through the
+    iterations at which slices stop, and a stopped slice is left unchanged;
+    the coarse part replayed from a graph gives the same iterates."""
+    P = 8
+    w, h, y0, m = _pfasst_case((8, 6, 4), 6, 3, 2, P, 0.1)
+    m.tol, m.max_iter, m.prefix_stop = 1e-9, 60, 1
+    stream = torch.cuda.Stream()
+    ctx = H.Context(lib_problem(w), m, dev(y0), stream)
+    ctg = H.Context(lib_problem(w), m, dev(y0), stream)
+    ctg.use_graph(True)
+    seen = []
+
+    def check(k, z, zc):
+        res, conv = ctx.pfasst_iter()
+        resg, _ = ctg.pfasst_iter()
+        assert np.array_equal(res, resg), (k, res, resg)
+        for n in range(P):
+            for j in (0, 6):
+                g = host(ctx.get_state(0, n, j))
+                e = field_errors(g, z[n][j])
+                assert np.max(e) < 1e-10, (k, n, j, np.max(e))
+                assert np.array_equal(g, host(ctg.get_state(0, n, j))), (k, n, j)
+        seen.append((res, conv))
+
+    _, hist, k = pfasst_block(h, y0, P, 60, tol=1e-9, prefix_stop=True, callback=check)
+    assert len(seen) == k and seen[-1][1]
+    stopped = [sum(1 for x in r if x < 1e-9) for r in hist]
+    assert 0 < stopped[-2] < P  # some slices stopped before the last iteration
+    for q in range(k):
+        assert np.max(np.abs(np.array(hist[q]) - seen[q][0])) < 1e-9 * max(1.0, np.max(hist[q]))
+    assert ctx.stats()["pfasst_iters"] == k
+    ctx.destroy()
+    ctg.destroy()
+
+
 @pytest.mark.parametrize("coarse_fp32", [False, True])
 def test_pfasst_graph_replay_equals_eager_iterations(coarse_fp32):
     """PFASST with the coarse part of each iteration (FAS restriction, coarse

@@ -292,6 +292,50 @@ def test_pfasst_space_coarsened_converges_to_serial():
     assert np.max(np.abs(z[-1][-1] - y)) < 1e-12 * np.max(np.abs(y))
 
 
+def test_pfasst_prefix_stop():
+    """The variant in which converged leading slices stop iterating (Sec. 3.2,
+    beside Algorithm 1): with no slice below tol it is Algorithm 1 (to
+    rounding); with a tolerance it stops slices in order, never iterates more
+    than Algorithm 1, keeps stopped slices unchanged, and ends at the fine
+    collocation solution."""
+    dims = (8, 4)
+    p = _tiny_tissue(dims, sigma=(3.0, 1.0, 1.0))
+    pc = Monodomain(coarse_dims(dims), 0.05, (3.0, 1.0, 1.0), stim_w=restrict_space(p.stim_w, dims),
+                    stim_amp=50.0, stim_t0=0.0, stim_dur=1.0)
+    y0 = np.repeat(ttp06.rest_state()[:, None], p.N, 1)
+    h = Hierarchy([Level(p, 6, 0.1), Level(pc, 3, 0.1)],
+                  space_restrict=[lambda u: restrict_space(u, dims)],
+                  space_prolong=[lambda u: prolong_space(u, dims)])
+    P = 6
+    za, ha, _ = pfasst_block(h, y0, P, 4, tol=0.0)
+    zb, hb, _ = pfasst_block(h, y0, P, 4, tol=0.0, prefix_stop=True)
+    for a, b in zip(za, zb):
+        assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a))
+    assert np.max(np.abs(np.array(ha) - np.array(hb))) < 1e-12
+    tol = 1e-10
+    _, hc, kc = pfasst_block(h, y0, P, 80, tol=tol)
+    zd, hd, kd = pfasst_block(h, y0, P, 80, tol=tol, prefix_stop=True)
+    # a second run checks that a slice, once its prefix is below tol, keeps its iterate
+    frozen = {}
+
+    def check(k, z, zc):
+        for n, Y in frozen.items():
+            assert np.array_equal(z[n], Y), (k, n)
+        a0 = 0
+        while a0 < P and hd[k - 1][a0] < tol:
+            frozen.setdefault(a0, np.array(z[a0], copy=True))
+            a0 += 1
+
+    pfasst_block(h, y0, P, 80, tol=tol, prefix_stop=True, callback=check)
+    assert kd <= kc and max(hd[-1]) < tol
+    assert len(frozen) == P
+    y = y0
+    for n in range(P):
+        Y, _ = collocation_solve(h.levels[0], n, y, tol=1e-14)
+        y = Y[-1]
+    assert np.max(np.abs(zd[-1][-1] - y)) < 1e-8 * np.max(np.abs(y))
+
+
 def test_run_pfasst_blocks_chain():
     p = _tiny_tissue((8,))
     y0 = np.repeat(ttp06.rest_state()[:, None], p.N, 1)
