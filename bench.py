@@ -168,7 +168,7 @@ def cpu_baseline(nsteps=2, side=128):
 def _kernel_sources_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("hsdc_kernels.hip", "ttp06_device.h", "hsdc_internal.h"):
+    for f in ("hsdc_kernels.hip", "hsdc_device.h", "ttp06_device.h", "hsdc_internal.h"):
         with open(os.path.join(ROOT, "paper_2405_19994_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -22,6 +22,7 @@
 #include "hsdc_device.h"
 #include "hsdc_internal.h"
 #include "ttp06_device.h"
+#include "ttp06_vjp.h"
 
 namespace hsdc {
 namespace ad {
@@ -62,46 +63,29 @@ __device__ __forceinline__ D sqrt(D a) {
 //   G_V = (I_stim - Cm I_ion(x)) / Cm,  G_aux = h_a(x),
 //   G_g = Lambda_g(x) (x_g - w_inf,g(x)) + Lambda_n,g (u_g - x_g).
 // vx += (dG/dx)^T cot and vgs += (dG/dgs)^T cot (u and Lambda_n held fixed);
-// Gg receives the gate terms G_g(x).  The currents take one dual pass per
-// state and per scaling (22), the gates two (their rates and steady states
-// depend on V and Ca_ss only).
-__device__ __attribute__((noinline)) void reaction_vjp(const double *x, const double *gs,
+// Gg receives the gate terms G_g(x).  The currents are taken back in one
+// reverse pass (currents_vjp), the gates by one dual pass in V (their rates
+// and steady states depend on V, except fCass, which depends on Ca_ss alone).
+__device__ __forceinline__ void reaction_vjp(const double *x, const double *gs,
                                                       const double *lam_n, const double *ug,
                                                       const double *cot, double *vx, double *vgs,
                                                       double *Gg) {
-  double lam[NG], inf[NG], dlv[NG], div[NG], dlc[NG], dic[NG];
+  // pass 1, dual in V: the gate terms, their V derivatives and the diagonal
   ttp06::gates<ad::D>(ad::D(x[0], 1.0), ad::D(x[3], 0.0), [&](int k, ad::D in, ad::D rate) {
-    lam[k] = -rate.v;
-    inf[k] = in.v;
-    dlv[k] = -rate.d;
-    div[k] = in.d;
+    const double w = x[GATE0 + k], c = cot[GATE0 + k], lam = -rate.v;
+    Gg[k] = lam * (w - in.v) + lam_n[k] * (ug[k] - w);
+    vx[0] += c * (-rate.d * (w - in.v) - lam * in.d);
+    vx[GATE0 + k] += c * (lam - lam_n[k]);
   });
-  ttp06::gates<ad::D>(ad::D(x[0], 0.0), ad::D(x[3], 1.0), [&](int k, ad::D in, ad::D rate) {
-    dlc[k] = -rate.d;
-    dic[k] = in.d;
-  });
-  for (int k = 0; k < NG; ++k) {
-    const double w = x[GATE0 + k], c = cot[GATE0 + k];
-    Gg[k] = lam[k] * (w - inf[k]) + lam_n[k] * (ug[k] - w);
-    vx[0] += c * (dlv[k] * (w - inf[k]) - lam[k] * div[k]);
-    vx[3] += c * (dlc[k] * (w - inf[k]) - lam[k] * dic[k]);
-    vx[GATE0 + k] += c * (lam[k] - lam_n[k]);
+  // Ca_ss derivatives: fCass is the only gate that depends on Ca_ss
+  {
+    ad::D in, rate;
+    ttp06::fcass_gate<ad::D>(ad::D(x[3], 1.0), in, rate);
+    const double w = x[GATE0 + NG - 1], c = cot[GATE0 + NG - 1];
+    vx[3] += c * (-rate.d * (w - in.v) + rate.v * in.d);
   }
-#pragma unroll 1
-  for (int m = 0; m < NF + 3; ++m) {
-    ad::D y[NF];
-    for (int f = 0; f < NF; ++f) y[f] = ad::D(x[f], f == m ? 1.0 : 0.0);
-    const ad::D g0(gs[0], m == NF ? 1.0 : 0.0), g1(gs[1], m == NF + 1 ? 1.0 : 0.0),
-        g2(gs[2], m == NF + 2 ? 1.0 : 0.0);
-    ad::D I, ha[6];
-    ttp06::currents<ad::D>(y, g0, g1, g2, I, ha);
-    double s = -cot[0] * I.d;  // d G_V = -d I_ion
-    for (int k = 0; k < 6; ++k) s += cot[1 + k] * ha[k].d;
-    if (m < NF)
-      vx[m] += s;
-    else
-      vgs[m - NF] += s;
-  }
+  // d G_V = -d I_ion; the auxiliary rows take h_a directly
+  ttp06::currents_vjp<double>(x, gs[0], gs[1], gs[2], -cot[0], cot + 1, vx, vgs);
 }
 
 // phi_1(x) and phi_1'(x) = phi_1(x) - phi_2(x).
@@ -174,7 +158,7 @@ k_adj_backsub(AdjArgs a, int i) {
 }
 
 // The collocation integrals and the P terms built from the previous iterate,
-// backwards, for every stage j = 0..M of X (X_0 = u) at once:
+// backwards, for every stage j = 0..M of X (X_0 = u):
 //   gamma_j = dt sum_i (a_ij - a_{i-1,j}) rho_i          (j >= 1; a_0j = 0)
 //   cot_j   = gamma_j - dt d_{j+1} rho_{j+1} (gate rows times phi_1(d_{j+1} z))
 //   MUX_j (or DYN for j = 0) += (dG/dx)^T cot_j at X_j, the anchor parts as
@@ -184,11 +168,18 @@ k_adj_backsub(AdjArgs a, int i) {
 //   a'_ij(z) = sum_k c_i^{k+1} w_j^{k-1} phi_k'(c_i z).
 // W_j = gamma_j^V - dt d_j rho_j^V is the adjoint the stencil products K X_j^V
 // receive (applied by the host with the operator, j = 1..M).
+// The stages are independent given rho, so each (node, stage) pair has a
+// thread of its own (blockIdx.y = j): M + 1 times the waves of one thread per
+// node, which the transposed cell model needs to hide its latencies.  What
+// every stage adds to one node (cot_g lambda_n,g to the gate rows of DYN,
+// cot_g (u_g - x_g) to DLAM, the DZ terms) goes to PS[j] and is summed in
+// stage order by k_adj_assemble_sum.
 template <int M>
 __global__ void __launch_bounds__(ADB)
 k_adj_assemble(AdjArgs a) {
   __shared__ double lds[3 * (ADB / 64)];
   const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  const int j = blockIdx.y;
   double vgs[3] = {0.0, 0.0, 0.0};
   if (p < a.N) {
     const int64_t Np = a.Np, sS = (int64_t)NF * Np;
@@ -196,105 +187,105 @@ k_adj_assemble(AdjArgs a) {
     const double dt = co.dt;
     const double *X = a.X + p;
     const double *rho = a.RHO + p;
-    double gam[M + 1][NF];
-    for (int j = 0; j <= M; ++j)
-      for (int f = 0; f < NF; ++f) gam[j][f] = 0.0;
-    // rows V .. Rbar: collocation weights Q
-    for (int f = 0; f < GATE0; ++f)
-      for (int i = 1; i <= M; ++i) {
-        const double r = rho[(int64_t)i * sS + f * Np];
-        for (int j = 1; j <= M; ++j)
-          gam[j][f] += dt * (co.Q[i - 1][j - 1] - (i > 1 ? co.Q[i - 2][j - 1] : 0.0)) * r;
-      }
-    // gate rows: a_ij(z) and its derivative, with G_g(X_j) for the z terms
-    double lam_n[NG], ug[NG];
+    const bool nxt = j + 1 <= M;
+    const double ddn = nxt ? dt * co.d[j] : 0.0;  // dt d_{j+1}
+    double lam_n[NG], ug[NG], x[NF], cot[NF], vx[NF], ck[NG], Gg[NG];
     for (int k = 0; k < NG; ++k) {
       lam_n[k] = a.L0[k * Np + p];
       ug[k] = X[(GATE0 + k) * Np];
     }
-    double Gg[M + 1][NG];
-    for (int j = 0; j <= M; ++j) {
-      const double V = X[(int64_t)j * sS], C = X[(int64_t)j * sS + 3 * Np];
-      ttp06::gates<double>(V, C, [&](int k, double in, double rate) {
-        const double w = X[(int64_t)j * sS + (GATE0 + k) * Np];
-        Gg[j][k] = -rate * (w - in) + lam_n[k] * (ug[k] - w);
-      });
+    for (int f = 0; f < NF; ++f) {
+      x[f] = X[(int64_t)j * sS + f * Np];
+      vx[f] = 0.0;
     }
-    double dz[NG];
+    // rows V .. Rbar: collocation weights Q
+    double gam0 = 0.0;
+    for (int f = 0; f < GATE0; ++f) {
+      double c = 0.0;
+      if (j >= 1)
+        for (int i = 1; i <= M; ++i)
+          c += dt * (co.Q[i - 1][j - 1] - (i > 1 ? co.Q[i - 2][j - 1] : 0.0)) *
+               rho[(int64_t)i * sS + f * Np];
+      if (f == 0) gam0 = c;
+      if (nxt) c -= ddn * rho[(int64_t)(j + 1) * sS + f * Np];
+      cot[f] = c;
+    }
+    // gate rows: column j of a_ij(z) and of its derivative in z; ck collects
+    // the factor of G_g(X_j) in the DZ terms
     for (int k = 0; k < NG; ++k) {
-      const double z = dt * lam_n[k];
-      double A[M + 1][M + 1], Ad[M + 1][M + 1];  // rows i = 0..M (row 0: zero)
-      for (int j = 0; j <= M; ++j) A[0][j] = Ad[0][j] = 0.0;
-      for (int i = 1; i <= M; ++i) {
-        double ph[M + 1];
-        if (z == 0.0) {
-          for (int j = 1; j <= M; ++j) A[i][j] = co.Q[i - 1][j - 1];
-        } else {
-          phis<M + 1>(co.c[i - 1] * z, co.invfact, ph);
-          for (int j = 1; j <= M; ++j) {
-            double s = 0.0;
-            for (int q = 0; q < M; ++q) s += co.cpow[i - 1][q + 1] * co.W[q][j - 1] * ph[q];
-            A[i][j] = s;
-          }
-        }
-        // derivative in z, also at z = 0 (phi_k(0) = 1/k!)
-        if (z == 0.0)
-          for (int q = 0; q <= M; ++q) ph[q] = co.invfact[q + 1];
-        for (int j = 1; j <= M; ++j) {
-          double s = 0.0;
-          for (int q = 0; q < M; ++q)
-            s += co.cpow[i - 1][q + 1] * co.c[i - 1] * co.W[q][j - 1] *
-                 (ph[q] - (q + 1) * ph[q + 1]);
-          Ad[i][j] = s;
-        }
-      }
-      double dzk = 0.0;
       const int f = GATE0 + k;
-      for (int i = 1; i <= M; ++i) {
-        const double r = rho[(int64_t)i * sS + f * Np];
-        for (int j = 1; j <= M; ++j) {
-          gam[j][f] += dt * (A[i][j] - A[i - 1][j]) * r;
-          dzk += dt * r * (Ad[i][j] - Ad[i - 1][j]) * Gg[j][k];
-        }
-      }
-      dz[k] = dzk;
-    }
-    // the P terms of the previous iterate and the transposed cell model at X_j
-    for (int j = 0; j <= M; ++j) {
-      double x[NF], cot[NF], vx[NF], gtmp[NG];
-      const bool nxt = j + 1 <= M;
-      const double ddn = nxt ? dt * co.d[j] : 0.0;  // dt d_{j+1}
-      for (int f = 0; f < NF; ++f) {
-        x[f] = X[(int64_t)j * sS + f * Np];
-        vx[f] = 0.0;
-        double c = (j >= 1) ? gam[j][f] : 0.0;
-        if (nxt) {
-          double sc = 1.0;
-          if (f >= GATE0) {
-            double p1, dp1;
-            phi1_d(co.d[j] * dt * lam_n[f - GATE0], co.invfact, p1, dp1);
-            sc = p1;
-            dz[f - GATE0] -= rho[(int64_t)(j + 1) * sS + f * Np] * ddn * Gg[j][f - GATE0] *
-                             co.d[j] * dp1;
+      const double z = dt * lam_n[k];
+      double c = 0.0, s = 0.0;
+      if (j >= 1) {
+        double Ap = 0.0, Dp = 0.0;  // row i - 1 (row 0: zero)
+        for (int i = 1; i <= M; ++i) {
+          double ph[M + 1], Aij = 0.0, Dij = 0.0;
+          if (z == 0.0) {
+            Aij = co.Q[i - 1][j - 1];
+            for (int q = 0; q <= M; ++q) ph[q] = co.invfact[q + 1];  // phi_k(0) = 1/k!
+          } else {
+            phis<M + 1>(co.c[i - 1] * z, co.invfact, ph);
+            for (int q = 0; q < M; ++q) Aij += co.cpow[i - 1][q + 1] * co.W[q][j - 1] * ph[q];
           }
-          c -= ddn * sc * rho[(int64_t)(j + 1) * sS + f * Np];
+          for (int q = 0; q < M; ++q)
+            Dij += co.cpow[i - 1][q + 1] * co.c[i - 1] * co.W[q][j - 1] *
+                   (ph[q] - (q + 1) * ph[q + 1]);
+          const double r = rho[(int64_t)i * sS + f * Np];
+          c += dt * (Aij - Ap) * r;
+          s += dt * r * (Dij - Dp);
+          Ap = Aij;
+          Dp = Dij;
         }
-        cot[f] = c;
       }
-      const double gs[3] = {a.gs[0], a.gs[1], a.gs[2]};
-      reaction_vjp(x, gs, lam_n, ug, cot, vx, vgs, gtmp);
-      double *tgt = (j == 0) ? a.DYN + p : a.MUX + (int64_t)j * sS + p;
-      for (int f = 0; f < NF; ++f) tgt[f * Np] += vx[f];
-      for (int k = 0; k < NG; ++k) {
-        const double c = cot[GATE0 + k];
-        a.DLAM[k * Np + p] += c * (ug[k] - x[GATE0 + k]);
-        a.DYN[(GATE0 + k) * Np + p] += c * lam_n[k];
+      if (nxt) {
+        double p1, dp1;
+        phi1_d(co.d[j] * dt * lam_n[k], co.invfact, p1, dp1);
+        const double r = rho[(int64_t)(j + 1) * sS + f * Np];
+        c -= ddn * p1 * r;
+        s -= r * ddn * co.d[j] * dp1;
       }
-      if (j >= 1) a.W[(int64_t)j * Np + p] = gam[j][0] - dt * co.d[j - 1] * rho[(int64_t)j * sS];
+      cot[f] = c;
+      ck[k] = s;
     }
-    for (int k = 0; k < NG; ++k) a.DZ[k * Np + p] += dz[k];
+    const double gs[3] = {a.gs[0], a.gs[1], a.gs[2]};
+    reaction_vjp(x, gs, lam_n, ug, cot, vx, vgs, Gg);
+    double *tgt = (j == 0) ? a.DYN + p : a.MUX + (int64_t)j * sS + p;
+    for (int f = 0; f < NF; ++f) tgt[f * Np] += vx[f];
+    double *ps = a.PS + (int64_t)j * (3 * NG) * Np + p;
+    for (int k = 0; k < NG; ++k) {
+      const double c = cot[GATE0 + k];
+      ps[k * Np] = c;
+      ps[(NG + k) * Np] = c * (ug[k] - x[GATE0 + k]);
+      ps[(2 * NG + k) * Np] = ck[k] * Gg[k];
+    }
+    if (j >= 1) a.W[(int64_t)j * Np + p] = gam0 - dt * co.d[j - 1] * rho[(int64_t)j * sS];
   }
-  block_gs<ADB>(vgs, lds, a.gs_part);
+  block_sums<3, ADB>(vgs, lds);
+  if (threadIdx.x == 0) {
+    double *part = a.gs_part + 3 * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x);
+    part[0] = vgs[0];
+    part[1] = vgs[1];
+    part[2] = vgs[2];
+  }
+}
+
+// The stage contributions of k_adj_assemble, summed in stage order.
+__global__ void __launch_bounds__(ADB) k_adj_assemble_sum(AdjArgs a, int nstages) {
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  if (p >= a.N) return;
+  const int64_t Np = a.Np;
+  for (int k = 0; k < NG; ++k) {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int j = 0; j < nstages; ++j) {
+      const double *ps = a.PS + (int64_t)j * (3 * NG) * Np + p;
+      s1 += ps[k * Np];
+      s2 += ps[(NG + k) * Np];
+      s3 += ps[(2 * NG + k) * Np];
+    }
+    a.DYN[(GATE0 + k) * Np + p] += s1 * a.L0[k * Np + p];
+    a.DLAM[k * Np + p] += s2;
+    a.DZ[k * Np + p] += s3;
+  }
 }
 
 // Lambda_n = Lambda(u) backwards: DYN at V and Ca_ss += (dLambda/du)^T (dt DZ + DLAM).
@@ -307,9 +298,12 @@ __global__ void __launch_bounds__(ADB) k_adj_anchor(AdjArgs a) {
   ttp06::gates<ad::D>(ad::D(V, 1.0), ad::D(C, 0.0), [&](int k, ad::D, ad::D rate) {
     sv += (a.co.dt * a.DZ[k * Np + p] + a.DLAM[k * Np + p]) * (-rate.d);
   });
-  ttp06::gates<ad::D>(ad::D(V, 0.0), ad::D(C, 1.0), [&](int k, ad::D, ad::D rate) {
-    sc += (a.co.dt * a.DZ[k * Np + p] + a.DLAM[k * Np + p]) * (-rate.d);
-  });
+  {  // Ca_ss enters the rate of fCass only
+    constexpr int k = NG - 1;
+    ad::D in, rate;
+    ttp06::fcass_gate<ad::D>(ad::D(C, 1.0), in, rate);
+    sc = (a.co.dt * a.DZ[k * Np + p] + a.DLAM[k * Np + p]) * (-rate.d);
+  }
   a.DYN[p] += sv;
   a.DYN[3 * Np + p] += sc;
 }
@@ -404,17 +398,19 @@ hipError_t launch_adj_backsub(hipStream_t s, const AdjArgs &a, int i) {
 }
 
 hipError_t launch_adj_assemble(hipStream_t s, const AdjArgs &a) {
+  const dim3 grid(adj_blocks(a.N), a.co.M + 1);
   switch (a.co.M) {
-    case 1: hipLaunchKernelGGL(k_adj_assemble<1>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_adj_assemble<2>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_adj_assemble<3>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_adj_assemble<4>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
-    case 5: hipLaunchKernelGGL(k_adj_assemble<5>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
-    case 6: hipLaunchKernelGGL(k_adj_assemble<6>, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_adj_assemble<1>, grid, dim3(ADB), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_adj_assemble<2>, grid, dim3(ADB), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_adj_assemble<3>, grid, dim3(ADB), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_adj_assemble<4>, grid, dim3(ADB), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(k_adj_assemble<5>, grid, dim3(ADB), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_adj_assemble<6>, grid, dim3(ADB), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_adj_gs_reduce, dim3(1), dim3(ADB), 0, s, a.gs_part, (int)adj_blocks(a.N),
-                     a.gs_acc);
+  hipLaunchKernelGGL(k_adj_assemble_sum, dim3(adj_blocks(a.N)), dim3(ADB), 0, s, a, a.co.M + 1);
+  hipLaunchKernelGGL(k_adj_gs_reduce, dim3(1), dim3(ADB), 0, s, a.gs_part,
+                     (int)(adj_blocks(a.N) * (a.co.M + 1)), a.gs_acc);
   return hipGetLastError();
 }
 

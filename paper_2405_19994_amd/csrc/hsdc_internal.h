@@ -349,7 +349,8 @@ struct AdjArgs {
   double gs[3];
   const double *X, *Z, *L0;
   double *MU, *MUX, *RHO, *DYN, *DZ, *DLAM, *W;
-  double *gs_part, *gs_acc;
+  double *PS;  // (M + 1) x 3 NG x Np: per-stage terms of the transposed assembly
+  double *gs_part, *gs_acc;  // gs_part: 3 per block of 256 nodes and stage
 };
 hipError_t launch_adj_backsub(hipStream_t s, const AdjArgs &a, int i);
 hipError_t launch_adj_assemble(hipStream_t s, const AdjArgs &a);  // M <= 6

@@ -2349,7 +2349,7 @@ namespace {
 // The adjoint of one step's sweeps; lam holds the adjoint of y_{n+1} on entry
 // and receives that of y_n.  Xs must hold the step's iterates X^0 .. X^K.
 struct AdjBuffers {
-  double *Xs, *MU, *MUX, *RHO, *lam, *DYN, *DZ, *DLAM, *W, *dk, *gs_part, *gs_acc;
+  double *Xs, *MU, *MUX, *RHO, *lam, *DYN, *DZ, *DLAM, *W, *dk, *PS, *gs_part, *gs_acc;
 };
 
 void adjoint_step(hsdc_ctx *c, const AdjBuffers &b) {
@@ -2374,6 +2374,7 @@ void adjoint_step(hsdc_ctx *c, const AdjBuffers &b) {
   a.DZ = b.DZ;
   a.DLAM = b.DLAM;
   a.W = b.W;
+  a.PS = b.PS;
   a.gs_part = b.gs_part;
   a.gs_acc = b.gs_acc;
   double *dkx = b.dk, *dky = b.dk + Np, *dkz = b.dk + 2 * Np;
@@ -2544,17 +2545,18 @@ hsdc_status hsdc_misfit_backward(hsdc_adj *adj, double *grad_sigma, double *grad
     Level &F = c->L[0];
     const int M = F.co.M, K = c->meth.max_iter;
     const int64_t N = F.g.N, Np = F.g.Np, sS = (int64_t)NF * Np, sY = (int64_t)(M + 1) * sS;
-    const int64_t nbl = (N + 255) / 256;
+    const int64_t nbl = (M + 1) * ((N + 255) / 256);  // blocks of the transposed assembly
     const int64_t sizes[] = {(K + 1) * sY, sY, sY, sY, sS, sS, (int64_t)NG * Np, (int64_t)NG * Np,
-                             (int64_t)(M + 1) * Np, 3 * Np, 3 * nbl, 8};
+                             (int64_t)(M + 1) * Np, 3 * Np, (int64_t)(M + 1) * 3 * NG * Np,
+                             3 * nbl, 8};
     int64_t total = 0;
     for (int64_t v : sizes) total += v;
     if (!adj->work) adj->work = dalloc<double>(c, total);
     double *w = adj->work;
     AdjBuffers b{};
     double **slots[] = {&b.Xs, &b.MU, &b.MUX, &b.RHO, &b.lam, &b.DYN, &b.DZ, &b.DLAM, &b.W, &b.dk,
-                        &b.gs_part, &b.gs_acc};
-    for (int q = 0; q < 12; ++q) {
+                        &b.PS, &b.gs_part, &b.gs_acc};
+    for (int q = 0; q < 13; ++q) {
       *slots[q] = w;
       w += sizes[q];
     }

@@ -61,6 +61,16 @@ __device__ __forceinline__ R logistic(R x) { return R(1) / (R(1) + exp(x)); }
 // e^{b} (written out below as literals): e^{aV + b} = e^{b} e^{aV}, and
 // 1/(1 + e^{b} / E) = E / (E + e^{b}) needs no reciprocal of E.  An FP64
 // exponential costs about thirty instructions, a product one.
+// fCass, the one gate driven by Ca_ss alone: w_inf = 0.6 / (1 + q) + 0.4,
+// tau = 80 / (1 + q) + 2, q = (Ca_ss / 0.05)^2.
+template <class R>
+__host__ __device__ __forceinline__ void fcass_gate(R Ca_ss, R &inf, R &rate) {
+  const R q = (Ca_ss * R(20.0)) * (Ca_ss * R(20.0));
+  const R iq = R(1.0) / (R(1.0) + q);
+  inf = R(0.6) * iq + R(0.4);
+  rate = (R(1.0) + q) / (R(82.0) + R(2.0) * q);
+}
+
 template <class R, class Sink>
 __device__ __forceinline__ void gates(R V, R Ca_ss, Sink &&sink) {
   const R E20 = exp(V * R(0.05));  // e^{V/20}
@@ -131,17 +141,18 @@ __device__ __forceinline__ void gates(R V, R Ca_ss, Sink &&sink) {
                    R(31.0) * E10 / (E10 + R(12.182493960703473)) +  // e^2.5
                    R(16.0) * l30));
   }
-  {  // fCass: w_inf = 0.6 / (1 + q) + 0.4, tau = 80 / (1 + q) + 2, q = (Ca_ss / 0.05)^2
-    const R q = (Ca_ss * R(20.0)) * (Ca_ss * R(20.0));
-    const R iq = R(1.0) / (R(1.0) + q);
-    sink(11, R(0.6) * iq + R(0.4), (R(1.0) + q) / (R(82.0) + R(2.0) * q));
+  {
+    R inf, rate;
+    fcass_gate(Ca_ss, inf, rate);
+    sink(11, inf, rate);
   }
 }
 
 // Total ionic current I_ion (pA/pF) and the auxiliary derivatives h_a
 // (Ca_i, Ca_SR, Ca_ss, Na_i, K_i, Rbar).  gs scales G_Na, G_CaL, G_Kr.
 template <class R>
-__device__ __forceinline__ void currents(const R *y, R gs0, R gs1, R gs2, R &I_ion, R *ha) {
+__host__ __device__ __forceinline__ void currents(const R *y, R gs0, R gs1, R gs2, R &I_ion,
+                                                  R *ha) {
   const R V = y[0], Ca_i = y[1], Ca_sr = y[2], Ca_ss = y[3], Na_i = y[4], K_i = y[5];
   const R Rbar = y[6];
   const R m = y[7], h = y[8], jg = y[9], xr1 = y[10], xr2 = y[11], xs = y[12];
