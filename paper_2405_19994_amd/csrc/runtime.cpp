@@ -177,6 +177,10 @@ struct hsdc_ctx {
   CgScalars *cg_dlog = nullptr;  // device: final scalars of every budgeted solve
   int cg_log_cap = 0, cg_log_used = 0;
   int cg_fails = 0;  // unconverged budgeted solves found by flush_cg_log
+  // when set, flush_cg_log appends the CG launches each fine-level solve used
+  // (in the order the solves were enqueued): the misfit forward's record,
+  // which its backward run's recomputed steps take as their budgets
+  std::vector<int> *cg_record = nullptr;
   bool nonfinite = false;  // a solve met a NaN or Inf (reset by every stepping call)
   std::vector<CgLogEntry> cg_pending;
   Profiler prof;
@@ -740,6 +744,7 @@ void flush_cg_log(hsdc_ctx *c) {
     // budget = launches needed + margin, lowered by at most one per check;
     // doubled after a miss (a spare no-op launch costs far less than a
     // recomputed step)
+    if (c->cg_record && e.lev == 0) c->cg_record->push_back(ok_all ? used : -1);
     int &pred = pred_table(c, e.lev)[e.row & 15][e.i - 1];
     if (!ok_all)
       pred = std::min(c->meth.cg_maxit + 1, std::max(2 * e.budget, used + 4));
@@ -909,6 +914,7 @@ CgLogArgs cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, in
     if (!cg_ok(sc, tol2)) c->stats.cg_unconverged += 1;
     if (cg_nonfinite(sc)) c->nonfinite = true;
   }
+  if (c->cg_record && lev == 0) c->cg_record->push_back(used);
   pred = std::max(used + cg_margin(c, cb.x0_to_p), pred - 1);
   return lg;
 }
@@ -2342,6 +2348,9 @@ struct hsdc_adj {
   double *targets = nullptr;  // [nsamples][np]
   double *sigma = nullptr;    // [N] per-node sigma, or null
   double *work = nullptr;     // the reverse run's buffers (allocated on first use)
+  // CG launches of the forward's budgeted solves, step n at cg_used[cg_off[n]..cg_off[n + 1])
+  std::vector<int> cg_used;
+  std::vector<int64_t> cg_off;
 };
 
 namespace {
@@ -2350,9 +2359,66 @@ namespace {
 // and receives that of y_n.  Xs must hold the step's iterates X^0 .. X^K.
 struct AdjBuffers {
   double *Xs, *MU, *MUX, *RHO, *lam, *DYN, *DZ, *DLAM, *W, *dk, *PS, *gs_part, *gs_acc;
+  double *bak;          // lam, dk and gs_acc before the step (a budgeted step run again)
+  CgScalars *dlog;      // final scalars of the step's adjoint solves, [K][M]
+  std::vector<int> *pred;  // CG launches per adjoint solve (sweep, node); -1: not yet known
 };
 
-void adjoint_step(hsdc_ctx *c, const AdjBuffers &b) {
+// The adjoint diffusion solves of a step run at predicted numbers of CG
+// launches without a host synchronisation; their final scalars go to dlog and
+// are checked once per step (adjoint_verify).  In safe mode each solve is run
+// to convergence with host checks, and its launches become the prediction.
+void adjoint_solve(hsdc_ctx *c, const AdjBuffers &b, const CgBatch &cb, int k, int i, bool safe) {
+  Level &F = c->L[0];
+  const hipStream_t s = c->s;
+  const int M = F.co.M;
+  int &pred = (*b.pred)[(k - 1) * M + (i - 1)];
+  if (safe) {
+    int used = 0;
+    bool conv = false;
+    run_cg(s, F.g, cb, &used, &conv);
+    if (!conv) {
+      fail(c, HSDC_ENOCONV, "an adjoint diffusion solve reached cg_maxit");
+      throw StatusFail{HSDC_ENOCONV};
+    }
+    c->stats.cg_iters += used;
+    c->stats.cg_solves += 1;
+    pred = used + 2;
+    return;
+  }
+  const int budget = std::max(1, std::min(pred, cb.maxit + 1));
+  HIPC(launch_cg_resid0(s, F.g, cb));
+  HIPC(launch_cg_init(s, F.g, cb));
+  for (int q = 0; q < budget; ++q) HIPC(launch_cg_iter(s, F.g, cb, q));
+  HIPC(hipMemcpyAsync(b.dlog + (int64_t)(k - 1) * M + (i - 1), cb.sc + (budget & 1),
+                      sizeof(CgScalars), hipMemcpyDeviceToDevice, s));
+}
+
+// One host synchronisation: did every adjoint solve of the step converge?
+// Predictions follow the iterations used plus two launches, lowered by at
+// most one per step, raised at once.
+bool adjoint_verify(hsdc_ctx *c, const AdjBuffers &b) {
+  Level &F = c->L[0];
+  const int n = c->meth.max_iter * F.co.M;
+  std::vector<CgScalars> h(n);
+  HIPC(hipMemcpyAsync(h.data(), b.dlog, n * sizeof(CgScalars), hipMemcpyDeviceToHost, c->s));
+  HIPC(hipStreamSynchronize(c->s));
+  const double tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
+  bool ok = true;
+  for (int q = 0; q < n; ++q) {
+    int &pred = (*b.pred)[q];
+    if (!cg_ok(h[q], tol2)) {
+      ok = false;
+      continue;
+    }
+    c->stats.cg_iters += h[q].it;
+    c->stats.cg_solves += 1;
+    pred = std::max(h[q].it + 2, pred - 1);
+  }
+  return ok;
+}
+
+void adjoint_step(hsdc_ctx *c, const AdjBuffers &b, bool safe) {
   Level &F = c->L[0];
   const int M = F.co.M, K = c->meth.max_iter;
   const int64_t Np = F.g.Np, sS = (int64_t)NF * Np, sY = (int64_t)(M + 1) * sS;
@@ -2408,13 +2474,7 @@ void adjoint_step(hsdc_ctx *c, const AdjBuffers &b) {
       cb.a = F.co.dt * F.co.d[i - 1];
       cb.tol2 = c->meth.cg_rtol * c->meth.cg_rtol;
       cb.maxit = c->meth.cg_maxit;
-      int used = 0;
-      bool conv = false;
-      run_cg(s, F.g, cb, &used, &conv);
-      if (!conv) {
-        fail(c, HSDC_ENOCONV, "an adjoint diffusion solve reached cg_maxit");
-        throw StatusFail{HSDC_ENOCONV};
-      }
+      adjoint_solve(c, b, cb, k, i, safe);
       HIPC(launch_adj_faces(s, F.g, cb.x, Z + (int64_t)i * sS, cb.a, dkx, dky, dkz));
       HIPC(launch_adj_backsub(s, a, i));
     }
@@ -2435,8 +2495,10 @@ void adjoint_step(hsdc_ctx *c, const AdjBuffers &b) {
   HIPC(hipMemcpyAsync(b.lam, b.DYN, sS * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 
-// Recompute step n from its checkpoint, keeping every sweep's iterate.
-void recompute_step(hsdc_ctx *c, const hsdc_adj *adj, int n, double *Xs) {
+// Recompute step n from its checkpoint, keeping every sweep's iterate.  The
+// solves run at budgets, verified once at the end (flush_cg_log); a step with
+// a solve that missed cg_rtol is recomputed with every solve checked.
+void recompute_step(hsdc_ctx *c, const hsdc_adj *adj, int n, double *Xs, bool safe = false) {
   Level &F = c->L[0];
   const int M = F.co.M, K = c->meth.max_iter;
   const int64_t sY = F.st.sY();
@@ -2445,11 +2507,34 @@ void recompute_step(hsdc_ctx *c, const hsdc_adj *adj, int n, double *Xs) {
   HIPC(launch_copy_fields(c->s, F.g.Np, F.st.Y, 0, adj->ckpt + (int64_t)n * NF * F.g.Np, 0, NF, 1));
   begin_serial_step(c);
   materialize(c);
-  c->safe_cg = true;
+  // the forward's own launches as budgets: the recomputation repeats its work
+  if (!safe && (int64_t)adj->cg_off.size() > n + 1 &&
+      adj->cg_off[n + 1] - adj->cg_off[n] == (int64_t)K * M) {
+    const int *u = adj->cg_used.data() + adj->cg_off[n];
+    bool known = true;
+    for (int q = 0; q < K * M; ++q) known = known && u[q] >= 0;
+    if (known)
+      for (int k = 0; k < K; ++k)
+        for (int i = 1; i <= M; ++i) F.cg_pred[k & 15][i - 1] = u[k * M + (i - 1)];
+  }
+  c->safe_cg = safe;
+  c->cg_fails = 0;
   HIPC(launch_copy_fields(c->s, F.g.Np, Xs, 0, F.st.Y, 0, (M + 1) * NF, 1));
   for (int k = 1; k <= K; ++k) {
     sweep(c, F, 0, 0, 1, nullptr, nullptr, k - 1, false);
     HIPC(launch_copy_fields(c->s, F.g.Np, Xs + (int64_t)k * sY, 0, F.st.Y, 0, (M + 1) * NF, 1));
+  }
+  if (safe) return;
+  flush_cg_log(c);
+  c->safe_cg = true;
+  if (c->nonfinite) {
+    fail(c, HSDC_ENONFINITE, "non-finite state in the recomputed step");
+    throw StatusFail{HSDC_ENONFINITE};
+  }
+  if (c->cg_fails > 0) {
+    c->stats.cg_redo_steps += 1;
+    c->cg_fails = 0;
+    recompute_step(c, adj, n, Xs, true);
   }
 }
 
@@ -2505,9 +2590,17 @@ hsdc_status hsdc_misfit_forward(const hsdc_problem *prob, const hsdc_method *met
     }
     adj->ckpt = dalloc<double>(c, (size_t)(nsteps + 1) * NF * Np);
     double *sq = dalloc<double>(c, (size_t)std::max(1, ns) * nprobes);
+    adj->cg_off.assign(1, 0);
     for (int n = 0; n < nsteps; ++n) {
       HIPC(launch_copy_fields(c->s, Np, adj->ckpt + (int64_t)n * NF * Np, 0, F.st.Y, 0, NF, 1));
+      c->cg_record = &adj->cg_used;
       const hsdc_status sa = hsdc_advance(c, 1);
+      c->cg_record = nullptr;
+      // a step run again with checked solves: its own solves come last
+      const int64_t per = (int64_t)c->meth.max_iter * F.co.M, got = (int64_t)adj->cg_used.size() - adj->cg_off.back();
+      if (got > per)
+        adj->cg_used.erase(adj->cg_used.begin() + adj->cg_off.back(), adj->cg_used.end() - per);
+      adj->cg_off.push_back((int64_t)adj->cg_used.size());
       if (sa != HSDC_OK) return sa;
       if ((n + 1) % sample_every == 0) {
         const int smp = (n + 1) / sample_every - 1;
@@ -2546,20 +2639,25 @@ hsdc_status hsdc_misfit_backward(hsdc_adj *adj, double *grad_sigma, double *grad
     const int M = F.co.M, K = c->meth.max_iter;
     const int64_t N = F.g.N, Np = F.g.Np, sS = (int64_t)NF * Np, sY = (int64_t)(M + 1) * sS;
     const int64_t nbl = (M + 1) * ((N + 255) / 256);  // blocks of the transposed assembly
+    const int64_t nlog = (int64_t)K * M * (int64_t)((sizeof(CgScalars) + 7) / 8);
     const int64_t sizes[] = {(K + 1) * sY, sY, sY, sY, sS, sS, (int64_t)NG * Np, (int64_t)NG * Np,
                              (int64_t)(M + 1) * Np, 3 * Np, (int64_t)(M + 1) * 3 * NG * Np,
-                             3 * nbl, 8};
+                             3 * nbl, 8, sS + 3 * Np + 8, nlog};
     int64_t total = 0;
     for (int64_t v : sizes) total += v;
     if (!adj->work) adj->work = dalloc<double>(c, total);
     double *w = adj->work;
     AdjBuffers b{};
+    double *dlog = nullptr;
     double **slots[] = {&b.Xs, &b.MU, &b.MUX, &b.RHO, &b.lam, &b.DYN, &b.DZ, &b.DLAM, &b.W, &b.dk,
-                        &b.PS, &b.gs_part, &b.gs_acc};
-    for (int q = 0; q < 13; ++q) {
+                        &b.PS, &b.gs_part, &b.gs_acc, &b.bak, &dlog};
+    for (int q = 0; q < 15; ++q) {
       *slots[q] = w;
       w += sizes[q];
     }
+    b.dlog = reinterpret_cast<CgScalars *>(dlog);
+    std::vector<int> pred((size_t)K * M, -1);
+    b.pred = &pred;
     HIPC(hipMemsetAsync(b.lam, 0, sS * sizeof(double), c->s));
     HIPC(hipMemsetAsync(b.dk, 0, 3 * Np * sizeof(double), c->s));
     HIPC(hipMemsetAsync(b.gs_acc, 0, 8 * sizeof(double), c->s));
@@ -2570,7 +2668,24 @@ hsdc_status hsdc_misfit_backward(hsdc_adj *adj, double *grad_sigma, double *grad
                              adj->targets + (int64_t)(adj->nsteps / every - 1) * np, np, nullptr, b.lam));
     for (int n = adj->nsteps - 1; n >= 0; --n) {
       recompute_step(c, adj, n, b.Xs);
-      adjoint_step(c, b);
+      // budgeted adjoint solves once every solve has a prediction
+      const bool safe = *std::min_element(pred.begin(), pred.end()) < 0;
+      if (!safe) {
+        HIPC(hipMemcpyAsync(b.bak, b.lam, sS * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+        HIPC(hipMemcpyAsync(b.bak + sS, b.dk, 3 * Np * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+        HIPC(hipMemcpyAsync(b.bak + sS + 3 * Np, b.gs_acc, 8 * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->s));
+      }
+      adjoint_step(c, b, safe);
+      if (!safe && !adjoint_verify(c, b)) {
+        // a solve missed cg_rtol: restore what the step accumulates, run it safe
+        c->stats.cg_redo_steps += 1;
+        HIPC(hipMemcpyAsync(b.lam, b.bak, sS * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+        HIPC(hipMemcpyAsync(b.dk, b.bak + sS, 3 * Np * sizeof(double), hipMemcpyDeviceToDevice, c->s));
+        HIPC(hipMemcpyAsync(b.gs_acc, b.bak + sS + 3 * Np, 8 * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->s));
+        adjoint_step(c, b, true);
+      }
       if (n > 0 && n % every == 0)
         HIPC(launch_adj_probes(c->s, adj->ckpt + (int64_t)n * NF * Np, adj->probes,
                                adj->targets + (int64_t)(n / every - 1) * np, np, nullptr, b.lam));
