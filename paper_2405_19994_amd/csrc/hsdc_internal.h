@@ -307,9 +307,15 @@ hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb
 // theta = pi k / n (one entry 0 for an axis of one node).
 struct DctPlan {
   const double *C[3], *CT[3], *lam[3];
+  // fast: every transformed axis has a power-of-two length in [2, 2048]; ft
+  // holds per axis the twiddles W (n/2 complex), E (n complex), s and 1/s (n)
+  int fast;
+  const double *ft[3];
 };
 // x = (I - a K)^-1 b for nslices slices (slice strides sb, sx; t1, t2 scratch
 // [nslices][st]); g uniform, not a batch.
+// allows the fast transforms' LDS for lines up to nmax long (once per process)
+hipError_t fdct_setup(int nmax);
 hipError_t launch_dct_solve(hipStream_t s, const Grid &g, const DctPlan &d, double a,
                             const double *b, int64_t sb, double *x, int64_t sx, double *t1,
                             double *t2, int64_t st, int nslices);

@@ -582,6 +582,36 @@ DctPlan make_dct_plan(hsdc_ctx *c, const Grid &g) {
     d.CT[ax] = dCT;
     d.lam[ax] = dl;
   }
+  // the fast transforms: every transformed axis (x, and y, z when longer than
+  // one node) of a power-of-two length in [2, 2048]
+  bool fast = true;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = nn[ax];
+    if (ax > 0 && n == 1) continue;
+    fast = fast && n >= 2 && n <= 2048 && (n & (n - 1)) == 0;
+  }
+  d.fast = fast ? 1 : 0;
+  if (fast) HIPC(fdct_setup(std::max(nn[0], std::max(nn[1], nn[2]))));
+  if (fast)
+    for (int ax = 0; ax < 3; ++ax) {
+      const int n = nn[ax];
+      if (ax > 0 && n == 1) continue;
+      std::vector<double> t((size_t)5 * n);
+      for (int k = 0; k < n / 2; ++k) {  // W_k = e^{-2 pi i k / n}
+        t[2 * k] = (double)std::cos(2.0L * pi * k / n);
+        t[2 * k + 1] = (double)-std::sin(2.0L * pi * k / n);
+      }
+      for (int k = 0; k < n; ++k) {  // E_k = e^{-i pi k / 2n}, s_k
+        t[n + 2 * k] = (double)std::cos(pi * k / (2.0L * n));
+        t[n + 2 * k + 1] = (double)-std::sin(pi * k / (2.0L * n));
+        t[3 * n + k] = (double)std::sqrt((k == 0 ? 1.0L : 2.0L) / n);
+        t[4 * n + k] = (double)std::sqrt(n / (k == 0 ? 1.0L : 2.0L));
+      }
+      double *dt = dalloc<double>(c, t.size());
+      HIPC(hipMemcpyAsync(dt, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, c->s));
+      HIPC(hipStreamSynchronize(c->s));
+      d.ft[ax] = dt;
+    }
   return d;
 }
 
@@ -825,10 +855,15 @@ CgLogArgs cg_solve(hsdc_ctx *c, LevelT<T> &L, int lev, int s0, int ns, int i, in
   if constexpr (std::is_same<T, double>::value) {
     if (cb.direct) {
       // exact solve in the DCT-II eigenbasis: b to the stage's V, through two
-      // [P][Np] work vectors; algorithmic work 2 n FLOP per node and axis, each way
+      // [P][Np] work vectors.  Fast transforms: one launch per axis each way,
+      // the last axis's two fused, each reading and writing 8 B per node; dense
+      // transforms: 2 n FLOP per node and axis each way (the dct_solve class
+      // then counts FLOPs where the others count bytes)
       const int64_t Np = L.g.Np;
-      const double fl = 4.0 * (L.g.nx + (L.g.ny > 1 ? L.g.ny : 0) + (L.g.nz > 1 ? L.g.nz : 0));
-      // (the dct_solve class counts FLOPs where the others count bytes)
+      const int na = 1 + (L.g.ny > 1 ? 1 : 0) + (L.g.nz > 1 ? 1 : 0);
+      const double fl = L.dct.fast
+                            ? 16.0 * (2 * na - 1)
+                            : 4.0 * (L.g.nx + (L.g.ny > 1 ? L.g.ny : 0) + (L.g.nz > 1 ? L.g.nz : 0));
       PLAUNCH(c, PC_DCT, fl * nodes,
               launch_dct_solve(c->s, L.g, L.dct, cb.a, cb.bout, Np, cb.x, cb.sx,
                                L.cg_r[0] + s0 * Np, L.cg_w[0] + s0 * Np, Np, ns));

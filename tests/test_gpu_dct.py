@@ -35,8 +35,13 @@ def lib_problem(w):
                           w["stim_t0"], w["stim_dur"], fd_order=w.get("fd_order", 2))
 
 
+# lengths that are not powers of two take the dense transforms, the others
+# (every transformed axis a power of two) the fast ones
 CASES = {"1d": ((37,), (1.0, 1, 1)), "2d": ((33, 21), (1.0, 2.0, 1)),
-         "3d_aniso": ((12, 10, 6), (3.0, 1.0, 0.5)), "2d_odd_small": ((5, 3), (1.0, 1, 1))}
+         "3d_aniso": ((12, 10, 6), (3.0, 1.0, 0.5)), "2d_odd_small": ((5, 3), (1.0, 1, 1)),
+         "1d_pow2": ((128,), (1.0, 1, 1)), "2d_pow2": ((64, 32), (1.0, 2.0, 1)),
+         "3d_pow2_aniso": ((16, 8, 4), (3.0, 1.0, 0.5)), "2d_pow2_tiny": ((2, 4), (1.0, 1, 1)),
+         "2d_pow2_long": ((2048, 2), (1.0, 1.5, 1))}
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -100,7 +105,8 @@ def _serial(w, nsteps, every, M, K, tol=1e-10):
 
 
 @pytest.mark.parametrize("kind,dims,order", [("cable1d", (64,), 4), ("slab2d", (31, 23), 4),
-                                             ("slab3d", (10, 8, 6), 4), ("slab2d", (31, 23), 2)])
+                                             ("slab3d", (10, 8, 6), 4), ("slab2d", (31, 23), 2),
+                                             ("slab2d", (32, 16), 4), ("slab3d", (8, 4, 4), 4)])
 def test_dct_serial_parity(kind, dims, order):
     """Serial hybrid SDC with the DCT-II solver, fourth-order stencil (and the
     second-order one), 1D/2D/3D, against the oracle's LU solves."""
@@ -110,7 +116,7 @@ def test_dct_serial_parity(kind, dims, order):
     assert np.all(np.isfinite(y))
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 4), (36, 18)])
+@pytest.mark.parametrize("dims", [(8, 6, 4), (36, 18), (16, 8)])
 def test_dct_pfasst_iterates_parity(dims):
     """Two-level PFASST (space-coarsened, the coarse level fourth order on its
     own mesh) with DCT-II solves on both levels: every iterate of Algorithm 1
