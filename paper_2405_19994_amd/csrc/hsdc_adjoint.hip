@@ -332,6 +332,20 @@ __global__ void __launch_bounds__(ADB) k_adj_spmv_add(Grid g, const double *v, d
   out[p] += s * applyK<DIM, PN>(g, p, c, v[p], [&](int64_t k) { return v[k]; });
 }
 
+// The first Chebyshev step of an adjoint solve, x_1 = x_0 + (b - A x_0) / theta
+// with A = I - a K (as the node update forms it for the forward solves).
+template <int DIM, bool PN>
+__global__ void __launch_bounds__(ADB)
+k_adj_cheb_x1(Grid g, const double *x0, const double *b, double a, const ChebTab *tab,
+              double *x1) {
+  const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
+  if (p >= g.N) return;
+  const Ijk c = ijk(g, p);
+  const double xc = x0[p];
+  const double r = b[p] - (xc - a * applyK<DIM, PN>(g, p, c, xc, [&](int64_t q) { return x0[q]; }));
+  x1[p] = xc + r * tab->inv_theta;
+}
+
 // dsigma_p from the face gradients: a face coefficient is sc 2 s_p s_q / (s_p + s_q).
 __global__ void __launch_bounds__(ADB)
 k_adj_sigma(Grid g, const double *sig, double sc, const double *dkx, const double *dky,
@@ -430,6 +444,13 @@ hipError_t launch_adj_spmv_add(hipStream_t s, const Grid &g, const double *v, do
                                double *out) {
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_adj_spmv_add<DIM, PN>), dim3(adj_blocks(g.N)),
                                          dim3(ADB), 0, s, g, v, scale, out));
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_cheb_x1(hipStream_t s, const Grid &g, const double *x0, const double *b,
+                              double a, const ChebTab *tab, double *x1) {
+  HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_adj_cheb_x1<DIM, PN>), dim3(adj_blocks(g.N)),
+                                         dim3(ADB), 0, s, g, x0, b, a, tab, x1));
   return hipGetLastError();
 }
 

@@ -365,6 +365,9 @@ hipError_t launch_adj_faces(hipStream_t s, const Grid &g, const double *u, const
                             double scale, double *dkx, double *dky, double *dkz);
 hipError_t launch_adj_spmv_add(hipStream_t s, const Grid &g, const double *v, double scale,
                                double *out);
+// x1 = x0 + (b - (I - a K) x0) * tab->inv_theta (the first Chebyshev step)
+hipError_t launch_adj_cheb_x1(hipStream_t s, const Grid &g, const double *x0, const double *b,
+                              double a, const ChebTab *tab, double *x1);
 hipError_t launch_adj_sigma(hipStream_t s, const Grid &g, const double *sig, double sc,
                             const double *dkx, const double *dky, const double *dkz, double *dsig);
 hipError_t launch_adj_probes(hipStream_t s, const double *y, const int64_t *probes,

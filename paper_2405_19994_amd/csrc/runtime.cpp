@@ -2403,10 +2403,23 @@ struct AdjBuffers {
 // launches without a host synchronisation; their final scalars go to dlog and
 // are checked once per step (adjoint_verify).  In safe mode each solve is run
 // to convergence with host checks, and its launches become the prediction.
+// With the Chebyshev tables of the forward solves (solver 0 or 1), the CG
+// starts from x_D, D Chebyshev steps from x_0 = b (a spectral interval of the
+// operator is known, so they need no inner products).
+constexpr int kAdjChebDegree = 8;  // even: x_D lands in x
+
 void adjoint_solve(hsdc_ctx *c, const AdjBuffers &b, const CgBatch &cb, int k, int i, bool safe) {
   Level &F = c->L[0];
   const hipStream_t s = c->s;
   const int M = F.co.M;
+  if (F.cheb_x) {
+    CgBatch cs = cb;
+    cs.xt = F.cheb_x;
+    cs.tab = F.cheb_tab + (i - 1);
+    cs.tab_stride = M;
+    HIPC(launch_adj_cheb_x1(s, F.g, cb.x, cb.b, cb.a, cs.tab, cs.xt));
+    HIPC(launch_cheb_steps(s, F.g, cs, kAdjChebDegree - 1));
+  }
   int &pred = (*b.pred)[(k - 1) * M + (i - 1)];
   if (safe) {
     int used = 0;
