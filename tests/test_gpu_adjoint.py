@@ -125,3 +125,46 @@ def test_adjoint_gradient_of_initial_state_and_repeat():
     fd = (loss_from(yp) - loss_from(ym)) / (2 * h)
     ad = float(dy1[0].cpu().numpy() @ v)
     assert abs(fd - ad) <= 1e-5 * abs(fd), (fd, ad)
+
+
+@pytest.mark.parametrize("solver", ["chebyshev", "cg_plain"])
+def test_adjoint_solver_options_agree(solver):
+    """The adjoint's diffusion solves start from Chebyshev steps when the
+    forward solves have Chebyshev tables (solvers "cg" and "chebyshev") and
+    run plain CG otherwise ("cg_plain"); every solve converges to 1e-14, so
+    the gradients of the three options agree to rounding (1e-8 relative),
+    also on a 1D cable (the other stencil)."""
+    N, rng, sigma0, truth, probes, stim = _case()
+    targets = _oracle_V(truth, (1.1, 0.9, 1.2), probes, stim)
+
+    def grads(dims, sig, st, pr, tg, solv):
+        prob = H.make_problem(dims, DX, (1.0, 1.0, 1.0),
+                              torch.tensor(sig, dtype=torch.float64, device="cuda"), 1400.0, 1.0,
+                              (1.0, 1.0, 1.0), torch.tensor(st, dtype=torch.float64, device="cuda"),
+                              50.0, 0.0, 1.0)
+        m = H.Misfit(prob, H.make_method(M=(M, 1), dt=DT, max_iter=K, cg_rtol=1e-14, cg_maxit=400,
+                                         solver=solv),
+                     torch.tensor(pr, dtype=torch.int64, device="cuda"),
+                     torch.tensor(tg, dtype=torch.float64, device="cuda"), NSTEPS, EVERY)
+        ds, dg, dy = m.backward(sigma=True, y0=True)
+        m.destroy()
+        return ds.cpu().numpy(), np.asarray(dg), dy.cpu().numpy()
+
+    def close(a, b):
+        return np.max(np.abs(a - b)) <= 1e-8 * np.max(np.abs(b))
+
+    ref = grads(DIMS, sigma0, stim, probes, targets, "cg")
+    got = grads(DIMS, sigma0, stim, probes, targets, solver)
+    for a, b in zip(got, ref):
+        assert close(a, b), (np.max(np.abs(a - b)), np.max(np.abs(b)))
+    # 1D: 64 cells, the first 4 stimulated, 4 probes, random targets
+    n1 = 64
+    s1 = np.exp(0.3 * rng.standard_normal(n1))
+    st1 = np.zeros(n1)
+    st1[:4] = 1.0
+    pr1 = np.array([5, 20, 40, 60])
+    tg1 = -80.0 + 10.0 * rng.standard_normal((NSTEPS // EVERY, 4))
+    ref1 = grads((n1,), s1, st1, pr1, tg1, "cg")
+    got1 = grads((n1,), s1, st1, pr1, tg1, solver)
+    for a, b in zip(got1, ref1):
+        assert close(a, b), (np.max(np.abs(a - b)), np.max(np.abs(b)))
