@@ -350,9 +350,11 @@ hsdc_status hsdc_diffusion_solve_noalloc(const hsdc_problem *prob, double a, con
  * state.  The gradient is the exact derivative of the discrete forward map
  * (solves taken as exact: use cg_rtol of 1e-13 or below): the forward keeps
  * y_n before every step, the backward recomputes each step from it and runs
- * the transposed sweep (the cell model's Jacobian by forward-mode dual
- * numbers, the symmetric diffusion solves, the derivatives of a_ij(z) and of
- * phi_1 through phi_k' = phi_k - k phi_{k+1}).
+ * the transposed sweep (the cell model's Jacobian transposed: the currents in
+ * one reverse pass, the gates by dual numbers; the symmetric diffusion solves;
+ * the derivatives of a_ij(z) and of phi_1 through phi_k' = phi_k - k
+ * phi_{k+1}).  Its solves run at iteration budgets checked once per step (a
+ * step with a missed solve is run again with every solve checked).
  * hsdc_misfit_forward: meth serial (levels = 1, P = 1) with M <= 6; probes
  * device [nprobes] distinct node indices; targets device [S][nprobes] (copied);
  * *loss_host receives L; *out an opaque handle holding the checkpoints
