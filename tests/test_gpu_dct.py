@@ -139,3 +139,41 @@ def test_dct_pfasst_iterates_parity(dims):
                 e = field_errors(host(ctx.get_state(0, n, j)), z[n][j])
                 assert np.max(e) < 1e-10, (k, n, j, np.max(e))
     ctx.destroy()
+
+
+@pytest.mark.parametrize("dims", [(16, 8), (36, 20)])
+def test_dct_three_level_pfasst_iterates_parity(dims):
+    """The paper's spatial setup with three levels (Sec. 5.1: M 6, 3, 1): the
+    fourth-order stencil and DCT-II solves on every level, each level on a mesh
+    coarsened twice in space; after each of three iterations every stage of
+    every slice on the fine level and the coarsest level's two stages equal the
+    oracle's.  16 x 8 takes the fast transforms on all three levels (16 x 8,
+    8 x 4, 4 x 2), 36 x 20 the dense ones (36 x 20, 18 x 10, 9 x 5)."""
+    from tests._parity import oracle_hierarchy_levels
+    P = 4
+    w = dict(si.workload("slab2d", dims=dims))
+    w["dt"] = 0.1
+    w["fd_order"] = 4
+    h = oracle_hierarchy_levels(w, (6, 3, 1), 2)
+    y0 = rest(h.levels[0].prob.N)
+    m = H.make_method(M=(6, 3, 1), levels=3, space_coarsen=2, P=P, dt=0.1, max_iter=50, tol=0.0,
+                      burn_in=1, cg_rtol=1e-14, cg_maxit=300, solver="dct")
+    ctx = H.Context(lib_problem(w), m, dev(y0))
+    seen = []
+
+    def check(k, z, zc):
+        res, _ = ctx.pfasst_iter()
+        for n in range(P):
+            for j in range(7):
+                e = field_errors(host(ctx.get_state(0, n, j)), z[n][j])
+                assert np.max(e) < 1e-10, ("fine", k, n, j, np.max(e))
+            for j in range(2):
+                e = field_errors(host(ctx.get_state(2, n, j)), zc[n][j])
+                assert np.max(e) < 1e-10, ("coarsest", k, n, j, np.max(e))
+        seen.append(res)
+
+    _, hist, _ = pfasst_block(h, y0, P, 3, tol=0.0, callback=check)
+    assert len(seen) == 3
+    for k in range(3):
+        assert np.max(np.abs(np.array(hist[k]) - seen[k])) < 1e-9 * max(1.0, np.max(hist[k]))
+    ctx.destroy()
