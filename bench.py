@@ -70,6 +70,9 @@ def _args():
                                            "slab2d_fd4"),
                     default="slab2d")
     ap.add_argument("--tissues", type=int, default=64, help="batch2d: tissues in the batch")
+    ap.add_argument("--side", type=int, default=512,
+                    help="slab2d: mesh side (the metric is quoted on 512; other sides show how "
+                         "the kernels scale with the mesh, without the CPU baseline and counters)")
     ap.add_argument("--summarize-valu", metavar="COUNTER_CSV",
                     help="write the VALU instruction counters (SQ_WAVES, SQ_INSTS_VALU and its "
                          "FP64 FMA/ADD/MUL/TRANS parts) of a rocprofv3 --pmc run into "
@@ -215,15 +218,16 @@ def _valu_issue(kernel, avg_us):
     return None if k is None else k["valu"] * 4.0 / (1024 * 2.4e9 * avg_us * 1e-6)
 
 
-def _roofline(name, k, N):
+def _roofline(name, k, N, counters=True):
     """Roofline object of the dominant kernel from its event-timed average
     launch duration.  The fused cell-model kernel (node_update) is judged
     against the FP64 vector peak (algorithmic FLOP = FLOP_PER_NODE_UPDATE x the
     launch's nodes); its HBM side is given beside it (bytes per launch counted
     from the sizes, against the 8 TB/s peak) with the ceiling its arithmetic
     intensity allows (an HBM-bound kernel reaches at most intensity x 8 TB/s).
-    Other kernels are judged against the HBM peak."""
-    traffic = _traffic(name)
+    Other kernels are judged against the HBM peak.  counters=False (another
+    mesh than the counters' 512 x 512): no counter-based figures."""
+    traffic = _traffic(name) if counters else None
     gbps = k["GBps"]
     if name != "node_update":
         return {"kernel": name, "bound": "hbm", "achieved": gbps, "peak": 8000.0, "unit": "GB/s",
@@ -237,7 +241,7 @@ def _roofline(name, k, N):
             "flop_per_node_update": FLOP_PER_NODE_UPDATE,
             "intensity_flop_per_byte": intensity,
             "attainable_frac": min(1.0, intensity * 8.0 / 78.6),
-            "valu_issue_frac": _valu_issue(name, k["avg_us"]),
+            "valu_issue_frac": _valu_issue(name, k["avg_us"]) if counters else None,
             "hbm": {"achieved": gbps, "peak": 8000.0, "unit": "GB/s", "frac": gbps / 8000.0,
                     "bytes_per_launch": k["bytes_per_launch"],
                     "bytes_per_node_update": k["bytes_per_launch"] / N,
@@ -912,15 +916,16 @@ def main():
     if a.workload == "slab2d_fd4":
         bench_slab2d_fd4(a)
         return
-    # the oracle's worker processes run before anything touches the GPU
-    cpu = None if a.no_cpu_baseline else cpu_baseline()
+    # the oracle's worker processes run before anything touches the GPU (the
+    # baseline is of the 512 x 512 slab the metric is quoted on)
+    cpu = None if (a.no_cpu_baseline or a.side != 512) else cpu_baseline()
 
     import torch
 
     import synthetic_inputs as si
     from paper_2405_19994_amd import hsdc as H
 
-    w = si.workload("slab2d")
+    w = si.workload("slab2d", dims=(a.side, a.side))
     N = int(np.prod(w["dims"]))
     dev = torch.device("cuda:0")
     stim = torch.tensor(w["stim_w"], dtype=torch.float64, device=dev)
@@ -995,7 +1000,7 @@ def main():
     ctx.destroy()
     kernels = _kernel_table(kp, _solver_bytes(pst, N))
     dom = max(kernels, key=lambda k: kernels[k]["time_share"])
-    roofline = _roofline(dom, kernels[dom], N)
+    roofline = _roofline(dom, kernels[dom], N, counters=a.side == 512)
 
     updates = N * w["M"] * w["K"] * a.steps
     value = updates / wall
@@ -1012,7 +1017,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "slab2d 512x512, 5-point, TTP06, M6 K6, dt 0.05 ms, "
+        "config": {"workload": f"slab2d {a.side}x{a.side}, 5-point, TTP06, M6 K6, dt 0.05 ms, "
                                + SOLVER_NAMES[a.solver] + " 1e-12",
                    "nodes": N, "M": w["M"], "sweeps": w["K"], "dt_ms": w["dt"],
                    "t_simulated_ms": a.steps * w["dt"]},
