@@ -234,6 +234,20 @@ hsdc_status hsdc_tune_shapes(hsdc_ctx *ctx, int32_t node_block, int32_t cg_tile,
  * the graph. */
 hsdc_status hsdc_use_graph(hsdc_ctx *ctx, int32_t on);
 
+/* Serial steps of a small 1D mesh in one launch (Sec. 3.1.3, the sweep of eq.
+ * prec_picard; on by default).  A serial context on a 1D mesh of at most 256
+ * nodes (second-order stencil, solver 0, 1 or 2) advances all steps of an
+ * hsdc_advance call in one launch of one workgroup: one thread per node, the
+ * stencil products and the diffusion solves through LDS, each solve direct
+ * (cyclic reduction of the tridiagonal system, exact up to rounding, counted
+ * in the stats as a solve with no CG iteration) instead of CG to cg_rtol.
+ * The per-launch kernels of other meshes need launches of a few microseconds
+ * each, about a hundred per step.  Not taken while graph replay or kernel
+ * timing is on, or between the sweeps of a step (hsdc_sdc_sweep).  on = 0
+ * keeps every step on the per-launch kernels.  A step that turns a state
+ * non-finite ends the call with HSDC_ENONFINITE. */
+hsdc_status hsdc_single_block(hsdc_ctx *ctx, int32_t on);
+
 /* Apply nsweeps preconditioned Picard iterations (eq. prec_picard, one forward
  * substitution with P^-1 of eq. def_P each) to the stage vector of one slice of
  * the fine level.  PFASST contexts keep the slice's start value y_{n,0}; serial

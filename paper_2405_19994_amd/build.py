@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsdc.so")
-SOURCES = ["hsdc_kernels.hip", "hsdc_adjoint.hip", "hsdc_dct.hip", "runtime.cpp", "coeffs.cpp"]
+SOURCES = ["hsdc_kernels.hip", "hsdc_adjoint.hip", "hsdc_dct.hip", "hsdc_small.hip", "runtime.cpp",
+           "coeffs.cpp"]
 ARCH = os.environ.get("HSDC_OFFLOAD_ARCH", "gfx950")
 
 

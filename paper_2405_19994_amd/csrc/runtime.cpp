@@ -41,6 +41,16 @@ void transfer_matrix(int Mfrom, const double *c_from, int Mto, const double *c_t
 
 using namespace hsdc;
 
+namespace hsdc {
+// Serial steps of a 1D mesh of at most 256 nodes in one launch of one
+// workgroup (hsdc_small.hip): y_n in stage 0 of st, y_{n+nsteps} left there;
+// *steps_done receives the steps completed, negated when the last of them
+// turned a state non-finite (the launch stops after that step).
+hipError_t launch_small_steps(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
+                              const Stim &stim, double gs0, double gs1, double gs2, int K,
+                              int nsteps, int *steps_done);
+}  // namespace hsdc
+
 namespace {
 
 thread_local std::string g_free_error;
@@ -187,6 +197,9 @@ struct hsdc_ctx {
   // graph replay of serial steps (hsdc_use_graph): one captured step, replayed
   // while the CG budgets it was captured with stay in force
   bool graph_on = false;
+  // serial steps of a small 1D mesh in one single-workgroup launch (hsdc_single_block)
+  bool single_block = true;
+  int *d_small = nullptr;  // device: steps the last such launch completed
   bool graph_dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -1890,6 +1903,12 @@ hsdc_status hsdc_use_graph(hsdc_ctx *c, int32_t on) {
   });
 }
 
+hsdc_status hsdc_single_block(hsdc_ctx *c, int32_t on) {
+  if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
+  c->single_block = on != 0;
+  return HSDC_OK;
+}
+
 hsdc_status hsdc_sdc_sweep(hsdc_ctx *c, int32_t level, int32_t slice, int32_t nsweeps) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
   if (level != 0) return fail(c, HSDC_EINVAL, "level must be 0");
@@ -1911,6 +1930,17 @@ hsdc_status hsdc_sdc_sweep(hsdc_ctx *c, int32_t level, int32_t slice, int32_t ns
   });
 }
 
+// Serial steps may run as one single-workgroup launch: a serial context (one
+// tissue) on a 1D mesh of at most 256 nodes with the second-order stencil, CG
+// or the Chebyshev iteration as its solver, between steps, without graph
+// replay or kernel timing, unless hsdc_single_block turned it off.
+static bool single_block_ok(const hsdc_ctx *c) {
+  const Level &F = c->L[0];
+  return c->single_block && !c->pfasst && c->nlev == 1 && F.P == 1 && F.g.dim == 1 &&
+         F.g.nx <= 256 && F.g.rag == nullptr && F.g.order == 2 && c->meth.solver != 3 &&
+         c->sweeps_done == 0 && !c->graph_on && !c->prof.on;
+}
+
 hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
   if (!c) return fail(nullptr, HSDC_EINVAL, "ctx is NULL");
   if (nsteps < 0) return fail(c, HSDC_EINVAL, "nsteps must be >= 0");
@@ -1919,6 +1949,28 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
   c->nonfinite = false;
   return run_guarded(c, [&]() -> hsdc_status {
     Level &F = c->L[0];
+    if (single_block_ok(c) && nsteps > 0) {
+      // every step in one launch of one workgroup (hsdc_small.hip)
+      if (!c->d_small) c->d_small = dalloc<int>(c, 1);
+      const hsdc_problem &p = c->prob;
+      HIPC(launch_small_steps(c->s, F.g, F.st, F.co, c->stim[0], p.g_scale[0], p.g_scale[1],
+                              p.g_scale[2], c->meth.max_iter, nsteps, c->d_small));
+      int flag = 0;
+      HIPC(hipMemcpyAsync(&flag, c->d_small, sizeof(int), hipMemcpyDeviceToHost, c->s));
+      HIPC(hipStreamSynchronize(c->s));
+      const int done = flag < 0 ? -flag : flag;
+      const int K = c->meth.max_iter, M = F.co.M;
+      c->step += done;
+      HIPC(launch_step_add(c->s, c->d_step, done));
+      c->stats.steps += done;
+      c->stats.sweeps += (int64_t)K * done;
+      c->stats.cg_solves += (int64_t)K * M * done;  // direct solves: no CG iteration
+      c->stats.ionic_evals += F.g.N * (int64_t)(1 + K * (M - 1) + (K - 1)) * done;
+      c->nonfinite = flag < 0;
+      begin_serial_step(c);
+      if (c->nonfinite) return fail(c, HSDC_ENONFINITE, "a step met a non-finite state");
+      return HSDC_OK;
+    }
     for (int s = 0; s < nsteps; ++s) {
       if (c->nonfinite) break;  // a non-finite state: no further step helps
       if (!c->pfasst && c->graph_on && !c->prof.on && c->sweeps_done == 0) {
@@ -2608,6 +2660,8 @@ hsdc_status hsdc_misfit_forward(const hsdc_problem *prob, const hsdc_method *met
   hsdc_ctx *c = nullptr;
   hsdc_status st = hsdc_init_state(prob, meth, y0, hip_stream, &c);
   if (st != HSDC_OK) return st;
+  // the recomputation in the reverse run repeats the per-launch kernels' steps
+  c->single_block = false;
   hsdc_adj *adj = new hsdc_adj();
   adj->c = c;
   adj->nsteps = nsteps;

@@ -77,6 +77,7 @@ def lib():
             "hsdc_tune": [vp, i32, i32],
             "hsdc_tune_shapes": [vp, i32, i32, i32],
             "hsdc_use_graph": [vp, i32],
+            "hsdc_single_block": [vp, i32],
             "hsdc_advance": [vp, i32],
             "hsdc_pfasst_iter": [vp, vp, vp],
             "hsdc_residual": [vp, i32, vp],
@@ -226,6 +227,11 @@ class Context:
         """Replay serial steps, or the coarse part of PFASST iterations, from a
         captured HIP graph (needs a non-null stream)."""
         _check(lib().hsdc_use_graph(self.handle, 1 if on else 0), self.handle)
+
+    def single_block(self, on=True):
+        """Serial steps of a 1D mesh of at most 256 nodes in one launch of one
+        workgroup (the default), or on the per-launch kernels (on=False)."""
+        _check(lib().hsdc_single_block(self.handle, 1 if on else 0), self.handle)
 
     def sdc_sweep(self, nsweeps=1, level=0, slice=0):
         _check(lib().hsdc_sdc_sweep(self.handle, level, slice, nsweeps), self.handle)
