@@ -4,10 +4,11 @@
 // On such a mesh every kernel of a step is a few microseconds of launch
 // latency around a few hundred nanoseconds of work (a step of the 128-node
 // cable is about a hundred launches).  Here one workgroup runs the whole
-// step sequence: thread p owns node p and keeps its stage vectors, reaction
-// terms and right-hand sides in the level's arrays (read and written by that
-// thread only), and the nodes meet only in the stencil products and the
-// diffusion solves, which go through LDS.  The arithmetic is that of the
+// step sequence: thread p owns node p and keeps its stage vectors and
+// reaction terms in the level's arrays (read and written by that thread
+// only); the right-hand sides of the (field, node) pairs are shared among all
+// 256 threads, and the nodes meet in the stencil products and the diffusion
+// solves, which go through LDS.  The arithmetic is that of the
 // per-phase kernels (hsdc_kernels.hip): the same sweep (eq. prec_picard with
 // the preconditioner of eq. def_P, the integrals of eq. def_C), except that
 // (I - dt d_i K) V = b is solved directly: parallel cyclic reduction of the
@@ -167,35 +168,39 @@ __global__ void __launch_bounds__(kSmallMaxNodes) k_small_steps(SmallArgs a) {
 #pragma unroll 1
     for (int k = 0; k < a.K; ++k) {
       const bool last = k == a.K - 1;
-      // ---- right-hand sides RH_i = R_i - R_{i-1} of every row
-      if (live) {
+      // ---- right-hand sides RH_i = R_i - R_{i-1} of every row: the (field,
+      // node) pairs are shared among all threads of the block (a node's rows
+      // are independent), so meshes below 256 nodes use the idle threads
 #pragma unroll 1
-        for (int f = 0; f < NF; ++f) {
-          double Gv[M + 1], gfull[M], I[M];
+      for (int q = threadIdx.x; q < NF * g.nx; q += blockDim.x) {
+        const int f = q / g.nx, nd = q - f * g.nx;
+        const double *Gq = a.st.G + nd + f * Np;
+        double Gv[M + 1], gfull[M], I[M];
 #pragma unroll
-          for (int j = 0; j <= M; ++j) Gv[j] = G[j * sS + f * Np];
-          double fvn[M + 1];  // K V of the V row (0 elsewhere)
+        for (int j = 0; j <= M; ++j) Gv[j] = Gq[j * sS];
+        double fvn[M + 1];  // K V of the V row (0 elsewhere)
 #pragma unroll
-          for (int j = 0; j <= M; ++j) fvn[j] = (f == 0 && j > 0) ? FV[j * Np] : 0.0;
+        for (int j = 0; j <= M; ++j) fvn[j] = (f == 0 && j > 0) ? a.st.FV[nd + j * Np] : 0.0;
 #pragma unroll
-          for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + fvn[j + 1];
-          double pz = 0.0;  // d_i dt Lambda_n of a gate row (the Phi term's phi_1)
-          if (f >= GATE0) {
-            const double lam_n = L0[(f - GATE0) * Np];
-            colloc_integrals<M>(co, dt * lam_n, gfull, I, lam_n * Y[f * Np]);
-            pz = dt * lam_n;
-          } else {
-            colloc_weights<M>(co, gfull, I);
-          }
-          double prevI = 0.0;
+        for (int j = 0; j < M; ++j) gfull[j] = Gv[j + 1] + fvn[j + 1];
+        double pz = 0.0;  // dt Lambda_n of a gate row (the Phi term's phi_1(d_i pz))
+        if (f >= GATE0) {
+          const double lam_n = a.st.L0[nd + (f - GATE0) * Np];
+          colloc_integrals<M>(co, dt * lam_n, gfull, I, lam_n * a.st.Y[nd + f * Np]);
+          pz = dt * lam_n;
+        } else {
+          colloc_weights<M>(co, gfull, I);
+        }
+        double prevI = 0.0;
+        double *Rq = a.st.RH + nd + f * Np;
 #pragma unroll
-          for (int i = 0; i < M; ++i) {
-            const double phi = f >= GATE0 ? phi1(co.d[i] * pz) * Gv[i] : fvn[i + 1] + Gv[i];
-            RH[(int64_t)i * sS + f * Np] = dt * (I[i] - prevI) - dt * co.d[i] * phi;
-            prevI = I[i];
-          }
+        for (int i = 0; i < M; ++i) {
+          const double phi = f >= GATE0 ? phi1(co.d[i] * pz) * Gv[i] : fvn[i + 1] + Gv[i];
+          Rq[(int64_t)i * sS] = dt * (I[i] - prevI) - dt * co.d[i] * phi;
+          prevI = I[i];
         }
       }
+      __syncthreads();  // a node's right-hand sides come from other threads
       // ---- node to node: stage i from stage i - 1, then V_i by the solve
 #pragma unroll 1
       for (int i = 1; i <= M; ++i) {
@@ -301,7 +306,7 @@ hipError_t launch_small_steps(hipStream_t s, const Grid &g, const Stages &st, co
     return hipErrorInvalidValue;
   if (nsteps == 0) return hipSuccess;
   SmallArgs a{g, st, co, stim, gs0, gs1, gs2, K, nsteps, flag};
-  const dim3 block((unsigned)((g.nx + 63) / 64 * 64));
+  const dim3 block(kSmallMaxNodes);
   HSDC_DISPATCH_M(co.M, hipLaunchKernelGGL(k_small_steps<M>, dim3(1), block, 0, s, a));
   return hipGetLastError();
 }
