@@ -5,10 +5,10 @@
 // latency around a few hundred nanoseconds of work (a step of the 128-node
 // cable is about a hundred launches).  Here one workgroup runs the whole
 // step sequence: thread p owns node p and keeps its stage vectors and
-// reaction terms in the level's arrays (read and written by that thread
-// only); the right-hand sides of the (field, node) pairs are shared among all
-// 256 threads, and the nodes meet in the stencil products and the diffusion
-// solves, which go through LDS.  The arithmetic is that of the
+// reaction terms in the level's arrays (a mesh of at most 128 nodes gives the
+// gate rows of each node to a second thread), the right-hand sides of the
+// (field, node) pairs are shared among all 256 threads, and the nodes meet
+// in the stencil products and the diffusion solves, which go through LDS.  The arithmetic is that of the
 // per-phase kernels (hsdc_kernels.hip): the same sweep (eq. prec_picard with
 // the preconditioner of eq. def_P, the integrals of eq. def_C), except that
 // (I - dt d_i K) V = b is solved directly: parallel cyclic reduction of the
@@ -115,39 +115,50 @@ __global__ void __launch_bounds__(kSmallMaxNodes) k_small_steps(SmallArgs a) {
   __shared__ int bad;
   const Grid &g = a.g;
   const Colloc &co = a.co;
-  const int p = threadIdx.x;
-  const bool live = p < g.nx;
+  // Meshes of at most 128 nodes give each node two threads, one wave apart:
+  // one forms the gate rows, the other (the owner) the V and auxiliary rows,
+  // the currents, the solve's row and the copies; larger meshes do both in
+  // one thread.
+  constexpr int H = kSmallMaxNodes / 2;
+  const int t = threadIdx.x;
+  const bool split = g.nx <= H;
+  const int p = split ? t % H : t;
+  const bool own = p < g.nx && (!split || t >= H);
+  const bool gat = p < g.nx && (!split || t < H);
   const int64_t Np = a.st.Np, sS = a.st.sS();
   double *Y = a.st.Y + p, *G = a.st.G + p, *FV = a.st.FV + p, *RH = a.st.RH + p;
   double *L0 = a.st.L0 + p;
   const double dt = co.dt;
   const double Cm = a.stim.Cm;
   const int64_t step00 = *a.stim.step;
-  if (p == 0) bad = 0;
+  if (t == 0) bad = 0;
 #pragma unroll 1
   for (int step = 0; step < a.nsteps; ++step) {
     const int64_t step0 = step00 + step;
     // ---- stage 0 = y_n: its reaction terms, Lambda_n, K V; spread to 1..M
-    if (live) {
+    if (own || gat) {
       double y[NF];
 #pragma unroll
       for (int f = 0; f < NF; ++f) y[f] = Y[f * Np];
-      ttp06::gates<double>(y[0], y[3], [&](int k, double inf, double rate) {
-        const double lam = -rate;
-        const double w = y[GATE0 + k];
-        G[(GATE0 + k) * Np] = lam * (w - inf) - lam * w;
-        L0[k * Np] = lam;
-      });
-      double I_ion, ha[6];
-      ttp06::currents<double>(y, a.gs0, a.gs1, a.gs2, I_ion, ha);
-      const double s0 = stim_value(a.stim, (double)step0 * dt, 0, p);
-      G[0] = (s0 - Cm * I_ion) / Cm;
+      if (gat)
+        ttp06::gates<double>(y[0], y[3], [&](int k, double inf, double rate) {
+          const double lam = -rate;
+          const double w = y[GATE0 + k];
+          G[(GATE0 + k) * Np] = lam * (w - inf) - lam * w;
+          L0[k * Np] = lam;
+        });
+      if (own) {
+        double I_ion, ha[6];
+        ttp06::currents<double>(y, a.gs0, a.gs1, a.gs2, I_ion, ha);
+        const double s0 = stim_value(a.stim, (double)step0 * dt, 0, p);
+        G[0] = (s0 - Cm * I_ion) / Cm;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) G[(1 + k) * Np] = ha[k];
-      sv[p] = y[0];
+        for (int k = 0; k < 6; ++k) G[(1 + k) * Np] = ha[k];
+        sv[p] = y[0];
+      }
     }
     __syncthreads();
-    if (live) {
+    if (own) {
       const double fv0 = small_K(g, p, sv);
       FV[0] = fv0;
       const double s0 = stim_value(a.stim, (double)step0 * dt, 0, p);
@@ -170,9 +181,9 @@ __global__ void __launch_bounds__(kSmallMaxNodes) k_small_steps(SmallArgs a) {
       const bool last = k == a.K - 1;
       // ---- right-hand sides RH_i = R_i - R_{i-1} of every row: the (field,
       // node) pairs are shared among all threads of the block (a node's rows
-      // are independent), so meshes below 256 nodes use the idle threads
+      // are independent)
 #pragma unroll 1
-      for (int q = threadIdx.x; q < NF * g.nx; q += blockDim.x) {
+      for (int q = t; q < NF * g.nx; q += blockDim.x) {
         const int f = q / g.nx, nd = q - f * g.nx;
         const double *Gq = a.st.G + nd + f * Np;
         double Gv[M + 1], gfull[M], I[M];
@@ -206,7 +217,7 @@ __global__ void __launch_bounds__(kSmallMaxNodes) k_small_steps(SmallArgs a) {
       for (int i = 1; i <= M; ++i) {
         const double ddt = dt * co.d[i - 1];
         double bv = 0.0;
-        if (live) {
+        if (own || gat) {
           const double *Yp = Y + (int64_t)(i - 1) * sS;
           double *Yi = Y + (int64_t)i * sS;
           const double *R = RH + (int64_t)(i - 1) * sS;
@@ -214,73 +225,84 @@ __global__ void __launch_bounds__(kSmallMaxNodes) k_small_steps(SmallArgs a) {
           double yd[NF];
 #pragma unroll
           for (int f = 0; f < NF; ++f) yd[f] = Yp[f * Np];
-          double gV;
+          double gV = 0.0;
           if (i == 1) {
             // y_{n,0}: its stored reaction terms
+            if (own) {
 #pragma unroll
-            for (int f = 1; f < GATE0; ++f) Yi[f * Np] = yd[f] + R[f * Np] + ddt * Gp[f * Np];
-#pragma unroll
-            for (int kk = 0; kk < NG; ++kk) {
-              const int f = GATE0 + kk;
-              Yi[f * Np] = yd[f] + R[f * Np] + ddt * phi1(ddt * L0[kk * Np]) * Gp[f * Np];
+              for (int f = 1; f < GATE0; ++f) Yi[f * Np] = yd[f] + R[f * Np] + ddt * Gp[f * Np];
+              gV = Gp[0];
             }
-            gV = Gp[0];
-          } else {
-            const double t = ((double)step0 + co.c[i - 2]) * dt;
-            ttp06::gates<double>(yd[0], yd[3], [&](int kk, double inf, double rate) {
-              const int f = GATE0 + kk;
-              const double lu = L0[kk * Np];
-              const double w = yd[f];
-              const double gv = -rate * (w - inf) - lu * w;
-              if (!last) Gp[f * Np] = gv;
-              Yi[f * Np] = yd[f] + R[f * Np] + ddt * phi1(ddt * lu) * gv;
-            });
-            double I_ion, ha[6];
-            ttp06::currents<double>(yd, a.gs0, a.gs1, a.gs2, I_ion, ha);
-            gV = (stim_value(a.stim, t, 0, p) - Cm * I_ion) / Cm;
-            if (!last) Gp[0] = gV;
+            if (gat) {
 #pragma unroll
-            for (int kk = 0; kk < 6; ++kk) {
-              if (!last) Gp[(1 + kk) * Np] = ha[kk];
-              Yi[(1 + kk) * Np] = yd[1 + kk] + R[(1 + kk) * Np] + ddt * ha[kk];
+              for (int kk = 0; kk < NG; ++kk) {
+                const int f = GATE0 + kk;
+                Yi[f * Np] = yd[f] + R[f * Np] + ddt * phi1(ddt * L0[kk * Np]) * Gp[f * Np];
+              }
+            }
+          } else {
+            if (gat)
+              ttp06::gates<double>(yd[0], yd[3], [&](int kk, double inf, double rate) {
+                const int f = GATE0 + kk;
+                const double lu = L0[kk * Np];
+                const double w = yd[f];
+                const double gv = -rate * (w - inf) - lu * w;
+                if (!last) Gp[f * Np] = gv;
+                Yi[f * Np] = yd[f] + R[f * Np] + ddt * phi1(ddt * lu) * gv;
+              });
+            if (own) {
+              const double tt = ((double)step0 + co.c[i - 2]) * dt;
+              double I_ion, ha[6];
+              ttp06::currents<double>(yd, a.gs0, a.gs1, a.gs2, I_ion, ha);
+              gV = (stim_value(a.stim, tt, 0, p) - Cm * I_ion) / Cm;
+              if (!last) Gp[0] = gV;
+#pragma unroll
+              for (int kk = 0; kk < 6; ++kk) {
+                if (!last) Gp[(1 + kk) * Np] = ha[kk];
+                Yi[(1 + kk) * Np] = yd[1 + kk] + R[(1 + kk) * Np] + ddt * ha[kk];
+              }
             }
           }
-          bv = yd[0] + R[0] + ddt * gV;
+          if (own) bv = yd[0] + R[0] + ddt * gV;
         }
-        const double v = small_solve(g, ddt, live, p, bv, sl, sm, su, sr);
-        if (live) Y[(int64_t)i * sS] = v;
+        const double v = small_solve(g, ddt, own, p, bv, sl, sm, su, sr);
+        if (own) Y[(int64_t)i * sS] = v;
+        __syncthreads();  // stage i whole (its rows come from two threads) before node i + 1
       }
       if (!last) {
         // reaction terms of stage M and K V of stages 1..M for the next sweep
-        if (live) {
+        if (own || gat) {
           const double *Ym = Y + (int64_t)M * sS;
           double *Gm = G + (int64_t)M * sS;
           double y[NF];
 #pragma unroll
           for (int f = 0; f < NF; ++f) y[f] = Ym[f * Np];
-          ttp06::gates<double>(y[0], y[3], [&](int kk, double inf, double rate) {
-            const double w = y[GATE0 + kk];
-            Gm[(GATE0 + kk) * Np] = -rate * (w - inf) - L0[kk * Np] * w;
-          });
-          double I_ion, ha[6];
-          ttp06::currents<double>(y, a.gs0, a.gs1, a.gs2, I_ion, ha);
-          const double t = ((double)step0 + co.c[M - 1]) * dt;
-          Gm[0] = (stim_value(a.stim, t, 0, p) - Cm * I_ion) / Cm;
+          if (gat)
+            ttp06::gates<double>(y[0], y[3], [&](int kk, double inf, double rate) {
+              const double w = y[GATE0 + kk];
+              Gm[(GATE0 + kk) * Np] = -rate * (w - inf) - L0[kk * Np] * w;
+            });
+          if (own) {
+            double I_ion, ha[6];
+            ttp06::currents<double>(y, a.gs0, a.gs1, a.gs2, I_ion, ha);
+            const double tt = ((double)step0 + co.c[M - 1]) * dt;
+            Gm[0] = (stim_value(a.stim, tt, 0, p) - Cm * I_ion) / Cm;
 #pragma unroll
-          for (int kk = 0; kk < 6; ++kk) Gm[(1 + kk) * Np] = ha[kk];
+            for (int kk = 0; kk < 6; ++kk) Gm[(1 + kk) * Np] = ha[kk];
+          }
         }
 #pragma unroll 1
         for (int j = 1; j <= M; ++j) {
-          if (live) sv[p] = Y[(int64_t)j * sS];
+          if (own) sv[p] = Y[(int64_t)j * sS];
           __syncthreads();
-          if (live) FV[j * Np] = small_K(g, p, sv);
+          if (own) FV[j * Np] = small_K(g, p, sv);
           __syncthreads();
         }
       }
     }
     // ---- y_{n+1} = y_{n,M}; stop after a step whose state is not finite
     bool nf = false;
-    if (live) {
+    if (own) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const double v = Y[(int64_t)M * sS + f * Np];
@@ -291,11 +313,11 @@ __global__ void __launch_bounds__(kSmallMaxNodes) k_small_steps(SmallArgs a) {
     if (nf) bad = 1;
     __syncthreads();
     if (bad) {
-      if (p == 0) *a.flag = -(step + 1);
+      if (t == 0) *a.flag = -(step + 1);
       return;
     }
   }
-  if (p == 0) *a.flag = a.nsteps;
+  if (t == 0) *a.flag = a.nsteps;
 }
 
 hipError_t launch_small_steps(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
