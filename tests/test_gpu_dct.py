@@ -116,7 +116,7 @@ def test_dct_serial_parity(kind, dims, order):
     assert np.all(np.isfinite(y))
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 4), (36, 18), (16, 8)])
+@pytest.mark.parametrize("dims", [(8, 6, 4), (36, 18), (16, 8), (8, 4, 4)])
 def test_dct_pfasst_iterates_parity(dims):
     """Two-level PFASST (space-coarsened, the coarse level fourth order on its
     own mesh) with DCT-II solves on both levels: every iterate of Algorithm 1
