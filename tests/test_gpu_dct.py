@@ -116,13 +116,13 @@ def test_dct_serial_parity(kind, dims, order):
     assert np.all(np.isfinite(y))
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 4), (36, 18), (16, 8), (8, 4, 4)])
+@pytest.mark.parametrize("dims", [(8, 6, 4), (36, 18), (16, 8), (8, 4, 4), (64,)])
 def test_dct_pfasst_iterates_parity(dims):
     """Two-level PFASST (space-coarsened, the coarse level fourth order on its
     own mesh) with DCT-II solves on both levels: every iterate of Algorithm 1
     matches the oracle slice by slice."""
     P = 4
-    kind = {2: "slab2d", 3: "slab3d"}[len(dims)]
+    kind = {1: "cable1d", 2: "slab2d", 3: "slab3d"}[len(dims)]
     w = dict(si.workload(kind, dims=dims))
     w["dt"] = 0.1
     w["fd_order"] = 4
