@@ -1950,23 +1950,28 @@ hsdc_status hsdc_advance(hsdc_ctx *c, int32_t nsteps) {
   return run_guarded(c, [&]() -> hsdc_status {
     Level &F = c->L[0];
     if (single_block_ok(c) && nsteps > 0) {
-      // every step in one launch of one workgroup (hsdc_small.hip)
+      // the steps in launches of one workgroup (hsdc_small.hip), at most
+      // kSmallChunk steps each (a launch of the 128-node cable: about 0.25 s)
+      constexpr int kSmallChunk = 1024;
       if (!c->d_small) c->d_small = dalloc<int>(c, 1);
       const hsdc_problem &p = c->prob;
-      HIPC(launch_small_steps(c->s, F.g, F.st, F.co, c->stim[0], p.g_scale[0], p.g_scale[1],
-                              p.g_scale[2], c->meth.max_iter, nsteps, c->d_small));
-      int flag = 0;
-      HIPC(hipMemcpyAsync(&flag, c->d_small, sizeof(int), hipMemcpyDeviceToHost, c->s));
-      HIPC(hipStreamSynchronize(c->s));
-      const int done = flag < 0 ? -flag : flag;
       const int K = c->meth.max_iter, M = F.co.M;
-      c->step += done;
-      HIPC(launch_step_add(c->s, c->d_step, done));
-      c->stats.steps += done;
-      c->stats.sweeps += (int64_t)K * done;
-      c->stats.cg_solves += (int64_t)K * M * done;  // direct solves: no CG iteration
-      c->stats.ionic_evals += F.g.N * (int64_t)(1 + K * (M - 1) + (K - 1)) * done;
-      c->nonfinite = flag < 0;
+      for (int s0 = 0; s0 < nsteps && !c->nonfinite; s0 += kSmallChunk) {
+        const int n = std::min(kSmallChunk, nsteps - s0);
+        HIPC(launch_small_steps(c->s, F.g, F.st, F.co, c->stim[0], p.g_scale[0], p.g_scale[1],
+                                p.g_scale[2], K, n, c->d_small));
+        int flag = 0;
+        HIPC(hipMemcpyAsync(&flag, c->d_small, sizeof(int), hipMemcpyDeviceToHost, c->s));
+        HIPC(hipStreamSynchronize(c->s));
+        const int done = flag < 0 ? -flag : flag;
+        c->step += done;
+        HIPC(launch_step_add(c->s, c->d_step, done));
+        c->stats.steps += done;
+        c->stats.sweeps += (int64_t)K * done;
+        c->stats.cg_solves += (int64_t)K * M * done;  // direct solves: no CG iteration
+        c->stats.ionic_evals += F.g.N * (int64_t)(1 + K * (M - 1) + (K - 1)) * done;
+        c->nonfinite = flag < 0;
+      }
       begin_serial_step(c);
       if (c->nonfinite) return fail(c, HSDC_ENONFINITE, "a step met a non-finite state");
       return HSDC_OK;

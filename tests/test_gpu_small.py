@@ -111,3 +111,20 @@ def test_single_block_nonfinite_state():
     assert e.value.code == -5
     assert ctx.stats()["steps"] == 1
     ctx.destroy()
+
+
+def test_single_block_chunks_are_seamless():
+    """Calls longer than one launch's chunk of steps (1024) equal the same
+    steps taken in other call sizes, bit for bit (each step is computed from
+    stage 0 and the step counter alone)."""
+    w = _cable(16)
+    m = H.make_method(M=2, dt=w["dt"], max_iter=1)
+    ys = []
+    for calls in ((1030,), (515, 515), (1024, 6)):
+        ctx = H.Context(lib_problem(w), m)
+        for n in calls:
+            ctx.advance(n)
+        ys.append(host(ctx.get_state(0, 0, 0)))
+        assert ctx.stats()["steps"] == 1030
+        ctx.destroy()
+    assert np.array_equal(ys[0], ys[1]) and np.array_equal(ys[0], ys[2])
