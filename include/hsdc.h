@@ -236,8 +236,9 @@ hsdc_status hsdc_use_graph(hsdc_ctx *ctx, int32_t on);
 
 /* Serial steps of a small 1D mesh in one launch (Sec. 3.1.3, the sweep of eq.
  * prec_picard; on by default).  A serial context on a 1D mesh of at most 256
- * nodes (second-order stencil, solver 0, 1 or 2) advances all steps of an
- * hsdc_advance call in one launch of one workgroup: one thread per node, the
+ * nodes (second-order stencil, solver 0, 1 or 2) advances the steps of an
+ * hsdc_advance call in launches of one workgroup (at most 1024 steps a
+ * launch): one thread per node, the
  * stencil products and the diffusion solves through LDS, each solve direct
  * (cyclic reduction of the tridiagonal system, exact up to rounding, counted
  * in the stats as a solve with no CG iteration) instead of CG to cg_rtol.
