@@ -238,10 +238,10 @@ hsdc_status hsdc_use_graph(hsdc_ctx *ctx, int32_t on);
  * prec_picard; on by default).  A serial context on a 1D mesh of at most 256
  * nodes (second-order stencil, solver 0, 1 or 2) advances the steps of an
  * hsdc_advance call in launches of one workgroup (at most 1024 steps a
- * launch): one thread per node, the
- * stencil products and the diffusion solves through LDS, each solve direct
- * (cyclic reduction of the tridiagonal system, exact up to rounding, counted
- * in the stats as a solve with no CG iteration) instead of CG to cg_rtol.
+ * launch): one thread per node, the stencil products and the diffusion
+ * solves through LDS, each solve direct (cyclic reduction of the tridiagonal
+ * system, exact up to rounding, counted in the stats as a solve with no CG
+ * iteration) instead of CG to cg_rtol.
  * The per-launch kernels of other meshes need launches of a few microseconds
  * each, about a hundred per step.  Not taken while graph replay or kernel
  * timing is on, or between the sweeps of a step (hsdc_sdc_sweep).  on = 0
