@@ -62,13 +62,18 @@ struct Grid {
   int order;  // finite-difference order of K: 2, or 4 (uniform sigma; hsdc_dct.hip)
 };
 
-// Tiles of the one-launch CG start (x by y nodes, threads per block).
+// Tiles of the one-launch CG start (x by y nodes, threads per block): 0..4
+// with the iterates in LDS, 5..8 in registers (64-column blocks).
 struct TileShape {
   int tx, ty, threads;
 };
-constexpr int kNumCgTiles = 5;
+constexpr int kNumCgTiles = 9;
 constexpr TileShape kCgTiles[kNumCgTiles] = {
-    {64, 16, 1024}, {32, 32, 1024}, {32, 16, 512}, {32, 8, 256}, {16, 16, 256}};
+    {64, 16, 1024}, {32, 32, 1024}, {32, 16, 512}, {32, 8, 256}, {16, 16, 256},
+    {48, 16, 512},  {48, 8, 512},   {48, 24, 512}, {48, 32, 512}};
+// 48 x 24 in registers: the fastest on 256^2 to 1024^2 slabs but for 48 x 8 on
+// 256^2 (the LDS tile 64 x 16 takes 4% to 7% longer on each)
+constexpr int kDefaultCgTile = 7;
 // Tiles of the coarse-to-fine correction (fine nodes x, y, z; 256 threads).
 constexpr int kNumProlongTiles = 4;
 constexpr int kProlongTiles3D[kNumProlongTiles][3] = {{32, 4, 2}, {64, 2, 2}, {16, 8, 2}, {16, 4, 4}};

@@ -5,6 +5,7 @@
 // the cell model is bound by FP64 VALU work (exp/log/div sequences), the
 // stencil, CG vector updates, assembly, residual and transfers by HBM bytes.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "hsdc_device.h"
 #include "hsdc_internal.h"
@@ -1417,6 +1418,193 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch 
   }
 }
 
+// The same CG start with the iterates in registers.  A block covers 64
+// columns of the mesh (one per lane) by NW RW rows (RW consecutive rows per
+// wave); its tile is the interior 48 x (NW RW - 2 H), H = D + 1 cells in from
+// every edge.  A lane takes its left and right neighbours from the adjacent
+// lanes (DPP shifts across the wave), the rows above and below from its own
+// registers, and only the first and last row of each wave go through LDS
+// (two buffers by step parity, one barrier a step).  Every cell of the block
+// is updated in every step: after s applications of K a cell closer than s
+// to the block's edge holds a wrong value (its missing neighbour reads the
+// cell itself), which never reaches the tile, H applications away.  Cells
+// outside the mesh hold zeros and are read by none inside (a boundary node
+// reads itself for its missing neighbour, as in the LDS-tiled kernel, whose
+// arithmetic this one repeats expression by expression).
+
+// The value of lane - 1 (lane 0: 0) and of lane + 1 (lane 63: 0).
+__device__ __forceinline__ double lane_from_left(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_from_right(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int D, bool PN, int RW, int NW>
+__global__ void __launch_bounds__(64 * NW) k_cg_start_strip(Grid g0, CgBatch cb) {
+  constexpr int H = D + 1, TX = 64 - 2 * H, TY = NW * RW - 2 * H;
+  static_assert(TX > 0 && TY > 0, "the block must hold the tile and its halo");
+  __shared__ double s_first[2][NW][64], s_last[2][NW][64];
+  __shared__ double lds[2 * NW];
+  const int n = blockIdx.y;
+  const Grid g = slice_grid(g0, cb.slice0 + n);
+  const int nx = g.nx, ny = g.ny;
+  const int tiles_x = (nx + TX - 1) / TX;
+  const int t = (int)blockIdx.x;
+  double *part = cb.part + (int64_t)n * 5 * cb.pstride;
+  if (t >= tiles_x * ((ny + TY - 1) / TY)) {
+    // past this tissue's tiles (a smaller tissue of a ragged batch)
+    if (threadIdx.x == 0) {
+      part[2 * cb.pstride + t] = 0.0;
+      part[3 * cb.pstride + t] = 0.0;
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int gx = (t % tiles_x) * TX - H + lane;
+  const int gy0 = (t / tiles_x) * TY - H + w * RW;
+  const bool colin = gx >= 0 && gx < nx;
+  const double *x1g = cb.xt + (int64_t)n * g.Np;
+  const double *x0g = cb.p + (int64_t)n * g.Np;  // x_0, stored there by the node update
+  const double *bg = cb.b + n * cb.sb;
+  const ChebTab &tb = cb.tab[(cb.slice0 + n) * cb.tab_stride];
+  const double ith = tb.inv_theta, a = cb.a;
+  // xm: x_{k-1}, xk: x_k (x_0 and x_1 to start with); kl, kr, kd, ku: the
+  // face coefficients left, right, below and above (per-node sigma)
+  double xm[RW], xk[RW], bv[RW];
+  double kl[PN ? RW : 1], kr[PN ? RW : 1], kd[PN ? RW : 1], ku[PN ? RW : 1];
+#pragma unroll
+  for (int j = 0; j < RW; ++j) {
+    const int gy = gy0 + j;
+    const bool in = colin && gy >= 0 && gy < ny;
+    const int64_t p = gx + (int64_t)nx * gy;
+    xk[j] = in ? x1g[p] : 0.0;
+    xm[j] = in ? x0g[p] : 0.0;
+    bv[j] = in ? bg[p] : 0.0;
+    if (PN) {
+      kr[j] = in ? g.kx[p] : 0.0;
+      kl[j] = in && gx > 0 ? g.kx[p - 1] : 0.0;
+      ku[j] = in ? g.ky[p] : 0.0;
+      kd[j] = in && gy > 0 ? g.ky[p - nx] : 0.0;
+    }
+  }
+  // Blocks with no cell on the mesh's boundary take every neighbour as it
+  // is; the others select the cell itself for a missing one.
+  const int X0 = (t % tiles_x) * TX - H, Y0 = (t / tiles_x) * TY - H;
+  const bool edge = !(X0 > 0 && X0 + 63 < nx - 1 && Y0 > 0 && Y0 + NW * RW - 1 < ny - 1);
+  const bool hl = gx > 0, hr = gx < nx - 1;
+  double gam = 0.0, del = 0.0;
+  auto body = [&](auto edge_c) {
+    constexpr bool E = decltype(edge_c)::value;
+    // K at row j from the cell c and its neighbours, in the LDS-tiled kernel's order
+    auto Kat = [&](int j, double c, double l, double r, double d, double up) {
+      const int gy = gy0 + j;
+      const bool hd = !E || gy > 0, hu = !E || gy < ny - 1;
+      const bool el = !E || hl, er = !E || hr;
+      if (PN) {
+        double acc = 0.0;
+        if (el) acc += kl[PN ? j : 0] * (l - c);
+        if (er) acc += kr[PN ? j : 0] * (r - c);
+        if (hd) acc += kd[PN ? j : 0] * (d - c);
+        if (hu) acc += ku[PN ? j : 0] * (up - c);
+        return acc;
+      }
+      l = el ? l : c;
+      r = er ? r : c;
+      d = hd ? d : c;
+      up = hu ? up : c;
+      double acc = g.cx * ((l - c) + (r - c));
+      acc += g.cy * ((d - c) + (up - c));
+      return acc;
+    };
+    // the rows next to this wave's strip: the previous wave's last row and
+    // the next wave's first (the block's edge rows take the strip's own)
+    auto rows_around = [&](const double (&x)[RW], int k, double &below, double &above) {
+      s_first[k & 1][w][lane] = x[0];
+      s_last[k & 1][w][lane] = x[RW - 1];
+      __syncthreads();
+      below = w > 0 ? s_last[k & 1][w - 1][lane] : x[0];
+      above = w < NW - 1 ? s_first[k & 1][w + 1][lane] : x[RW - 1];
+    };
+    // x_{k+1} = x_{k-1} + omega_{k+1} (x_k - x_{k-1} + (b - A x_k) / theta)
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+      const double om = cheb_omega(tb, k);
+      double below, above;
+      rows_around(xk, k, below, above);
+#pragma unroll
+      for (int j = 0; j < RW; ++j) {
+        const double xc = xk[j], xo = xm[j];
+        const double l = lane_from_left(xc), r = lane_from_right(xc);
+        const double d = j > 0 ? xk[j - 1] : below, up = j < RW - 1 ? xk[j + 1] : above;
+        const double rr = bv[j] - (xc - a * Kat(j, xc, l, r, d, up));
+        xm[j] = xo + om * (xc - xo + ith * rr);
+      }
+#pragma unroll
+      for (int j = 0; j < RW; ++j) {
+        const double tmp = xm[j];
+        xm[j] = xk[j];
+        xk[j] = tmp;
+      }
+    }
+    // r_D = b - A x_D, over x_{D-1}
+    {
+      double below, above;
+      rows_around(xk, D, below, above);
+#pragma unroll
+      for (int j = 0; j < RW; ++j) {
+        const double xq = xk[j];
+        const double l = lane_from_left(xq), r = lane_from_right(xq);
+        const double d = j > 0 ? xk[j - 1] : below, up = j < RW - 1 ? xk[j + 1] : above;
+        xm[j] = bv[j] - (xq - a * Kat(j, xq, l, r, d, up));
+      }
+    }
+    // w_D = A r_D on the tile; x_D to x, r_D and w_D to the parity-1 vectors
+    double below, above;
+    rows_around(xm, D + 1, below, above);
+    const bool tcol = lane >= H && lane < H + TX && colin;
+#pragma unroll
+    for (int j = 0; j < RW; ++j) {
+      const double rc = xm[j];
+      const double l = lane_from_left(rc), r = lane_from_right(rc);
+      const double d = j > 0 ? xm[j - 1] : below, up = j < RW - 1 ? xm[j + 1] : above;
+      const double wv = rc - a * Kat(j, rc, l, r, d, up);
+      const int v = w * RW + j, gy = gy0 + j;
+      if (tcol && v >= H && v < H + TY && gy < ny) {
+        const int64_t p = gx + (int64_t)nx * gy;
+        cb.x[n * cb.sx + p] = xk[j];
+        cb.r[1][n * g.Np + p] = rc;
+        cb.w[1][n * g.Np + p] = wv;
+        gam += rc * rc;
+        del += wv * rc;
+      }
+    }
+  };
+  if (edge)
+    body(std::true_type{});
+  else
+    body(std::false_type{});
+  double t2[2] = {gam, del};
+  block_sums<2, 64 * NW>(t2, lds);
+  if (threadIdx.x == 0) {
+    part[2 * cb.pstride + t] = t2[0];
+    part[3 * cb.pstride + t] = t2[1];
+    if (blockIdx.x == 0) {
+      CgScalars o;
+      o.bb = -1.0;  // reduced by the first iteration kernel
+      o.gamma = 1.0;
+      o.alpha = 1.0;
+      o.it = 0;
+      o.done = 0;
+      cb.sc[2 * n + 1] = o;
+    }
+  }
+}
+
 hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb, int ntiles) {
   if (ntiles <= 0 || cb.nslices <= 0 || g.dim != 2 || cb.cstart != 7) return hipErrorInvalidValue;
   const dim3 grid(ntiles, cb.nslices);
@@ -1429,15 +1617,28 @@ hipError_t launch_cg_start_tiled(hipStream_t s, const Grid &g, const CgBatch &cb
       hipLaunchKernelGGL((k_cg_start_tiled<7, false, X_, Y_, NT_>), grid, dim3(NT_), 0, s, g,   \
                          cb);                                                                 \
   } while (0)
-  static_assert(kNumCgTiles == 5, "one launch per tile of kCgTiles");
+#define HSDC_CS_LAUNCH(RW_, NW_)                                                               \
+  do {                                                                                        \
+    if (pn)                                                                                   \
+      hipLaunchKernelGGL((k_cg_start_strip<7, true, RW_, NW_>), grid, dim3(64 * NW_), 0, s, g, cb); \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_cg_start_strip<7, false, RW_, NW_>), grid, dim3(64 * NW_), 0, s, g,   \
+                         cb);                                                                 \
+  } while (0)
+  static_assert(kNumCgTiles == 9, "one launch per tile of kCgTiles");
   switch (g.ctile) {
     case 0: HSDC_CT_LAUNCH(64, 16, 1024); break;
     case 1: HSDC_CT_LAUNCH(32, 32, 1024); break;
     case 2: HSDC_CT_LAUNCH(32, 16, 512); break;
     case 3: HSDC_CT_LAUNCH(32, 8, 256); break;
     case 4: HSDC_CT_LAUNCH(16, 16, 256); break;
+    case 5: HSDC_CS_LAUNCH(4, 8); break;  // 48 x 16 nodes, 512 threads
+    case 6: HSDC_CS_LAUNCH(3, 8); break;  // 48 x 8
+    case 7: HSDC_CS_LAUNCH(5, 8); break;  // 48 x 24
+    case 8: HSDC_CS_LAUNCH(6, 8); break;  // 48 x 32
     default: return hipErrorInvalidValue;
   }
+#undef HSDC_CS_LAUNCH
 #undef HSDC_CT_LAUNCH
   return hipGetLastError();
 }

@@ -425,7 +425,7 @@ Grid make_grid(const hsdc_problem &p, int nx, int ny, int nz, double dx) {
   g.fx = make_fastdiv((uint32_t)nx);
   g.fy = make_fastdiv((uint32_t)ny);
   g.nub = kDefaultNodeBlock;
-  g.ctile = 0;
+  g.ctile = kDefaultCgTile;
   g.ptile = 0;
   g.order = p.fd_order == 4 ? 4 : 2;
   const double s = 1.0 / (dx * dx * p.chi * p.Cm);
@@ -1865,7 +1865,7 @@ hsdc_status hsdc_tune_shapes(hsdc_ctx *c, int32_t node_block, int32_t cg_tile,
       node_block != 512)
     return fail(c, HSDC_EINVAL, "node_block must be 0, 64, 128, 256 or 512");
   if (cg_tile < -1 || cg_tile >= kNumCgTiles)
-    return fail(c, HSDC_EINVAL, "cg_tile must be -1 or 0..4");
+    return fail(c, HSDC_EINVAL, "cg_tile must be -1 or 0..8");
   if (prolong_tile < -1 || prolong_tile >= kNumProlongTiles)
     return fail(c, HSDC_EINVAL, "prolong_tile must be -1 or 0..3");
   // FP64 levels; an FP32 coarse level keeps the default shapes

@@ -586,22 +586,27 @@ def test_batch_matches_oracle_per_tissue(solver):
         assert np.max(field_errors(g, y)) < 1e-10, (n, w["dims"], np.max(field_errors(g, y)))
 
 
-@pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain"])
+@pytest.mark.parametrize("solver", ["cg", "chebyshev", "cg_plain", "cg_register_tiles"])
 def test_batch_matches_single_contexts(solver):
     """Five ragged tissues (20..60 nodes a side): the batch equals five separate
     contexts bitwise (every reduction adds the same partials in the same order,
     and a Chebyshev solve takes its tissue's own spectral bound and count),
-    including set_state on one tissue and a sweep applied to all."""
+    including set_state on one tissue and a sweep applied to all; also with
+    the CG start's register-resident tiles (48 x 16) on both sides."""
     ws = si.batch2d_tissues(5, seed=7, lo=20, hi=60)
+    tile = 5 if solver == "cg_register_tiles" else -1
+    solver = "cg" if tile >= 0 else solver
     m = H.make_method(M=4, dt=ws[0]["dt"], max_iter=4, cg_rtol=1e-14, cg_maxit=300, solver=solver)
     probs = [lib_problem(w) for w in ws]
     y0 = [None] * 5
     y0[2] = dev(si.random_states(ws[2]["dims"][0] * ws[2]["dims"][1], seed=5))
     ctx = H.BatchContext(probs, m, y0)
+    ctx.tune_shapes(0, tile, -1)
     ctx.advance(10)
     ctx.sdc_sweep(2)
     for n, w in enumerate(ws):
         single = H.Context(probs[n], m, y0[n])
+        single.tune_shapes(0, tile, -1)
         single.advance(10)
         single.sdc_sweep(2)
         for j in (0, 4):
@@ -647,7 +652,8 @@ def test_tuned_block_and_tile_shapes_give_the_same_run(pernode):
     ref.advance(8)
     y_ref = host(ref.get_state(0, 0, 0))
     ref.destroy()
-    shapes = [(nb, 0) for nb in (64, 128, 512)] + [(256, t) for t in (1, 2, 3, 4)] + [(64, 4)]
+    shapes = ([(nb, 0) for nb in (64, 128, 512)] + [(256, t) for t in (1, 2, 3, 4, 5, 6, 7, 8)]
+              + [(64, 4), (128, 5)])
     for nb, tile in shapes:
         c = H.Context(prob, m)
         c.tune_shapes(nb, tile, -1)
@@ -658,7 +664,7 @@ def test_tuned_block_and_tile_shapes_give_the_same_run(pernode):
         assert np.max(e) < 1e-11, (nb, tile, np.max(e))
         assert st["cg_unconverged"] == 0
     c = H.Context(prob, m)
-    for bad in ((96, -1, -1), (0, 5, -1), (0, -1, 4), (1024, 0, 0)):
+    for bad in ((96, -1, -1), (0, 9, -1), (0, -1, 4), (1024, 0, 0)):
         with pytest.raises(H.HsdcError):
             c.tune_shapes(*bad)
     c.destroy()
