@@ -108,7 +108,7 @@ __device__ __forceinline__ void block_gs(double (&vgs)[3], double *lds, double *
   }
 }
 
-constexpr int ADB = 256;
+constexpr int ADB = kAdjBlock;
 
 // Node i of the forward substitution, backwards.  beta_i (the adjoint of b_i)
 // is MU_i with its V row replaced by the adjoint solve's result (in RHO_i);
@@ -333,17 +333,26 @@ __global__ void __launch_bounds__(ADB) k_adj_spmv_add(Grid g, const double *v, d
 }
 
 // The first Chebyshev step of an adjoint solve, x_1 = x_0 + (b - A x_0) / theta
-// with A = I - a K (as the node update forms it for the forward solves).
+// with A = I - a K (as the node update forms it for the forward solves); with
+// bpart, also the block partials of ||b||^2 (the reference of CG's stop test).
 template <int DIM, bool PN>
 __global__ void __launch_bounds__(ADB)
 k_adj_cheb_x1(Grid g, const double *x0, const double *b, double a, const ChebTab *tab,
-              double *x1) {
+              double *x1, double *bpart) {
+  __shared__ double lds[ADB / 64];
   const int64_t p = (int64_t)blockIdx.x * ADB + threadIdx.x;
-  if (p >= g.N) return;
-  const Ijk c = ijk(g, p);
-  const double xc = x0[p];
-  const double r = b[p] - (xc - a * applyK<DIM, PN>(g, p, c, xc, [&](int64_t q) { return x0[q]; }));
-  x1[p] = xc + r * tab->inv_theta;
+  double bb = 0.0;
+  if (p < g.N) {
+    const Ijk c = ijk(g, p);
+    const double xc = x0[p], bp = b[p];
+    const double r = bp - (xc - a * applyK<DIM, PN>(g, p, c, xc, [&](int64_t q) { return x0[q]; }));
+    x1[p] = xc + r * tab->inv_theta;
+    bb = bp * bp;
+  }
+  if (bpart == nullptr) return;  // the same for every thread of the launch
+  double t1[1] = {bb};
+  block_sums<1, ADB>(t1, lds);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = t1[0];
 }
 
 // dsigma_p from the face gradients: a face coefficient is sc 2 s_p s_q / (s_p + s_q).
@@ -448,9 +457,9 @@ hipError_t launch_adj_spmv_add(hipStream_t s, const Grid &g, const double *v, do
 }
 
 hipError_t launch_adj_cheb_x1(hipStream_t s, const Grid &g, const double *x0, const double *b,
-                              double a, const ChebTab *tab, double *x1) {
+                              double a, const ChebTab *tab, double *x1, double *bpart) {
   HSDC_DISPATCH_OP(g, hipLaunchKernelGGL((k_adj_cheb_x1<DIM, PN>), dim3(adj_blocks(g.N)),
-                                         dim3(ADB), 0, s, g, x0, b, a, tab, x1));
+                                         dim3(ADB), 0, s, g, x0, b, a, tab, x1, bpart));
   return hipGetLastError();
 }
 

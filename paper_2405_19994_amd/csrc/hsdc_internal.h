@@ -370,9 +370,11 @@ hipError_t launch_adj_faces(hipStream_t s, const Grid &g, const double *u, const
                             double scale, double *dkx, double *dky, double *dkz);
 hipError_t launch_adj_spmv_add(hipStream_t s, const Grid &g, const double *v, double scale,
                                double *out);
-// x1 = x0 + (b - (I - a K) x0) * tab->inv_theta (the first Chebyshev step)
+// x1 = x0 + (b - (I - a K) x0) * tab->inv_theta (the first Chebyshev step);
+// bpart (or null): the partials of ||b||^2, one per block of kAdjBlock nodes
+constexpr int kAdjBlock = 256;
 hipError_t launch_adj_cheb_x1(hipStream_t s, const Grid &g, const double *x0, const double *b,
-                              double a, const ChebTab *tab, double *x1);
+                              double a, const ChebTab *tab, double *x1, double *bpart);
 hipError_t launch_adj_sigma(hipStream_t s, const Grid &g, const double *sig, double sc,
                             const double *dkx, const double *dky, const double *dkz, double *dsig);
 hipError_t launch_adj_probes(hipStream_t s, const double *y, const int64_t *probes,

@@ -2462,26 +2462,43 @@ struct AdjBuffers {
 // to convergence with host checks, and its launches become the prediction.
 // With the Chebyshev tables of the forward solves (solver 0 or 1), the CG
 // starts from x_D, D Chebyshev steps from x_0 = b (a spectral interval of the
-// operator is known, so they need no inner products).
+// operator is known, so they need no inner products).  Where the forward
+// solves take the one-launch start (solver 0, 2D meshes), so do these: x_1
+// with the partials of ||b||^2, then x_2 .. x_7, r_7, w_7 and their partials
+// in one launch, and CG continues from launch k = 1.
 constexpr int kAdjChebDegree = 8;  // even: x_D lands in x
 
-void adjoint_solve(hsdc_ctx *c, const AdjBuffers &b, const CgBatch &cb, int k, int i, bool safe) {
+void adjoint_solve(hsdc_ctx *c, const AdjBuffers &b, const CgBatch &cb0, int k, int i, bool safe) {
   Level &F = c->L[0];
   const hipStream_t s = c->s;
   const int M = F.co.M;
+  CgBatch cb = cb0;
+  const int tiles = F.cheb_x ? level_start_tiles(c, F) : 0;
   if (F.cheb_x) {
     CgBatch cs = cb;
     cs.xt = F.cheb_x;
     cs.tab = F.cheb_tab + (i - 1);
     cs.tab_stride = M;
-    HIPC(launch_adj_cheb_x1(s, F.g, cb.x, cb.b, cb.a, cs.tab, cs.xt));
-    HIPC(launch_cheb_steps(s, F.g, cs, kAdjChebDegree - 1));
+    if (tiles > 0) {
+      // x_0 = b: the start reads it from p (and only reads p) and writes x_7 to x
+      cs.p = const_cast<double *>(cb.b);
+      cs.cstart = kChebStartDegreeTiled;
+      cs.x0_to_p = 1;
+      HIPC(launch_adj_cheb_x1(s, F.g, cb.b, cb.b, cb.a, cs.tab, cs.xt, cb.part + 4 * cb.pstride));
+      HIPC(launch_cg_start_tiled(s, F.g, cs, tiles));
+      cb.cstart = kChebStartDegreeTiled;
+      cb.nblk_s = tiles;
+      cb.nblk0 = (int)((F.g.N + kAdjBlock - 1) / kAdjBlock);
+    } else {
+      HIPC(launch_adj_cheb_x1(s, F.g, cb.x, cb.b, cb.a, cs.tab, cs.xt, nullptr));
+      HIPC(launch_cheb_steps(s, F.g, cs, kAdjChebDegree - 1));
+    }
   }
   int &pred = (*b.pred)[(k - 1) * M + (i - 1)];
   if (safe) {
     int used = 0;
     bool conv = false;
-    run_cg(s, F.g, cb, &used, &conv);
+    run_cg(s, F.g, cb0, &used, &conv);  // from the start's x_D
     if (!conv) {
       fail(c, HSDC_ENOCONV, "an adjoint diffusion solve reached cg_maxit");
       throw StatusFail{HSDC_ENOCONV};
@@ -2492,10 +2509,13 @@ void adjoint_solve(hsdc_ctx *c, const AdjBuffers &b, const CgBatch &cb, int k, i
     return;
   }
   const int budget = std::max(1, std::min(pred, cb.maxit + 1));
-  HIPC(launch_cg_resid0(s, F.g, cb));
-  HIPC(launch_cg_init(s, F.g, cb));
-  for (int q = 0; q < budget; ++q) HIPC(launch_cg_iter(s, F.g, cb, q));
-  HIPC(hipMemcpyAsync(b.dlog + (int64_t)(k - 1) * M + (i - 1), cb.sc + (budget & 1),
+  const int k0 = tiles > 0 ? 1 : 0;  // the one-launch start's vectors have parity 1
+  if (k0 == 0) {
+    HIPC(launch_cg_resid0(s, F.g, cb));
+    HIPC(launch_cg_init(s, F.g, cb));
+  }
+  for (int q = k0; q < budget + k0; ++q) HIPC(launch_cg_iter(s, F.g, cb, q));
+  HIPC(hipMemcpyAsync(b.dlog + (int64_t)(k - 1) * M + (i - 1), cb.sc + ((budget + k0) & 1),
                       sizeof(CgScalars), hipMemcpyDeviceToDevice, s));
 }
 
