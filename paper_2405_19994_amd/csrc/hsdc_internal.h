@@ -296,8 +296,9 @@ hipError_t launch_cheb_steps(hipStream_t s, const Grid &g, const CgBatch &cb, in
 // (w_D, r_D), the parity-1 scalars, and x_D in x.
 hipError_t launch_cg_start(hipStream_t s, const Grid &g, const CgBatch &cb);
 // The whole CG start of degree D = cb.cstart (7) in one launch on 2D meshes
-// (x_2 .. x_D, r_D, w_D in LDS tiles of kCgTiles[g.ctile] with a halo of
-// D + 1); x_0 is read from p (cb.x0_to_p) and x_D written to x.
+// (x_2 .. x_D, r_D, w_D on tiles of kCgTiles[g.ctile] with a halo of D + 1,
+// the iterates in LDS or in registers); x_0 is read from p (cb.x0_to_p) and
+// x_D written to x.
 // cg_start_tiles(g, D) = its tiles per slice on a mesh that is not a ragged
 // batch (0: not applicable); ntiles = the launch's tiles per slice (a ragged
 // batch: the most of any tissue, cg_start_tiles_of).

@@ -1465,8 +1465,9 @@ __global__ void __launch_bounds__(64 * NW) k_cg_start_strip(Grid g0, CgBatch cb)
     return;
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int gx = (t % tiles_x) * TX - H + lane;
-  const int gy0 = (t / tiles_x) * TY - H + w * RW;
+  // the block's first column and row on the mesh, and this lane's
+  const int X0 = (t % tiles_x) * TX - H, Y0 = (t / tiles_x) * TY - H;
+  const int gx = X0 + lane, gy0 = Y0 + w * RW;
   const bool colin = gx >= 0 && gx < nx;
   const double *x1g = cb.xt + (int64_t)n * g.Np;
   const double *x0g = cb.p + (int64_t)n * g.Np;  // x_0, stored there by the node update
@@ -1494,7 +1495,6 @@ __global__ void __launch_bounds__(64 * NW) k_cg_start_strip(Grid g0, CgBatch cb)
   }
   // Blocks with no cell on the mesh's boundary take every neighbour as it
   // is; the others select the cell itself for a missing one.
-  const int X0 = (t % tiles_x) * TX - H, Y0 = (t / tiles_x) * TY - H;
   const bool edge = !(X0 > 0 && X0 + 63 < nx - 1 && Y0 > 0 && Y0 + NW * RW - 1 < ny - 1);
   const bool hl = gx > 0, hr = gx < nx - 1;
   double gam = 0.0, del = 0.0;
