@@ -280,7 +280,16 @@ __device__ __forceinline__ void fft_lds(double2 *z, const double2 *W, int n, int
     const double2 x0 = z[i0], x1 = cmul(w, z[i1]);
     z[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
     z[i1] = make_double2(x0.x - x1.x, x0.y - x1.y);
-    __syncthreads();
+    // Up to a span of 64 the butterflies of wave w stay in z[128 w, 128 w +
+    // 128), so where the next stage's span is 64 or less the wave's own
+    // LDS order suffices; wider stages and the last one wait for the block.
+    if (half <= 32 && s + 1 < logn) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
   }
 }
 
