@@ -1426,11 +1426,11 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch 
 // registers, and only the first and last row of each wave go through LDS
 // (two buffers by step parity, one barrier a step).  Every cell of the block
 // is updated in every step: after s applications of K a cell closer than s
-// to the block's edge holds a wrong value (its missing neighbour reads the
-// cell itself), which never reaches the tile, H applications away.  Cells
-// outside the mesh hold zeros and are read by none inside (a boundary node
-// reads itself for its missing neighbour, as in the LDS-tiled kernel, whose
-// arithmetic this one repeats expression by expression).
+// to the block's edge holds a wrong value (a neighbour beyond the block reads
+// zero or the cell itself), which never reaches the tile, H applications
+// away.  Cells outside the mesh hold zeros and are read by none inside (a
+// boundary node reads itself for its missing neighbour, as in the LDS-tiled
+// kernel, whose arithmetic this one repeats expression by expression).
 
 // The value of lane - 1 (lane 0: 0) and of lane + 1 (lane 63: 0).
 __device__ __forceinline__ double lane_from_left(double x) {
