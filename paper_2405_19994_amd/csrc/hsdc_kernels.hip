@@ -1424,7 +1424,8 @@ __global__ void __launch_bounds__(CT_THREADS) k_cg_start_tiled(Grid g0, CgBatch 
 // every edge.  A lane takes its left and right neighbours from the adjacent
 // lanes (DPP shifts across the wave), the rows above and below from its own
 // registers, and only the first and last row of each wave go through LDS
-// (two buffers by step parity, one barrier a step).  Every cell of the block
+// (two buffers by step parity, one barrier a step, the rows inside a strip
+// updated while the waves meet there).  Every cell of the block
 // is updated in every step: after s applications of K a cell closer than s
 // to the block's edge holds a wrong value (a neighbour beyond the block reads
 // zero or the cell itself), which never reaches the tile, H applications
@@ -1448,6 +1449,7 @@ template <int D, bool PN, int RW, int NW>
 __global__ void __launch_bounds__(64 * NW) k_cg_start_strip(Grid g0, CgBatch cb) {
   constexpr int H = D + 1, TX = 64 - 2 * H, TY = NW * RW - 2 * H;
   static_assert(TX > 0 && TY > 0, "the block must hold the tile and its halo");
+  static_assert(RW >= 2, "a strip's first and last row are distinct");
   __shared__ double s_first[2][NW][64], s_last[2][NW][64];
   __shared__ double lds[2 * NW];
   const int n = blockIdx.y;
@@ -1521,29 +1523,33 @@ __global__ void __launch_bounds__(64 * NW) k_cg_start_strip(Grid g0, CgBatch cb)
       acc += g.cy * ((d - c) + (up - c));
       return acc;
     };
-    // the rows next to this wave's strip: the previous wave's last row and
-    // the next wave's first (the block's edge rows take the strip's own)
-    auto rows_around = [&](const double (&x)[RW], int k, double &below, double &above) {
+    // One application of K over the block: the wave publishes its strip's
+    // first and last row, updates the rows inside the strip (their
+    // neighbours above and below are its own) while the other waves catch
+    // up, then takes the previous wave's last row and the next wave's first
+    // (the block's edge rows take the strip's own) and updates its first and
+    // last row.  row(j, below, above) updates row j.
+    auto phase = [&](const double (&x)[RW], int k, auto &&row) {
       s_first[k & 1][w][lane] = x[0];
       s_last[k & 1][w][lane] = x[RW - 1];
+#pragma unroll
+      for (int j = 1; j < RW - 1; ++j) row(j, x[j - 1], x[j + 1]);
       __syncthreads();
-      below = w > 0 ? s_last[k & 1][w - 1][lane] : x[0];
-      above = w < NW - 1 ? s_first[k & 1][w + 1][lane] : x[RW - 1];
+      const double below = w > 0 ? s_last[k & 1][w - 1][lane] : x[0];
+      const double above = w < NW - 1 ? s_first[k & 1][w + 1][lane] : x[RW - 1];
+      row(0, below, x[1]);
+      row(RW - 1, x[RW - 2], above);
     };
     // x_{k+1} = x_{k-1} + omega_{k+1} (x_k - x_{k-1} + (b - A x_k) / theta)
 #pragma unroll
     for (int k = 1; k < D; ++k) {
       const double om = cheb_omega(tb, k);
-      double below, above;
-      rows_around(xk, k, below, above);
-#pragma unroll
-      for (int j = 0; j < RW; ++j) {
+      phase(xk, k, [&](int j, double d, double up) {
         const double xc = xk[j], xo = xm[j];
         const double l = lane_from_left(xc), r = lane_from_right(xc);
-        const double d = j > 0 ? xk[j - 1] : below, up = j < RW - 1 ? xk[j + 1] : above;
         const double rr = bv[j] - (xc - a * Kat(j, xc, l, r, d, up));
         xm[j] = xo + om * (xc - xo + ith * rr);
-      }
+      });
 #pragma unroll
       for (int j = 0; j < RW; ++j) {
         const double tmp = xm[j];
@@ -1552,26 +1558,16 @@ __global__ void __launch_bounds__(64 * NW) k_cg_start_strip(Grid g0, CgBatch cb)
       }
     }
     // r_D = b - A x_D, over x_{D-1}
-    {
-      double below, above;
-      rows_around(xk, D, below, above);
-#pragma unroll
-      for (int j = 0; j < RW; ++j) {
-        const double xq = xk[j];
-        const double l = lane_from_left(xq), r = lane_from_right(xq);
-        const double d = j > 0 ? xk[j - 1] : below, up = j < RW - 1 ? xk[j + 1] : above;
-        xm[j] = bv[j] - (xq - a * Kat(j, xq, l, r, d, up));
-      }
-    }
+    phase(xk, D, [&](int j, double d, double up) {
+      const double xq = xk[j];
+      const double l = lane_from_left(xq), r = lane_from_right(xq);
+      xm[j] = bv[j] - (xq - a * Kat(j, xq, l, r, d, up));
+    });
     // w_D = A r_D on the tile; x_D to x, r_D and w_D to the parity-1 vectors
-    double below, above;
-    rows_around(xm, D + 1, below, above);
     const bool tcol = lane >= H && lane < H + TX && colin;
-#pragma unroll
-    for (int j = 0; j < RW; ++j) {
+    phase(xm, D + 1, [&](int j, double d, double up) {
       const double rc = xm[j];
       const double l = lane_from_left(rc), r = lane_from_right(rc);
-      const double d = j > 0 ? xm[j - 1] : below, up = j < RW - 1 ? xm[j + 1] : above;
       const double wv = rc - a * Kat(j, rc, l, r, d, up);
       const int v = w * RW + j, gy = gy0 + j;
       if (tcol && v >= H && v < H + TY && gy < ny) {
@@ -1582,7 +1578,7 @@ __global__ void __launch_bounds__(64 * NW) k_cg_start_strip(Grid g0, CgBatch cb)
         gam += rc * rc;
         del += wv * rc;
       }
-    }
+    });
   };
   if (edge)
     body(std::true_type{});
