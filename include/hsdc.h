@@ -204,8 +204,9 @@ hsdc_status hsdc_tune(hsdc_ctx *ctx, int32_t cg_blocks, int32_t cg_margin);
  *                 iterates in LDS: 0: 64 x 16 nodes, 1024 threads;
  *                 1: 32 x 32, 1024; 2: 32 x 16, 512; 3: 32 x 8, 256;
  *                 4: 16 x 16, 256; iterates in registers (blocks of 64
- *                 columns, 512 threads): 5: 48 x 16; 6: 48 x 8; 7: 48 x 24
- *                 (default); 8: 48 x 32; -1 keeps.
+ *                 columns, 512 threads): 5: 48 x 16; 6: 48 x 8; 7: 48 x 24;
+ *                 8: 48 x 32; -1 keeps.  The default is the tallest register
+ *                 tile that gives at least 192 tiles, else 48 x 8.
  *   prolong_tile: tile of the coarse-to-fine correction into the fine level
  *                 (Algorithm 1, space coarsening 2), 256 fine nodes per tile:
  *                 3D 0: 32 x 4 x 2 (default), 1: 64 x 2 x 2, 2: 16 x 8 x 2,

@@ -27,7 +27,8 @@ CG_MARGINS = (-1, 1, 2)
 NODE_BLOCKS = (64, 128, 256, 512)
 CG_TILES = (0, 1, 2, 3, 4, 5, 6, 7, 8)  # include/hsdc.h, hsdc_tune_shapes: 64x16 .. 48x32
 PROLONG_TILES = (0, 1, 2, 3)
-DEFAULT = {"cg_blocks": 512, "cg_margin": -1, "node_block": 256, "cg_tile": 7, "prolong_tile": 0}
+# cg_tile -1: the library's default tile for the mesh (hsdc_tune_shapes keeps it)
+DEFAULT = {"cg_blocks": 512, "cg_margin": -1, "node_block": 256, "cg_tile": -1, "prolong_tile": 0}
 # the order in which launch parameters are tuned; each group is timed with the
 # others at the best setting found so far
 AXES = ("cg", "node_block", "cg_tile", "prolong_tile")

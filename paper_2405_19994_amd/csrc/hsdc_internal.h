@@ -71,9 +71,11 @@ constexpr int kNumCgTiles = 9;
 constexpr TileShape kCgTiles[kNumCgTiles] = {
     {64, 16, 1024}, {32, 32, 1024}, {32, 16, 512}, {32, 8, 256}, {16, 16, 256},
     {48, 16, 512},  {48, 8, 512},   {48, 24, 512}, {48, 32, 512}};
-// 48 x 24 in registers: the fastest on 256^2 to 1024^2 slabs but for 48 x 8 on
-// 256^2 (the LDS tile 64 x 16 takes 4% to 7% longer on each)
-constexpr int kDefaultCgTile = 7;
+// The default tile on an nx x ny mesh: the tallest register tile that still
+// gives 192 tiles (three quarters of the compute units), else the one with
+// the most tiles (48 x 8); on 256^2 to 1024^2 slabs the fastest or within 1%
+// of it, where the LDS tile 64 x 16 takes 4% to 7% longer.
+int default_cg_tile(int nx, int ny);
 // Tiles of the coarse-to-fine correction (fine nodes x, y, z; 256 threads).
 constexpr int kNumProlongTiles = 4;
 constexpr int kProlongTiles3D[kNumProlongTiles][3] = {{32, 4, 2}, {64, 2, 2}, {16, 8, 2}, {16, 4, 4}};

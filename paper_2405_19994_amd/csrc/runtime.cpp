@@ -49,6 +49,12 @@ namespace hsdc {
 hipError_t launch_small_steps(hipStream_t s, const Grid &g, const Stages &st, const Colloc &co,
                               const Stim &stim, double gs0, double gs1, double gs2, int K,
                               int nsteps, int *steps_done);
+
+int default_cg_tile(int nx, int ny) {
+  for (int t : {8, 7, 5})  // register tiles 48 x 32, 48 x 24, 48 x 16
+    if (cg_start_tiles_of(nx, ny, t) >= 192) return t;
+  return 6;  // 48 x 8
+}
 }  // namespace hsdc
 
 namespace {
@@ -425,7 +431,7 @@ Grid make_grid(const hsdc_problem &p, int nx, int ny, int nz, double dx) {
   g.fx = make_fastdiv((uint32_t)nx);
   g.fy = make_fastdiv((uint32_t)ny);
   g.nub = kDefaultNodeBlock;
-  g.ctile = kDefaultCgTile;
+  g.ctile = default_cg_tile(nx, ny);
   g.ptile = 0;
   g.order = p.fd_order == 4 ? 4 : 2;
   const double s = 1.0 / (dx * dx * p.chi * p.Cm);

@@ -47,9 +47,12 @@ def test_tuner_picks_fastest_per_axis_and_caches(tmp_path, monkeypatch):
     assert axes == ("cg", "node_block", "cg_tile")  # 2D, one level: no correction tile
     best, timings = autotune.tune(_FakeContext, key, axes=axes, sync=lambda: None)
     assert best == dict(autotune.DEFAULT, cg_blocks=256, node_block=64, cg_tile=3)
-    # one timing per distinct setting: the CG grid, then each shape axis
+    # one timing per distinct setting: the CG grid, then each shape axis (the
+    # default start tile, -1, is the library's choice for the mesh, which the
+    # explicit tiles 0..8 are timed against)
     n_cg = len(autotune.CG_BLOCKS) * len(autotune.CG_MARGINS)
-    assert len(timings) == n_cg + (len(autotune.NODE_BLOCKS) - 1) + (len(autotune.CG_TILES) - 1)
+    assert autotune.DEFAULT["cg_tile"] == -1
+    assert len(timings) == n_cg + (len(autotune.NODE_BLOCKS) - 1) + len(autotune.CG_TILES)
     # a second call is served from the cache without timing
     again, t2 = autotune.tune(_FakeContext, key, axes=axes, sync=lambda: None)
     assert again == best and t2 is None
