@@ -637,6 +637,29 @@ def test_tuned_launch_shapes_give_the_same_run():
     assert np.max(e) < 1e-11
 
 
+def test_cg_start_tiles_agree_bitwise_on_the_full_slab():
+    """On the 512 x 512 slab of the benchmark (M 6, K 6, solves to 1e-12) the
+    one-launch start of degree 7 meets the tolerance by itself, so the state
+    depends on the start kernel alone (no CG iteration updates it): the LDS
+    tile and every register tile (blocks of 48 x 8 .. 48 x 32 nodes, the
+    mesh's edges cutting them) give the same state bit for bit."""
+    w = si.workload("slab2d", dims=(512, 512))
+    prob = lib_problem(w)
+    m = H.make_method(M=w["M"], dt=w["dt"], max_iter=w["K"], cg_rtol=w["cg_rtol"], cg_maxit=500)
+    ref = None
+    for tile in (0, 5, 6, 7, 8):
+        c = H.Context(prob, m)
+        c.tune_shapes(0, tile, -1)
+        c.advance(6)
+        y = host(c.get_state(0, 0, 0))
+        st = c.stats()
+        c.destroy()
+        assert st["cg_iters"] == 0 and st["cg_unconverged"] == 0, (tile, st)
+        if ref is None:
+            ref = y
+        assert np.array_equal(y, ref), (tile, np.max(field_errors(y, ref)))
+
+
 @pytest.mark.parametrize("pernode", [False, True])
 def test_tuned_block_and_tile_shapes_give_the_same_run(pernode):
     """Every node-update block size and every CG-start tile (uniform and
