@@ -1852,7 +1852,9 @@ k_prolong_tiled(Grid gf, Grid gc, const double *Dc, int64_t sYc, int Mc, const d
   const int n = blockIdx.z;
   const int f = blockIdx.y;
   const int ntx = (gf.nx + TX - 1) / TX, nty = (gf.ny + TY - 1) / TY;
-  const int t = blockIdx.x;
+  // tiles in XCD order: neighbouring tiles, which stage overlapping coarse
+  // blocks, run on one XCD and find each other's coarse values in its L2
+  const int t = gridDim.x % kXcds == 0 ? (int)xcd_node_block(blockIdx.x, gridDim.x) : blockIdx.x;
   const int fx0 = (t % ntx) * TX, fy0 = ((t / ntx) % nty) * TY, fz0 = (t / (ntx * nty)) * TZ;
   // coarse origin of the staged block (one cell before the tile's first)
   const int cx0 = TX > 1 ? (fx0 >> 1) - 1 : 0, cy0 = TY > 1 ? (fy0 >> 1) - 1 : 0,
